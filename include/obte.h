@@ -1,0 +1,209 @@
+/*
+ * obte.h - C ABI of the MI355X (gfx950) aMFP-BTE hot-path library.
+ *
+ * The library solves the steady-state RTA phonon BTE with temperatures
+ * interpolated onto vectorial mean-free-paths F_ml = Lambda_m s_l (the
+ * anisotropic-MFP BTE of the OpenBTE paper, arXiv:2106.02764) on a structured
+ * periodic finite-volume cell with diffuse pore walls, by the source iteration
+ * of the paper's Eq. (iter) / Algorithm 1, starting from the Fourier first
+ * guess of Eq. (fourier_iter).
+ *
+ * Conventions shared by every entry point
+ *  - Units are SI: lengths in metres, conductivities in W/m/K, dT in K.
+ *  - Cells are numbered x fastest: c = ix + nx (iy + ny iz).  2D meshes use
+ *    nz = 1 and ndim = 2.
+ *  - "host" pointers are read during the call only and may be freed after it;
+ *    "device" pointers must stay valid until the work enqueued on `stream`
+ *    has completed.  `stream` is a hipStream_t passed as void* (NULL = the
+ *    legacy default stream).
+ *  - Functions return an obte_status and never throw; obte_last_error()
+ *    returns a thread-local description of the last failure.
+ *  - Device memory larger than the small per-mesh tables is owned by the
+ *    caller (workspace, sigma, outputs); the handle owns only its tables.
+ */
+#ifndef OBTE_H
+#define OBTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct obte_mesh obte_mesh;     /* opaque handle */
+
+typedef enum {
+    OBTE_OK = 0,
+    OBTE_ERR_ARG = -1,            /* invalid argument (checked on the host) */
+    OBTE_ERR_HIP = -2,            /* a HIP runtime call failed */
+    OBTE_ERR_STATE = -3,          /* call order violated (e.g. no material) */
+    OBTE_ERR_NOT_CONVERGED = -4,  /* results written, tolerance not reached */
+    OBTE_ERR_NUMERIC = -5,        /* non-finite value detected */
+    OBTE_ERR_NOMEM = -6           /* workspace too small / host allocation */
+} obte_status;
+
+/* Geometry (paper: section "Geometry module"; Appendix A mesh terms).
+ * solid: host, n[0]*n[1]*n[2] bytes, 1 = material, 0 = pore.  Faces between a
+ * solid and a pore cell, and outer faces of non-periodic axes, are diffuse
+ * thermalising walls.  grad_axis must be periodic; the image across its
+ * periodic plane obeys T(x + L) = T(x) - dT_ext.
+ * GPU-path limits: ndim 2 or 3; periodic[0] and periodic[1] may be 0 or 1,
+ * periodic[2] must be 0 in 3D; n[0] <= 256; in 3D n[2] <= 16; grad_axis 0/1. */
+typedef struct {
+    int ndim;
+    int n[3];
+    double L[3];
+    int periodic[3];
+    int grad_axis;
+    double dT_ext;
+    const uint8_t* solid;
+} obte_mesh_desc;
+
+/* Material on the vectorial-MFP grid (paper: section "Material", Appendix A).
+ * mfp: n_mfp MFP magnitudes Lambda_m (> 0); dirs: n_dir x ndim unit vectors
+ * s_l (row-major), the set must be centrally symmetric; dir_w: quadrature
+ * weights (> 0, sum 1); kappa_m: per-MFP bulk conductivity kernel (>= 0).
+ * The library derives alpha_ml = kappa_m w_l / (Lambda_m^2 mu_g) with
+ * mu_g = sum_l w_l s_{l,g}^2, the T_L weights D_ml = alpha / sum alpha, the flux
+ * weights S_ml = alpha Lambda_m s_l and the outgoing wall weights per wall
+ * orientation ReLu(S.n)/sum ReLu(S.n).  All pointers are host pointers. */
+typedef struct {
+    int n_mfp;
+    const double* mfp;
+    int n_dir;
+    const double* dirs;
+    const double* dir_w;
+    const double* kappa_m;
+} obte_material_desc;
+
+enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
+
+/* Solver options.  precision OBTE_FP64: every sweep and Krylov vector in
+ * double.  OBTE_FP32: sweeps and Krylov vectors in float, while T_L, T_w,
+ * kappa and the convergence test accumulate in double.
+ * outer_tol: stop when |kappa_n - kappa_{n-1}| <= outer_tol |kappa_n|
+ * (Algorithm 1).  inner_tol: relative residual of the periodic-wrap Krylov
+ * solve inside each (m,l) system.  init: 0 = Fourier first guess, 1 = resume
+ * from the state left in the workspace by the previous call.
+ * passes_per_graph: outer passes captured per HIP-graph replay (>= 1); the
+ * host reads kappa back once per replay.  waves_per_group: systems that share
+ * one workgroup's lockstep reduction (1..8, 0 = auto).  fourier_tol /
+ * max_fourier: CG tolerance (relative residual) and iteration cap of the
+ * Fourier first guess.  only_fourier: stop after the first guess.
+ * keep_state: store the converged per-system solutions in the workspace (the
+ * forward checkpoint obte_adjoint needs; n_systems * n_cells doubles). */
+typedef struct {
+    int precision;
+    double outer_tol;
+    int max_outer;
+    double inner_tol;
+    int max_inner;
+    int init;
+    int only_fourier;
+    int passes_per_graph;
+    int waves_per_group;
+    double fourier_tol;
+    int max_fourier;
+    int keep_state;
+} obte_solve_opts;
+
+typedef struct {
+    int outer_iters;          /* passes executed */
+    long long inner_iters;    /* BiCGSTAB iterations summed over systems/passes */
+    long long sweeps;         /* upwind sweeps summed over systems/passes */
+    int fourier_iters;
+    double kappa;             /* kappa_cc: volume-averaged flux * L / dT */
+    double kappa_face;        /* upwind flux through the hot contact plane */
+    double kappa_fourier;
+    double last_rel_change;
+    int status;
+} obte_stats;
+
+/* Fill opts with defaults (FP64, outer_tol 1e-8, ...). */
+void obte_default_opts(obte_solve_opts* opts);
+
+/* Create a mesh handle from a host description (validates, builds the face
+ * classes on the host).  No device work. */
+obte_status obte_mesh_create(const obte_mesh_desc* desc, obte_mesh** out);
+
+/* Attach the material (computes the weights above on the host and uploads the
+ * small tables to the current device).  Must precede obte_solve. */
+obte_status obte_material_set(obte_mesh* mesh, const obte_material_desc* mat);
+
+/* Bytes of device workspace obte_solve / obte_adjoint need for `opts`. */
+obte_status obte_workspace_size(const obte_mesh* mesh, const obte_solve_opts* opts,
+                                size_t* bytes);
+
+/* Source iteration to convergence (paper Algorithm 1).
+ * sigma_dev: device, n_cells doubles (pore entries ignored), NULL => 1.
+ * workspace_dev: device, 256-byte aligned, workspace_bytes >= obte_workspace_size
+ * (checked: a smaller workspace returns OBTE_ERR_NOMEM before any launch).
+ * T_L_dev (nullable): device, n_cells doubles, receives the lattice
+ * temperature with the solid-cell mean subtracted (0 in pores).
+ * J_dev (nullable): device, n_cells*ndim doubles, receives the flux map
+ * J_i = sum_ml S_ml T_iml (cell-major, component fastest).
+ * stats: host.  Returns OBTE_ERR_NOT_CONVERGED (results written) when
+ * max_outer passes did not reach outer_tol. */
+obte_status obte_solve(obte_mesh* mesh, const obte_solve_opts* opts, const double* sigma_dev,
+                       void* workspace_dev, size_t workspace_bytes, void* stream, double* T_L_dev,
+                       double* J_dev, obte_stats* stats);
+
+/* Many independent geometries in one persistent launch per pass.  meshes[i]
+ * and sigma_dev[i] (nullable entries) as above; one workspace holds all; the
+ * needed size is the sum of obte_workspace_size over the meshes (each part
+ * rounded up to 256 bytes); all meshes must share the number of MFPs unless
+ * waves_per_group is set.  kappa_out: host, n doubles (kappa_cc).  stats: host,
+ * n entries. */
+obte_status obte_solve_batch(obte_mesh* const* meshes, int n, const obte_solve_opts* opts,
+                             const double* const* sigma_dev, void* workspace_dev,
+                             size_t workspace_bytes, void* stream, double* kappa_out,
+                             obte_stats* stats);
+
+/* kappa_cc of the last solve and, if kappa_per_mfp is non-NULL, its split
+ * over the n_mfp MFPs (host arrays). */
+obte_status obte_kappa(const obte_mesh* mesh, double* kappa_eff, double* kappa_per_mfp);
+
+/* Adjoint gradient d kappa_cc / d sigma_i (derived from Appendix A,
+ * Eq. (iter2)): M^T lambda = k by the transposed source iteration, then
+ * d kappa / d sigma_i = -sum_ml lambda_iml (T_iml - T_L,i).  Requires a
+ * converged obte_solve with keep_state = 1 on the same mesh, sigma pointer,
+ * precision and workspace (else OBTE_ERR_STATE); max_outer must not exceed
+ * that solve's.  stats->kappa receives p^T lambda, which equals kappa_cc at
+ * convergence.  dkappa_dsigma_dev: device, n_cells doubles, 0 in pores. */
+obte_status obte_adjoint(obte_mesh* mesh, const obte_solve_opts* opts, const double* sigma_dev,
+                         void* workspace_dev, size_t workspace_bytes, void* stream,
+                         double* dkappa_dsigma_dev, obte_stats* stats);
+
+/* Matrix-free upwind apply of one (m,l) system, y = (sigma + Lambda_m A_l) x
+ * (transpose = 1: sigma + Lambda_m A_l^T), for n_sys systems at once.
+ * x, y: device, n_sys * n_cells values of the precision (0 = double,
+ * 1 = float), system-major; sys_ids: device int32 (n_sys) of m * n_dir + l.
+ * Pore entries of y are written 0.  Used for the outer residual and by the
+ * tests; paper Appendix A, Eq. (iter2) left-hand side. */
+obte_status obte_upwind_apply(const obte_mesh* mesh, int precision, int transpose,
+                              const double* sigma_dev, const int* sys_ids_dev, int n_sys,
+                              const void* x_dev, void* y_dev, void* stream);
+
+/* Save / restore the outer-loop state (pass count, kappa history, T_L, T_w
+ * and the wrap inflow vectors) of the last solve to a host file.  Loading
+ * needs a mesh with the same geometry and material; a following obte_solve
+ * with init = 1 and the same precision, waves_per_group, max_outer and
+ * keep_state continues the iteration exactly where the saved run stopped. */
+obte_status obte_checkpoint_save(const obte_mesh* mesh, const void* workspace_dev,
+                                 const char* path);
+obte_status obte_checkpoint_load(obte_mesh* mesh, void* workspace_dev, const char* path);
+
+const char* obte_last_error(void);
+void obte_mesh_destroy(obte_mesh* mesh);
+
+/* Mesh/material queries (host). */
+int obte_mesh_n_cells(const obte_mesh* mesh);
+int obte_mesh_n_solid(const obte_mesh* mesh);
+int obte_mesh_n_walls(const obte_mesh* mesh);
+int obte_mesh_n_systems(const obte_mesh* mesh);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OBTE_H */

@@ -1,0 +1,862 @@
+// Host driver of the aMFP-BTE library: argument checking, face classes,
+// material weights, workspace carving, the outer source iteration
+// (Algorithm 1) replayed as HIP graphs, outputs, adjoint, checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/obte.h"
+#include "obte_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+obte_status fail(obte_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(OBTE_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct obte_mesh {
+    // geometry
+    int ndim = 2, nx = 1, ny = 1, nz = 1, nf = 4, ncells = 0, nsolid = 0, nwalls = 0;
+    double L[3] = {0, 0, 0}, h[3] = {0, 0, 0}, dT = 1.0;
+    int periodic[3] = {0, 0, 0};
+    int grad_axis = 0;
+    std::vector<uint16_t> fc;
+    std::vector<int> wall_idx, wall_cell, wall_face;
+    // material
+    bool has_material = false;
+    int n_mfp = 0, n_dir = 0, n_sys = 0;
+    std::vector<double> mfp, dirs3, dir_w, kappa_m, alpha, Dw, S, wout, kappa_axis;
+    // device tables (library-owned)
+    int device = -1;
+    uint16_t* d_fc = nullptr;
+    int *d_wall_idx = nullptr, *d_wall_cell = nullptr, *d_wall_face = nullptr;
+    double *d_mfp = nullptr, *d_dirs = nullptr, *d_D = nullptr, *d_S = nullptr, *d_wout = nullptr,
+           *d_kax = nullptr;
+    GeomDev* d_geom = nullptr;      // single-geometry view (apply, outputs)
+    // results of the last solve
+    bool solved = false, adj_ready = false;
+    const void* last_ws = nullptr;
+    const double* last_sigma = nullptr;
+    double kappa = 0, kappa_face = 0, kappa_fourier = 0;
+    std::vector<double> kappa_per_mfp;
+    GeomDev host_view{};
+    int last_precision = 0, last_waves = 0, last_max_outer = 0, last_keep = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// workspace layout of one geometry
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t sigma, sigma_f, sT, Tw, T_L, U, part_TL, part_Tw, part_J, ksys, kfsys, iters, sweeps,
+        hist, hist_face, ctrl, fx, fscal, Tstore, lam_psi, lam_phi, grad, part_G, total;
+};
+
+int auto_waves(const obte_mesh* m) {
+    int w = 4;
+    if (m->n_mfp < w) w = m->n_mfp;
+    return std::max(1, w);
+}
+
+int n_groups(const obte_mesh* m, int waves) { return (m->n_mfp + waves - 1) / waves; }
+
+Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    const size_t nc = (size_t)m->ncells, nw = (size_t)std::max(m->nwalls, 1);
+    const size_t n_items = (size_t)m->n_dir * n_groups(m, waves);
+    const size_t tsz = (o->precision == OBTE_FP32) ? 4 : 8;
+    const size_t nwrap = (size_t)m->nx * m->nz;
+    const int max_outer = std::max(o->max_outer, 1);
+    L.sigma = take(nc * 8);
+    L.sigma_f = take(nc * 4);
+    L.sT = take(2 * nc * 8);
+    L.Tw = take(2 * nw * 8);
+    L.T_L = take(nc * 8);
+    L.part_TL = take(n_items * nc * 8);
+    L.part_Tw = take(n_items * nw * 8);
+    L.part_J = take(n_items * nc * m->ndim * 8);
+    L.ksys = take((size_t)m->n_sys * 8);
+    L.kfsys = take((size_t)m->n_sys * 8);
+    L.iters = take((size_t)m->n_sys * 8);
+    L.sweeps = take((size_t)m->n_sys * 8);
+    L.ctrl = take(CTRL_N * 4);
+    L.fx = take(4 * nc * 8);
+    L.fscal = take(4 * 8);
+    L.lam_psi = take(2 * nc * 8);
+    L.lam_phi = take(2 * nw * 8);
+    L.grad = take(nc * 8);
+    L.part_G = take(n_items * nc * 8);
+    // the parts below depend on precision / keep_state / max_outer
+    L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
+    L.Tstore = o->keep_state ? take((size_t)m->n_sys * nc * 8) : 0;
+    L.hist = take((size_t)max_outer * 8 + 8);
+    L.hist_face = take((size_t)max_outer * 8 + 8);
+    L.total = off;
+    return L;
+}
+
+GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves) {
+    GeomDev g{};
+    g.nx = m->nx; g.ny = m->ny; g.nz = m->nz; g.ndim = m->ndim; g.nf = m->nf;
+    g.ncells = m->ncells; g.nwalls = m->nwalls; g.nwrap = m->nx * m->nz;
+    for (int a = 0; a < 3; ++a) { g.periodic[a] = m->periodic[a]; g.h[a] = m->h[a]; g.L[a] = m->L[a]; }
+    g.grad_axis = m->grad_axis;
+    g.dT = m->dT;
+    g.n_mfp = m->n_mfp; g.n_dir = m->n_dir; g.n_sys = m->n_sys;
+    g.n_grp = waves > 0 ? n_groups(m, waves) : 1;
+    g.n_items = m->n_dir * g.n_grp;
+    g.n_perp = m->ncells / (m->grad_axis == 0 ? m->nx : (m->grad_axis == 1 ? m->ny : m->nz));
+    g.fc = m->d_fc; g.wall_idx = m->d_wall_idx; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face;
+    g.mfp = m->d_mfp; g.dirs = m->d_dirs; g.Dw = m->d_D; g.S = m->d_S; g.wout = m->d_wout;
+    g.kappa_axis = m->d_kax;
+    if (ws) {
+        g.sigma = (double*)(ws + L.sigma);
+        g.sigma_f = (float*)(ws + L.sigma_f);
+        g.sT = (double*)(ws + L.sT);
+        g.Tw = (double*)(ws + L.Tw);
+        g.T_L = (double*)(ws + L.T_L);
+        g.U = ws + L.U;
+        g.part_TL = (double*)(ws + L.part_TL);
+        g.part_Tw = (double*)(ws + L.part_Tw);
+        g.part_J = (double*)(ws + L.part_J);
+        g.ksys = (double*)(ws + L.ksys);
+        g.kfsys = (double*)(ws + L.kfsys);
+        g.iters = (long long*)(ws + L.iters);
+        g.sweeps = (long long*)(ws + L.sweeps);
+        g.hist = (double*)(ws + L.hist);
+        g.hist_face = (double*)(ws + L.hist_face);
+        g.ctrl = (int*)(ws + L.ctrl);
+        g.fx = (double*)(ws + L.fx);
+        g.fscal = (double*)(ws + L.fscal);
+        g.Tstore = L.Tstore ? (double*)(ws + L.Tstore) : nullptr;
+        g.lam_psi = (double*)(ws + L.lam_psi);
+        g.lam_phi = (double*)(ws + L.lam_phi);
+        g.gradient = (double*)(ws + L.grad);
+        g.part_G = (double*)(ws + L.part_G);
+    }
+    return g;
+}
+
+template <typename T>
+obte_status upload(T** dst, const std::vector<T>& src) {
+    if (*dst) { (void)hipFree(*dst); *dst = nullptr; }
+    const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+    HIPCHK(hipMalloc((void**)dst, bytes));
+    if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return OBTE_OK;
+}
+
+void free_dev(obte_mesh* m) {
+    void* ptrs[] = {m->d_fc, m->d_wall_idx, m->d_wall_cell, m->d_wall_face, m->d_mfp, m->d_dirs,
+                    m->d_D, m->d_S, m->d_wout, m->d_kax, m->d_geom};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    m->d_fc = nullptr; m->d_wall_idx = m->d_wall_cell = m->d_wall_face = nullptr;
+    m->d_mfp = m->d_dirs = m->d_D = m->d_S = m->d_wout = m->d_kax = nullptr;
+    m->d_geom = nullptr;
+}
+
+obte_status check_opts(const obte_solve_opts* o) {
+    if (!o) return fail(OBTE_ERR_ARG, "opts is NULL");
+    if (o->precision != OBTE_FP64 && o->precision != OBTE_FP32)
+        return fail(OBTE_ERR_ARG, "precision must be OBTE_FP64 or OBTE_FP32");
+    if (!(o->outer_tol >= 0.0) || o->max_outer < 1)
+        return fail(OBTE_ERR_ARG, "outer_tol must be >= 0 and max_outer >= 1");
+    if (!(o->inner_tol > 0.0) || o->max_inner < 0)
+        return fail(OBTE_ERR_ARG, "inner_tol must be > 0 and max_inner >= 0");
+    if (o->waves_per_group < 0 || o->waves_per_group > 8)
+        return fail(OBTE_ERR_ARG, "waves_per_group must be in 0..8");
+    if (o->passes_per_graph < 0) return fail(OBTE_ERR_ARG, "passes_per_graph must be >= 0");
+    if (!(o->fourier_tol > 0.0) || o->max_fourier < 0)
+        return fail(OBTE_ERR_ARG, "fourier_tol must be > 0 and max_fourier >= 0");
+    if (o->init != 0 && o->init != 1) return fail(OBTE_ERR_ARG, "init must be 0 or 1");
+    return OBTE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the outer loop shared by obte_solve, obte_solve_batch and obte_adjoint
+// ---------------------------------------------------------------------------
+struct Run {
+    std::vector<obte_mesh*> meshes;
+    std::vector<GeomDev> views;
+    std::vector<Item> items;
+    GeomDev* d_views = nullptr;
+    Item* d_items = nullptr;
+    int waves = 4, cpl = 1, nzmax = 1, precision = 0;
+    size_t lds = 0;
+    int max_cells = 0, max_walls = 0;
+    ~Run() {
+        if (d_views) (void)hipFree(d_views);
+        if (d_items) (void)hipFree(d_items);
+    }
+};
+
+obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_opts* o,
+                      char* ws, std::vector<size_t>* offsets) {
+    R.meshes.assign(meshes, meshes + n);
+    R.precision = o->precision;
+    int W = o->waves_per_group;
+    if (W == 0) {
+        W = auto_waves(meshes[0]);
+        for (int i = 1; i < n; ++i)
+            if (auto_waves(meshes[i]) != W)
+                return fail(OBTE_ERR_ARG, "meshes differ in their automatic waves_per_group; set it explicitly");
+    }
+    {
+        int cpl = 1, nzm = 1;
+        for (int i = 0; i < n; ++i) { cpl = std::max(cpl, (meshes[i]->nx + 63) / 64); nzm = std::max(nzm, meshes[i]->nz); }
+        const int nd = nzm > 1 ? 3 : 2;
+        const size_t per_wave = (size_t)(1 + 2 * nd) * 64 * (nzm > 1 ? 1 : cpl) * sizeof(double);
+        const int wmax = (int)std::max<size_t>(1, (64 * 1024) / per_wave);
+        if (W > wmax) {
+            if (o->waves_per_group) return fail(OBTE_ERR_ARG, "waves_per_group %d needs more than 64 KiB of LDS (max %d)", W, wmax);
+            W = wmax;
+        }
+    }
+    R.waves = W;
+    size_t off = 0;
+    for (int gi = 0; gi < n; ++gi) {
+        obte_mesh* m = meshes[gi];
+        Layout L = make_layout(m, o, W);
+        if (offsets) offsets->push_back(off);
+        GeomDev v = make_view(m, ws + off, L, W);
+        v.item0 = (int)R.items.size();
+        const int ng = n_groups(m, W);
+        for (int l = 0; l < m->n_dir; ++l)
+            for (int gp = 0; gp < ng; ++gp) {
+                Item it;
+                it.geom = gi;
+                it.l = l;
+                it.m0 = gp * W;
+                it.nm = std::min(W, m->n_mfp - gp * W);
+                it.local = l * ng + gp;
+                R.items.push_back(it);
+            }
+        R.views.push_back(v);
+        R.cpl = std::max(R.cpl, (m->nx + 63) / 64);
+        R.nzmax = std::max(R.nzmax, m->nz);
+        R.max_cells = std::max(R.max_cells, m->ncells);
+        R.max_walls = std::max(R.max_walls, m->nwalls);
+        off += align256(L.total);
+    }
+    if (R.nzmax > 1 && R.cpl > 1) return fail(OBTE_ERR_ARG, "3D meshes need nx <= 64");
+    for (int gi = 0; gi < n; ++gi)
+        if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
+            return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
+    const int rowlen = 64 * (R.nzmax > 1 ? 1 : R.cpl);
+    const int ndim = R.nzmax > 1 ? 3 : 2;
+    const int NV = 1 + 2 * ndim;
+    R.lds = (size_t)W * NV * rowlen * sizeof(double);
+    HIPCHK(hipMalloc((void**)&R.d_views, R.views.size() * sizeof(GeomDev)));
+    HIPCHK(hipMalloc((void**)&R.d_items, R.items.size() * sizeof(Item)));
+    HIPCHK(hipMemcpy(R.d_views, R.views.data(), R.views.size() * sizeof(GeomDev), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(R.d_items, R.items.data(), R.items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    return OBTE_OK;
+}
+
+obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st) {
+    HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items, (int)R.items.size(),
+                             R.waves, pp, R.lds, st));
+    HIPCHK(launch_reduce_pass(R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
+    HIPCHK(launch_finalize(R.d_views, (int)R.views.size(), pp, st));
+    return OBTE_OK;
+}
+
+// Replays graphs of K passes until every geometry reports done.
+obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st, int max_outer) {
+    const int n = (int)R.views.size();
+    std::vector<int> ctrl(CTRL_N);
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (K > 1) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        obte_status s = OBTE_OK;
+        for (int k = 0; k < K && s == OBTE_OK; ++k) s = enqueue_pass(R, pp, st);
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        if (s != OBTE_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
+        if (e != hipSuccess) return fail(OBTE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(OBTE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
+    }
+    obte_status out = OBTE_OK;
+    int launched = 0;
+    while (true) {
+        if (exec) {
+            hipError_t e = hipGraphLaunch(exec, st);
+            if (e != hipSuccess) { out = fail(OBTE_ERR_HIP, "graph launch: %s", hipGetErrorString(e)); break; }
+            launched += K;
+        } else {
+            out = enqueue_pass(R, pp, st);
+            if (out != OBTE_OK) break;
+            launched += 1;
+        }
+        bool all_done = true;
+        for (int i = 0; i < n && all_done; ++i) {
+            hipError_t e = hipMemcpyAsync(ctrl.data(), R.views[i].ctrl, CTRL_N * sizeof(int),
+                                          hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) { out = fail(OBTE_ERR_HIP, "readback: %s", hipGetErrorString(e)); all_done = true; break; }
+            if (!ctrl[CTRL_DONE]) all_done = false;
+        }
+        if (out != OBTE_OK || all_done) break;
+        if (launched > max_outer + K + 2) { out = fail(OBTE_ERR_STATE, "outer loop did not terminate"); break; }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return out;
+}
+
+PassParams base_params(const obte_solve_opts* o) {
+    PassParams pp{};
+    pp.inner_tol = o->inner_tol;
+    pp.max_inner = o->max_inner;
+    pp.mode = 0;
+    pp.max_outer = o->max_outer;
+    pp.outer_tol = o->outer_tol;
+    return pp;
+}
+
+obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o,
+                       const double* const* sigma, void* workspace, size_t ws_bytes, void* stream,
+                       double* T_L_out, double* J_out, double* kappa_out, obte_stats* stats,
+                       bool keep_T) {
+    obte_status s = check_opts(o);
+    if (s != OBTE_OK) return s;
+    if (!meshes || n < 1) return fail(OBTE_ERR_ARG, "no meshes");
+    if (!workspace) return fail(OBTE_ERR_ARG, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(OBTE_ERR_ARG, "workspace must be 256-byte aligned");
+    for (int i = 0; i < n; ++i) {
+        if (!meshes[i]) return fail(OBTE_ERR_ARG, "mesh %d is NULL", i);
+        if (!meshes[i]->has_material) return fail(OBTE_ERR_STATE, "mesh %d has no material", i);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Run R;
+    std::vector<size_t> offs;
+    s = build_run(R, meshes, n, o, (char*)workspace, &offs);
+    if (s != OBTE_OK) return s;
+    {
+        size_t need = 0;
+        for (int i = 0; i < n; ++i) need += align256(make_layout(meshes[i], o, R.waves).total);
+        if (ws_bytes < need)
+            return fail(OBTE_ERR_NOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    }
+    for (int i = 0; i < n; ++i) {
+        obte_mesh* m = meshes[i];
+        Layout L = make_layout(m, o, R.waves);
+        char* ws = (char*)workspace + offs[i];
+        HIPCHK(hipMemcpy(m->d_geom, &R.views[i], sizeof(GeomDev), hipMemcpyHostToDevice));
+        m->host_view = R.views[i];
+        HIPCHK(launch_prep_sigma(m->d_geom, m->ncells, sigma ? sigma[i] : nullptr, st));
+        if (o->init == 0) {
+            const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
+            HIPCHK(hipMemsetAsync(ws + L.U, 0, 2 * (size_t)m->n_sys * m->nx * m->nz * tsz, st));
+        }
+        HIPCHK(hipMemsetAsync(ws + L.iters, 0, 2 * (size_t)m->n_sys * 8, st));
+    }
+    if (o->init == 0) {
+        HIPCHK(launch_fourier(R.d_views, n, o->fourier_tol, o->max_fourier, st));
+    } else {
+        // resume: clear the done / converged flags, keep the pass count
+        for (int i = 0; i < n; ++i) {
+            int zero2[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(R.views[i].ctrl + CTRL_DONE, zero2, sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(R.views[i].ctrl + CTRL_CONVERGED, zero2, sizeof(int), hipMemcpyHostToDevice, st));
+        }
+    }
+    if (!o->only_fourier) {
+        PassParams pp = base_params(o);
+        const int K = (o->passes_per_graph <= 1 || !st) ? 1 : o->passes_per_graph;
+        s = outer_loop(R, pp, K, st, o->max_outer);
+        if (s != OBTE_OK) return s;
+        // replay the last pass's final sweep for the flux map / stored state
+        if ((J_out || keep_T) && n == 1) {
+            PassParams rp = pp;
+            rp.mode = 1;
+            rp.want_J = J_out != nullptr;
+            rp.store_T = keep_T ? 1 : 0;
+            HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items,
+                                     (int)R.items.size(), R.waves, rp, R.lds, st));
+        }
+    }
+    if (n == 1 && (T_L_out || J_out)) HIPCHK(launch_output(meshes[0]->d_geom, 1, T_L_out, o->only_fourier ? nullptr : J_out, nullptr, st));
+    if (n == 1 && J_out && o->only_fourier) HIPCHK(hipMemsetAsync(J_out, 0, sizeof(double) * meshes[0]->ncells * meshes[0]->ndim, st));
+    // results
+    obte_status ret = OBTE_OK;
+    for (int i = 0; i < n; ++i) {
+        obte_mesh* m = meshes[i];
+        const GeomDev& v = R.views[i];
+        std::vector<int> ctrl(CTRL_N);
+        double fs[4];
+        HIPCHK(hipMemcpyAsync(ctrl.data(), v.ctrl, CTRL_N * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(fs, v.fscal, sizeof fs, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int passes = o->only_fourier ? 0 : ctrl[CTRL_PASS];
+        std::vector<double> hist(passes + 1, 0.0), histf(passes + 1, 0.0), ks(m->n_sys), kfs(m->n_sys);
+        std::vector<long long> its(m->n_sys), sws(m->n_sys);
+        if (passes > 0) {
+            HIPCHK(hipMemcpy(hist.data(), v.hist, passes * sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(histf.data(), v.hist_face, passes * sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(ks.data(), v.ksys, m->n_sys * sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(its.data(), v.iters, m->n_sys * sizeof(long long), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(sws.data(), v.sweeps, m->n_sys * sizeof(long long), hipMemcpyDeviceToHost));
+        }
+        m->kappa_fourier = fs[0];
+        m->kappa = passes > 0 ? hist[passes - 1] : fs[0];
+        m->kappa_face = passes > 0 ? histf[passes - 1] : fs[0];
+        m->kappa_per_mfp.assign(m->n_mfp, 0.0);
+        for (int sys = 0; sys < m->n_sys; ++sys) m->kappa_per_mfp[sys / m->n_dir] += ks[sys];
+        m->solved = true;
+        m->adj_ready = keep_T && !o->only_fourier && ctrl[CTRL_CONVERGED];
+        m->last_ws = workspace;
+        m->last_sigma = sigma ? sigma[i] : nullptr;
+        m->last_precision = o->precision;
+        m->last_waves = R.waves;
+        m->last_max_outer = o->max_outer;
+        m->last_keep = o->keep_state;
+        obte_status si = OBTE_OK;
+        if (ctrl[CTRL_NONFINITE]) si = fail(OBTE_ERR_NUMERIC, "non-finite kappa in mesh %d", i);
+        else if (!o->only_fourier && !ctrl[CTRL_CONVERGED])
+            si = fail(OBTE_ERR_NOT_CONVERGED, "mesh %d: no convergence in %d passes", i, passes);
+        if (stats) {
+            obte_stats& S = stats[i];
+            S.outer_iters = passes;
+            S.inner_iters = 0;
+            S.sweeps = 0;
+            for (int sys = 0; sys < m->n_sys; ++sys) { S.inner_iters += its[sys]; S.sweeps += sws[sys]; }
+            S.fourier_iters = (int)fs[1];
+            S.kappa = m->kappa;
+            S.kappa_face = m->kappa_face;
+            S.kappa_fourier = fs[0];
+            S.last_rel_change = passes >= 2 ? std::fabs(hist[passes - 1] - hist[passes - 2]) /
+                                                  std::fabs(hist[passes - 1])
+                                            : 0.0;
+            S.status = si;
+        }
+        if (kappa_out) kappa_out[i] = m->kappa;
+        if (si != OBTE_OK && ret == OBTE_OK) ret = si;
+    }
+    return ret;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* obte_last_error(void) { return g_err.c_str(); }
+
+void obte_default_opts(obte_solve_opts* o) {
+    if (!o) return;
+    o->precision = OBTE_FP64;
+    o->outer_tol = 1e-8;
+    o->max_outer = 1000;
+    o->inner_tol = 1e-12;
+    o->max_inner = 64;
+    o->init = 0;
+    o->only_fourier = 0;
+    o->passes_per_graph = 8;
+    o->waves_per_group = 0;
+    o->fourier_tol = 1e-13;
+    o->max_fourier = 20000;
+    o->keep_state = 0;
+}
+
+obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
+    if (!out) return fail(OBTE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(OBTE_ERR_ARG, "desc is NULL");
+    if (d->ndim != 2 && d->ndim != 3) return fail(OBTE_ERR_ARG, "ndim must be 2 or 3");
+    const int nz = d->ndim == 3 ? d->n[2] : 1;
+    for (int a = 0; a < d->ndim; ++a) {
+        if (d->n[a] < 2) return fail(OBTE_ERR_ARG, "n[%d] must be >= 2", a);
+        if (!(d->L[a] > 0.0) || !std::isfinite(d->L[a])) return fail(OBTE_ERR_ARG, "L[%d] must be > 0", a);
+        if (d->periodic[a] != 0 && d->periodic[a] != 1) return fail(OBTE_ERR_ARG, "periodic[%d] must be 0/1", a);
+    }
+    if (d->n[0] > 256) return fail(OBTE_ERR_ARG, "n[0] must be <= 256");
+    if (d->ndim == 3) {
+        if (d->n[0] > 64) return fail(OBTE_ERR_ARG, "3D meshes need n[0] <= 64");
+        if (nz > 16) return fail(OBTE_ERR_ARG, "3D meshes need n[2] <= 16");
+        if (d->periodic[2]) return fail(OBTE_ERR_ARG, "periodic z is not supported (diffuse top/bottom)");
+    }
+    if (d->grad_axis < 0 || d->grad_axis > 1) return fail(OBTE_ERR_ARG, "grad_axis must be 0 or 1");
+    if (!d->periodic[d->grad_axis]) return fail(OBTE_ERR_ARG, "the gradient axis must be periodic");
+    if (!(d->dT_ext != 0.0) || !std::isfinite(d->dT_ext)) return fail(OBTE_ERR_ARG, "dT_ext must be finite and non-zero");
+    if (!d->solid) return fail(OBTE_ERR_ARG, "solid mask is NULL");
+    const long long nc = (long long)d->n[0] * d->n[1] * nz;
+    if (nc > (1LL << 26)) return fail(OBTE_ERR_ARG, "mesh too large");
+    obte_mesh* m = new (std::nothrow) obte_mesh();
+    if (!m) return fail(OBTE_ERR_NOMEM, "host allocation failed");
+    m->ndim = d->ndim;
+    m->nx = d->n[0]; m->ny = d->n[1]; m->nz = nz;
+    m->nf = 2 * d->ndim;
+    m->ncells = (int)nc;
+    for (int a = 0; a < 3; ++a) {
+        m->L[a] = (a < d->ndim) ? d->L[a] : 1.0;
+        m->periodic[a] = (a < d->ndim) ? d->periodic[a] : 0;
+        m->h[a] = m->L[a] / (a == 0 ? m->nx : (a == 1 ? m->ny : m->nz));
+    }
+    m->grad_axis = d->grad_axis;
+    m->dT = d->dT_ext;
+    m->fc.assign(nc, 0);
+    m->wall_idx.assign(nc * m->nf, -1);
+    const int n3[3] = {m->nx, m->ny, m->nz};
+    for (long long c = 0; c < nc; ++c) {
+        if (d->solid[c] > 1) { delete m; return fail(OBTE_ERR_ARG, "solid mask entries must be 0/1"); }
+        if (!d->solid[c]) continue;
+        m->nsolid++;
+        const int q0[3] = {(int)(c % m->nx), (int)((c / m->nx) % m->ny), (int)(c / ((long long)m->nx * m->ny))};
+        uint16_t w = 1;
+        for (int a = 0; a < d->ndim; ++a)
+            for (int side = 0; side < 2; ++side) {
+                const int f = 2 * a + side;
+                int q[3] = {q0[0], q0[1], q0[2]};
+                q[a] += side ? 1 : -1;
+                int cls = FC_INTERIOR;
+                bool wrapped = false;
+                if (q[a] < 0 || q[a] >= n3[a]) {
+                    if (!m->periodic[a]) cls = FC_WALL;
+                    q[a] = (q[a] + n3[a]) % n3[a];
+                    wrapped = true;
+                }
+                if (cls != FC_WALL) {
+                    const long long cc = q[0] + (long long)m->nx * (q[1] + (long long)m->ny * q[2]);
+                    if (!d->solid[cc]) cls = FC_WALL;
+                    else if (wrapped && a == m->grad_axis) cls = side == 0 ? FC_JUMP_P : FC_JUMP_M;
+                }
+                if (cls == FC_WALL) {
+                    m->wall_idx[c * m->nf + f] = (int)m->wall_cell.size();
+                    m->wall_cell.push_back((int)c);
+                    m->wall_face.push_back(f);
+                }
+                w |= (uint16_t)(cls << (1 + 2 * f));
+            }
+        m->fc[c] = w;
+    }
+    m->nwalls = (int)m->wall_cell.size();
+    if (m->nsolid == 0) { delete m; return fail(OBTE_ERR_ARG, "the mesh has no solid cell"); }
+    *out = m;
+    return OBTE_OK;
+}
+
+obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
+    if (!m || !d) return fail(OBTE_ERR_ARG, "NULL argument");
+    if (d->n_mfp < 1 || d->n_dir < 2) return fail(OBTE_ERR_ARG, "need n_mfp >= 1 and n_dir >= 2");
+    if (!d->mfp || !d->dirs || !d->dir_w || !d->kappa_m) return fail(OBTE_ERR_ARG, "NULL material array");
+    const int nd = m->ndim;
+    double wsum = 0.0;
+    std::vector<double> ssum(3, 0.0);
+    for (int l = 0; l < d->n_dir; ++l) {
+        double nrm = 0.0;
+        for (int a = 0; a < nd; ++a) nrm += d->dirs[l * nd + a] * d->dirs[l * nd + a];
+        if (std::fabs(nrm - 1.0) > 1e-9) return fail(OBTE_ERR_ARG, "direction %d is not a unit vector", l);
+        if (!(d->dir_w[l] > 0.0)) return fail(OBTE_ERR_ARG, "direction weight %d must be > 0", l);
+        wsum += d->dir_w[l];
+        for (int a = 0; a < nd; ++a) ssum[a] += d->dirs[l * nd + a] * d->dir_w[l];
+    }
+    if (std::fabs(wsum - 1.0) > 1e-9) return fail(OBTE_ERR_ARG, "direction weights must sum to 1");
+    for (int a = 0; a < nd; ++a)
+        if (std::fabs(ssum[a]) > 1e-9) return fail(OBTE_ERR_ARG, "direction set must be centrally symmetric");
+    for (int mm = 0; mm < d->n_mfp; ++mm) {
+        if (!(d->mfp[mm] > 0.0) || !std::isfinite(d->mfp[mm])) return fail(OBTE_ERR_ARG, "mfp[%d] must be > 0", mm);
+        if (!(d->kappa_m[mm] >= 0.0) || !std::isfinite(d->kappa_m[mm])) return fail(OBTE_ERR_ARG, "kappa_m[%d] must be >= 0", mm);
+    }
+    m->n_mfp = d->n_mfp;
+    m->n_dir = d->n_dir;
+    m->n_sys = d->n_mfp * d->n_dir;
+    m->mfp.assign(d->mfp, d->mfp + d->n_mfp);
+    m->kappa_m.assign(d->kappa_m, d->kappa_m + d->n_mfp);
+    m->dir_w.assign(d->dir_w, d->dir_w + d->n_dir);
+    m->dirs3.assign(3 * d->n_dir, 0.0);
+    for (int l = 0; l < d->n_dir; ++l)
+        for (int a = 0; a < nd; ++a) m->dirs3[l * 3 + a] = d->dirs[l * nd + a];
+    // alpha_ml = kappa_m w_l / (Lambda_m^2 mu_g), mu_g = sum w s_g^2
+    const int g = m->grad_axis;
+    double mu = 0.0;
+    for (int l = 0; l < m->n_dir; ++l) mu += m->dir_w[l] * m->dirs3[l * 3 + g] * m->dirs3[l * 3 + g];
+    if (!(mu > 0.0)) return fail(OBTE_ERR_ARG, "directions have no component along the gradient axis");
+    m->alpha.assign(m->n_sys, 0.0);
+    double asum = 0.0;
+    for (int mm = 0; mm < m->n_mfp; ++mm)
+        for (int l = 0; l < m->n_dir; ++l) {
+            const double a = m->kappa_m[mm] * m->dir_w[l] / (m->mfp[mm] * m->mfp[mm] * mu);
+            m->alpha[mm * m->n_dir + l] = a;
+            asum += a;
+        }
+    if (!(asum > 0.0)) return fail(OBTE_ERR_ARG, "kappa_m is all zero");
+    m->Dw.assign(m->n_sys, 0.0);
+    m->S.assign(3 * m->n_sys, 0.0);
+    m->kappa_axis.assign(3, 0.0);
+    for (int mm = 0; mm < m->n_mfp; ++mm)
+        for (int l = 0; l < m->n_dir; ++l) {
+            const int sys = mm * m->n_dir + l;
+            const double a = m->alpha[sys];
+            m->Dw[sys] = a / asum;
+            for (int ax = 0; ax < 3; ++ax) {
+                m->S[sys * 3 + ax] = a * m->mfp[mm] * m->dirs3[l * 3 + ax];
+                m->kappa_axis[ax] += a * m->mfp[mm] * m->mfp[mm] * m->dirs3[l * 3 + ax] * m->dirs3[l * 3 + ax];
+            }
+        }
+    // outgoing wall weights per face orientation
+    m->wout.assign((size_t)m->nf * m->n_sys, 0.0);
+    for (int f = 0; f < m->nf; ++f) {
+        const int ax = f >> 1;
+        const double sg = (f & 1) ? 1.0 : -1.0;
+        double tot = 0.0;
+        for (int sys = 0; sys < m->n_sys; ++sys) tot += std::max(0.0, m->S[sys * 3 + ax] * sg);
+        for (int sys = 0; sys < m->n_sys; ++sys)
+            m->wout[(size_t)f * m->n_sys + sys] = tot > 0.0 ? std::max(0.0, m->S[sys * 3 + ax] * sg) / tot : 0.0;
+    }
+    // device tables
+    free_dev(m);
+    HIPCHK(hipGetDevice(&m->device));
+    obte_status s;
+    if ((s = upload(&m->d_fc, m->fc)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_wall_idx, m->wall_idx)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_wall_cell, m->wall_cell)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_wall_face, m->wall_face)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_mfp, m->mfp)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_dirs, m->dirs3)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_D, m->Dw)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_S, m->S)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_wout, m->wout)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_kax, m->kappa_axis)) != OBTE_OK) return s;
+    HIPCHK(hipMalloc((void**)&m->d_geom, sizeof(GeomDev)));
+    GeomDev v = make_view(m, nullptr, Layout{}, 0);
+    HIPCHK(hipMemcpy(m->d_geom, &v, sizeof v, hipMemcpyHostToDevice));
+    m->host_view = v;
+    m->has_material = true;
+    m->solved = false;
+    m->adj_ready = false;
+    return OBTE_OK;
+}
+
+obte_status obte_workspace_size(const obte_mesh* m, const obte_solve_opts* o, size_t* bytes) {
+    if (!m || !bytes) return fail(OBTE_ERR_ARG, "NULL argument");
+    obte_status s = check_opts(o);
+    if (s != OBTE_OK) return s;
+    if (!m->has_material) return fail(OBTE_ERR_STATE, "material not set");
+    int W = o->waves_per_group ? o->waves_per_group : auto_waves(m);
+    *bytes = align256(make_layout(m, o, W).total);
+    return OBTE_OK;
+}
+
+obte_status obte_solve(obte_mesh* m, const obte_solve_opts* o, const double* sigma_dev,
+                       void* workspace, size_t ws_bytes, void* stream, double* T_L_dev,
+                       double* J_dev, obte_stats* stats) {
+    if (!m) return fail(OBTE_ERR_ARG, "mesh is NULL");
+    const double* sg[1] = {sigma_dev};
+    return solve_impl(&m, 1, o, sg, workspace, ws_bytes, stream, T_L_dev, J_dev, nullptr, stats,
+                      o && o->keep_state);
+}
+
+obte_status obte_solve_batch(obte_mesh* const* meshes, int n, const obte_solve_opts* o,
+                             const double* const* sigma_dev, void* workspace, size_t ws_bytes,
+                             void* stream, double* kappa_out, obte_stats* stats) {
+    if (o && o->keep_state) return fail(OBTE_ERR_ARG, "keep_state is not supported by the batch entry point");
+    return solve_impl(meshes, n, o, sigma_dev, workspace, ws_bytes, stream, nullptr, nullptr, kappa_out,
+                      stats, false);
+}
+
+obte_status obte_kappa(const obte_mesh* m, double* kappa_eff, double* kappa_per_mfp) {
+    if (!m) return fail(OBTE_ERR_ARG, "mesh is NULL");
+    if (!m->solved) return fail(OBTE_ERR_STATE, "no solve has completed on this mesh");
+    if (kappa_eff) *kappa_eff = m->kappa;
+    if (kappa_per_mfp)
+        for (int i = 0; i < m->n_mfp; ++i) kappa_per_mfp[i] = m->kappa_per_mfp[i];
+    return OBTE_OK;
+}
+
+obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* sigma_dev,
+                         void* workspace, size_t ws_bytes, void* stream, double* grad_dev,
+                         obte_stats* stats) {
+    if (!m) return fail(OBTE_ERR_ARG, "mesh is NULL");
+    obte_status s = check_opts(o);
+    if (s != OBTE_OK) return s;
+    if (!grad_dev) return fail(OBTE_ERR_ARG, "gradient output is NULL");
+    if (!m->adj_ready || m->last_ws != workspace || m->last_sigma != sigma_dev ||
+        m->last_precision != o->precision)
+        return fail(OBTE_ERR_STATE, "obte_adjoint needs a converged obte_solve with keep_state = 1 "
+                                    "and the same sigma, precision and workspace");
+    if (o->max_outer > m->last_max_outer)
+        return fail(OBTE_ERR_ARG, "adjoint max_outer must not exceed the forward solve's");
+    hipStream_t st = (hipStream_t)stream;
+    Run R;
+    obte_solve_opts oo = *o;
+    oo.waves_per_group = m->last_waves;
+    oo.keep_state = 1;
+    obte_mesh* mp = m;
+    s = build_run(R, &mp, 1, &oo, (char*)workspace, nullptr);
+    if (s != OBTE_OK) return s;
+    Layout L = make_layout(m, &oo, R.waves);
+    if (ws_bytes < align256(L.total)) return fail(OBTE_ERR_NOMEM, "workspace too small for the adjoint");
+    char* ws = (char*)workspace;
+    // lambda^(0) = 0: Psi = Phi = 0, no warm start, fresh counters
+    HIPCHK(hipMemsetAsync(ws + L.lam_psi, 0, 2 * (size_t)m->ncells * 8, st));
+    HIPCHK(hipMemsetAsync(ws + L.lam_phi, 0, 2 * (size_t)std::max(m->nwalls, 1) * 8, st));
+    const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
+    const size_t half = (size_t)m->n_sys * m->nx * m->nz * tsz;
+    HIPCHK(hipMemsetAsync(ws + L.U + half, 0, half, st));
+    HIPCHK(hipMemsetAsync(ws + L.iters, 0, 2 * (size_t)m->n_sys * 8, st));
+    HIPCHK(hipMemsetAsync(ws + L.ctrl, 0, CTRL_N * sizeof(int), st));
+    PassParams pp = base_params(o);
+    pp.adjoint = 1;
+    const int K = (o->passes_per_graph <= 1 || !st) ? 1 : o->passes_per_graph;
+    s = outer_loop(R, pp, K, st, o->max_outer);
+    if (s != OBTE_OK) return s;
+    HIPCHK(launch_output(m->d_geom, 1, nullptr, nullptr, grad_dev, st));
+    std::vector<int> ctrl(CTRL_N);
+    HIPCHK(hipMemcpyAsync(ctrl.data(), R.views[0].ctrl, CTRL_N * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int passes = ctrl[CTRL_PASS];
+    std::vector<double> hist(std::max(passes, 1));
+    if (passes > 0) HIPCHK(hipMemcpy(hist.data(), R.views[0].hist, passes * sizeof(double), hipMemcpyDeviceToHost));
+    if (stats) {
+        std::vector<long long> its(m->n_sys), sws(m->n_sys);
+        HIPCHK(hipMemcpy(its.data(), R.views[0].iters, m->n_sys * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(sws.data(), R.views[0].sweeps, m->n_sys * 8, hipMemcpyDeviceToHost));
+        stats->outer_iters = passes;
+        stats->inner_iters = 0;
+        stats->sweeps = 0;
+        for (int i = 0; i < m->n_sys; ++i) { stats->inner_iters += its[i]; stats->sweeps += sws[i]; }
+        stats->fourier_iters = 0;
+        stats->kappa = passes > 0 ? hist[passes - 1] : 0.0;   // p^T lambda
+        stats->kappa_face = 0.0;
+        stats->kappa_fourier = m->kappa_fourier;
+        stats->last_rel_change = passes >= 2 ? std::fabs(hist[passes - 1] - hist[passes - 2]) / std::fabs(hist[passes - 1]) : 0.0;
+        stats->status = ctrl[CTRL_CONVERGED] ? OBTE_OK : OBTE_ERR_NOT_CONVERGED;
+    }
+    if (ctrl[CTRL_NONFINITE]) return fail(OBTE_ERR_NUMERIC, "non-finite adjoint functional");
+    if (!ctrl[CTRL_CONVERGED]) return fail(OBTE_ERR_NOT_CONVERGED, "adjoint: no convergence in %d passes", passes);
+    return OBTE_OK;
+}
+
+obte_status obte_upwind_apply(const obte_mesh* m, int precision, int transpose, const double* sigma_dev,
+                              const int* sys_ids_dev, int n_sys, const void* x_dev, void* y_dev,
+                              void* stream) {
+    if (!m || !x_dev || !y_dev || !sys_ids_dev) return fail(OBTE_ERR_ARG, "NULL argument");
+    if (!m->has_material) return fail(OBTE_ERR_STATE, "material not set");
+    if (precision != 0 && precision != 1) return fail(OBTE_ERR_ARG, "precision must be 0 or 1");
+    if (n_sys < 1 || n_sys > 65535) return fail(OBTE_ERR_ARG, "n_sys must be in 1..65535");
+    HIPCHK(launch_apply(precision, transpose ? 1 : 0, m->d_geom, m->host_view, sigma_dev, sys_ids_dev,
+                        n_sys, x_dev, y_dev, (hipStream_t)stream));
+    return OBTE_OK;
+}
+
+obte_status obte_checkpoint_save(const obte_mesh* m, const void* workspace, const char* path) {
+    if (!m || !workspace || !path) return fail(OBTE_ERR_ARG, "NULL argument");
+    if (!m->solved) return fail(OBTE_ERR_STATE, "nothing to checkpoint");
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(OBTE_ERR_ARG, "cannot open %s", path);
+    // header: magic, sizes; body: ctrl, T_L, sT (2), Tw (2), U, hist
+    const GeomDev& v = m->host_view;
+    if (m->last_ws != workspace) return fail(OBTE_ERR_ARG, "workspace differs from the last solve's");
+    const int hdr[10] = {0x4f425445, m->ncells, m->nwalls, m->n_sys, m->nx * m->nz, m->last_precision,
+                         m->last_waves, m->last_max_outer, m->last_keep, 0};
+    fwrite(hdr, sizeof hdr, 1, f);
+    auto dump = [&](const void* dptr, size_t bytes) -> bool {
+        std::vector<char> buf(bytes);
+        if (hipMemcpy(buf.data(), dptr, bytes, hipMemcpyDeviceToHost) != hipSuccess) return false;
+        return fwrite(buf.data(), 1, bytes, f) == bytes;
+    };
+    std::vector<int> ctrl(CTRL_N);
+    bool ok = dump(v.ctrl, CTRL_N * sizeof(int));
+    if (ok && hipMemcpy(ctrl.data(), v.ctrl, CTRL_N * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+    const size_t tsz = m->last_precision == OBTE_FP32 ? 4 : 8;
+    ok = ok && dump(v.T_L, (size_t)m->ncells * 8) && dump(v.sT, 2 * (size_t)m->ncells * 8) &&
+         dump(v.Tw, 2 * (size_t)std::max(m->nwalls, 1) * 8) &&
+         dump(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz);
+    const int passes = ctrl[CTRL_PASS];
+    fwrite(&passes, sizeof passes, 1, f);
+    ok = ok && (passes == 0 || dump(v.hist, (size_t)passes * 8)) && (passes == 0 || dump(v.hist_face, (size_t)passes * 8));
+    fclose(f);
+    if (!ok) return fail(OBTE_ERR_HIP, "checkpoint write failed");
+    return OBTE_OK;
+}
+
+obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path) {
+    if (!m || !workspace || !path) return fail(OBTE_ERR_ARG, "NULL argument");
+    if (!m->has_material) return fail(OBTE_ERR_STATE, "material not set");
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(OBTE_ERR_ARG, "cannot open %s", path);
+    int hdr[10];
+    if (fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != 0x4f425445 || hdr[1] != m->ncells ||
+        hdr[2] != m->nwalls || hdr[3] != m->n_sys || hdr[4] != m->nx * m->nz) {
+        fclose(f);
+        return fail(OBTE_ERR_ARG, "checkpoint does not match this mesh / precision");
+    }
+    obte_solve_opts o;
+    obte_default_opts(&o);
+    o.precision = hdr[5];
+    o.max_outer = hdr[7];
+    o.keep_state = hdr[8];
+    const GeomDev v = make_view(m, (char*)workspace, make_layout(m, &o, hdr[6]), hdr[6]);
+    auto load = [&](void* dptr, size_t bytes) -> bool {
+        std::vector<char> buf(bytes);
+        if (fread(buf.data(), 1, bytes, f) != bytes) return false;
+        return hipMemcpy(dptr, buf.data(), bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    const size_t tsz = m->last_precision == OBTE_FP32 ? 4 : 8;
+    bool ok = load(v.ctrl, CTRL_N * sizeof(int)) && load(v.T_L, (size_t)m->ncells * 8) &&
+              load(v.sT, 2 * (size_t)m->ncells * 8) && load(v.Tw, 2 * (size_t)std::max(m->nwalls, 1) * 8) &&
+              load(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz);
+    int passes = 0;
+    ok = ok && fread(&passes, sizeof passes, 1, f) == 1;
+    ok = ok && (passes == 0 || load(v.hist, (size_t)passes * 8)) && (passes == 0 || load(v.hist_face, (size_t)passes * 8));
+    fclose(f);
+    if (!ok) return fail(OBTE_ERR_ARG, "checkpoint read failed");
+    m->last_precision = hdr[5];
+    m->last_waves = hdr[6];
+    m->last_max_outer = hdr[7];
+    m->last_keep = hdr[8];
+    return OBTE_OK;
+}
+
+void obte_mesh_destroy(obte_mesh* m) {
+    if (!m) return;
+    free_dev(m);
+    delete m;
+}
+
+int obte_mesh_n_cells(const obte_mesh* m) { return m ? m->ncells : -1; }
+int obte_mesh_n_solid(const obte_mesh* m) { return m ? m->nsolid : -1; }
+int obte_mesh_n_walls(const obte_mesh* m) { return m ? m->nwalls : -1; }
+int obte_mesh_n_systems(const obte_mesh* m) { return m ? m->n_sys : -1; }
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal types shared by the host driver and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Face classes, two bits per face, face index f = 2 * axis + side
+// (side 0 = '-' face, 1 = '+' face); bit 0 of the cell word = solid.
+#define FC_INTERIOR 0   // solid neighbour (with periodic wrap), no jump
+#define FC_WALL 1       // pore neighbour or outer face of a non-periodic axis
+#define FC_JUMP_P 2     // solid neighbour across the periodic plane, image hotter by dT
+#define FC_JUMP_M 3     // solid neighbour across the periodic plane, image colder by dT
+
+__host__ __device__ inline int fc_solid(uint16_t w) { return w & 1; }
+__host__ __device__ inline int fc_class(uint16_t w, int f) { return (w >> (1 + 2 * f)) & 3; }
+
+enum { CTRL_DONE = 0, CTRL_PASS = 1, CTRL_CONVERGED = 2, CTRL_NONFINITE = 3, CTRL_N = 8 };
+
+// Per-geometry view used by every kernel: static tables (library-owned) plus
+// the per-solve workspace carve (caller-owned).
+struct GeomDev {
+    int nx, ny, nz, ndim, nf, ncells, nwalls, nwrap;
+    int periodic[3];
+    int grad_axis;
+    double h[3], L[3], dT;
+    int n_mfp, n_dir, n_sys;
+    int n_items, item0;          // this geometry's work items in the global list
+    int n_grp;                   // MFP groups per direction (items are ordered l-major)
+    int n_perp;                  // ncells / n[grad_axis]
+    // ---- static tables
+    const uint16_t* fc;          // ncells
+    const int* wall_idx;         // ncells * nf, -1 where the face is not a wall
+    const int* wall_cell;        // nwalls
+    const int* wall_face;        // nwalls: face index 2a+side of the owning cell
+    const double* mfp;           // n_mfp
+    const double* dirs;          // n_dir * 3 (z = 0 in 2D)
+    const double* Dw;            // n_sys: T_L weights D_ml
+    const double* S;             // n_sys * 3: flux weights S_ml
+    const double* wout;          // nf * n_sys: outgoing wall weights per face orientation
+    const double* kappa_axis;    // 3
+    // ---- workspace
+    double* sigma;               // ncells (1 in pores)
+    float* sigma_f;              // ncells
+    double* sT;                  // 2 * ncells: sigma * T_L of the pass input (double buffered)
+    double* Tw;                  // 2 * nwalls: wall temperatures (double buffered)
+    double* T_L;                 // ncells: latest lattice temperature
+    void* U;                     // n_sys * nwrap (compute precision): wrap inflow vectors
+    double* part_TL;             // n_items * ncells
+    double* part_Tw;             // n_items * nwalls
+    double* part_J;              // n_items * ncells * ndim
+    double* ksys;                // n_sys: kappa_cc contribution of each system
+    double* kfsys;               // n_sys: kappa_face contribution
+    long long* iters;            // n_sys: accumulated BiCGSTAB iterations
+    long long* sweeps;           // n_sys: accumulated sweeps
+    double* hist;                // max_outer
+    double* hist_face;           // max_outer
+    int* ctrl;                   // CTRL_N ints
+    double* fx;                  // Fourier CG vectors: 4 * ncells
+    double* fscal;               // Fourier scalars: [0] kappa_F, [1] iterations, [2] residual
+    double* Tstore;              // n_sys * ncells (adjoint forward state) or null
+    double* lam_psi;             // adjoint: 2 * ncells (double buffered Psi)
+    double* lam_phi;             // adjoint: 2 * nwalls (double buffered Phi)
+    double* gradient;            // adjoint: ncells
+    double* part_G;              // adjoint: n_items * ncells (gradient partials)
+};
+
+struct Item {
+    int geom;    // index into the geometry array
+    int l;       // direction
+    int m0;      // first MFP of the group
+    int nm;      // MFPs in the group (<= waves per group)
+    int local;   // item index within its geometry
+};
+
+struct PassParams {
+    double inner_tol;
+    int max_inner;
+    int mode;          // 0 = full pass, 1 = replay the last pass's final sweep only (J / store)
+    int want_J;
+    int store_T;       // write the final x of every system to Tstore
+    int adjoint;       // 1 = transposed system with adjoint sources
+    int max_outer;
+    double outer_tol;
+};
+
+// kernel launchers (kernels.hip)
+hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, double tol, int max_iter,
+                          hipStream_t st);
+hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
+                             const Item* items_dev, int n_items, int waves, PassParams pp,
+                             size_t lds_bytes, hipStream_t st);
+hipError_t launch_reduce_pass(const GeomDev* geoms_dev, int n_geoms, int max_cells, int max_walls,
+                              PassParams pp, hipStream_t st);
+hipError_t launch_finalize(const GeomDev* geoms_dev, int n_geoms, PassParams pp, hipStream_t st);
+hipError_t launch_output(const GeomDev* geoms_dev, int n_geoms, double* T_L_out, double* J_out,
+                         double* grad_out, hipStream_t st);
+hipError_t launch_prep_sigma(const GeomDev* g_dev, int ncells, const double* sig, hipStream_t st);
+hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, const GeomDev& g_host,
+                        const double* sigma, const int* sys_ids, int n_sys, const void* x, void* y,
+                        hipStream_t st);

@@ -1,0 +1,235 @@
+"""ctypes binding of the C ABI in include/obte.h (argument marshalling only).
+
+Every function here forwards to the gfx950 library ``libobte.so`` built in
+this package directory; nothing is computed in Python.  torch is imported
+before the library is loaded so that the process has a single HIP runtime
+(torch's), whose device memory and streams the library then shares.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libobte.so")
+
+OBTE_OK, OBTE_ERR_ARG, OBTE_ERR_HIP, OBTE_ERR_STATE = 0, -1, -2, -3
+OBTE_ERR_NOT_CONVERGED, OBTE_ERR_NUMERIC, OBTE_ERR_NOMEM = -4, -5, -6
+OBTE_FP64, OBTE_FP32 = 0, 1
+STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_STATE", -4: "ERR_NOT_CONVERGED",
+                -5: "ERR_NUMERIC", -6: "ERR_NOMEM"}
+
+
+class ObteError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class obte_mesh_desc(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3),
+                ("periodic", C.c_int * 3), ("grad_axis", C.c_int), ("dT_ext", C.c_double),
+                ("solid", C.POINTER(C.c_uint8))]
+
+
+class obte_material_desc(C.Structure):
+    _fields_ = [("n_mfp", C.c_int), ("mfp", C.POINTER(C.c_double)), ("n_dir", C.c_int),
+                ("dirs", C.POINTER(C.c_double)), ("dir_w", C.POINTER(C.c_double)),
+                ("kappa_m", C.POINTER(C.c_double))]
+
+
+class obte_solve_opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("outer_tol", C.c_double), ("max_outer", C.c_int),
+                ("inner_tol", C.c_double), ("max_inner", C.c_int), ("init", C.c_int),
+                ("only_fourier", C.c_int), ("passes_per_graph", C.c_int),
+                ("waves_per_group", C.c_int), ("fourier_tol", C.c_double),
+                ("max_fourier", C.c_int), ("keep_state", C.c_int)]
+
+
+class obte_stats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_longlong), ("sweeps", C.c_longlong),
+                ("fourier_iters", C.c_int), ("kappa", C.c_double), ("kappa_face", C.c_double),
+                ("kappa_fourier", C.c_double), ("last_rel_change", C.c_double), ("status", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = {
+    "obte_default_opts": (None, [C.POINTER(obte_solve_opts)]),
+    "obte_mesh_create": (C.c_int, [C.POINTER(obte_mesh_desc), C.POINTER(C.c_void_p)]),
+    "obte_material_set": (C.c_int, [C.c_void_p, C.POINTER(obte_material_desc)]),
+    "obte_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.POINTER(C.c_size_t)]),
+    "obte_solve": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.c_void_p, C.c_void_p,
+                             C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(obte_stats)]),
+    "obte_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(obte_solve_opts),
+                                   C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_void_p,
+                                   C.POINTER(C.c_double), C.POINTER(obte_stats)]),
+    "obte_kappa": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "obte_adjoint": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.c_void_p, C.c_void_p,
+                               C.c_size_t, C.c_void_p, C.c_void_p, C.POINTER(obte_stats)]),
+    "obte_upwind_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "obte_checkpoint_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_char_p]),
+    "obte_checkpoint_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_char_p]),
+    "obte_last_error": (C.c_char_p, []),
+    "obte_mesh_destroy": (None, [C.c_void_p]),
+    "obte_mesh_n_cells": (C.c_int, [C.c_void_p]),
+    "obte_mesh_n_solid": (C.c_int, [C.c_void_p]),
+    "obte_mesh_n_walls": (C.c_int, [C.c_void_p]),
+    "obte_mesh_n_systems": (C.c_int, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libobte.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2106_02764_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OBTE_OK:
+        raise ObteError(st, lib().obte_last_error().decode())
+
+
+def _dptr(t):
+    """Device pointer of a CUDA/HIP tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_opts(**kw):
+    o = obte_solve_opts()
+    lib().obte_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def obte_mesh_create(ndim, n, L, solid, periodic, grad_axis=0, dT_ext=1.0):
+    solid = np.ascontiguousarray(solid, dtype=np.uint8).ravel()
+    d = obte_mesh_desc()
+    d.ndim = ndim
+    for a in range(3):
+        d.n[a] = int(n[a]) if a < len(n) else 1
+        d.L[a] = float(L[a]) if a < len(L) else 1.0
+        d.periodic[a] = int(periodic[a]) if a < len(periodic) else 0
+    d.grad_axis = grad_axis
+    d.dT_ext = dT_ext
+    d.solid = solid.ctypes.data_as(C.POINTER(C.c_uint8))
+    h = C.c_void_p()
+    _check(lib().obte_mesh_create(C.byref(d), C.byref(h)))
+    return h
+
+
+def obte_material_set(mesh, mfp, dirs, dir_w, kappa_m):
+    mfp, dirs, dir_w, kappa_m = _f64(mfp), _f64(dirs), _f64(dir_w), _f64(kappa_m)
+    d = obte_material_desc()
+    P = C.POINTER(C.c_double)
+    d.n_mfp = len(mfp)
+    d.mfp = mfp.ctypes.data_as(P)
+    d.n_dir = len(dir_w)
+    d.dirs = dirs.ctypes.data_as(P)
+    d.dir_w = dir_w.ctypes.data_as(P)
+    d.kappa_m = kappa_m.ctypes.data_as(P)
+    _check(lib().obte_material_set(mesh, C.byref(d)))
+
+
+def obte_workspace_size(mesh, opts):
+    n = C.c_size_t()
+    _check(lib().obte_workspace_size(mesh, C.byref(opts), C.byref(n)))
+    return n.value
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def obte_solve(mesh, opts, sigma, workspace, stream=None, T_L=None, J=None, raise_not_converged=False):
+    st = obte_stats()
+    rc = lib().obte_solve(mesh, C.byref(opts), _dptr(sigma), _dptr(workspace),
+                          workspace.numel() * workspace.element_size(), _stream(stream),
+                          _dptr(T_L), _dptr(J), C.byref(st))
+    if rc != OBTE_OK and not (rc == OBTE_ERR_NOT_CONVERGED and not raise_not_converged):
+        _check(rc)
+    return st
+
+
+def obte_solve_batch(meshes, opts, sigmas, workspace, stream=None):
+    n = len(meshes)
+    arr = (C.c_void_p * n)(*[m.value for m in meshes])
+    sg = (C.c_void_p * n)(*[(s.data_ptr() if s is not None else None) for s in sigmas])
+    kap = (C.c_double * n)()
+    stats = (obte_stats * n)()
+    rc = lib().obte_solve_batch(arr, n, C.byref(opts), sg, _dptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream),
+                                kap, stats)
+    if rc not in (OBTE_OK, OBTE_ERR_NOT_CONVERGED):
+        _check(rc)
+    return list(kap), [stats[i] for i in range(n)]
+
+
+def obte_kappa(mesh, n_mfp):
+    k = C.c_double()
+    per = (C.c_double * n_mfp)()
+    _check(lib().obte_kappa(mesh, C.byref(k), per))
+    return k.value, np.array(per[:])
+
+
+def obte_adjoint(mesh, opts, sigma, workspace, grad, stream=None):
+    st = obte_stats()
+    _check(lib().obte_adjoint(mesh, C.byref(opts), _dptr(sigma), _dptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream),
+                              _dptr(grad), C.byref(st)))
+    return st
+
+
+def obte_upwind_apply(mesh, precision, transpose, sigma, sys_ids, x, y, stream=None):
+    _check(lib().obte_upwind_apply(mesh, precision, int(transpose), _dptr(sigma), _dptr(sys_ids),
+                                   int(sys_ids.numel()), _dptr(x), _dptr(y), _stream(stream)))
+
+
+def obte_checkpoint_save(mesh, workspace, path):
+    _check(lib().obte_checkpoint_save(mesh, _dptr(workspace), path.encode()))
+
+
+def obte_checkpoint_load(mesh, workspace, path):
+    _check(lib().obte_checkpoint_load(mesh, _dptr(workspace), path.encode()))
+
+
+def obte_mesh_destroy(mesh):
+    lib().obte_mesh_destroy(mesh)
+
+
+def obte_mesh_counts(mesh):
+    L = lib()
+    return {"n_cells": L.obte_mesh_n_cells(mesh), "n_solid": L.obte_mesh_n_solid(mesh),
+            "n_walls": L.obte_mesh_n_walls(mesh), "n_systems": L.obte_mesh_n_systems(mesh)}

@@ -1,0 +1,125 @@
+"""Convenience layer over the C ABI: one geometry + material + caller-owned
+device workspace, and the autograd function for d kappa / d sigma.
+Argument marshalling only; every step runs in libobte.so."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import obte as _o
+
+
+class Solver:
+    """Owns one obte_mesh handle and a device workspace (torch tensor)."""
+
+    def __init__(self, ndim, n, L, solid, periodic, grad_axis, dT, mfp, dirs, dir_w, kappa_m,
+                 device="cuda"):
+        self.ndim = ndim
+        self.n = tuple(int(v) for v in n)
+        self.device = torch.device(device)
+        self.mesh = _o.obte_mesh_create(ndim, n, L, solid, periodic, grad_axis, dT)
+        _o.obte_material_set(self.mesh, mfp, dirs, dir_w, kappa_m)
+        c = _o.obte_mesh_counts(self.mesh)
+        self.n_cells, self.n_solid, self.n_walls, self.n_systems = (
+            c["n_cells"], c["n_solid"], c["n_walls"], c["n_systems"])
+        self.n_mfp = len(mfp)
+        self.n_dir = len(dir_w)
+        self.workspace = None
+        self.last_stats = None
+
+    @classmethod
+    def from_workload(cls, w, device="cuda"):
+        return cls(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT, w.mfp, w.dirs,
+                   w.dir_w, w.kappa_m, device=device)
+
+    def opts(self, **kw):
+        return _o.default_opts(**kw)
+
+    def ensure_workspace(self, opts):
+        nbytes = _o.obte_workspace_size(self.mesh, opts)
+        if self.workspace is None or self.workspace.numel() < nbytes:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.workspace
+
+    def sigma_tensor(self, sigma):
+        if sigma is None:
+            return None
+        if isinstance(sigma, torch.Tensor):
+            return sigma.to(device=self.device, dtype=torch.float64).contiguous()
+        return torch.as_tensor(np.asarray(sigma, np.float64), device=self.device).contiguous()
+
+    def solve(self, opts=None, sigma=None, want_T_L=True, want_J=False, stream=None, **kw):
+        opts = opts or self.opts(**kw)
+        ws = self.ensure_workspace(opts)
+        T_L = torch.empty(self.n_cells, dtype=torch.float64, device=self.device) if want_T_L else None
+        J = torch.empty(self.n_cells * self.ndim, dtype=torch.float64, device=self.device) if want_J else None
+        self._sigma = self.sigma_tensor(sigma)
+        st = _o.obte_solve(self.mesh, opts, self._sigma, ws, stream=stream, T_L=T_L, J=J)
+        self.last_stats = st
+        out = st.as_dict()
+        if want_T_L:
+            out["T_L"] = T_L
+        if want_J:
+            out["J"] = J.view(self.n_cells, self.ndim)
+        return out
+
+    def kappa(self):
+        return _o.obte_kappa(self.mesh, self.n_mfp)
+
+    def adjoint(self, opts, stream=None):
+        g = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        st = _o.obte_adjoint(self.mesh, opts, self._sigma, self.workspace, g, stream=stream)
+        return g, st.as_dict()
+
+    def apply(self, x, sys_ids, precision=0, transpose=False, sigma=None, stream=None):
+        dt = torch.float64 if precision == 0 else torch.float32
+        x = x.to(device=self.device, dtype=dt).contiguous()
+        y = torch.empty_like(x)
+        ids = torch.as_tensor(np.asarray(sys_ids, np.int32), device=self.device)
+        sg = self.sigma_tensor(sigma)
+        _o.obte_upwind_apply(self.mesh, precision, transpose, sg, ids, x, y, stream=stream)
+        return y
+
+    def checkpoint_save(self, path):
+        _o.obte_checkpoint_save(self.mesh, self.workspace, path)
+
+    def checkpoint_load(self, path):
+        _o.obte_checkpoint_load(self.mesh, self.workspace, path)
+
+    def close(self):
+        if self.mesh is not None:
+            _o.obte_mesh_destroy(self.mesh)
+            self.mesh = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class KappaEff(torch.autograd.Function):
+    """kappa_eff(sigma) with the hand-written adjoint as its backward."""
+
+    @staticmethod
+    def forward(ctx, sigma, solver, opts):
+        o = _o.default_opts(**{f: getattr(opts, f) for f, _ in opts._fields_})
+        o.keep_state = 1
+        out = solver.solve(o, sigma=sigma.detach(), want_T_L=False)
+        ctx.solver = solver
+        ctx.opts = o
+        return torch.tensor(out["kappa"], dtype=torch.float64, device=sigma.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        grad, _ = ctx.solver.adjoint(ctx.opts)
+        return g * grad, None, None
+
+
+def solve_batch(solvers, opts, sigmas=None, device="cuda"):
+    """All geometries in one launch per pass; returns (kappas, stats dicts)."""
+    sizes = [_o.obte_workspace_size(s.mesh, opts) for s in solvers]
+    ws = torch.empty(sum(sizes), dtype=torch.uint8, device=device)
+    sg = [None] * len(solvers) if sigmas is None else [s.sigma_tensor(x) for s, x in zip(solvers, sigmas)]
+    k, st = _o.obte_solve_batch([s.mesh for s in solvers], opts, sg, ws)
+    return k, [x.as_dict() for x in st]

@@ -1,0 +1,143 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs (element by element where the oracle can afford it)."""
+import numpy as np
+import pytest
+import torch
+
+from inputs import gen
+from oracle.bte import Problem, source_iteration
+from oracle.fourier import fourier_solve
+from tests.gpu_common import gpu_solve, oracle_full, rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+NM = 1e-9
+
+
+@pytest.fixture(scope="module")
+def P():
+    return require_gpu()
+
+
+def ragged_porous():
+    # 70 x 37: rows span two wavefronts with a ragged tail; two pores, one
+    # crossing the periodic boundary
+    L = 120 * NM
+    s = gen.circles_mask(70, 37, L, L * 37 / 70, [(10 * NM, 20 * NM), (80 * NM, 30 * NM)],
+                         [14 * NM, 9 * NM])
+    w = gen.small_2d(70, 37, solid=s, n_dir=12, n_mfp=5, L=L, Ly=L * 37 / 70)
+    return w
+
+
+def small3d():
+    s = np.ones((4, 6, 7), np.uint8)
+    s[:, 2:4, 2:5] = 0
+    return gen.small_3d(7, 6, 4, solid=s, n_theta=4, n_phi=8, n_mfp=3)
+
+
+CASES = {
+    "cfg1": gen.config1,
+    "ragged": ragged_porous,
+    "bulk": lambda: gen.small_2d(16, 12, n_dir=8, n_mfp=4),
+    "grad_y": lambda: gen.small_2d(12, 10, solid=gen.square_block_mask(12, 10, 3, 7), n_dir=8,
+                                   n_mfp=3, grad_axis=1),
+    "channel": lambda: gen.small_2d(9, 10, solid=gen.stripe_mask(9, 10, 6), n_dir=16, n_mfp=4),
+    "sigma": lambda: gen.small_2d(10, 9, solid=gen.square_block_mask(10, 9, 3, 6), n_dir=8, n_mfp=3,
+                                  sigma=np.random.default_rng(11).uniform(0.5, 2.0, 90)),
+    "3d": small3d,
+}
+
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "3d"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_upwind_apply(P, name, prec):
+    w = CASES[name]()
+    prob = Problem(w)
+    s = P.Solver.from_workload(w)
+    rng = np.random.default_rng(5)
+    ids = [0, w.n_systems - 1, w.n_systems // 2 + 1, 3]
+    X = np.zeros((len(ids), w.n_cells))
+    for k in range(len(ids)):
+        X[k, prob.mesh.cells] = rng.standard_normal(prob.mesh.n_solid)
+    for tr in (False, True):
+        Y = s.apply(torch.as_tensor(X.ravel()), ids, precision=prec, transpose=tr).cpu().numpy()
+        Y = Y.reshape(len(ids), -1).astype(float)
+        for k, sid in enumerate(ids):
+            m, l = divmod(sid, w.dirs.shape[0])
+            M = prob.system_matrix(m, l)
+            if tr:
+                M = M.T
+            ref = M @ X[k, prob.mesh.cells]
+            tol = 1e-13 if prec == 0 else 2e-6
+            assert rel(Y[k, prob.mesh.cells], ref) < tol
+            assert np.all(Y[k][w.solid.ravel() == 0] == 0)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "grad_y", "3d"])
+def test_fourier_first_guess(P, name):
+    w = CASES[name]()
+    prob = Problem(w)
+    r = gpu_solve(P, w, want_J=False, only_fourier=1, fourier_tol=1e-14)
+    T, kF = fourier_solve(prob.mesh, prob.mat.kappa_axis)
+    assert abs(r["kappa_fourier"] - kF) <= 1e-10 * abs(kF)
+    assert rel(r["T_L"], oracle_full(prob, T - T.mean())) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "channel", "sigma", "grad_y", "3d"])
+def test_lockstep_passes(P, name):
+    """Same Fourier start, the same K passes: kappa, kappa_face and T_L agree."""
+    w = CASES[name]()
+    K = 6
+    prob = Problem(w)
+    ref = source_iteration(prob, n_passes=K)
+    r = gpu_solve(P, w, outer_tol=0.0, max_outer=K, inner_tol=1e-14, fourier_tol=1e-14,
+                  max_inner=200)
+    assert r["outer_iters"] == K
+    assert abs(r["kappa"] - ref["kappa_cc"]) <= 1e-10 * abs(ref["kappa_cc"])
+    assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-10
+    Jref = np.zeros((w.n_cells, w.ndim))
+    Jref[prob.mesh.cells] = ref["J"]
+    assert rel(r["J"], Jref) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["cfg1", "bulk", "channel"])
+def test_converged(P, name):
+    w = CASES[name]()
+    prob = Problem(w)
+    ref = source_iteration(prob, tol=1e-12)
+    r = gpu_solve(P, w, outer_tol=1e-12, inner_tol=1e-14, fourier_tol=1e-14, max_inner=200)
+    assert r["status"] == 0
+    assert abs(r["kappa"] - ref["kappa_cc"]) <= 1e-10 * abs(ref["kappa_cc"])
+    assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
+    if name == "bulk":
+        assert abs(r["kappa"] - 150.0) < 1e-11 * 150.0
+
+
+def test_fp32_form_cfg1(P):
+    w = gen.config1()
+    prob = Problem(w)
+    ref = source_iteration(prob, tol=1e-12)
+    r32 = gpu_solve(P, w, precision=1, outer_tol=1e-9, inner_tol=1e-6, fourier_tol=1e-12)
+    r64 = gpu_solve(P, w, precision=0, outer_tol=1e-9, inner_tol=1e-13, fourier_tol=1e-12)
+    assert abs(r32["kappa"] - ref["kappa_cc"]) <= 1e-4 * ref["kappa_cc"]
+    assert abs(r32["kappa"] - r64["kappa"]) <= 1e-4 * r64["kappa"]
+    assert rel(r32["T_L"], oracle_full(prob, ref["T_L"])) < 1e-3
+
+
+def test_deterministic_fp64(P):
+    w = ragged_porous()
+    a = gpu_solve(P, w, outer_tol=1e-9)
+    b = gpu_solve(P, w, outer_tol=1e-9)
+    assert a["kappa"] == b["kappa"] and a["outer_iters"] == b["outer_iters"]
+    assert np.array_equal(a["T_L"], b["T_L"]) and np.array_equal(a["J"], b["J"])
+
+
+def test_workspace_too_small(P):
+    w = gen.small_2d(8, 6)
+    s = P.Solver.from_workload(w)
+    o = s.opts()
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.ObteError) as e:
+        P.obte.obte_solve(s.mesh, o, None, ws)
+    assert e.value.status == P.obte.OBTE_ERR_NOMEM

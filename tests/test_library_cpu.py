@@ -1,0 +1,104 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and rejects bad arguments on the host (no device work)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from tests._lib import ensure_built, header_functions
+from inputs import gen
+
+
+@pytest.fixture(scope="module")
+def L():
+    ensure_built()
+    from paper_2106_02764_amd import obte
+    return obte
+
+
+def test_exports_every_header_symbol(L):
+    lib = L.lib()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(L.EXPORTS), set(names) - set(L.EXPORTS)
+
+
+def test_default_opts(L):
+    o = L.default_opts()
+    assert o.precision == L.OBTE_FP64 and o.max_outer > 0 and o.inner_tol > 0
+    assert o.keep_state == 0
+
+
+def _desc_ok(**kw):
+    base = dict(ndim=2, n=(8, 6, 1), L=(1e-7, 1e-7, 1.0), solid=np.ones(48, np.uint8),
+                periodic=(1, 1, 0), grad_axis=0, dT_ext=1.0)
+    base.update(kw)
+    return base
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ndim=4), dict(n=(1, 6, 1)), dict(L=(0.0, 1e-7, 1.0)), dict(periodic=(0, 1, 0)),
+    dict(grad_axis=2), dict(solid=np.zeros(48, np.uint8)), dict(solid=np.full(48, 2, np.uint8)),
+    dict(n=(300, 2, 1), solid=np.ones(600, np.uint8)), dict(dT_ext=0.0),
+    dict(ndim=3, n=(4, 4, 20), solid=np.ones(320, np.uint8)),
+    dict(ndim=3, n=(4, 4, 2), periodic=(1, 1, 1), solid=np.ones(32, np.uint8)),
+])
+def test_mesh_create_rejects(L, bad):
+    d = _desc_ok(**bad)
+    with pytest.raises(L.ObteError) as e:
+        L.obte_mesh_create(d["ndim"], d["n"], d["L"], d["solid"], d["periodic"], d["grad_axis"], d["dT_ext"])
+    assert e.value.status == L.OBTE_ERR_ARG
+
+
+@pytest.mark.parametrize("w", [gen.config1(), gen.small_3d(5, 4, 3, solid=None),
+                               gen.small_2d(7, 5, solid=gen.stripe_mask(7, 5, 3))])
+def test_mesh_counts_match_face_classes(L, w):
+    from oracle.mesh import Mesh
+    h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
+    c = L.obte_mesh_counts(h)
+    me = Mesh(w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT, ndim=w.ndim)
+    assert c["n_cells"] == me.n_cells and c["n_solid"] == me.n_solid and c["n_walls"] == me.n_walls
+    L.obte_mesh_destroy(h)
+
+
+@pytest.mark.parametrize("bad", ["norm", "weights", "asym", "mfp", "kappa"])
+def test_material_set_rejects_on_host(L, bad):
+    w = gen.small_2d(8, 6, n_dir=8, n_mfp=3)
+    h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
+    mfp, dirs, dw, km = w.mfp.copy(), w.dirs.copy(), w.dir_w.copy(), w.kappa_m.copy()
+    if bad == "norm":
+        dirs[0] *= 1.1
+    elif bad == "weights":
+        dw[0] *= 2
+    elif bad == "asym":
+        dirs = np.array([[1.0, 0.0]] * 8)
+    elif bad == "mfp":
+        mfp[1] = -1.0
+    else:
+        km[0] = np.nan
+    with pytest.raises(L.ObteError) as e:
+        L.obte_material_set(h, mfp, dirs, dw, km)
+    assert e.value.status == L.OBTE_ERR_ARG
+    L.obte_mesh_destroy(h)
+
+
+def test_solve_state_errors_on_host(L):
+    w = gen.small_2d(8, 6)
+    h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
+    o = L.default_opts()
+    st = L.obte_stats()
+    lib = L.lib()
+    # no material yet -> state error before any device access
+    rc = lib.obte_solve(h, C.byref(o), None, C.c_void_p(4096), 1 << 20, None, None, None, C.byref(st))
+    assert rc == L.OBTE_ERR_STATE
+    o.precision = 7
+    rc = lib.obte_solve(h, C.byref(o), None, C.c_void_p(4096), 1 << 20, None, None, None, C.byref(st))
+    assert rc == L.OBTE_ERR_ARG
+    o = L.default_opts()
+    rc = lib.obte_solve(h, C.byref(o), None, None, 0, None, None, None, C.byref(st))
+    assert rc == L.OBTE_ERR_ARG
+    k = C.c_double()
+    assert lib.obte_kappa(h, C.byref(k), None) == L.OBTE_ERR_STATE
+    L.obte_mesh_destroy(h)
