@@ -83,7 +83,7 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * double.  OBTE_FP32: sweeps and Krylov vectors in float, while T_L, T_w,
  * kappa and the convergence test accumulate in double.
  * outer_tol: stop when |kappa_n - kappa_{n-1}| <= outer_tol |kappa_n|
- * (Algorithm 1).  inner_tol: relative residual of the periodic-wrap Krylov
+ * (Algorithm 1); 1 <= max_outer < 65536.  inner_tol: relative residual of the periodic-wrap Krylov
  * solve inside each (m,l) system.  init: 0 = Fourier first guess, 1 = resume
  * from the state left in the workspace by the previous call.
  * passes_per_graph: outer passes captured per HIP-graph replay (>= 1); the
@@ -92,7 +92,9 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * max_fourier: CG tolerance (relative residual) and iteration cap of the
  * Fourier first guess.  only_fourier: stop after the first guess.
  * keep_state: store the converged per-system solutions in the workspace (the
- * forward checkpoint obte_adjoint needs; n_systems * n_cells doubles). */
+ * forward checkpoint obte_adjoint needs; n_systems * n_cells doubles).
+ * timing: record HIP events on `stream` around every sweep, reduction and
+ * Fourier launch and report their summed durations in obte_stats. */
 typedef struct {
     int precision;
     double outer_tol;
@@ -106,6 +108,7 @@ typedef struct {
     double fourier_tol;
     int max_fourier;
     int keep_state;
+    int timing;
 } obte_solve_opts;
 
 typedef struct {
@@ -118,6 +121,10 @@ typedef struct {
     double kappa_fourier;
     double last_rel_change;
     int status;
+    int sweep_launches;       /* with opts.timing: pass-kernel launches timed */
+    double sweep_ms;          /* summed duration of the sweep kernel launches */
+    double reduce_ms;         /* summed duration of the per-pass reduction kernels */
+    double fourier_ms;        /* duration of the Fourier first guess */
 } obte_stats;
 
 /* Fill opts with defaults (FP64, outer_tol 1e-8, ...). */
@@ -168,8 +175,7 @@ obte_status obte_kappa(const obte_mesh* mesh, double* kappa_eff, double* kappa_p
  * Eq. (iter2)): M^T lambda = k by the transposed source iteration, then
  * d kappa / d sigma_i = -sum_ml lambda_iml (T_iml - T_L,i).  Requires a
  * converged obte_solve with keep_state = 1 on the same mesh, sigma pointer,
- * precision and workspace (else OBTE_ERR_STATE); max_outer must not exceed
- * that solve's.  stats->kappa receives p^T lambda, which equals kappa_cc at
+ * precision and workspace (else OBTE_ERR_STATE).  stats->kappa receives p^T lambda, which equals kappa_cc at
  * convergence.  dkappa_dsigma_dev: device, n_cells doubles, 0 in pores. */
 obte_status obte_adjoint(obte_mesh* mesh, const obte_solve_opts* opts, const double* sigma_dev,
                          void* workspace_dev, size_t workspace_bytes, void* stream,
@@ -188,8 +194,8 @@ obte_status obte_upwind_apply(const obte_mesh* mesh, int precision, int transpos
 /* Save / restore the outer-loop state (pass count, kappa history, T_L, T_w
  * and the wrap inflow vectors) of the last solve to a host file.  Loading
  * needs a mesh with the same geometry and material; a following obte_solve
- * with init = 1 and the same precision, waves_per_group, max_outer and
- * keep_state continues the iteration exactly where the saved run stopped. */
+ * with init = 1 and the same precision, waves_per_group and keep_state
+ * continues the iteration exactly where the saved run stopped. */
 obte_status obte_checkpoint_save(const obte_mesh* mesh, const void* workspace_dev,
                                  const char* path);
 obte_status obte_checkpoint_load(obte_mesh* mesh, void* workspace_dev, const char* path);

@@ -37,6 +37,10 @@ obte_status fail(obte_status st, const char* fmt, ...) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// kappa history capacity (passes); fixed so the workspace layout does not
+// depend on max_outer and a checkpoint can be resumed with a larger cap.
+constexpr int HIST_CAP = 1 << 16;
+
 }  // namespace
 
 struct obte_mesh {
@@ -98,7 +102,6 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     const size_t n_items = (size_t)m->n_dir * n_groups(m, waves);
     const size_t tsz = (o->precision == OBTE_FP32) ? 4 : 8;
     const size_t nwrap = (size_t)m->nx * m->nz;
-    const int max_outer = std::max(o->max_outer, 1);
     L.sigma = take(nc * 8);
     L.sigma_f = take(nc * 4);
     L.sT = take(2 * nc * 8);
@@ -118,11 +121,11 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.lam_phi = take(2 * nw * 8);
     L.grad = take(nc * 8);
     L.part_G = take(n_items * nc * 8);
-    // the parts below depend on precision / keep_state / max_outer
+    // the parts below depend on precision / keep_state
     L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
     L.Tstore = o->keep_state ? take((size_t)m->n_sys * nc * 8) : 0;
-    L.hist = take((size_t)max_outer * 8 + 8);
-    L.hist_face = take((size_t)max_outer * 8 + 8);
+    L.hist = take((size_t)HIST_CAP * 8);
+    L.hist_face = take((size_t)HIST_CAP * 8);
     L.total = off;
     return L;
 }
@@ -192,8 +195,8 @@ obte_status check_opts(const obte_solve_opts* o) {
     if (!o) return fail(OBTE_ERR_ARG, "opts is NULL");
     if (o->precision != OBTE_FP64 && o->precision != OBTE_FP32)
         return fail(OBTE_ERR_ARG, "precision must be OBTE_FP64 or OBTE_FP32");
-    if (!(o->outer_tol >= 0.0) || o->max_outer < 1)
-        return fail(OBTE_ERR_ARG, "outer_tol must be >= 0 and max_outer >= 1");
+    if (!(o->outer_tol >= 0.0) || o->max_outer < 1 || o->max_outer >= HIST_CAP)
+        return fail(OBTE_ERR_ARG, "outer_tol must be >= 0 and 1 <= max_outer < %d", HIST_CAP);
     if (!(o->inner_tol > 0.0) || o->max_inner < 0)
         return fail(OBTE_ERR_ARG, "inner_tol must be > 0 and max_inner >= 0");
     if (o->waves_per_group < 0 || o->waves_per_group > 8)
@@ -204,6 +207,45 @@ obte_status check_opts(const obte_solve_opts* o) {
     if (o->init != 0 && o->init != 1) return fail(OBTE_ERR_ARG, "init must be 0 or 1");
     return OBTE_OK;
 }
+
+// ---------------------------------------------------------------------------
+// live kernel timing with HIP events recorded on the caller's stream
+// ---------------------------------------------------------------------------
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;     // pairs: (start, stop) for sweep, then reduce, per pass
+    int K = 0;
+    double sweep_ms = 0, reduce_ms = 0, fourier_ms = 0;
+    int launches = 0;
+    hipEvent_t f0 = nullptr, f1 = nullptr;
+    obte_status init(int passes) {
+        K = passes;
+        ev.resize(4 * (size_t)K, nullptr);
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventCreate(&f0));
+        HIPCHK(hipEventCreate(&f1));
+        on = true;
+        return OBTE_OK;
+    }
+    // after the stream synchronised: accumulate the K passes just replayed
+    obte_status collect(int passes_done) {
+        for (int k = 0; k < passes_done && k < K; ++k) {
+            float a = 0, b = 0;
+            if (hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]) != hipSuccess) continue;
+            if (hipEventElapsedTime(&b, ev[4 * k + 2], ev[4 * k + 3]) != hipSuccess) continue;
+            sweep_ms += a;
+            reduce_ms += b;
+            ++launches;
+        }
+        return OBTE_OK;
+    }
+    ~Timer() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (f0) (void)hipEventDestroy(f0);
+        if (f1) (void)hipEventDestroy(f1);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // the outer loop shared by obte_solve, obte_solve_batch and obte_adjoint
@@ -286,24 +328,30 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     return OBTE_OK;
 }
 
-obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st) {
+obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Timer* tm, int k) {
+    if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k], st));
     HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items, (int)R.items.size(),
                              R.waves, pp, R.lds, st));
+    if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 1], st));
+    if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 2], st));
     HIPCHK(launch_reduce_pass(R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
     HIPCHK(launch_finalize(R.d_views, (int)R.views.size(), pp, st));
+    if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 3], st));
     return OBTE_OK;
 }
 
 // Replays graphs of K passes until every geometry reports done.
-obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st, int max_outer) {
+obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st, int max_outer,
+                       Timer* tm) {
     const int n = (int)R.views.size();
     std::vector<int> ctrl(CTRL_N);
+    if (tm && tm->on && tm->K < K) return fail(OBTE_ERR_STATE, "timer sized for fewer passes");
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     if (K > 1) {
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         obte_status s = OBTE_OK;
-        for (int k = 0; k < K && s == OBTE_OK; ++k) s = enqueue_pass(R, pp, st);
+        for (int k = 0; k < K && s == OBTE_OK; ++k) s = enqueue_pass(R, pp, st, tm, k);
         hipError_t e = hipStreamEndCapture(st, &graph);
         if (s != OBTE_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
         if (e != hipSuccess) return fail(OBTE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -321,7 +369,7 @@ obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st
             if (e != hipSuccess) { out = fail(OBTE_ERR_HIP, "graph launch: %s", hipGetErrorString(e)); break; }
             launched += K;
         } else {
-            out = enqueue_pass(R, pp, st);
+            out = enqueue_pass(R, pp, st, tm, 0);
             if (out != OBTE_OK) break;
             launched += 1;
         }
@@ -333,6 +381,7 @@ obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st
             if (e != hipSuccess) { out = fail(OBTE_ERR_HIP, "readback: %s", hipGetErrorString(e)); all_done = true; break; }
             if (!ctrl[CTRL_DONE]) all_done = false;
         }
+        if (tm && tm->on && out == OBTE_OK) tm->collect(exec ? K : 1);
         if (out != OBTE_OK || all_done) break;
         if (launched > max_outer + K + 2) { out = fail(OBTE_ERR_STATE, "outer loop did not terminate"); break; }
     }
@@ -388,8 +437,16 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         }
         HIPCHK(hipMemsetAsync(ws + L.iters, 0, 2 * (size_t)m->n_sys * 8, st));
     }
+    Timer tm;
+    const int K = (o->passes_per_graph <= 1 || !st) ? 1 : o->passes_per_graph;
+    if (o->timing) {
+        s = tm.init(K);
+        if (s != OBTE_OK) return s;
+    }
     if (o->init == 0) {
+        if (tm.on) HIPCHK(hipEventRecord(tm.f0, st));
         HIPCHK(launch_fourier(R.d_views, n, o->fourier_tol, o->max_fourier, st));
+        if (tm.on) HIPCHK(hipEventRecord(tm.f1, st));
     } else {
         // resume: clear the done / converged flags, keep the pass count
         for (int i = 0; i < n; ++i) {
@@ -400,8 +457,7 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
     }
     if (!o->only_fourier) {
         PassParams pp = base_params(o);
-        const int K = (o->passes_per_graph <= 1 || !st) ? 1 : o->passes_per_graph;
-        s = outer_loop(R, pp, K, st, o->max_outer);
+        s = outer_loop(R, pp, K, st, o->max_outer, &tm);
         if (s != OBTE_OK) return s;
         // replay the last pass's final sweep for the flux map / stored state
         if ((J_out || keep_T) && n == 1) {
@@ -466,6 +522,14 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
                                                   std::fabs(hist[passes - 1])
                                             : 0.0;
             S.status = si;
+            S.sweep_launches = tm.launches;
+            S.sweep_ms = tm.sweep_ms;
+            S.reduce_ms = tm.reduce_ms;
+            S.fourier_ms = 0.0;
+            if (tm.on && o->init == 0) {
+                float f = 0;
+                if (hipEventElapsedTime(&f, tm.f0, tm.f1) == hipSuccess) S.fourier_ms = f;
+            }
         }
         if (kappa_out) kappa_out[i] = m->kappa;
         if (si != OBTE_OK && ret == OBTE_OK) ret = si;
@@ -496,6 +560,7 @@ void obte_default_opts(obte_solve_opts* o) {
     o->fourier_tol = 1e-13;
     o->max_fourier = 20000;
     o->keep_state = 0;
+    o->timing = 0;
 }
 
 obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
@@ -714,8 +779,6 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
         m->last_precision != o->precision)
         return fail(OBTE_ERR_STATE, "obte_adjoint needs a converged obte_solve with keep_state = 1 "
                                     "and the same sigma, precision and workspace");
-    if (o->max_outer > m->last_max_outer)
-        return fail(OBTE_ERR_ARG, "adjoint max_outer must not exceed the forward solve's");
     hipStream_t st = (hipStream_t)stream;
     Run R;
     obte_solve_opts oo = *o;
@@ -738,7 +801,9 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     PassParams pp = base_params(o);
     pp.adjoint = 1;
     const int K = (o->passes_per_graph <= 1 || !st) ? 1 : o->passes_per_graph;
-    s = outer_loop(R, pp, K, st, o->max_outer);
+    Timer tm;
+    if (o->timing && (s = tm.init(K)) != OBTE_OK) return s;
+    s = outer_loop(R, pp, K, st, o->max_outer, &tm);
     if (s != OBTE_OK) return s;
     HIPCHK(launch_output(m->d_geom, 1, nullptr, nullptr, grad_dev, st));
     std::vector<int> ctrl(CTRL_N);
@@ -761,6 +826,10 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
         stats->kappa_fourier = m->kappa_fourier;
         stats->last_rel_change = passes >= 2 ? std::fabs(hist[passes - 1] - hist[passes - 2]) / std::fabs(hist[passes - 1]) : 0.0;
         stats->status = ctrl[CTRL_CONVERGED] ? OBTE_OK : OBTE_ERR_NOT_CONVERGED;
+        stats->sweep_launches = tm.launches;
+        stats->sweep_ms = tm.sweep_ms;
+        stats->reduce_ms = tm.reduce_ms;
+        stats->fourier_ms = 0.0;
     }
     if (ctrl[CTRL_NONFINITE]) return fail(OBTE_ERR_NUMERIC, "non-finite adjoint functional");
     if (!ctrl[CTRL_CONVERGED]) return fail(OBTE_ERR_NOT_CONVERGED, "adjoint: no convergence in %d passes", passes);

@@ -26,6 +26,9 @@ class Solver:
         self.n_dir = len(dir_w)
         self.workspace = None
         self.last_stats = None
+        # a stream of our own (default priority) so the outer loop can be
+        # captured into HIP graphs; torch's legacy default stream cannot
+        self.stream = torch.cuda.Stream(device=self.device) if self.device.type == "cuda" else None
 
     @classmethod
     def from_workload(cls, w, device="cuda"):
@@ -48,13 +51,20 @@ class Solver:
             return sigma.to(device=self.device, dtype=torch.float64).contiguous()
         return torch.as_tensor(np.asarray(sigma, np.float64), device=self.device).contiguous()
 
+    def _stream(self, stream):
+        s = stream or self.stream
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        return s
+
     def solve(self, opts=None, sigma=None, want_T_L=True, want_J=False, stream=None, **kw):
         opts = opts or self.opts(**kw)
         ws = self.ensure_workspace(opts)
         T_L = torch.empty(self.n_cells, dtype=torch.float64, device=self.device) if want_T_L else None
         J = torch.empty(self.n_cells * self.ndim, dtype=torch.float64, device=self.device) if want_J else None
         self._sigma = self.sigma_tensor(sigma)
-        st = _o.obte_solve(self.mesh, opts, self._sigma, ws, stream=stream, T_L=T_L, J=J)
+        s = self._stream(stream)
+        st = _o.obte_solve(self.mesh, opts, self._sigma, ws, stream=s, T_L=T_L, J=J)
+        torch.cuda.current_stream(self.device).wait_stream(s)
         self.last_stats = st
         out = st.as_dict()
         if want_T_L:
@@ -68,7 +78,9 @@ class Solver:
 
     def adjoint(self, opts, stream=None):
         g = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
-        st = _o.obte_adjoint(self.mesh, opts, self._sigma, self.workspace, g, stream=stream)
+        s = self._stream(stream)
+        st = _o.obte_adjoint(self.mesh, opts, self._sigma, self.workspace, g, stream=s)
+        torch.cuda.current_stream(self.device).wait_stream(s)
         return g, st.as_dict()
 
     def apply(self, x, sys_ids, precision=0, transpose=False, sigma=None, stream=None):
@@ -77,7 +89,9 @@ class Solver:
         y = torch.empty_like(x)
         ids = torch.as_tensor(np.asarray(sys_ids, np.int32), device=self.device)
         sg = self.sigma_tensor(sigma)
-        _o.obte_upwind_apply(self.mesh, precision, transpose, sg, ids, x, y, stream=stream)
+        s = self._stream(stream)
+        _o.obte_upwind_apply(self.mesh, precision, transpose, sg, ids, x, y, stream=s)
+        torch.cuda.current_stream(self.device).wait_stream(s)
         return y
 
     def checkpoint_save(self, path):
@@ -121,5 +135,8 @@ def solve_batch(solvers, opts, sigmas=None, device="cuda"):
     sizes = [_o.obte_workspace_size(s.mesh, opts) for s in solvers]
     ws = torch.empty(sum(sizes), dtype=torch.uint8, device=device)
     sg = [None] * len(solvers) if sigmas is None else [s.sigma_tensor(x) for s, x in zip(solvers, sigmas)]
-    k, st = _o.obte_solve_batch([s.mesh for s in solvers], opts, sg, ws)
+    stream = solvers[0].stream
+    stream.wait_stream(torch.cuda.current_stream())
+    k, st = _o.obte_solve_batch([s.mesh for s in solvers], opts, sg, ws, stream=stream)
+    torch.cuda.current_stream().wait_stream(stream)
     return k, [x.as_dict() for x in st]

@@ -88,10 +88,11 @@ def test_lockstep_passes(P, name):
     w = CASES[name]()
     K = 6
     prob = Problem(w)
-    ref = source_iteration(prob, n_passes=K)
     r = gpu_solve(P, w, outer_tol=0.0, max_outer=K, inner_tol=1e-14, fourier_tol=1e-14,
                   max_inner=200)
-    assert r["outer_iters"] == K
+    # an exactly repeated kappa stops the loop early (Algorithm 1: error <= tol)
+    assert 2 <= r["outer_iters"] <= K
+    ref = source_iteration(prob, n_passes=r["outer_iters"])
     assert abs(r["kappa"] - ref["kappa_cc"]) <= 1e-10 * abs(ref["kappa_cc"])
     assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
     assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-10
