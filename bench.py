@@ -75,16 +75,27 @@ def time_solves(P, solver, opts, steps, warmup):
 
 
 def calibrate(P, solver, prec, kref, inner_tol):
-    """Loosest outer tolerance whose kappa is within 1e-4 of the reference
-    (Algorithm 1 stops on the relative change, which understates the error)."""
-    for tol in (3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7):
-        o = solver.opts(precision=prec, outer_tol=tol, inner_tol=inner_tol, fourier_tol=1e-8,
-                        timing=1, passes_per_graph=4)
-        out = solver.solve(o, want_T_L=False)
-        err = abs(out["kappa"] - kref) / abs(kref)
-        if err <= 0.5e-4:
-            return o, err
-    return o, err
+    """Fastest configuration (inner-iteration cap per pass, loosest outer
+    tolerance) whose kappa is within 1e-4 of the reference; Algorithm 1 stops
+    on the relative change, which understates the error.  Untimed."""
+    import torch
+    best = None
+    for max_inner in (2, 4, 64):
+        for tol in (3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7):
+            o = solver.opts(precision=prec, outer_tol=tol, inner_tol=inner_tol, fourier_tol=1e-8,
+                            passes_per_graph=4, max_inner=max_inner)
+            solver.solve(o, want_T_L=False)           # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = solver.solve(o, want_T_L=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            err = abs(out["kappa"] - kref) / abs(kref)
+            if err <= 0.5e-4 and out["status"] == 0:
+                if best is None or dt < best[2]:
+                    best = (o, err, dt)
+                break
+    return best[0], best[1]
 
 
 def cpu_baseline(w, seconds, passes):
@@ -156,9 +167,20 @@ def main():
     res = {}
     for name, prec, itol in (("fp32", 1, 1e-5), ("fp64", 0, 1e-8)):
         o, cal_err = calibrate(P, solver, prec, kref, itol)
+        # leg 1: the throughput (pass kernels replayed as HIP graphs)
         r = time_solves(P, solver, o, a.steps, a.warmup)
+        # leg 2: the same solves with HIP events around every kernel launch on
+        # the library's stream (direct launches), for the per-kernel durations
+        ot = solver.opts(**{f: getattr(o, f) for f, _ in o._fields_})
+        ot.timing = 1
+        rt = time_solves(P, solver, ot, a.steps, 0)
+        for key in ("sweep_ms", "reduce_ms", "fourier_ms", "launches"):
+            r[key] = rt[key]
+        r["timed_leg_solves_per_s"] = a.steps / rt["seconds"]
+        r["sweeps_timed_leg"] = rt["sweeps"]
         r["outer_tol"] = o.outer_tol
         r["inner_tol"] = o.inner_tol
+        r["max_inner"] = o.max_inner
         r["kappa_rel_err_vs_fp64_ref"] = abs(r["kappa"] - kref) / abs(kref)
         if golden:
             r["kappa_rel_err_vs_oracle"] = abs(r["kappa"] - golden["kappa_cc"]) / golden["kappa_cc"]
@@ -169,10 +191,10 @@ def main():
     main_r = res["fp32"]
     # roofline of the dominant kernel (the sweep pass): algorithmic flops per
     # launch = sweeps in that launch x solid cells x flops per cell-sweep
-    sweeps_per_launch = main_r["sweeps"] / max(main_r["launches"], 1)
+    sweeps_per_launch = main_r["sweeps_timed_leg"] / max(main_r["launches"], 1)
     flops_launch = sweeps_per_launch * w.n_solid * FLOPS_PER_CELL_SWEEP[w.ndim]
     avg_ms = main_r["sweep_ms"] / max(main_r["launches"], 1)
-    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK["fp32_vector_tflops"],
             "unit": "TFLOP/s", "frac": achieved / PEAK["fp32_vector_tflops"], "traffic": None,
             "kernel": "k_sweep_pass<float,2,1>", "avg_launch_ms": avg_ms,

@@ -84,7 +84,10 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * kappa and the convergence test accumulate in double.
  * outer_tol: stop when |kappa_n - kappa_{n-1}| <= outer_tol |kappa_n|
  * (Algorithm 1); 1 <= max_outer < 65536.  inner_tol: relative residual of the periodic-wrap Krylov
- * solve inside each (m,l) system.  init: 0 = Fourier first guess, 1 = resume
+ * solve inside each (m,l) system; max_inner caps its iterations per pass
+ * (a small cap carries the rest of the wrap solve into later passes, and
+ * the stop then also requires every wrap residual <= max(inner_tol,
+ * outer_tol)).  init: 0 = Fourier first guess, 1 = resume
  * from the state left in the workspace by the previous call.
  * passes_per_graph: outer passes captured per HIP-graph replay (>= 1); the
  * host reads kappa back once per replay.  waves_per_group: systems that share
@@ -93,8 +96,12 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * Fourier first guess.  only_fourier: stop after the first guess.
  * keep_state: store the converged per-system solutions in the workspace (the
  * forward checkpoint obte_adjoint needs; n_systems * n_cells doubles).
+ * recycle: Krylov pairs kept per system across outer passes (0..32): the
+ * periodic-wrap matrix of a system is fixed during a solve, so earlier
+ * products project most of a later pass's wrap residual away.
  * timing: record HIP events on `stream` around every sweep, reduction and
- * Fourier launch and report their summed durations in obte_stats. */
+ * Fourier launch and report their summed durations in obte_stats (the pass
+ * kernels are then launched directly instead of through a HIP graph). */
 typedef struct {
     int precision;
     double outer_tol;
@@ -108,6 +115,7 @@ typedef struct {
     double fourier_tol;
     int max_fourier;
     int keep_state;
+    int recycle;
     int timing;
 } obte_solve_opts;
 
@@ -120,6 +128,7 @@ typedef struct {
     double kappa_face;        /* upwind flux through the hot contact plane */
     double kappa_fourier;
     double last_rel_change;
+    double wrap_residual;     /* max relative wrap-row residual of the last pass */
     int status;
     int sweep_launches;       /* with opts.timing: pass-kernel launches timed */
     double sweep_ms;          /* summed duration of the sweep kernel launches */

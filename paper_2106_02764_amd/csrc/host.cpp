@@ -37,6 +37,16 @@ obte_status fail(obte_status st, const char* fmt, ...) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Cleanup calls whose failure must not abort the caller: report them when
+// OBTE_DEBUG is set and clear HIP's per-thread last error so the next
+// launch check sees only its own status.
+void soft(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        if (getenv("OBTE_DEBUG")) fprintf(stderr, "obte: %s: %s\n", what, hipGetErrorString(e));
+        (void)hipGetLastError();
+    }
+}
+
 // kappa history capacity (passes); fixed so the workspace layout does not
 // depend on max_outer and a checkpoint can be resumed with a larger cap.
 constexpr int HIST_CAP = 1 << 16;
@@ -69,7 +79,7 @@ struct obte_mesh {
     double kappa = 0, kappa_face = 0, kappa_fourier = 0;
     std::vector<double> kappa_per_mfp;
     GeomDev host_view{};
-    int last_precision = 0, last_waves = 0, last_max_outer = 0, last_keep = 0;
+    int last_precision = 0, last_waves = 0, last_max_outer = 0, last_keep = 0, last_recycle = 0;
 };
 
 namespace {
@@ -79,7 +89,8 @@ namespace {
 // ---------------------------------------------------------------------------
 struct Layout {
     size_t sigma, sigma_f, sT, Tw, T_L, U, part_TL, part_Tw, part_J, ksys, kfsys, iters, sweeps,
-        hist, hist_face, ctrl, fx, fscal, Tstore, lam_psi, lam_phi, grad, part_G, total;
+        hist, hist_face, ctrl, fx, fscal, Tstore, lam_psi, lam_phi, grad, part_G, bnd, mem, mem_count,
+        mem_bytes, wres, wres_hist, total;
 };
 
 int auto_waves(const obte_mesh* m) {
@@ -121,17 +132,24 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.lam_phi = take(2 * nw * 8);
     L.grad = take(nc * 8);
     L.part_G = take(n_items * nc * 8);
-    // the parts below depend on precision / keep_state
+    L.bnd = take(4 * (size_t)m->nf * nc * 8);
+    L.mem_count = take(2 * (size_t)m->n_sys * 4);
+    L.wres = take((size_t)m->n_sys * 8);
+    // the parts below depend on precision / recycle / keep_state
     L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
+    L.mem_bytes = 2 * (size_t)m->n_sys * 2 * (size_t)std::max(o->recycle, 0) * nwrap * tsz;
+    L.mem = take(L.mem_bytes);
     L.Tstore = o->keep_state ? take((size_t)m->n_sys * nc * 8) : 0;
     L.hist = take((size_t)HIST_CAP * 8);
     L.hist_face = take((size_t)HIST_CAP * 8);
+    L.wres_hist = take((size_t)HIST_CAP * 8);
     L.total = off;
     return L;
 }
 
-GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves) {
+GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int recycle) {
     GeomDev g{};
+    g.mem_R = recycle;
     g.nx = m->nx; g.ny = m->ny; g.nz = m->nz; g.ndim = m->ndim; g.nf = m->nf;
     g.ncells = m->ncells; g.nwalls = m->nwalls; g.nwrap = m->nx * m->nz;
     for (int a = 0; a < 3; ++a) { g.periodic[a] = m->periodic[a]; g.h[a] = m->h[a]; g.L[a] = m->L[a]; }
@@ -168,13 +186,18 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves) {
         g.lam_phi = (double*)(ws + L.lam_phi);
         g.gradient = (double*)(ws + L.grad);
         g.part_G = (double*)(ws + L.part_G);
+        g.bnd = (double*)(ws + L.bnd);
+        g.mem = ws + L.mem;
+        g.mem_count = (int*)(ws + L.mem_count);
+        g.wres = (double*)(ws + L.wres);
+        g.wres_hist = (double*)(ws + L.wres_hist);
     }
     return g;
 }
 
 template <typename T>
 obte_status upload(T** dst, const std::vector<T>& src) {
-    if (*dst) { (void)hipFree(*dst); *dst = nullptr; }
+    if (*dst) { soft(hipFree(*dst), "hipFree(table)"); *dst = nullptr; }
     const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
     HIPCHK(hipMalloc((void**)dst, bytes));
     if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -185,7 +208,7 @@ void free_dev(obte_mesh* m) {
     void* ptrs[] = {m->d_fc, m->d_wall_idx, m->d_wall_cell, m->d_wall_face, m->d_mfp, m->d_dirs,
                     m->d_D, m->d_S, m->d_wout, m->d_kax, m->d_geom};
     for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+        if (p) soft(hipFree(p), "hipFree(table)");
     m->d_fc = nullptr; m->d_wall_idx = m->d_wall_cell = m->d_wall_face = nullptr;
     m->d_mfp = m->d_dirs = m->d_D = m->d_S = m->d_wout = m->d_kax = nullptr;
     m->d_geom = nullptr;
@@ -205,6 +228,7 @@ obte_status check_opts(const obte_solve_opts* o) {
     if (!(o->fourier_tol > 0.0) || o->max_fourier < 0)
         return fail(OBTE_ERR_ARG, "fourier_tol must be > 0 and max_fourier >= 0");
     if (o->init != 0 && o->init != 1) return fail(OBTE_ERR_ARG, "init must be 0 or 1");
+    if (o->recycle < 0 || o->recycle > 32) return fail(OBTE_ERR_ARG, "recycle must be in 0..32");
     return OBTE_OK;
 }
 
@@ -231,8 +255,12 @@ struct Timer {
     obte_status collect(int passes_done) {
         for (int k = 0; k < passes_done && k < K; ++k) {
             float a = 0, b = 0;
-            if (hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]) != hipSuccess) continue;
-            if (hipEventElapsedTime(&b, ev[4 * k + 2], ev[4 * k + 3]) != hipSuccess) continue;
+            hipError_t e1 = hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]);
+            hipError_t e2 = hipEventElapsedTime(&b, ev[4 * k + 2], ev[4 * k + 3]);
+            if (e1 != hipSuccess || e2 != hipSuccess) {
+                soft(e1 != hipSuccess ? e1 : e2, "hipEventElapsedTime");
+                continue;
+            }
             sweep_ms += a;
             reduce_ms += b;
             ++launches;
@@ -241,9 +269,9 @@ struct Timer {
     }
     ~Timer() {
         for (auto e : ev)
-            if (e) (void)hipEventDestroy(e);
-        if (f0) (void)hipEventDestroy(f0);
-        if (f1) (void)hipEventDestroy(f1);
+            if (e) soft(hipEventDestroy(e), "hipEventDestroy");
+        if (f0) soft(hipEventDestroy(f0), "hipEventDestroy");
+        if (f1) soft(hipEventDestroy(f1), "hipEventDestroy");
     }
 };
 
@@ -260,8 +288,8 @@ struct Run {
     size_t lds = 0;
     int max_cells = 0, max_walls = 0;
     ~Run() {
-        if (d_views) (void)hipFree(d_views);
-        if (d_items) (void)hipFree(d_items);
+        if (d_views) soft(hipFree(d_views), "hipFree(views)");
+        if (d_items) soft(hipFree(d_items), "hipFree(items)");
     }
 };
 
@@ -293,7 +321,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         obte_mesh* m = meshes[gi];
         Layout L = make_layout(m, o, W);
         if (offsets) offsets->push_back(off);
-        GeomDev v = make_view(m, ws + off, L, W);
+        GeomDev v = make_view(m, ws + off, L, W, o->recycle);
         v.item0 = (int)R.items.size();
         const int ng = n_groups(m, W);
         for (int l = 0; l < m->n_dir; ++l)
@@ -321,6 +349,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     const int ndim = R.nzmax > 1 ? 3 : 2;
     const int NV = 1 + 2 * ndim;
     R.lds = (size_t)W * NV * rowlen * sizeof(double);
+    if (R.nzmax > 1) R.lds += (size_t)W * 16 * rowlen * (R.precision == OBTE_FP32 ? 4 : 8);   // z-plane rows
     HIPCHK(hipMalloc((void**)&R.d_views, R.views.size() * sizeof(GeomDev)));
     HIPCHK(hipMalloc((void**)&R.d_items, R.items.size() * sizeof(Item)));
     HIPCHK(hipMemcpy(R.d_views, R.views.data(), R.views.size() * sizeof(GeomDev), hipMemcpyHostToDevice));
@@ -353,11 +382,11 @@ obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st
         obte_status s = OBTE_OK;
         for (int k = 0; k < K && s == OBTE_OK; ++k) s = enqueue_pass(R, pp, st, tm, k);
         hipError_t e = hipStreamEndCapture(st, &graph);
-        if (s != OBTE_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
+        if (s != OBTE_OK) { if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy"); return s; }
         if (e != hipSuccess) return fail(OBTE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
+            soft(hipGraphDestroy(graph), "hipGraphDestroy");
             return fail(OBTE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
         }
     }
@@ -385,8 +414,8 @@ obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st
         if (out != OBTE_OK || all_done) break;
         if (launched > max_outer + K + 2) { out = fail(OBTE_ERR_STATE, "outer loop did not terminate"); break; }
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    if (exec) soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
+    if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy");
     return out;
 }
 
@@ -434,18 +463,22 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         if (o->init == 0) {
             const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
             HIPCHK(hipMemsetAsync(ws + L.U, 0, 2 * (size_t)m->n_sys * m->nx * m->nz * tsz, st));
+            HIPCHK(hipMemsetAsync(ws + L.mem_count, 0, 2 * (size_t)m->n_sys * 4, st));
         }
         HIPCHK(hipMemsetAsync(ws + L.iters, 0, 2 * (size_t)m->n_sys * 8, st));
+        HIPCHK(hipMemsetAsync(ws + L.wres, 0, (size_t)m->n_sys * 8, st));
     }
     Timer tm;
-    const int K = (o->passes_per_graph <= 1 || !st) ? 1 : o->passes_per_graph;
+    // events recorded inside a captured graph cannot be timed: timing runs
+    // launch the pass kernels directly
+    const int K = (o->passes_per_graph <= 1 || !st || o->timing) ? 1 : o->passes_per_graph;
     if (o->timing) {
         s = tm.init(K);
         if (s != OBTE_OK) return s;
     }
     if (o->init == 0) {
         if (tm.on) HIPCHK(hipEventRecord(tm.f0, st));
-        HIPCHK(launch_fourier(R.d_views, n, o->fourier_tol, o->max_fourier, st));
+        HIPCHK(launch_fourier(R.d_views, n, R.max_cells, o->fourier_tol, o->max_fourier, st));
         if (tm.on) HIPCHK(hipEventRecord(tm.f1, st));
     } else {
         // resume: clear the done / converged flags, keep the pass count
@@ -482,11 +515,13 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         HIPCHK(hipMemcpyAsync(fs, v.fscal, sizeof fs, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         const int passes = o->only_fourier ? 0 : ctrl[CTRL_PASS];
-        std::vector<double> hist(passes + 1, 0.0), histf(passes + 1, 0.0), ks(m->n_sys), kfs(m->n_sys);
+        std::vector<double> hist(passes + 1, 0.0), histf(passes + 1, 0.0), ks(m->n_sys), kfs(m->n_sys),
+            wrh(passes + 1, 0.0);
         std::vector<long long> its(m->n_sys), sws(m->n_sys);
         if (passes > 0) {
             HIPCHK(hipMemcpy(hist.data(), v.hist, passes * sizeof(double), hipMemcpyDeviceToHost));
             HIPCHK(hipMemcpy(histf.data(), v.hist_face, passes * sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(wrh.data(), v.wres_hist, passes * sizeof(double), hipMemcpyDeviceToHost));
             HIPCHK(hipMemcpy(ks.data(), v.ksys, m->n_sys * sizeof(double), hipMemcpyDeviceToHost));
             HIPCHK(hipMemcpy(its.data(), v.iters, m->n_sys * sizeof(long long), hipMemcpyDeviceToHost));
             HIPCHK(hipMemcpy(sws.data(), v.sweeps, m->n_sys * sizeof(long long), hipMemcpyDeviceToHost));
@@ -504,6 +539,7 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         m->last_waves = R.waves;
         m->last_max_outer = o->max_outer;
         m->last_keep = o->keep_state;
+        m->last_recycle = o->recycle;
         obte_status si = OBTE_OK;
         if (ctrl[CTRL_NONFINITE]) si = fail(OBTE_ERR_NUMERIC, "non-finite kappa in mesh %d", i);
         else if (!o->only_fourier && !ctrl[CTRL_CONVERGED])
@@ -522,13 +558,16 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
                                                   std::fabs(hist[passes - 1])
                                             : 0.0;
             S.status = si;
+            S.wrap_residual = passes > 0 ? wrh[passes - 1] : 0.0;
             S.sweep_launches = tm.launches;
             S.sweep_ms = tm.sweep_ms;
             S.reduce_ms = tm.reduce_ms;
             S.fourier_ms = 0.0;
             if (tm.on && o->init == 0) {
                 float f = 0;
-                if (hipEventElapsedTime(&f, tm.f0, tm.f1) == hipSuccess) S.fourier_ms = f;
+                hipError_t e = hipEventElapsedTime(&f, tm.f0, tm.f1);
+                if (e == hipSuccess) S.fourier_ms = f;
+                else soft(e, "hipEventElapsedTime");
             }
         }
         if (kappa_out) kappa_out[i] = m->kappa;
@@ -560,6 +599,7 @@ void obte_default_opts(obte_solve_opts* o) {
     o->fourier_tol = 1e-13;
     o->max_fourier = 20000;
     o->keep_state = 0;
+    o->recycle = 0;
     o->timing = 0;
 }
 
@@ -723,7 +763,7 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     if ((s = upload(&m->d_wout, m->wout)) != OBTE_OK) return s;
     if ((s = upload(&m->d_kax, m->kappa_axis)) != OBTE_OK) return s;
     HIPCHK(hipMalloc((void**)&m->d_geom, sizeof(GeomDev)));
-    GeomDev v = make_view(m, nullptr, Layout{}, 0);
+    GeomDev v = make_view(m, nullptr, Layout{}, 0, 0);
     HIPCHK(hipMemcpy(m->d_geom, &v, sizeof v, hipMemcpyHostToDevice));
     m->host_view = v;
     m->has_material = true;
@@ -784,6 +824,7 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     obte_solve_opts oo = *o;
     oo.waves_per_group = m->last_waves;
     oo.keep_state = 1;
+    oo.recycle = m->last_recycle;
     obte_mesh* mp = m;
     s = build_run(R, &mp, 1, &oo, (char*)workspace, nullptr);
     if (s != OBTE_OK) return s;
@@ -796,11 +837,15 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
     const size_t half = (size_t)m->n_sys * m->nx * m->nz * tsz;
     HIPCHK(hipMemsetAsync(ws + L.U + half, 0, half, st));
+    HIPCHK(hipMemsetAsync(ws + L.mem_count + (size_t)m->n_sys * 4, 0, (size_t)m->n_sys * 4, st));
+    HIPCHK(hipMemsetAsync(ws + L.bnd + 2 * (size_t)m->nf * m->ncells * 8, 0,
+                          2 * (size_t)m->nf * m->ncells * 8, st));
     HIPCHK(hipMemsetAsync(ws + L.iters, 0, 2 * (size_t)m->n_sys * 8, st));
+    HIPCHK(hipMemsetAsync(ws + L.wres, 0, (size_t)m->n_sys * 8, st));
     HIPCHK(hipMemsetAsync(ws + L.ctrl, 0, CTRL_N * sizeof(int), st));
     PassParams pp = base_params(o);
     pp.adjoint = 1;
-    const int K = (o->passes_per_graph <= 1 || !st) ? 1 : o->passes_per_graph;
+    const int K = (o->passes_per_graph <= 1 || !st || o->timing) ? 1 : o->passes_per_graph;
     Timer tm;
     if (o->timing && (s = tm.init(K)) != OBTE_OK) return s;
     s = outer_loop(R, pp, K, st, o->max_outer, &tm);
@@ -857,7 +902,7 @@ obte_status obte_checkpoint_save(const obte_mesh* m, const void* workspace, cons
     const GeomDev& v = m->host_view;
     if (m->last_ws != workspace) return fail(OBTE_ERR_ARG, "workspace differs from the last solve's");
     const int hdr[10] = {0x4f425445, m->ncells, m->nwalls, m->n_sys, m->nx * m->nz, m->last_precision,
-                         m->last_waves, m->last_max_outer, m->last_keep, 0};
+                         m->last_waves, m->last_max_outer, m->last_keep, m->last_recycle};
     fwrite(hdr, sizeof hdr, 1, f);
     auto dump = [&](const void* dptr, size_t bytes) -> bool {
         std::vector<char> buf(bytes);
@@ -870,7 +915,10 @@ obte_status obte_checkpoint_save(const obte_mesh* m, const void* workspace, cons
     const size_t tsz = m->last_precision == OBTE_FP32 ? 4 : 8;
     ok = ok && dump(v.T_L, (size_t)m->ncells * 8) && dump(v.sT, 2 * (size_t)m->ncells * 8) &&
          dump(v.Tw, 2 * (size_t)std::max(m->nwalls, 1) * 8) &&
-         dump(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz);
+         dump(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz) &&
+         dump(v.bnd, 2 * (size_t)m->nf * m->ncells * 8) && dump(v.mem_count, (size_t)m->n_sys * 4) &&
+         (m->last_recycle == 0 ||
+          dump(v.mem, (size_t)m->n_sys * 2 * m->last_recycle * m->nx * m->nz * tsz));
     const int passes = ctrl[CTRL_PASS];
     fwrite(&passes, sizeof passes, 1, f);
     ok = ok && (passes == 0 || dump(v.hist, (size_t)passes * 8)) && (passes == 0 || dump(v.hist_face, (size_t)passes * 8));
@@ -895,7 +943,8 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     o.precision = hdr[5];
     o.max_outer = hdr[7];
     o.keep_state = hdr[8];
-    const GeomDev v = make_view(m, (char*)workspace, make_layout(m, &o, hdr[6]), hdr[6]);
+    o.recycle = hdr[9];
+    const GeomDev v = make_view(m, (char*)workspace, make_layout(m, &o, hdr[6]), hdr[6], hdr[9]);
     auto load = [&](void* dptr, size_t bytes) -> bool {
         std::vector<char> buf(bytes);
         if (fread(buf.data(), 1, bytes, f) != bytes) return false;
@@ -904,7 +953,9 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     const size_t tsz = m->last_precision == OBTE_FP32 ? 4 : 8;
     bool ok = load(v.ctrl, CTRL_N * sizeof(int)) && load(v.T_L, (size_t)m->ncells * 8) &&
               load(v.sT, 2 * (size_t)m->ncells * 8) && load(v.Tw, 2 * (size_t)std::max(m->nwalls, 1) * 8) &&
-              load(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz);
+              load(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz) &&
+              load(v.bnd, 2 * (size_t)m->nf * m->ncells * 8) && load(v.mem_count, (size_t)m->n_sys * 4) &&
+              (hdr[9] == 0 || load(v.mem, (size_t)m->n_sys * 2 * hdr[9] * m->nx * m->nz * tsz));
     int passes = 0;
     ok = ok && fread(&passes, sizeof passes, 1, f) == 1;
     ok = ok && (passes == 0 || load(v.hist, (size_t)passes * 8)) && (passes == 0 || load(v.hist_face, (size_t)passes * 8));
@@ -914,6 +965,7 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     m->last_waves = hdr[6];
     m->last_max_outer = hdr[7];
     m->last_keep = hdr[8];
+    m->last_recycle = hdr[9];
     return OBTE_OK;
 }
 

@@ -119,205 +119,390 @@ template <typename T>
 __device__ __forceinline__ T pick3(const T (&a)[3], int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
 
 template <typename T>
+__device__ __forceinline__ const T* sigma_ptr(const GeomDev& g);
+template <>
+__device__ __forceinline__ const double* sigma_ptr<double>(const GeomDev& g) { return g.sigma; }
+template <>
+__device__ __forceinline__ const float* sigma_ptr<float>(const GeomDev& g) { return g.sigma_f; }
+
+template <typename T>
 __device__ __forceinline__ T sigma_of(const GeomDev& g, int cell);
 template <>
 __device__ __forceinline__ double sigma_of<double>(const GeomDev& g, int cell) { return g.sigma[cell]; }
 template <>
 __device__ __forceinline__ float sigma_of<float>(const GeomDev& g, int cell) { return g.sigma_f[cell]; }
 
-// Reduction state of the lockstep final sweep.
+// ---------------------------------------------------------------------------
+// cross-lane primitives: DPP row shifts / row broadcasts / wave shift and
+// v_readlane.  `old` is what a lane receives when it has no source lane.
+// ---------------------------------------------------------------------------
+template <int CTRL, int RM>
+__device__ __forceinline__ float dpp(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, RM, 0xf, false));
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp(double v, double old) {
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, CTRL, RM, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, RM, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One Hillis-Steele step of the affine-map scan: this lane's map (A,Q,P)
+// is composed after the map of the source lane (identity where none).
+template <int CTRL, int RM, typename T>
+__device__ __forceinline__ void scan_step(T& A, T& Q, T& P) {
+    const T A2 = dpp<CTRL, RM>(A, T(0)), Q2 = dpp<CTRL, RM>(Q, T(1)), P2 = dpp<CTRL, RM>(P, T(0));
+    A = A + Q * A2;
+    P = P + Q * P2;
+    Q = Q * Q2;
+}
+
+// Inclusive wavefront scan of x -> A + Q x maps (P = 1 - Q carried exactly).
+template <typename T>
+__device__ __forceinline__ void wave_scan(T& A, T& Q, T& P) {
+    scan_step<0x111, 0xf>(A, Q, P);   // row_shr:1
+    scan_step<0x112, 0xf>(A, Q, P);   // row_shr:2
+    scan_step<0x114, 0xf>(A, Q, P);   // row_shr:4
+    scan_step<0x118, 0xf>(A, Q, P);   // row_shr:8
+    scan_step<0x142, 0xa>(A, Q, P);   // row_bcast:15 into rows 1, 3
+    scan_step<0x143, 0xc>(A, Q, P);   // row_bcast:31 into rows 2, 3
+}
+
+// Workgroup barrier ordering LDS only (pending global loads stay in flight).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Reduction state of a lockstep sweep.
 struct Red {
     double* lds;      // W * NV * ROW doubles
-    int w, W, NV, ROW;
-    int item;         // global item index
+    int w, W, ROW;
     int local;        // item index within the geometry
-    int want_J, store_T, adjoint;
+    int want_J, store_T;
     double kacc, kface;
 };
 
-// ---------------------------------------------------------------------------
-// The upwind sweep.  WITH_B: include the pass sources b; otherwise the only
-// source is the wrap inflow u.  RED: lockstep reductions (all waves of the
-// block must call it together).  Returns the last row (jj = ny-1) in xl.
-// ---------------------------------------------------------------------------
-template <typename T, int CPL, int NZ, bool WITH_B, bool RED>
-__device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int active, int lane,
-                      const double* __restrict__ srcbase, const double* __restrict__ wallv,
-                      const T (&u)[NZ][CPL], T (&xl)[NZ][CPL], Red* rd) {
-    T xr[NZ][CPL];
+// Loads through these views compile to global (not flat) loads, which keep
+// only the vector-memory counter pending while the row computes.
+template <typename T>
+using gptr_t = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr_t<T> gview(const T* p) { return (gptr_t<T>)p; }
+
+// 1/d: hardware reciprocal (float), refined by two Newton steps (double).
+__device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = r * (2.0 - d * r);
+    return r * (2.0 - d * r);
+}
+
+// per-row inputs of one lane (prefetched ahead of use)
+template <typename T, int CPL>
+struct RowIn {
+    uint32_t w[CPL];
+    T sg[CPL];
+    double sb[CPL];     // base source (sigma T_L, or k + D Psi)
+    double bx[CPL], by[CPL], bz[CPL];   // inflow boundary values per axis
+};
+
+// per-sweep constant views
+template <typename T>
+struct Views {
+    gptr_t<uint16_t> fc;
+    gptr_t<T> sg;
+    gptr_t<double> src, bx, by, bz;
+};
+
+template <typename T, int CPL, int NZ, bool WITH_B>
+__device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, const Views<T>& v, int lane,
+                                         int jj, int kk, RowIn<T, CPL>& r) {
+    const int nx = g.nx;
+    const int iy = s.pos[1] ? jj : g.ny - 1 - jj;
+    const int iz = (NZ > 1) ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
+    const int rowbase = nx * (iy + g.ny * iz);
 #pragma unroll
-    for (int k = 0; k < NZ; ++k)
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) xr[k][c] = T(0);
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    for (int c = 0; c < CPL; ++c) {
+        const int p = lane * CPL + c;
+        const bool in = p < nx;
+        const int cell = rowbase + (in ? (s.pos[0] ? p : nx - 1 - p) : 0);
+        r.w[c] = in ? (uint32_t)v.fc[cell] : 0u;
+        r.sg[c] = v.sg[cell];
+        if (WITH_B) {
+            r.sb[c] = v.src[cell];
+            r.bx[c] = v.bx[cell];
+            r.by[c] = v.by[cell];
+            if (NZ > 1) r.bz[c] = v.bz[cell];
+        }
+    }
+}
+
+// Row storage of the sweep: registers in 2D; in 3D one row per z-plane in
+// this wave's LDS region (the z index is a runtime value there).
+template <typename T, int CPL, int NZ>
+struct Rows {
+    T xr[CPL];
+    T* xz;        // NZ * ROW values (3D)
+    int ROW;
+    __device__ __forceinline__ T prev_y(int kk, int c, int lane) const {
+        return NZ > 1 ? xz[kk * ROW + lane * CPL + c] : xr[c];
+    }
+    __device__ __forceinline__ T prev_z(int kk, int c, int lane) const {
+        return NZ > 1 ? xz[(kk - 1) * ROW + lane * CPL + c] : T(0);
+    }
+    __device__ __forceinline__ void put(int kk, int c, int lane, T v) {
+        if (NZ > 1) xz[kk * ROW + lane * CPL + c] = v;
+        else xr[c] = v;
+    }
+};
+
+// Wrap-row vectors (u in, last row out): registers in 2D, LDS rows in 3D.
+template <typename T, int CPL, int NZ>
+struct WrapIO {
+    const T (*u)[CPL];      // [NZ][CPL] registers (2D path)
+    T (*xl)[CPL];
+};
+
+// One row step of the sweep (cells of row (jj, kk) in upwind order).
+template <typename T, int CPL, int NZ, bool WITH_B, bool RED, bool ADD>
+__device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, const Views<T>& vw,
+                                         int active, int lane, int adj, int jj, int kk,
+                                         const RowIn<T, CPL>& cur, Rows<T, CPL, NZ>& rows,
+                                         const T (&u)[NZ][CPL], T (&xl)[NZ][CPL],
+                                         const double (&mb)[3], const double (&wo)[3], Red* rd) {
     constexpr int ND = NZ > 1 ? 3 : 2;
-    const int adj = RED ? rd->adjoint : 0;
-    for (int jj = 0; jj < ny; ++jj) {
+    const int nx = g.nx, ny = g.ny;
+    const T cz = (NZ > 1) ? s.c[2] : T(0);
+    T a[CPL], q[CPL];
+    T Al = T(0), Ql = T(1), Pl = T(0);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int p = lane * CPL + c;
+        const uint32_t w = cur.w[c];
+        const bool sol = active && fc_solid(w);
+        const int clx = fc_class(w, s.fin[0]);
+        const int cly = fc_class(w, s.fin[1]);
+        const int clz = (NZ > 1) ? fc_class(w, s.fin[2]) : FC_WALL;
+        const T sg = cur.sg[c];
+        const T rdv = recip(sg + s.c[0] + s.c[1] + cz);
+        T src = T(0);
+        if (WITH_B) {
+            double sd = adj ? s.kw + s.Dml * cur.sb[c] : cur.sb[c];
+            sd += mb[0] * cur.bx[c] + mb[1] * cur.by[c];
+            if (NZ > 1) sd += mb[2] * cur.bz[c];
+            src = (T)sd;
+        }
+        // kk and jj are wave-uniform; u / xz rows are read only where used
+        T yup = (jj == 0) ? u[NZ > 1 ? 0 : 0][c] : T(0);
+        if (NZ > 1 && jj == 0) {
+#pragma unroll
+            for (int k2 = 0; k2 < NZ; ++k2)
+                if (k2 == kk) yup = u[k2][c];
+        }
+        const T yin = (cly != FC_WALL) ? ((jj == 0) ? yup : s.c[1] * rows.prev_y(kk, c, lane)) : T(0);
+        T zin = T(0);
+        if (NZ > 1) zin = (clz != FC_WALL && kk > 0) ? cz * rows.prev_z(kk > 0 ? kk : 1, c, lane) : T(0);
+        const bool xs = (clx != FC_WALL);
+        T av = (src + yin + zin) * rdv;
+        T qv = xs ? s.c[0] * rdv : T(0);
+        T pv = (sg + s.c[1] + cz + (xs ? T(0) : s.c[0])) * rdv;
+        // pore: (0, 0, 1) breaks the chain; beyond the row: identity (0, 1, 0)
+        if (!sol) { av = T(0); qv = T(0); pv = T(1); }
+        if (p >= nx) { av = T(0); qv = T(1); pv = T(0); }
+        a[c] = av;
+        q[c] = qv;
+        Al = av + qv * Al;
+        Pl = pv + qv * Pl;
+        Ql = qv * Ql;
+    }
+    T A = Al, Q = Ql, P = Pl;
+    wave_scan(A, Q, P);
+    const T At = readlane(A, WAVE - 1), Pt = readlane(P, WAVE - 1);
+    const T xin = (Pt > T(0)) ? At * recip(Pt) : T(0);   // cyclic closure x_{-1} = x_{nx-1}
+    const T Ae = dpp<0x138, 0xf>(A, T(0)), Qe = dpp<0x138, 0xf>(Q, T(1));   // wave_shr:1
+    T xp = Ae + Qe * xin;
+    T xrow[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const T xv = a[c] + q[c] * xp;
+        const int p = lane * CPL + c;
+        xrow[c] = (p < nx) ? xv : T(0);
+        rows.put(kk, c, lane, xrow[c]);
+        xp = xv;
+    }
+    if (jj == ny - 1) {
+#pragma unroll
+        for (int k2 = 0; k2 < NZ; ++k2)
+            if (k2 == kk)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) xl[k2][c] = xrow[c];
+    }
+    if (RED) {
         const int iy = s.pos[1] ? jj : ny - 1 - jj;
-        for (int kk = 0; kk < NZ; ++kk) {
-            if (kk >= nz) break;
-            const int iz = (NZ > 1) ? (s.pos[2] ? kk : nz - 1 - kk) : 0;
-            const int rowbase = nx * (iy + ny * iz);
-            T a[CPL], q[CPL];
-            T Al = T(0), Ql = T(1), Pl = T(0);
+        const int iz = (NZ > 1) ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
+        const int rowbase = nx * (iy + ny * iz);
+        double* buf = rd->lds;
+        const int ROW = rd->ROW, W = rd->W;
+        constexpr int NV = 1 + 2 * ND;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int p = lane * CPL + c;
+            const uint32_t wv = cur.w[c];
+            const bool sol = p < nx && active && fc_solid(wv);
+            const double xv = sol ? (double)xrow[c] : 0.0;
+            double* slot = buf + (size_t)(rd->w * NV) * ROW + p;
+            double tw[3] = {0.0, 0.0, 0.0};
+            double gp = 0.0;
+            if (sol) {
+                const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
+                rd->kacc += xv;
+                if (adj) {
+                    // p^T lambda: forward jump inflow = reversed outflow faces
+#pragma unroll
+                    for (int ax = 0; ax < ND; ++ax) {
+                        const int cl = fc_class(wv, s.fout[ax]);
+                        if (cl == FC_JUMP_P) rd->kface += s.cd[ax] * g.dT * xv;
+                        else if (cl == FC_JUMP_M) rd->kface -= s.cd[ax] * g.dT * xv;
+                    }
+                    // gradient partial lambda (T - T_L), linear in lambda
+                    gp = xv * (g.Tstore[(size_t)s.sys * g.ncells + cell] - g.T_L[cell]);
+                } else {
+                    // kappa through the periodic plane of the gradient axis;
+                    // the jump term belongs to the b sweep only
+                    if (g.grad_axis == 0 && p == nx - 1 && fc_class(wv, s.fout[0]) != FC_WALL)
+                        rd->kface += xv + ((!ADD && s.pos[0]) ? g.dT : 0.0);
+                    if (g.grad_axis == 1 && jj == ny - 1 && fc_class(wv, s.fout[1]) != FC_WALL)
+                        rd->kface += xv + ((!ADD && s.pos[1]) ? g.dT : 0.0);
+                }
+#pragma unroll
+                for (int ax = 0; ax < ND; ++ax)
+                    if (fc_class(wv, s.fout[ax]) == FC_WALL) tw[ax] = (adj ? s.cd[ax] : wo[ax]) * xv;
+                if (rd->store_T) g.Tstore[(size_t)s.sys * g.ncells + cell] = xv;
+            }
+            slot[0] = adj ? xv : s.Dml * xv;
+#pragma unroll
+            for (int ax = 0; ax < ND; ++ax) slot[(size_t)(1 + ax) * ROW] = tw[ax];
+            if (adj) {
+                slot[(size_t)(1 + ND) * ROW] = gp;
+            } else if (rd->want_J) {
+#pragma unroll
+                for (int ax = 0; ax < ND; ++ax) slot[(size_t)(1 + ND + ax) * ROW] = s.S[ax] * xv;
+            }
+        }
+        lds_barrier();
+        // wave w combines the values v = w, w + W, ... for the cells its lanes
+        // own; the face words are already in registers
+        const int nvu = 1 + ND + (adj ? 1 : (rd->want_J ? ND : 0));
+        for (int v = rd->w; v < nvu; v += W) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int p = lane * CPL + c;
-                T av = T(0), qv = T(1), pv = T(0);      // identity beyond the row
-                if (p < nx) {
-                    av = T(0); qv = T(0); pv = T(1);      // pore: breaks the chain
-                    const int ix = s.pos[0] ? p : nx - 1 - p;
-                    const int cell = rowbase + ix;
-                    const uint16_t w = g.fc[cell];
-                    if (active && fc_solid(w)) {
-                        const int clx = fc_class(w, s.fin[0]);
-                        const int cly = fc_class(w, s.fin[1]);
-                        const int clz = (NZ > 1) ? fc_class(w, s.fin[2]) : FC_WALL;
-                        const T sg = sigma_of<T>(g, cell);
-                        const T cz = (NZ > 1) ? s.c[2] : T(0);
-                        const T d = sg + s.c[0] + s.c[1] + cz;
-                        const T rdv = T(1) / d;
-                        T src = T(0);
-                        if (WITH_B) {
-                            double sd = srcbase[cell];
-                            if (adj) sd = s.kw + s.Dml * sd;
-#pragma unroll
-                            for (int ax = 0; ax < ND; ++ax) {
-                                const int cl = ax == 0 ? clx : (ax == 1 ? cly : clz);
-                                if (cl == FC_WALL) {
-                                    const int wi = g.wall_idx[cell * g.nf + s.fin[ax]];
-                                    const double wv = wallv[wi];
-                                    sd += adj ? g.wout[s.fin[ax] * g.n_sys + s.sys] * wv : s.cd[ax] * wv;
-                                } else if (!adj && cl == FC_JUMP_P) {
-                                    sd += s.cd[ax] * g.dT;
-                                } else if (!adj && cl == FC_JUMP_M) {
-                                    sd -= s.cd[ax] * g.dT;
-                                }
-                            }
-                            src = (T)sd;
-                        }
-                        T yin = T(0);
-                        if (cly != FC_WALL) yin = (jj == 0) ? u[kk][c] : s.c[1] * xr[kk][c];
-                        T zin = T(0);
-                        if (NZ > 1 && clz != FC_WALL && kk > 0) zin = cz * xr[kk > 0 ? kk - 1 : 0][c];
-                        av = (src + yin + zin) * rdv;
-                        const bool xs = (clx != FC_WALL);
-                        qv = xs ? s.c[0] * rdv : T(0);
-                        pv = (sg + s.c[1] + cz + (xs ? T(0) : s.c[0])) * rdv;
-                    }
+                if (p >= nx) continue;
+                double sum = 0.0;
+                for (int ww = 0; ww < W; ++ww) sum += buf[(size_t)(ww * NV + v) * ROW + p];
+                const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
+                const uint32_t wv = cur.w[c];
+                double* dst = nullptr;
+                if (v == 0) {
+                    dst = &g.part_TL[(size_t)rd->local * g.ncells + cell];
+                    if (!fc_solid(wv)) sum = 0.0;
+                } else if (v <= ND) {
+                    const int fo = pick3(s.fout, v - 1);
+                    if (fc_solid(wv) && fc_class(wv, fo) == FC_WALL)
+                        dst = &g.part_Tw[(size_t)rd->local * g.nwalls + g.wall_idx[cell * g.nf + fo]];
+                } else if (adj) {
+                    dst = &g.part_G[(size_t)rd->local * g.ncells + cell];
+                } else {
+                    dst = &g.part_J[((size_t)rd->local * g.ncells + cell) * ND + (v - 1 - ND)];
                 }
-                a[c] = av;
-                q[c] = qv;
-                Al = av + qv * Al;
-                Pl = pv + qv * Pl;
-                Ql = qv * Ql;
+                if (dst) *dst = ADD ? *dst + sum : sum;
             }
-            // inclusive scan of affine maps across the wavefront
-            T A = Al, Q = Ql, P = Pl;
+        }
+        lds_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The upwind sweep x = M^{-1}(src + P u): rows in y-upwind order (planes in
+// z-upwind order), each row's cyclic x-recurrence solved by a wavefront scan.
+// WITH_B: the pass sources are included, otherwise the only source is the
+// wrap inflow u.  RED: lockstep reductions (every wave of the block calls
+// it); ADD: add to the partials written by an earlier RED sweep of the same
+// block.  Returns the last row (jj = ny-1) in xl.  Row inputs are prefetched
+// two rows ahead (2D) through a three-buffer rotation without copies.
+// ---------------------------------------------------------------------------
+template <typename T, int CPL, int NZ, bool WITH_B, bool RED, bool ADD>
+__device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int active, int lane, int adj,
+                                      const double* __restrict__ srcbase, const double* __restrict__ bnd,
+                                      const T (&u)[NZ][CPL], T (&xl)[NZ][CPL], Red* rd, T* zrows) {
+    constexpr int ND = NZ > 1 ? 3 : 2;
+    double mb[3], wo[3];
 #pragma unroll
-            for (int off = 1; off < WAVE; off <<= 1) {
-                const T A2 = shfl_up(A, off), Q2 = shfl_up(Q, off), P2 = shfl_up(P, off);
-                if (lane >= off) {
-                    A = A + Q * A2;
-                    P = P + Q * P2;
-                    Q = Q * Q2;
+    for (int ax = 0; ax < 3; ++ax) {
+        mb[ax] = adj ? (ax < ND ? g.wout[s.fin[ax] * g.n_sys + s.sys] : 0.0) : s.cd[ax];
+        wo[ax] = ax < ND ? g.wout[s.fout[ax] * g.n_sys + s.sys] : 0.0;
+    }
+    Views<T> vw;
+    vw.fc = gview(g.fc);
+    vw.sg = gview(sigma_ptr<T>(g));
+    vw.src = gview(srcbase);
+    vw.bx = gview(bnd + (size_t)s.fin[0] * g.ncells);
+    vw.by = gview(bnd + (size_t)s.fin[1] * g.ncells);
+    vw.bz = gview(bnd + (size_t)(NZ > 1 ? s.fin[2] : 0) * g.ncells);
+    Rows<T, CPL, NZ> rows;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) rows.xr[c] = T(0);
+    rows.xz = zrows;
+    rows.ROW = WAVE * CPL;
+    const int ny = g.ny;
+    if (NZ == 1) {
+        RowIn<T, CPL> b0, b1, b2;
+        load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, 0, 0, b0);
+        if (ny > 1) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, 1, 0, b1);
+        for (int jj = 0; jj < ny; jj += 3) {
+            if (jj + 2 < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, jj + 2, 0, b2);
+            row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, 0, b0, rows, u, xl, mb, wo, rd);
+            if (jj + 1 >= ny) break;
+            if (jj + 3 < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, jj + 3, 0, b0);
+            row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 1, 0, b1, rows, u, xl, mb, wo, rd);
+            if (jj + 2 >= ny) break;
+            if (jj + 4 < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, jj + 4, 0, b1);
+            row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 2, 0, b2, rows, u, xl, mb, wo, rd);
+        }
+    } else {
+        // 3D: rows (jj, kk) with kk inner; ping-pong buffers one row ahead
+        const int nz = g.nz;
+        RowIn<T, CPL> b0, b1;
+        load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, 0, 0, b0);
+        for (int jj = 0; jj < ny; ++jj) {
+            for (int kk = 0; kk < nz; kk += 2) {
+                {
+                    int nj = jj, nk = kk + 1;
+                    if (nk >= nz) { nk = 0; ++nj; }
+                    if (nj < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, nj, nk, b1);
                 }
-            }
-            const T At = shfl_at(A, WAVE - 1), Pt = shfl_at(P, WAVE - 1);
-            const T xin = (Pt > T(0)) ? At / Pt : T(0);   // cyclic closure x_{-1} = x_{nx-1}
-            T Ae = shfl_up(A, 1), Qe = shfl_up(Q, 1);
-            if (lane == 0) { Ae = T(0); Qe = T(1); }
-            T xp = Ae + Qe * xin;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const T xv = a[c] + q[c] * xp;
-                const int p = lane * CPL + c;
-                xr[kk][c] = (p < nx) ? xv : T(0);
-                xp = xv;
-            }
-            if (jj == ny - 1) {
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) xl[kk][c] = xr[kk][c];
-            }
-            if (RED) {
-                // ---- per-row reductions, lockstep across the block's waves
-                double* buf = rd->lds;
-                const int ROW = rd->ROW, NV = rd->NV, W = rd->W;
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int p = lane * CPL + c;
-                    double xv = (double)xr[kk][c];
-                    double* slot = buf + (size_t)(rd->w * NV) * ROW + p;
-                    double tw[3] = {0.0, 0.0, 0.0};
-                    if (p < nx && active) {
-                        const int ix = s.pos[0] ? p : nx - 1 - p;
-                        const int cell = rowbase + ix;
-                        const uint16_t wv = g.fc[cell];
-                        if (fc_solid(wv)) {
-                            rd->kacc += xv;
-                            if (adj) {
-                                // p^T lambda: forward jump inflow = reversed outflow faces
-#pragma unroll
-                                for (int ax = 0; ax < ND; ++ax) {
-                                    const int cl = fc_class(wv, s.fout[ax]);
-                                    if (cl == FC_JUMP_P) rd->kface += s.cd[ax] * g.dT * xv;
-                                    else if (cl == FC_JUMP_M) rd->kface -= s.cd[ax] * g.dT * xv;
-                                }
-                            }
-                            // kappa through the periodic plane of the gradient axis
-                            if (!adj && g.grad_axis == 0 && p == nx - 1 && fc_class(wv, s.fout[0]) != FC_WALL)
-                                rd->kface += xv + (s.pos[0] ? g.dT : 0.0);
-                            if (!adj && g.grad_axis == 1 && jj == ny - 1 && fc_class(wv, s.fout[1]) != FC_WALL)
-                                rd->kface += xv + (s.pos[1] ? g.dT : 0.0);
-#pragma unroll
-                            for (int ax = 0; ax < ND; ++ax)
-                                if (fc_class(wv, s.fout[ax]) == FC_WALL)
-                                    tw[ax] = adj ? s.cd[ax] * xv : g.wout[s.fout[ax] * g.n_sys + s.sys] * xv;
-                            if (rd->store_T) g.Tstore[(size_t)s.sys * g.ncells + cell] = xv;
-                            if (adj) {
-                                // gradient partial: lambda (T - T_L)
-                                const double Tf = g.Tstore[(size_t)s.sys * g.ncells + cell];
-                                slot[(size_t)(1 + ND) * ROW] = xv * (Tf - g.T_L[cell]);
-                            }
-                        } else {
-                            xv = 0.0;
-                            if (adj) slot[(size_t)(1 + ND) * ROW] = 0.0;
-                        }
-                    } else {
-                        xv = 0.0;
-                        if (adj) slot[(size_t)(1 + ND) * ROW] = 0.0;
-                    }
-                    slot[0] = adj ? xv : s.Dml * xv;
-#pragma unroll
-                    for (int ax = 0; ax < ND; ++ax) slot[(size_t)(1 + ax) * ROW] = tw[ax];
-                    if (rd->want_J)
-#pragma unroll
-                        for (int ax = 0; ax < ND; ++ax)
-                            slot[(size_t)(1 + ND + ax) * ROW] = s.S[ax] * xv;
+                row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, kk, b0, rows, u, xl, mb, wo, rd);
+                if (kk + 1 >= nz) {      // odd nz: the next row already sits in b1
+                    b0 = b1;
+                    break;
                 }
-                __syncthreads();
-                const int nvu = 1 + ND + ((rd->want_J || adj) ? (adj ? 1 : ND) : 0);
-                for (int idx = threadIdx.x; idx < nx * nvu; idx += blockDim.x) {
-                    const int p = idx % nx, v = idx / nx;
-                    double sum = 0.0;
-                    for (int ww = 0; ww < W; ++ww) sum += buf[(size_t)(ww * NV + v) * ROW + p];
-                    const int ix = s.pos[0] ? p : nx - 1 - p;
-                    const int cell = rowbase + ix;
-                    const uint16_t wv = g.fc[cell];
-                    if (v == 0) {
-                        g.part_TL[(size_t)rd->local * g.ncells + cell] = fc_solid(wv) ? sum : 0.0;
-                    } else if (v <= ND) {
-                        const int fo = pick3(s.fout, v - 1);
-                        if (fc_solid(wv) && fc_class(wv, fo) == FC_WALL)
-                            g.part_Tw[(size_t)rd->local * g.nwalls + g.wall_idx[cell * g.nf + fo]] = sum;
-                    } else if (adj) {
-                        g.part_G[(size_t)rd->local * g.ncells + cell] = sum;
-                    } else {
-                        const int ax = v - 1 - ND;
-                        g.part_J[((size_t)rd->local * g.ncells + cell) * ND + ax] = sum;
-                    }
+                {
+                    int nj = jj, nk = kk + 2;
+                    if (nk >= nz) { nk = 0; ++nj; }
+                    if (nj < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, nj, nk, b0);
                 }
-                __syncthreads();
+                row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, kk + 1, b1, rows, u, xl, mb, wo, rd);
             }
         }
     }
@@ -327,7 +512,7 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
 // across the y-wrap is solid.
 template <typename T, int CPL, int NZ>
 __device__ __forceinline__ void wrap_mask(const GeomDev& g, const SysC<T>& s, int active, int lane,
-                          T (&mk)[NZ][CPL]) {
+                                          T (&mk)[NZ][CPL]) {
     const int iy = s.pos[1] ? 0 : g.ny - 1;
 #pragma unroll
     for (int k = 0; k < NZ; ++k)
@@ -338,7 +523,7 @@ __device__ __forceinline__ void wrap_mask(const GeomDev& g, const SysC<T>& s, in
             if (k < g.nz && p < g.nx && active && g.periodic[1]) {
                 const int ix = s.pos[0] ? p : g.nx - 1 - p;
                 const int iz = (NZ > 1) ? (s.pos[2] ? k : g.nz - 1 - k) : 0;
-                const uint16_t w = g.fc[ix + g.nx * (iy + g.ny * iz)];
+                const uint32_t w = g.fc[ix + g.nx * (iy + g.ny * iz)];
                 if (fc_solid(w) && fc_class(w, s.fin[1]) != FC_WALL) mk[k][c] = s.c[1];
             }
         }
@@ -354,18 +539,98 @@ __device__ __forceinline__ double vdot(const T (&a)[NZ][CPL], const T (&b)[NZ][C
     return wave_sum(acc);
 }
 
-#define VLOOP(body)                       \
+#define VLOOP(body)                                \
     _Pragma("unroll") for (int k = 0; k < NZ; ++k) \
     _Pragma("unroll") for (int c = 0; c < CPL; ++c) { body; }
 
 // ---------------------------------------------------------------------------
+// Recycled Krylov memory of one system: R pairs (v_i, w_i = (I - G) v_i) with
+// the w_i orthonormal.  The wrap matrix I - G is fixed during a solve, so the
+// pairs gathered in earlier passes solve most of a later pass's residual by a
+// projection.
+// ---------------------------------------------------------------------------
+template <typename T, int CPL, int NZ>
+struct Mem {
+    T* base;     // R pairs, each 2 * nwrap values (v then w)
+    int* count;  // stored pairs (read at the start, written back at the end)
+    int n;       // wave-uniform copy of *count
+    int R, nwrap, nx, nz, lane;
+    // every lane reads and writes only its own entries, so no cross-lane
+    // ordering is needed; the count lives in a register meanwhile
+    __device__ void begin() { n = R > 0 ? min(*count, R) : 0; }
+    __device__ void end() const { if (lane == 0 && R > 0) *count = n; }
+    __device__ T* v(int i) const { return base + (size_t)i * 2 * nwrap; }
+    __device__ T* w(int i) const { return base + (size_t)i * 2 * nwrap + nwrap; }
+    __device__ void load(const T* src, T (&x)[NZ][CPL]) const {
+        VLOOP({
+            const int p = lane * CPL + c;
+            x[k][c] = (k < nz && p < nx) ? src[k * nx + p] : T(0);
+        });
+    }
+    __device__ void store(T* dst, const T (&x)[NZ][CPL]) const {
+        VLOOP({
+            const int p = lane * CPL + c;
+            if (k < nz && p < nx) dst[k * nx + p] = x[k][c];
+        });
+    }
+    // project r onto span(w): u += V c, r -= W c
+    __device__ void project(T (&u)[NZ][CPL], T (&r)[NZ][CPL]) const {
+        for (int i = 0; i < n; ++i) {
+            T wi[NZ][CPL], vi[NZ][CPL];
+            load(w(i), wi);
+            const double ci = vdot<T, CPL, NZ>(wi, r);
+            load(v(i), vi);
+            VLOOP({ r[k][c] -= (T)ci * wi[k][c]; u[k][c] += (T)ci * vi[k][c]; });
+        }
+    }
+    // insert the pair (x, y = (I - G) x), orthonormalising y against the memory
+    __device__ void insert(const T (&x)[NZ][CPL], const T (&y)[NZ][CPL]) {
+        if (R <= 0) return;
+        T xv[NZ][CPL], yv[NZ][CPL];
+        VLOOP({ xv[k][c] = x[k][c]; yv[k][c] = y[k][c]; });
+        const double n0 = sqrt(vdot<T, CPL, NZ>(yv, yv));
+        if (!(n0 > 0.0)) return;
+        for (int i = 0; i < n; ++i) {
+            T wi[NZ][CPL], vi[NZ][CPL];
+            load(w(i), wi);
+            const double h = vdot<T, CPL, NZ>(wi, yv);
+            load(v(i), vi);
+            VLOOP({ yv[k][c] -= (T)h * wi[k][c]; xv[k][c] -= (T)h * vi[k][c]; });
+        }
+        const double nn = sqrt(vdot<T, CPL, NZ>(yv, yv));
+        if (!(nn > 1e-6 * n0)) return;         // (numerically) dependent
+        int slot = n;
+        if (n >= R) {
+            // full: drop the oldest pair (the others stay orthonormal)
+            for (int i = 1; i < R; ++i) {
+                T t[NZ][CPL];
+                load(v(i), t);
+                store(v(i - 1), t);
+                load(w(i), t);
+                store(w(i - 1), t);
+            }
+            slot = R - 1;
+        }
+        const T inv = (T)(1.0 / nn);
+        VLOOP({ xv[k][c] *= inv; yv[k][c] *= inv; });
+        store(v(slot), xv);
+        store(w(slot), yv);
+        if (n < R) ++n;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // One outer pass for every work item (block = one item = W systems sharing a
-// direction).
+// direction).  Phase A: all waves sweep in lockstep with the sources b and
+// the previous wrap inflow u0, writing the reductions.  Phase B: each wave
+// corrects its wrap inflow (recycled projection, then BiCGSTAB on the wrap
+// row).  Phase C: if any wave changed u, a lockstep correction sweep with
+// source P (u - u0) adds its (linear) contribution to the reductions.
 // ---------------------------------------------------------------------------
 template <typename T, int CPL, int NZ>
 __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ geoms,
-                                                     const Item* __restrict__ items, int n_items,
-                                                     PassParams pp) {
+                                                    const Item* __restrict__ items, int n_items,
+                                                    PassParams pp) {
     extern __shared__ double lds[];
     const int it = blockIdx.x;
     if (it >= n_items) return;
@@ -380,46 +645,75 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     const int pass = g.ctrl[CTRL_PASS];
     const int buf_in = (pp.mode == 1) ? ((pass + 1) & 1) : (pass & 1);
     const double* srcbase = adj ? (g.lam_psi + (size_t)buf_in * g.ncells) : (g.sT + (size_t)buf_in * g.ncells);
-    const double* wallv = adj ? (g.lam_phi + (size_t)buf_in * g.nwalls) : (g.Tw + (size_t)buf_in * g.nwalls);
-    T* Uall = reinterpret_cast<T*>(g.U) + (adj ? (size_t)g.n_sys * g.nwrap : 0);
+    const double* bnd = g.bnd + ((size_t)(adj ? 2 : 0) + buf_in) * g.nf * g.ncells;
+    const size_t half = adj ? (size_t)g.n_sys : 0;
+    T* Uall = reinterpret_cast<T*>(g.U) + half * g.nwrap;
+    Mem<T, CPL, NZ> mem;
+    mem.R = g.mem_R;
+    mem.nwrap = g.nwrap;
+    mem.nx = g.nx;
+    mem.nz = g.nz;
+    mem.lane = lane;
+    mem.base = reinterpret_cast<T*>(g.mem) + (half + s.sys) * (size_t)2 * g.mem_R * g.nwrap;
+    mem.count = g.mem_count + half + s.sys;
 
+    // 3D: per-wave LDS rows (one per z-plane) after the reduction buffers
+    constexpr int NVR = 1 + 2 * (NZ > 1 ? 3 : 2);
+    T* zrows = reinterpret_cast<T*>(lds + (size_t)W * NVR * WAVE * CPL) + (size_t)w * NZ * WAVE * CPL;
     T u[NZ][CPL], xl[NZ][CPL], mk[NZ][CPL];
     wrap_mask<T, CPL, NZ>(g, s, active, lane, mk);
-    // warm start from the previous pass
     VLOOP({
         const int p = lane * CPL + c;
         u[k][c] = (active && k < g.nz && p < g.nx) ? Uall[(size_t)s.sys * g.nwrap + k * g.nx + p] : T(0);
     });
-    long long n_it = 0, n_sw = 0;
+    Red rd;
+    rd.lds = lds;
+    rd.w = w;
+    rd.W = W;
+    rd.ROW = WAVE * CPL;
+    rd.local = item.local;
+    rd.want_J = pp.want_J;
+    rd.store_T = pp.store_T;
+    rd.kacc = 0.0;
+    rd.kface = 0.0;
+    // ---- phase A
+    sweep<T, CPL, NZ, true, true, false>(g, s, active, lane, adj, srcbase, bnd, u, xl, &rd, zrows);
+    long long n_it = 0, n_sw = 1;
+    int need = 0;
+    T du[NZ][CPL];
+    VLOOP(du[k][c] = T(0));
     const bool has_wrap = g.periodic[1] != 0;
     if (pp.mode == 0 && active && has_wrap) {
-        T z[NZ][CPL];
-        sweep<T, CPL, NZ, true, false>(g, s, active, lane, srcbase, wallv, u, z, nullptr);
-        ++n_sw;
-        T r[NZ][CPL];
-        VLOOP(r[k][c] = mk[k][c] * z[k][c] - u[k][c]);
-        T ez[NZ][CPL];
-        VLOOP(ez[k][c] = mk[k][c] * z[k][c]);
+        // ---- phase B: residual of the wrap system for the inflow u0 just used
+        T r[NZ][CPL], ez[NZ][CPL];
+        VLOOP({ ez[k][c] = mk[k][c] * xl[k][c]; r[k][c] = ez[k][c] - u[k][c]; });
         const double scale = sqrt(vdot<T, CPL, NZ>(ez, ez));
-        double rn = sqrt(vdot<T, CPL, NZ>(r, r));
         const double thr = pp.inner_tol * scale;
+        double rn = sqrt(vdot<T, CPL, NZ>(r, r));
+        mem.begin();
         if (rn > thr && scale > 0.0) {
-            T rh[NZ][CPL], p[NZ][CPL], v[NZ][CPL], sv[NZ][CPL], t[NZ][CPL];
-            VLOOP({ rh[k][c] = r[k][c]; p[k][c] = T(0); v[k][c] = T(0); });
+            need = 1;
+            mem.project(du, r);
+            rn = sqrt(vdot<T, CPL, NZ>(r, r));
+        }
+        if (rn > thr && scale > 0.0) {
+            // BiCGSTAB for the remaining correction: (I - G) e = r
+            T e[NZ][CPL], rh[NZ][CPL], p[NZ][CPL], v[NZ][CPL], sv[NZ][CPL], t[NZ][CPL];
+            VLOOP({ e[k][c] = T(0); rh[k][c] = r[k][c]; p[k][c] = T(0); v[k][c] = T(0); });
             double rho_old = 1.0, alpha = 1.0, omega = 1.0;
             for (int iter = 0; iter < pp.max_inner; ++iter) {
                 double rho = vdot<T, CPL, NZ>(rh, r);
                 if (fabs(rho) <= 1e-30 * rn * rn || !(omega != 0.0)) {
-                    // breakdown: restart with the current residual as shadow
                     VLOOP({ rh[k][c] = r[k][c]; p[k][c] = T(0); v[k][c] = T(0); });
                     rho = vdot<T, CPL, NZ>(r, r);
                     rho_old = 1.0; alpha = 1.0; omega = 1.0;
                 }
                 const double beta = (rho / rho_old) * (alpha / omega);
                 VLOOP(p[k][c] = r[k][c] + (T)beta * (p[k][c] - (T)omega * v[k][c]));
-                sweep<T, CPL, NZ, false, false>(g, s, active, lane, srcbase, wallv, p, xl, nullptr);
+                sweep<T, CPL, NZ, false, false, false>(g, s, active, lane, adj, srcbase, bnd, p, xl, nullptr, zrows);
                 ++n_sw;
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
+                mem.insert(p, v);
                 const double rv = vdot<T, CPL, NZ>(rh, v);
                 if (rv == 0.0) break;
                 alpha = rho / rv;
@@ -427,42 +721,37 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 const double sn = sqrt(vdot<T, CPL, NZ>(sv, sv));
                 ++n_it;
                 if (sn <= thr) {
-                    VLOOP(u[k][c] += (T)alpha * p[k][c]);
+                    VLOOP(e[k][c] += (T)alpha * p[k][c]);
                     break;
                 }
-                sweep<T, CPL, NZ, false, false>(g, s, active, lane, srcbase, wallv, sv, xl, nullptr);
+                sweep<T, CPL, NZ, false, false, false>(g, s, active, lane, adj, srcbase, bnd, sv, xl, nullptr, zrows);
                 ++n_sw;
                 VLOOP(t[k][c] = sv[k][c] - mk[k][c] * xl[k][c]);
+                mem.insert(sv, t);
                 const double tt = vdot<T, CPL, NZ>(t, t);
                 omega = tt > 0.0 ? vdot<T, CPL, NZ>(t, sv) / tt : 0.0;
-                VLOOP(u[k][c] += (T)alpha * p[k][c] + (T)omega * sv[k][c]);
+                VLOOP(e[k][c] += (T)alpha * p[k][c] + (T)omega * sv[k][c]);
                 VLOOP(r[k][c] = sv[k][c] - (T)omega * t[k][c]);
                 rn = sqrt(vdot<T, CPL, NZ>(r, r));
                 rho_old = rho;
                 if (rn <= thr) break;
             }
+            VLOOP(du[k][c] += e[k][c]);
         }
-        VLOOP({
-            const int pp_ = lane * CPL + c;
-            if (k < g.nz && pp_ < g.nx) Uall[(size_t)s.sys * g.nwrap + k * g.nx + pp_] = u[k][c];
-        });
+        mem.end();
+        if (lane == 0) g.wres[s.sys] = scale > 0.0 ? rn / scale : 0.0;
+        if (need) {
+            VLOOP({
+                const int pp_ = lane * CPL + c;
+                if (k < g.nz && pp_ < g.nx) Uall[(size_t)s.sys * g.nwrap + k * g.nx + pp_] = u[k][c] + du[k][c];
+            });
+        }
     }
-    // final sweep with the lockstep reductions
-    Red rd;
-    rd.lds = lds;
-    rd.w = w;
-    rd.W = W;
-    rd.NV = 1 + 2 * (NZ > 1 ? 3 : 2);
-    rd.ROW = WAVE * CPL;
-    rd.item = it;
-    rd.local = item.local;
-    rd.want_J = pp.want_J;
-    rd.store_T = pp.store_T;
-    rd.adjoint = adj;
-    rd.kacc = 0.0;
-    rd.kface = 0.0;
-    sweep<T, CPL, NZ, true, true>(g, s, active, lane, srcbase, wallv, u, xl, &rd);
-    ++n_sw;
+    // ---- phase C: lockstep correction sweep when any wave moved its inflow
+    if (__syncthreads_or(need)) {
+        sweep<T, CPL, NZ, false, true, true>(g, s, active && need, lane, adj, srcbase, bnd, du, xl, &rd, zrows);
+        ++n_sw;
+    }
     const double ks = wave_sum(rd.kacc), kf = wave_sum(rd.kface);
     if (active && lane == 0) {
         if (adj) {
@@ -483,39 +772,67 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
 // Per-cell / per-wall sums of the item partials (fixed order) and the next
 // pass's inputs sigma T_L and T_w.
 // ---------------------------------------------------------------------------
-__global__ void k_reduce_pass(const GeomDev* __restrict__ geoms, PassParams pp) {
+__global__ void __launch_bounds__(256) k_reduce_pass(const GeomDev* __restrict__ geoms, PassParams pp) {
+    __shared__ double part[4][64];
     const GeomDev& g = geoms[blockIdx.y];
     if (g.ctrl[CTRL_DONE] && pp.mode == 0) return;
     const int pass = g.ctrl[CTRL_PASS];
     const int out = (pass + 1) & 1;
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int stride = gridDim.x * blockDim.x;
     const int adj = pp.adjoint;
-    for (int cell = tid; cell < g.ncells; cell += stride) {
-        double acc = 0.0;
-        for (int i = 0; i < g.n_items; ++i) acc += g.part_TL[(size_t)i * g.ncells + cell];
+    // cells: 64 per block, the item sum split in 4 fixed chunks combined in order
+    const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
+    const int cell = blockIdx.x * 64 + cl;
+    const int per = (g.n_items + 3) / 4;
+    const int i0 = q * per, i1 = min(g.n_items, i0 + per);
+    double acc = 0.0;
+    if (cell < g.ncells) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int i = i0;
+        for (; i + 3 < i1; i += 4) {
+            a0 += g.part_TL[(size_t)i * g.ncells + cell];
+            a1 += g.part_TL[(size_t)(i + 1) * g.ncells + cell];
+            a2 += g.part_TL[(size_t)(i + 2) * g.ncells + cell];
+            a3 += g.part_TL[(size_t)(i + 3) * g.ncells + cell];
+        }
+        for (; i < i1; ++i) a0 += g.part_TL[(size_t)i * g.ncells + cell];
+        acc = (a0 + a1) + (a2 + a3);
+    }
+    part[q][cl] = acc;
+    __syncthreads();
+    if (q == 0 && cell < g.ncells) {
+        const double tot = ((part[0][cl] + part[1][cl]) + part[2][cl]) + part[3][cl];
         const bool sol = fc_solid(g.fc[cell]);
         if (adj) {
-            g.lam_psi[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * acc : 0.0;
+            g.lam_psi[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * tot : 0.0;
         } else {
-            g.T_L[cell] = sol ? acc : 0.0;
-            g.sT[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * acc : 0.0;
+            g.T_L[cell] = sol ? tot : 0.0;
+            g.sT[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * tot : 0.0;
         }
     }
-    for (int wi = tid; wi < g.nwalls; wi += stride) {
+    // walls: one wavefront per wall face; items whose direction leaves the
+    // cell through the face (forward) or enters it (adjoint: outflow of the
+    // reversed direction); each lane sums a fixed strided subset, then a
+    // butterfly, so the order is fixed
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    double* bnd_out = g.bnd + ((size_t)(adj ? 2 : 0) + out) * g.nf * g.ncells;
+    for (int wi = wave; wi < g.nwalls; wi += nwaves) {
         const int f = g.wall_face[wi];
         const int ax = f >> 1;
         const double nsgn = (f & 1) ? 1.0 : -1.0;
-        double acc = 0.0;
-        // items whose direction leaves the cell through this face (forward) or
-        // enters it (adjoint: outflow of the reversed direction)
-        for (int i = 0; i < g.n_items; ++i) {
+        double a = 0.0;
+        for (int i = lane; i < g.n_items; i += 64) {
             const int l = i / g.n_grp;          // items are ordered (l, MFP group)
             const double sn = g.dirs[l * 3 + ax] * nsgn;
-            if ((!adj && sn > 0.0) || (adj && sn < 0.0)) acc += g.part_Tw[(size_t)i * g.nwalls + wi];
+            if ((!adj && sn > 0.0) || (adj && sn < 0.0)) a += g.part_Tw[(size_t)i * g.nwalls + wi];
         }
-        if (adj) g.lam_phi[(size_t)out * g.nwalls + wi] = acc;
-        else g.Tw[(size_t)out * g.nwalls + wi] = acc;
+        a = wave_sum(a);
+        if (lane == 0) {
+            if (adj) g.lam_phi[(size_t)out * g.nwalls + wi] = a;
+            else g.Tw[(size_t)out * g.nwalls + wi] = a;
+            bnd_out[(size_t)f * g.ncells + g.wall_cell[wi]] = a;
+        }
     }
 }
 
@@ -524,14 +841,26 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
     __shared__ double red[32];
     const GeomDev& g = geoms[blockIdx.x];
     if (g.ctrl[CTRL_DONE]) return;
-    double k = 0.0, kf = 0.0;
+    double k = 0.0, kf = 0.0, wr = 0.0;
     for (int i = threadIdx.x; i < g.n_sys; i += blockDim.x) {
         k += g.ksys[i];
         kf += g.kfsys[i];
+        wr = fmax(wr, g.wres[i]);
     }
     // fixed-order: every thread sums a fixed strided subset, then block_sum
     k = block_sum(k, red);
     kf = block_sum(kf, red);
+    // max of the wrap residuals (every value is >= 0: max via the sum of a
+    // one-hot is not needed, a plain block max suffices)
+    __syncthreads();
+    {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        for (int m2 = 32; m2 >= 1; m2 >>= 1) wr = fmax(wr, shfl_xor(wr, m2));
+        if (lane == 0) red[20 + wid] = wr;
+        __syncthreads();
+        wr = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) wr = fmax(wr, red[20 + i]);
+    }
     if (threadIdx.x == 0) {
         const int pass = g.ctrl[CTRL_PASS];
         if (pass >= pp.max_outer) {      // history is sized for max_outer passes
@@ -540,12 +869,16 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
         }
         g.hist[pass] = k;
         g.hist_face[pass] = kf;
+        g.wres_hist[pass] = wr;
         const int n = pass + 1;
         g.ctrl[CTRL_PASS] = n;
+        // Algorithm 1's test on the relative change of kappa; with a bounded
+        // number of inner iterations per pass the wrap rows must be solved too
+        const bool wrap_ok = wr <= fmax(pp.inner_tol, pp.outer_tol);
         if (!isfinite(k)) {
             g.ctrl[CTRL_NONFINITE] = 1;
             g.ctrl[CTRL_DONE] = 1;
-        } else if (n >= 2 && fabs(k - g.hist[pass - 1]) <= pp.outer_tol * fabs(k)) {
+        } else if (n >= 2 && wrap_ok && fabs(k - g.hist[pass - 1]) <= pp.outer_tol * fabs(k)) {
             g.ctrl[CTRL_CONVERGED] = 1;
             g.ctrl[CTRL_DONE] = 1;
         } else if (n >= pp.max_outer) {
@@ -558,6 +891,201 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
 // Fourier first guess: CG on the negated 5/7-point finite-volume Laplacian
 // with adiabatic pores and the periodic jump (one block per geometry).
 // ---------------------------------------------------------------------------
+
+// Sum over the block returned to every thread with a single barrier; `red`
+// alternates between two halves so back-to-back calls do not race.
+__device__ __forceinline__ double block_sum1(double v, double* red, int& phase) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    double* r = red + 16 * phase;
+    phase ^= 1;
+    if (lane == 0) r[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += r[i];
+    return t;
+}
+
+// Shared epilogue: x (solution, global) -> mean-free T_F, sigma T_F, T_w, the
+// inflow boundary tables and kappa_F; resets the pass control words.
+__device__ void fourier_epilogue(const GeomDev& g, double* red, int iter, double rn, double bn) {
+    const int n = g.ncells, nf = g.nf;
+    double* x = g.fx;
+    double sx = 0.0, ns = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x)
+        if (fc_solid(g.fc[c])) { sx += x[c]; ns += 1.0; }
+    sx = block_sum(sx, red);
+    ns = block_sum(ns, red);
+    const double mean = sx / ns;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const bool sol = fc_solid(g.fc[c]);
+        const double t = sol ? x[c] - mean : 0.0;
+        x[c] = t;
+        g.T_L[c] = t;
+        g.sT[c] = sol ? g.sigma[c] * t : 0.0;   // buffer 0
+    }
+    __syncthreads();
+    // inflow boundary values per (face, cell): periodic jumps +-dT (fixed),
+    // walls T_w (updated every pass), interior 0; forward buffers 0 and 1,
+    // adjoint buffers 2 and 3 (no jump source; walls updated per pass)
+    for (int e = threadIdx.x; e < nf * n; e += blockDim.x) {
+        const int f = e / n, c = e - f * n;
+        const uint16_t w = g.fc[c];
+        const int cl = fc_solid(w) ? fc_class(w, f) : FC_INTERIOR;
+        const double v = cl == FC_JUMP_P ? g.dT : (cl == FC_JUMP_M ? -g.dT : 0.0);
+        g.bnd[e] = v;
+        g.bnd[(size_t)nf * n + e] = v;
+        g.bnd[(size_t)2 * nf * n + e] = 0.0;
+        g.bnd[(size_t)3 * nf * n + e] = 0.0;
+    }
+    __syncthreads();
+    for (int wi = threadIdx.x; wi < g.nwalls; wi += blockDim.x) {
+        const double t = x[g.wall_cell[wi]];
+        g.Tw[wi] = t;
+        g.bnd[(size_t)g.wall_face[wi] * n + g.wall_cell[wi]] = t;
+    }
+    // kappa_F: plane flux through the periodic plane of the gradient axis
+    const int ga = g.grad_axis;
+    double fl = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const uint16_t w = g.fc[c];
+        if (!fc_solid(w)) continue;
+        const int f = 2 * ga;   // '-' face of the cell at index 0
+        if (fc_class(w, f) == FC_JUMP_P) {
+            const int j = nbr_cell(g, c, f);
+            fl += g.kappa_axis[ga] * (x[j] + g.dT - x[c]) / g.h[ga];
+        }
+    }
+    fl = block_sum(fl, red);
+    if (threadIdx.x == 0) {
+        g.fscal[0] = g.L[ga] / (g.dT * (double)g.n_perp) * fl;
+        g.fscal[1] = (double)iter;
+        g.fscal[2] = bn > 0.0 ? rn / bn : 0.0;
+        for (int i = 0; i < CTRL_N; ++i) g.ctrl[i] = 0;
+    }
+}
+
+__device__ __forceinline__ double fourier_rhs(const GeomDev& g, uint16_t w, const double (&kf)[3]) {
+    double b = 0.0;
+    if (fc_solid(w))
+        for (int f = 0; f < g.nf; ++f) {
+            const int cl = fc_class(w, f);
+            if (cl == FC_JUMP_P) b += kf[f >> 1] * g.dT;
+            else if (cl == FC_JUMP_M) b -= kf[f >> 1] * g.dT;
+        }
+    return b;
+}
+
+// Small meshes (<= FOURIER_LDS_CELLS): the search direction lives in LDS and
+// each thread keeps its cells' residual in registers (x accumulates in global
+// memory).  A cell's face word carries, above the face classes, whether the
+// cell sits on the low / high edge of each axis, so a neighbour index is an
+// add with a wrap correction rather than an integer division.
+constexpr int FOURIER_LDS_CELLS = 16384;
+constexpr int FOURIER_PER_THREAD = FOURIER_LDS_CELLS / 1024;
+
+__device__ __forceinline__ uint32_t edge_bits(const GeomDev& g, int c) {
+    const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
+    uint32_t b = 0;
+    b |= (ix == 0) << 16;
+    b |= (ix == g.nx - 1) << 17;
+    b |= (iy == 0) << 18;
+    b |= (iy == g.ny - 1) << 19;
+    b |= (iz == 0) << 20;
+    b |= (iz == g.nz - 1) << 21;
+    return b;
+}
+
+__device__ __forceinline__ int nbr_fast(int c, uint32_t w, int f, const int (&stride)[3], const int (&span)[3]) {
+    const int a = f >> 1;
+    const bool hi = f & 1;
+    const bool edge = (w >> (16 + f)) & 1;
+    const int d = edge ? (hi ? -span[a] : span[a]) : (hi ? stride[a] : -stride[a]);
+    return c + d;
+}
+
+__global__ void __launch_bounds__(1024) k_fourier_lds(const GeomDev* __restrict__ geoms, double tol,
+                                                     int max_iter) {
+    extern __shared__ double pl[];      // ncells
+    __shared__ double red[32];
+    const GeomDev& g = geoms[blockIdx.x];
+    const int n = g.ncells, nf = g.nf;
+    const int stride[3] = {1, g.nx, g.nx * g.ny};
+    const int span[3] = {g.nx - 1, (g.ny - 1) * g.nx, (g.nz - 1) * g.nx * g.ny};
+    double kf[3];
+    for (int a = 0; a < 3; ++a) kf[a] = (a < g.ndim) ? g.kappa_axis[a] / (g.h[a] * g.h[a]) : 0.0;
+    gptr_t<uint16_t> fcv = gview(g.fc);
+    double r[FOURIER_PER_THREAD];       // x accumulates in global memory
+    uint32_t fw[FOURIER_PER_THREAD];
+    double rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
+        const int c = threadIdx.x + k * 1024;
+        fw[k] = c < n ? ((uint32_t)fcv[c] | edge_bits(g, c)) : 0u;
+        const double b = c < n ? fourier_rhs(g, (uint16_t)fw[k], kf) : 0.0;
+        r[k] = b;
+        if (c < n) {
+            pl[c] = b;
+            g.fx[c] = 0.0;
+        }
+        rr += b * b;
+    }
+    int ph = 0;
+    rr = block_sum1(rr, red, ph);
+    const double bn = sqrt(rr);
+    double rn = bn;
+    int iter = 0;
+    if (bn > 0.0) {
+        for (iter = 0; iter < max_iter; ++iter) {
+            // p is complete in LDS (the reduction above synchronised); A p is
+            // evaluated twice from LDS rather than held in registers
+            double pap = 0.0;
+#pragma unroll
+            for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
+                const int c = threadIdx.x + k * 1024;
+                if (c < n && fc_solid(fw[k])) {
+                    const double pc = pl[c];
+                    double y = 0.0;
+                    for (int f = 0; f < nf; ++f)
+                        if (fc_class(fw[k], f) != FC_WALL) y += kf[f >> 1] * (pc - pl[nbr_fast(c, fw[k], f, stride, span)]);
+                    pap += pc * y;
+                }
+            }
+            pap = block_sum1(pap, red, ph);
+            const double alpha = rr / pap;
+            double rr2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
+                const int c = threadIdx.x + k * 1024;
+                if (c < n && fc_solid(fw[k])) {
+                    const double pc = pl[c];
+                    double y = 0.0;
+                    for (int f = 0; f < nf; ++f)
+                        if (fc_class(fw[k], f) != FC_WALL) y += kf[f >> 1] * (pc - pl[nbr_fast(c, fw[k], f, stride, span)]);
+                    g.fx[c] += alpha * pc;
+                    r[k] -= alpha * y;
+                    rr2 += r[k] * r[k];
+                }
+            }
+            rr2 = block_sum1(rr2, red, ph);
+            rn = sqrt(rr2);
+            if (rn <= tol * bn) { ++iter; break; }
+            const double beta = rr2 / rr;
+            rr = rr2;
+            // every thread has read its p entries above; update them in place
+#pragma unroll
+            for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
+                const int c = threadIdx.x + k * 1024;
+                if (c < n) pl[c] = r[k] + beta * pl[c];
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    fourier_epilogue(g, red, iter, rn, bn);
+}
+
+// Larger meshes: vectors in global memory (L2-resident).
 __global__ void __launch_bounds__(1024) k_fourier(const GeomDev* __restrict__ geoms, double tol,
                                                  int max_iter) {
     __shared__ double red[32];
@@ -570,17 +1098,9 @@ __global__ void __launch_bounds__(1024) k_fourier(const GeomDev* __restrict__ ge
     double kf[3];
     for (int a = 0; a < 3; ++a) kf[a] = (a < g.ndim) ? g.kappa_axis[a] / (g.h[a] * g.h[a]) : 0.0;
     const int nf = g.nf;
-    // b = sum over jump faces of k/h^2 delta dT  (system: -Lap T = b)
     double rr = 0.0;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const uint16_t w = g.fc[c];
-        double b = 0.0;
-        if (fc_solid(w))
-            for (int f = 0; f < nf; ++f) {
-                const int cl = fc_class(w, f);
-                if (cl == FC_JUMP_P) b += kf[f >> 1] * g.dT;
-                else if (cl == FC_JUMP_M) b -= kf[f >> 1] * g.dT;
-            }
+        const double b = fourier_rhs(g, g.fc[c], kf);
         x[c] = 0.0;
         r[c] = b;
         p[c] = b;
@@ -623,41 +1143,7 @@ __global__ void __launch_bounds__(1024) k_fourier(const GeomDev* __restrict__ ge
         }
     }
     __syncthreads();
-    // mean over solid cells -> 0
-    double sx = 0.0, ns = 0.0;
-    for (int c = threadIdx.x; c < n; c += blockDim.x)
-        if (fc_solid(g.fc[c])) { sx += x[c]; ns += 1.0; }
-    sx = block_sum(sx, red);
-    ns = block_sum(ns, red);
-    const double mean = sx / ns;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const bool sol = fc_solid(g.fc[c]);
-        const double t = sol ? x[c] - mean : 0.0;
-        x[c] = t;
-        g.T_L[c] = t;
-        g.sT[c] = sol ? g.sigma[c] * t : 0.0;   // buffer 0
-    }
-    __syncthreads();
-    for (int wi = threadIdx.x; wi < g.nwalls; wi += blockDim.x) g.Tw[wi] = x[g.wall_cell[wi]];
-    // kappa_F: plane flux through the periodic plane of the gradient axis
-    const int ga = g.grad_axis;
-    double fl = 0.0;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const uint16_t w = g.fc[c];
-        if (!fc_solid(w)) continue;
-        const int f = 2 * ga;   // '-' face of the cell at index 0
-        if (fc_class(w, f) == FC_JUMP_P) {
-            const int j = nbr_cell(g, c, f);
-            fl += g.kappa_axis[ga] * (x[j] + g.dT - x[c]) / g.h[ga];
-        }
-    }
-    fl = block_sum(fl, red);
-    if (threadIdx.x == 0) {
-        g.fscal[0] = g.L[ga] / (g.dT * (double)g.n_perp) * fl;
-        g.fscal[1] = (double)iter;
-        g.fscal[2] = bn > 0.0 ? rn / bn : 0.0;
-        for (int i = 0; i < CTRL_N; ++i) g.ctrl[i] = 0;
-    }
+    fourier_epilogue(g, red, iter, rn, bn);
 }
 
 // ---------------------------------------------------------------------------
@@ -745,15 +1231,30 @@ __global__ void __launch_bounds__(1024) k_output(const GeomDev* __restrict__ gp,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, double tol, int max_iter,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(k_fourier, dim3(n_geoms), dim3(1024), 0, st, geoms_dev, tol, max_iter);
+hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, int max_cells, double tol,
+                          int max_iter, hipStream_t st) {
+    (void)hipGetLastError();
+    if (max_cells <= FOURIER_LDS_CELLS) {
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void*)k_fourier_lds,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      FOURIER_LDS_CELLS * (int)sizeof(double));
+            (void)hipGetLastError();
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_fourier_lds, dim3(n_geoms), dim3(1024), (size_t)max_cells * sizeof(double),
+                           st, geoms_dev, tol, max_iter);
+    } else {
+        hipLaunchKernelGGL(k_fourier, dim3(n_geoms), dim3(1024), 0, st, geoms_dev, tol, max_iter);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int CPL, int NZ>
 static hipError_t launch_sweep_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
                                  size_t lds, hipStream_t st) {
+    (void)hipGetLastError();
     hipLaunchKernelGGL((k_sweep_pass<T, CPL, NZ>), dim3(n), dim3(64 * waves), lds, st, g, it, n, pp);
     return hipGetLastError();
 }
@@ -782,14 +1283,16 @@ hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, c
 
 hipError_t launch_reduce_pass(const GeomDev* geoms_dev, int n_geoms, int max_cells, int max_walls,
                               PassParams pp, hipStream_t st) {
-    const int work = max_cells > max_walls ? max_cells : max_walls;
-    int blocks = (work + 255) / 256;
+    (void)max_walls;
+    int blocks = (max_cells + 63) / 64;
     if (blocks < 1) blocks = 1;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_reduce_pass, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const GeomDev* geoms_dev, int n_geoms, PassParams pp, hipStream_t st) {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_finalize, dim3(n_geoms), dim3(256), 0, st, geoms_dev, pp);
     return hipGetLastError();
 }
@@ -798,6 +1301,7 @@ hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, cons
                         const double* sigma, const int* sys_ids, int n_sys, const void* x, void* y,
                         hipStream_t st) {
     dim3 grid((g_host.ncells + 255) / 256, n_sys);
+    (void)hipGetLastError();
     if (precision == 0)
         hipLaunchKernelGGL(k_apply<double>, grid, dim3(256), 0, st, g_dev, sigma, sys_ids, n_sys,
                            (const double*)x, (double*)y, transpose);
@@ -810,6 +1314,7 @@ hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, cons
 hipError_t launch_prep_sigma(const GeomDev* g_dev, int ncells, const double* sig, hipStream_t st) {
     int blocks = (ncells + 255) / 256;
     if (blocks > 1024) blocks = 1024;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_prep_sigma, dim3(blocks), dim3(256), 0, st, g_dev, sig);
     return hipGetLastError();
 }
@@ -817,6 +1322,7 @@ hipError_t launch_prep_sigma(const GeomDev* g_dev, int ncells, const double* sig
 hipError_t launch_output(const GeomDev* geoms_dev, int n_geoms, double* T_L_out, double* J_out,
                          double* grad_out, hipStream_t st) {
     (void)n_geoms;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_output, dim3(1), dim3(1024), 0, st, geoms_dev, T_L_out, J_out, grad_out);
     return hipGetLastError();
 }

@@ -61,6 +61,13 @@ struct GeomDev {
     double* lam_phi;             // adjoint: 2 * nwalls (double buffered Phi)
     double* gradient;            // adjoint: ncells
     double* part_G;              // adjoint: n_items * ncells (gradient partials)
+    double* bnd;                 // 4 * nf * ncells: inflow boundary value per (face, cell);
+                                 // forward buffers 0/1, adjoint buffers 2/3 (double buffered)
+    void* mem;                   // 2 * n_sys * 2 * mem_R * nwrap: recycled Krylov pairs
+    int* mem_count;              // 2 * n_sys
+    int mem_R;                   // pairs kept per system
+    double* wres;                // n_sys: relative wrap-row residual after this pass's solve
+    double* wres_hist;           // max_outer: max over systems per pass
 };
 
 struct Item {
@@ -83,8 +90,8 @@ struct PassParams {
 };
 
 // kernel launchers (kernels.hip)
-hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, double tol, int max_iter,
-                          hipStream_t st);
+hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, int max_cells, double tol,
+                          int max_iter, hipStream_t st);
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
                              const Item* items_dev, int n_items, int waves, PassParams pp,
                              size_t lds_bytes, hipStream_t st);

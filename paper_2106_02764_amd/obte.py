@@ -46,13 +46,15 @@ class obte_solve_opts(C.Structure):
                 ("inner_tol", C.c_double), ("max_inner", C.c_int), ("init", C.c_int),
                 ("only_fourier", C.c_int), ("passes_per_graph", C.c_int),
                 ("waves_per_group", C.c_int), ("fourier_tol", C.c_double),
-                ("max_fourier", C.c_int), ("keep_state", C.c_int), ("timing", C.c_int)]
+                ("max_fourier", C.c_int), ("keep_state", C.c_int), ("recycle", C.c_int),
+                ("timing", C.c_int)]
 
 
 class obte_stats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_longlong), ("sweeps", C.c_longlong),
                 ("fourier_iters", C.c_int), ("kappa", C.c_double), ("kappa_face", C.c_double),
-                ("kappa_fourier", C.c_double), ("last_rel_change", C.c_double), ("status", C.c_int),
+                ("kappa_fourier", C.c_double), ("last_rel_change", C.c_double),
+                ("wrap_residual", C.c_double), ("status", C.c_int),
                 ("sweep_launches", C.c_int), ("sweep_ms", C.c_double), ("reduce_ms", C.c_double),
                 ("fourier_ms", C.c_double)]
 

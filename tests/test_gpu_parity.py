@@ -95,10 +95,12 @@ def test_lockstep_passes(P, name):
     ref = source_iteration(prob, n_passes=r["outer_iters"])
     assert abs(r["kappa"] - ref["kappa_cc"]) <= 1e-10 * abs(ref["kappa_cc"])
     assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
-    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-10
+    # T_L (max norm): the wrap-row solve stops at a 1e-14 relative residual
+    # and its matrix has condition numbers up to ~1e4 at the longest MFPs
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
     Jref = np.zeros((w.n_cells, w.ndim))
     Jref[prob.mesh.cells] = ref["J"]
-    assert rel(r["J"], Jref) < 1e-10
+    assert rel(r["J"], Jref) < 1e-9
 
 
 @pytest.mark.parametrize("name", ["cfg1", "bulk", "channel"])
