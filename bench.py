@@ -36,7 +36,20 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--workload", default="cfg2")
+    p.add_argument("--copy-probe", type=int, default=0,
+                   help="only run a plain device copy of this many bytes (scales rocprofv3 "
+                        "FETCH_SIZE / WRITE_SIZE) and exit")
     return p.parse_args()
+
+
+def copy_probe(nbytes):
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "launches": 3}), flush=True)
 
 
 def make_workload(name):
@@ -98,62 +111,43 @@ def calibrate(P, solver, prec, kref, inner_tol):
     return best[0], best[1]
 
 
-def cpu_baseline(w, seconds, passes):
-    """The FP64 oracle (SuperLU per (m,l) system, as the paper) on a bounded
-    sample of the same workload, extrapolated to one converged solve."""
-    import numpy as np
-    from multiprocessing import get_context
-
-    from oracle.bte import Problem
-    cores = len(os.sched_getaffinity(0))
-    cores = max(1, min(cores, 16))
+def cpu_baseline_measure(w, seconds):
+    """Time the FP64 oracle on the same workload before the GPU is touched:
+    every (m, l) system factored once (SuperLU, reused as in the paper) and a
+    few source-iteration passes, with the directions spread over the host
+    cores.  Bounded by `seconds` of passes."""
+    from oracle.parallel import source_iteration_parallel
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
     t0 = time.perf_counter()
-    prob = Problem(w)
-    t_setup = time.perf_counter() - t0
-    n_sys = prob.mat.n_mfp * prob.mat.n_dir
-    rng = np.random.default_rng(0)
-    order = rng.permutation(n_sys)
-    T_L = np.zeros(prob.mesh.n_solid)
-    T_w = np.zeros(prob.mesh.n_walls)
-    # serial timing of factor + solve on a sample, bounded by `seconds`
-    tf = ts = 0.0
-    done = 0
-    t_start = time.perf_counter()
-    for sid in order:
-        m, l = divmod(int(sid), prob.mat.n_dir)
-        a = time.perf_counter()
-        lu = prob.lu(m, l, cache=False)
-        b = time.perf_counter()
-        lu.solve(prob.rhs(m, l, T_L, T_w))
-        c = time.perf_counter()
-        tf += b - a
-        ts += c - b
-        done += 1
-        if time.perf_counter() - t_start > seconds:
-            break
-    per_factor, per_solve = tf / done, ts / done
-    # one converged solve: every system factored once (cached as the paper
-    # does) plus `passes` solves; systems are independent across cores
-    serial = n_sys * (per_factor + passes * per_solve) + t_setup
-    parallel = serial / cores
-    return {"value": 1.0 / parallel, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": (f"{done} of {n_sys} (m,l) systems factored+solved serially in "
-                       f"{tf + ts:.1f}s; extrapolated to {n_sys} factorizations + {passes} passes "
-                       f"of solves, divided over {cores} cores (directions are independent)"),
-            "dof_per_s": prob.mesh.n_solid * n_sys / parallel,
-            "seconds_per_solve_estimate": parallel}
+    r = source_iteration_parallel(w, n_workers=cores, n_passes=3, time_limit=seconds)
+    total = time.perf_counter() - t0
+    return {"cores": cores, "t_factor": r["t_factor"], "pass_s": float(r["pass_times"].mean()),
+            "passes_run": int(r["passes"]), "wall_s": total}
+
+
+def cpu_baseline_value(m, passes, dof):
+    per_solve = m["t_factor"] + passes * m["pass_s"]
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": m["cores"], "kind": "oracle",
+            "sample": (f"full workload, all systems factored ({m['t_factor']:.1f}s) + "
+                       f"{m['passes_run']} passes ({m['pass_s']:.3f}s each) on {m['cores']} worker "
+                       f"processes; extrapolated to the {passes} passes of the FP64 GPU solve"),
+            "dof_per_s": dof / per_solve, "seconds_per_solve_estimate": per_solve}
 
 
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is design-only)"}))
         sys.exit(2)
+    w = make_workload(a.workload)
+    cpu = None if a.no_cpu else cpu_baseline_measure(w, a.cpu_seconds)
     import torch
     import paper_2106_02764_amd as P
 
-    w = make_workload(a.workload)
     solver = P.Solver.from_workload(w)
     dof = w.dof
     # reference: FP64 GPU form converged far below the target error (untimed)
@@ -216,8 +210,8 @@ def main():
     }
     if golden:
         line["kappa_oracle"] = golden["kappa_cc"]
-    if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, int(round(res["fp64"]["passes"] / a.steps)))
+    if cpu is not None:
+        line["cpu_baseline"] = cpu_baseline_value(cpu, int(round(res["fp64"]["passes"] / a.steps)), dof)
     print(json.dumps(line), flush=True)
 
 

@@ -1,0 +1,51 @@
+"""Write the oracle's reference values for the full-size workloads.
+
+Calls only the CPU oracle (oracle/) on the seeded inputs (inputs/gen.py) and
+stores kappa_cc, kappa_face, kappa_fourier, per-MFP kappa and T_L at seeded
+sample cells.  Run:  python tests/golden/make_golden.py cfg2 [--workers 8]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from inputs import gen  # noqa: E402
+from oracle.parallel import source_iteration_parallel  # noqa: E402
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("config", choices=["cfg2", "cfg4"])
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--tol", type=float, default=1e-11)
+    a = ap.parse_args()
+    w = gen.config2() if a.config == "cfg2" else gen.config4()
+    t0 = time.time()
+    r = source_iteration_parallel(w, n_workers=a.workers, tol=a.tol, verbose=True)
+    cells = np.nonzero(w.solid.ravel())[0]
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(len(cells), size=64, replace=False))
+    out = {
+        "config": a.config, "source": "oracle.parallel.source_iteration_parallel (FP64, SuperLU per system)",
+        "tol": a.tol, "passes": r["passes"], "converged": bool(r["converged"]),
+        "kappa_cc": r["kappa_cc"], "kappa_face": r["kappa_face"], "kappa_fourier": r["kappa_fourier"],
+        "kappa_per_mfp": list(map(float, r["kappa_per_mfp"])),
+        "T_L_sample_cells": [int(cells[i]) for i in pick],
+        "T_L_sample": [float(r["T_L"][i]) for i in pick],
+        "history_tail": list(map(float, r["history"][-5:])),
+        "seconds": time.time() - t0,
+    }
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{a.config}_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", path, out["kappa_cc"], out["passes"])
+
+
+if __name__ == "__main__":
+    main()
