@@ -93,10 +93,10 @@ def calibrate(P, solver, prec, kref, inner_tol):
     on the relative change, which understates the error.  Untimed."""
     import torch
     best = None
-    for max_inner in (2, 4, 64):
+    for lag, rtol in ((1, 0.3), (1, 0.1), (0, 0.1), (0, 0.0)):
         for tol in (3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7):
-            o = solver.opts(precision=prec, outer_tol=tol, inner_tol=inner_tol, fourier_tol=1e-8,
-                            passes_per_graph=4, max_inner=max_inner)
+            o = solver.opts(precision=prec, outer_tol=tol, inner_tol=inner_tol, fourier_tol=1e-6,
+                            passes_per_graph=4, inner_rtol=rtol, lag_wrap=lag)
             solver.solve(o, want_T_L=False)           # warm
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -175,6 +175,8 @@ def main():
         r["outer_tol"] = o.outer_tol
         r["inner_tol"] = o.inner_tol
         r["max_inner"] = o.max_inner
+        r["inner_rtol"] = o.inner_rtol
+        r["lag_wrap"] = o.lag_wrap
         r["kappa_rel_err_vs_fp64_ref"] = abs(r["kappa"] - kref) / abs(kref)
         if golden:
             r["kappa_rel_err_vs_oracle"] = abs(r["kappa"] - golden["kappa_cc"]) / golden["kappa_cc"]

@@ -84,10 +84,14 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * kappa and the convergence test accumulate in double.
  * outer_tol: stop when |kappa_n - kappa_{n-1}| <= outer_tol |kappa_n|
  * (Algorithm 1); 1 <= max_outer < 65536.  inner_tol: relative residual of the periodic-wrap Krylov
- * solve inside each (m,l) system; max_inner caps its iterations per pass
- * (a small cap carries the rest of the wrap solve into later passes, and
- * the stop then also requires every wrap residual <= max(inner_tol,
- * outer_tol)).  init: 0 = Fourier first guess, 1 = resume
+ * solve inside each (m,l) system; inner_rtol (0 = off) lets a pass stop
+ * once the wrap residual it started from fell by that factor, and max_inner
+ * caps the iterations per pass (either carries the rest of the wrap solve
+ * into later passes).
+ * The stop test also requires every relative wrap residual <= wrap_tol
+ * (0 = max(inner_tol, 10 outer_tol)).  lag_wrap = 1 applies a pass's wrap
+ * correction in the next pass instead of a correction sweep (the wrap
+ * inflow is then lagged like T_L; the fixed point is unchanged).  init: 0 = Fourier first guess, 1 = resume
  * from the state left in the workspace by the previous call.
  * passes_per_graph: outer passes captured per HIP-graph replay (>= 1); the
  * host reads kappa back once per replay.  waves_per_group: systems that share
@@ -116,6 +120,9 @@ typedef struct {
     int max_fourier;
     int keep_state;
     int recycle;
+    int lag_wrap;
+    double inner_rtol;
+    double wrap_tol;
     int timing;
 } obte_solve_opts;
 

@@ -229,6 +229,9 @@ obte_status check_opts(const obte_solve_opts* o) {
         return fail(OBTE_ERR_ARG, "fourier_tol must be > 0 and max_fourier >= 0");
     if (o->init != 0 && o->init != 1) return fail(OBTE_ERR_ARG, "init must be 0 or 1");
     if (o->recycle < 0 || o->recycle > 32) return fail(OBTE_ERR_ARG, "recycle must be in 0..32");
+    if (o->lag_wrap != 0 && o->lag_wrap != 1) return fail(OBTE_ERR_ARG, "lag_wrap must be 0 or 1");
+    if (!(o->wrap_tol >= 0.0)) return fail(OBTE_ERR_ARG, "wrap_tol must be >= 0");
+    if (!(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0)) return fail(OBTE_ERR_ARG, "inner_rtol must be in [0, 1)");
     return OBTE_OK;
 }
 
@@ -426,6 +429,9 @@ PassParams base_params(const obte_solve_opts* o) {
     pp.mode = 0;
     pp.max_outer = o->max_outer;
     pp.outer_tol = o->outer_tol;
+    pp.lag_wrap = o->lag_wrap;
+    pp.inner_rtol = o->inner_rtol;
+    pp.wrap_tol = o->wrap_tol > 0.0 ? o->wrap_tol : std::max(o->inner_tol, 10.0 * o->outer_tol);
     return pp;
 }
 
@@ -600,6 +606,9 @@ void obte_default_opts(obte_solve_opts* o) {
     o->max_fourier = 20000;
     o->keep_state = 0;
     o->recycle = 0;
+    o->lag_wrap = 0;
+    o->inner_rtol = 0.0;
+    o->wrap_tol = 0.0;
     o->timing = 0;
 }
 

@@ -391,8 +391,10 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                 if (rd->store_T) g.Tstore[(size_t)s.sys * g.ncells + cell] = xv;
             }
             slot[0] = adj ? xv : s.Dml * xv;
+            // wall slots are read back only at cells with an outgoing wall face
 #pragma unroll
-            for (int ax = 0; ax < ND; ++ax) slot[(size_t)(1 + ax) * ROW] = tw[ax];
+            for (int ax = 0; ax < ND; ++ax)
+                if (fc_class(wv, s.fout[ax]) == FC_WALL) slot[(size_t)(1 + ax) * ROW] = tw[ax];
             if (adj) {
                 slot[(size_t)(1 + ND) * ROW] = gp;
             } else if (rd->want_J) {
@@ -409,10 +411,13 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
             for (int c = 0; c < CPL; ++c) {
                 const int p = lane * CPL + c;
                 if (p >= nx) continue;
+                const uint32_t wv = cur.w[c];
+                // wall values exist only where this direction leaves through a wall
+                if (v >= 1 && v <= ND && !(fc_solid(wv) && fc_class(wv, pick3(s.fout, v - 1)) == FC_WALL))
+                    continue;
                 double sum = 0.0;
                 for (int ww = 0; ww < W; ++ww) sum += buf[(size_t)(ww * NV + v) * ROW + p];
                 const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
-                const uint32_t wv = cur.w[c];
                 double* dst = nullptr;
                 if (v == 0) {
                     dst = &g.part_TL[(size_t)rd->local * g.ncells + cell];
@@ -688,18 +693,24 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
         T r[NZ][CPL], ez[NZ][CPL];
         VLOOP({ ez[k][c] = mk[k][c] * xl[k][c]; r[k][c] = ez[k][c] - u[k][c]; });
         const double scale = sqrt(vdot<T, CPL, NZ>(ez, ez));
-        const double thr = pp.inner_tol * scale;
         double rn = sqrt(vdot<T, CPL, NZ>(r, r));
+        // target of this pass: inner_tol relative to the inflow, or (forcing)
+        // a reduction by inner_rtol of the residual the pass started from
+        const double thr = fmax(pp.inner_tol * scale, pp.inner_rtol * rn);
+        const double thr_final = pp.inner_tol * scale;
         mem.begin();
-        if (rn > thr && scale > 0.0) {
+        if (rn > thr_final && scale > 0.0) {
             need = 1;
             mem.project(du, r);
             rn = sqrt(vdot<T, CPL, NZ>(r, r));
         }
         if (rn > thr && scale > 0.0) {
-            // BiCGSTAB for the remaining correction: (I - G) e = r
-            T e[NZ][CPL], rh[NZ][CPL], p[NZ][CPL], v[NZ][CPL], sv[NZ][CPL], t[NZ][CPL];
-            VLOOP({ e[k][c] = T(0); rh[k][c] = r[k][c]; p[k][c] = T(0); v[k][c] = T(0); });
+            // BiCGSTAB for the remaining correction: (I - G) e = r.  A capped
+            // BiCGSTAB is not monotone, so the iterate with the smallest
+            // residual is kept: a pass never increases the wrap residual.
+            T e[NZ][CPL], eb[NZ][CPL], rh[NZ][CPL], p[NZ][CPL], v[NZ][CPL], sv[NZ][CPL], t[NZ][CPL];
+            VLOOP({ e[k][c] = T(0); eb[k][c] = T(0); rh[k][c] = r[k][c]; p[k][c] = T(0); v[k][c] = T(0); });
+            double best = rn;
             double rho_old = 1.0, alpha = 1.0, omega = 1.0;
             for (int iter = 0; iter < pp.max_inner; ++iter) {
                 double rho = vdot<T, CPL, NZ>(rh, r);
@@ -715,13 +726,14 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
                 mem.insert(p, v);
                 const double rv = vdot<T, CPL, NZ>(rh, v);
-                if (rv == 0.0) break;
+                if (!(rv != 0.0) || !isfinite(rv)) break;
                 alpha = rho / rv;
                 VLOOP(sv[k][c] = r[k][c] - (T)alpha * v[k][c]);
                 const double sn = sqrt(vdot<T, CPL, NZ>(sv, sv));
                 ++n_it;
                 if (sn <= thr) {
                     VLOOP(e[k][c] += (T)alpha * p[k][c]);
+                    if (sn < best) { best = sn; VLOOP(eb[k][c] = e[k][c]); }
                     break;
                 }
                 sweep<T, CPL, NZ, false, false, false>(g, s, active, lane, adj, srcbase, bnd, sv, xl, nullptr, zrows);
@@ -734,9 +746,12 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 VLOOP(r[k][c] = sv[k][c] - (T)omega * t[k][c]);
                 rn = sqrt(vdot<T, CPL, NZ>(r, r));
                 rho_old = rho;
+                if (!isfinite(rn)) break;
+                if (rn < best) { best = rn; VLOOP(eb[k][c] = e[k][c]); }
                 if (rn <= thr) break;
             }
-            VLOOP(du[k][c] += e[k][c]);
+            rn = best;
+            VLOOP(du[k][c] += eb[k][c]);
         }
         mem.end();
         if (lane == 0) g.wres[s.sys] = scale > 0.0 ? rn / scale : 0.0;
@@ -748,7 +763,8 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
         }
     }
     // ---- phase C: lockstep correction sweep when any wave moved its inflow
-    if (__syncthreads_or(need)) {
+    // (skipped when the correction is lagged into the next pass)
+    if (!pp.lag_wrap && __syncthreads_or(need)) {
         sweep<T, CPL, NZ, false, true, true>(g, s, active && need, lane, adj, srcbase, bnd, du, xl, &rd, zrows);
         ++n_sw;
     }
@@ -874,7 +890,7 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
         g.ctrl[CTRL_PASS] = n;
         // Algorithm 1's test on the relative change of kappa; with a bounded
         // number of inner iterations per pass the wrap rows must be solved too
-        const bool wrap_ok = wr <= fmax(pp.inner_tol, pp.outer_tol);
+        const bool wrap_ok = wr <= pp.wrap_tol;
         if (!isfinite(k)) {
             g.ctrl[CTRL_NONFINITE] = 1;
             g.ctrl[CTRL_DONE] = 1;
@@ -982,7 +998,8 @@ __device__ __forceinline__ double fourier_rhs(const GeomDev& g, uint16_t w, cons
 // cell sits on the low / high edge of each axis, so a neighbour index is an
 // add with a wrap correction rather than an integer division.
 constexpr int FOURIER_LDS_CELLS = 16384;
-constexpr int FOURIER_PER_THREAD = FOURIER_LDS_CELLS / 1024;
+constexpr int FOURIER_THREADS = 512;
+constexpr int FOURIER_PER_THREAD = FOURIER_LDS_CELLS / FOURIER_THREADS;
 
 __device__ __forceinline__ uint32_t edge_bits(const GeomDev& g, int c) {
     const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
@@ -1004,7 +1021,7 @@ __device__ __forceinline__ int nbr_fast(int c, uint32_t w, int f, const int (&st
     return c + d;
 }
 
-__global__ void __launch_bounds__(1024) k_fourier_lds(const GeomDev* __restrict__ geoms, double tol,
+__global__ void __launch_bounds__(FOURIER_THREADS) k_fourier_lds(const GeomDev* __restrict__ geoms, double tol,
                                                      int max_iter) {
     extern __shared__ double pl[];      // ncells
     __shared__ double red[32];
@@ -1015,19 +1032,17 @@ __global__ void __launch_bounds__(1024) k_fourier_lds(const GeomDev* __restrict_
     double kf[3];
     for (int a = 0; a < 3; ++a) kf[a] = (a < g.ndim) ? g.kappa_axis[a] / (g.h[a] * g.h[a]) : 0.0;
     gptr_t<uint16_t> fcv = gview(g.fc);
-    double r[FOURIER_PER_THREAD];       // x accumulates in global memory
+    double r[FOURIER_PER_THREAD], x[FOURIER_PER_THREAD];
     uint32_t fw[FOURIER_PER_THREAD];
     double rr = 0.0;
 #pragma unroll
     for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-        const int c = threadIdx.x + k * 1024;
+        const int c = threadIdx.x + k * FOURIER_THREADS;
         fw[k] = c < n ? ((uint32_t)fcv[c] | edge_bits(g, c)) : 0u;
         const double b = c < n ? fourier_rhs(g, (uint16_t)fw[k], kf) : 0.0;
         r[k] = b;
-        if (c < n) {
-            pl[c] = b;
-            g.fx[c] = 0.0;
-        }
+        x[k] = 0.0;
+        if (c < n) pl[c] = b;
         rr += b * b;
     }
     int ph = 0;
@@ -1042,7 +1057,7 @@ __global__ void __launch_bounds__(1024) k_fourier_lds(const GeomDev* __restrict_
             double pap = 0.0;
 #pragma unroll
             for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-                const int c = threadIdx.x + k * 1024;
+                const int c = threadIdx.x + k * FOURIER_THREADS;
                 if (c < n && fc_solid(fw[k])) {
                     const double pc = pl[c];
                     double y = 0.0;
@@ -1056,13 +1071,13 @@ __global__ void __launch_bounds__(1024) k_fourier_lds(const GeomDev* __restrict_
             double rr2 = 0.0;
 #pragma unroll
             for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-                const int c = threadIdx.x + k * 1024;
+                const int c = threadIdx.x + k * FOURIER_THREADS;
                 if (c < n && fc_solid(fw[k])) {
                     const double pc = pl[c];
                     double y = 0.0;
                     for (int f = 0; f < nf; ++f)
                         if (fc_class(fw[k], f) != FC_WALL) y += kf[f >> 1] * (pc - pl[nbr_fast(c, fw[k], f, stride, span)]);
-                    g.fx[c] += alpha * pc;
+                    x[k] += alpha * pc;
                     r[k] -= alpha * y;
                     rr2 += r[k] * r[k];
                 }
@@ -1075,11 +1090,16 @@ __global__ void __launch_bounds__(1024) k_fourier_lds(const GeomDev* __restrict_
             // every thread has read its p entries above; update them in place
 #pragma unroll
             for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-                const int c = threadIdx.x + k * 1024;
+                const int c = threadIdx.x + k * FOURIER_THREADS;
                 if (c < n) pl[c] = r[k] + beta * pl[c];
             }
             __syncthreads();
         }
+    }
+#pragma unroll
+    for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
+        const int c = threadIdx.x + k * FOURIER_THREADS;
+        if (c < n) g.fx[c] = x[k];
     }
     __syncthreads();
     fourier_epilogue(g, red, iter, rn, bn);
@@ -1243,7 +1263,7 @@ hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, int max_cells, 
             (void)hipGetLastError();
             attr = true;
         }
-        hipLaunchKernelGGL(k_fourier_lds, dim3(n_geoms), dim3(1024), (size_t)max_cells * sizeof(double),
+        hipLaunchKernelGGL(k_fourier_lds, dim3(n_geoms), dim3(FOURIER_THREADS), (size_t)max_cells * sizeof(double),
                            st, geoms_dev, tol, max_iter);
     } else {
         hipLaunchKernelGGL(k_fourier, dim3(n_geoms), dim3(1024), 0, st, geoms_dev, tol, max_iter);

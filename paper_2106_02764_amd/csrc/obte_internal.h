@@ -87,6 +87,9 @@ struct PassParams {
     int adjoint;       // 1 = transposed system with adjoint sources
     int max_outer;
     double outer_tol;
+    int lag_wrap;      // 1 = apply this pass's wrap correction in the next pass
+    double inner_rtol; // per-pass wrap solve stops once the residual fell by this factor
+    double wrap_tol;   // stop test: every relative wrap residual <= wrap_tol
 };
 
 // kernel launchers (kernels.hip)

@@ -47,6 +47,7 @@ class obte_solve_opts(C.Structure):
                 ("only_fourier", C.c_int), ("passes_per_graph", C.c_int),
                 ("waves_per_group", C.c_int), ("fourier_tol", C.c_double),
                 ("max_fourier", C.c_int), ("keep_state", C.c_int), ("recycle", C.c_int),
+                ("lag_wrap", C.c_int), ("inner_rtol", C.c_double), ("wrap_tol", C.c_double),
                 ("timing", C.c_int)]
 
 

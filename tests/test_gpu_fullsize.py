@@ -1,0 +1,107 @@
+"""Full-size workloads on the GPU against the oracle's stored values
+(tests/golden/*_oracle.json, written by tests/golden/make_golden.py from the
+oracle only) and against properties that hold at any size."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from inputs import gen
+from tests.gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    return require_gpu()
+
+
+def golden(name):
+    return json.load(open(os.path.join(GOLD, f"{name}_oracle.json")))
+
+
+def solve(P, w, **opt):
+    s = P.Solver.from_workload(w)
+    out = s.solve(s.opts(**opt), sigma=w.sigma, want_T_L=True, want_J=False)
+    out["T_L"] = out["T_L"].cpu().numpy()
+    out["solver"] = s
+    return out
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg4"])
+def test_fp64_converged_vs_oracle(P, name):
+    w = gen.config2() if name == "cfg2" else gen.config4()
+    g = golden(name)
+    out = solve(P, w, outer_tol=1e-11, inner_tol=1e-13, fourier_tol=1e-12, max_outer=3000)
+    assert out["status"] == 0
+    # both sides stop at a 1e-11 relative change with a contraction ~0.85:
+    # fixed-point error ~6e-11 each
+    assert abs(out["kappa"] - g["kappa_cc"]) <= 1e-9 * g["kappa_cc"]
+    assert abs(out["kappa_face"] - g["kappa_face"]) <= 1e-9 * g["kappa_face"]
+    assert abs(out["kappa_fourier"] - g["kappa_fourier"]) <= 1e-9 * g["kappa_fourier"]
+    k, per = out["solver"].kappa()
+    assert np.allclose(per, g["kappa_per_mfp"], rtol=1e-8, atol=1e-9 * g["kappa_cc"])
+    T = out["T_L"][g["T_L_sample_cells"]]
+    ref = np.asarray(g["T_L_sample"])
+    assert np.max(np.abs(T - ref)) <= 1e-8 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg4"])
+@pytest.mark.parametrize("lag,rtol", [(0, 0.0), (1, 0.3), (1, 0.1), (0, 0.1)])
+def test_fp32_form_vs_oracle(P, name, lag, rtol):
+    """The FP32-sweep form at the bench's operating points reaches 1e-4."""
+    w = gen.config2() if name == "cfg2" else gen.config4()
+    g = golden(name)
+    out = solve(P, w, precision=1, outer_tol=1e-6, inner_tol=1e-5, fourier_tol=1e-8,
+                lag_wrap=lag, inner_rtol=rtol, max_outer=3000)
+    assert out["status"] == 0
+    assert abs(out["kappa"] - g["kappa_cc"]) <= 1e-4 * g["kappa_cc"]
+
+
+@pytest.mark.parametrize("lag", [0, 1])
+def test_fp64_lagged_wrap_same_fixed_point(P, lag):
+    w = gen.config2()
+    g = golden("cfg2")
+    out = solve(P, w, outer_tol=1e-11, inner_tol=1e-13, fourier_tol=1e-12, lag_wrap=lag,
+                inner_rtol=0.1, max_outer=3000)
+    assert out["status"] == 0
+    assert abs(out["kappa"] - g["kappa_cc"]) <= 1e-9 * g["kappa_cc"]
+
+
+def test_cfg4_adjoint_vs_finite_differences(P):
+    """Adjoint d kappa / d sigma against central differences of the forward
+    solve with the same fixed number of passes (the iteration error of the
+    two solves then cancels).  FD error: rounding ~1e-14 kappa / h plus
+    truncation O(h^2)."""
+    w = gen.config4()
+    cells = gen.config4_fd_cells()[:6]
+    s = P.Solver.from_workload(w)
+    N = 400
+    o = s.opts(outer_tol=0.0, max_outer=N, inner_tol=1e-14, fourier_tol=1e-13, keep_state=1,
+               passes_per_graph=8, max_inner=64)
+    base = s.solve(o, sigma=w.sigma, want_T_L=False)
+    grad, st = s.adjoint(s.opts(outer_tol=1e-13, inner_tol=1e-14, max_outer=N, keep_state=1,
+                                max_inner=64))
+    grad = grad.cpu().numpy()
+    assert abs(st["kappa"] - base["kappa"]) <= 1e-9 * base["kappa"]      # p^T lambda = kappa
+    o2 = s.opts(outer_tol=0.0, max_outer=N, inner_tol=1e-14, fourier_tol=1e-13, passes_per_graph=8,
+                max_inner=64)
+    for h, tol in ((1e-4, 1e-5), (1e-6, 1e-3)):
+        for c in cells:
+            k = []
+            for d in (h, -h):
+                sg = w.sigma.copy()
+                sg[c] += d
+                k.append(s.solve(o2, sigma=sg, want_T_L=False)["kappa"])
+            fd = (k[0] - k[1]) / (2 * h)
+            assert abs(fd - grad[c]) <= tol * abs(grad[c]) + 1e-14 * base["kappa"] / h, (h, c, fd, grad[c])
+    # sum rule: sum_i sigma_i d kappa / d sigma_i = L d kappa / dL - kappa is not
+    # cheap here; the uniform-scaling check below is: d kappa(t sigma)/dt at t=1
+    t = 1e-5
+    kp = s.solve(o2, sigma=w.sigma * (1 + t), want_T_L=False)["kappa"]
+    km = s.solve(o2, sigma=w.sigma * (1 - t), want_T_L=False)["kappa"]
+    assert abs((kp - km) / (2 * t) - float(np.dot(w.sigma, grad))) <= 1e-6 * abs(base["kappa"])
