@@ -58,7 +58,44 @@ def make_workload(name):
         return gen.config2()
     if name == "cfg1":
         return gen.config1()
+    if name == "cfg4":
+        return gen.config4()
+    if name == "cfg5":
+        return gen.config5()
     raise SystemExit(f"unknown workload {name}")
+
+
+def batch_bench(a):
+    """64 geometries of uneven size in one launch per pass: geometry solves/s."""
+    import torch
+    import paper_2106_02764_amd as P
+    from inputs import gen
+    geoms = gen.config3()
+    solvers = [P.Solver.from_workload(w) for w in geoms]
+    dof = sum(w.dof for w in geoms)
+    ref, _ = P.solve_batch(solvers, P.default_opts(outer_tol=1e-10, inner_tol=1e-12,
+                                                   fourier_tol=1e-10, max_outer=4000))
+    out = {}
+    for name, prec, itol in (("fp32", 1, 1e-5), ("fp64", 0, 1e-8)):
+        o = P.default_opts(precision=prec, outer_tol=3e-6, inner_tol=itol, inner_rtol=0.3,
+                           lag_wrap=1, fourier_tol=1e-6, max_outer=4000, passes_per_graph=4)
+        o.waves_per_group = P.autotune.tune(solvers, o)
+        for _ in range(a.warmup):
+            P.solve_batch(solvers, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            k, st = P.solve_batch(solvers, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        err = max(abs(x - y) / y for x, y in zip(k, ref))
+        out[name] = {"geometry_solves_per_s": len(geoms) / dt, "ms_per_batch": 1e3 * dt,
+                     "dof_per_s": dof / dt, "max_kappa_rel_err_vs_fp64_ref": err,
+                     "waves_per_group": o.waves_per_group,
+                     "max_passes": max(x["outer_iters"] for x in st)}
+    print(json.dumps({"workload": "64 periodic geometries (48^2..256^2, 1-4 circular pores, "
+                      "L 50-500 nm), 48 directions x 30 MFPs, one launch per pass",
+                      "dof": dof, **out}), flush=True)
 
 
 def time_solves(P, solver, opts, steps, warmup):
@@ -138,6 +175,9 @@ def main():
     a = parse()
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.workload == "cfg3":
+        batch_bench(a)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "

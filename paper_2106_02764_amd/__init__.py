@@ -5,7 +5,7 @@ source iteration of the anisotropic-MFP phonon BTE; this package only
 marshals arguments to it.  Importing the binding requires the built library:
 there is no CPU fallback.
 """
-from . import obte
+from . import autotune, obte
 from .obte import ObteError, default_opts, lib
 from .solver import KappaEff, Solver, solve_batch
 

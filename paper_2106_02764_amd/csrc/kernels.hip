@@ -711,6 +711,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
             T e[NZ][CPL], eb[NZ][CPL], rh[NZ][CPL], p[NZ][CPL], v[NZ][CPL], sv[NZ][CPL], t[NZ][CPL];
             VLOOP({ e[k][c] = T(0); eb[k][c] = T(0); rh[k][c] = r[k][c]; p[k][c] = T(0); v[k][c] = T(0); });
             double best = rn;
+            int restarts = 0;
             double rho_old = 1.0, alpha = 1.0, omega = 1.0;
             for (int iter = 0; iter < pp.max_inner; ++iter) {
                 double rho = vdot<T, CPL, NZ>(rh, r);
@@ -726,7 +727,14 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
                 mem.insert(p, v);
                 const double rv = vdot<T, CPL, NZ>(rh, v);
-                if (!(rv != 0.0) || !isfinite(rv)) break;
+                if (!isfinite(rv)) break;
+                if (!(fabs(rv) > 1e-30 * fabs(rho))) {
+                    // breakdown (shadow residual orthogonal to A p): restart
+                    // from the current residual on the next iteration
+                    if (restarts++ >= 4) break;
+                    omega = 0.0;
+                    continue;
+                }
                 alpha = rho / rv;
                 VLOOP(sv[k][c] = r[k][c] - (T)alpha * v[k][c]);
                 const double sn = sqrt(vdot<T, CPL, NZ>(sv, sv));

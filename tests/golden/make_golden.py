@@ -3,6 +3,9 @@
 Calls only the CPU oracle (oracle/) on the seeded inputs (inputs/gen.py) and
 stores kappa_cc, kappa_face, kappa_fourier, per-MFP kappa and T_L at seeded
 sample cells.  Run:  python tests/golden/make_golden.py cfg2 [--workers 8]
+
+``cfg3`` stores kappa_cc / kappa_face of the members of the 64-geometry batch
+whose grids are 48x48 or 64x64 (the oracle's cost grows quickly with the grid).
 """
 import argparse
 import json
@@ -21,10 +24,12 @@ from oracle.parallel import source_iteration_parallel  # noqa: E402
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["cfg2", "cfg4"])
+    ap.add_argument("config", choices=["cfg2", "cfg3", "cfg4"])
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-11)
     a = ap.parse_args()
+    if a.config == "cfg3":
+        return batch(a)
     w = gen.config2() if a.config == "cfg2" else gen.config4()
     t0 = time.time()
     r = source_iteration_parallel(w, n_workers=a.workers, tol=a.tol, verbose=True)
@@ -45,6 +50,28 @@ def main():
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path, out["kappa_cc"], out["passes"])
+
+
+def batch(a):
+    geoms = gen.config3()
+    members = []
+    t0 = time.time()
+    for g, w in enumerate(geoms):
+        if w.n[0] > 64:
+            continue
+        r = source_iteration_parallel(w, n_workers=a.workers, tol=a.tol)
+        h = r["history"]
+        members.append({"index": g, "n": w.n[0], "L": w.L[0], "passes": r["passes"],
+                        "converged": bool(r["converged"]), "kappa_cc": r["kappa_cc"],
+                        "kappa_face": r["kappa_face"], "kappa_fourier": r["kappa_fourier"],
+                        "history_tail": list(map(float, h[-4:]))})
+        print(g, w.n[0], r["passes"], r["kappa_cc"], flush=True)
+    out = {"config": "cfg3", "tol": a.tol, "members": members, "seconds": time.time() - t0,
+           "source": "oracle.parallel.source_iteration_parallel (FP64, SuperLU per system)"}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg3_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", path)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,74 @@
+"""The 64-geometry batched launch (every geometry's systems in one launch per
+pass) against the oracle's stored values for its small members
+(tests/golden/cfg3_oracle.json), against single-geometry solves, and the
+FP32-sweep form against FP64."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from inputs import gen
+from tests.gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_oracle.json")
+
+
+@pytest.fixture(scope="module")
+def P():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def geoms():
+    return gen.config3()
+
+
+@pytest.fixture(scope="module")
+def solvers(P, geoms):
+    return [P.Solver.from_workload(w) for w in geoms]
+
+
+@pytest.fixture(scope="module")
+def k64(P, solvers):
+    o = P.default_opts(outer_tol=1e-12, inner_tol=1e-13, fourier_tol=1e-12, max_outer=6000)
+    k, st = P.solve_batch(solvers, o)
+    assert all(s["status"] == 0 for s in st), [s["status"] for s in st]
+    return np.asarray(k), st
+
+
+def test_batch_fp64_vs_oracle(k64):
+    k, st = k64
+    g = json.load(open(GOLD))
+    assert len(g["members"]) >= 8
+    for m in g["members"]:
+        # both sides stop at a 1e-12 relative change; the slowest members
+        # contract at ~0.97 per pass, fixed-point error ~3e-11 each
+        ref = m["kappa_cc"]
+        assert abs(k[m["index"]] - ref) <= 1e-9 * ref, (m["index"], k[m["index"]], ref)
+        assert abs(st[m["index"]]["kappa_face"] - m["kappa_face"]) <= 1e-9 * m["kappa_face"]
+        assert abs(st[m["index"]]["kappa_fourier"] - m["kappa_fourier"]) <= 1e-9 * m["kappa_fourier"]
+
+
+def test_batch_vs_single_fixed_passes(P, geoms, solvers):
+    """Same number of passes in the batch and alone: the per-system work is
+    the same, only the launch grouping differs."""
+    o = P.default_opts(outer_tol=0.0, max_outer=40, inner_tol=1e-13, fourier_tol=1e-12)
+    kb, _ = P.solve_batch(solvers, o)
+    sizes = [w.n[0] for w in geoms]
+    for n in sorted(set(sizes)):
+        i = sizes.index(n)
+        k1 = P.Solver.from_workload(geoms[i]).solve(o, want_T_L=False)["kappa"]
+        assert abs(kb[i] - k1) <= 1e-11 * abs(k1), (i, n, kb[i], k1)
+
+
+def test_batch_fp32_vs_fp64(P, solvers, k64):
+    k, _ = k64
+    for lag, rtol in ((1, 0.3), (0, 0.0)):
+        k32, st = P.solve_batch(solvers, P.default_opts(precision=1, outer_tol=1e-6, inner_tol=1e-5,
+                                                        inner_rtol=rtol, lag_wrap=lag,
+                                                        fourier_tol=1e-8, max_outer=6000))
+        assert all(s["status"] == 0 for s in st)
+        rel = np.abs(np.asarray(k32) - k) / k
+        assert rel.max() <= 1e-4, (lag, rtol, rel.max(), int(rel.argmax()))
