@@ -49,7 +49,9 @@ typedef enum {
  * thermalising walls.  grad_axis must be periodic; the image across its
  * periodic plane obeys T(x + L) = T(x) - dT_ext.
  * GPU-path limits: ndim 2 or 3; periodic[0] and periodic[1] may be 0 or 1,
- * periodic[2] must be 0 in 3D; n[0] <= 256; in 3D n[2] <= 16; grad_axis 0/1. */
+ * periodic[2] must be 0 in 3D; n[0] <= 256; in 3D n[2] <= 128, and a solve
+ * rejects meshes whose per-wave LDS rows (1 + 2 ndim reduction rows of ceil(n[0]/64) * 64
+ * doubles plus, in 3D, n[2] rows in the compute type) exceed 64 KiB; grad_axis 0/1. */
 typedef struct {
     int ndim;
     int n[3];
@@ -102,10 +104,18 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * forward checkpoint obte_adjoint needs; n_systems * n_cells doubles).
  * recycle: Krylov pairs kept per system across outer passes (0..32): the
  * periodic-wrap matrix of a system is fixed during a solve, so earlier
- * products project most of a later pass's wrap residual away.
+ * products project most of a later pass's wrap residual away.  2D meshes
+ * only; experimental (the orthogonalised pairs lose accuracy over many
+ * passes), off by default.
  * timing: record HIP events on `stream` around every sweep, reduction and
  * Fourier launch and report their summed durations in obte_stats (the pass
- * kernels are then launched directly instead of through a HIP graph). */
+ * kernels are then launched directly instead of through a HIP graph).
+ * stop_rule: 0 = the relative change test above (Algorithm 1); 1 = the
+ * estimated remaining error |kappa_n - kappa_{n-1}| rho/(1 - rho) <=
+ * outer_tol |kappa_n|, with the contraction rho taken as the larger of the
+ * last two ratios of successive changes (clamped to [0, 0.995]); a slowly
+ * contracting geometry then runs longer and a fast one stops earlier, so
+ * outer_tol bounds the error of kappa rather than its last change. */
 typedef struct {
     int precision;
     double outer_tol;
@@ -124,6 +134,7 @@ typedef struct {
     double inner_rtol;
     double wrap_tol;
     int timing;
+    int stop_rule;
 } obte_solve_opts;
 
 typedef struct {

@@ -90,7 +90,7 @@ namespace {
 struct Layout {
     size_t sigma, sigma_f, sT, Tw, T_L, U, part_TL, part_Tw, part_J, ksys, kfsys, iters, sweeps,
         hist, hist_face, ctrl, fx, fscal, Tstore, lam_psi, lam_phi, grad, part_G, bnd, mem, mem_count,
-        mem_bytes, wres, wres_hist, total;
+        mem_bytes, wres, wres_hist, kry, total;
 };
 
 int auto_waves(const obte_mesh* m) {
@@ -137,6 +137,7 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.wres = take((size_t)m->n_sys * 8);
     // the parts below depend on precision / recycle / keep_state
     L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
+    L.kry = m->nz > 1 ? take((size_t)m->n_sys * KRY3_VECS * nwrap * tsz) : 0;
     L.mem_bytes = 2 * (size_t)m->n_sys * 2 * (size_t)std::max(o->recycle, 0) * nwrap * tsz;
     L.mem = take(L.mem_bytes);
     L.Tstore = o->keep_state ? take((size_t)m->n_sys * nc * 8) : 0;
@@ -169,6 +170,7 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.Tw = (double*)(ws + L.Tw);
         g.T_L = (double*)(ws + L.T_L);
         g.U = ws + L.U;
+        g.kry = L.kry ? ws + L.kry : nullptr;
         g.part_TL = (double*)(ws + L.part_TL);
         g.part_Tw = (double*)(ws + L.part_Tw);
         g.part_J = (double*)(ws + L.part_J);
@@ -232,6 +234,7 @@ obte_status check_opts(const obte_solve_opts* o) {
     if (o->lag_wrap != 0 && o->lag_wrap != 1) return fail(OBTE_ERR_ARG, "lag_wrap must be 0 or 1");
     if (!(o->wrap_tol >= 0.0)) return fail(OBTE_ERR_ARG, "wrap_tol must be >= 0");
     if (!(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0)) return fail(OBTE_ERR_ARG, "inner_rtol must be in [0, 1)");
+    if (o->stop_rule != 0 && o->stop_rule != 1) return fail(OBTE_ERR_ARG, "stop_rule must be 0 or 1");
     return OBTE_OK;
 }
 
@@ -307,16 +310,23 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
             if (auto_waves(meshes[i]) != W)
                 return fail(OBTE_ERR_ARG, "meshes differ in their automatic waves_per_group; set it explicitly");
     }
+    size_t per_wave = 0;
     {
         int cpl = 1, nzm = 1;
         for (int i = 0; i < n; ++i) { cpl = std::max(cpl, (meshes[i]->nx + 63) / 64); nzm = std::max(nzm, meshes[i]->nz); }
         const int nd = nzm > 1 ? 3 : 2;
-        const size_t per_wave = (size_t)(1 + 2 * nd) * 64 * (nzm > 1 ? 1 : cpl) * sizeof(double);
-        const int wmax = (int)std::max<size_t>(1, (64 * 1024) / per_wave);
+        // reduction rows, plus in 3D one row per z-plane in the compute type
+        per_wave = (size_t)red_rows(nd) * 64 * cpl * sizeof(double);
+        if (nzm > 1) per_wave += (size_t)nzm * 64 * cpl * (o->precision == OBTE_FP32 ? 4 : 8);
+        const size_t cap = 64 * 1024;
+        if (per_wave > cap)
+            return fail(OBTE_ERR_ARG, "a wave needs %zu bytes of LDS (nx, nz too large; limit %zu)", per_wave, cap);
+        const int wmax = (int)(cap / per_wave);
         if (W > wmax) {
             if (o->waves_per_group) return fail(OBTE_ERR_ARG, "waves_per_group %d needs more than 64 KiB of LDS (max %d)", W, wmax);
             W = wmax;
         }
+        if (nzm > 1 && o->recycle > 0) return fail(OBTE_ERR_ARG, "recycle is not available for 3D meshes");
     }
     R.waves = W;
     size_t off = 0;
@@ -344,15 +354,10 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         R.max_walls = std::max(R.max_walls, m->nwalls);
         off += align256(L.total);
     }
-    if (R.nzmax > 1 && R.cpl > 1) return fail(OBTE_ERR_ARG, "3D meshes need nx <= 64");
     for (int gi = 0; gi < n; ++gi)
         if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
             return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
-    const int rowlen = 64 * (R.nzmax > 1 ? 1 : R.cpl);
-    const int ndim = R.nzmax > 1 ? 3 : 2;
-    const int NV = 1 + 2 * ndim;
-    R.lds = (size_t)W * NV * rowlen * sizeof(double);
-    if (R.nzmax > 1) R.lds += (size_t)W * 16 * rowlen * (R.precision == OBTE_FP32 ? 4 : 8);   // z-plane rows
+    R.lds = (size_t)W * per_wave;
     HIPCHK(hipMalloc((void**)&R.d_views, R.views.size() * sizeof(GeomDev)));
     HIPCHK(hipMalloc((void**)&R.d_items, R.items.size() * sizeof(Item)));
     HIPCHK(hipMemcpy(R.d_views, R.views.data(), R.views.size() * sizeof(GeomDev), hipMemcpyHostToDevice));
@@ -432,6 +437,7 @@ PassParams base_params(const obte_solve_opts* o) {
     pp.lag_wrap = o->lag_wrap;
     pp.inner_rtol = o->inner_rtol;
     pp.wrap_tol = o->wrap_tol > 0.0 ? o->wrap_tol : std::max(o->inner_tol, 10.0 * o->outer_tol);
+    pp.stop_rule = o->stop_rule;
     return pp;
 }
 
@@ -610,6 +616,7 @@ void obte_default_opts(obte_solve_opts* o) {
     o->inner_rtol = 0.0;
     o->wrap_tol = 0.0;
     o->timing = 0;
+    o->stop_rule = 0;
 }
 
 obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
@@ -625,8 +632,9 @@ obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
     }
     if (d->n[0] > 256) return fail(OBTE_ERR_ARG, "n[0] must be <= 256");
     if (d->ndim == 3) {
-        if (d->n[0] > 64) return fail(OBTE_ERR_ARG, "3D meshes need n[0] <= 64");
-        if (nz > 16) return fail(OBTE_ERR_ARG, "3D meshes need n[2] <= 16");
+        // one wave keeps a row per z-plane in LDS (checked against the LDS
+        // budget per solve, which depends on the precision)
+        if (nz > 128) return fail(OBTE_ERR_ARG, "3D meshes need n[2] <= 128");
         if (d->periodic[2]) return fail(OBTE_ERR_ARG, "periodic z is not supported (diffuse top/bottom)");
     }
     if (d->grad_axis < 0 || d->grad_axis > 1) return fail(OBTE_ERR_ARG, "grad_axis must be 0 or 1");

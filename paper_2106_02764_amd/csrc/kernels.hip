@@ -125,12 +125,6 @@ __device__ __forceinline__ const double* sigma_ptr<double>(const GeomDev& g) { r
 template <>
 __device__ __forceinline__ const float* sigma_ptr<float>(const GeomDev& g) { return g.sigma_f; }
 
-template <typename T>
-__device__ __forceinline__ T sigma_of(const GeomDev& g, int cell);
-template <>
-__device__ __forceinline__ double sigma_of<double>(const GeomDev& g, int cell) { return g.sigma[cell]; }
-template <>
-__device__ __forceinline__ float sigma_of<float>(const GeomDev& g, int cell) { return g.sigma_f[cell]; }
 
 // ---------------------------------------------------------------------------
 // cross-lane primitives: DPP row shifts / row broadcasts / wave shift and
@@ -225,12 +219,12 @@ struct Views {
     gptr_t<double> src, bx, by, bz;
 };
 
-template <typename T, int CPL, int NZ, bool WITH_B>
+template <typename T, int CPL, bool D3, bool WITH_B>
 __device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, const Views<T>& v, int lane,
                                          int jj, int kk, RowIn<T, CPL>& r) {
     const int nx = g.nx;
     const int iy = s.pos[1] ? jj : g.ny - 1 - jj;
-    const int iz = (NZ > 1) ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
+    const int iz = D3 ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
     const int rowbase = nx * (iy + g.ny * iz);
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
@@ -243,47 +237,65 @@ __device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, con
             r.sb[c] = v.src[cell];
             r.bx[c] = v.bx[cell];
             r.by[c] = v.by[cell];
-            if (NZ > 1) r.bz[c] = v.bz[cell];
+            if (D3) r.bz[c] = v.bz[cell];
         }
     }
 }
 
-// Row storage of the sweep: registers in 2D; in 3D one row per z-plane in
-// this wave's LDS region (the z index is a runtime value there).
-template <typename T, int CPL, int NZ>
+// Row storage of the sweep.  2D: the previous row in registers.  3D: the
+// previous y-row of every z-plane in this wave's LDS region (the plane index
+// is a runtime value), and the row just below in z in registers.
+template <typename T, int CPL, bool D3>
 struct Rows {
-    T xr[CPL];
-    T* xz;        // NZ * ROW values (3D)
+    T xr[CPL];    // 2D: row jj-1; 3D: row (jj, kk-1)
+    T* xz;        // 3D: nz * ROW values, plane kk holds row (jj-1, kk) until overwritten
     int ROW;
     __device__ __forceinline__ T prev_y(int kk, int c, int lane) const {
-        return NZ > 1 ? xz[kk * ROW + lane * CPL + c] : xr[c];
+        return D3 ? xz[kk * ROW + lane * CPL + c] : xr[c];
     }
-    __device__ __forceinline__ T prev_z(int kk, int c, int lane) const {
-        return NZ > 1 ? xz[(kk - 1) * ROW + lane * CPL + c] : T(0);
-    }
+    __device__ __forceinline__ T prev_z(int c) const { return D3 ? xr[c] : T(0); }
     __device__ __forceinline__ void put(int kk, int c, int lane, T v) {
-        if (NZ > 1) xz[kk * ROW + lane * CPL + c] = v;
-        else xr[c] = v;
+        if (D3) xz[kk * ROW + lane * CPL + c] = v;
+        xr[c] = v;
     }
 };
 
-// Wrap-row vectors (u in, last row out): registers in 2D, LDS rows in 3D.
-template <typename T, int CPL, int NZ>
-struct WrapIO {
-    const T (*u)[CPL];      // [NZ][CPL] registers (2D path)
-    T (*xl)[CPL];
+// Wrap-row input (inflow u of the first row) and output (the last row).
+// 2D: register arrays of this lane.  3D: the system's nz x nx plane in
+// global memory, element (kk, p) at kk * nx + p, always touched by the lane
+// that owns column p, so no cross-lane ordering is needed.
+template <typename T, int CPL>
+struct RegIO {
+    const T (&u)[CPL];
+    T (&xl)[CPL];
+    __device__ __forceinline__ T in(int, int c, int) const { return u[c]; }
+    __device__ __forceinline__ void out(int, int c, int, T v) { xl[c] = v; }
+};
+template <typename T, int CPL>
+struct GlobIO {
+    const T* u;
+    T* xl;        // nullptr: the last row is not needed
+    int nx;
+    int active;
+    __device__ __forceinline__ T in(int kk, int c, int lane) const {
+        const int p = lane * CPL + c;
+        return p < nx ? u[kk * nx + p] : T(0);
+    }
+    __device__ __forceinline__ void out(int kk, int c, int lane, T v) {
+        const int p = lane * CPL + c;
+        if (xl && active && p < nx) xl[kk * nx + p] = v;
+    }
 };
 
 // One row step of the sweep (cells of row (jj, kk) in upwind order).
-template <typename T, int CPL, int NZ, bool WITH_B, bool RED, bool ADD>
+template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, class IO>
 __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, const Views<T>& vw,
                                          int active, int lane, int adj, int jj, int kk,
-                                         const RowIn<T, CPL>& cur, Rows<T, CPL, NZ>& rows,
-                                         const T (&u)[NZ][CPL], T (&xl)[NZ][CPL],
+                                         const RowIn<T, CPL>& cur, Rows<T, CPL, D3>& rows, IO& io,
                                          const double (&mb)[3], const double (&wo)[3], Red* rd) {
-    constexpr int ND = NZ > 1 ? 3 : 2;
+    constexpr int ND = D3 ? 3 : 2;
     const int nx = g.nx, ny = g.ny;
-    const T cz = (NZ > 1) ? s.c[2] : T(0);
+    const T cz = D3 ? s.c[2] : T(0);
     T a[CPL], q[CPL];
     T Al = T(0), Ql = T(1), Pl = T(0);
 #pragma unroll
@@ -293,26 +305,21 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         const bool sol = active && fc_solid(w);
         const int clx = fc_class(w, s.fin[0]);
         const int cly = fc_class(w, s.fin[1]);
-        const int clz = (NZ > 1) ? fc_class(w, s.fin[2]) : FC_WALL;
+        const int clz = D3 ? fc_class(w, s.fin[2]) : FC_WALL;
         const T sg = cur.sg[c];
         const T rdv = recip(sg + s.c[0] + s.c[1] + cz);
         T src = T(0);
         if (WITH_B) {
             double sd = adj ? s.kw + s.Dml * cur.sb[c] : cur.sb[c];
             sd += mb[0] * cur.bx[c] + mb[1] * cur.by[c];
-            if (NZ > 1) sd += mb[2] * cur.bz[c];
+            if (D3) sd += mb[2] * cur.bz[c];
             src = (T)sd;
         }
-        // kk and jj are wave-uniform; u / xz rows are read only where used
-        T yup = (jj == 0) ? u[NZ > 1 ? 0 : 0][c] : T(0);
-        if (NZ > 1 && jj == 0) {
-#pragma unroll
-            for (int k2 = 0; k2 < NZ; ++k2)
-                if (k2 == kk) yup = u[k2][c];
-        }
-        const T yin = (cly != FC_WALL) ? ((jj == 0) ? yup : s.c[1] * rows.prev_y(kk, c, lane)) : T(0);
+        // kk and jj are wave-uniform: the wrap input is read on the first row only
+        T yin = T(0);
+        if (cly != FC_WALL) yin = (jj == 0) ? io.in(kk, c, lane) : s.c[1] * rows.prev_y(kk, c, lane);
         T zin = T(0);
-        if (NZ > 1) zin = (clz != FC_WALL && kk > 0) ? cz * rows.prev_z(kk > 0 ? kk : 1, c, lane) : T(0);
+        if (D3) zin = (clz != FC_WALL && kk > 0) ? cz * rows.prev_z(c) : T(0);
         const bool xs = (clx != FC_WALL);
         T av = (src + yin + zin) * rdv;
         T qv = xs ? s.c[0] * rdv : T(0);
@@ -343,14 +350,11 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
     }
     if (jj == ny - 1) {
 #pragma unroll
-        for (int k2 = 0; k2 < NZ; ++k2)
-            if (k2 == kk)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) xl[k2][c] = xrow[c];
+        for (int c = 0; c < CPL; ++c) io.out(kk, c, lane, xrow[c]);
     }
     if (RED) {
         const int iy = s.pos[1] ? jj : ny - 1 - jj;
-        const int iz = (NZ > 1) ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
+        const int iz = D3 ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
         const int rowbase = nx * (iy + ny * iz);
         double* buf = rd->lds;
         const int ROW = rd->ROW, W = rd->W;
@@ -447,11 +451,11 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 // block.  Returns the last row (jj = ny-1) in xl.  Row inputs are prefetched
 // two rows ahead (2D) through a three-buffer rotation without copies.
 // ---------------------------------------------------------------------------
-template <typename T, int CPL, int NZ, bool WITH_B, bool RED, bool ADD>
+template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, class IO>
 __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int active, int lane, int adj,
                                       const double* __restrict__ srcbase, const double* __restrict__ bnd,
-                                      const T (&u)[NZ][CPL], T (&xl)[NZ][CPL], Red* rd, T* zrows) {
-    constexpr int ND = NZ > 1 ? 3 : 2;
+                                      IO& io, Red* rd, T* zrows) {
+    constexpr int ND = D3 ? 3 : 2;
     double mb[3], wo[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -464,51 +468,43 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     vw.src = gview(srcbase);
     vw.bx = gview(bnd + (size_t)s.fin[0] * g.ncells);
     vw.by = gview(bnd + (size_t)s.fin[1] * g.ncells);
-    vw.bz = gview(bnd + (size_t)(NZ > 1 ? s.fin[2] : 0) * g.ncells);
-    Rows<T, CPL, NZ> rows;
+    vw.bz = gview(bnd + (size_t)(D3 ? s.fin[2] : 0) * g.ncells);
+    Rows<T, CPL, D3> rows;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) rows.xr[c] = T(0);
     rows.xz = zrows;
     rows.ROW = WAVE * CPL;
     const int ny = g.ny;
-    if (NZ == 1) {
+    if (!D3) {
         RowIn<T, CPL> b0, b1, b2;
-        load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, 0, 0, b0);
-        if (ny > 1) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, 1, 0, b1);
+        load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 0, 0, b0);
+        if (ny > 1) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 1, 0, b1);
         for (int jj = 0; jj < ny; jj += 3) {
-            if (jj + 2 < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, jj + 2, 0, b2);
-            row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, 0, b0, rows, u, xl, mb, wo, rd);
+            if (jj + 2 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 2, 0, b2);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, 0, b0, rows, io, mb, wo, rd);
             if (jj + 1 >= ny) break;
-            if (jj + 3 < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, jj + 3, 0, b0);
-            row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 1, 0, b1, rows, u, xl, mb, wo, rd);
+            if (jj + 3 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 3, 0, b0);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 1, 0, b1, rows, io, mb, wo, rd);
             if (jj + 2 >= ny) break;
-            if (jj + 4 < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, jj + 4, 0, b1);
-            row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 2, 0, b2, rows, u, xl, mb, wo, rd);
+            if (jj + 4 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 4, 0, b1);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 2, 0, b2, rows, io, mb, wo, rd);
         }
     } else {
-        // 3D: rows (jj, kk) with kk inner; ping-pong buffers one row ahead
-        const int nz = g.nz;
-        RowIn<T, CPL> b0, b1;
-        load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, 0, 0, b0);
-        for (int jj = 0; jj < ny; ++jj) {
-            for (int kk = 0; kk < nz; kk += 2) {
-                {
-                    int nj = jj, nk = kk + 1;
-                    if (nk >= nz) { nk = 0; ++nj; }
-                    if (nj < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, nj, nk, b1);
-                }
-                row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, kk, b0, rows, u, xl, mb, wo, rd);
-                if (kk + 1 >= nz) {      // odd nz: the next row already sits in b1
-                    b0 = b1;
-                    break;
-                }
-                {
-                    int nj = jj, nk = kk + 2;
-                    if (nk >= nz) { nk = 0; ++nj; }
-                    if (nj < ny) load_row<T, CPL, NZ, WITH_B>(g, s, vw, lane, nj, nk, b0);
-                }
-                row_step<T, CPL, NZ, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, kk + 1, b1, rows, u, xl, mb, wo, rd);
-            }
+        // 3D: rows (jj, kk) with kk inner; a three-buffer rotation keeps the
+        // inputs two rows ahead (the row order is y-major, z-minor)
+        const int nz = g.nz, nrows = ny * nz;
+        RowIn<T, CPL> b0, b1, b2;
+        load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 0, 0, b0);
+        if (nrows > 1) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 1 / nz, 1 % nz, b1);
+        for (int r = 0; r < nrows; r += 3) {
+            if (r + 2 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 2) / nz, (r + 2) % nz, b2);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, r / nz, r % nz, b0, rows, io, mb, wo, rd);
+            if (r + 1 >= nrows) break;
+            if (r + 3 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 3) / nz, (r + 3) % nz, b0);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, (r + 1) / nz, (r + 1) % nz, b1, rows, io, mb, wo, rd);
+            if (r + 2 >= nrows) break;
+            if (r + 4 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 4) / nz, (r + 4) % nz, b1);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, (r + 2) / nz, (r + 2) % nz, b2, rows, io, mb, wo, rd);
         }
     }
 }
@@ -624,6 +620,27 @@ struct Mem {
     }
 };
 
+// Per-system results of a pass: kappa partials and counters.
+template <typename T>
+__device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s, int active, int lane,
+                                              int adj, const PassParams& pp, const Red& rd,
+                                              long long n_it, long long n_sw) {
+    const double ks = wave_sum(rd.kacc), kf = wave_sum(rd.kface);
+    if (active && lane == 0) {
+        if (adj) {
+            g.ksys[s.sys] = kf;                 // this system's share of p^T lambda
+            g.kfsys[s.sys] = 0.0;
+        } else {
+            g.ksys[s.sys] = g.L[g.grad_axis] / (g.dT * (double)g.ncells) * s.Sg * ks;
+            g.kfsys[s.sys] = g.L[g.grad_axis] / (g.dT * (double)g.n_perp) * s.Sg * kf;
+        }
+        if (pp.mode == 0) {
+            g.iters[s.sys] += n_it;
+            g.sweeps[s.sys] += n_sw;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // One outer pass for every work item (block = one item = W systems sharing a
 // direction).  Phase A: all waves sweep in lockstep with the sources b and
@@ -632,10 +649,11 @@ struct Mem {
 // row).  Phase C: if any wave changed u, a lockstep correction sweep with
 // source P (u - u0) adds its (linear) contribution to the reductions.
 // ---------------------------------------------------------------------------
-template <typename T, int CPL, int NZ>
+template <typename T, int CPL>
 __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ geoms,
                                                     const Item* __restrict__ items, int n_items,
                                                     PassParams pp) {
+    constexpr int NZ = 1;      // 2D: the wrap row is one x-row, held in registers
     extern __shared__ double lds[];
     const int it = blockIdx.x;
     if (it >= n_items) return;
@@ -662,9 +680,6 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     mem.base = reinterpret_cast<T*>(g.mem) + (half + s.sys) * (size_t)2 * g.mem_R * g.nwrap;
     mem.count = g.mem_count + half + s.sys;
 
-    // 3D: per-wave LDS rows (one per z-plane) after the reduction buffers
-    constexpr int NVR = 1 + 2 * (NZ > 1 ? 3 : 2);
-    T* zrows = reinterpret_cast<T*>(lds + (size_t)W * NVR * WAVE * CPL) + (size_t)w * NZ * WAVE * CPL;
     T u[NZ][CPL], xl[NZ][CPL], mk[NZ][CPL];
     wrap_mask<T, CPL, NZ>(g, s, active, lane, mk);
     VLOOP({
@@ -682,7 +697,10 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     rd.kacc = 0.0;
     rd.kface = 0.0;
     // ---- phase A
-    sweep<T, CPL, NZ, true, true, false>(g, s, active, lane, adj, srcbase, bnd, u, xl, &rd, zrows);
+    {
+        RegIO<T, CPL> io{u[0], xl[0]};
+        sweep<T, CPL, false, true, true, false>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+    }
     long long n_it = 0, n_sw = 1;
     int need = 0;
     T du[NZ][CPL];
@@ -722,7 +740,10 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 }
                 const double beta = (rho / rho_old) * (alpha / omega);
                 VLOOP(p[k][c] = r[k][c] + (T)beta * (p[k][c] - (T)omega * v[k][c]));
-                sweep<T, CPL, NZ, false, false, false>(g, s, active, lane, adj, srcbase, bnd, p, xl, nullptr, zrows);
+                {
+                    RegIO<T, CPL> io{p[0], xl[0]};
+                    sweep<T, CPL, false, false, false, false>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                }
                 ++n_sw;
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
                 mem.insert(p, v);
@@ -744,7 +765,10 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                     if (sn < best) { best = sn; VLOOP(eb[k][c] = e[k][c]); }
                     break;
                 }
-                sweep<T, CPL, NZ, false, false, false>(g, s, active, lane, adj, srcbase, bnd, sv, xl, nullptr, zrows);
+                {
+                    RegIO<T, CPL> io{sv[0], xl[0]};
+                    sweep<T, CPL, false, false, false, false>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                }
                 ++n_sw;
                 VLOOP(t[k][c] = sv[k][c] - mk[k][c] * xl[k][c]);
                 mem.insert(sv, t);
@@ -773,24 +797,209 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     // ---- phase C: lockstep correction sweep when any wave moved its inflow
     // (skipped when the correction is lagged into the next pass)
     if (!pp.lag_wrap && __syncthreads_or(need)) {
-        sweep<T, CPL, NZ, false, true, true>(g, s, active && need, lane, adj, srcbase, bnd, du, xl, &rd, zrows);
+        RegIO<T, CPL> io{du[0], xl[0]};
+        sweep<T, CPL, false, false, true, true>(g, s, active && need, lane, adj, srcbase, bnd, io, &rd, nullptr);
         ++n_sw;
     }
-    const double ks = wave_sum(rd.kacc), kf = wave_sum(rd.kface);
-    if (active && lane == 0) {
-        if (adj) {
-            g.ksys[s.sys] = kf;                 // this system's share of p^T lambda
-            g.kfsys[s.sys] = 0.0;
-        } else {
-            g.ksys[s.sys] = g.L[g.grad_axis] / (g.dT * (double)g.ncells) * s.Sg * ks;
-            g.kfsys[s.sys] = g.L[g.grad_axis] / (g.dT * (double)g.n_perp) * s.Sg * kf;
-        }
-        if (pp.mode == 0) {
-            g.iters[s.sys] += n_it;
-            g.sweeps[s.sys] += n_sw;
-        }
-    }
+    finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
 }
+
+// ---------------------------------------------------------------------------
+// The 3D pass.  Same phases as the 2D kernel; the wrap plane of a system
+// (nx * nz values) is too large for registers, so its Krylov vectors live in
+// a per-system slab of the workspace (KV_N planes).  Every element (k, p) is
+// read and written only by the lane owning column p, as in the sweep.
+// ---------------------------------------------------------------------------
+enum { KV_XL, KV_MK, KV_DU, KV_R, KV_E, KV_EB, KV_RH, KV_P, KV_V, KV_S, KV_T, KV_N };
+static_assert(KV_N == KRY3_VECS, "workspace carve and kernel disagree on the 3D slab");
+
+#define PLOOP(body)                                     \
+    for (int k = 0; k < nz; ++k)                        \
+        _Pragma("unroll") for (int c = 0; c < CPL; ++c) { \
+            const int p_ = lane * CPL + c;              \
+            if (p_ < nx) {                              \
+                const int i = k * nx + p_;              \
+                body;                                   \
+            }                                           \
+        }
+
+template <typename T, int CPL>
+__global__ void __launch_bounds__(512) k_sweep_pass3(const GeomDev* __restrict__ geoms,
+                                                     const Item* __restrict__ items, int n_items,
+                                                     PassParams pp) {
+    extern __shared__ double lds[];
+    const int it = blockIdx.x;
+    if (it >= n_items) return;
+    const Item item = items[it];
+    const GeomDev& g = geoms[item.geom];
+    if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int m = item.m0 + w;
+    const int active = (w < item.nm) && (m < g.n_mfp);
+    const int adj = pp.adjoint;
+    const SysC<T> s = make_sys<T>(g, active ? m : item.m0, item.l, adj);
+    const int pass = g.ctrl[CTRL_PASS];
+    const int buf_in = (pp.mode == 1) ? ((pass + 1) & 1) : (pass & 1);
+    const double* srcbase = adj ? (g.lam_psi + (size_t)buf_in * g.ncells) : (g.sT + (size_t)buf_in * g.ncells);
+    const double* bnd = g.bnd + ((size_t)(adj ? 2 : 0) + buf_in) * g.nf * g.ncells;
+    const int nx = g.nx, nz = g.nz, nw = g.nwrap;
+    const size_t half = adj ? (size_t)g.n_sys : 0;
+    T* U = reinterpret_cast<T*>(g.U) + (half + s.sys) * (size_t)nw;
+    T* K = reinterpret_cast<T*>(g.kry) + (size_t)s.sys * KV_N * nw;
+    T* xl = K + (size_t)KV_XL * nw;
+    T* du = K + (size_t)KV_DU * nw;
+    // per-wave LDS: the reduction rows, then nz rows of this wave
+    constexpr int NVR = red_rows(3);
+    T* zrows = reinterpret_cast<T*>(lds + (size_t)W * NVR * WAVE * CPL) + (size_t)w * nz * WAVE * CPL;
+    Red rd;
+    rd.lds = lds;
+    rd.w = w;
+    rd.W = W;
+    rd.ROW = WAVE * CPL;
+    rd.local = item.local;
+    rd.want_J = pp.want_J;
+    rd.store_T = pp.store_T;
+    rd.kacc = 0.0;
+    rd.kface = 0.0;
+    // ---- phase A
+    {
+        GlobIO<T, CPL> io{U, xl, nx, active};
+        sweep<T, CPL, true, true, true, false>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+    }
+    long long n_it = 0, n_sw = 1;
+    int need = 0;
+    const bool has_wrap = g.periodic[1] != 0;
+    if (pp.mode == 0 && active && has_wrap) {
+        T* mk = K + (size_t)KV_MK * nw;
+        T* r = K + (size_t)KV_R * nw;
+        T* e = K + (size_t)KV_E * nw;
+        T* eb = K + (size_t)KV_EB * nw;
+        T* rh = K + (size_t)KV_RH * nw;
+        T* p = K + (size_t)KV_P * nw;
+        T* v = K + (size_t)KV_V * nw;
+        T* sv = K + (size_t)KV_S * nw;
+        T* t = K + (size_t)KV_T * nw;
+        // wrap mask E' (c_y where the pair across the y-wrap is solid), the
+        // inflow produced by the sweep and the residual of the wrap system
+        const int iy = s.pos[1] ? 0 : g.ny - 1;
+        double ss = 0.0, rr = 0.0;
+        PLOOP({
+            const int ix = s.pos[0] ? p_ : nx - 1 - p_;
+            const int iz = s.pos[2] ? k : nz - 1 - k;
+            const uint32_t wv = g.fc[ix + nx * (iy + g.ny * iz)];
+            const T mv = (fc_solid(wv) && fc_class(wv, s.fin[1]) != FC_WALL) ? s.c[1] : T(0);
+            mk[i] = mv;
+            const T ez = mv * xl[i];
+            const T rv = ez - U[i];
+            r[i] = rv;
+            du[i] = T(0);
+            ss += (double)ez * (double)ez;
+            rr += (double)rv * (double)rv;
+        });
+        const double scale = sqrt(wave_sum(ss));
+        double rn = sqrt(wave_sum(rr));
+        const double thr = fmax(pp.inner_tol * scale, pp.inner_rtol * rn);
+        const double thr_final = pp.inner_tol * scale;
+        if (rn > thr_final && scale > 0.0) need = 1;
+        if (rn > thr && scale > 0.0) {
+            // BiCGSTAB on (I - G) e = r with the best iterate kept (as in 2D)
+            PLOOP({ e[i] = T(0); eb[i] = T(0); rh[i] = r[i]; p[i] = T(0); v[i] = T(0); });
+            double best = rn;
+            int restarts = 0;
+            double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+            for (int iter = 0; iter < pp.max_inner; ++iter) {
+                double acc = 0.0;
+                PLOOP(acc += (double)rh[i] * (double)r[i]);
+                double rho = wave_sum(acc);
+                if (fabs(rho) <= 1e-30 * rn * rn || !(omega != 0.0)) {
+                    acc = 0.0;
+                    PLOOP({ rh[i] = r[i]; p[i] = T(0); v[i] = T(0); acc += (double)r[i] * (double)r[i]; });
+                    rho = wave_sum(acc);
+                    rho_old = 1.0; alpha = 1.0; omega = 1.0;
+                }
+                const double beta = (rho / rho_old) * (alpha / omega);
+                PLOOP(p[i] = r[i] + (T)beta * (p[i] - (T)omega * v[i]));
+                {
+                    GlobIO<T, CPL> io{p, xl, nx, 1};
+                    sweep<T, CPL, true, false, false, false>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
+                }
+                ++n_sw;
+                acc = 0.0;
+                PLOOP({
+                    const T vv = p[i] - mk[i] * xl[i];
+                    v[i] = vv;
+                    acc += (double)rh[i] * (double)vv;
+                });
+                const double rv = wave_sum(acc);
+                if (!isfinite(rv)) break;
+                if (!(fabs(rv) > 1e-30 * fabs(rho))) {
+                    if (restarts++ >= 4) break;
+                    omega = 0.0;
+                    continue;
+                }
+                alpha = rho / rv;
+                acc = 0.0;
+                PLOOP({
+                    const T x = r[i] - (T)alpha * v[i];
+                    sv[i] = x;
+                    acc += (double)x * (double)x;
+                });
+                const double sn = sqrt(wave_sum(acc));
+                ++n_it;
+                if (sn <= thr) {
+                    PLOOP(e[i] += (T)alpha * p[i]);
+                    if (sn < best) {
+                        best = sn;
+                        PLOOP(eb[i] = e[i]);
+                    }
+                    break;
+                }
+                {
+                    GlobIO<T, CPL> io{sv, xl, nx, 1};
+                    sweep<T, CPL, true, false, false, false>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
+                }
+                ++n_sw;
+                double tt = 0.0, ts = 0.0;
+                PLOOP({
+                    const T x = sv[i] - mk[i] * xl[i];
+                    t[i] = x;
+                    tt += (double)x * (double)x;
+                    ts += (double)x * (double)sv[i];
+                });
+                tt = wave_sum(tt);
+                ts = wave_sum(ts);
+                omega = tt > 0.0 ? ts / tt : 0.0;
+                acc = 0.0;
+                PLOOP({
+                    e[i] += (T)alpha * p[i] + (T)omega * sv[i];
+                    const T x = sv[i] - (T)omega * t[i];
+                    r[i] = x;
+                    acc += (double)x * (double)x;
+                });
+                rn = sqrt(wave_sum(acc));
+                rho_old = rho;
+                if (!isfinite(rn)) break;
+                if (rn < best) {
+                    best = rn;
+                    PLOOP(eb[i] = e[i]);
+                }
+                if (rn <= thr) break;
+            }
+            rn = best;
+            PLOOP(du[i] += eb[i]);
+        }
+        if (lane == 0) g.wres[s.sys] = scale > 0.0 ? rn / scale : 0.0;
+        if (need) PLOOP(U[i] += du[i]);
+    }
+    // ---- phase C (see the 2D kernel)
+    if (!pp.lag_wrap && __syncthreads_or(need)) {
+        GlobIO<T, CPL> io{du, nullptr, nx, 0};
+        sweep<T, CPL, true, false, true, true>(g, s, active && need, lane, adj, srcbase, bnd, io, &rd, zrows);
+        ++n_sw;
+    }
+    finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
+}
+#undef PLOOP
 
 // ---------------------------------------------------------------------------
 // Per-cell / per-wall sums of the item partials (fixed order) and the next
@@ -899,10 +1108,24 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
         // Algorithm 1's test on the relative change of kappa; with a bounded
         // number of inner iterations per pass the wrap rows must be solved too
         const bool wrap_ok = wr <= pp.wrap_tol;
+        bool small = n >= 2 && fabs(k - g.hist[pass - 1]) <= pp.outer_tol * fabs(k);
+        if (pp.stop_rule == 1) {
+            // error estimate of a linear fixed-point iteration from the
+            // observed contraction of the last three changes
+            small = false;
+            if (n >= 4) {
+                const double d0 = fabs(k - g.hist[pass - 1]);
+                const double d1 = fabs(g.hist[pass - 1] - g.hist[pass - 2]);
+                const double d2 = fabs(g.hist[pass - 2] - g.hist[pass - 3]);
+                double rho = fmax(d1 > 0.0 ? d0 / d1 : 0.0, d2 > 0.0 ? d1 / d2 : 0.0);
+                rho = fmin(rho, 0.995);
+                small = d0 * rho / (1.0 - rho) <= pp.outer_tol * fabs(k);
+            }
+        }
         if (!isfinite(k)) {
             g.ctrl[CTRL_NONFINITE] = 1;
             g.ctrl[CTRL_DONE] = 1;
-        } else if (n >= 2 && wrap_ok && fabs(k - g.hist[pass - 1]) <= pp.outer_tol * fabs(k)) {
+        } else if (wrap_ok && small) {
             g.ctrl[CTRL_CONVERGED] = 1;
             g.ctrl[CTRL_DONE] = 1;
         } else if (n >= pp.max_outer) {
@@ -1279,33 +1502,53 @@ hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, int max_cells, 
     return hipGetLastError();
 }
 
-template <typename T, int CPL, int NZ>
+template <typename T, int CPL>
 static hipError_t launch_sweep_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
                                  size_t lds, hipStream_t st) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL((k_sweep_pass<T, CPL, NZ>), dim3(n), dim3(64 * waves), lds, st, g, it, n, pp);
+    hipLaunchKernelGGL((k_sweep_pass<T, CPL>), dim3(n), dim3(64 * waves), lds, st, g, it, n, pp);
+    return hipGetLastError();
+}
+
+template <typename T, int CPL>
+static hipError_t launch_sweep3_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
+                                  size_t lds, hipStream_t st) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((k_sweep_pass3<T, CPL>), dim3(n), dim3(64 * waves), lds, st, g, it, n, pp);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, const Item* it,
                              int n, int waves, PassParams pp, size_t lds, hipStream_t st) {
     if (nz > 1) {
-        if (precision == 0) return launch_sweep_t<double, 1, 16>(g, it, n, waves, pp, lds, st);
-        return launch_sweep_t<float, 1, 16>(g, it, n, waves, pp, lds, st);
+        if (precision == 0) {
+            switch (cpl) {
+                case 1: return launch_sweep3_t<double, 1>(g, it, n, waves, pp, lds, st);
+                case 2: return launch_sweep3_t<double, 2>(g, it, n, waves, pp, lds, st);
+                case 3: return launch_sweep3_t<double, 3>(g, it, n, waves, pp, lds, st);
+                default: return launch_sweep3_t<double, 4>(g, it, n, waves, pp, lds, st);
+            }
+        }
+        switch (cpl) {
+            case 1: return launch_sweep3_t<float, 1>(g, it, n, waves, pp, lds, st);
+            case 2: return launch_sweep3_t<float, 2>(g, it, n, waves, pp, lds, st);
+            case 3: return launch_sweep3_t<float, 3>(g, it, n, waves, pp, lds, st);
+            default: return launch_sweep3_t<float, 4>(g, it, n, waves, pp, lds, st);
+        }
     }
     if (precision == 0) {
         switch (cpl) {
-            case 1: return launch_sweep_t<double, 1, 1>(g, it, n, waves, pp, lds, st);
-            case 2: return launch_sweep_t<double, 2, 1>(g, it, n, waves, pp, lds, st);
-            case 3: return launch_sweep_t<double, 3, 1>(g, it, n, waves, pp, lds, st);
-            default: return launch_sweep_t<double, 4, 1>(g, it, n, waves, pp, lds, st);
+            case 1: return launch_sweep_t<double, 1>(g, it, n, waves, pp, lds, st);
+            case 2: return launch_sweep_t<double, 2>(g, it, n, waves, pp, lds, st);
+            case 3: return launch_sweep_t<double, 3>(g, it, n, waves, pp, lds, st);
+            default: return launch_sweep_t<double, 4>(g, it, n, waves, pp, lds, st);
         }
     }
     switch (cpl) {
-        case 1: return launch_sweep_t<float, 1, 1>(g, it, n, waves, pp, lds, st);
-        case 2: return launch_sweep_t<float, 2, 1>(g, it, n, waves, pp, lds, st);
-        case 3: return launch_sweep_t<float, 3, 1>(g, it, n, waves, pp, lds, st);
-        default: return launch_sweep_t<float, 4, 1>(g, it, n, waves, pp, lds, st);
+        case 1: return launch_sweep_t<float, 1>(g, it, n, waves, pp, lds, st);
+        case 2: return launch_sweep_t<float, 2>(g, it, n, waves, pp, lds, st);
+        case 3: return launch_sweep_t<float, 3>(g, it, n, waves, pp, lds, st);
+        default: return launch_sweep_t<float, 4>(g, it, n, waves, pp, lds, st);
     }
 }
 

@@ -15,6 +15,11 @@ __host__ __device__ inline int fc_class(uint16_t w, int f) { return (w >> (1 + 2
 
 enum { CTRL_DONE = 0, CTRL_PASS = 1, CTRL_CONVERGED = 2, CTRL_NONFINITE = 3, CTRL_N = 8 };
 
+// wrap-plane vectors per system kept in the workspace by the 3D pass kernel
+constexpr int KRY3_VECS = 11;
+// reduction rows per wave in the pass kernels' LDS: T_L, walls, J (per axis)
+__host__ __device__ constexpr int red_rows(int ndim) { return 1 + 2 * ndim; }
+
 // Per-geometry view used by every kernel: static tables (library-owned) plus
 // the per-solve workspace carve (caller-owned).
 struct GeomDev {
@@ -44,6 +49,7 @@ struct GeomDev {
     double* Tw;                  // 2 * nwalls: wall temperatures (double buffered)
     double* T_L;                 // ncells: latest lattice temperature
     void* U;                     // n_sys * nwrap (compute precision): wrap inflow vectors
+    void* kry;                   // 3D: n_sys * 11 * nwrap (compute precision): wrap-plane Krylov vectors
     double* part_TL;             // n_items * ncells
     double* part_Tw;             // n_items * nwalls
     double* part_J;              // n_items * ncells * ndim
@@ -90,6 +96,7 @@ struct PassParams {
     int lag_wrap;      // 1 = apply this pass's wrap correction in the next pass
     double inner_rtol; // per-pass wrap solve stops once the residual fell by this factor
     double wrap_tol;   // stop test: every relative wrap residual <= wrap_tol
+    int stop_rule;     // 0 = relative change, 1 = change * rho / (1 - rho)
 };
 
 // kernel launchers (kernels.hip)

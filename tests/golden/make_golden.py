@@ -4,6 +4,8 @@ Calls only the CPU oracle (oracle/) on the seeded inputs (inputs/gen.py) and
 stores kappa_cc, kappa_face, kappa_fourier, per-MFP kappa and T_L at seeded
 sample cells.  Run:  python tests/golden/make_golden.py cfg2 [--workers 8]
 
+``cfg5r`` is the 3D membrane at 16x16x4 cells with the full direction and MFP
+sets (the reduced replica of the 64x64x16 case).
 ``cfg3`` stores kappa_cc / kappa_face of the members of the 64-geometry batch
 whose grids are 48x48 or 64x64 (the oracle's cost grows quickly with the grid).
 """
@@ -24,13 +26,14 @@ from oracle.parallel import source_iteration_parallel  # noqa: E402
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["cfg2", "cfg3", "cfg4"])
+    ap.add_argument("config", choices=["cfg2", "cfg3", "cfg4", "cfg5r"])
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-11)
     a = ap.parse_args()
     if a.config == "cfg3":
         return batch(a)
-    w = gen.config2() if a.config == "cfg2" else gen.config4()
+    w = {"cfg2": gen.config2, "cfg4": gen.config4,
+         "cfg5r": lambda: gen.config5(nx=16, nz=4)}[a.config]()
     t0 = time.time()
     r = source_iteration_parallel(w, n_workers=a.workers, tol=a.tol, verbose=True)
     cells = np.nonzero(w.solid.ravel())[0]

@@ -34,6 +34,21 @@ def small3d():
     return gen.small_3d(7, 6, 4, solid=s, n_theta=4, n_phi=8, n_mfp=3)
 
 
+def wide3d():
+    # 70 x 5 x 3: rows span two wavefronts (two columns per lane) with a
+    # ragged tail, a pore through the thickness crossing the x boundary
+    s = np.ones((3, 5, 70), np.uint8)
+    s[:, 1:3, 66:70] = 0
+    s[:, 1:3, 0:3] = 0
+    return gen.small_3d(70, 5, 3, solid=s, n_theta=2, n_phi=4, n_mfp=3, L=280 * NM, t=30 * NM)
+
+
+def membrane3d():
+    # the 3D membrane geometry (through-pore, diffuse top/bottom) at 12x12x5
+    # with a reduced direction and MFP set
+    return gen.config5(nx=12, nz=5, n_theta=4, n_phi=8, n_mfp=4)
+
+
 CASES = {
     "cfg1": gen.config1,
     "ragged": ragged_porous,
@@ -44,10 +59,12 @@ CASES = {
     "sigma": lambda: gen.small_2d(10, 9, solid=gen.square_block_mask(10, 9, 3, 6), n_dir=8, n_mfp=3,
                                   sigma=np.random.default_rng(11).uniform(0.5, 2.0, 90)),
     "3d": small3d,
+    "3d_wide": wide3d,
+    "3d_membrane": membrane3d,
 }
 
 
-@pytest.mark.parametrize("name", ["cfg1", "ragged", "3d"])
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "3d", "3d_wide"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_upwind_apply(P, name, prec):
     w = CASES[name]()
@@ -72,7 +89,7 @@ def test_upwind_apply(P, name, prec):
             assert np.all(Y[k][w.solid.ravel() == 0] == 0)
 
 
-@pytest.mark.parametrize("name", ["cfg1", "ragged", "grad_y", "3d"])
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "grad_y", "3d", "3d_wide"])
 def test_fourier_first_guess(P, name):
     w = CASES[name]()
     prob = Problem(w)
@@ -82,7 +99,8 @@ def test_fourier_first_guess(P, name):
     assert rel(r["T_L"], oracle_full(prob, T - T.mean())) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["cfg1", "ragged", "channel", "sigma", "grad_y", "3d"])
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "channel", "sigma", "grad_y", "3d", "3d_wide",
+                                  "3d_membrane"])
 def test_lockstep_passes(P, name):
     """Same Fourier start, the same K passes: kappa, kappa_face and T_L agree."""
     w = CASES[name]()
@@ -103,7 +121,7 @@ def test_lockstep_passes(P, name):
     assert rel(r["J"], Jref) < 1e-9
 
 
-@pytest.mark.parametrize("name", ["cfg1", "bulk", "channel"])
+@pytest.mark.parametrize("name", ["cfg1", "bulk", "channel", "3d", "3d_membrane"])
 def test_converged(P, name):
     w = CASES[name]()
     prob = Problem(w)

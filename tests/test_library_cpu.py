@@ -28,7 +28,7 @@ def test_exports_every_header_symbol(L):
 def test_default_opts(L):
     o = L.default_opts()
     assert o.precision == L.OBTE_FP64 and o.max_outer > 0 and o.inner_tol > 0
-    assert o.keep_state == 0
+    assert o.keep_state == 0 and o.stop_rule == 0 and o.timing == 0
 
 
 def _desc_ok(**kw):
@@ -42,7 +42,7 @@ def _desc_ok(**kw):
     dict(ndim=4), dict(n=(1, 6, 1)), dict(L=(0.0, 1e-7, 1.0)), dict(periodic=(0, 1, 0)),
     dict(grad_axis=2), dict(solid=np.zeros(48, np.uint8)), dict(solid=np.full(48, 2, np.uint8)),
     dict(n=(300, 2, 1), solid=np.ones(600, np.uint8)), dict(dT_ext=0.0),
-    dict(ndim=3, n=(4, 4, 20), solid=np.ones(320, np.uint8)),
+    dict(ndim=3, n=(4, 4, 130), solid=np.ones(2080, np.uint8)),
     dict(ndim=3, n=(4, 4, 2), periodic=(1, 1, 1), solid=np.ones(32, np.uint8)),
 ])
 def test_mesh_create_rejects(L, bad):
@@ -101,4 +101,22 @@ def test_solve_state_errors_on_host(L):
     assert rc == L.OBTE_ERR_ARG
     k = C.c_double()
     assert lib.obte_kappa(h, C.byref(k), None) == L.OBTE_ERR_STATE
+    L.obte_mesh_destroy(h)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("precision", 2), ("outer_tol", -1.0), ("max_outer", 0), ("max_outer", 65536),
+    ("inner_tol", 0.0), ("max_inner", -1), ("waves_per_group", 9), ("passes_per_graph", -1),
+    ("fourier_tol", 0.0), ("init", 2), ("recycle", 33), ("lag_wrap", 2), ("wrap_tol", -1.0),
+    ("inner_rtol", 1.0), ("stop_rule", 2)])
+def test_options_rejected_on_host(L, field, value):
+    w = gen.small_2d(8, 6)
+    h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
+    # options are checked before anything else (no material, no device needed)
+    with pytest.raises(L.ObteError) as e:
+        L.obte_workspace_size(h, L.default_opts())
+    assert e.value.status == L.OBTE_ERR_STATE
+    with pytest.raises(L.ObteError) as e:
+        L.obte_workspace_size(h, L.default_opts(**{field: value}))
+    assert e.value.status == L.OBTE_ERR_ARG
     L.obte_mesh_destroy(h)
