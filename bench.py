@@ -4,13 +4,16 @@ relative kappa error, on the 128x128 porous-cell workload.
 
 A step is one converged kappa_eff computation through the C ABI: the Fourier
 first guess, then source-iteration passes (batched (m,l) solves + reductions)
-until the relative kappa change meets the tolerance that gives <= 1e-4 error.
-Inputs (mesh tables, material weights, sigma) are resident on the device
-before the timed region starts.
+until the estimated kappa error meets the target.  Inputs (mesh tables,
+material weights, sigma) are resident on the device before the timed region
+starts.  The same JSON line also carries the 3D membrane (64x64x16, 288
+directions x 30 MFPs) and the 64-geometry batch, each at the same error
+target (skip them with --no-extras).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,8 +27,25 @@ METRIC = ("converged κ_eff solves/s and cell·dir·MFP DoF/s, FP32 vs FP64, "
           "at 1e-4 rel err")
 PEAK = {"fp64_vector_tflops": 78.6, "fp32_vector_tflops": 157.3, "hbm_gbs": 8000.0}
 # algorithmic flops of one upwind sweep per solid cell: the triangular update
-# x = (b + c_x x_up,x + c_y x_up,y) / d  (2 FMA + 1 divide, counted as 5)
-FLOPS_PER_CELL_SWEEP = {2: 5, 3: 7}
+# x = (b + c_x x_up,x + c_y x_up,y [+ c_z x_up,z]) / d  (2 or 3 FMA + 1 divide
+# counted as 3)
+FLOPS_PER_CELL_SWEEP = {2: 5, 3: 6}
+# Operating points: the error-estimate stop rule at half the 1e-4 target, a
+# forcing term of 0.3 on the per-pass wrap solve, the wrap correction lagged
+# into the next pass (the GPU tests check each point against the oracle).
+OP = {
+    "fp32": dict(precision=1, outer_tol=5e-5, stop_rule=1, inner_tol=1e-5, inner_rtol=0.3,
+                 lag_wrap=1, fourier_tol=1e-6, passes_per_graph=4, max_outer=5000),
+    "fp64": dict(precision=0, outer_tol=5e-5, stop_rule=1, inner_tol=1e-8, inner_rtol=0.3,
+                 lag_wrap=1, fourier_tol=1e-6, passes_per_graph=4, max_outer=5000),
+}
+REF = dict(precision=0, outer_tol=1e-9, stop_rule=1, inner_tol=1e-12, fourier_tol=1e-11,
+           passes_per_graph=8, max_outer=20000)
+# HBM traffic of the FP32 pass kernel on the 128x128 workload at the fp32
+# operating point, per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over one
+# solve, each scaled by the same counter on a plain 256 MiB copy); valid only
+# for the kernel source it was taken on.
+TRAFFIC = {"kernels_sha256": None, "fetch_bytes": None, "write_bytes": None}
 
 
 def parse():
@@ -34,12 +54,21 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-extras", action="store_true", help="skip the 3D and batch workloads")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
-    p.add_argument("--workload", default="cfg2")
+    p.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg4", "cfg5"])
+    p.add_argument("--profile", action="store_true",
+                   help="only run --steps FP32 solves of --workload at the operating point with "
+                        "direct launches (for rocprofv3 counter runs) and exit")
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only run a plain device copy of this many bytes (scales rocprofv3 "
                         "FETCH_SIZE / WRITE_SIZE) and exit")
     return p.parse_args()
+
+
+def kernels_sha():
+    with open(os.path.join(ROOT, "paper_2106_02764_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def copy_probe(nbytes):
@@ -54,98 +83,125 @@ def copy_probe(nbytes):
 
 def make_workload(name):
     from inputs import gen
+    return {"cfg1": gen.config1, "cfg2": gen.config2, "cfg4": gen.config4, "cfg5": gen.config5}[name]()
+
+
+def describe(name, w):
     if name == "cfg2":
-        return gen.config2()
-    if name == "cfg1":
-        return gen.config1()
-    if name == "cfg4":
-        return gen.config4()
+        return ("128x128 periodic cell, centred circular pore r=%.3f nm (seeded), L=100 nm, "
+                "48 directions x 30 MFPs (1 nm..100 um), lognormal kernel, 1e-4 rel kappa error"
+                % (w.meta["pore_radius"] * 1e9))
     if name == "cfg5":
-        return gen.config5()
-    raise SystemExit(f"unknown workload {name}")
+        return ("3D membrane 64x64x16, L=200 nm, t=50 nm, cylindrical through-pore r=0.3 L, "
+                "diffuse top/bottom, 288 directions x 30 MFPs, 1e-4 rel kappa error")
+    return name
 
 
-def batch_bench(a):
-    """64 geometries of uneven size in one launch per pass: geometry solves/s."""
-    import torch
-    import paper_2106_02764_amd as P
-    from inputs import gen
-    geoms = gen.config3()
-    solvers = [P.Solver.from_workload(w) for w in geoms]
-    dof = sum(w.dof for w in geoms)
-    ref, _ = P.solve_batch(solvers, P.default_opts(outer_tol=1e-10, inner_tol=1e-12,
-                                                   fourier_tol=1e-10, max_outer=4000))
-    out = {}
-    for name, prec, itol in (("fp32", 1, 1e-5), ("fp64", 0, 1e-8)):
-        o = P.default_opts(precision=prec, outer_tol=3e-6, inner_tol=itol, inner_rtol=0.3,
-                           lag_wrap=1, fourier_tol=1e-6, max_outer=4000, passes_per_graph=4)
-        o.waves_per_group = P.autotune.tune(solvers, o)
-        for _ in range(a.warmup):
-            P.solve_batch(solvers, o)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(a.steps):
-            k, st = P.solve_batch(solvers, o)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / a.steps
-        err = max(abs(x - y) / y for x, y in zip(k, ref))
-        out[name] = {"geometry_solves_per_s": len(geoms) / dt, "ms_per_batch": 1e3 * dt,
-                     "dof_per_s": dof / dt, "max_kappa_rel_err_vs_fp64_ref": err,
-                     "waves_per_group": o.waves_per_group,
-                     "max_passes": max(x["outer_iters"] for x in st)}
-    print(json.dumps({"workload": "64 periodic geometries (48^2..256^2, 1-4 circular pores, "
-                      "L 50-500 nm), 48 directions x 30 MFPs, one launch per pass",
-                      "dof": dof, **out}), flush=True)
-
-
-def time_solves(P, solver, opts, steps, warmup):
+def run_solves(solver, opts, steps, warmup):
+    """Timed solves; returns wall time and the summed solver statistics."""
     import torch
     for _ in range(warmup):
         solver.solve(opts, want_T_L=False)
     torch.cuda.synchronize()
+    acc = {"sweep_ms": 0.0, "reduce_ms": 0.0, "fourier_ms": 0.0, "sweep_launches": 0,
+           "outer_iters": 0, "sweeps": 0, "inner_iters": 0}
     t0 = time.perf_counter()
-    sweep_ms = red_ms = four_ms = 0.0
-    launches = passes = sweeps = inner = 0
-    k = None
     for _ in range(steps):
         out = solver.solve(opts, want_T_L=False)
-        sweep_ms += out["sweep_ms"]
-        red_ms += out["reduce_ms"]
-        four_ms += out["fourier_ms"]
-        launches += out["sweep_launches"]
-        passes += out["outer_iters"]
-        sweeps += out["sweeps"]
-        inner += out["inner_iters"]
-        k = out["kappa"]
+        for k in acc:
+            acc[k] += out[k]
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return {"seconds": dt, "kappa": k, "sweep_ms": sweep_ms, "reduce_ms": red_ms,
-            "fourier_ms": four_ms, "launches": launches, "passes": passes, "sweeps": sweeps,
-            "inner_iters": inner, "status": out["status"]}
+    acc["seconds"] = time.perf_counter() - t0
+    acc["kappa"] = out["kappa"]
+    acc["status"] = out["status"]
+    return acc
 
 
-def calibrate(P, solver, prec, kref, inner_tol):
-    """Fastest configuration (inner-iteration cap per pass, loosest outer
-    tolerance) whose kappa is within 1e-4 of the reference; Algorithm 1 stops
-    on the relative change, which understates the error.  Untimed."""
+def leg(P, solver, w, name, steps, warmup, kref, kor):
+    """Throughput leg (pass kernels replayed as HIP graphs), then the same
+    solves with HIP events around every launch on the library's stream
+    (direct launches) for the per-kernel durations."""
+    o = solver.opts(**OP[name])
+    r = run_solves(solver, o, steps, warmup)
+    ot = solver.opts(**OP[name], timing=1)
+    rt = run_solves(solver, ot, steps, 0)
+    out = {"solves_per_s": steps / r["seconds"], "ms_per_solve": 1e3 * r["seconds"] / steps,
+           "dof_per_s": w.dof * steps / r["seconds"], "kappa": r["kappa"], "status": r["status"],
+           "passes_per_solve": r["outer_iters"] / steps, "sweeps_per_system_pass":
+           r["sweeps"] / max(r["outer_iters"] * w.n_systems, 1),
+           "kappa_rel_err_vs_fp64_ref": abs(r["kappa"] - kref) / abs(kref),
+           "opts": OP[name],
+           "timed_leg": {"solves_per_s": steps / rt["seconds"], "sweep_ms": rt["sweep_ms"],
+                         "reduce_ms": rt["reduce_ms"], "fourier_ms": rt["fourier_ms"],
+                         "sweep_launches": rt["sweep_launches"], "sweeps": rt["sweeps"]}}
+    if kor is not None:
+        out["kappa_rel_err_vs_oracle"] = abs(r["kappa"] - kor) / kor
+    return out
+
+
+def roofline(w, tl, kernel, fp32=True):
+    """The pass kernel: algorithmic flops per launch = sweeps in that launch
+    x solid cells x flops per cell-sweep, over its average launch duration."""
+    sweeps_per_launch = tl["sweeps"] / max(tl["sweep_launches"], 1)
+    flops = sweeps_per_launch * w.n_solid * FLOPS_PER_CELL_SWEEP[w.ndim]
+    avg_ms = tl["sweep_ms"] / max(tl["sweep_launches"], 1)
+    achieved = flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    peak = PEAK["fp32_vector_tflops"] if fp32 else PEAK["fp64_vector_tflops"]
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "kernel": kernel, "avg_launch_ms": avg_ms,
+            "sweeps_per_launch": sweeps_per_launch}
+
+
+def single(P, name, steps, warmup):
+    w = make_workload(name)
+    solver = P.Solver.from_workload(w)
+    ref = solver.solve(solver.opts(**REF), want_T_L=False)        # untimed
+    kref = ref["kappa"]
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")
+    if os.path.exists(gpath):
+        golden = json.load(open(gpath))
+    kor = golden["kappa_cc"] if golden else None
+    res = {n: leg(P, solver, w, n, steps, warmup, kref, kor) for n in ("fp32", "fp64")}
+    return w, kref, kor, res
+
+
+def batch(P, steps, warmup):
+    """64 geometries of uneven size in one launch per pass: geometry solves/s."""
     import torch
-    best = None
-    for lag, rtol in ((1, 0.3), (1, 0.1), (0, 0.1), (0, 0.0)):
-        for tol in (3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7):
-            o = solver.opts(precision=prec, outer_tol=tol, inner_tol=inner_tol, fourier_tol=1e-6,
-                            passes_per_graph=4, inner_rtol=rtol, lag_wrap=lag)
-            solver.solve(o, want_T_L=False)           # warm
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out = solver.solve(o, want_T_L=False)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            err = abs(out["kappa"] - kref) / abs(kref)
-            if err <= 0.5e-4 and out["status"] == 0:
-                if best is None or dt < best[2]:
-                    best = (o, err, dt)
-                break
-    return best[0], best[1]
+    from inputs import gen
+    geoms = gen.config3()
+    solvers = [P.Solver.from_workload(w) for w in geoms]
+    dof = sum(w.dof for w in geoms)
+    ref, _ = P.solve_batch(solvers, P.default_opts(**REF))
+    out = {"workload": "64 periodic 2D geometries (48^2..256^2, 1-4 circular pores, L 50-500 nm), "
+                       "48 directions x 30 MFPs, all in one launch per pass",
+           "dof": dof, "solid_cells": sum(w.n_solid for w in geoms)}
+    for name in ("fp32", "fp64"):
+        o = P.default_opts(**OP[name])
+        o.waves_per_group = P.autotune.tune(solvers, o)
+        for _ in range(warmup):
+            P.solve_batch(solvers, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            k, st = P.solve_batch(solvers, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ot = P.default_opts(**OP[name], timing=1)
+        ot.waves_per_group = o.waves_per_group
+        _, stt = P.solve_batch(solvers, ot)
+        out[name] = {"geometry_solves_per_s": len(geoms) / dt, "ms_per_batch": 1e3 * dt,
+                     "dof_per_s": dof / dt,
+                     "max_kappa_rel_err_vs_fp64_ref": max(abs(x - y) / y for x, y in zip(k, ref)),
+                     "waves_per_group": o.waves_per_group,
+                     "max_passes": max(x["outer_iters"] for x in st),
+                     "mean_passes": sum(x["outer_iters"] for x in st) / len(st),
+                     "status_ok": sum(1 for x in st if x["status"] == 0),
+                     "timed_leg": {"sweep_ms": stt[0]["sweep_ms"], "reduce_ms": stt[0]["reduce_ms"],
+                                   "fourier_ms": stt[0]["fourier_ms"],
+                                   "sweep_launches": stt[0]["sweep_launches"]}}
+    return out
 
 
 def cpu_baseline_measure(w, seconds):
@@ -167,7 +223,8 @@ def cpu_baseline_value(m, passes, dof):
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": m["cores"], "kind": "oracle",
             "sample": (f"full workload, all systems factored ({m['t_factor']:.1f}s) + "
                        f"{m['passes_run']} passes ({m['pass_s']:.3f}s each) on {m['cores']} worker "
-                       f"processes; extrapolated to the {passes} passes of the FP64 GPU solve"),
+                       f"processes; extrapolated to the {passes} passes the FP64 form needs for "
+                       f"the same error target"),
             "dof_per_s": dof / per_solve, "seconds_per_solve_estimate": per_solve}
 
 
@@ -176,84 +233,52 @@ def main():
     if a.copy_probe:
         copy_probe(a.copy_probe)
         return
-    if a.workload == "cfg3":
-        batch_bench(a)
-        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is design-only)"}))
         sys.exit(2)
-    w = make_workload(a.workload)
-    cpu = None if a.no_cpu else cpu_baseline_measure(w, a.cpu_seconds)
-    import torch
+    if a.profile:
+        import paper_2106_02764_amd as P
+        w = make_workload(a.workload)
+        s = P.Solver.from_workload(w)
+        r = run_solves(s, s.opts(**OP["fp32"], timing=1), a.steps, 0)
+        print(json.dumps({"profile": a.workload, "kernels_sha256": kernels_sha(), **r}), flush=True)
+        return
+    w0 = make_workload(a.workload)
+    cpu = None if a.no_cpu else cpu_baseline_measure(w0, a.cpu_seconds)
     import paper_2106_02764_amd as P
 
-    solver = P.Solver.from_workload(w)
-    dof = w.dof
-    # reference: FP64 GPU form converged far below the target error (untimed)
-    oref = solver.opts(outer_tol=1e-11, inner_tol=1e-12, fourier_tol=1e-12)
-    ref = solver.solve(oref, want_T_L=False)
-    kref = ref["kappa"]
-    golden = None
-    gpath = os.path.join(ROOT, "tests", "golden", f"{a.workload}_oracle.json")
-    if os.path.exists(gpath):
-        golden = json.load(open(gpath))
-    res = {}
-    for name, prec, itol in (("fp32", 1, 1e-5), ("fp64", 0, 1e-8)):
-        o, cal_err = calibrate(P, solver, prec, kref, itol)
-        # leg 1: the throughput (pass kernels replayed as HIP graphs)
-        r = time_solves(P, solver, o, a.steps, a.warmup)
-        # leg 2: the same solves with HIP events around every kernel launch on
-        # the library's stream (direct launches), for the per-kernel durations
-        ot = solver.opts(**{f: getattr(o, f) for f, _ in o._fields_})
-        ot.timing = 1
-        rt = time_solves(P, solver, ot, a.steps, 0)
-        for key in ("sweep_ms", "reduce_ms", "fourier_ms", "launches"):
-            r[key] = rt[key]
-        r["timed_leg_solves_per_s"] = a.steps / rt["seconds"]
-        r["sweeps_timed_leg"] = rt["sweeps"]
-        r["outer_tol"] = o.outer_tol
-        r["inner_tol"] = o.inner_tol
-        r["max_inner"] = o.max_inner
-        r["inner_rtol"] = o.inner_rtol
-        r["lag_wrap"] = o.lag_wrap
-        r["kappa_rel_err_vs_fp64_ref"] = abs(r["kappa"] - kref) / abs(kref)
-        if golden:
-            r["kappa_rel_err_vs_oracle"] = abs(r["kappa"] - golden["kappa_cc"]) / golden["kappa_cc"]
-        r["solves_per_s"] = a.steps / r["seconds"]
-        r["dof_per_s"] = dof * a.steps / r["seconds"]
-        r["ms_per_solve"] = 1e3 * r["seconds"] / a.steps
-        res[name] = r
+    w, kref, kor, res = single(P, a.workload, a.steps, a.warmup)
     main_r = res["fp32"]
-    # roofline of the dominant kernel (the sweep pass): algorithmic flops per
-    # launch = sweeps in that launch x solid cells x flops per cell-sweep
-    sweeps_per_launch = main_r["sweeps_timed_leg"] / max(main_r["launches"], 1)
-    flops_launch = sweeps_per_launch * w.n_solid * FLOPS_PER_CELL_SWEEP[w.ndim]
-    avg_ms = main_r["sweep_ms"] / max(main_r["launches"], 1)
-    achieved = flops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK["fp32_vector_tflops"],
-            "unit": "TFLOP/s", "frac": achieved / PEAK["fp32_vector_tflops"], "traffic": None,
-            "kernel": "k_sweep_pass<float,2,1>", "avg_launch_ms": avg_ms,
-            "sweeps_per_launch": sweeps_per_launch}
+    roof = roofline(w, main_r["timed_leg"], "k_sweep_pass<float>")
+    sha = kernels_sha()
+    if TRAFFIC["kernels_sha256"] == sha and a.workload == "cfg2":
+        roof["traffic"] = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+        roof["traffic_fetch_bytes"] = TRAFFIC["fetch_bytes"]
+        roof["traffic_write_bytes"] = TRAFFIC["write_bytes"]
     line = {
         "metric": METRIC, "value": main_r["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": main_r["ms_per_solve"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": ("128x128 periodic cell, centred circular pore r=%.3f nm (seeded), "
-                                "L=100 nm, 48 directions x 30 MFPs (1 nm..100 um), lognormal "
-                                "kernel, 1e-4 rel kappa error" % (w.meta["pore_radius"] * 1e9)
-                                if a.workload == "cfg2" else a.workload),
-                   "solid_cells": w.n_solid, "systems": w.n_systems, "dof": dof},
+        "config": {"workload": describe(a.workload, w), "solid_cells": w.n_solid,
+                   "systems": w.n_systems, "dof": w.dof},
         "dof_per_s": main_r["dof_per_s"],
-        "kappa": main_r["kappa"], "kappa_ref_fp64": kref,
+        "kappa": main_r["kappa"], "kappa_ref_fp64": kref, "kappa_oracle": kor,
         "fp32": res["fp32"], "fp64": res["fp64"],
         "roofline": roof,
+        "kernels_sha256": sha,
     }
-    if golden:
-        line["kappa_oracle"] = golden["kappa_cc"]
     if cpu is not None:
-        line["cpu_baseline"] = cpu_baseline_value(cpu, int(round(res["fp64"]["passes"] / a.steps)), dof)
+        line["cpu_baseline"] = cpu_baseline_value(cpu, int(round(res["fp64"]["passes_per_solve"])), w.dof)
+    if not a.no_extras:
+        steps_x, warm_x = max(1, min(a.steps, 2)), 1
+        w5, kref5, kor5, res5 = single(P, "cfg5", steps_x, warm_x)
+        line["extra_3d_membrane"] = {"workload": describe("cfg5", w5), "dof": w5.dof,
+                                     "kappa_ref_fp64": kref5, **res5,
+                                     "roofline": roofline(w5, res5["fp32"]["timed_leg"],
+                                                          "k_sweep_pass3<float>")}
+        line["extra_batch_64"] = batch(P, steps_x, warm_x)
     print(json.dumps(line), flush=True)
 
 

@@ -91,7 +91,7 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * caps the iterations per pass (either carries the rest of the wrap solve
  * into later passes).
  * The stop test also requires every relative wrap residual <= wrap_tol
- * (0 = max(inner_tol, 10 outer_tol)).  lag_wrap = 1 applies a pass's wrap
+ * (0 = max(inner_tol, 0.2 outer_tol)).  lag_wrap = 1 applies a pass's wrap
  * correction in the next pass instead of a correction sweep (the wrap
  * inflow is then lagged like T_L; the fixed point is unchanged).  init: 0 = Fourier first guess, 1 = resume
  * from the state left in the workspace by the previous call.
@@ -112,8 +112,9 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * kernels are then launched directly instead of through a HIP graph).
  * stop_rule: 0 = the relative change test above (Algorithm 1); 1 = the
  * estimated remaining error |kappa_n - kappa_{n-1}| rho/(1 - rho) <=
- * outer_tol |kappa_n|, with the contraction rho taken as the larger of the
- * last two ratios of successive changes (clamped to [0, 0.995]); a slowly
+ * outer_tol |kappa_n| (from the 12th pass on), with the contraction rho the
+ * largest of the last two ratios of successive changes and the mean ratio
+ * over the last ten passes (clamped to [0, 0.995]); a slowly
  * contracting geometry then runs longer and a fast one stops earlier, so
  * outer_tol bounds the error of kappa rather than its last change. */
 typedef struct {

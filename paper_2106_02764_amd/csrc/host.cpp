@@ -436,7 +436,7 @@ PassParams base_params(const obte_solve_opts* o) {
     pp.outer_tol = o->outer_tol;
     pp.lag_wrap = o->lag_wrap;
     pp.inner_rtol = o->inner_rtol;
-    pp.wrap_tol = o->wrap_tol > 0.0 ? o->wrap_tol : std::max(o->inner_tol, 10.0 * o->outer_tol);
+    pp.wrap_tol = o->wrap_tol > 0.0 ? o->wrap_tol : std::max(o->inner_tol, 0.2 * o->outer_tol);
     pp.stop_rule = o->stop_rule;
     return pp;
 }

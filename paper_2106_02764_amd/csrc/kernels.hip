@@ -1110,14 +1110,18 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
         const bool wrap_ok = wr <= pp.wrap_tol;
         bool small = n >= 2 && fabs(k - g.hist[pass - 1]) <= pp.outer_tol * fabs(k);
         if (pp.stop_rule == 1) {
-            // error estimate of a linear fixed-point iteration from the
-            // observed contraction of the last three changes
+            // error estimate of a linear fixed-point iteration: the
+            // contraction is the largest of the last two ratios of
+            // successive changes and of the mean ratio over ten passes (the
+            // window sees through a transient or noisy pair)
             small = false;
-            if (n >= 4) {
+            if (n >= 12) {
                 const double d0 = fabs(k - g.hist[pass - 1]);
                 const double d1 = fabs(g.hist[pass - 1] - g.hist[pass - 2]);
                 const double d2 = fabs(g.hist[pass - 2] - g.hist[pass - 3]);
+                const double d10 = fabs(g.hist[pass - 10] - g.hist[pass - 11]);
                 double rho = fmax(d1 > 0.0 ? d0 / d1 : 0.0, d2 > 0.0 ? d1 / d2 : 0.0);
+                if (d10 > 0.0) rho = fmax(rho, pow(d0 / d10, 0.1));
                 rho = fmin(rho, 0.995);
                 small = d0 * rho / (1.0 - rho) <= pp.outer_tol * fabs(k);
             }

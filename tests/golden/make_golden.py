@@ -4,6 +4,7 @@ Calls only the CPU oracle (oracle/) on the seeded inputs (inputs/gen.py) and
 stores kappa_cc, kappa_face, kappa_fourier, per-MFP kappa and T_L at seeded
 sample cells.  Run:  python tests/golden/make_golden.py cfg2 [--workers 8]
 
+``cfg5r_adjoint`` stores d kappa / d sigma of that replica at sigma = 1.
 ``cfg5r`` is the 3D membrane at 16x16x4 cells with the full direction and MFP
 sets (the reduced replica of the 64x64x16 case).
 ``cfg3`` stores kappa_cc / kappa_face of the members of the 64-geometry batch
@@ -26,12 +27,14 @@ from oracle.parallel import source_iteration_parallel  # noqa: E402
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["cfg2", "cfg3", "cfg4", "cfg5r"])
+    ap.add_argument("config", choices=["cfg2", "cfg3", "cfg4", "cfg5r", "cfg5r_adjoint"])
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-11)
     a = ap.parse_args()
     if a.config == "cfg3":
         return batch(a)
+    if a.config == "cfg5r_adjoint":
+        return adjoint_replica(a)
     w = {"cfg2": gen.config2, "cfg4": gen.config4,
          "cfg5r": lambda: gen.config5(nx=16, nz=4)}[a.config]()
     t0 = time.time()
@@ -53,6 +56,28 @@ def main():
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path, out["kappa_cc"], out["passes"])
+
+
+def adjoint_replica(a):
+    """d kappa / d sigma of the 16x16x4 membrane replica at sigma = 1 (serial
+    oracle: forward source iteration, then the transposed one)."""
+    from oracle.adjoint import adjoint_source_iteration
+    from oracle.bte import Problem, source_iteration
+    w = gen.config5(nx=16, nz=4)
+    t0 = time.time()
+    prob = Problem(w)
+    r = source_iteration(prob, tol=a.tol)
+    ad = adjoint_source_iteration(prob, r["T"], tol=a.tol)
+    g = np.zeros(w.n_cells)
+    g[prob.mesh.cells] = ad["grad"]
+    out = {"config": "cfg5r_adjoint", "tol": a.tol, "passes_forward": r["passes"],
+           "passes_adjoint": ad["passes"], "kappa_cc": r["kappa_cc"], "kappa_adj": ad["kappa_adj"],
+           "grad": list(map(float, g)), "seconds": time.time() - t0,
+           "source": "oracle.bte.source_iteration + oracle.adjoint.adjoint_source_iteration (FP64)"}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg5r_adjoint_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path, r["kappa_cc"], ad["kappa_adj"])
 
 
 def batch(a):

@@ -72,3 +72,13 @@ def test_batch_fp32_vs_fp64(P, solvers, k64):
         assert all(s["status"] == 0 for s in st)
         rel = np.abs(np.asarray(k32) - k) / k
         assert rel.max() <= 1e-4, (lag, rtol, rel.max(), int(rel.argmax()))
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+def test_bench_operating_points_batch(P, solvers, form):
+    import bench
+    g = json.load(open(GOLD))
+    k, st = P.solve_batch(solvers, P.default_opts(**bench.OP[form]))
+    assert all(s["status"] == 0 for s in st)
+    for m in g["members"]:
+        assert abs(k[m["index"]] - m["kappa_cc"]) <= 1e-4 * m["kappa_cc"], m["index"]

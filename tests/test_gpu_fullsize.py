@@ -105,3 +105,16 @@ def test_cfg4_adjoint_vs_finite_differences(P):
     kp = s.solve(o2, sigma=w.sigma * (1 + t), want_T_L=False)["kappa"]
     km = s.solve(o2, sigma=w.sigma * (1 - t), want_T_L=False)["kappa"]
     assert abs((kp - km) / (2 * t) - float(np.dot(w.sigma, grad))) <= 1e-6 * abs(base["kappa"])
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg4"])
+@pytest.mark.parametrize("form", ["fp32", "fp64"])
+def test_bench_operating_points_vs_oracle(P, name, form):
+    """The operating points bench.py times (error-estimate stop rule at half
+    the target) meet the 1e-4 target against the oracle."""
+    import bench
+    w = gen.config2() if name == "cfg2" else gen.config4()
+    g = golden(name)
+    out = solve(P, w, **bench.OP[form])
+    assert out["status"] == 0
+    assert abs(out["kappa"] - g["kappa_cc"]) <= 1e-4 * g["kappa_cc"]
