@@ -116,7 +116,17 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * largest of the last two ratios of successive changes and the mean ratio
  * over the last ten passes (clamped to [0, 0.995]); a slowly
  * contracting geometry then runs longer and a fast one stops earlier, so
- * outer_tol bounds the error of kappa rather than its last change. */
+ * outer_tol bounds the error of kappa rather than its last change.
+ * accel: 0 = the plain source iteration of Algorithm 1 (each pass's T_L and
+ * T_w are the next pass's inputs); 1..8 = Anderson mixing of depth accel on
+ * the pair (T_L, T_w) (the adjoint: on (sum lambda, Phi)): the next inputs are
+ * the combination of the last accel+1 iterates that minimises the linearised
+ * residual.  Same fixed point, far fewer passes when the iteration contracts
+ * slowly.  With accel > 0 the stop test also requires the estimated
+ * relative error of the iterate, |G(x) - x| / (s |x|), <= outer_tol, where s
+ * (>= 1e-3) estimates the smallest singular value of I - G' by the smallest
+ * |dF_j| / |dX_j| over the mixing history.  An adjoint's accel may not exceed the depth of the forward solve
+ * that sized the workspace. */
 typedef struct {
     int precision;
     double outer_tol;
@@ -136,6 +146,7 @@ typedef struct {
     double wrap_tol;
     int timing;
     int stop_rule;
+    int accel;
 } obte_solve_opts;
 
 typedef struct {

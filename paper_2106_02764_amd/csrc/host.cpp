@@ -90,7 +90,7 @@ namespace {
 struct Layout {
     size_t sigma, sigma_f, sT, Tw, T_L, U, part_TL, part_Tw, part_J, ksys, kfsys, iters, sweeps,
         hist, hist_face, ctrl, fx, fscal, Tstore, lam_psi, lam_phi, grad, part_G, bnd, mem, mem_count,
-        mem_bytes, wres, wres_hist, kry, total;
+        mem_bytes, wres, wres_hist, kry, ax, actl, ag, axp, afp, adX, adF, agram, apart, total;
 };
 
 int auto_waves(const obte_mesh* m) {
@@ -126,7 +126,7 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.iters = take((size_t)m->n_sys * 8);
     L.sweeps = take((size_t)m->n_sys * 8);
     L.ctrl = take(CTRL_N * 4);
-    L.fx = take(4 * nc * 8);
+    L.fx = take(fourier_scratch_doubles(nc) * 8);
     L.fscal = take(4 * 8);
     L.lam_psi = take(2 * nc * 8);
     L.lam_phi = take(2 * nw * 8);
@@ -135,22 +135,38 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.bnd = take(4 * (size_t)m->nf * nc * 8);
     L.mem_count = take(2 * (size_t)m->n_sys * 4);
     L.wres = take((size_t)m->n_sys * 8);
-    // the parts below depend on precision / recycle / keep_state
+    L.hist = take((size_t)HIST_CAP * 8);
+    L.hist_face = take((size_t)HIST_CAP * 8);
+    L.wres_hist = take((size_t)HIST_CAP * 8);
+    const size_t naa = nc + (size_t)m->nwalls;
+    L.ax = take(naa * 8);
+    L.actl = take(8 * 4);
+    // the parts below depend on precision / recycle / keep_state / accel, so
+    // the state a resumed solve reads (above, and U) keeps its place
     L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
     L.kry = m->nz > 1 ? take((size_t)m->n_sys * KRY3_VECS * nwrap * tsz) : 0;
     L.mem_bytes = 2 * (size_t)m->n_sys * 2 * (size_t)std::max(o->recycle, 0) * nwrap * tsz;
     L.mem = take(L.mem_bytes);
     L.Tstore = o->keep_state ? take((size_t)m->n_sys * nc * 8) : 0;
-    L.hist = take((size_t)HIST_CAP * 8);
-    L.hist_face = take((size_t)HIST_CAP * 8);
-    L.wres_hist = take((size_t)HIST_CAP * 8);
+    // last: the mixing history (an adjoint may use another depth than the
+    // forward solve whose stored state it reads)
+    const size_t M = (size_t)std::max(o->accel, 0);
+    L.ag = M ? take(naa * 8) : 0;
+    L.axp = M ? take(naa * 8) : 0;
+    L.afp = M ? take(naa * 8) : 0;
+    L.adX = M ? take(M * naa * 8) : 0;
+    L.adF = M ? take(M * naa * 8) : 0;
+    L.agram = M ? take((M * M + M) * 8) : 0;
+    L.apart = M ? take(aa_partial_doubles() * 8) : 0;
     L.total = off;
     return L;
 }
 
-GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int recycle) {
+GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int recycle, int accel) {
     GeomDev g{};
     g.mem_R = recycle;
+    g.n_aa = m->ncells + m->nwalls;
+    g.aa_m = accel;
     g.nx = m->nx; g.ny = m->ny; g.nz = m->nz; g.ndim = m->ndim; g.nf = m->nf;
     g.ncells = m->ncells; g.nwalls = m->nwalls; g.nwrap = m->nx * m->nz;
     for (int a = 0; a < 3; ++a) { g.periodic[a] = m->periodic[a]; g.h[a] = m->h[a]; g.L[a] = m->L[a]; }
@@ -193,6 +209,17 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.mem_count = (int*)(ws + L.mem_count);
         g.wres = (double*)(ws + L.wres);
         g.wres_hist = (double*)(ws + L.wres_hist);
+        g.ax = (double*)(ws + L.ax);
+        g.actl = (int*)(ws + L.actl);
+        if (accel > 0) {
+            g.ag = (double*)(ws + L.ag);
+            g.axp = (double*)(ws + L.axp);
+            g.afp = (double*)(ws + L.afp);
+            g.adX = (double*)(ws + L.adX);
+            g.adF = (double*)(ws + L.adF);
+            g.agram = (double*)(ws + L.agram);
+            g.apart = (double*)(ws + L.apart);
+        }
     }
     return g;
 }
@@ -235,6 +262,7 @@ obte_status check_opts(const obte_solve_opts* o) {
     if (!(o->wrap_tol >= 0.0)) return fail(OBTE_ERR_ARG, "wrap_tol must be >= 0");
     if (!(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0)) return fail(OBTE_ERR_ARG, "inner_rtol must be in [0, 1)");
     if (o->stop_rule != 0 && o->stop_rule != 1) return fail(OBTE_ERR_ARG, "stop_rule must be 0 or 1");
+    if (o->accel < 0 || o->accel > AA_MAX) return fail(OBTE_ERR_ARG, "accel must be in 0..%d", AA_MAX);
     return OBTE_OK;
 }
 
@@ -290,12 +318,14 @@ struct Run {
     std::vector<Item> items;
     GeomDev* d_views = nullptr;
     Item* d_items = nullptr;
-    int waves = 4, cpl = 1, nzmax = 1, precision = 0;
+    int* d_pending = nullptr;     // geometries whose Fourier CG still iterates
+    int waves = 4, cpl = 1, nzmax = 1, precision = 0, accel = 0;
     size_t lds = 0;
     int max_cells = 0, max_walls = 0;
     ~Run() {
         if (d_views) soft(hipFree(d_views), "hipFree(views)");
         if (d_items) soft(hipFree(d_items), "hipFree(items)");
+        if (d_pending) soft(hipFree(d_pending), "hipFree(pending)");
     }
 };
 
@@ -303,6 +333,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
                       char* ws, std::vector<size_t>* offsets) {
     R.meshes.assign(meshes, meshes + n);
     R.precision = o->precision;
+    R.accel = o->accel;
     int W = o->waves_per_group;
     if (W == 0) {
         W = auto_waves(meshes[0]);
@@ -334,7 +365,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         obte_mesh* m = meshes[gi];
         Layout L = make_layout(m, o, W);
         if (offsets) offsets->push_back(off);
-        GeomDev v = make_view(m, ws + off, L, W, o->recycle);
+        GeomDev v = make_view(m, ws + off, L, W, o->recycle, o->accel);
         v.item0 = (int)R.items.size();
         const int ng = n_groups(m, W);
         for (int l = 0; l < m->n_dir; ++l)
@@ -360,6 +391,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     R.lds = (size_t)W * per_wave;
     HIPCHK(hipMalloc((void**)&R.d_views, R.views.size() * sizeof(GeomDev)));
     HIPCHK(hipMalloc((void**)&R.d_items, R.items.size() * sizeof(Item)));
+    HIPCHK(hipMalloc((void**)&R.d_pending, sizeof(int)));
     HIPCHK(hipMemcpy(R.d_views, R.views.data(), R.views.size() * sizeof(GeomDev), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(R.d_items, R.items.data(), R.items.size() * sizeof(Item), hipMemcpyHostToDevice));
     return OBTE_OK;
@@ -372,8 +404,56 @@ obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Tim
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 1], st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 2], st));
     HIPCHK(launch_reduce_pass(R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
+    if (R.accel > 0) HIPCHK(launch_anderson(R.d_views, (int)R.views.size(), R.max_cells + R.max_walls, pp, st));
     HIPCHK(launch_finalize(R.d_views, (int)R.views.size(), pp, st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 3], st));
+    return OBTE_OK;
+}
+
+// Fourier first guess of every geometry: CG iterations replayed as HIP graphs
+// of KF iterations (with the count of geometries still iterating at the end)
+// until none is left; direct launches when there is no stream to capture.
+obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st) {
+    const int n = (int)R.views.size();
+    constexpr int KF = 8;     // even: an iteration's parity is its position in the graph
+    HIPCHK(launch_fourier_init(R.d_views, n, R.max_cells, st));
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int j = 0; j < KF && e == hipSuccess; ++j)
+            e = launch_fourier_iter(R.d_views, n, R.max_cells, j & 1, o->fourier_tol, o->max_fourier, st);
+        if (e == hipSuccess) e = launch_fourier_pending(R.d_views, n, R.d_pending, st);
+        return e;
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (st) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const hipError_t e1 = enqueue();
+        const hipError_t e2 = hipStreamEndCapture(st, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy");
+            return fail(OBTE_ERR_HIP, "Fourier graph capture failed: %s",
+                        hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        }
+        const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e3 != hipSuccess) {
+            soft(hipGraphDestroy(graph), "hipGraphDestroy");
+            return fail(OBTE_ERR_HIP, "Fourier graph instantiate failed: %s", hipGetErrorString(e3));
+        }
+    }
+    obte_status out = OBTE_OK;
+    int pending = 1;
+    for (int it = 0; pending > 0 && it <= o->max_fourier + KF; it += KF) {
+        const hipError_t e = exec ? hipGraphLaunch(exec, st) : enqueue();
+        if (e != hipSuccess) { out = fail(OBTE_ERR_HIP, "Fourier iterations: %s", hipGetErrorString(e)); break; }
+        hipError_t e2 = hipMemcpyAsync(&pending, R.d_pending, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        if (e2 != hipSuccess) { out = fail(OBTE_ERR_HIP, "Fourier readback: %s", hipGetErrorString(e2)); break; }
+    }
+    if (exec) soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
+    if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy");
+    if (out != OBTE_OK) return out;
+    HIPCHK(launch_fourier_finish(R.d_views, n, st));
     return OBTE_OK;
 }
 
@@ -490,14 +570,17 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
     }
     if (o->init == 0) {
         if (tm.on) HIPCHK(hipEventRecord(tm.f0, st));
-        HIPCHK(launch_fourier(R.d_views, n, R.max_cells, o->fourier_tol, o->max_fourier, st));
+        s = run_fourier(R, o, st);
+        if (s != OBTE_OK) return s;
         if (tm.on) HIPCHK(hipEventRecord(tm.f1, st));
     } else {
-        // resume: clear the done / converged flags, keep the pass count
+        // resume: clear the done / converged flags, keep the pass count; the
+        // mixing history restarts from the stored iterate
         for (int i = 0; i < n; ++i) {
             int zero2[2] = {0, 0};
             HIPCHK(hipMemcpyAsync(R.views[i].ctrl + CTRL_DONE, zero2, sizeof(int), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(R.views[i].ctrl + CTRL_CONVERGED, zero2, sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemsetAsync(R.views[i].actl, 0, 8 * sizeof(int), st));
         }
     }
     if (!o->only_fourier) {
@@ -617,6 +700,7 @@ void obte_default_opts(obte_solve_opts* o) {
     o->wrap_tol = 0.0;
     o->timing = 0;
     o->stop_rule = 0;
+    o->accel = 0;
 }
 
 obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
@@ -780,7 +864,7 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     if ((s = upload(&m->d_wout, m->wout)) != OBTE_OK) return s;
     if ((s = upload(&m->d_kax, m->kappa_axis)) != OBTE_OK) return s;
     HIPCHK(hipMalloc((void**)&m->d_geom, sizeof(GeomDev)));
-    GeomDev v = make_view(m, nullptr, Layout{}, 0, 0);
+    GeomDev v = make_view(m, nullptr, Layout{}, 0, 0, 0);
     HIPCHK(hipMemcpy(m->d_geom, &v, sizeof v, hipMemcpyHostToDevice));
     m->host_view = v;
     m->has_material = true;
@@ -846,7 +930,8 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     s = build_run(R, &mp, 1, &oo, (char*)workspace, nullptr);
     if (s != OBTE_OK) return s;
     Layout L = make_layout(m, &oo, R.waves);
-    if (ws_bytes < align256(L.total)) return fail(OBTE_ERR_NOMEM, "workspace too small for the adjoint");
+    if (ws_bytes < align256(L.total))
+        return fail(OBTE_ERR_NOMEM, "workspace too small for the adjoint (accel deeper than the forward solve's?)");
     char* ws = (char*)workspace;
     // lambda^(0) = 0: Psi = Phi = 0, no warm start, fresh counters
     HIPCHK(hipMemsetAsync(ws + L.lam_psi, 0, 2 * (size_t)m->ncells * 8, st));
@@ -860,6 +945,8 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     HIPCHK(hipMemsetAsync(ws + L.iters, 0, 2 * (size_t)m->n_sys * 8, st));
     HIPCHK(hipMemsetAsync(ws + L.wres, 0, (size_t)m->n_sys * 8, st));
     HIPCHK(hipMemsetAsync(ws + L.ctrl, 0, CTRL_N * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(ws + L.ax, 0, ((size_t)m->ncells + m->nwalls) * 8, st));
+    HIPCHK(hipMemsetAsync(ws + L.actl, 0, 8 * sizeof(int), st));
     PassParams pp = base_params(o);
     pp.adjoint = 1;
     const int K = (o->passes_per_graph <= 1 || !st || o->timing) ? 1 : o->passes_per_graph;
@@ -918,7 +1005,7 @@ obte_status obte_checkpoint_save(const obte_mesh* m, const void* workspace, cons
     // header: magic, sizes; body: ctrl, T_L, sT (2), Tw (2), U, hist
     const GeomDev& v = m->host_view;
     if (m->last_ws != workspace) return fail(OBTE_ERR_ARG, "workspace differs from the last solve's");
-    const int hdr[10] = {0x4f425445, m->ncells, m->nwalls, m->n_sys, m->nx * m->nz, m->last_precision,
+    const int hdr[10] = {0x4f425446, m->ncells, m->nwalls, m->n_sys, m->nx * m->nz, m->last_precision,
                          m->last_waves, m->last_max_outer, m->last_keep, m->last_recycle};
     fwrite(hdr, sizeof hdr, 1, f);
     auto dump = [&](const void* dptr, size_t bytes) -> bool {
@@ -935,7 +1022,8 @@ obte_status obte_checkpoint_save(const obte_mesh* m, const void* workspace, cons
          dump(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz) &&
          dump(v.bnd, 2 * (size_t)m->nf * m->ncells * 8) && dump(v.mem_count, (size_t)m->n_sys * 4) &&
          (m->last_recycle == 0 ||
-          dump(v.mem, (size_t)m->n_sys * 2 * m->last_recycle * m->nx * m->nz * tsz));
+          dump(v.mem, (size_t)m->n_sys * 2 * m->last_recycle * m->nx * m->nz * tsz)) &&
+         dump(v.ax, ((size_t)m->ncells + m->nwalls) * 8);
     const int passes = ctrl[CTRL_PASS];
     fwrite(&passes, sizeof passes, 1, f);
     ok = ok && (passes == 0 || dump(v.hist, (size_t)passes * 8)) && (passes == 0 || dump(v.hist_face, (size_t)passes * 8));
@@ -950,7 +1038,7 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     FILE* f = fopen(path, "rb");
     if (!f) return fail(OBTE_ERR_ARG, "cannot open %s", path);
     int hdr[10];
-    if (fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != 0x4f425445 || hdr[1] != m->ncells ||
+    if (fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != 0x4f425446 || hdr[1] != m->ncells ||
         hdr[2] != m->nwalls || hdr[3] != m->n_sys || hdr[4] != m->nx * m->nz) {
         fclose(f);
         return fail(OBTE_ERR_ARG, "checkpoint does not match this mesh / precision");
@@ -961,18 +1049,19 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     o.max_outer = hdr[7];
     o.keep_state = hdr[8];
     o.recycle = hdr[9];
-    const GeomDev v = make_view(m, (char*)workspace, make_layout(m, &o, hdr[6]), hdr[6], hdr[9]);
+    const GeomDev v = make_view(m, (char*)workspace, make_layout(m, &o, hdr[6]), hdr[6], hdr[9], 0);
     auto load = [&](void* dptr, size_t bytes) -> bool {
         std::vector<char> buf(bytes);
         if (fread(buf.data(), 1, bytes, f) != bytes) return false;
         return hipMemcpy(dptr, buf.data(), bytes, hipMemcpyHostToDevice) == hipSuccess;
     };
-    const size_t tsz = m->last_precision == OBTE_FP32 ? 4 : 8;
+    const size_t tsz = hdr[5] == OBTE_FP32 ? 4 : 8;
     bool ok = load(v.ctrl, CTRL_N * sizeof(int)) && load(v.T_L, (size_t)m->ncells * 8) &&
               load(v.sT, 2 * (size_t)m->ncells * 8) && load(v.Tw, 2 * (size_t)std::max(m->nwalls, 1) * 8) &&
               load(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz) &&
               load(v.bnd, 2 * (size_t)m->nf * m->ncells * 8) && load(v.mem_count, (size_t)m->n_sys * 4) &&
-              (hdr[9] == 0 || load(v.mem, (size_t)m->n_sys * 2 * hdr[9] * m->nx * m->nz * tsz));
+              (hdr[9] == 0 || load(v.mem, (size_t)m->n_sys * 2 * hdr[9] * m->nx * m->nz * tsz)) &&
+              load(v.ax, ((size_t)m->ncells + m->nwalls) * 8);
     int passes = 0;
     ok = ok && fread(&passes, sizeof passes, 1, f) == 1;
     ok = ok && (passes == 0 || load(v.hist, (size_t)passes * 8)) && (passes == 0 || load(v.hist_face, (size_t)passes * 8));

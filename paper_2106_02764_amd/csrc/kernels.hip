@@ -1035,11 +1035,14 @@ __global__ void __launch_bounds__(256) k_reduce_pass(const GeomDev* __restrict__
     if (q == 0 && cell < g.ncells) {
         const double tot = ((part[0][cl] + part[1][cl]) + part[2][cl]) + part[3][cl];
         const bool sol = fc_solid(g.fc[cell]);
-        if (adj) {
-            g.lam_psi[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * tot : 0.0;
+        const double xv = sol ? tot : 0.0;
+        if (!adj) g.T_L[cell] = xv;
+        if (g.aa_m > 0) {
+            g.ag[cell] = xv;               // the mixing step writes the next inputs
         } else {
-            g.T_L[cell] = sol ? tot : 0.0;
-            g.sT[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * tot : 0.0;
+            g.ax[cell] = xv;
+            if (adj) g.lam_psi[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * tot : 0.0;
+            else g.sT[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * tot : 0.0;
         }
     }
     // walls: one wavefront per wall face; items whose direction leaves the
@@ -1062,9 +1065,14 @@ __global__ void __launch_bounds__(256) k_reduce_pass(const GeomDev* __restrict__
         }
         a = wave_sum(a);
         if (lane == 0) {
-            if (adj) g.lam_phi[(size_t)out * g.nwalls + wi] = a;
-            else g.Tw[(size_t)out * g.nwalls + wi] = a;
-            bnd_out[(size_t)f * g.ncells + g.wall_cell[wi]] = a;
+            if (g.aa_m > 0) {
+                g.ag[g.ncells + wi] = a;
+            } else {
+                g.ax[g.ncells + wi] = a;
+                if (adj) g.lam_phi[(size_t)out * g.nwalls + wi] = a;
+                else g.Tw[(size_t)out * g.nwalls + wi] = a;
+                bnd_out[(size_t)f * g.ncells + g.wall_cell[wi]] = a;
+            }
         }
     }
 }
@@ -1126,6 +1134,10 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
                 small = d0 * rho / (1.0 - rho) <= pp.outer_tol * fabs(k);
             }
         }
+        // with mixing, successive kappa can agree before the iterate has
+        // settled: the error estimated from the fixed-point residual must
+        // meet the tolerance too
+        if (g.aa_m > 0) small = small && g.fscal[3] <= pp.outer_tol;
         if (!isfinite(k)) {
             g.ctrl[CTRL_NONFINITE] = 1;
             g.ctrl[CTRL_DONE] = 1;
@@ -1139,24 +1151,224 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
 }
 
 // ---------------------------------------------------------------------------
-// Fourier first guess: CG on the negated 5/7-point finite-volume Laplacian
-// with adiabatic pores and the periodic jump (one block per geometry).
+// Anderson mixing of the outer fixed point x -> G(x).  The pass computed
+// G(x_k); with f_k = G(x_k) - x_k and the last aa_m differences dX, dF of
+// iterates and residuals,
+//   gamma = argmin |f_k - dF gamma|,   x_{k+1} = x_k + f_k - (dX + dF) gamma
+// (gamma from the normal equations of the column-scaled dF, Cholesky in
+// double; a failed factorisation drops the history and takes the plain step
+// x_{k+1} = G(x_k)).  Two kernels over up to AAB_MAX blocks per geometry:
+// the first stores the new difference column and the per-block partial dot
+// products, the second sums them in a fixed order, solves the small system
+// in every block (the same numbers everywhere), and writes the next pass's
+// inputs: sigma T_L (or sigma sum lambda), the wall values and their inflow
+// table entries.  The history counters are double buffered by pass parity.
 // ---------------------------------------------------------------------------
+constexpr int AAB_MAX = 256, AA_THREADS = 256, AA_NP = 2 * AA_MAX + 3;
 
-// Sum over the block returned to every thread with a single barrier; `red`
-// alternates between two halves so back-to-back calls do not race.
-__device__ __forceinline__ double block_sum1(double v, double* red, int& phase) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = wave_sum(v);
-    double* r = red + 16 * phase;
-    phase ^= 1;
-    if (lane == 0) r[wid] = v;
-    __syncthreads();
-    double t = 0.0;
-    for (int i = 0; i < nw; ++i) t += r[i];
-    return t;
+struct AView {
+    int n, B, c0, c1;
+};
+__device__ __forceinline__ AView aa_view(const GeomDev& g, int b) {
+    AView v;
+    v.n = g.n_aa;
+    v.B = min(AAB_MAX, (v.n + AA_THREADS - 1) / AA_THREADS);
+    const int chunk = (v.n + v.B - 1) / v.B;
+    v.c0 = min(v.n, b * chunk);
+    v.c1 = min(v.n, v.c0 + chunk);
+    return v;
 }
 
+__global__ void __launch_bounds__(AA_THREADS) k_aa_partial(const GeomDev* __restrict__ geoms) {
+    __shared__ double red[AA_NP][AA_THREADS / 64];
+    const GeomDev& g = geoms[blockIdx.y];
+    if (g.aa_m <= 0 || g.ctrl[CTRL_DONE]) return;
+    const AView v = aa_view(g, blockIdx.x);
+    if ((int)blockIdx.x >= v.B) return;
+    const int n = v.n, M = g.aa_m;
+    const int* ac = g.actl + 4 * (g.ctrl[CTRL_PASS] & 1);
+    const int cnt = ac[0], head = ac[1], have = ac[2];
+    const int slot = head;                            // the new column (when have)
+    const int cnt1 = have ? min(cnt + 1, M) : cnt;    // valid columns: 0 .. cnt1-1
+    double dA[AA_MAX], db[AA_MAX];
+#pragma unroll
+    for (int j = 0; j < AA_MAX; ++j) { dA[j] = 0.0; db[j] = 0.0; }
+    double ff = 0.0, xx = 0.0, dxx = 0.0;
+    for (int i = v.c0 + threadIdx.x; i < v.c1; i += blockDim.x) {
+        const double x = g.ax[i];
+        const double f = g.ag[i] - x;
+        xx += x * x;
+        ff += f * f;
+        double df = 0.0;
+        if (have) {
+            df = f - g.afp[i];
+            const double dx = x - g.axp[i];
+            dxx += dx * dx;
+            g.adX[(size_t)slot * n + i] = dx;
+            g.adF[(size_t)slot * n + i] = df;
+        }
+        g.axp[i] = x;
+        g.afp[i] = f;
+#pragma unroll
+        for (int j = 0; j < AA_MAX; ++j) {
+            if (j < cnt1) {
+                const double Fj = (have && j == slot) ? df : g.adF[(size_t)j * n + i];
+                db[j] += Fj * f;
+                if (have) dA[j] += df * Fj;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int j = 0; j < AA_MAX; ++j) {
+        const double a = wave_sum(dA[j]), b = wave_sum(db[j]);
+        if (lane == 0) { red[j][wid] = a; red[AA_MAX + j][wid] = b; }
+    }
+    {
+        const double t = wave_sum(ff), u = wave_sum(xx), w2 = wave_sum(dxx);
+        if (lane == 0) { red[2 * AA_MAX][wid] = t; red[2 * AA_MAX + 1][wid] = u; red[2 * AA_MAX + 2][wid] = w2; }
+    }
+    __syncthreads();
+    if (threadIdx.x < AA_NP) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
+        g.apart[(size_t)blockIdx.x * AA_NP + threadIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(AA_THREADS) k_aa_apply(const GeomDev* __restrict__ geoms, PassParams pp) {
+    __shared__ double tot[AA_NP];
+    __shared__ double gam[AA_MAX];
+    const GeomDev& g = geoms[blockIdx.y];
+    if (g.aa_m <= 0 || g.ctrl[CTRL_DONE]) return;
+    const AView v = aa_view(g, blockIdx.x);
+    if ((int)blockIdx.x >= v.B) return;
+    const int n = v.n, M = g.aa_m, nc = g.ncells;
+    const int adj = pp.adjoint;
+    const int par = g.ctrl[CTRL_PASS] & 1;
+    const int out = par ^ 1;                           // pass input buffers of the next pass
+    const int* ac = g.actl + 4 * par;
+    const int cnt = ac[0], head = ac[1], have = ac[2];
+    const int slot = head;
+    const int cnt1 = have ? min(cnt + 1, M) : cnt;
+    // fixed-order sums of the per-block partials
+    if (threadIdx.x < AA_NP) {
+        double t = 0.0;
+        for (int b = 0; b < v.B; ++b) t += g.apart[(size_t)b * AA_NP + threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double* dxg = g.agram + M * M;            // |dX_j|^2 of the stored columns
+        // this pass's Gram matrix: the new column's row from the partials,
+        // the rest from the stored matrix (block 0 stores the new row)
+        double G[AA_MAX][AA_MAX], dxn[AA_MAX], b[AA_MAX], d[AA_MAX];
+        for (int j = 0; j < cnt1; ++j) {
+            for (int k2 = 0; k2 < cnt1; ++k2) {
+                const bool fresh = have && (j == slot || k2 == slot);
+                G[j][k2] = fresh ? tot[j == slot ? k2 : j] : g.agram[j * M + k2];
+            }
+            dxn[j] = (have && j == slot) ? tot[2 * AA_MAX + 2] : dxg[j];
+            b[j] = tot[AA_MAX + j];
+        }
+        if (blockIdx.x == 0 && have) {
+            for (int j = 0; j < cnt1; ++j) {
+                g.agram[slot * M + j] = G[slot][j];
+                g.agram[j * M + slot] = G[slot][j];
+            }
+            g.agram[M * M + slot] = dxn[slot];
+        }
+        // error estimate for the stop test: with f = (G - I) e for a linear G,
+        // |e| <= |f| / s_min(I - G); s_min is estimated by the smallest
+        // |dF_j| / |dX_j| over the stored columns (no columns: |f| itself)
+        double smin = 1.0;
+        for (int j = 0; j < cnt1; ++j)
+            if (dxn[j] > 0.0) smin = fmin(smin, sqrt(G[j][j] / dxn[j]));
+        smin = fmax(smin, 1e-3);
+        const double sf = tot[2 * AA_MAX], sx = tot[2 * AA_MAX + 1];
+        const double res = sx > 0.0 ? sqrt(sf / sx) : (sf > 0.0 ? INFINITY : 0.0);
+        if (blockIdx.x == 0) g.fscal[3] = res / smin;
+        // scaled normal equations with a small ridge, Cholesky in place
+        bool ok = cnt1 > 0;
+        for (int j = 0; j < cnt1 && ok; ++j) {
+            d[j] = sqrt(G[j][j]);
+            ok = d[j] > 0.0 && isfinite(d[j]);
+        }
+        for (int j = 0; j < cnt1 && ok; ++j)
+            for (int k2 = 0; k2 < cnt1; ++k2) G[j][k2] = G[j][k2] / (d[j] * d[k2]) + (j == k2 ? 1e-10 : 0.0);
+        for (int j = 0; j < cnt1 && ok; ++j) {
+            double s2 = G[j][j];
+            for (int k2 = 0; k2 < j; ++k2) s2 -= G[j][k2] * G[j][k2];
+            if (!(s2 > 1e-14)) { ok = false; break; }
+            G[j][j] = sqrt(s2);
+            for (int r = j + 1; r < cnt1; ++r) {
+                double t = G[r][j];
+                for (int k2 = 0; k2 < j; ++k2) t -= G[r][k2] * G[j][k2];
+                G[r][j] = t / G[j][j];
+            }
+        }
+        double y[AA_MAX];
+        if (ok) {
+            for (int j = 0; j < cnt1; ++j) {
+                double t = b[j] / d[j];
+                for (int k2 = 0; k2 < j; ++k2) t -= G[j][k2] * y[k2];
+                y[j] = t / G[j][j];
+            }
+            for (int j = cnt1 - 1; j >= 0; --j) {
+                double t = y[j];
+                for (int k2 = j + 1; k2 < cnt1; ++k2) t -= G[k2][j] * y[k2];
+                y[j] = t / G[j][j];
+            }
+            for (int j = 0; j < cnt1; ++j) {
+                gam[j] = y[j] / d[j];
+                ok = ok && isfinite(gam[j]);
+            }
+        }
+        if (!ok)
+            for (int j = 0; j < AA_MAX; ++j) gam[j] = 0.0;
+        for (int j = ok ? cnt1 : 0; j < AA_MAX; ++j) gam[j] = 0.0;
+        if (blockIdx.x == 0) {
+            int* ao = g.actl + 4 * out;
+            if (ok || cnt1 == 0) {
+                ao[0] = cnt1;
+                ao[1] = have ? (slot + 1) % M : head;
+            } else {          // drop the history; the next pass starts a new one
+                ao[0] = 0;
+                ao[1] = 0;
+            }
+            ao[2] = 1;
+        }
+    }
+    __syncthreads();
+    double* bnd_out = g.bnd + ((size_t)(adj ? 2 : 0) + out) * g.nf * nc;
+    for (int i = v.c0 + threadIdx.x; i < v.c1; i += blockDim.x) {
+        double xn = g.axp[i] + g.afp[i];
+        for (int j = 0; j < cnt1; ++j)
+            xn -= gam[j] * (g.adX[(size_t)j * n + i] + g.adF[(size_t)j * n + i]);
+        if (i < nc) {
+            const bool sol = fc_solid(g.fc[i]);
+            xn = sol ? xn : 0.0;
+            const double sx = sol ? g.sigma[i] * xn : 0.0;
+            if (adj) g.lam_psi[(size_t)out * nc + i] = sx;
+            else g.sT[(size_t)out * nc + i] = sx;
+        } else {
+            const int wi = i - nc;
+            if (adj) g.lam_phi[(size_t)out * g.nwalls + wi] = xn;
+            else g.Tw[(size_t)out * g.nwalls + wi] = xn;
+            bnd_out[(size_t)g.wall_face[wi] * nc + g.wall_cell[wi]] = xn;
+        }
+        g.ax[i] = xn;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fourier first guess: CG on the negated 5/7-point finite-volume Laplacian
+// with adiabatic pores and the periodic jump (Appendix B on the structured
+// grid), spread over up to FB_MAX blocks per geometry.  Two kernels per
+// iteration; each sums the per-block partials of the previous one in a fixed
+// order (no atomics), so every block of a geometry takes the same decisions,
+// and a converged geometry's blocks exit at once.
+// ---------------------------------------------------------------------------
 // Shared epilogue: x (solution, global) -> mean-free T_F, sigma T_F, T_w, the
 // inflow boundary tables and kappa_F; resets the pass control words.
 __device__ void fourier_epilogue(const GeomDev& g, double* red, int iter, double rn, double bn) {
@@ -1194,7 +1406,11 @@ __device__ void fourier_epilogue(const GeomDev& g, double* red, int iter, double
         const double t = x[g.wall_cell[wi]];
         g.Tw[wi] = t;
         g.bnd[(size_t)g.wall_face[wi] * n + g.wall_cell[wi]] = t;
+        g.ax[n + wi] = t;
     }
+    // the first iterate of the outer fixed point, mixing history cleared
+    for (int c = threadIdx.x; c < n; c += blockDim.x) g.ax[c] = x[c];
+    if (g.aa_m > 0 && threadIdx.x < 8) g.actl[threadIdx.x] = 0;
     // kappa_F: plane flux through the periodic plane of the gradient axis
     const int ga = g.grad_axis;
     double fl = 0.0;
@@ -1227,178 +1443,168 @@ __device__ __forceinline__ double fourier_rhs(const GeomDev& g, uint16_t w, cons
     return b;
 }
 
-// Small meshes (<= FOURIER_LDS_CELLS): the search direction lives in LDS and
-// each thread keeps its cells' residual in registers (x accumulates in global
-// memory).  A cell's face word carries, above the face classes, whether the
-// cell sits on the low / high edge of each axis, so a neighbour index is an
-// add with a wrap correction rather than an integer division.
-constexpr int FOURIER_LDS_CELLS = 16384;
-constexpr int FOURIER_THREADS = 512;
-constexpr int FOURIER_PER_THREAD = FOURIER_LDS_CELLS / FOURIER_THREADS;
+constexpr int FB_MAX = 256, FB_THREADS = 256;
 
-__device__ __forceinline__ uint32_t edge_bits(const GeomDev& g, int c) {
-    const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
-    uint32_t b = 0;
-    b |= (ix == 0) << 16;
-    b |= (ix == g.nx - 1) << 17;
-    b |= (iy == 0) << 18;
-    b |= (iy == g.ny - 1) << 19;
-    b |= (iz == 0) << 20;
-    b |= (iz == g.nz - 1) << 21;
-    return b;
-}
-
-__device__ __forceinline__ int nbr_fast(int c, uint32_t w, int f, const int (&stride)[3], const int (&span)[3]) {
-    const int a = f >> 1;
-    const bool hi = f & 1;
-    const bool edge = (w >> (16 + f)) & 1;
-    const int d = edge ? (hi ? -span[a] : span[a]) : (hi ? stride[a] : -stride[a]);
-    return c + d;
-}
-
-__global__ void __launch_bounds__(FOURIER_THREADS) k_fourier_lds(const GeomDev* __restrict__ geoms, double tol,
-                                                     int max_iter) {
-    extern __shared__ double pl[];      // ncells
-    __shared__ double red[32];
-    const GeomDev& g = geoms[blockIdx.x];
-    const int n = g.ncells, nf = g.nf;
-    const int stride[3] = {1, g.nx, g.nx * g.ny};
-    const int span[3] = {g.nx - 1, (g.ny - 1) * g.nx, (g.nz - 1) * g.nx * g.ny};
-    double kf[3];
-    for (int a = 0; a < 3; ++a) kf[a] = (a < g.ndim) ? g.kappa_axis[a] / (g.h[a] * g.h[a]) : 0.0;
-    gptr_t<uint16_t> fcv = gview(g.fc);
-    double r[FOURIER_PER_THREAD], x[FOURIER_PER_THREAD];
-    uint32_t fw[FOURIER_PER_THREAD];
-    double rr = 0.0;
-#pragma unroll
-    for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-        const int c = threadIdx.x + k * FOURIER_THREADS;
-        fw[k] = c < n ? ((uint32_t)fcv[c] | edge_bits(g, c)) : 0u;
-        const double b = c < n ? fourier_rhs(g, (uint16_t)fw[k], kf) : 0.0;
-        r[k] = b;
-        x[k] = 0.0;
-        if (c < n) pl[c] = b;
-        rr += b * b;
-    }
-    int ph = 0;
-    rr = block_sum1(rr, red, ph);
-    const double bn = sqrt(rr);
-    double rn = bn;
-    int iter = 0;
-    if (bn > 0.0) {
-        for (iter = 0; iter < max_iter; ++iter) {
-            // p is complete in LDS (the reduction above synchronised); A p is
-            // evaluated twice from LDS rather than held in registers
-            double pap = 0.0;
-#pragma unroll
-            for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-                const int c = threadIdx.x + k * FOURIER_THREADS;
-                if (c < n && fc_solid(fw[k])) {
-                    const double pc = pl[c];
-                    double y = 0.0;
-                    for (int f = 0; f < nf; ++f)
-                        if (fc_class(fw[k], f) != FC_WALL) y += kf[f >> 1] * (pc - pl[nbr_fast(c, fw[k], f, stride, span)]);
-                    pap += pc * y;
-                }
-            }
-            pap = block_sum1(pap, red, ph);
-            const double alpha = rr / pap;
-            double rr2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-                const int c = threadIdx.x + k * FOURIER_THREADS;
-                if (c < n && fc_solid(fw[k])) {
-                    const double pc = pl[c];
-                    double y = 0.0;
-                    for (int f = 0; f < nf; ++f)
-                        if (fc_class(fw[k], f) != FC_WALL) y += kf[f >> 1] * (pc - pl[nbr_fast(c, fw[k], f, stride, span)]);
-                    x[k] += alpha * pc;
-                    r[k] -= alpha * y;
-                    rr2 += r[k] * r[k];
-                }
-            }
-            rr2 = block_sum1(rr2, red, ph);
-            rn = sqrt(rr2);
-            if (rn <= tol * bn) { ++iter; break; }
-            const double beta = rr2 / rr;
-            rr = rr2;
-            // every thread has read its p entries above; update them in place
-#pragma unroll
-            for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-                const int c = threadIdx.x + k * FOURIER_THREADS;
-                if (c < n) pl[c] = r[k] + beta * pl[c];
-            }
-            __syncthreads();
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < FOURIER_PER_THREAD; ++k) {
-        const int c = threadIdx.x + k * FOURIER_THREADS;
-        if (c < n) g.fx[c] = x[k];
-    }
-    __syncthreads();
-    fourier_epilogue(g, red, iter, rn, bn);
-}
-
-// Larger meshes: vectors in global memory (L2-resident).
-__global__ void __launch_bounds__(1024) k_fourier(const GeomDev* __restrict__ geoms, double tol,
-                                                 int max_iter) {
-    __shared__ double red[32];
-    const GeomDev& g = geoms[blockIdx.x];
+// This geometry's CG storage (in the fx region) and block b's cell range.
+struct FView {
+    double *x, *r, *p0, *p1, *ap, *pap, *rr0, *rr1, *sc;   // sc: [0] |b|, [1] done, [4] iterations
+    int n, B, c0, c1;
+};
+__device__ __forceinline__ FView fourier_view(const GeomDev& g, int b) {
+    FView v;
     const int n = g.ncells;
-    double* x = g.fx;
-    double* r = g.fx + n;
-    double* p = g.fx + 2 * (size_t)n;
-    double* Ap = g.fx + 3 * (size_t)n;
+    v.n = n;
+    v.B = min(FB_MAX, (n + FB_THREADS - 1) / FB_THREADS);
+    double* f = g.fx;
+    v.x = f;
+    v.r = f + n;
+    v.p0 = f + 2 * (size_t)n;
+    v.p1 = f + 3 * (size_t)n;
+    v.ap = f + 4 * (size_t)n;
+    v.pap = f + 5 * (size_t)n;
+    v.rr0 = v.pap + FB_MAX;
+    v.rr1 = v.rr0 + FB_MAX;
+    v.sc = v.rr1 + FB_MAX;
+    const int chunk = (n + v.B - 1) / v.B;
+    v.c0 = min(n, b * chunk);
+    v.c1 = min(n, v.c0 + chunk);
+    return v;
+}
+
+__device__ __forceinline__ double axis_pick(double k0, double k1, double k2, int a) {
+    return a == 0 ? k0 : (a == 1 ? k1 : k2);
+}
+
+// fixed-order sum of the B per-block partials, returned to every thread
+__device__ __forceinline__ double sum_partials(const double* part, int B, double* red) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < B; i += blockDim.x) t += part[i];
+    return block_sum(t, red);
+}
+
+__global__ void __launch_bounds__(FB_THREADS) k_fourier_init(const GeomDev* __restrict__ geoms) {
+    __shared__ double red[32];
+    const GeomDev& g = geoms[blockIdx.y];
+    const FView v = fourier_view(g, blockIdx.x);
+    if ((int)blockIdx.x >= v.B) return;
     double kf[3];
     for (int a = 0; a < 3; ++a) kf[a] = (a < g.ndim) ? g.kappa_axis[a] / (g.h[a] * g.h[a]) : 0.0;
-    const int nf = g.nf;
-    double rr = 0.0;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double s = 0.0;
+    for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
         const double b = fourier_rhs(g, g.fc[c], kf);
-        x[c] = 0.0;
-        r[c] = b;
-        p[c] = b;
-        rr += b * b;
+        v.x[c] = 0.0;
+        v.r[c] = b;
+        v.p0[c] = 0.0;
+        s += b * b;
     }
-    rr = block_sum(rr, red);
-    const double bn = sqrt(rr);
-    int iter = 0;
-    double rn = bn;
-    if (bn > 0.0) {
-        for (iter = 0; iter < max_iter; ++iter) {
-            double pap = 0.0;
-            for (int c = threadIdx.x; c < n; c += blockDim.x) {
-                const uint16_t w = g.fc[c];
-                double y = 0.0;
-                if (fc_solid(w)) {
-                    const double pc = p[c];
-                    for (int f = 0; f < nf; ++f)
-                        if (fc_class(w, f) != FC_WALL) y += kf[f >> 1] * (pc - p[nbr_cell(g, c, f)]);
-                }
-                Ap[c] = y;
-                pap += p[c] * y;
-            }
-            pap = block_sum(pap, red);
-            const double alpha = rr / pap;
-            double rr2 = 0.0;
-            for (int c = threadIdx.x; c < n; c += blockDim.x) {
-                x[c] += alpha * p[c];
-                const double rv = r[c] - alpha * Ap[c];
-                r[c] = rv;
-                rr2 += rv * rv;
-            }
-            rr2 = block_sum(rr2, red);
-            rn = sqrt(rr2);
-            if (rn <= tol * bn) { ++iter; break; }
-            const double beta = rr2 / rr;
-            rr = rr2;
-            for (int c = threadIdx.x; c < n; c += blockDim.x) p[c] = r[c] + beta * p[c];
-            __syncthreads();
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        v.rr0[blockIdx.x] = s;
+        v.rr1[blockIdx.x] = INFINITY;        // first beta = 0
+        if (blockIdx.x == 0) {
+            v.sc[1] = 0.0;
+            v.sc[4] = 0.0;
         }
     }
+}
+
+// |b| of every geometry (one block each)
+__global__ void __launch_bounds__(FB_THREADS) k_fourier_norm(const GeomDev* __restrict__ geoms) {
+    __shared__ double red[32];
+    const GeomDev& g = geoms[blockIdx.x];
+    const FView v = fourier_view(g, 0);
+    const double bb = sum_partials(v.rr0, v.B, red);
+    if (threadIdx.x == 0) {
+        v.sc[0] = sqrt(bb);
+        if (!(bb > 0.0)) v.sc[1] = 1.0;
+    }
+}
+
+// p <- r + beta p, A p and the partials of p.Ap; the stop test (every block of
+// the geometry computes the same sums).  q: iteration parity.
+__global__ void __launch_bounds__(FB_THREADS) k_fourier_pq(const GeomDev* __restrict__ geoms, int q,
+                                                         double tol, int max_iter) {
+    __shared__ double red[32];
+    const GeomDev& g = geoms[blockIdx.y];
+    const FView v = fourier_view(g, blockIdx.x);
+    if ((int)blockIdx.x >= v.B || v.sc[1] != 0.0) return;
+    const double rr_new = sum_partials(q ? v.rr1 : v.rr0, v.B, red);
+    const double rr_old = sum_partials(q ? v.rr0 : v.rr1, v.B, red);
+    const double rn = sqrt(rr_new);
+    if (!(rn > tol * v.sc[0]) || v.sc[4] >= (double)max_iter) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) v.sc[1] = 1.0;
+        return;
+    }
+    const double beta = isinf(rr_old) ? 0.0 : rr_new / rr_old;
+    const double* pold = q ? v.p1 : v.p0;
+    double* pnew = q ? v.p0 : v.p1;
+    const double k0 = g.kappa_axis[0] / (g.h[0] * g.h[0]);
+    const double k1 = g.ndim > 1 ? g.kappa_axis[1] / (g.h[1] * g.h[1]) : 0.0;
+    const double k2 = g.ndim > 2 ? g.kappa_axis[2] / (g.h[2] * g.h[2]) : 0.0;
+    const int nf = g.nf;
+    double pap = 0.0;
+    for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
+        const uint16_t w = g.fc[c];
+        double pc = 0.0, y = 0.0;
+        if (fc_solid(w)) {
+            pc = v.r[c] + beta * pold[c];
+            for (int f = 0; f < nf; ++f) {
+                if (fc_class(w, f) == FC_WALL) continue;
+                const int j = nbr_cell(g, c, f);
+                y += axis_pick(k0, k1, k2, f >> 1) * (pc - (v.r[j] + beta * pold[j]));
+            }
+        }
+        pnew[c] = pc;
+        v.ap[c] = y;
+        pap += pc * y;
+    }
+    pap = block_sum(pap, red);
+    if (threadIdx.x == 0) v.pap[blockIdx.x] = pap;
+}
+
+// x += alpha p, r -= alpha A p and the partials of the new r.r.
+__global__ void __launch_bounds__(FB_THREADS) k_fourier_xr(const GeomDev* __restrict__ geoms, int q) {
+    __shared__ double red[32];
+    const GeomDev& g = geoms[blockIdx.y];
+    const FView v = fourier_view(g, blockIdx.x);
+    if ((int)blockIdx.x >= v.B || v.sc[1] != 0.0) return;
+    const double pap = sum_partials(v.pap, v.B, red);
+    const double rr = sum_partials(q ? v.rr1 : v.rr0, v.B, red);
+    const double alpha = rr / pap;
+    const double* pnew = q ? v.p0 : v.p1;
+    double s = 0.0;
+    for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
+        v.x[c] += alpha * pnew[c];
+        const double rc = v.r[c] - alpha * v.ap[c];
+        v.r[c] = rc;
+        s += rc * rc;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        (q ? v.rr0 : v.rr1)[blockIdx.x] = s;
+        if (blockIdx.x == 0) v.sc[4] += 1.0;
+    }
+}
+
+// geometries still iterating -> *pending (one block)
+__global__ void __launch_bounds__(256) k_fourier_pending(const GeomDev* __restrict__ geoms, int n_geoms,
+                                                        int* pending) {
+    __shared__ double red[32];
+    double c = 0.0;
+    for (int i = threadIdx.x; i < n_geoms; i += blockDim.x) c += fourier_view(geoms[i], 0).sc[1] == 0.0 ? 1.0 : 0.0;
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) *pending = (int)c;
+}
+
+__global__ void __launch_bounds__(1024) k_fourier_finish(const GeomDev* __restrict__ geoms) {
+    __shared__ double red[32];
+    const GeomDev& g = geoms[blockIdx.x];
+    const FView v = fourier_view(g, 0);
+    const int it = (int)v.sc[4];
+    const double rr = sum_partials((it & 1) ? v.rr1 : v.rr0, v.B, red);
+    const double bn = v.sc[0];
     __syncthreads();
-    fourier_epilogue(g, red, iter, rn, bn);
+    fourier_epilogue(g, red, it, sqrt(rr), bn);
 }
 
 // ---------------------------------------------------------------------------
@@ -1486,23 +1692,39 @@ __global__ void __launch_bounds__(1024) k_output(const GeomDev* __restrict__ gp,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, int max_cells, double tol,
-                          int max_iter, hipStream_t st) {
+static_assert(fourier_scratch_doubles(0) == 3 * FB_MAX + 8, "Fourier scratch carve and kernels disagree");
+static_assert(aa_partial_doubles() == (size_t)AAB_MAX * AA_NP, "mixing partials carve and kernels disagree");
+
+int fourier_blocks(int max_cells) {
+    const int b = (max_cells + FB_THREADS - 1) / FB_THREADS;
+    return b < FB_MAX ? b : FB_MAX;
+}
+
+hipError_t launch_fourier_init(const GeomDev* geoms_dev, int n_geoms, int max_cells, hipStream_t st) {
     (void)hipGetLastError();
-    if (max_cells <= FOURIER_LDS_CELLS) {
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void*)k_fourier_lds,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      FOURIER_LDS_CELLS * (int)sizeof(double));
-            (void)hipGetLastError();
-            attr = true;
-        }
-        hipLaunchKernelGGL(k_fourier_lds, dim3(n_geoms), dim3(FOURIER_THREADS), (size_t)max_cells * sizeof(double),
-                           st, geoms_dev, tol, max_iter);
-    } else {
-        hipLaunchKernelGGL(k_fourier, dim3(n_geoms), dim3(1024), 0, st, geoms_dev, tol, max_iter);
-    }
+    hipLaunchKernelGGL(k_fourier_init, dim3(fourier_blocks(max_cells), n_geoms), dim3(FB_THREADS), 0, st, geoms_dev);
+    hipLaunchKernelGGL(k_fourier_norm, dim3(n_geoms), dim3(FB_THREADS), 0, st, geoms_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_iter(const GeomDev* geoms_dev, int n_geoms, int max_cells, int parity, double tol,
+                               int max_iter, hipStream_t st) {
+    (void)hipGetLastError();
+    const dim3 grid(fourier_blocks(max_cells), n_geoms);
+    hipLaunchKernelGGL(k_fourier_pq, grid, dim3(FB_THREADS), 0, st, geoms_dev, parity, tol, max_iter);
+    hipLaunchKernelGGL(k_fourier_xr, grid, dim3(FB_THREADS), 0, st, geoms_dev, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_pending(const GeomDev* geoms_dev, int n_geoms, int* pending_dev, hipStream_t st) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_fourier_pending, dim3(1), dim3(256), 0, st, geoms_dev, n_geoms, pending_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, hipStream_t st) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_fourier_finish, dim3(n_geoms), dim3(1024), 0, st, geoms_dev);
     return hipGetLastError();
 }
 
@@ -1569,6 +1791,16 @@ hipError_t launch_reduce_pass(const GeomDev* geoms_dev, int n_geoms, int max_cel
 hipError_t launch_finalize(const GeomDev* geoms_dev, int n_geoms, PassParams pp, hipStream_t st) {
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_finalize, dim3(n_geoms), dim3(256), 0, st, geoms_dev, pp);
+    return hipGetLastError();
+}
+
+hipError_t launch_anderson(const GeomDev* geoms_dev, int n_geoms, int max_naa, PassParams pp, hipStream_t st) {
+    (void)hipGetLastError();
+    int b = (max_naa + AA_THREADS - 1) / AA_THREADS;
+    if (b > AAB_MAX) b = AAB_MAX;
+    const dim3 grid(b, n_geoms);
+    hipLaunchKernelGGL(k_aa_partial, grid, dim3(AA_THREADS), 0, st, geoms_dev);
+    hipLaunchKernelGGL(k_aa_apply, grid, dim3(AA_THREADS), 0, st, geoms_dev, pp);
     return hipGetLastError();
 }
 

@@ -74,7 +74,23 @@ struct GeomDev {
     int mem_R;                   // pairs kept per system
     double* wres;                // n_sys: relative wrap-row residual after this pass's solve
     double* wres_hist;           // max_outer: max over systems per pass
+    // ---- the outer fixed point x = (cell field, wall values), n_aa = ncells + nwalls:
+    // forward (T_L, T_w), adjoint (sum_ml lambda, Phi)
+    int n_aa;
+    double* ax;                  // n_aa: the iterate the next pass consumes
+    // Anderson mixing (aa_m > 0 only)
+    int aa_m;                    // history depth
+    double* ag;                  // n_aa: G(x) of this pass
+    double* axp;                 // n_aa: previous iterate
+    double* afp;                 // n_aa: previous residual G(x) - x
+    double* adX;                 // aa_m * n_aa: iterate differences (ring)
+    double* adF;                 // aa_m * n_aa: residual differences (ring)
+    double* agram;               // aa_m * aa_m Gram matrix of the adF columns, then aa_m |adX_j|^2
+    double* apart;               // per-block partial sums of the mixing kernels
+    int* actl;                   // 2 x 4 (by pass parity): stored columns, ring head, previous pass valid
 };
+
+constexpr int AA_MAX = 8;
 
 struct Item {
     int geom;    // index into the geometry array
@@ -100,13 +116,25 @@ struct PassParams {
 };
 
 // kernel launchers (kernels.hip)
-hipError_t launch_fourier(const GeomDev* geoms_dev, int n_geoms, int max_cells, double tol,
-                          int max_iter, hipStream_t st);
+// Fourier CG: init (x = 0, r = p = b), per iteration (parity = iteration & 1)
+// the direction / A p kernel and the x, r update, the count of geometries
+// still iterating, and the epilogue (mean-free T_F, pass inputs, kappa_F).
+// fx must hold fourier_scratch_doubles(ncells) doubles.
+constexpr size_t fourier_scratch_doubles(size_t ncells) { return 5 * ncells + 3 * 256 + 8; }
+hipError_t launch_fourier_init(const GeomDev* geoms_dev, int n_geoms, int max_cells, hipStream_t st);
+hipError_t launch_fourier_iter(const GeomDev* geoms_dev, int n_geoms, int max_cells, int parity, double tol,
+                               int max_iter, hipStream_t st);
+hipError_t launch_fourier_pending(const GeomDev* geoms_dev, int n_geoms, int* pending_dev, hipStream_t st);
+hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, hipStream_t st);
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
                              const Item* items_dev, int n_items, int waves, PassParams pp,
                              size_t lds_bytes, hipStream_t st);
 hipError_t launch_reduce_pass(const GeomDev* geoms_dev, int n_geoms, int max_cells, int max_walls,
                               PassParams pp, hipStream_t st);
+// Anderson mixing: per-block partials (up to 256 blocks of 256 threads per
+// geometry, 2 * AA_MAX + 3 sums each), then the combination.
+constexpr size_t aa_partial_doubles() { return 256 * (2 * AA_MAX + 3); }
+hipError_t launch_anderson(const GeomDev* geoms_dev, int n_geoms, int max_naa, PassParams pp, hipStream_t st);
 hipError_t launch_finalize(const GeomDev* geoms_dev, int n_geoms, PassParams pp, hipStream_t st);
 hipError_t launch_output(const GeomDev* geoms_dev, int n_geoms, double* T_L_out, double* J_out,
                          double* grad_out, hipStream_t st);

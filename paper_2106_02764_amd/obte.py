@@ -48,7 +48,7 @@ class obte_solve_opts(C.Structure):
                 ("waves_per_group", C.c_int), ("fourier_tol", C.c_double),
                 ("max_fourier", C.c_int), ("keep_state", C.c_int), ("recycle", C.c_int),
                 ("lag_wrap", C.c_int), ("inner_rtol", C.c_double), ("wrap_tol", C.c_double),
-                ("timing", C.c_int), ("stop_rule", C.c_int)]
+                ("timing", C.c_int), ("stop_rule", C.c_int), ("accel", C.c_int)]
 
 
 class obte_stats(C.Structure):

@@ -136,7 +136,7 @@ def test_full_adjoint_scaling_identity(P, full):
     assert abs(fd - float(np.dot(sig, grad))) <= 1e-6 * abs(base["kappa"]), (fd, float(np.dot(sig, grad)))
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("form", ["fp32", "fp64", "fp32_aa", "fp64_aa"])
 def test_bench_operating_points_replica(P, form):
     import bench
     w = gen.config5(nx=16, nz=4)

@@ -26,8 +26,9 @@ def _adj_case():
     return gen.small_2d(10, 9, solid=s, n_dir=8, n_mfp=3, sigma=rng.uniform(0.5, 2.0, 90))
 
 
+@pytest.mark.parametrize("accel", [0, 5])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_adjoint_vs_oracle(P, prec):
+def test_adjoint_vs_oracle(P, prec, accel):
     w = _adj_case()
     prob = Problem(w)
     fwd = source_iteration(prob, tol=1e-14, max_passes=20000)
@@ -36,7 +37,7 @@ def test_adjoint_vs_oracle(P, prec):
     s = P.Solver.from_workload(w)
     o = s.opts(precision=prec, outer_tol=1e-13 if prec == 0 else 1e-9,
                inner_tol=1e-14 if prec == 0 else 1e-7, fourier_tol=1e-14, keep_state=1,
-               max_outer=20000)
+               max_outer=20000, accel=accel)
     s.solve(o, sigma=w.sigma, want_T_L=False)
     g, st = s.adjoint(o)
     g = g.cpu().numpy()

@@ -74,7 +74,7 @@ def test_batch_fp32_vs_fp64(P, solvers, k64):
         assert rel.max() <= 1e-4, (lag, rtol, rel.max(), int(rel.argmax()))
 
 
-@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("form", ["fp32", "fp64", "fp32_aa", "fp64_aa"])
 def test_bench_operating_points_batch(P, solvers, form):
     import bench
     g = json.load(open(GOLD))

@@ -108,7 +108,7 @@ def test_cfg4_adjoint_vs_finite_differences(P):
 
 
 @pytest.mark.parametrize("name", ["cfg2", "cfg4"])
-@pytest.mark.parametrize("form", ["fp32", "fp64"])
+@pytest.mark.parametrize("form", ["fp32", "fp64", "fp32_aa", "fp64_aa"])
 def test_bench_operating_points_vs_oracle(P, name, form):
     """The operating points bench.py times (error-estimate stop rule at half
     the target) meet the 1e-4 target against the oracle."""
@@ -118,3 +118,34 @@ def test_bench_operating_points_vs_oracle(P, name, form):
     out = solve(P, w, **bench.OP[form])
     assert out["status"] == 0
     assert abs(out["kappa"] - g["kappa_cc"]) <= 1e-4 * g["kappa_cc"]
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg4"])
+def test_fp64_anderson_vs_oracle(P, name):
+    w = gen.config2() if name == "cfg2" else gen.config4()
+    g = golden(name)
+    out = solve(P, w, outer_tol=1e-11, inner_tol=1e-13, fourier_tol=1e-12, max_outer=3000, accel=6)
+    assert out["status"] == 0
+    assert out["outer_iters"] < g["passes"] // 2
+    assert abs(out["kappa"] - g["kappa_cc"]) <= 1e-9 * g["kappa_cc"]
+    assert abs(out["kappa_face"] - g["kappa_face"]) <= 1e-9 * g["kappa_face"]
+    T = out["T_L"][g["T_L_sample_cells"]]
+    ref = np.asarray(g["T_L_sample"])
+    assert np.max(np.abs(T - ref)) <= 1e-8 * max(1.0, np.abs(ref).max())
+
+
+def test_cfg4_adjoint_anderson_vs_plain(P):
+    """The mixed adjoint iteration reaches the plain one's gradient."""
+    w = gen.config4()
+    s = P.Solver.from_workload(w)
+    o = s.opts(outer_tol=1e-12, inner_tol=1e-14, fourier_tol=1e-13, keep_state=1, max_outer=3000,
+               accel=6)
+    s.solve(o, sigma=w.sigma, want_T_L=False)
+    ga, sta = s.adjoint(o)
+    o0 = s.opts(outer_tol=1e-12, inner_tol=1e-14, fourier_tol=1e-13, keep_state=1, max_outer=3000)
+    s.solve(o0, sigma=w.sigma, want_T_L=False)
+    gp, stp = s.adjoint(o0)
+    assert sta["status"] == 0 and stp["status"] == 0
+    assert sta["outer_iters"] < stp["outer_iters"]
+    ga, gp = ga.cpu().numpy(), gp.cpu().numpy()
+    assert np.linalg.norm(ga - gp) <= 1e-8 * np.linalg.norm(gp)

@@ -162,3 +162,23 @@ def test_workspace_too_small(P):
     with pytest.raises(P.ObteError) as e:
         P.obte.obte_solve(s.mesh, o, None, ws)
     assert e.value.status == P.obte.OBTE_ERR_NOMEM
+
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "channel", "sigma", "grad_y", "3d", "3d_membrane"])
+@pytest.mark.parametrize("accel", [3, 8])
+def test_converged_anderson(P, name, accel):
+    """Anderson mixing of the outer fixed point reaches the oracle's fixed
+    point (plain Algorithm 1 run far past the target) in fewer passes."""
+    w = CASES[name]()
+    prob = Problem(w)
+    ref = source_iteration(prob, tol=1e-13, max_passes=20000)
+    r = gpu_solve(P, w, outer_tol=1e-12, inner_tol=1e-14, fourier_tol=1e-14, max_inner=200,
+                  accel=accel)
+    assert r["status"] == 0
+    assert r["outer_iters"] <= ref["passes"]
+    assert abs(r["kappa"] - ref["kappa_cc"]) <= 1e-10 * abs(ref["kappa_cc"])
+    assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
+    Jref = np.zeros((w.n_cells, w.ndim))
+    Jref[prob.mesh.cells] = ref["J"]
+    assert rel(r["J"], Jref) < 1e-9
