@@ -50,7 +50,7 @@ typedef enum {
  * periodic plane obeys T(x + L) = T(x) - dT_ext.
  * GPU-path limits: ndim 2 or 3; periodic[0] and periodic[1] may be 0 or 1,
  * periodic[2] must be 0 in 3D; n[0] <= 256; in 3D n[2] <= 128, and a solve
- * rejects meshes whose per-wave LDS rows (1 + 2 ndim reduction rows of ceil(n[0]/64) * 64
+ * rejects meshes whose per-wave LDS rows (2 (1 + 2 ndim) reduction rows of ceil(n[0]/64) * 64
  * doubles plus, in 3D, n[2] rows in the compute type) exceed 64 KiB; grad_axis 0/1. */
 typedef struct {
     int ndim;
@@ -181,6 +181,13 @@ obte_status obte_material_set(obte_mesh* mesh, const obte_material_desc* mat);
 obte_status obte_workspace_size(const obte_mesh* mesh, const obte_solve_opts* opts,
                                 size_t* bytes);
 
+/* Bytes of device workspace obte_solve_batch needs for these meshes under
+ * `opts` (the systems per workgroup of a batch follow its widest mesh, so this
+ * can exceed the sum of the single-mesh sizes).  meshes: host array of n
+ * handles with their material set. */
+obte_status obte_workspace_size_batch(const obte_mesh* const* meshes, int n,
+                                      const obte_solve_opts* opts, size_t* bytes);
+
 /* Source iteration to convergence (paper Algorithm 1).
  * sigma_dev: device, n_cells doubles (pore entries ignored), NULL => 1.
  * workspace_dev: device, 256-byte aligned, workspace_bytes >= obte_workspace_size
@@ -196,10 +203,9 @@ obte_status obte_solve(obte_mesh* mesh, const obte_solve_opts* opts, const doubl
                        double* J_dev, obte_stats* stats);
 
 /* Many independent geometries in one persistent launch per pass.  meshes[i]
- * and sigma_dev[i] (nullable entries) as above; one workspace holds all; the
- * needed size is the sum of obte_workspace_size over the meshes (each part
- * rounded up to 256 bytes); all meshes must share the number of MFPs unless
- * waves_per_group is set.  kappa_out: host, n doubles (kappa_cc).  stats: host,
+ * and sigma_dev[i] (nullable entries) as above; one workspace holds all, of
+ * at least obte_workspace_size_batch bytes (OBTE_ERR_NOMEM otherwise); all
+ * meshes must share the number of MFPs unless waves_per_group is set.  kappa_out: host, n doubles (kappa_cc).  stats: host,
  * n entries. */
 obte_status obte_solve_batch(obte_mesh* const* meshes, int n, const obte_solve_opts* opts,
                              const double* const* sigma_dev, void* workspace_dev,

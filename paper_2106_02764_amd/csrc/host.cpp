@@ -329,11 +329,10 @@ struct Run {
     }
 };
 
-obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_opts* o,
-                      char* ws, std::vector<size_t>* offsets) {
-    R.meshes.assign(meshes, meshes + n);
-    R.precision = o->precision;
-    R.accel = o->accel;
+// Systems per workgroup of a launch over these meshes, and the LDS each of
+// its waves needs (the same rule for the workspace size and the solve).
+obte_status resolve_waves(const obte_mesh* const* meshes, int n, const obte_solve_opts* o, int* W_out,
+                          size_t* per_wave_out) {
     int W = o->waves_per_group;
     if (W == 0) {
         W = auto_waves(meshes[0]);
@@ -346,8 +345,9 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         int cpl = 1, nzm = 1;
         for (int i = 0; i < n; ++i) { cpl = std::max(cpl, (meshes[i]->nx + 63) / 64); nzm = std::max(nzm, meshes[i]->nz); }
         const int nd = nzm > 1 ? 3 : 2;
-        // reduction rows, plus in 3D one row per z-plane in the compute type
-        per_wave = (size_t)red_rows(nd) * 64 * cpl * sizeof(double);
+        // reduction rows (double buffered), plus in 3D one row per z-plane in
+        // the compute type
+        per_wave = 2 * (size_t)red_rows(nd) * 64 * cpl * sizeof(double);
         if (nzm > 1) per_wave += (size_t)nzm * 64 * cpl * (o->precision == OBTE_FP32 ? 4 : 8);
         const size_t cap = 64 * 1024;
         if (per_wave > cap)
@@ -359,6 +359,20 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         }
         if (nzm > 1 && o->recycle > 0) return fail(OBTE_ERR_ARG, "recycle is not available for 3D meshes");
     }
+    *W_out = W;
+    *per_wave_out = per_wave;
+    return OBTE_OK;
+}
+
+obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_opts* o,
+                      char* ws, std::vector<size_t>* offsets) {
+    R.meshes.assign(meshes, meshes + n);
+    R.precision = o->precision;
+    R.accel = o->accel;
+    int W = 0;
+    size_t per_wave = 0;
+    obte_status s = resolve_waves(meshes, n, o, &W, &per_wave);
+    if (s != OBTE_OK) return s;
     R.waves = W;
     size_t off = 0;
     for (int gi = 0; gi < n; ++gi) {
@@ -874,12 +888,25 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
 }
 
 obte_status obte_workspace_size(const obte_mesh* m, const obte_solve_opts* o, size_t* bytes) {
-    if (!m || !bytes) return fail(OBTE_ERR_ARG, "NULL argument");
+    return obte_workspace_size_batch(&m, 1, o, bytes);
+}
+
+obte_status obte_workspace_size_batch(const obte_mesh* const* meshes, int n, const obte_solve_opts* o,
+                                      size_t* bytes) {
+    if (!meshes || n < 1 || !bytes) return fail(OBTE_ERR_ARG, "NULL argument or no meshes");
     obte_status s = check_opts(o);
     if (s != OBTE_OK) return s;
-    if (!m->has_material) return fail(OBTE_ERR_STATE, "material not set");
-    int W = o->waves_per_group ? o->waves_per_group : auto_waves(m);
-    *bytes = align256(make_layout(m, o, W).total);
+    for (int i = 0; i < n; ++i) {
+        if (!meshes[i]) return fail(OBTE_ERR_ARG, "mesh %d is NULL", i);
+        if (!meshes[i]->has_material) return fail(OBTE_ERR_STATE, "material not set on mesh %d", i);
+    }
+    int W = 0;
+    size_t per_wave = 0;
+    s = resolve_waves(meshes, n, o, &W, &per_wave);
+    if (s != OBTE_OK) return s;
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) total += align256(make_layout(meshes[i], o, W).total);
+    *bytes = total;
     return OBTE_OK;
 }
 

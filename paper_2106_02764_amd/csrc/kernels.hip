@@ -356,9 +356,12 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         const int iy = s.pos[1] ? jj : ny - 1 - jj;
         const int iz = D3 ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
         const int rowbase = nx * (iy + ny * iz);
-        double* buf = rd->lds;
         const int ROW = rd->ROW, W = rd->W;
         constexpr int NV = 1 + 2 * ND;
+        // the slots are double buffered by row parity: a wave writes this
+        // buffer again two rows later, after the next row's barrier, which
+        // every wave reaches only once it has combined this row
+        double* buf = rd->lds + (size_t)((jj * (D3 ? g.nz : 1) + kk) & 1) * W * NV * ROW;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int p = lane * CPL + c;
@@ -438,7 +441,6 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                 if (dst) *dst = ADD ? *dst + sum : sum;
             }
         }
-        lds_barrier();
     }
 }
 
@@ -476,18 +478,23 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     rows.ROW = WAVE * CPL;
     const int ny = g.ny;
     if (!D3) {
-        RowIn<T, CPL> b0, b1, b2;
+        // four buffers: the loads of row jj + 3 are issued before row jj runs
+        RowIn<T, CPL> b0, b1, b2, b3;
         load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 0, 0, b0);
         if (ny > 1) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 1, 0, b1);
-        for (int jj = 0; jj < ny; jj += 3) {
-            if (jj + 2 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 2, 0, b2);
+        if (ny > 2) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 2, 0, b2);
+        for (int jj = 0; jj < ny; jj += 4) {
+            if (jj + 3 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 3, 0, b3);
             row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, 0, b0, rows, io, mb, wo, rd);
             if (jj + 1 >= ny) break;
-            if (jj + 3 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 3, 0, b0);
+            if (jj + 4 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 4, 0, b0);
             row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 1, 0, b1, rows, io, mb, wo, rd);
             if (jj + 2 >= ny) break;
-            if (jj + 4 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 4, 0, b1);
+            if (jj + 5 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 5, 0, b1);
             row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 2, 0, b2, rows, io, mb, wo, rd);
+            if (jj + 3 >= ny) break;
+            if (jj + 6 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 6, 0, b2);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 3, 0, b3, rows, io, mb, wo, rd);
         }
     } else {
         // 3D: rows (jj, kk) with kk inner; a three-buffer rotation keeps the
@@ -850,7 +857,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass3(const GeomDev* __restrict__
     T* du = K + (size_t)KV_DU * nw;
     // per-wave LDS: the reduction rows, then nz rows of this wave
     constexpr int NVR = red_rows(3);
-    T* zrows = reinterpret_cast<T*>(lds + (size_t)W * NVR * WAVE * CPL) + (size_t)w * nz * WAVE * CPL;
+    T* zrows = reinterpret_cast<T*>(lds + (size_t)2 * W * NVR * WAVE * CPL) + (size_t)w * nz * WAVE * CPL;
     Red rd;
     rd.lds = lds;
     rd.w = w;
@@ -1238,6 +1245,7 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_partial(const GeomDev* __rest
 
 __global__ void __launch_bounds__(AA_THREADS) k_aa_apply(const GeomDev* __restrict__ geoms, PassParams pp) {
     __shared__ double tot[AA_NP];
+    __shared__ double wred[AA_NP][AA_THREADS / 64];
     __shared__ double gam[AA_MAX];
     const GeomDev& g = geoms[blockIdx.y];
     if (g.aa_m <= 0 || g.ctrl[CTRL_DONE]) return;
@@ -1251,82 +1259,119 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_apply(const GeomDev* __restri
     const int cnt = ac[0], head = ac[1], have = ac[2];
     const int slot = head;
     const int cnt1 = have ? min(cnt + 1, M) : cnt;
-    // fixed-order sums of the per-block partials
-    if (threadIdx.x < AA_NP) {
-        double t = 0.0;
-        for (int b = 0; b < v.B; ++b) t += g.apart[(size_t)b * AA_NP + threadIdx.x];
-        tot[threadIdx.x] = t;
+    // fixed-order sums of the per-block partials: thread b holds block b's
+    // row (B <= blockDim), a butterfly per wave, then the waves in order
+    {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        const bool mine = (int)threadIdx.x < v.B;
+        const double* row = g.apart + (size_t)threadIdx.x * AA_NP;
+        for (int q = 0; q < AA_NP; ++q) {
+            const double t = wave_sum(mine ? row[q] : 0.0);
+            if (lane == 0) wred[q][wid] = t;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < AA_NP) {
+            double t = 0.0;
+            for (int w = 0; w < nw; ++w) t += wred[threadIdx.x][w];
+            tot[threadIdx.x] = t;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x == 0) {
+        // every loop below runs over the fixed AA_MAX so the small matrices
+        // stay in registers; columns beyond cnt1 are identity rows
         const double* dxg = g.agram + M * M;            // |dX_j|^2 of the stored columns
         // this pass's Gram matrix: the new column's row from the partials,
         // the rest from the stored matrix (block 0 stores the new row)
-        double G[AA_MAX][AA_MAX], dxn[AA_MAX], b[AA_MAX], d[AA_MAX];
-        for (int j = 0; j < cnt1; ++j) {
-            for (int k2 = 0; k2 < cnt1; ++k2) {
-                const bool fresh = have && (j == slot || k2 == slot);
-                G[j][k2] = fresh ? tot[j == slot ? k2 : j] : g.agram[j * M + k2];
+        double G[AA_MAX][AA_MAX], dxn[AA_MAX], b[AA_MAX], d[AA_MAX], y[AA_MAX];
+#pragma unroll
+        for (int j = 0; j < AA_MAX; ++j) {
+            const bool aj = j < cnt1;
+#pragma unroll
+            for (int k2 = 0; k2 < AA_MAX; ++k2) {
+                double val = (j == k2) ? 1.0 : 0.0;
+                if (aj && k2 < cnt1) {
+                    const bool fresh = have && (j == slot || k2 == slot);
+                    val = fresh ? tot[j == slot ? k2 : j] : g.agram[j * M + k2];
+                }
+                G[j][k2] = val;
             }
-            dxn[j] = (have && j == slot) ? tot[2 * AA_MAX + 2] : dxg[j];
-            b[j] = tot[AA_MAX + j];
+            dxn[j] = aj ? ((have && j == slot) ? tot[2 * AA_MAX + 2] : dxg[j]) : 0.0;
+            b[j] = aj ? tot[AA_MAX + j] : 0.0;
         }
         if (blockIdx.x == 0 && have) {
-            for (int j = 0; j < cnt1; ++j) {
-                g.agram[slot * M + j] = G[slot][j];
-                g.agram[j * M + slot] = G[slot][j];
-            }
-            g.agram[M * M + slot] = dxn[slot];
+#pragma unroll
+            for (int j = 0; j < AA_MAX; ++j)
+                if (j < cnt1) {
+                    const double val = tot[j];          // new column against column j
+                    g.agram[slot * M + j] = val;
+                    g.agram[j * M + slot] = val;
+                }
+            g.agram[M * M + slot] = tot[2 * AA_MAX + 2];
         }
         // error estimate for the stop test: with f = (G - I) e for a linear G,
         // |e| <= |f| / s_min(I - G); s_min is estimated by the smallest
         // |dF_j| / |dX_j| over the stored columns (no columns: |f| itself)
         double smin = 1.0;
-        for (int j = 0; j < cnt1; ++j)
-            if (dxn[j] > 0.0) smin = fmin(smin, sqrt(G[j][j] / dxn[j]));
+#pragma unroll
+        for (int j = 0; j < AA_MAX; ++j)
+            if (j < cnt1 && dxn[j] > 0.0) smin = fmin(smin, sqrt(G[j][j] / dxn[j]));
         smin = fmax(smin, 1e-3);
         const double sf = tot[2 * AA_MAX], sx = tot[2 * AA_MAX + 1];
         const double res = sx > 0.0 ? sqrt(sf / sx) : (sf > 0.0 ? INFINITY : 0.0);
         if (blockIdx.x == 0) g.fscal[3] = res / smin;
         // scaled normal equations with a small ridge, Cholesky in place
         bool ok = cnt1 > 0;
-        for (int j = 0; j < cnt1 && ok; ++j) {
-            d[j] = sqrt(G[j][j]);
-            ok = d[j] > 0.0 && isfinite(d[j]);
+#pragma unroll
+        for (int j = 0; j < AA_MAX; ++j) {
+            d[j] = j < cnt1 ? sqrt(G[j][j]) : 1.0;
+            ok = ok && d[j] > 0.0 && isfinite(d[j]);
         }
-        for (int j = 0; j < cnt1 && ok; ++j)
-            for (int k2 = 0; k2 < cnt1; ++k2) G[j][k2] = G[j][k2] / (d[j] * d[k2]) + (j == k2 ? 1e-10 : 0.0);
-        for (int j = 0; j < cnt1 && ok; ++j) {
-            double s2 = G[j][j];
-            for (int k2 = 0; k2 < j; ++k2) s2 -= G[j][k2] * G[j][k2];
-            if (!(s2 > 1e-14)) { ok = false; break; }
-            G[j][j] = sqrt(s2);
-            for (int r = j + 1; r < cnt1; ++r) {
-                double t = G[r][j];
-                for (int k2 = 0; k2 < j; ++k2) t -= G[r][k2] * G[j][k2];
-                G[r][j] = t / G[j][j];
-            }
-        }
-        double y[AA_MAX];
         if (ok) {
-            for (int j = 0; j < cnt1; ++j) {
+#pragma unroll
+            for (int j = 0; j < AA_MAX; ++j)
+#pragma unroll
+                for (int k2 = 0; k2 < AA_MAX; ++k2)
+                    G[j][k2] = G[j][k2] / (d[j] * d[k2]) + ((j == k2 && j < cnt1) ? 1e-10 : 0.0);
+#pragma unroll
+            for (int j = 0; j < AA_MAX; ++j) {
+                double s2 = G[j][j];
+#pragma unroll
+                for (int k2 = 0; k2 < j; ++k2) s2 -= G[j][k2] * G[j][k2];
+                ok = ok && s2 > 1e-14;
+                const double ljj = sqrt(fmax(s2, 1e-300));
+                G[j][j] = ljj;
+#pragma unroll
+                for (int r = j + 1; r < AA_MAX; ++r) {
+                    double t = G[r][j];
+#pragma unroll
+                    for (int k2 = 0; k2 < j; ++k2) t -= G[r][k2] * G[j][k2];
+                    G[r][j] = t / ljj;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < AA_MAX; ++j) {
                 double t = b[j] / d[j];
+#pragma unroll
                 for (int k2 = 0; k2 < j; ++k2) t -= G[j][k2] * y[k2];
                 y[j] = t / G[j][j];
             }
-            for (int j = cnt1 - 1; j >= 0; --j) {
+#pragma unroll
+            for (int j = AA_MAX - 1; j >= 0; --j) {
                 double t = y[j];
-                for (int k2 = j + 1; k2 < cnt1; ++k2) t -= G[k2][j] * y[k2];
+#pragma unroll
+                for (int k2 = j + 1; k2 < AA_MAX; ++k2) t -= G[k2][j] * y[k2];
                 y[j] = t / G[j][j];
             }
-            for (int j = 0; j < cnt1; ++j) {
-                gam[j] = y[j] / d[j];
-                ok = ok && isfinite(gam[j]);
+#pragma unroll
+            for (int j = 0; j < AA_MAX; ++j) {
+                const double gj = j < cnt1 ? y[j] / d[j] : 0.0;
+                ok = ok && isfinite(gj);
+                y[j] = gj;
             }
         }
-        if (!ok)
-            for (int j = 0; j < AA_MAX; ++j) gam[j] = 0.0;
-        for (int j = ok ? cnt1 : 0; j < AA_MAX; ++j) gam[j] = 0.0;
+#pragma unroll
+        for (int j = 0; j < AA_MAX; ++j) gam[j] = ok ? y[j] : 0.0;
         if (blockIdx.x == 0) {
             int* ao = g.actl + 4 * out;
             if (ok || cnt1 == 0) {

@@ -68,6 +68,8 @@ EXPORTS = {
     "obte_mesh_create": (C.c_int, [C.POINTER(obte_mesh_desc), C.POINTER(C.c_void_p)]),
     "obte_material_set": (C.c_int, [C.c_void_p, C.POINTER(obte_material_desc)]),
     "obte_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.POINTER(C.c_size_t)]),
+    "obte_workspace_size_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(obte_solve_opts),
+                                            C.POINTER(C.c_size_t)]),
     "obte_solve": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.c_void_p, C.c_void_p,
                              C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(obte_stats)]),
     "obte_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(obte_solve_opts),
@@ -176,6 +178,13 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return C.c_void_p(stream.cuda_stream)
+
+
+def obte_workspace_size_batch(meshes, opts):
+    n = C.c_size_t()
+    arr = (C.c_void_p * len(meshes))(*[m.value for m in meshes])
+    _check(lib().obte_workspace_size_batch(arr, len(meshes), C.byref(opts), C.byref(n)))
+    return n.value
 
 
 def obte_solve(mesh, opts, sigma, workspace, stream=None, T_L=None, J=None, raise_not_converged=False):

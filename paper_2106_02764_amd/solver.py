@@ -132,8 +132,8 @@ class KappaEff(torch.autograd.Function):
 
 def solve_batch(solvers, opts, sigmas=None, device="cuda"):
     """All geometries in one launch per pass; returns (kappas, stats dicts)."""
-    sizes = [_o.obte_workspace_size(s.mesh, opts) for s in solvers]
-    ws = torch.empty(sum(sizes), dtype=torch.uint8, device=device)
+    nbytes = _o.obte_workspace_size_batch([s.mesh for s in solvers], opts)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
     sg = [None] * len(solvers) if sigmas is None else [s.sigma_tensor(x) for s, x in zip(solvers, sigmas)]
     stream = solvers[0].stream
     stream.wait_stream(torch.cuda.current_stream())
