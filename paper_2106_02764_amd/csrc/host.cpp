@@ -119,7 +119,7 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.Tw = take(2 * nw * 8);
     L.T_L = take(nc * 8);
     L.part_TL = take(n_items * nc * 8);
-    L.part_Tw = take(n_items * nw * 8);
+    L.part_Tw = take(n_items * (size_t)m->ndim * nc * 8);
     L.part_J = take(n_items * nc * m->ndim * 8);
     L.ksys = take((size_t)m->n_sys * 8);
     L.kfsys = take((size_t)m->n_sys * 8);

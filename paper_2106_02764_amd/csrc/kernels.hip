@@ -114,10 +114,6 @@ __device__ __forceinline__ SysC<T> make_sys(const GeomDev& g, int m, int l, int 
     return s;
 }
 
-// a[i] for a small array and a runtime index without forcing it to memory
-template <typename T>
-__device__ __forceinline__ T pick3(const T (&a)[3], int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
-
 template <typename T>
 __device__ __forceinline__ const T* sigma_ptr(const GeomDev& g);
 template <>
@@ -362,6 +358,17 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         // buffer again two rows later, after the next row's barrier, which
         // every wave reaches only once it has combined this row
         double* buf = rd->lds + (size_t)((jj * (D3 ? g.nz : 1) + kk) & 1) * W * NV * ROW;
+        // the cells this wave combines after the barrier: a contiguous share
+        // of the row (their face words are loaded now, ahead of the barrier)
+        const int CH = (ROW + W - 1) / W;
+        const int pbeg = rd->w * CH, pend = min(nx, pbeg + CH);
+        uint32_t fcc[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int p = pbeg + lane + WAVE * c;
+            fcc[c] = p < pend ? (uint32_t)vw.fc[rowbase + (s.pos[0] ? p : nx - 1 - p)] : 0u;
+        }
+        bool wall_here = false;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int p = lane * CPL + c;
@@ -369,7 +376,6 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
             const bool sol = p < nx && active && fc_solid(wv);
             const double xv = sol ? (double)xrow[c] : 0.0;
             double* slot = buf + (size_t)(rd->w * NV) * ROW + p;
-            double tw[3] = {0.0, 0.0, 0.0};
             double gp = 0.0;
             if (sol) {
                 const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
@@ -392,16 +398,18 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                     if (g.grad_axis == 1 && jj == ny - 1 && fc_class(wv, s.fout[1]) != FC_WALL)
                         rd->kface += xv + ((!ADD && s.pos[1]) ? g.dT : 0.0);
                 }
-#pragma unroll
-                for (int ax = 0; ax < ND; ++ax)
-                    if (fc_class(wv, s.fout[ax]) == FC_WALL) tw[ax] = (adj ? s.cd[ax] : wo[ax]) * xv;
                 if (rd->store_T) g.Tstore[(size_t)s.sys * g.ncells + cell] = xv;
             }
             slot[0] = adj ? xv : s.Dml * xv;
-            // wall slots are read back only at cells with an outgoing wall face
+            // wall slots exist where the geometry sends this direction into a
+            // wall (every wave of the block writes them, 0 when inactive)
 #pragma unroll
-            for (int ax = 0; ax < ND; ++ax)
-                if (fc_class(wv, s.fout[ax]) == FC_WALL) slot[(size_t)(1 + ax) * ROW] = tw[ax];
+            for (int ax = 0; ax < ND; ++ax) {
+                if (p < nx && fc_solid(wv) && fc_class(wv, s.fout[ax]) == FC_WALL) {
+                    slot[(size_t)(1 + ax) * ROW] = (adj ? s.cd[ax] : wo[ax]) * xv;
+                    wall_here = true;
+                }
+            }
             if (adj) {
                 slot[(size_t)(1 + ND) * ROW] = gp;
             } else if (rd->want_J) {
@@ -409,36 +417,43 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                 for (int ax = 0; ax < ND; ++ax) slot[(size_t)(1 + ND + ax) * ROW] = s.S[ax] * xv;
             }
         }
+        // the same in every wave of the block (geometry and direction only)
+        const bool wall_row = __any(wall_here);
         lds_barrier();
-        // wave w combines the values v = w, w + W, ... for the cells its lanes
-        // own; the face words are already in registers
-        const int nvu = 1 + ND + (adj ? 1 : (rd->want_J ? ND : 0));
-        for (int v = rd->w; v < nvu; v += W) {
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int p = lane * CPL + c;
-                if (p >= nx) continue;
-                const uint32_t wv = cur.w[c];
-                // wall values exist only where this direction leaves through a wall
-                if (v >= 1 && v <= ND && !(fc_solid(wv) && fc_class(wv, pick3(s.fout, v - 1)) == FC_WALL))
-                    continue;
-                double sum = 0.0;
-                for (int ww = 0; ww < W; ++ww) sum += buf[(size_t)(ww * NV + v) * ROW + p];
-                const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
-                double* dst = nullptr;
-                if (v == 0) {
-                    dst = &g.part_TL[(size_t)rd->local * g.ncells + cell];
-                    if (!fc_solid(wv)) sum = 0.0;
-                } else if (v <= ND) {
-                    const int fo = pick3(s.fout, v - 1);
-                    if (fc_solid(wv) && fc_class(wv, fo) == FC_WALL)
-                        dst = &g.part_Tw[(size_t)rd->local * g.nwalls + g.wall_idx[cell * g.nf + fo]];
-                } else if (adj) {
-                    dst = &g.part_G[(size_t)rd->local * g.ncells + cell];
-                } else {
-                    dst = &g.part_J[((size_t)rd->local * g.ncells + cell) * ND + (v - 1 - ND)];
+        for (int c = 0; c < CPL; ++c) {
+            const int p = pbeg + lane + WAVE * c;
+            if (p >= pend) continue;
+            const uint32_t wv = fcc[c];
+            const bool sol = fc_solid(wv);
+            const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
+            double sum = 0.0;
+            for (int ww = 0; ww < W; ++ww) sum += buf[(size_t)(ww * NV) * ROW + p];
+            double* dst = &g.part_TL[(size_t)rd->local * g.ncells + cell];
+            *dst = ADD ? *dst + sum : (sol ? sum : 0.0);
+            if (wall_row && sol) {
+#pragma unroll
+                for (int ax = 0; ax < ND; ++ax) {
+                    if (fc_class(wv, s.fout[ax]) != FC_WALL) continue;
+                    double sw = 0.0;
+                    for (int ww = 0; ww < W; ++ww) sw += buf[(size_t)(ww * NV + 1 + ax) * ROW + p];
+                    double* dw = &g.part_Tw[((size_t)rd->local * ND + ax) * g.ncells + cell];
+                    *dw = ADD ? *dw + sw : sw;
                 }
-                if (dst) *dst = ADD ? *dst + sum : sum;
+            }
+            if (adj) {
+                double sg = 0.0;
+                for (int ww = 0; ww < W; ++ww) sg += buf[(size_t)(ww * NV + 1 + ND) * ROW + p];
+                double* dg = &g.part_G[(size_t)rd->local * g.ncells + cell];
+                *dg = ADD ? *dg + sg : sg;
+            } else if (rd->want_J) {
+#pragma unroll
+                for (int ax = 0; ax < ND; ++ax) {
+                    double sj = 0.0;
+                    for (int ww = 0; ww < W; ++ww) sj += buf[(size_t)(ww * NV + 1 + ND + ax) * ROW + p];
+                    double* dj = &g.part_J[((size_t)rd->local * g.ncells + cell) * ND + ax];
+                    *dj = ADD ? *dj + sj : sj;
+                }
             }
         }
     }
@@ -1065,10 +1080,12 @@ __global__ void __launch_bounds__(256) k_reduce_pass(const GeomDev* __restrict__
         const int ax = f >> 1;
         const double nsgn = (f & 1) ? 1.0 : -1.0;
         double a = 0.0;
+        const int cell = g.wall_cell[wi];
         for (int i = lane; i < g.n_items; i += 64) {
             const int l = i / g.n_grp;          // items are ordered (l, MFP group)
             const double sn = g.dirs[l * 3 + ax] * nsgn;
-            if ((!adj && sn > 0.0) || (adj && sn < 0.0)) a += g.part_Tw[(size_t)i * g.nwalls + wi];
+            if ((!adj && sn > 0.0) || (adj && sn < 0.0))
+                a += g.part_Tw[((size_t)i * g.ndim + ax) * g.ncells + cell];
         }
         a = wave_sum(a);
         if (lane == 0) {

@@ -51,7 +51,7 @@ struct GeomDev {
     void* U;                     // n_sys * nwrap (compute precision): wrap inflow vectors
     void* kry;                   // 3D: n_sys * 11 * nwrap (compute precision): wrap-plane Krylov vectors
     double* part_TL;             // n_items * ncells
-    double* part_Tw;             // n_items * nwalls
+    double* part_Tw;             // n_items * ndim * ncells: wall partial at (item, axis of the wall face, cell)
     double* part_J;              // n_items * ncells * ndim
     double* ksys;                // n_sys: kappa_cc contribution of each system
     double* kfsys;               // n_sys: kappa_face contribution
