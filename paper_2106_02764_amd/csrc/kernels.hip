@@ -174,14 +174,34 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Reduction state of a lockstep sweep.
+// Reduction state of a lockstep sweep.  The output pointers are copied here
+// once: kept in registers, they are not reloaded after every barrier.
 struct Red {
-    double* lds;      // W * NV * ROW doubles
+    double* lds;      // 2 * W * NV * ROW doubles
     int w, W, ROW;
     int local;        // item index within the geometry
     int want_J, store_T;
     double kacc, kface;
+    double *pTL, *pTw, *pG, *pJ;   // this item's partial rows
+    int ncells;
 };
+
+constexpr int WMAX = 8;     // systems per workgroup, at most
+
+// Fixed-order sum of the W slot values at v (loaded together, then added;
+// the index is clamped so every load stays inside the block's slots).
+__device__ __forceinline__ double slot_sum(const double* buf, int W, int NV, int ROW, int v, int p) {
+    double t[WMAX];
+#pragma unroll
+    for (int ww = 0; ww < WMAX; ++ww) {
+        const double val = buf[(size_t)((ww < W ? ww : 0) * NV + v) * ROW + p];
+        t[ww] = ww < W ? val : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < WMAX; ++ww) s += t[ww];
+    return s;
+}
 
 // Loads through these views compile to global (not flat) loads, which keep
 // only the vector-memory counter pending while the row computes.
@@ -427,31 +447,27 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
             const uint32_t wv = fcc[c];
             const bool sol = fc_solid(wv);
             const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
-            double sum = 0.0;
-            for (int ww = 0; ww < W; ++ww) sum += buf[(size_t)(ww * NV) * ROW + p];
-            double* dst = &g.part_TL[(size_t)rd->local * g.ncells + cell];
+            const double sum = slot_sum(buf, W, NV, ROW, 0, p);
+            double* dst = rd->pTL + cell;
             *dst = ADD ? *dst + sum : (sol ? sum : 0.0);
             if (wall_row && sol) {
 #pragma unroll
                 for (int ax = 0; ax < ND; ++ax) {
                     if (fc_class(wv, s.fout[ax]) != FC_WALL) continue;
-                    double sw = 0.0;
-                    for (int ww = 0; ww < W; ++ww) sw += buf[(size_t)(ww * NV + 1 + ax) * ROW + p];
-                    double* dw = &g.part_Tw[((size_t)rd->local * ND + ax) * g.ncells + cell];
+                    const double sw = slot_sum(buf, W, NV, ROW, 1 + ax, p);
+                    double* dw = rd->pTw + (size_t)ax * rd->ncells + cell;
                     *dw = ADD ? *dw + sw : sw;
                 }
             }
             if (adj) {
-                double sg = 0.0;
-                for (int ww = 0; ww < W; ++ww) sg += buf[(size_t)(ww * NV + 1 + ND) * ROW + p];
-                double* dg = &g.part_G[(size_t)rd->local * g.ncells + cell];
+                const double sg = slot_sum(buf, W, NV, ROW, 1 + ND, p);
+                double* dg = rd->pG + cell;
                 *dg = ADD ? *dg + sg : sg;
             } else if (rd->want_J) {
 #pragma unroll
                 for (int ax = 0; ax < ND; ++ax) {
-                    double sj = 0.0;
-                    for (int ww = 0; ww < W; ++ww) sj += buf[(size_t)(ww * NV + 1 + ND + ax) * ROW + p];
-                    double* dj = &g.part_J[((size_t)rd->local * g.ncells + cell) * ND + ax];
+                    const double sj = slot_sum(buf, W, NV, ROW, 1 + ND + ax, p);
+                    double* dj = rd->pJ + (size_t)cell * ND + ax;
                     *dj = ADD ? *dj + sj : sj;
                 }
             }
@@ -718,6 +734,11 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     rd.store_T = pp.store_T;
     rd.kacc = 0.0;
     rd.kface = 0.0;
+    rd.ncells = g.ncells;
+    rd.pTL = g.part_TL + (size_t)item.local * g.ncells;
+    rd.pTw = g.part_Tw + (size_t)item.local * g.ndim * g.ncells;
+    rd.pG = g.part_G + (size_t)item.local * g.ncells;
+    rd.pJ = g.part_J + (size_t)item.local * g.ncells * g.ndim;
     // ---- phase A
     {
         RegIO<T, CPL> io{u[0], xl[0]};
@@ -883,6 +904,11 @@ __global__ void __launch_bounds__(512) k_sweep_pass3(const GeomDev* __restrict__
     rd.store_T = pp.store_T;
     rd.kacc = 0.0;
     rd.kface = 0.0;
+    rd.ncells = g.ncells;
+    rd.pTL = g.part_TL + (size_t)item.local * g.ncells;
+    rd.pTw = g.part_Tw + (size_t)item.local * g.ndim * g.ncells;
+    rd.pG = g.part_G + (size_t)item.local * g.ncells;
+    rd.pJ = g.part_J + (size_t)item.local * g.ncells * g.ndim;
     // ---- phase A
     {
         GlobIO<T, CPL> io{U, xl, nx, active};
