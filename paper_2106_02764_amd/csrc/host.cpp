@@ -320,7 +320,8 @@ struct Run {
     Item* d_items = nullptr;
     int* d_pending = nullptr;     // geometries whose Fourier CG still iterates
     int waves = 4, cpl = 1, nzmax = 1, precision = 0, accel = 0;
-    size_t lds = 0;
+    size_t lds = 0;               // the largest any launch of this run needs
+    size_t lds_for[2][2] = {};    // [adjoint][want_J]
     int max_cells = 0, max_walls = 0;
     ~Run() {
         if (d_views) soft(hipFree(d_views), "hipFree(views)");
@@ -345,9 +346,9 @@ obte_status resolve_waves(const obte_mesh* const* meshes, int n, const obte_solv
         int cpl = 1, nzm = 1;
         for (int i = 0; i < n; ++i) { cpl = std::max(cpl, (meshes[i]->nx + 63) / 64); nzm = std::max(nzm, meshes[i]->nz); }
         const int nd = nzm > 1 ? 3 : 2;
-        // reduction rows (double buffered), plus in 3D one row per z-plane in
-        // the compute type
-        per_wave = 2 * (size_t)red_rows(nd) * 64 * cpl * sizeof(double);
+        // reduction rows (double buffered; the largest set, the flux replay),
+        // plus in 3D one row per z-plane in the compute type
+        per_wave = 2 * (size_t)red_rows(nd, 0, 1) * 64 * cpl * sizeof(double);
         if (nzm > 1) per_wave += (size_t)nzm * 64 * cpl * (o->precision == OBTE_FP32 ? 4 : 8);
         const size_t cap = 64 * 1024;
         if (per_wave > cap)
@@ -403,6 +404,15 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
             return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
     R.lds = (size_t)W * per_wave;
+    {
+        // launches size their LDS for the slot rows they use
+        const int nd = R.nzmax > 1 ? 3 : 2;
+        const size_t row = 64 * (size_t)R.cpl;
+        const size_t zr = R.nzmax > 1 ? (size_t)R.nzmax * row * (o->precision == OBTE_FP32 ? 4 : 8) : 0;
+        for (int a = 0; a < 2; ++a)
+            for (int j = 0; j < 2; ++j)
+                R.lds_for[a][j] = (size_t)W * (2 * (size_t)red_rows(nd, a, j) * row * sizeof(double) + zr);
+    }
     HIPCHK(hipMalloc((void**)&R.d_views, R.views.size() * sizeof(GeomDev)));
     HIPCHK(hipMalloc((void**)&R.d_items, R.items.size() * sizeof(Item)));
     HIPCHK(hipMalloc((void**)&R.d_pending, sizeof(int)));
@@ -414,7 +424,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
 obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Timer* tm, int k) {
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k], st));
     HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items, (int)R.items.size(),
-                             R.waves, pp, R.lds, st));
+                             R.waves, pp, R.lds_for[pp.adjoint ? 1 : 0][pp.want_J ? 1 : 0], st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 1], st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 2], st));
     HIPCHK(launch_reduce_pass(R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
@@ -608,7 +618,8 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
             rp.want_J = J_out != nullptr;
             rp.store_T = keep_T ? 1 : 0;
             HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items,
-                                     (int)R.items.size(), R.waves, rp, R.lds, st));
+                                     (int)R.items.size(), R.waves, rp,
+                                     R.lds_for[rp.adjoint ? 1 : 0][rp.want_J ? 1 : 0], st));
         }
     }
     if (n == 1 && (T_L_out || J_out)) HIPCHK(launch_output(meshes[0]->d_geom, 1, T_L_out, o->only_fourier ? nullptr : J_out, nullptr, st));

@@ -174,6 +174,19 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Loads through these views compile to global (not flat) loads, which keep
+// only the vector-memory counter pending while the row computes.
+template <typename T>
+using gptr_t = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr_t<T> gview(const T* p) { return (gptr_t<T>)p; }
+// Writable global views: stores through them are global (not flat) stores,
+// which a barrier's wait on the LDS counter does not include.
+template <typename T>
+using gmut_t = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gmut_t<T> gmut(T* p) { return (gmut_t<T>)p; }
+
 // Reduction state of a lockstep sweep.  The output pointers are copied here
 // once: kept in registers, they are not reloaded after every barrier.
 struct Red {
@@ -181,8 +194,11 @@ struct Red {
     int w, W, ROW;
     int local;        // item index within the geometry
     int want_J, store_T;
+    int NV;           // slot rows per wave (red_rows)
     double kacc, kface;
-    double *pTL, *pTw, *pG, *pJ;   // this item's partial rows
+    gmut_t<double> pTL, pTw, pG, pJ;   // this item's partial rows
+    gmut_t<double> Tstore;             // this system's stored state (or null)
+    gptr_t<double> T_L;
     int ncells;
 };
 
@@ -203,12 +219,6 @@ __device__ __forceinline__ double slot_sum(const double* buf, int W, int NV, int
     return s;
 }
 
-// Loads through these views compile to global (not flat) loads, which keep
-// only the vector-memory counter pending while the row computes.
-template <typename T>
-using gptr_t = const __attribute__((address_space(1))) T*;
-template <typename T>
-__device__ __forceinline__ gptr_t<T> gview(const T* p) { return (gptr_t<T>)p; }
 
 // 1/d: hardware reciprocal (float), refined by two Newton steps (double).
 __device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
@@ -289,8 +299,8 @@ struct RegIO {
 };
 template <typename T, int CPL>
 struct GlobIO {
-    const T* u;
-    T* xl;        // nullptr: the last row is not needed
+    gptr_t<T> u;
+    gmut_t<T> xl;        // nullptr: the last row is not needed
     int nx;
     int active;
     __device__ __forceinline__ T in(int kk, int c, int lane) const {
@@ -373,7 +383,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         const int iz = D3 ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
         const int rowbase = nx * (iy + ny * iz);
         const int ROW = rd->ROW, W = rd->W;
-        constexpr int NV = 1 + 2 * ND;
+        const int NV = rd->NV;
         // the slots are double buffered by row parity: a wave writes this
         // buffer again two rows later, after the next row's barrier, which
         // every wave reaches only once it has combined this row
@@ -409,7 +419,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                         else if (cl == FC_JUMP_M) rd->kface -= s.cd[ax] * g.dT * xv;
                     }
                     // gradient partial lambda (T - T_L), linear in lambda
-                    gp = xv * (g.Tstore[(size_t)s.sys * g.ncells + cell] - g.T_L[cell]);
+                    gp = xv * (rd->Tstore[cell] - rd->T_L[cell]);
                 } else {
                     // kappa through the periodic plane of the gradient axis;
                     // the jump term belongs to the b sweep only
@@ -418,7 +428,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                     if (g.grad_axis == 1 && jj == ny - 1 && fc_class(wv, s.fout[1]) != FC_WALL)
                         rd->kface += xv + ((!ADD && s.pos[1]) ? g.dT : 0.0);
                 }
-                if (rd->store_T) g.Tstore[(size_t)s.sys * g.ncells + cell] = xv;
+                if (rd->store_T) rd->Tstore[cell] = xv;
             }
             slot[0] = adj ? xv : s.Dml * xv;
             // wall slots exist where the geometry sends this direction into a
@@ -448,26 +458,26 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
             const bool sol = fc_solid(wv);
             const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
             const double sum = slot_sum(buf, W, NV, ROW, 0, p);
-            double* dst = rd->pTL + cell;
+            gmut_t<double> dst = rd->pTL + cell;
             *dst = ADD ? *dst + sum : (sol ? sum : 0.0);
             if (wall_row && sol) {
 #pragma unroll
                 for (int ax = 0; ax < ND; ++ax) {
                     if (fc_class(wv, s.fout[ax]) != FC_WALL) continue;
                     const double sw = slot_sum(buf, W, NV, ROW, 1 + ax, p);
-                    double* dw = rd->pTw + (size_t)ax * rd->ncells + cell;
+                    gmut_t<double> dw = rd->pTw + (size_t)ax * rd->ncells + cell;
                     *dw = ADD ? *dw + sw : sw;
                 }
             }
             if (adj) {
                 const double sg = slot_sum(buf, W, NV, ROW, 1 + ND, p);
-                double* dg = rd->pG + cell;
+                gmut_t<double> dg = rd->pG + cell;
                 *dg = ADD ? *dg + sg : sg;
             } else if (rd->want_J) {
 #pragma unroll
                 for (int ax = 0; ax < ND; ++ax) {
                     const double sj = slot_sum(buf, W, NV, ROW, 1 + ND + ax, p);
-                    double* dj = rd->pJ + (size_t)cell * ND + ax;
+                    gmut_t<double> dj = rd->pJ + (size_t)cell * ND + ax;
                     *dj = ADD ? *dj + sj : sj;
                 }
             }
@@ -734,11 +744,14 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     rd.store_T = pp.store_T;
     rd.kacc = 0.0;
     rd.kface = 0.0;
+    rd.NV = red_rows(2, adj, pp.want_J);
     rd.ncells = g.ncells;
-    rd.pTL = g.part_TL + (size_t)item.local * g.ncells;
-    rd.pTw = g.part_Tw + (size_t)item.local * g.ndim * g.ncells;
-    rd.pG = g.part_G + (size_t)item.local * g.ncells;
-    rd.pJ = g.part_J + (size_t)item.local * g.ncells * g.ndim;
+    rd.pTL = gmut(g.part_TL + (size_t)item.local * g.ncells);
+    rd.pTw = gmut(g.part_Tw + (size_t)item.local * g.ndim * g.ncells);
+    rd.pG = gmut(g.part_G + (size_t)item.local * g.ncells);
+    rd.pJ = gmut(g.part_J + (size_t)item.local * g.ncells * g.ndim);
+    rd.Tstore = g.Tstore ? gmut(g.Tstore + (size_t)s.sys * g.ncells) : nullptr;
+    rd.T_L = gview(g.T_L);
     // ---- phase A
     {
         RegIO<T, CPL> io{u[0], xl[0]};
@@ -867,7 +880,7 @@ static_assert(KV_N == KRY3_VECS, "workspace carve and kernel disagree on the 3D 
         }
 
 template <typename T, int CPL>
-__global__ void __launch_bounds__(512) k_sweep_pass3(const GeomDev* __restrict__ geoms,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL == 1 ? 3 : 1))) k_sweep_pass3(const GeomDev* __restrict__ geoms,
                                                      const Item* __restrict__ items, int n_items,
                                                      PassParams pp) {
     extern __shared__ double lds[];
@@ -887,12 +900,12 @@ __global__ void __launch_bounds__(512) k_sweep_pass3(const GeomDev* __restrict__
     const double* bnd = g.bnd + ((size_t)(adj ? 2 : 0) + buf_in) * g.nf * g.ncells;
     const int nx = g.nx, nz = g.nz, nw = g.nwrap;
     const size_t half = adj ? (size_t)g.n_sys : 0;
-    T* U = reinterpret_cast<T*>(g.U) + (half + s.sys) * (size_t)nw;
-    T* K = reinterpret_cast<T*>(g.kry) + (size_t)s.sys * KV_N * nw;
-    T* xl = K + (size_t)KV_XL * nw;
-    T* du = K + (size_t)KV_DU * nw;
+    const gmut_t<T> U = gmut(reinterpret_cast<T*>(g.U) + (half + s.sys) * (size_t)nw);
+    const gmut_t<T> K = gmut(reinterpret_cast<T*>(g.kry) + (size_t)s.sys * KV_N * nw);
+    const gmut_t<T> xl = K + (size_t)KV_XL * nw;
+    const gmut_t<T> du = K + (size_t)KV_DU * nw;
     // per-wave LDS: the reduction rows, then nz rows of this wave
-    constexpr int NVR = red_rows(3);
+    const int NVR = red_rows(3, adj, pp.want_J);
     T* zrows = reinterpret_cast<T*>(lds + (size_t)2 * W * NVR * WAVE * CPL) + (size_t)w * nz * WAVE * CPL;
     Red rd;
     rd.lds = lds;
@@ -904,11 +917,14 @@ __global__ void __launch_bounds__(512) k_sweep_pass3(const GeomDev* __restrict__
     rd.store_T = pp.store_T;
     rd.kacc = 0.0;
     rd.kface = 0.0;
+    rd.NV = red_rows(3, adj, pp.want_J);
     rd.ncells = g.ncells;
-    rd.pTL = g.part_TL + (size_t)item.local * g.ncells;
-    rd.pTw = g.part_Tw + (size_t)item.local * g.ndim * g.ncells;
-    rd.pG = g.part_G + (size_t)item.local * g.ncells;
-    rd.pJ = g.part_J + (size_t)item.local * g.ncells * g.ndim;
+    rd.pTL = gmut(g.part_TL + (size_t)item.local * g.ncells);
+    rd.pTw = gmut(g.part_Tw + (size_t)item.local * g.ndim * g.ncells);
+    rd.pG = gmut(g.part_G + (size_t)item.local * g.ncells);
+    rd.pJ = gmut(g.part_J + (size_t)item.local * g.ncells * g.ndim);
+    rd.Tstore = g.Tstore ? gmut(g.Tstore + (size_t)s.sys * g.ncells) : nullptr;
+    rd.T_L = gview(g.T_L);
     // ---- phase A
     {
         GlobIO<T, CPL> io{U, xl, nx, active};
@@ -918,15 +934,15 @@ __global__ void __launch_bounds__(512) k_sweep_pass3(const GeomDev* __restrict__
     int need = 0;
     const bool has_wrap = g.periodic[1] != 0;
     if (pp.mode == 0 && active && has_wrap) {
-        T* mk = K + (size_t)KV_MK * nw;
-        T* r = K + (size_t)KV_R * nw;
-        T* e = K + (size_t)KV_E * nw;
-        T* eb = K + (size_t)KV_EB * nw;
-        T* rh = K + (size_t)KV_RH * nw;
-        T* p = K + (size_t)KV_P * nw;
-        T* v = K + (size_t)KV_V * nw;
-        T* sv = K + (size_t)KV_S * nw;
-        T* t = K + (size_t)KV_T * nw;
+        const gmut_t<T> mk = K + (size_t)KV_MK * nw;
+        const gmut_t<T> r = K + (size_t)KV_R * nw;
+        const gmut_t<T> e = K + (size_t)KV_E * nw;
+        const gmut_t<T> eb = K + (size_t)KV_EB * nw;
+        const gmut_t<T> rh = K + (size_t)KV_RH * nw;
+        const gmut_t<T> p = K + (size_t)KV_P * nw;
+        const gmut_t<T> v = K + (size_t)KV_V * nw;
+        const gmut_t<T> sv = K + (size_t)KV_S * nw;
+        const gmut_t<T> t = K + (size_t)KV_T * nw;
         // wrap mask E' (c_y where the pair across the y-wrap is solid), the
         // inflow produced by the sweep and the residual of the wrap system
         const int iy = s.pos[1] ? 0 : g.ny - 1;

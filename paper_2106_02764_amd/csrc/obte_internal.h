@@ -17,8 +17,12 @@ enum { CTRL_DONE = 0, CTRL_PASS = 1, CTRL_CONVERGED = 2, CTRL_NONFINITE = 3, CTR
 
 // wrap-plane vectors per system kept in the workspace by the 3D pass kernel
 constexpr int KRY3_VECS = 11;
-// reduction rows per wave in the pass kernels' LDS: T_L, walls, J (per axis)
-__host__ __device__ constexpr int red_rows(int ndim) { return 1 + 2 * ndim; }
+// reduction rows per wave in the pass kernels' LDS: T_L and the walls (one
+// per axis), then the gradient partial (adjoint) or the flux (per axis, only
+// when the flux map is wanted)
+__host__ __device__ constexpr int red_rows(int ndim, int adjoint, int want_J) {
+    return 1 + ndim + (adjoint ? 1 : (want_J ? ndim : 0));
+}
 
 // Per-geometry view used by every kernel: static tables (library-owned) plus
 // the per-solve workspace carve (caller-owned).
