@@ -1593,17 +1593,38 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_init(const GeomDev* __re
     if ((int)blockIdx.x >= v.B) return;
     double kf[3];
     for (int a = 0; a < 3; ++a) kf[a] = (a < g.ndim) ? g.kappa_axis[a] / (g.h[a] * g.h[a]) : 0.0;
-    double s = 0.0;
+    // start from the linear profile T = -dT (i + 1/2) / n along the gradient
+    // axis: the exact solution without pores, so the first residual lives
+    // only next to pore faces
+    const int ga = g.grad_axis;
+    const double ng = (double)(ga == 0 ? g.nx : g.ny);
+    auto lin = [&](int c) {
+        const int i = ga == 0 ? c % g.nx : (c / g.nx) % g.ny;
+        return -g.dT * ((double)i + 0.5) / ng;
+    };
+    double s = 0.0, bb = 0.0;
     for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
-        const double b = fourier_rhs(g, g.fc[c], kf);
-        v.x[c] = 0.0;
-        v.r[c] = b;
+        const uint16_t w = g.fc[c];
+        const double b = fourier_rhs(g, w, kf);
+        double x0 = 0.0, r0 = 0.0;
+        if (fc_solid(w)) {
+            x0 = lin(c);
+            double y = 0.0;
+            for (int f = 0; f < g.nf; ++f)
+                if (fc_class(w, f) != FC_WALL) y += kf[f >> 1] * (x0 - lin(nbr_cell(g, c, f)));
+            r0 = b - y;
+        }
+        v.x[c] = x0;
+        v.r[c] = r0;
         v.p0[c] = 0.0;
-        s += b * b;
+        s += r0 * r0;
+        bb += b * b;
     }
     s = block_sum(s, red);
+    bb = block_sum(bb, red);
     if (threadIdx.x == 0) {
         v.rr0[blockIdx.x] = s;
+        v.pap[blockIdx.x] = bb;              // |b|^2 partials, read by k_fourier_norm
         v.rr1[blockIdx.x] = INFINITY;        // first beta = 0
         if (blockIdx.x == 0) {
             v.sc[1] = 0.0;
@@ -1612,15 +1633,16 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_init(const GeomDev* __re
     }
 }
 
-// |b| of every geometry (one block each)
+// |b| of every geometry (one block each); a zero first residual is converged
 __global__ void __launch_bounds__(FB_THREADS) k_fourier_norm(const GeomDev* __restrict__ geoms) {
     __shared__ double red[32];
     const GeomDev& g = geoms[blockIdx.x];
     const FView v = fourier_view(g, 0);
-    const double bb = sum_partials(v.rr0, v.B, red);
+    const double bb = sum_partials(v.pap, v.B, red);
+    const double rr = sum_partials(v.rr0, v.B, red);
     if (threadIdx.x == 0) {
         v.sc[0] = sqrt(bb);
-        if (!(bb > 0.0)) v.sc[1] = 1.0;
+        if (!(bb > 0.0) || !(rr > 0.0)) v.sc[1] = 1.0;
     }
 }
 
