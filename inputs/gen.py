@@ -46,6 +46,9 @@ class Workload:
     dir_w: np.ndarray   # (n_dir,) weights summing to 1
     sigma: np.ndarray | None = None   # per-cell multiplier (flattened), None => 1
     meta: dict = field(default_factory=dict)
+    # optional mode table: (F (n_modes, ndim) vectorial MFPs in metres,
+    # alpha (n_modes,) C/tau weights); when set, the grid weights come from it
+    modes: tuple | None = None
 
     @property
     def n_cells(self) -> int:
@@ -289,6 +292,44 @@ def small_3d(nx: int, ny: int, nz: int, solid=None, n_theta: int = 4, n_phi: int
                     np.asarray(solid, np.uint8).reshape(nz, ny, nx), 0, 1.0,
                     mfp, lognormal_kernel(mfp), dirs, w,
                     sigma=None if sigma is None else np.asarray(sigma, float).ravel())
+
+
+def with_modes(w: Workload, n_modes: int, seed: int, on_node: bool = False,
+               mfp_lo: float | None = None, mfp_hi: float | None = None) -> Workload:
+    """A copy of `w` whose material is a synthetic mode table.
+
+    on_node: one mode per grid point F_ml = Lambda_m s_l with the kernel's
+    weight alpha_ml (the interpolation is then the identity).  Otherwise
+    n_modes modes (n_modes/2 random ones and their reverses -F, so the table
+    carries no net flux) with log-uniform |F| in [mfp_lo, mfp_hi] (default: a
+    bit beyond the grid, so some modes are clamped), uniform random directions,
+    and weights from the same lognormal kernel in ln|F| (median 300 nm,
+    sigma_ln 1.5) divided by |F|^2, scaled to a bulk conductivity of 150 W/m/K
+    along the gradient axis."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    nd = w.ndim
+    if on_node:
+        mu = float(np.sum(w.dir_w * w.dirs[:, w.grad_axis] ** 2))
+        alpha = w.kappa_m[:, None] * w.dir_w[None, :] / (w.mfp[:, None] ** 2 * mu)
+        F = (w.mfp[:, None, None] * w.dirs[None, :, :]).reshape(-1, nd)
+        return dataclasses.replace(w, modes=(F, alpha.ravel()), name=w.name + "_nodes")
+    lo = w.mfp.min() / 2 if mfp_lo is None else mfp_lo
+    hi = w.mfp.max() * 2 if mfp_hi is None else mfp_hi
+    half = n_modes // 2
+    lam = np.exp(rng.uniform(np.log(lo), np.log(hi), half))
+    if nd == 2:
+        ph = rng.uniform(0.0, 2.0 * math.pi, half)
+        s = np.stack([np.cos(ph), np.sin(ph)], axis=1)
+    else:
+        v = rng.standard_normal((half, 3))
+        s = v / np.linalg.norm(v, axis=1, keepdims=True)
+    F = np.concatenate([lam[:, None] * s, -lam[:, None] * s])
+    lam = np.concatenate([lam, lam])
+    dens = np.exp(-np.log(lam / 300e-9) ** 2 / (2 * 1.5 ** 2))
+    alpha = dens / lam ** 2
+    alpha *= 150.0 / float(np.sum(alpha * F[:, w.grad_axis] ** 2))
+    return dataclasses.replace(w, modes=(F, alpha), name=w.name + f"_modes{n_modes}")
 
 
 CONFIGS = {"cfg1": config1, "cfg2": config2, "cfg4": config4, "cfg5": config5}

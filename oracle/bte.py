@@ -80,7 +80,8 @@ class Problem:
         if work is not None:
             mesh = Mesh(work.n, work.L, work.solid, work.periodic, work.grad_axis, work.dT,
                         ndim=work.ndim)
-            mat = Material(work.mfp, work.dirs, work.dir_w, work.kappa_m, work.grad_axis)
+            mat = Material(work.mfp, work.dirs, work.dir_w, work.kappa_m, work.grad_axis,
+                           modes=getattr(work, "modes", None))
             sigma = work.sigma
         self.mesh, self.mat = mesh, mat
         if sigma is None:

@@ -23,7 +23,7 @@ import numpy as np
 
 
 class Material:
-    def __init__(self, mfp, dirs, dir_w, kappa_m, grad_axis=0):
+    def __init__(self, mfp, dirs, dir_w, kappa_m, grad_axis=0, modes=None):
         mfp = np.asarray(mfp, float)
         dirs = np.asarray(dirs, float)
         dir_w = np.asarray(dir_w, float)
@@ -32,6 +32,15 @@ class Material:
         self.n_mfp, self.n_dir = len(mfp), len(dir_w)
         self.ndim = dirs.shape[1]
         self.grad_axis = grad_axis
+        self.modes = modes
+        if modes is not None:
+            # grid weights interpolated from a mode table (oracle/modes.py)
+            from .modes import grid_weights
+            F, alpha = modes
+            self.mu = float(np.sum(dir_w * dirs[:, grad_axis] ** 2))
+            self.D, self.S, self.kappa_axis = grid_weights(mfp, dirs, F, alpha, grad_axis)
+            self.alpha = self.D * float(np.sum(alpha))   # sum alpha_mu c: the T_L weights unnormalised
+            return
         w = material_weights(mfp, dirs, dir_w, kappa_m, grad_axis)
         self.mu = w["mu"]
         self.alpha = w["alpha"]        # (n_mfp, n_dir)

@@ -365,3 +365,76 @@ def test_adjoint_scaling_identity():
     LdkdL = (kp - km) / (2 * eps)
     lhs = float(np.sum(p.sigma * g))
     assert abs(lhs - (LdkdL - k0)) < 1e-6 * abs(k0)
+
+
+# ------------------------------------------------- mode tables (interpolation)
+
+from oracle.modes import interp_weights, kappa_modes  # noqa: E402
+
+
+def test_modes_on_node_identity():
+    """Modes sitting on the grid nodes with the kernel's weights: every c is a
+    single 1, the grid weights equal the kernel path's, and kappa_mu is the
+    per-system kappa."""
+    w0 = gen.small_2d(8, 6, solid=gen.square_block_mask(8, 6, 2, 5), n_dir=8, n_mfp=3)
+    wn = gen.with_modes(w0, 0, 0, on_node=True)
+    F, _ = wn.modes
+    W = interp_weights(w0.mfp, w0.dirs, F)
+    for mu, terms in enumerate(W):
+        assert len(terms) == 1 or max(c for _, _, c in terms) > 1 - 1e-12
+        m, l, c = max(terms, key=lambda t: t[2])
+        assert (m, l) == divmod(mu, len(w0.dir_w)) and abs(c - 1.0) < 1e-12
+    p0, pn = Problem(w0), Problem(wn)
+    assert np.allclose(pn.mat.D, p0.mat.D, rtol=1e-12, atol=0)
+    assert np.allclose(pn.mat.S, p0.mat.S, rtol=1e-12, atol=1e-12 * np.abs(p0.mat.S).max())
+    r = source_iteration(pn, tol=1e-13)
+    km = kappa_modes(pn, r["T"])
+    assert np.allclose(km, r["kappa_ml"].ravel(), rtol=1e-10, atol=1e-12 * r["kappa_cc"])
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_modes_weights_properties(nd):
+    """c >= 0 and sum c = 1 per mode; in range, the weights reproduce |F|
+    (linear in Lambda) and the angle (linear in angle) exactly."""
+    if nd == 2:
+        w = gen.with_modes(gen.small_2d(4, 4, n_dir=12, n_mfp=5), 200, 3)
+    else:
+        w = gen.with_modes(gen.small_3d(3, 3, 2, n_theta=6, n_phi=8, n_mfp=4), 200, 4)
+    F, _ = w.modes
+    W = interp_weights(w.mfp, w.dirs, F)
+    lam = np.linalg.norm(F, axis=1)
+    for mu, terms in enumerate(W):
+        cs = np.array([c for _, _, c in terms])
+        assert np.all(cs >= -1e-15) and abs(cs.sum() - 1.0) < 1e-12
+        if w.mfp.min() < lam[mu] < w.mfp.max():
+            assert abs(sum(c * w.mfp[m] for m, _, c in terms) - lam[mu]) < 1e-12 * lam[mu]
+        # angle: weighted mean of the bracketing directions' angles (unwrapped
+        # around the mode's own angle) equals the mode's angle
+        if nd == 2:
+            phi = math.atan2(F[mu, 1], F[mu, 0])
+            a = [c * ((math.atan2(w.dirs[l, 1], w.dirs[l, 0]) - phi + math.pi) % (2 * math.pi) - math.pi)
+                 for _, l, c in terms]
+            assert abs(sum(a)) < 1e-12
+        else:
+            th = math.acos(F[mu, 2] / lam[mu])
+            ths = np.unique(np.round(np.arccos(w.dirs[:, 2]), 12))
+            if ths.min() < th < ths.max():
+                t = sum(c * math.acos(max(-1.0, min(1.0, w.dirs[l, 2]))) for _, l, c in terms)
+                assert abs(t - th) < 1e-12
+
+
+def test_modes_bulk_closed_form_and_sum_rule():
+    """No pores: kappa_cc = sum_ml S_ml,x Lambda_m s_x,l with the interpolated
+    S (the bulk closed form with any T_L weights); with pores the
+    mode-resolved kappa sums to kappa_cc (S_ml = sum_mu c S_mu)."""
+    wb = gen.with_modes(gen.small_2d(8, 6, n_dir=8, n_mfp=3), 40, 1)
+    p = Problem(wb)
+    r = source_iteration(p, tol=1e-13)
+    cf = float(np.sum(p.mat.S[:, :, 0] * wb.mfp[:, None] * wb.dirs[None, :, 0]))
+    assert abs(r["kappa_cc"] - cf) < 1e-11 * cf
+    wp = gen.with_modes(gen.small_2d(10, 8, solid=gen.square_block_mask(10, 8, 3, 6), n_dir=8, n_mfp=3),
+                        60, 5)
+    p = Problem(wp)
+    r = source_iteration(p, tol=1e-13)
+    km = kappa_modes(p, r["T"])
+    assert abs(km.sum() - r["kappa_cc"]) < 1e-12 * abs(r["kappa_cc"])
