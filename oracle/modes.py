@@ -13,7 +13,13 @@ goes to the end node).
 
 The mode-resolved conductivity (Eq. mode-resolved) in the cell-centred form
 used for kappa_eff: kappa_mu = L S_mu,g / (dT N_tot) sum_ml c^mu_ml sum_i
-T_iml, which sums to kappa_eff over the modes because S_ml = sum_mu c S_mu.
+(T_iml - <T_L>), which sums to kappa_eff over the modes because S_ml =
+sum_mu c S_mu and sum_mu S_mu = 0.  The temperatures of the periodic problem
+are fixed only up to a common constant; kappa_eff does not depend on it, a
+single mode's share does (by S_mu,g times the constant).  The paper does not
+say which constant (reading: deviations from the mean lattice temperature
+over the solid cells, <T_L> = sum_ml D_ml sum_i T_iml / N_solid, so each
+kappa_mu is unchanged when every T moves by the same amount).
 """
 from __future__ import annotations
 
@@ -104,13 +110,16 @@ def grid_weights(mfp, dirs, F, alpha, grad_axis=0):
 
 def kappa_modes(prob, T):
     """kappa_mu of every mode from the per-system solutions T (n_mfp, n_dir,
-    n_solid) of a converged solve (kappa_cc form)."""
+    n_solid) of a converged solve (kappa_cc form, T measured from the mean
+    lattice temperature)."""
     mat, me = prob.mat, prob.mesh
     F, alpha = mat.modes
     g = me.grad_axis
     tot = T.sum(axis=2)                                   # sum_i T_iml
+    tot_L = float(np.sum(mat.D * tot))                    # sum_i T_L,i = N_solid <T_L>
     pref = me.L[g] / (me.dT * me.n_cells)
     out = np.zeros(len(alpha))
     for mu, terms in enumerate(interp_weights(mat.mfp, mat.dirs, F)):
-        out[mu] = pref * alpha[mu] * F[mu, g] * sum(c * tot[m, l] for m, l, c in terms)
+        # sum_ml c = 1: the interpolated sum of (T - <T_L>)
+        out[mu] = pref * alpha[mu] * F[mu, g] * (sum(c * tot[m, l] for m, l, c in terms) - tot_L)
     return out

@@ -389,7 +389,11 @@ def test_modes_on_node_identity():
     assert np.allclose(pn.mat.S, p0.mat.S, rtol=1e-12, atol=1e-12 * np.abs(p0.mat.S).max())
     r = source_iteration(pn, tol=1e-13)
     km = kappa_modes(pn, r["T"])
-    assert np.allclose(km, r["kappa_ml"].ravel(), rtol=1e-10, atol=1e-12 * r["kappa_cc"])
+    # the per-system kappa measured from the mean lattice temperature
+    g = w0.grad_axis
+    tot_L = float(np.sum(pn.mat.D * r["T"].sum(axis=2)))
+    shift = pn.mesh.L[g] / (pn.mesh.dT * pn.mesh.n_cells) * pn.mat.S[:, :, g] * tot_L
+    assert np.allclose(km, (r["kappa_ml"] - shift).ravel(), rtol=1e-10, atol=1e-12 * r["kappa_cc"])
 
 
 @pytest.mark.parametrize("nd", [2, 3])
@@ -432,9 +436,22 @@ def test_modes_bulk_closed_form_and_sum_rule():
     r = source_iteration(p, tol=1e-13)
     cf = float(np.sum(p.mat.S[:, :, 0] * wb.mfp[:, None] * wb.dirs[None, :, 0]))
     assert abs(r["kappa_cc"] - cf) < 1e-11 * cf
+    # bulk, per mode: every T_ml - T_L is Lambda_m s_l,x dT / L in every cell
+    # (the upwind difference of a linear profile is exact), so kappa_mu =
+    # alpha_mu F_mu,x sum_ml c Lambda_m s_l,x
+    F, alpha = wb.modes
+    kmb = kappa_modes(p, r["T"])
+    proj = np.array([sum(c * wb.mfp[m] * wb.dirs[l, 0] for m, l, c in t)
+                     for t in interp_weights(wb.mfp, wb.dirs, F)])
+    assert np.max(np.abs(kmb - alpha * F[:, 0] * proj)) < 1e-11 * cf
     wp = gen.with_modes(gen.small_2d(10, 8, solid=gen.square_block_mask(10, 8, 3, 6), n_dir=8, n_mfp=3),
                         60, 5)
     p = Problem(wp)
     r = source_iteration(p, tol=1e-13)
     km = kappa_modes(p, r["T"])
     assert abs(km.sum() - r["kappa_cc"]) < 1e-12 * abs(r["kappa_cc"])
+    # gauge: the temperatures are fixed up to a common constant, which no
+    # kappa_mu may see
+    km2 = kappa_modes(p, r["T"] + 0.37)
+    assert np.max(np.abs(km2 - km)) < 1e-12 * abs(r["kappa_cc"])
+
