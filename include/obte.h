@@ -69,7 +69,10 @@ typedef struct {
  * The library derives alpha_ml = kappa_m w_l / (Lambda_m^2 mu_g) with
  * mu_g = sum_l w_l s_{l,g}^2, the T_L weights D_ml = alpha / sum alpha, the flux
  * weights S_ml = alpha Lambda_m s_l and the outgoing wall weights per wall
- * orientation ReLu(S.n)/sum ReLu(S.n).  All pointers are host pointers. */
+ * orientation ReLu(S.n)/sum ReLu(S.n) (Appendix A, B_{lm'l'j}: the wall
+ * temperature takes every system whose S leaves through the wall, which with
+ * a mode table can include a system whose direction enters through it).
+ * All pointers are host pointers. */
 typedef struct {
     int n_mfp;
     const double* mfp;
@@ -77,6 +80,20 @@ typedef struct {
     const double* dirs;
     const double* dir_w;
     const double* kappa_m;
+    /* Optional mode table (Appendix A, aMFP interpolation): n_modes > 0
+     * replaces kappa_m.  mode_F: n_modes x ndim vectorial MFPs F_mu (metres,
+     * row-major); mode_alpha: n_modes weights alpha_mu = C/tau >= 0.  The
+     * table must carry no net flux (sum alpha_mu F_mu = 0, e.g. every mode
+     * with its reverse).  Each mode is spread over the grid with weights
+     * c^mu_ml: linear in Lambda between the bracketing MFP nodes times linear
+     * in angle between the bracketing directions (2D: azimuth, cyclic; 3D: a
+     * tensor grid of polar bins x azimuths, polar angle clamped at the
+     * outermost bins); beyond the MFP range the weight goes to the end node.
+     * Then D_ml = sum_mu c D_mu, S_ml = sum_mu c alpha_mu F_mu, and the Fourier
+     * conductivity per axis is sum_mu alpha_mu F_mu,a^2. */
+    int n_modes;
+    const double* mode_F;
+    const double* mode_alpha;
 } obte_material_desc;
 
 enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
@@ -216,6 +233,18 @@ obte_status obte_solve_batch(obte_mesh* const* meshes, int n, const obte_solve_o
  * over the n_mfp MFPs (host arrays). */
 obte_status obte_kappa(const obte_mesh* mesh, double* kappa_eff, double* kappa_per_mfp);
 
+/* Mode-resolved conductivity of the last solve (paper Eq. mode-resolved, in
+ * the cell-centred form of kappa_cc): kappa_mu = L S_mu,g / (dT N_cells)
+ * sum_ml c^mu_ml sum_i (T_iml - <T_L>), which sums to kappa_cc over the
+ * modes.  The periodic problem fixes the temperatures only up to a common
+ * constant, which kappa_cc does not see but a single mode's share does; the
+ * shares are taken relative to the mean lattice temperature <T_L> over the
+ * solid cells (so they do not depend on that constant).  With a mode table
+ * the per-MFP split of obte_kappa does depend on it.
+ * kappa_mode: host, n_modes doubles.  OBTE_ERR_STATE without a mode table or
+ * a completed solve. */
+obte_status obte_kappa_modes(const obte_mesh* mesh, double* kappa_mode);
+
 /* Adjoint gradient d kappa_cc / d sigma_i (derived from Appendix A,
  * Eq. (iter2)): M^T lambda = k by the transposed source iteration, then
  * d kappa / d sigma_i = -sum_ml lambda_iml (T_iml - T_L,i).  Requires a
@@ -253,6 +282,7 @@ int obte_mesh_n_cells(const obte_mesh* mesh);
 int obte_mesh_n_solid(const obte_mesh* mesh);
 int obte_mesh_n_walls(const obte_mesh* mesh);
 int obte_mesh_n_systems(const obte_mesh* mesh);
+int obte_mesh_n_modes(const obte_mesh* mesh);
 
 #ifdef __cplusplus
 }

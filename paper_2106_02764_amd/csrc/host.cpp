@@ -80,6 +80,15 @@ struct obte_mesh {
     std::vector<double> kappa_per_mfp;
     GeomDev host_view{};
     int last_precision = 0, last_waves = 0, last_max_outer = 0, last_keep = 0, last_recycle = 0;
+    // mode table (optional): per mode up to MODE_TERMS (system, weight) pairs
+    // and its flux weight along the gradient axis; kappa_mu of the last solve
+    int n_modes = 0;
+    int wall_in = 0;      // see GeomDev::wall_in
+    std::vector<int> mode_sys;
+    std::vector<double> mode_w, mode_Sg, kappa_mode;
+    int* d_mode_sys = nullptr;
+    double *d_mode_w = nullptr, *d_mode_Sg = nullptr, *d_kmode = nullptr;
+    bool modes_solved = false;
 };
 
 namespace {
@@ -90,8 +99,147 @@ namespace {
 struct Layout {
     size_t sigma, sigma_f, sT, Tw, T_L, U, part_TL, part_Tw, part_J, ksys, kfsys, iters, sweeps,
         hist, hist_face, ctrl, fx, fscal, Tstore, lam_psi, lam_phi, grad, part_G, bnd, mem, mem_count,
-        mem_bytes, wres, wres_hist, kry, ax, actl, ag, axp, afp, adX, adF, agram, apart, total;
+        mem_bytes, wres, wres_hist, kry, ax, actl, ag, axp, afp, adX, adF, agram, apart, kraw, part_Twi,
+        total;
 };
+
+// Linear interpolation weights of x on the sorted values v (clamped to the
+// end nodes): up to two (index into v, weight) pairs.
+int bracket_linear(const std::vector<double>& v, double x, int* idx, double* w) {
+    const int n = (int)v.size();
+    if (x <= v[0]) { idx[0] = 0; w[0] = 1.0; return 1; }
+    if (x >= v[n - 1]) { idx[0] = n - 1; w[0] = 1.0; return 1; }
+    int a = (int)(std::upper_bound(v.begin(), v.end(), x) - v.begin()) - 1;
+    const double t = (x - v[a]) / (v[a + 1] - v[a]);
+    idx[0] = a; w[0] = 1.0 - t;
+    idx[1] = a + 1; w[1] = t;
+    return 2;
+}
+
+// The same on sorted angles in [0, 2 pi), wrapping around.
+int bracket_cyclic(const std::vector<double>& v, double x, int* idx, double* w) {
+    const double two_pi = 2.0 * M_PI;
+    const int n = (int)v.size();
+    x = std::fmod(std::fmod(x, two_pi) + two_pi, two_pi);
+    int b = (int)(std::upper_bound(v.begin(), v.end(), x) - v.begin());
+    const int a = (b - 1 + n) % n;
+    b %= n;
+    const double gap = std::fmod(v[b] - v[a] + two_pi, two_pi);
+    const double t = gap > 0.0 ? std::fmod(x - v[a] + two_pi, two_pi) / gap : 0.0;
+    idx[0] = a; w[0] = 1.0 - t;
+    idx[1] = b; w[1] = t;
+    return 2;
+}
+
+constexpr int MODE_TERMS = 8;
+
+// Spread every mode over the (MFP, direction) grid (see obte_material_desc).
+obte_status mode_weights(obte_mesh* m, const obte_material_desc* d) {
+    const int nd = m->ndim, nm = d->n_modes;
+    std::vector<int> morder(m->n_mfp);
+    for (int i = 0; i < m->n_mfp; ++i) morder[i] = i;
+    std::sort(morder.begin(), morder.end(), [&](int a, int b) { return m->mfp[a] < m->mfp[b]; });
+    std::vector<double> mv(m->n_mfp);
+    for (int i = 0; i < m->n_mfp; ++i) mv[i] = m->mfp[morder[i]];
+    for (int i = 1; i < m->n_mfp; ++i)
+        if (!(mv[i] > mv[i - 1])) return fail(OBTE_ERR_ARG, "MFP nodes must be distinct for a mode table");
+    auto angle = [](double y, double x) {
+        const double a = std::atan2(y, x);
+        return a < 0.0 ? a + 2.0 * M_PI : a;
+    };
+    // angular grid: 2D sorted azimuths; 3D distinct polar angles x azimuths
+    std::vector<double> thv, phv;
+    std::vector<int> lmap;            // (polar index, azimuth index) -> direction
+    auto uniq = [](std::vector<double> v) {
+        std::sort(v.begin(), v.end());
+        std::vector<double> u;
+        for (double x : v)
+            if (u.empty() || x - u.back() > 1e-9) u.push_back(x);
+        return u;
+    };
+    std::vector<double> th(m->n_dir), ph(m->n_dir);
+    for (int l = 0; l < m->n_dir; ++l) {
+        const double* s = &m->dirs3[l * 3];
+        ph[l] = angle(s[1], s[0]);
+        th[l] = std::acos(std::max(-1.0, std::min(1.0, s[2])));
+    }
+    phv = uniq(ph);
+    if (nd == 2) {
+        if ((int)phv.size() != m->n_dir) return fail(OBTE_ERR_ARG, "mode table: directions must have distinct angles");
+        lmap.assign(m->n_dir, -1);
+        for (int l = 0; l < m->n_dir; ++l)
+            lmap[std::lower_bound(phv.begin(), phv.end(), ph[l] - 1e-9) - phv.begin()] = l;
+    } else {
+        thv = uniq(th);
+        if (thv.size() * phv.size() != (size_t)m->n_dir)
+            return fail(OBTE_ERR_ARG, "3D mode table needs a tensor (polar x azimuth) direction grid");
+        lmap.assign(m->n_dir, -1);
+        for (int l = 0; l < m->n_dir; ++l) {
+            const int k = (int)(std::lower_bound(thv.begin(), thv.end(), th[l] - 1e-9) - thv.begin());
+            const int j = (int)(std::lower_bound(phv.begin(), phv.end(), ph[l] - 1e-9) - phv.begin());
+            if (lmap[k * phv.size() + j] >= 0) return fail(OBTE_ERR_ARG, "3D mode table: repeated direction");
+            lmap[k * phv.size() + j] = l;
+        }
+    }
+    m->n_modes = nm;
+    m->mode_sys.assign((size_t)nm * MODE_TERMS, 0);
+    m->mode_w.assign((size_t)nm * MODE_TERMS, 0.0);
+    m->mode_Sg.assign(nm, 0.0);
+    double asum = 0.0, net[3] = {0.0, 0.0, 0.0}, scale = 0.0;
+    for (int mu = 0; mu < nm; ++mu) {
+        const double a = d->mode_alpha[mu];
+        if (!(a >= 0.0) || !std::isfinite(a)) return fail(OBTE_ERR_ARG, "mode_alpha[%d] must be >= 0", mu);
+        asum += a;
+        double lam2 = 0.0;
+        for (int ax = 0; ax < nd; ++ax) {
+            const double f = d->mode_F[mu * nd + ax];
+            if (!std::isfinite(f)) return fail(OBTE_ERR_ARG, "mode_F[%d] is not finite", mu);
+            lam2 += f * f;
+            net[ax] += a * f;
+            scale += a * std::fabs(f);
+        }
+        if (!(lam2 > 0.0)) return fail(OBTE_ERR_ARG, "mode %d has a zero MFP", mu);
+    }
+    if (!(asum > 0.0)) return fail(OBTE_ERR_ARG, "mode_alpha is all zero");
+    for (int ax = 0; ax < nd; ++ax)
+        if (std::fabs(net[ax]) > 1e-9 * scale) return fail(OBTE_ERR_ARG, "mode table carries a net flux along axis %d", ax);
+    m->Dw.assign(m->n_sys, 0.0);
+    m->S.assign(3 * m->n_sys, 0.0);
+    m->kappa_axis.assign(3, 0.0);
+    for (int mu = 0; mu < nm; ++mu) {
+        const double* F = &d->mode_F[mu * nd];
+        const double a = d->mode_alpha[mu];
+        double lam = 0.0;
+        for (int ax = 0; ax < nd; ++ax) lam += F[ax] * F[ax];
+        lam = std::sqrt(lam);
+        int im[2], ip[2], it[2];
+        double wm[2], wp[2], wt[2];
+        const int nmm = bracket_linear(mv, lam, im, wm);
+        const int npp = bracket_cyclic(phv, angle(F[1], F[0]), ip, wp);
+        int ntt = 1;
+        it[0] = 0; wt[0] = 1.0;
+        if (nd == 3) ntt = bracket_linear(thv, std::acos(std::max(-1.0, std::min(1.0, F[2] / lam))), it, wt);
+        int k = 0;
+        for (int i = 0; i < nmm; ++i)
+            for (int t = 0; t < ntt; ++t)
+                for (int j = 0; j < npp; ++j) {
+                    const int l = nd == 2 ? lmap[ip[j]] : lmap[it[t] * phv.size() + ip[j]];
+                    const int sys = morder[im[i]] * m->n_dir + l;
+                    const double c = wm[i] * wt[t] * wp[j];
+                    m->mode_sys[(size_t)mu * MODE_TERMS + k] = sys;
+                    m->mode_w[(size_t)mu * MODE_TERMS + k] = c;
+                    ++k;
+                    m->Dw[sys] += c * a / asum;
+                    for (int ax = 0; ax < nd; ++ax) m->S[sys * 3 + ax] += c * a * F[ax];
+                }
+        m->mode_Sg[mu] = a * F[m->grad_axis];
+        for (int ax = 0; ax < nd; ++ax) m->kappa_axis[ax] += a * F[ax] * F[ax];
+    }
+    // the T_L weights unnormalised (kept for reference; the kernels use D)
+    m->alpha.assign(m->n_sys, 0.0);
+    for (int sys = 0; sys < m->n_sys; ++sys) m->alpha[sys] = m->Dw[sys] * asum;
+    return OBTE_OK;
+}
 
 int auto_waves(const obte_mesh* m) {
     int w = 4;
@@ -139,8 +287,10 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.hist_face = take((size_t)HIST_CAP * 8);
     L.wres_hist = take((size_t)HIST_CAP * 8);
     const size_t naa = nc + (size_t)m->nwalls;
-    L.ax = take(naa * 8);
+    L.ax = take((naa + 1) * 8);            // + the gauge shift of the pass
     L.actl = take(8 * 4);
+    L.kraw = take((size_t)m->n_sys * 8);
+    L.part_Twi = take(m->wall_in ? n_items * (size_t)m->ndim * nc * 8 : 8);
     // the parts below depend on precision / recycle / keep_state / accel, so
     // the state a resumed solve reads (above, and U) keeps its place
     L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
@@ -178,6 +328,8 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
     g.n_perp = m->ncells / (m->grad_axis == 0 ? m->nx : (m->grad_axis == 1 ? m->ny : m->nz));
     g.fc = m->d_fc; g.wall_idx = m->d_wall_idx; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face;
     g.mfp = m->d_mfp; g.dirs = m->d_dirs; g.Dw = m->d_D; g.S = m->d_S; g.wout = m->d_wout;
+    g.wall_in = m->wall_in;
+    g.gauge = m->n_modes > 0 ? 1 : 0;
     g.kappa_axis = m->d_kax;
     if (ws) {
         g.sigma = (double*)(ws + L.sigma);
@@ -211,6 +363,8 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.wres_hist = (double*)(ws + L.wres_hist);
         g.ax = (double*)(ws + L.ax);
         g.actl = (int*)(ws + L.actl);
+        g.kraw = (double*)(ws + L.kraw);
+        g.part_Twi = (double*)(ws + L.part_Twi);
         if (accel > 0) {
             g.ag = (double*)(ws + L.ag);
             g.axp = (double*)(ws + L.axp);
@@ -235,12 +389,15 @@ obte_status upload(T** dst, const std::vector<T>& src) {
 
 void free_dev(obte_mesh* m) {
     void* ptrs[] = {m->d_fc, m->d_wall_idx, m->d_wall_cell, m->d_wall_face, m->d_mfp, m->d_dirs,
-                    m->d_D, m->d_S, m->d_wout, m->d_kax, m->d_geom};
+                    m->d_D, m->d_S, m->d_wout, m->d_kax, m->d_geom, m->d_mode_sys, m->d_mode_w,
+                    m->d_mode_Sg, m->d_kmode};
     for (void* p : ptrs)
         if (p) soft(hipFree(p), "hipFree(table)");
     m->d_fc = nullptr; m->d_wall_idx = m->d_wall_cell = m->d_wall_face = nullptr;
     m->d_mfp = m->d_dirs = m->d_D = m->d_S = m->d_wout = m->d_kax = nullptr;
     m->d_geom = nullptr;
+    m->d_mode_sys = nullptr;
+    m->d_mode_w = m->d_mode_Sg = m->d_kmode = nullptr;
 }
 
 obte_status check_opts(const obte_solve_opts* o) {
@@ -320,6 +477,7 @@ struct Run {
     Item* d_items = nullptr;
     int* d_pending = nullptr;     // geometries whose Fourier CG still iterates
     int waves = 4, cpl = 1, nzmax = 1, precision = 0, accel = 0;
+    int gauge = 0;                // some geometry has a mode table (re-centred passes)
     size_t lds = 0;               // the largest any launch of this run needs
     size_t lds_for[2][2] = {};    // [adjoint][want_J]
     int max_cells = 0, max_walls = 0;
@@ -343,12 +501,16 @@ obte_status resolve_waves(const obte_mesh* const* meshes, int n, const obte_solv
     }
     size_t per_wave = 0;
     {
-        int cpl = 1, nzm = 1;
-        for (int i = 0; i < n; ++i) { cpl = std::max(cpl, (meshes[i]->nx + 63) / 64); nzm = std::max(nzm, meshes[i]->nz); }
+        int cpl = 1, nzm = 1, win = 0;
+        for (int i = 0; i < n; ++i) {
+            cpl = std::max(cpl, (meshes[i]->nx + 63) / 64);
+            nzm = std::max(nzm, meshes[i]->nz);
+            win |= meshes[i]->wall_in;
+        }
         const int nd = nzm > 1 ? 3 : 2;
         // reduction rows (double buffered; the largest set, the flux replay),
         // plus in 3D one row per z-plane in the compute type
-        per_wave = 2 * (size_t)red_rows(nd, 0, 1) * 64 * cpl * sizeof(double);
+        per_wave = 2 * (size_t)red_rows(nd, 0, 1, win) * 64 * cpl * sizeof(double);
         if (nzm > 1) per_wave += (size_t)nzm * 64 * cpl * (o->precision == OBTE_FP32 ? 4 : 8);
         const size_t cap = 64 * 1024;
         if (per_wave > cap)
@@ -370,6 +532,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     R.meshes.assign(meshes, meshes + n);
     R.precision = o->precision;
     R.accel = o->accel;
+    for (int i = 0; i < n; ++i) R.gauge |= meshes[i]->n_modes > 0 ? 1 : 0;
     int W = 0;
     size_t per_wave = 0;
     obte_status s = resolve_waves(meshes, n, o, &W, &per_wave);
@@ -407,11 +570,13 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     {
         // launches size their LDS for the slot rows they use
         const int nd = R.nzmax > 1 ? 3 : 2;
+        int win = 0;
+        for (int gi = 0; gi < n; ++gi) win |= meshes[gi]->wall_in;
         const size_t row = 64 * (size_t)R.cpl;
         const size_t zr = R.nzmax > 1 ? (size_t)R.nzmax * row * (o->precision == OBTE_FP32 ? 4 : 8) : 0;
         for (int a = 0; a < 2; ++a)
             for (int j = 0; j < 2; ++j)
-                R.lds_for[a][j] = (size_t)W * (2 * (size_t)red_rows(nd, a, j) * row * sizeof(double) + zr);
+                R.lds_for[a][j] = (size_t)W * (2 * (size_t)red_rows(nd, a, j, win) * row * sizeof(double) + zr);
     }
     HIPCHK(hipMalloc((void**)&R.d_views, R.views.size() * sizeof(GeomDev)));
     HIPCHK(hipMalloc((void**)&R.d_items, R.items.size() * sizeof(Item)));
@@ -428,6 +593,7 @@ obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Tim
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 1], st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 2], st));
     HIPCHK(launch_reduce_pass(R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
+    if (R.gauge && !pp.adjoint) HIPCHK(launch_gauge(R.d_views, (int)R.views.size(), R.max_cells + R.max_walls, st));
     if (R.accel > 0) HIPCHK(launch_anderson(R.d_views, (int)R.views.size(), R.max_cells + R.max_walls, pp, st));
     HIPCHK(launch_finalize(R.d_views, (int)R.views.size(), pp, st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 3], st));
@@ -651,6 +817,18 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         m->kappa_face = passes > 0 ? histf[passes - 1] : fs[0];
         m->kappa_per_mfp.assign(m->n_mfp, 0.0);
         for (int sys = 0; sys < m->n_sys; ++sys) m->kappa_per_mfp[sys / m->n_dir] += ks[sys];
+        m->modes_solved = false;
+        if (m->n_modes > 0 && passes > 0) {
+            // mode-resolved kappa: gather of the per-system sums (kernel)
+            const double pref = m->L[m->grad_axis] / (m->dT * (double)m->ncells);
+            HIPCHK(launch_kappa_modes(m->d_mode_sys, m->d_mode_w, m->d_mode_Sg, m->n_modes, MODE_TERMS,
+                                      m->d_D, m->n_sys, v.kraw, pref, m->d_kmode, st));
+            m->kappa_mode.assign(m->n_modes, 0.0);
+            HIPCHK(hipMemcpyAsync(m->kappa_mode.data(), m->d_kmode, (size_t)m->n_modes * sizeof(double),
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            m->modes_solved = true;
+        }
         m->solved = true;
         m->adj_ready = keep_T && !o->only_fourier && ctrl[CTRL_CONVERGED];
         m->last_ws = workspace;
@@ -809,7 +987,10 @@ obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
 obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     if (!m || !d) return fail(OBTE_ERR_ARG, "NULL argument");
     if (d->n_mfp < 1 || d->n_dir < 2) return fail(OBTE_ERR_ARG, "need n_mfp >= 1 and n_dir >= 2");
-    if (!d->mfp || !d->dirs || !d->dir_w || !d->kappa_m) return fail(OBTE_ERR_ARG, "NULL material array");
+    if (d->n_modes < 0) return fail(OBTE_ERR_ARG, "n_modes must be >= 0");
+    const bool modes = d->n_modes > 0;
+    if (!d->mfp || !d->dirs || !d->dir_w || (!modes && !d->kappa_m)) return fail(OBTE_ERR_ARG, "NULL material array");
+    if (modes && (!d->mode_F || !d->mode_alpha)) return fail(OBTE_ERR_ARG, "NULL mode table array");
     const int nd = m->ndim;
     double wsum = 0.0;
     std::vector<double> ssum(3, 0.0);
@@ -826,13 +1007,15 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
         if (std::fabs(ssum[a]) > 1e-9) return fail(OBTE_ERR_ARG, "direction set must be centrally symmetric");
     for (int mm = 0; mm < d->n_mfp; ++mm) {
         if (!(d->mfp[mm] > 0.0) || !std::isfinite(d->mfp[mm])) return fail(OBTE_ERR_ARG, "mfp[%d] must be > 0", mm);
-        if (!(d->kappa_m[mm] >= 0.0) || !std::isfinite(d->kappa_m[mm])) return fail(OBTE_ERR_ARG, "kappa_m[%d] must be >= 0", mm);
+        if (!modes && (!(d->kappa_m[mm] >= 0.0) || !std::isfinite(d->kappa_m[mm])))
+            return fail(OBTE_ERR_ARG, "kappa_m[%d] must be >= 0", mm);
     }
     m->n_mfp = d->n_mfp;
     m->n_dir = d->n_dir;
     m->n_sys = d->n_mfp * d->n_dir;
     m->mfp.assign(d->mfp, d->mfp + d->n_mfp);
-    m->kappa_m.assign(d->kappa_m, d->kappa_m + d->n_mfp);
+    if (modes) m->kappa_m.assign(d->n_mfp, 0.0);
+    else m->kappa_m.assign(d->kappa_m, d->kappa_m + d->n_mfp);
     m->dir_w.assign(d->dir_w, d->dir_w + d->n_dir);
     m->dirs3.assign(3 * d->n_dir, 0.0);
     for (int l = 0; l < d->n_dir; ++l)
@@ -842,28 +1025,34 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     double mu = 0.0;
     for (int l = 0; l < m->n_dir; ++l) mu += m->dir_w[l] * m->dirs3[l * 3 + g] * m->dirs3[l * 3 + g];
     if (!(mu > 0.0)) return fail(OBTE_ERR_ARG, "directions have no component along the gradient axis");
-    m->alpha.assign(m->n_sys, 0.0);
-    double asum = 0.0;
-    for (int mm = 0; mm < m->n_mfp; ++mm)
-        for (int l = 0; l < m->n_dir; ++l) {
-            const double a = m->kappa_m[mm] * m->dir_w[l] / (m->mfp[mm] * m->mfp[mm] * mu);
-            m->alpha[mm * m->n_dir + l] = a;
-            asum += a;
-        }
-    if (!(asum > 0.0)) return fail(OBTE_ERR_ARG, "kappa_m is all zero");
-    m->Dw.assign(m->n_sys, 0.0);
-    m->S.assign(3 * m->n_sys, 0.0);
-    m->kappa_axis.assign(3, 0.0);
-    for (int mm = 0; mm < m->n_mfp; ++mm)
-        for (int l = 0; l < m->n_dir; ++l) {
-            const int sys = mm * m->n_dir + l;
-            const double a = m->alpha[sys];
-            m->Dw[sys] = a / asum;
-            for (int ax = 0; ax < 3; ++ax) {
-                m->S[sys * 3 + ax] = a * m->mfp[mm] * m->dirs3[l * 3 + ax];
-                m->kappa_axis[ax] += a * m->mfp[mm] * m->mfp[mm] * m->dirs3[l * 3 + ax] * m->dirs3[l * 3 + ax];
+    m->n_modes = 0;
+    if (modes) {
+        obte_status sm = mode_weights(m, d);
+        if (sm != OBTE_OK) { m->n_modes = 0; return sm; }
+    } else {
+        m->alpha.assign(m->n_sys, 0.0);
+        double asum = 0.0;
+        for (int mm = 0; mm < m->n_mfp; ++mm)
+            for (int l = 0; l < m->n_dir; ++l) {
+                const double a = m->kappa_m[mm] * m->dir_w[l] / (m->mfp[mm] * m->mfp[mm] * mu);
+                m->alpha[mm * m->n_dir + l] = a;
+                asum += a;
             }
-        }
+        if (!(asum > 0.0)) return fail(OBTE_ERR_ARG, "kappa_m is all zero");
+        m->Dw.assign(m->n_sys, 0.0);
+        m->S.assign(3 * m->n_sys, 0.0);
+        m->kappa_axis.assign(3, 0.0);
+        for (int mm = 0; mm < m->n_mfp; ++mm)
+            for (int l = 0; l < m->n_dir; ++l) {
+                const int sys = mm * m->n_dir + l;
+                const double a = m->alpha[sys];
+                m->Dw[sys] = a / asum;
+                for (int ax = 0; ax < 3; ++ax) {
+                    m->S[sys * 3 + ax] = a * m->mfp[mm] * m->dirs3[l * 3 + ax];
+                    m->kappa_axis[ax] += a * m->mfp[mm] * m->mfp[mm] * m->dirs3[l * 3 + ax] * m->dirs3[l * 3 + ax];
+                }
+            }
+    }
     // outgoing wall weights per face orientation
     m->wout.assign((size_t)m->nf * m->n_sys, 0.0);
     for (int f = 0; f < m->nf; ++f) {
@@ -874,6 +1063,14 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
         for (int sys = 0; sys < m->n_sys; ++sys)
             m->wout[(size_t)f * m->n_sys + sys] = tot > 0.0 ? std::max(0.0, m->S[sys * 3 + ax] * sg) / tot : 0.0;
     }
+    // a wall weight on the face a system's direction enters through (S and
+    // the direction disagree in sign: only with a mode table)
+    m->wall_in = 0;
+    for (int f = 0; f < m->nf && m->nwalls > 0; ++f)
+        for (int sys = 0; sys < m->n_sys; ++sys) {
+            const bool out_face = (m->dirs3[(sys % m->n_dir) * 3 + (f >> 1)] > 0.0) == ((f & 1) != 0);
+            if (!out_face && m->wout[(size_t)f * m->n_sys + sys] > 0.0) m->wall_in = 1;
+        }
     // device tables
     free_dev(m);
     HIPCHK(hipGetDevice(&m->device));
@@ -888,6 +1085,13 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     if ((s = upload(&m->d_S, m->S)) != OBTE_OK) return s;
     if ((s = upload(&m->d_wout, m->wout)) != OBTE_OK) return s;
     if ((s = upload(&m->d_kax, m->kappa_axis)) != OBTE_OK) return s;
+    if (m->n_modes > 0) {
+        if ((s = upload(&m->d_mode_sys, m->mode_sys)) != OBTE_OK) return s;
+        if ((s = upload(&m->d_mode_w, m->mode_w)) != OBTE_OK) return s;
+        if ((s = upload(&m->d_mode_Sg, m->mode_Sg)) != OBTE_OK) return s;
+        HIPCHK(hipMalloc((void**)&m->d_kmode, (size_t)m->n_modes * sizeof(double)));
+    }
+    m->modes_solved = false;
     HIPCHK(hipMalloc((void**)&m->d_geom, sizeof(GeomDev)));
     GeomDev v = make_view(m, nullptr, Layout{}, 0, 0, 0);
     HIPCHK(hipMemcpy(m->d_geom, &v, sizeof v, hipMemcpyHostToDevice));
@@ -936,6 +1140,14 @@ obte_status obte_solve_batch(obte_mesh* const* meshes, int n, const obte_solve_o
     if (o && o->keep_state) return fail(OBTE_ERR_ARG, "keep_state is not supported by the batch entry point");
     return solve_impl(meshes, n, o, sigma_dev, workspace, ws_bytes, stream, nullptr, nullptr, kappa_out,
                       stats, false);
+}
+
+obte_status obte_kappa_modes(const obte_mesh* m, double* kappa_mode) {
+    if (!m || !kappa_mode) return fail(OBTE_ERR_ARG, "NULL argument");
+    if (m->n_modes <= 0) return fail(OBTE_ERR_STATE, "the material has no mode table");
+    if (!m->modes_solved) return fail(OBTE_ERR_STATE, "no solve with passes has completed on this mesh");
+    for (int i = 0; i < m->n_modes; ++i) kappa_mode[i] = m->kappa_mode[i];
+    return OBTE_OK;
 }
 
 obte_status obte_kappa(const obte_mesh* m, double* kappa_eff, double* kappa_per_mfp) {
@@ -1123,5 +1335,6 @@ int obte_mesh_n_cells(const obte_mesh* m) { return m ? m->ncells : -1; }
 int obte_mesh_n_solid(const obte_mesh* m) { return m ? m->nsolid : -1; }
 int obte_mesh_n_walls(const obte_mesh* m) { return m ? m->nwalls : -1; }
 int obte_mesh_n_systems(const obte_mesh* m) { return m ? m->n_sys : -1; }
+int obte_mesh_n_modes(const obte_mesh* m) { return m ? m->n_modes : -1; }
 
 }  // extern "C"

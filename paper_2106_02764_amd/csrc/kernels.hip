@@ -195,6 +195,7 @@ struct Red {
     int local;        // item index within the geometry
     int want_J, store_T;
     int NV;           // slot rows per wave (red_rows)
+    int wall_in;      // forward: also the walls a system meets against its direction
     double kacc, kface;
     gmut_t<double> pTL, pTw, pG, pJ;   // this item's partial rows
     gmut_t<double> Tstore;             // this system's stored state (or null)
@@ -440,6 +441,17 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                     wall_here = true;
                 }
             }
+            if (!adj && rd->wall_in) {
+                // the wall's outgoing-flux weights follow S, which (mode
+                // tables) may leave through the face this direction enters by
+                const int xr = 1 + ND + (rd->want_J ? ND : 0);
+                for (int ax = 0; ax < ND; ++ax) {
+                    if (p < nx && fc_solid(wv) && fc_class(wv, s.fin[ax]) == FC_WALL) {
+                        slot[(size_t)(xr + ax) * ROW] = g.wout[s.fin[ax] * g.n_sys + s.sys] * xv;
+                        wall_here = true;
+                    }
+                }
+            }
             if (adj) {
                 slot[(size_t)(1 + ND) * ROW] = gp;
             } else if (rd->want_J) {
@@ -467,6 +479,16 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                     const double sw = slot_sum(buf, W, NV, ROW, 1 + ax, p);
                     gmut_t<double> dw = rd->pTw + (size_t)ax * rd->ncells + cell;
                     *dw = ADD ? *dw + sw : sw;
+                }
+                if (!adj && rd->wall_in) {
+                    const int xr = 1 + ND + (rd->want_J ? ND : 0);
+                    for (int ax = 0; ax < ND; ++ax) {
+                        if (fc_class(wv, s.fin[ax]) != FC_WALL) continue;
+                        const double sw = slot_sum(buf, W, NV, ROW, xr + ax, p);
+                        gmut_t<double> dw =
+                            gmut(g.part_Twi + ((size_t)rd->local * g.ndim + ax) * rd->ncells + cell);
+                        *dw = ADD ? *dw + sw : sw;
+                    }
                 }
             }
             if (adj) {
@@ -500,18 +522,23 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
                                       IO& io, Red* rd, T* zrows) {
     constexpr int ND = D3 ? 3 : 2;
     double mb[3], wo[3];
+    // boundary input face per axis: forward, the wall this direction enters
+    // from; adjoint, the wall whose temperature takes this system, the one
+    // that S leaves through (with kappa_m weights: the reversed inflow face)
+    int fb[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        mb[ax] = adj ? (ax < ND ? g.wout[s.fin[ax] * g.n_sys + s.sys] : 0.0) : s.cd[ax];
+        fb[ax] = adj ? 2 * ax + (s.S[ax] > 0.0 ? 1 : 0) : s.fin[ax];
+        mb[ax] = adj ? (ax < ND ? g.wout[fb[ax] * g.n_sys + s.sys] : 0.0) : s.cd[ax];
         wo[ax] = ax < ND ? g.wout[s.fout[ax] * g.n_sys + s.sys] : 0.0;
     }
     Views<T> vw;
     vw.fc = gview(g.fc);
     vw.sg = gview(sigma_ptr<T>(g));
     vw.src = gview(srcbase);
-    vw.bx = gview(bnd + (size_t)s.fin[0] * g.ncells);
-    vw.by = gview(bnd + (size_t)s.fin[1] * g.ncells);
-    vw.bz = gview(bnd + (size_t)(D3 ? s.fin[2] : 0) * g.ncells);
+    vw.bx = gview(bnd + (size_t)fb[0] * g.ncells);
+    vw.by = gview(bnd + (size_t)fb[1] * g.ncells);
+    vw.bz = gview(bnd + (size_t)(D3 ? fb[2] : 0) * g.ncells);
     Rows<T, CPL, D3> rows;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) rows.xr[c] = T(0);
@@ -679,6 +706,7 @@ __device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s
             g.ksys[s.sys] = kf;                 // this system's share of p^T lambda
             g.kfsys[s.sys] = 0.0;
         } else {
+            g.kraw[s.sys] = ks;
             g.ksys[s.sys] = g.L[g.grad_axis] / (g.dT * (double)g.ncells) * s.Sg * ks;
             g.kfsys[s.sys] = g.L[g.grad_axis] / (g.dT * (double)g.n_perp) * s.Sg * kf;
         }
@@ -744,7 +772,8 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     rd.store_T = pp.store_T;
     rd.kacc = 0.0;
     rd.kface = 0.0;
-    rd.NV = red_rows(2, adj, pp.want_J);
+    rd.NV = red_rows(2, adj, pp.want_J, g.wall_in);
+    rd.wall_in = g.wall_in;
     rd.ncells = g.ncells;
     rd.pTL = gmut(g.part_TL + (size_t)item.local * g.ncells);
     rd.pTw = gmut(g.part_Tw + (size_t)item.local * g.ndim * g.ncells);
@@ -905,7 +934,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     const gmut_t<T> xl = K + (size_t)KV_XL * nw;
     const gmut_t<T> du = K + (size_t)KV_DU * nw;
     // per-wave LDS: the reduction rows, then nz rows of this wave
-    const int NVR = red_rows(3, adj, pp.want_J);
+    const int NVR = red_rows(3, adj, pp.want_J, g.wall_in);
     T* zrows = reinterpret_cast<T*>(lds + (size_t)2 * W * NVR * WAVE * CPL) + (size_t)w * nz * WAVE * CPL;
     Red rd;
     rd.lds = lds;
@@ -917,7 +946,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     rd.store_T = pp.store_T;
     rd.kacc = 0.0;
     rd.kface = 0.0;
-    rd.NV = red_rows(3, adj, pp.want_J);
+    rd.NV = NVR;
+    rd.wall_in = g.wall_in;
     rd.ncells = g.ncells;
     rd.pTL = gmut(g.part_TL + (size_t)item.local * g.ncells);
     rd.pTw = gmut(g.part_Tw + (size_t)item.local * g.ndim * g.ncells);
@@ -1125,9 +1155,15 @@ __global__ void __launch_bounds__(256) k_reduce_pass(const GeomDev* __restrict__
         const int cell = g.wall_cell[wi];
         for (int i = lane; i < g.n_items; i += 64) {
             const int l = i / g.n_grp;          // items are ordered (l, MFP group)
-            const double sn = g.dirs[l * 3 + ax] * nsgn;
-            if ((!adj && sn > 0.0) || (adj && sn < 0.0))
-                a += g.part_Tw[((size_t)i * g.ndim + ax) * g.ncells + cell];
+            const double sd = g.dirs[l * 3 + ax];
+            const size_t at = ((size_t)i * g.ndim + ax) * g.ncells + cell;
+            if (adj) {
+                if (sd * nsgn < 0.0) a += g.part_Tw[at];
+            } else if ((sd > 0.0) == ((f & 1) != 0)) {
+                a += g.part_Tw[at];             // the face is this direction's outflow face
+            } else if (g.wall_in) {
+                a += g.part_Twi[at];
+            }
         }
         a = wave_sum(a);
         if (lane == 0) {
@@ -1914,9 +1950,104 @@ hipError_t launch_reduce_pass(const GeomDev* geoms_dev, int n_geoms, int max_cel
     return hipGetLastError();
 }
 
+// Gauge of the outer iteration with a mode table.  The interpolated weights
+// do not conserve energy exactly (S_ml is not alpha_ml Lambda_m s_l), so the
+// pass map has no fixed point: its iterates drift by a common constant each
+// pass, which no conductivity sees.  Removing that drift (the mean lattice
+// temperature over the solid cells is set back to 0 after every pass) leaves
+// a map with a fixed point, which Anderson mixing and the lagged wrap need.
+// The stored wrap inflows stay as they are: re-centred, the next inputs are
+// close to this pass's, whose inflows they hold.  ax[n_aa] carries the shift
+// from the first kernel to the second.
+__global__ void __launch_bounds__(256) k_gauge_mean(const GeomDev* __restrict__ geoms) {
+    __shared__ double red[32];
+    const GeomDev& g = geoms[blockIdx.x];
+    if (!g.gauge || g.ctrl[CTRL_DONE]) return;
+    double s = 0.0, ns = 0.0;
+    for (int c = threadIdx.x; c < g.ncells; c += blockDim.x)
+        if (fc_solid(g.fc[c])) { s += g.T_L[c]; ns += 1.0; }
+    s = block_sum(s, red);
+    ns = block_sum(ns, red);
+    if (threadIdx.x == 0) g.ax[g.n_aa] = ns > 0.0 ? s / ns : 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_gauge_apply(const GeomDev* __restrict__ geoms) {
+    const GeomDev& g = geoms[blockIdx.y];
+    if (!g.gauge || g.ctrl[CTRL_DONE]) return;
+    const double d = g.ax[g.n_aa];
+    const int out = (g.ctrl[CTRL_PASS] + 1) & 1;
+    const int nc = g.ncells;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) {
+        if (!fc_solid(g.fc[i])) return;
+        if (g.aa_m > 0) {
+            g.ag[i] -= d;
+        } else {
+            g.sT[(size_t)out * nc + i] -= g.sigma[i] * d;
+            g.ax[i] -= d;
+        }
+    } else if (i < nc + g.nwalls) {
+        const int wi = i - nc;
+        if (g.aa_m > 0) {
+            g.ag[i] -= d;
+        } else {
+            g.Tw[(size_t)out * g.nwalls + wi] -= d;
+            g.ax[i] -= d;
+            g.bnd[((size_t)out * g.nf + g.wall_face[wi]) * nc + g.wall_cell[wi]] -= d;
+        }
+    }
+}
+
+hipError_t launch_gauge(const GeomDev* geoms_dev, int n_geoms, int max_aa, hipStream_t st) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_gauge_mean, dim3(n_geoms), dim3(256), 0, st, geoms_dev);
+    hipLaunchKernelGGL(k_gauge_apply, dim3((max_aa + 255) / 256, n_geoms), dim3(256), 0, st, geoms_dev);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const GeomDev* geoms_dev, int n_geoms, PassParams pp, hipStream_t st) {
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_finalize, dim3(n_geoms), dim3(256), 0, st, geoms_dev, pp);
+    return hipGetLastError();
+}
+
+// Mode-resolved kappa (paper Eq. mode-resolved, cell-centred form): a gather
+// of the per-system sums with each mode's interpolation weights, measured
+// from the mean lattice temperature (sum_i T_L,i = sum_ml D_ml sum_i T_iml;
+// the weights of a mode add up to 1).  One block: the D-weighted total in a
+// fixed-order tree, then the modes strided over the threads.
+__global__ void __launch_bounds__(256) k_kappa_modes(const int* __restrict__ sys, const double* __restrict__ w,
+                                                     const double* __restrict__ Sg, int n_modes, int terms,
+                                                     const double* __restrict__ D, int n_sys,
+                                                     const double* __restrict__ kraw, double pref,
+                                                     double* __restrict__ out) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    double a = 0.0;
+    for (int i = t; i < n_sys; i += 256) a += D[i] * kraw[i];
+    red[t] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const double tot_L = red[0];
+    for (int mu = t; mu < n_modes; mu += 256) {
+        double s = 0.0;
+        for (int k = 0; k < terms; ++k) {
+            const double c = w[(size_t)mu * terms + k];
+            if (c != 0.0) s += c * kraw[sys[(size_t)mu * terms + k]];
+        }
+        out[mu] = pref * Sg[mu] * (s - tot_L);
+    }
+}
+
+hipError_t launch_kappa_modes(const int* sys, const double* w, const double* Sg, int n_modes, int terms,
+                              const double* D, int n_sys, const double* kraw, double pref, double* out,
+                              hipStream_t st) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_kappa_modes, dim3(1), dim3(256), 0, st, sys, w, Sg, n_modes, terms, D, n_sys, kraw,
+                       pref, out);
     return hipGetLastError();
 }
 

@@ -19,9 +19,10 @@ enum { CTRL_DONE = 0, CTRL_PASS = 1, CTRL_CONVERGED = 2, CTRL_NONFINITE = 3, CTR
 constexpr int KRY3_VECS = 11;
 // reduction rows per wave in the pass kernels' LDS: T_L and the walls (one
 // per axis), then the gradient partial (adjoint) or the flux (per axis, only
-// when the flux map is wanted)
-__host__ __device__ constexpr int red_rows(int ndim, int adjoint, int want_J) {
-    return 1 + ndim + (adjoint ? 1 : (want_J ? ndim : 0));
+// when the flux map is wanted), then (forward, wall_in) the walls a system
+// reaches against its direction (one per axis)
+__host__ __device__ constexpr int red_rows(int ndim, int adjoint, int want_J, int wall_in = 0) {
+    return 1 + ndim + (adjoint ? 1 : (want_J ? ndim : 0)) + ((!adjoint && wall_in) ? ndim : 0);
 }
 
 // Per-geometry view used by every kernel: static tables (library-owned) plus
@@ -91,6 +92,15 @@ struct GeomDev {
     double* adF;                 // aa_m * n_aa: residual differences (ring)
     double* agram;               // aa_m * aa_m Gram matrix of the adF columns, then aa_m |adX_j|^2
     double* apart;               // per-block partial sums of the mixing kernels
+    double* kraw;                // n_sys: sum over cells of each system's last solution
+    // 1 when some system's flux weight S points out of a wall face that its
+    // direction enters through (mode tables only): the wall temperature then
+    // also takes those systems, through part_Twi [item][ndim][ncells]
+    int wall_in;
+    double* part_Twi;
+    // 1 with a mode table: the outer iterates are re-centred every pass
+    // (ax[n_aa] holds the shift between the two gauge kernels)
+    int gauge;
     int* actl;                   // 2 x 4 (by pass parity): stored columns, ring head, previous pass valid
 };
 
@@ -138,6 +148,13 @@ hipError_t launch_reduce_pass(const GeomDev* geoms_dev, int n_geoms, int max_cel
 // Anderson mixing: per-block partials (up to 256 blocks of 256 threads per
 // geometry, 2 * AA_MAX + 3 sums each), then the combination.
 constexpr size_t aa_partial_doubles() { return 256 * (2 * AA_MAX + 3); }
+// kappa_mu = pref * Sg_mu * (sum_k w_k kraw[sys_k] - sum_s D_s kraw[s]) for
+// every mode (terms per mode fixed, unused terms carry weight 0).
+hipError_t launch_kappa_modes(const int* sys, const double* w, const double* Sg, int n_modes, int terms,
+                              const double* D, int n_sys, const double* kraw, double pref, double* out,
+                              hipStream_t st);
+// re-centre T_L / T_w of the geometries with gauge = 1 (forward passes)
+hipError_t launch_gauge(const GeomDev* geoms_dev, int n_geoms, int max_aa, hipStream_t st);
 hipError_t launch_anderson(const GeomDev* geoms_dev, int n_geoms, int max_naa, PassParams pp, hipStream_t st);
 hipError_t launch_finalize(const GeomDev* geoms_dev, int n_geoms, PassParams pp, hipStream_t st);
 hipError_t launch_output(const GeomDev* geoms_dev, int n_geoms, double* T_L_out, double* J_out,

@@ -38,7 +38,8 @@ class obte_mesh_desc(C.Structure):
 class obte_material_desc(C.Structure):
     _fields_ = [("n_mfp", C.c_int), ("mfp", C.POINTER(C.c_double)), ("n_dir", C.c_int),
                 ("dirs", C.POINTER(C.c_double)), ("dir_w", C.POINTER(C.c_double)),
-                ("kappa_m", C.POINTER(C.c_double))]
+                ("kappa_m", C.POINTER(C.c_double)), ("n_modes", C.c_int),
+                ("mode_F", C.POINTER(C.c_double)), ("mode_alpha", C.POINTER(C.c_double))]
 
 
 class obte_solve_opts(C.Structure):
@@ -76,6 +77,7 @@ EXPORTS = {
                                    C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_void_p,
                                    C.POINTER(C.c_double), C.POINTER(obte_stats)]),
     "obte_kappa": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "obte_kappa_modes": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "obte_adjoint": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.c_void_p, C.c_void_p,
                                C.c_size_t, C.c_void_p, C.c_void_p, C.POINTER(obte_stats)]),
     "obte_upwind_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
@@ -88,6 +90,7 @@ EXPORTS = {
     "obte_mesh_n_solid": (C.c_int, [C.c_void_p]),
     "obte_mesh_n_walls": (C.c_int, [C.c_void_p]),
     "obte_mesh_n_systems": (C.c_int, [C.c_void_p]),
+    "obte_mesh_n_modes": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None
@@ -155,8 +158,10 @@ def obte_mesh_create(ndim, n, L, solid, periodic, grad_axis=0, dT_ext=1.0):
     return h
 
 
-def obte_material_set(mesh, mfp, dirs, dir_w, kappa_m):
-    mfp, dirs, dir_w, kappa_m = _f64(mfp), _f64(dirs), _f64(dir_w), _f64(kappa_m)
+def obte_material_set(mesh, mfp, dirs, dir_w, kappa_m, modes=None):
+    """modes = (F (n_modes, ndim), alpha (n_modes,)) or None; with a mode
+    table kappa_m is ignored (may be None)."""
+    mfp, dirs, dir_w = _f64(mfp), _f64(dirs), _f64(dir_w)
     d = obte_material_desc()
     P = C.POINTER(C.c_double)
     d.n_mfp = len(mfp)
@@ -164,8 +169,25 @@ def obte_material_set(mesh, mfp, dirs, dir_w, kappa_m):
     d.n_dir = len(dir_w)
     d.dirs = dirs.ctypes.data_as(P)
     d.dir_w = dir_w.ctypes.data_as(P)
-    d.kappa_m = kappa_m.ctypes.data_as(P)
+    keep = []
+    if kappa_m is not None:
+        kappa_m = _f64(kappa_m)
+        d.kappa_m = kappa_m.ctypes.data_as(P)
+    if modes is not None:
+        F, alpha = _f64(modes[0]), _f64(modes[1])
+        keep = [F, alpha]
+        d.n_modes = len(alpha)
+        d.mode_F = F.ctypes.data_as(P)
+        d.mode_alpha = alpha.ctypes.data_as(P)
     _check(lib().obte_material_set(mesh, C.byref(d)))
+    del keep
+
+
+def obte_kappa_modes(mesh):
+    n = lib().obte_mesh_n_modes(mesh)
+    out = np.zeros(max(n, 0))
+    _check(lib().obte_kappa_modes(mesh, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
 
 
 def obte_workspace_size(mesh, opts):

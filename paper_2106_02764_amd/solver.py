@@ -13,12 +13,13 @@ class Solver:
     """Owns one obte_mesh handle and a device workspace (torch tensor)."""
 
     def __init__(self, ndim, n, L, solid, periodic, grad_axis, dT, mfp, dirs, dir_w, kappa_m,
-                 device="cuda"):
+                 device="cuda", modes=None):
         self.ndim = ndim
         self.n = tuple(int(v) for v in n)
         self.device = torch.device(device)
         self.mesh = _o.obte_mesh_create(ndim, n, L, solid, periodic, grad_axis, dT)
-        _o.obte_material_set(self.mesh, mfp, dirs, dir_w, kappa_m)
+        _o.obte_material_set(self.mesh, mfp, dirs, dir_w, kappa_m, modes=modes)
+        self.n_modes = 0 if modes is None else len(modes[1])
         c = _o.obte_mesh_counts(self.mesh)
         self.n_cells, self.n_solid, self.n_walls, self.n_systems = (
             c["n_cells"], c["n_solid"], c["n_walls"], c["n_systems"])
@@ -33,7 +34,7 @@ class Solver:
     @classmethod
     def from_workload(cls, w, device="cuda"):
         return cls(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT, w.mfp, w.dirs,
-                   w.dir_w, w.kappa_m, device=device)
+                   w.dir_w, w.kappa_m, device=device, modes=getattr(w, "modes", None))
 
     def opts(self, **kw):
         return _o.default_opts(**kw)
@@ -75,6 +76,10 @@ class Solver:
 
     def kappa(self):
         return _o.obte_kappa(self.mesh, self.n_mfp)
+
+    def kappa_modes(self):
+        """Mode-resolved conductivity of the last solve (mode table only)."""
+        return _o.obte_kappa_modes(self.mesh)
 
     def adjoint(self, opts, stream=None):
         g = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)

@@ -84,6 +84,33 @@ def test_material_set_rejects_on_host(L, bad):
     L.obte_mesh_destroy(h)
 
 
+@pytest.mark.parametrize("bad", ["netflux", "alpha", "zero_mfp", "dup_nodes", "nan"])
+def test_mode_table_rejects_on_host(L, bad):
+    """Mode-table validation happens before any device call."""
+    w = gen.with_modes(gen.small_2d(8, 6, n_dir=8, n_mfp=3), 20, 5)
+    h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
+    assert L.lib().obte_mesh_n_modes(h) == 0
+    F, alpha = w.modes[0].copy(), w.modes[1].copy()
+    mfp = w.mfp.copy()
+    if bad == "netflux":
+        F, alpha = F[1:], alpha[1:]          # drop one of a mirrored pair
+    elif bad == "alpha":
+        alpha[3] = -1.0
+    elif bad == "zero_mfp":
+        F[2] = 0.0
+        F[3] = 0.0
+    elif bad == "dup_nodes":
+        mfp[1] = mfp[0]
+    else:
+        F[4, 0] = np.nan
+    with pytest.raises(L.ObteError) as e:
+        L.obte_material_set(h, mfp, w.dirs, w.dir_w, None, modes=(F, alpha))
+    assert e.value.status == L.OBTE_ERR_ARG
+    out = np.zeros(4)
+    assert L.lib().obte_kappa_modes(h, out.ctypes.data_as(C.POINTER(C.c_double))) == L.OBTE_ERR_STATE
+    L.obte_mesh_destroy(h)
+
+
 def test_solve_state_errors_on_host(L):
     w = gen.small_2d(8, 6)
     h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
