@@ -295,7 +295,8 @@ def small_3d(nx: int, ny: int, nz: int, solid=None, n_theta: int = 4, n_phi: int
 
 
 def with_modes(w: Workload, n_modes: int, seed: int, on_node: bool = False,
-               mfp_lo: float | None = None, mfp_hi: float | None = None) -> Workload:
+               mfp_lo: float | None = None, mfp_hi: float | None = None, dim3: bool = False,
+               n_static: int = 0) -> Workload:
     """A copy of `w` whose material is a synthetic mode table.
 
     on_node: one mode per grid point F_ml = Lambda_m s_l with the kernel's
@@ -305,7 +306,9 @@ def with_modes(w: Workload, n_modes: int, seed: int, on_node: bool = False,
     bit beyond the grid, so some modes are clamped), uniform random directions,
     and weights from the same lognormal kernel in ln|F| (median 300 nm,
     sigma_ln 1.5) divided by |F|^2, scaled to a bulk conductivity of 150 W/m/K
-    along the gradient axis."""
+    along the gradient axis.  dim3 (2D workloads): 3D modes, directions
+    uniform on the sphere (the library keeps their in-plane part); n_static
+    more modes moving only along z (zero in-plane MFP), weight like the rest."""
     import dataclasses
     rng = np.random.default_rng(seed)
     nd = w.ndim
@@ -318,6 +321,18 @@ def with_modes(w: Workload, n_modes: int, seed: int, on_node: bool = False,
     hi = w.mfp.max() * 2 if mfp_hi is None else mfp_hi
     half = n_modes // 2
     lam = np.exp(rng.uniform(np.log(lo), np.log(hi), half))
+    if dim3 and nd == 2:
+        v = rng.standard_normal((half, 3))
+        s = v / np.linalg.norm(v, axis=1, keepdims=True)
+        F = np.concatenate([lam[:, None] * s, -lam[:, None] * s])
+        lam2 = np.concatenate([lam, lam])
+        alpha = np.exp(-np.log(lam2 / 300e-9) ** 2 / (2 * 1.5 ** 2)) / lam2 ** 2
+        if n_static:
+            fz = np.exp(rng.uniform(np.log(lo), np.log(hi), n_static))
+            F = np.concatenate([F, np.stack([0 * fz, 0 * fz, fz], axis=1)])
+            alpha = np.concatenate([alpha, np.exp(-np.log(fz / 300e-9) ** 2 / (2 * 1.5 ** 2)) / fz ** 2])
+        alpha *= 150.0 / float(np.sum(alpha * F[:, w.grad_axis] ** 2))
+        return dataclasses.replace(w, modes=(F, alpha), name=w.name + f"_modes3d{n_modes}")
     if nd == 2:
         ph = rng.uniform(0.0, 2.0 * math.pi, half)
         s = np.stack([np.cos(ph), np.sin(ph)], axis=1)

@@ -35,11 +35,13 @@ class Material:
         self.modes = modes
         if modes is not None:
             # grid weights interpolated from a mode table (oracle/modes.py)
-            from .modes import grid_weights
+            from .modes import grid_weights, project
             F, alpha = modes
             self.mu = float(np.sum(dir_w * dirs[:, grad_axis] ** 2))
             self.D, self.S, self.kappa_axis = grid_weights(mfp, dirs, F, alpha, grad_axis)
-            self.alpha = self.D * float(np.sum(alpha))   # sum alpha_mu c: the T_L weights unnormalised
+            # sum alpha_mu c over the moving modes: the T_L weights unnormalised
+            moving = np.linalg.norm(project(F, dirs.shape[1]), axis=1) > 0.0
+            self.alpha = self.D * float(np.sum(np.asarray(alpha, float)[moving]))
             return
         w = material_weights(mfp, dirs, dir_w, kappa_m, grad_axis)
         self.mu = w["mu"]

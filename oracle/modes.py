@@ -20,6 +20,14 @@ single mode's share does (by S_mu,g times the constant).  The paper does not
 say which constant (reading: deviations from the mean lattice temperature
 over the solid cells, <T_L> = sum_ml D_ml sum_i T_iml / N_solid, so each
 kappa_mu is unchanged when every T moves by the same amount).
+
+Section Material, rta2DSym: a 2D domain (uniform along z) takes 3D modes
+through their in-plane part F_mu,xy; the out-of-plane part does not enter the
+2D transport operator.  A mode whose vectorial MFP is zero (in 2D: one that
+moves only along z) satisfies T_mu = T_L exactly (Eq. iter3 with F_mu = 0),
+so it drops out of T_L = sum D T once the remaining weights are renormalised:
+such modes get no grid weight, D_mu is alpha_mu over the sum of alpha of the
+moving modes, and their kappa_mu is 0.
 """
 from __future__ import annotations
 
@@ -53,11 +61,22 @@ def _bracket_cyclic(angles, x):
     return [(a, 1.0 - t), (b, t)]
 
 
+def project(F, nd):
+    """The part of the vectorial MFPs a domain of nd dimensions sees
+    (rta2DSym: 3D modes in a 2D domain keep their in-plane components)."""
+    F = np.asarray(F, float)
+    if F.shape[1] < nd:
+        raise ValueError("mode table has fewer components than the domain")
+    return F[:, :nd]
+
+
 def interp_weights(mfp, dirs, F):
-    """For each mode the list of (m, l, c) with nonzero weight."""
+    """For each mode the list of (m, l, c) with nonzero weight (empty for a
+    mode with zero vectorial MFP)."""
     mfp = np.asarray(mfp, float)
     dirs = np.asarray(dirs, float)
     nd = dirs.shape[1]
+    F = project(F, nd)
     m_order = np.argsort(mfp)
     m_nodes = mfp[m_order]
     out = []
@@ -65,8 +84,11 @@ def interp_weights(mfp, dirs, F):
         ang = np.arctan2(dirs[:, 1], dirs[:, 0]) % (2 * math.pi)
         l_order = np.argsort(ang)
         l_nodes = ang[l_order]
-        for f in np.asarray(F, float):
+        for f in F:
             lam = float(np.hypot(f[0], f[1]))
+            if lam == 0.0:
+                out.append([])
+                continue
             wm = _bracket_linear(m_nodes, lam)
             wl = _bracket_cyclic(l_nodes, math.atan2(f[1], f[0]))
             out.append([(int(m_order[i]), int(l_order[j]), a * b) for i, a in wm for j, b in wl])
@@ -81,8 +103,11 @@ def interp_weights(mfp, dirs, F):
         index[key] = l
     if len(index) != len(th_nodes) * len(ph_nodes):
         raise ValueError("3D mode interpolation needs a tensor (polar x azimuth) direction grid")
-    for f in np.asarray(F, float):
+    for f in F:
         lam = float(np.linalg.norm(f))
+        if lam == 0.0:
+            out.append([])
+            continue
         wm = _bracket_linear(m_nodes, lam)
         wt = _bracket_linear(th_nodes, math.acos(max(-1.0, min(1.0, f[2] / lam))))
         wp = _bracket_cyclic(ph_nodes, math.atan2(f[1], f[0]))
@@ -94,12 +119,13 @@ def interp_weights(mfp, dirs, F):
 def grid_weights(mfp, dirs, F, alpha, grad_axis=0):
     """D (n_mfp, n_dir), S (n_mfp, n_dir, ndim) and the Fourier conductivity
     per axis sum_mu alpha_mu F_mu,a^2 from a mode table."""
-    F = np.asarray(F, float)
     alpha = np.asarray(alpha, float)
     n_mfp, n_dir, nd = len(mfp), len(dirs), np.asarray(dirs).shape[1]
+    F = project(F, nd)
     D = np.zeros((n_mfp, n_dir))
     S = np.zeros((n_mfp, n_dir, nd))
-    Dmu = alpha / alpha.sum()
+    moving = np.linalg.norm(F, axis=1) > 0.0
+    Dmu = np.where(moving, alpha, 0.0) / alpha[moving].sum()
     for mu, terms in enumerate(interp_weights(mfp, dirs, F)):
         for m, l, c in terms:
             D[m, l] += c * Dmu[mu]
@@ -114,6 +140,7 @@ def kappa_modes(prob, T):
     lattice temperature)."""
     mat, me = prob.mat, prob.mesh
     F, alpha = mat.modes
+    F = project(F, mat.dirs.shape[1])
     g = me.grad_axis
     tot = T.sum(axis=2)                                   # sum_i T_iml
     tot_L = float(np.sum(mat.D * tot))                    # sum_i T_L,i = N_solid <T_L>

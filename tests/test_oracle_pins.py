@@ -455,3 +455,34 @@ def test_modes_bulk_closed_form_and_sum_rule():
     km2 = kappa_modes(p, r["T"] + 0.37)
     assert np.max(np.abs(km2 - km)) < 1e-12 * abs(r["kappa_cc"])
 
+
+
+def test_modes_projection_and_static_modes():
+    """3D modes in a 2D domain act through their in-plane part, and modes
+    with zero in-plane MFP (T_mu = T_L exactly) drop out: appending them,
+    with any weight, leaves the solution unchanged."""
+    from oracle.modes import grid_weights
+    w0 = gen.small_2d(10, 8, solid=gen.square_block_mask(10, 8, 3, 6), n_dir=8, n_mfp=3)
+    w3 = gen.with_modes(w0, 40, 13, dim3=True)
+    ws = gen.with_modes(w0, 40, 13, dim3=True, n_static=7)
+    F3, a3 = w3.modes
+    Fs, as_ = ws.modes
+    assert Fs.shape[1] == 3 and np.all(Fs[40:, :2] == 0.0)
+    assert np.array_equal(Fs[:40], F3)
+    # the in-plane part explicitly (2 columns) gives the same grid weights
+    D2, S2, k2 = grid_weights(w0.mfp, w0.dirs, F3[:, :2], a3)
+    D3, S3, k3 = grid_weights(w0.mfp, w0.dirs, F3, a3)
+    assert np.array_equal(D2, D3) and np.array_equal(S2, S3) and np.array_equal(k2, k3)
+    # static modes: same D after renormalisation over the moving ones
+    Dst, Sst, kst = grid_weights(w0.mfp, w0.dirs, Fs, as_ * 1.0)
+    scale = as_[:40].sum() / a3.sum()
+    assert np.allclose(Sst, S3 * scale, rtol=1e-14, atol=0)
+    assert np.allclose(Dst, D3, rtol=1e-14, atol=0)
+    p3, ps = Problem(w3), Problem(ws)
+    r3 = source_iteration(p3, tol=1e-13)
+    rs = source_iteration(ps, tol=1e-13)
+    assert abs(rs["kappa_cc"] - scale * r3["kappa_cc"]) < 1e-11 * abs(r3["kappa_cc"])
+    assert np.allclose(rs["T_L"], r3["T_L"], rtol=0, atol=1e-11)
+    km = kappa_modes(ps, rs["T"])
+    assert np.all(km[40:] == 0.0)
+    assert abs(km.sum() - rs["kappa_cc"]) < 1e-12 * abs(rs["kappa_cc"])
