@@ -49,6 +49,9 @@ class Workload:
     # optional mode table: (F (n_modes, ndim) vectorial MFPs in metres,
     # alpha (n_modes,) C/tau weights); when set, the grid weights come from it
     modes: tuple | None = None
+    # with a mode table: solve one system per mode (Eq. iter3) instead of
+    # interpolating onto the (MFP, direction) grid
+    modes_exact: bool = False
 
     @property
     def n_cells(self) -> int:

@@ -81,7 +81,7 @@ class Problem:
             mesh = Mesh(work.n, work.L, work.solid, work.periodic, work.grad_axis, work.dT,
                         ndim=work.ndim)
             mat = Material(work.mfp, work.dirs, work.dir_w, work.kappa_m, work.grad_axis,
-                           modes=getattr(work, "modes", None))
+                           modes=getattr(work, "modes", None), exact=getattr(work, "modes_exact", False))
             sigma = work.sigma
         self.mesh, self.mat = mesh, mat
         if sigma is None:

@@ -23,7 +23,7 @@ import numpy as np
 
 
 class Material:
-    def __init__(self, mfp, dirs, dir_w, kappa_m, grad_axis=0, modes=None):
+    def __init__(self, mfp, dirs, dir_w, kappa_m, grad_axis=0, modes=None, exact=False):
         mfp = np.asarray(mfp, float)
         dirs = np.asarray(dirs, float)
         dir_w = np.asarray(dir_w, float)
@@ -33,6 +33,29 @@ class Material:
         self.ndim = dirs.shape[1]
         self.grad_axis = grad_axis
         self.modes = modes
+        self.exact = bool(exact and modes is not None)
+        if self.exact:
+            # Eq. iter3: one system per moving mode, no interpolation.  The
+            # grid degenerates to one 'MFP' of 1 and the modes' own vectorial
+            # MFPs as transport vectors (the operators take F_mu directly).
+            from .modes import project
+            F, alpha = modes
+            alpha = np.asarray(alpha, float)
+            Fp = project(F, dirs.shape[1])
+            moving = np.linalg.norm(Fp, axis=1) > 0.0
+            Fm, am = Fp[moving], alpha[moving]
+            self.moving = np.flatnonzero(moving)
+            self.mfp = np.array([1.0])
+            self.dirs = Fm
+            self.dir_w = am / am.sum()
+            self.kappa_m = np.array([np.nan])
+            self.n_mfp, self.n_dir = 1, len(am)
+            self.mu = float("nan")
+            self.D = (am / am.sum())[None, :]
+            self.S = (am[:, None] * Fm)[None, :, :]
+            self.kappa_axis = np.array([np.sum(am * Fm[:, a] ** 2) for a in range(self.ndim)])
+            self.alpha = am[None, :].copy()
+            return
         if modes is not None:
             # grid weights interpolated from a mode table (oracle/modes.py)
             from .modes import grid_weights, project

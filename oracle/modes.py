@@ -11,6 +11,9 @@ azimuth, cyclic; 3D: polar bins times azimuth on a tensor direction grid;
 outside the MFP range, or beyond the outermost polar bin centres, the weight
 goes to the end node).
 
+Without interpolation (Eq. iter3, the mode-resolved iteration) every moving
+mode is its own system with transport vector F_mu (Material(..., exact=True)).
+
 The mode-resolved conductivity (Eq. mode-resolved) in the cell-centred form
 used for kappa_eff: kappa_mu = L S_mu,g / (dT N_tot) sum_ml c^mu_ml sum_i
 (T_iml - <T_L>), which sums to kappa_eff over the modes because S_ml =
@@ -146,7 +149,14 @@ def kappa_modes(prob, T):
     tot_L = float(np.sum(mat.D * tot))                    # sum_i T_L,i = N_solid <T_L>
     pref = me.L[g] / (me.dT * me.n_cells)
     out = np.zeros(len(alpha))
-    for mu, terms in enumerate(interp_weights(mat.mfp, mat.dirs, F)):
+    if mat.exact:
+        # one system per moving mode: c is the identity
+        terms_of = [[] for _ in range(len(alpha))]
+        for k, mu in enumerate(mat.moving):
+            terms_of[mu] = [(0, k, 1.0)]
+    else:
+        terms_of = interp_weights(mat.mfp, mat.dirs, F)
+    for mu, terms in enumerate(terms_of):
         # sum_ml c = 1: the interpolated sum of (T - <T_L>)
         out[mu] = pref * alpha[mu] * F[mu, g] * (sum(c * tot[m, l] for m, l, c in terms) - tot_L)
     return out

@@ -486,3 +486,38 @@ def test_modes_projection_and_static_modes():
     km = kappa_modes(ps, rs["T"])
     assert np.all(km[40:] == 0.0)
     assert abs(km.sum() - rs["kappa_cc"]) < 1e-12 * abs(rs["kappa_cc"])
+
+
+def test_exact_modes_on_nodes_equal_kernel_path():
+    """Eq. iter3 (one system per mode) with the modes on the grid nodes and
+    the kernel's weights is the grid problem itself, systems renumbered."""
+    import dataclasses
+    w0 = gen.small_2d(10, 8, solid=gen.square_block_mask(10, 8, 3, 6), n_dir=8, n_mfp=3)
+    we = dataclasses.replace(gen.with_modes(w0, 0, 0, on_node=True), modes_exact=True)
+    p0, pe = Problem(w0), Problem(we)
+    assert pe.mat.n_mfp == 1 and pe.mat.n_dir == 24
+    r0 = source_iteration(p0, tol=1e-13)
+    re = source_iteration(pe, tol=1e-13)
+    assert abs(re["kappa_cc"] - r0["kappa_cc"]) < 1e-11 * r0["kappa_cc"]
+    assert abs(re["kappa_face"] - r0["kappa_face"]) < 1e-11 * r0["kappa_face"]
+    assert np.allclose(re["T_L"], r0["T_L"], rtol=0, atol=1e-11)
+    # kappa_mu with c = I is the per-system share (from the mean T_L)
+    km = kappa_modes(pe, re["T"])
+    g = 0
+    tot_L = float(np.sum(p0.mat.D * r0["T"].sum(axis=2)))
+    shift = p0.mesh.L[g] / (p0.mesh.dT * p0.mesh.n_cells) * p0.mat.S[:, :, g] * tot_L
+    assert np.allclose(km, (r0["kappa_ml"] - shift).ravel(), rtol=1e-9, atol=1e-11 * r0["kappa_cc"])
+
+
+def test_exact_modes_bulk_closed_form():
+    """No pores: every mode's T - T_L is F_mu,x dT / L, so kappa = sum_mu
+    alpha_mu F_mu,x^2 and kappa_mu = alpha_mu F_mu,x^2 (static modes: 0)."""
+    import dataclasses
+    w = dataclasses.replace(gen.with_modes(gen.small_2d(8, 6, n_dir=8, n_mfp=3), 30, 3, dim3=True,
+                                           n_static=3), modes_exact=True)
+    p = Problem(w)
+    r = source_iteration(p, tol=1e-13)
+    F, alpha = w.modes
+    assert abs(r["kappa_cc"] - np.sum(alpha * F[:, 0] ** 2)) < 1e-11 * r["kappa_cc"]
+    km = kappa_modes(p, r["T"])
+    assert np.allclose(km, alpha * F[:, 0] ** 2, rtol=1e-10, atol=1e-12 * r["kappa_cc"])
