@@ -94,6 +94,18 @@ typedef struct {
     int n_modes;
     const double* mode_F;
     const double* mode_alpha;
+    /* Components per row of mode_F: 0 or ndim, or 3 with a 2D mesh (section
+     * Material, rta2DSym: the domain is uniform along z and each mode acts
+     * through its in-plane part).  A mode whose (in-plane) F is zero keeps
+     * T_mu = T_L and drops out: D is normalised over the moving modes and
+     * its kappa_mu is 0. */
+    int mode_dim;
+    /* 1: no interpolation (Eq. iter3, the mode-resolved iteration): every
+     * moving mode is its own system, transported along its own F_mu, with
+     * D_mu = alpha_mu / sum alpha and S_mu = alpha_mu F_mu.  n_mfp, mfp, dirs,
+     * dir_w and kappa_m are then ignored (may be 0 / NULL); the mesh has one
+     * system per moving mode. */
+    int modes_exact;
 } obte_material_desc;
 
 enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };

@@ -181,6 +181,10 @@ obte_status mode_weights(obte_mesh* m, const obte_material_desc* d) {
             lmap[k * phv.size() + j] = l;
         }
     }
+    // components per mode: ndim, or 3 in a 2D domain (the in-plane part is used)
+    const int md = d->mode_dim > 0 ? d->mode_dim : nd;
+    if (!(md == nd || (md == 3 && nd == 2)))
+        return fail(OBTE_ERR_ARG, "mode_dim %d does not fit a %dD mesh", d->mode_dim, nd);
     m->n_modes = nm;
     m->mode_sys.assign((size_t)nm * MODE_TERMS, 0);
     m->mode_w.assign((size_t)nm * MODE_TERMS, 0.0);
@@ -189,29 +193,31 @@ obte_status mode_weights(obte_mesh* m, const obte_material_desc* d) {
     for (int mu = 0; mu < nm; ++mu) {
         const double a = d->mode_alpha[mu];
         if (!(a >= 0.0) || !std::isfinite(a)) return fail(OBTE_ERR_ARG, "mode_alpha[%d] must be >= 0", mu);
-        asum += a;
         double lam2 = 0.0;
-        for (int ax = 0; ax < nd; ++ax) {
-            const double f = d->mode_F[mu * nd + ax];
+        for (int ax = 0; ax < md; ++ax) {
+            const double f = d->mode_F[mu * md + ax];
             if (!std::isfinite(f)) return fail(OBTE_ERR_ARG, "mode_F[%d] is not finite", mu);
+            if (ax >= nd) continue;
             lam2 += f * f;
             net[ax] += a * f;
             scale += a * std::fabs(f);
         }
-        if (!(lam2 > 0.0)) return fail(OBTE_ERR_ARG, "mode %d has a zero MFP", mu);
+        // a mode that does not move in this domain keeps T_L: it drops out
+        if (lam2 > 0.0) asum += a;
     }
-    if (!(asum > 0.0)) return fail(OBTE_ERR_ARG, "mode_alpha is all zero");
+    if (!(asum > 0.0)) return fail(OBTE_ERR_ARG, "no mode with a nonzero MFP and weight");
     for (int ax = 0; ax < nd; ++ax)
         if (std::fabs(net[ax]) > 1e-9 * scale) return fail(OBTE_ERR_ARG, "mode table carries a net flux along axis %d", ax);
     m->Dw.assign(m->n_sys, 0.0);
     m->S.assign(3 * m->n_sys, 0.0);
     m->kappa_axis.assign(3, 0.0);
     for (int mu = 0; mu < nm; ++mu) {
-        const double* F = &d->mode_F[mu * nd];
+        const double* F = &d->mode_F[mu * md];
         const double a = d->mode_alpha[mu];
         double lam = 0.0;
         for (int ax = 0; ax < nd; ++ax) lam += F[ax] * F[ax];
         lam = std::sqrt(lam);
+        if (lam == 0.0) continue;          // no grid weight, kappa_mu = 0
         int im[2], ip[2], it[2];
         double wm[2], wp[2], wt[2];
         const int nmm = bracket_linear(mv, lam, im, wm);
@@ -984,13 +990,11 @@ obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
     return OBTE_OK;
 }
 
-obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
-    if (!m || !d) return fail(OBTE_ERR_ARG, "NULL argument");
+// Material on the (MFP, direction) grid: kappa_m kernel or a mode table
+// interpolated onto it.
+obte_status grid_material(obte_mesh* m, const obte_material_desc* d, bool modes) {
     if (d->n_mfp < 1 || d->n_dir < 2) return fail(OBTE_ERR_ARG, "need n_mfp >= 1 and n_dir >= 2");
-    if (d->n_modes < 0) return fail(OBTE_ERR_ARG, "n_modes must be >= 0");
-    const bool modes = d->n_modes > 0;
     if (!d->mfp || !d->dirs || !d->dir_w || (!modes && !d->kappa_m)) return fail(OBTE_ERR_ARG, "NULL material array");
-    if (modes && (!d->mode_F || !d->mode_alpha)) return fail(OBTE_ERR_ARG, "NULL mode table array");
     const int nd = m->ndim;
     double wsum = 0.0;
     std::vector<double> ssum(3, 0.0);
@@ -1052,6 +1056,87 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
                     m->kappa_axis[ax] += a * m->mfp[mm] * m->mfp[mm] * m->dirs3[l * 3 + ax] * m->dirs3[l * 3 + ax];
                 }
             }
+    }
+    return OBTE_OK;
+}
+
+// Eq. iter3 without interpolation: one system per moving mode, its
+// vectorial MFP as the transport vector (stored as a direction with the
+// single MFP node 1).
+obte_status exact_modes(obte_mesh* m, const obte_material_desc* d) {
+    const int nd = m->ndim, nm = d->n_modes;
+    const int md = d->mode_dim > 0 ? d->mode_dim : nd;
+    if (!(md == nd || (md == 3 && nd == 2)))
+        return fail(OBTE_ERR_ARG, "mode_dim %d does not fit a %dD mesh", d->mode_dim, nd);
+    std::vector<int> moving;
+    double asum = 0.0, net[3] = {0.0, 0.0, 0.0}, scale = 0.0;
+    for (int mu = 0; mu < nm; ++mu) {
+        const double a = d->mode_alpha[mu];
+        if (!(a >= 0.0) || !std::isfinite(a)) return fail(OBTE_ERR_ARG, "mode_alpha[%d] must be >= 0", mu);
+        double lam2 = 0.0;
+        for (int ax = 0; ax < md; ++ax) {
+            const double f = d->mode_F[mu * md + ax];
+            if (!std::isfinite(f)) return fail(OBTE_ERR_ARG, "mode_F[%d] is not finite", mu);
+            if (ax >= nd) continue;
+            lam2 += f * f;
+            net[ax] += a * f;
+            scale += a * std::fabs(f);
+        }
+        if (lam2 > 0.0) { moving.push_back(mu); asum += a; }
+    }
+    if (!(asum > 0.0) || moving.size() < 2) return fail(OBTE_ERR_ARG, "no mode with a nonzero MFP and weight");
+    for (int ax = 0; ax < nd; ++ax)
+        if (std::fabs(net[ax]) > 1e-9 * scale) return fail(OBTE_ERR_ARG, "mode table carries a net flux along axis %d", ax);
+    const int n = (int)moving.size(), g = m->grad_axis;
+    m->n_mfp = 1;
+    m->n_dir = n;
+    m->n_sys = n;
+    m->mfp.assign(1, 1.0);
+    m->kappa_m.assign(1, 0.0);
+    m->dir_w.assign(n, 0.0);
+    m->dirs3.assign(3 * (size_t)n, 0.0);
+    m->alpha.assign(n, 0.0);
+    m->Dw.assign(n, 0.0);
+    m->S.assign(3 * (size_t)n, 0.0);
+    m->kappa_axis.assign(3, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const int mu = moving[k];
+        const double a = d->mode_alpha[mu];
+        m->alpha[k] = a;
+        m->Dw[k] = a / asum;
+        m->dir_w[k] = a / asum;
+        for (int ax = 0; ax < nd; ++ax) {
+            const double f = d->mode_F[mu * md + ax];
+            m->dirs3[k * 3 + ax] = f;
+            m->S[k * 3 + ax] = a * f;
+            m->kappa_axis[ax] += a * f * f;
+        }
+    }
+    if (!(m->kappa_axis[g] > 0.0)) return fail(OBTE_ERR_ARG, "no mode moves along the gradient axis");
+    m->n_modes = nm;
+    m->mode_sys.assign((size_t)nm * MODE_TERMS, 0);
+    m->mode_w.assign((size_t)nm * MODE_TERMS, 0.0);
+    m->mode_Sg.assign(nm, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const int mu = moving[k];
+        m->mode_sys[(size_t)mu * MODE_TERMS] = k;
+        m->mode_w[(size_t)mu * MODE_TERMS] = 1.0;
+        m->mode_Sg[mu] = m->S[k * 3 + g];
+    }
+    return OBTE_OK;
+}
+
+obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
+    if (!m || !d) return fail(OBTE_ERR_ARG, "NULL argument");
+    if (d->n_modes < 0) return fail(OBTE_ERR_ARG, "n_modes must be >= 0");
+    const bool modes = d->n_modes > 0;
+    if (modes && (!d->mode_F || !d->mode_alpha)) return fail(OBTE_ERR_ARG, "NULL mode table array");
+    m->n_modes = 0;
+    const obte_status sm = (modes && d->modes_exact) ? exact_modes(m, d) : grid_material(m, d, modes);
+    if (sm != OBTE_OK) {
+        m->n_modes = 0;
+        m->has_material = false;
+        return sm;
     }
     // outgoing wall weights per face orientation
     m->wout.assign((size_t)m->nf * m->n_sys, 0.0);

@@ -39,7 +39,8 @@ class obte_material_desc(C.Structure):
     _fields_ = [("n_mfp", C.c_int), ("mfp", C.POINTER(C.c_double)), ("n_dir", C.c_int),
                 ("dirs", C.POINTER(C.c_double)), ("dir_w", C.POINTER(C.c_double)),
                 ("kappa_m", C.POINTER(C.c_double)), ("n_modes", C.c_int),
-                ("mode_F", C.POINTER(C.c_double)), ("mode_alpha", C.POINTER(C.c_double))]
+                ("mode_F", C.POINTER(C.c_double)), ("mode_alpha", C.POINTER(C.c_double)),
+                ("mode_dim", C.c_int), ("modes_exact", C.c_int)]
 
 
 class obte_solve_opts(C.Structure):
@@ -158,18 +159,21 @@ def obte_mesh_create(ndim, n, L, solid, periodic, grad_axis=0, dT_ext=1.0):
     return h
 
 
-def obte_material_set(mesh, mfp, dirs, dir_w, kappa_m, modes=None):
-    """modes = (F (n_modes, ndim), alpha (n_modes,)) or None; with a mode
-    table kappa_m is ignored (may be None)."""
-    mfp, dirs, dir_w = _f64(mfp), _f64(dirs), _f64(dir_w)
+def obte_material_set(mesh, mfp, dirs, dir_w, kappa_m, modes=None, modes_exact=False):
+    """modes = (F (n_modes, ndim), alpha (n_modes,)) or None; F may have 3
+    columns for a 2D mesh (its in-plane part is used).  With a mode table
+    kappa_m is ignored (may be None).  modes_exact: one system per mode, no
+    interpolation (the grid arguments are then ignored)."""
     d = obte_material_desc()
     P = C.POINTER(C.c_double)
-    d.n_mfp = len(mfp)
-    d.mfp = mfp.ctypes.data_as(P)
-    d.n_dir = len(dir_w)
-    d.dirs = dirs.ctypes.data_as(P)
-    d.dir_w = dir_w.ctypes.data_as(P)
     keep = []
+    if mfp is not None:
+        mfp, dirs, dir_w = _f64(mfp), _f64(dirs), _f64(dir_w)
+        d.n_mfp = len(mfp)
+        d.mfp = mfp.ctypes.data_as(P)
+        d.n_dir = len(dir_w)
+        d.dirs = dirs.ctypes.data_as(P)
+        d.dir_w = dir_w.ctypes.data_as(P)
     if kappa_m is not None:
         kappa_m = _f64(kappa_m)
         d.kappa_m = kappa_m.ctypes.data_as(P)
@@ -177,8 +181,10 @@ def obte_material_set(mesh, mfp, dirs, dir_w, kappa_m, modes=None):
         F, alpha = _f64(modes[0]), _f64(modes[1])
         keep = [F, alpha]
         d.n_modes = len(alpha)
+        d.mode_dim = F.shape[1] if F.ndim == 2 else 0
         d.mode_F = F.ctypes.data_as(P)
         d.mode_alpha = alpha.ctypes.data_as(P)
+        d.modes_exact = 1 if modes_exact else 0
     _check(lib().obte_material_set(mesh, C.byref(d)))
     del keep
 

@@ -13,18 +13,18 @@ class Solver:
     """Owns one obte_mesh handle and a device workspace (torch tensor)."""
 
     def __init__(self, ndim, n, L, solid, periodic, grad_axis, dT, mfp, dirs, dir_w, kappa_m,
-                 device="cuda", modes=None):
+                 device="cuda", modes=None, modes_exact=False):
         self.ndim = ndim
         self.n = tuple(int(v) for v in n)
         self.device = torch.device(device)
         self.mesh = _o.obte_mesh_create(ndim, n, L, solid, periodic, grad_axis, dT)
-        _o.obte_material_set(self.mesh, mfp, dirs, dir_w, kappa_m, modes=modes)
+        _o.obte_material_set(self.mesh, mfp, dirs, dir_w, kappa_m, modes=modes, modes_exact=modes_exact)
         self.n_modes = 0 if modes is None else len(modes[1])
         c = _o.obte_mesh_counts(self.mesh)
         self.n_cells, self.n_solid, self.n_walls, self.n_systems = (
             c["n_cells"], c["n_solid"], c["n_walls"], c["n_systems"])
-        self.n_mfp = len(mfp)
-        self.n_dir = len(dir_w)
+        self.n_mfp = 1 if (modes is not None and modes_exact) else len(mfp)
+        self.n_dir = self.n_systems // self.n_mfp
         self.workspace = None
         self.last_stats = None
         # a stream of our own (default priority) so the outer loop can be
@@ -34,7 +34,8 @@ class Solver:
     @classmethod
     def from_workload(cls, w, device="cuda"):
         return cls(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT, w.mfp, w.dirs,
-                   w.dir_w, w.kappa_m, device=device, modes=getattr(w, "modes", None))
+                   w.dir_w, w.kappa_m, device=device, modes=getattr(w, "modes", None),
+                   modes_exact=getattr(w, "modes_exact", False))
 
     def opts(self, **kw):
         return _o.default_opts(**kw)

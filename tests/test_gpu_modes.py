@@ -52,6 +52,9 @@ CASES = {
     "bulk": lambda: gen.with_modes(gen.small_2d(16, 12, n_dir=8, n_mfp=4), 40, 2),
     # 3D tensor direction grid: polar x azimuth interpolation
     "3d": lambda: gen.with_modes(small3d(), 48, 9),
+    # 3D modes in a 2D domain (in-plane part) plus modes moving only along z
+    "proj": lambda: gen.with_modes(gen.small_2d(14, 11, solid=gen.square_block_mask(14, 11, 4, 9), n_dir=12,
+                                                n_mfp=4), 50, 17, dim3=True, n_static=6),
 }
 
 
@@ -84,6 +87,8 @@ def test_modes_vs_oracle(P, name, accel, lag):
     if name == "bulk":
         cf = float(np.sum(prob.mat.S[:, :, 0] * w.mfp[:, None] * w.dirs[None, :, 0]))
         assert abs(r["kappa"] - cf) <= 1e-11 * cf
+    if name == "proj":
+        assert np.all(km[-6:] == 0.0)       # the static modes carry nothing
 
 
 def test_modes_fp32(P):
@@ -146,6 +151,72 @@ def test_modes_adjoint_vs_oracle(P, accel):
     sv = P.Solver.from_workload(w)
     o = sv.opts(outer_tol=1e-13, inner_tol=1e-14, fourier_tol=1e-14, keep_state=1, max_outer=20000,
                 accel=accel)
+    sv.solve(o, sigma=w.sigma, want_T_L=False)
+    g, st = sv.adjoint(o)
+    g = g.cpu().numpy()
+    assert abs(st["kappa"] - fwd["kappa_cc"]) < 1e-10 * fwd["kappa_cc"]
+    assert np.linalg.norm(g - gref) <= 1e-9 * np.linalg.norm(gref)
+
+
+# ---------------------------------------------- no interpolation (Eq. iter3)
+
+def _exact(w):
+    import dataclasses
+    return dataclasses.replace(w, modes_exact=True)
+
+
+EXACT = {
+    "ragged": lambda: _exact(CASES["ragged"]()),
+    "proj": lambda: _exact(CASES["proj"]()),
+    "3d": lambda: _exact(CASES["3d"]()),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_exact(name):
+    w = EXACT[name]()
+    prob = Problem(w)
+    return w, prob, source_iteration(prob, tol=1e-13, max_passes=20000)
+
+
+def test_exact_on_nodes_match_kernel_path(P):
+    w0 = gen.small_2d(12, 10, solid=gen.square_block_mask(12, 10, 3, 7), n_dir=8, n_mfp=3)
+    we = _exact(gen.with_modes(w0, 0, 0, on_node=True))
+    r0 = gpu_solve(P, w0, **TIGHT)
+    re = gpu_solve(P, we, **TIGHT)
+    assert re["solver"].n_systems == 24
+    assert abs(re["kappa"] - r0["kappa"]) <= 1e-11 * abs(r0["kappa"])
+    assert abs(re["kappa_face"] - r0["kappa_face"]) <= 1e-11 * abs(r0["kappa_face"])
+    assert rel(re["T_L"], r0["T_L"]) < 1e-10
+
+
+@pytest.mark.parametrize("name", list(EXACT))
+@pytest.mark.parametrize("accel", [0, 8])
+def test_exact_modes_vs_oracle(P, name, accel):
+    w, prob, ref = oracle_exact(name)
+    r = gpu_solve(P, w, accel=accel, **TIGHT)
+    assert r["status"] == 0
+    kc = ref["kappa_cc"]
+    assert abs(r["kappa"] - kc) <= 1e-10 * abs(kc)
+    assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
+    km = r["solver"].kappa_modes()
+    assert np.max(np.abs(km - kappa_modes(prob, ref["T"]))) <= 1e-9 * abs(kc)
+    assert abs(km.sum() - r["kappa"]) <= 1e-11 * abs(r["kappa"])
+
+
+def test_exact_modes_adjoint_vs_oracle(P):
+    from oracle.adjoint import adjoint_source_iteration
+    rng = np.random.default_rng(23)
+    s = gen.square_block_mask(10, 9, 3, 6)
+    w = _exact(gen.with_modes(gen.small_2d(10, 9, solid=s, n_dir=8, n_mfp=3, sigma=rng.uniform(0.5, 2.0, 90)),
+                              30, 19))
+    prob = Problem(w)
+    fwd = source_iteration(prob, tol=1e-14, max_passes=20000)
+    ref = adjoint_source_iteration(prob, fwd["T"], tol=1e-14, max_passes=20000)
+    gref = oracle_full(prob, ref["grad"])
+    sv = P.Solver.from_workload(w)
+    o = sv.opts(outer_tol=1e-13, inner_tol=1e-14, fourier_tol=1e-14, keep_state=1, max_outer=20000)
     sv.solve(o, sigma=w.sigma, want_T_L=False)
     g, st = sv.adjoint(o)
     g = g.cpu().numpy()

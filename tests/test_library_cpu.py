@@ -84,7 +84,7 @@ def test_material_set_rejects_on_host(L, bad):
     L.obte_mesh_destroy(h)
 
 
-@pytest.mark.parametrize("bad", ["netflux", "alpha", "zero_mfp", "dup_nodes", "nan"])
+@pytest.mark.parametrize("bad", ["netflux", "alpha", "all_static", "dup_nodes", "nan", "dim"])
 def test_mode_table_rejects_on_host(L, bad):
     """Mode-table validation happens before any device call."""
     w = gen.with_modes(gen.small_2d(8, 6, n_dir=8, n_mfp=3), 20, 5)
@@ -96,9 +96,10 @@ def test_mode_table_rejects_on_host(L, bad):
         F, alpha = F[1:], alpha[1:]          # drop one of a mirrored pair
     elif bad == "alpha":
         alpha[3] = -1.0
-    elif bad == "zero_mfp":
-        F[2] = 0.0
-        F[3] = 0.0
+    elif bad == "all_static":
+        F[:] = 0.0                           # no mode moves in the plane
+    elif bad == "dim":
+        F = np.concatenate([F, F[:, :1]], axis=1)[:, :1]   # one column in a 2D domain
     elif bad == "dup_nodes":
         mfp[1] = mfp[0]
     else:
@@ -108,6 +109,27 @@ def test_mode_table_rejects_on_host(L, bad):
     assert e.value.status == L.OBTE_ERR_ARG
     out = np.zeros(4)
     assert L.lib().obte_kappa_modes(h, out.ctypes.data_as(C.POINTER(C.c_double))) == L.OBTE_ERR_STATE
+    L.obte_mesh_destroy(h)
+
+
+@pytest.mark.parametrize("bad", ["netflux", "all_static", "no_gradient", "dim"])
+def test_exact_modes_reject_on_host(L, bad):
+    """The mode-resolved material (no interpolation) checks its table before
+    any device call; the grid arguments may be absent."""
+    w = gen.with_modes(gen.small_2d(8, 6, n_dir=8, n_mfp=3), 20, 5)
+    h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
+    F, alpha = w.modes[0].copy(), w.modes[1].copy()
+    if bad == "netflux":
+        F, alpha = F[1:], alpha[1:]
+    elif bad == "all_static":
+        F[:] = 0.0
+    elif bad == "no_gradient":
+        F[:, 0] = 0.0                        # nothing moves along x
+    else:
+        F = F[:, :1]
+    with pytest.raises(L.ObteError) as e:
+        L.obte_material_set(h, None, None, None, None, modes=(F, alpha), modes_exact=True)
+    assert e.value.status == L.OBTE_ERR_ARG
     L.obte_mesh_destroy(h)
 
 
