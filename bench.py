@@ -8,7 +8,9 @@ until the estimated kappa error meets the target.  Inputs (mesh tables,
 material weights, sigma) are resident on the device before the timed region
 starts.  The same JSON line also carries the 3D membrane (64x64x16, 288
 directions x 30 MFPs) and the 64-geometry batch, each at the same error
-target (skip them with --no-extras).
+target, the Fourier-only batch, and one synthetic mode table solved by the
+aMFP interpolation and by the mode-resolved iteration (skip them with
+--no-extras).
 """
 from __future__ import annotations
 
@@ -237,6 +239,55 @@ def cpu_baseline_value(m, passes, dof):
             "dof_per_s": dof / per_solve, "seconds_per_solve_estimate": per_solve}
 
 
+def fourier_batch(P, steps, warmup):
+    """The Fourier-only workload (only_fourier) over the 64 geometries:
+    geometry solves/s of the batched FP64 CG."""
+    import torch
+    from inputs import gen
+    geoms = gen.config3()
+    solvers = [P.Solver.from_workload(w) for w in geoms]
+    ref, _ = P.solve_batch(solvers, P.default_opts(only_fourier=1, fourier_tol=1e-12))
+    o = P.default_opts(only_fourier=1, fourier_tol=1e-8)
+    for _ in range(warmup):
+        P.solve_batch(solvers, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        k, st = P.solve_batch(solvers, o)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"workload": "Fourier first guess only (FP64 CG to 1e-8) over the 64 geometries",
+            "geometry_solves_per_s": len(geoms) / dt, "ms_per_batch": 1e3 * dt,
+            "cells": sum(w.n_cells for w in geoms),
+            "max_cg_iters": max(x["fourier_iters"] for x in st),
+            "max_kappa_rel_err_vs_1e-12": max(abs(x - y) / y for x, y in zip(k, ref))}
+
+
+def modes_compare(P, n_modes, steps, warmup):
+    """One synthetic mode table (3D modes, in-plane part, mirrored pairs) on
+    the 128x128 cell: interpolated onto the 48 x 30 grid (aMFP) against one
+    system per mode (the mode-resolved iteration), both at the mixed FP32
+    operating point."""
+    import dataclasses
+    from inputs import gen
+    w = gen.with_modes(gen.config2(), n_modes, 29, dim3=True)
+    out = {"workload": f"128x128 cell, {n_modes} synthetic 3D modes (in-plane part), "
+                       "aMFP on 48 directions x 30 MFPs vs one system per mode",
+           "n_modes": n_modes}
+    for label, wk in (("amfp", w), ("mode_resolved", dataclasses.replace(w, modes_exact=True))):
+        s = P.Solver.from_workload(wk)
+        kref = s.solve(s.opts(**REF), want_T_L=False)["kappa"]
+        r = run_solves(s, s.opts(**OP[HEADLINE]), steps, warmup)
+        out[label] = {"systems": s.n_systems, "solves_per_s": steps / r["seconds"],
+                      "ms_per_solve": 1e3 * r["seconds"] / steps, "kappa": r["kappa"],
+                      "kappa_ref_fp64": kref, "passes_per_solve": r["outer_iters"] / steps,
+                      "kappa_rel_err_vs_fp64_ref": abs(r["kappa"] - kref) / abs(kref)}
+    out["speedup_amfp"] = out["mode_resolved"]["ms_per_solve"] / out["amfp"]["ms_per_solve"]
+    out["kappa_amfp_vs_mode_resolved"] = (out["amfp"]["kappa_ref_fp64"] /
+                                          out["mode_resolved"]["kappa_ref_fp64"])
+    return out
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -288,6 +339,8 @@ def main():
                                      "roofline": roofline(w5, res5[HEADLINE]["timed_leg"],
                                                           "k_sweep_pass3<float>")}
         line["extra_batch_64"] = batch(P, steps_x, warm_x)
+        line["extra_fourier_batch_64"] = fourier_batch(P, max(a.steps, 3), warm_x)
+        line["extra_modes_128"] = modes_compare(P, 11520, steps_x, warm_x)
     print(json.dumps(line), flush=True)
 
 
