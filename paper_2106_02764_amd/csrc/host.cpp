@@ -83,7 +83,6 @@ struct obte_mesh {
     // mode table (optional): per mode up to MODE_TERMS (system, weight) pairs
     // and its flux weight along the gradient axis; kappa_mu of the last solve
     int n_modes = 0;
-    int wall_in = 0;      // see GeomDev::wall_in
     std::vector<int> mode_sys;
     std::vector<double> mode_w, mode_Sg, kappa_mode;
     int* d_mode_sys = nullptr;
@@ -97,10 +96,9 @@ namespace {
 // workspace layout of one geometry
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t sigma, sigma_f, sT, Tw, T_L, U, part_TL, part_Tw, part_J, ksys, kfsys, iters, sweeps,
-        hist, hist_face, ctrl, fx, fscal, Tstore, lam_psi, lam_phi, grad, part_G, bnd, mem, mem_count,
-        mem_bytes, wres, wres_hist, kry, ax, actl, ag, axp, afp, adX, adF, agram, apart, kraw, part_Twi,
-        total;
+    size_t sigma, sigma_f, sT, Tw, T_L, U, X, ksys, kfsys, iters, sweeps, hist, hist_face, ctrl, fx, fscal,
+        Tstore, lam_psi, lam_phi, grad, bnd, mem, mem_count, mem_bytes, wres, wres_hist, kry, ax, actl, ag,
+        axp, afp, adX, adF, agram, apart, kraw, total;
 };
 
 // Linear interpolation weights of x on the sorted values v (clamped to the
@@ -264,7 +262,6 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
         return at;
     };
     const size_t nc = (size_t)m->ncells, nw = (size_t)std::max(m->nwalls, 1);
-    const size_t n_items = (size_t)m->n_dir * n_groups(m, waves);
     const size_t tsz = (o->precision == OBTE_FP32) ? 4 : 8;
     const size_t nwrap = (size_t)m->nx * m->nz;
     L.sigma = take(nc * 8);
@@ -272,9 +269,6 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.sT = take(2 * nc * 8);
     L.Tw = take(2 * nw * 8);
     L.T_L = take(nc * 8);
-    L.part_TL = take(n_items * nc * 8);
-    L.part_Tw = take(n_items * (size_t)m->ndim * nc * 8);
-    L.part_J = take(n_items * nc * m->ndim * 8);
     L.ksys = take((size_t)m->n_sys * 8);
     L.kfsys = take((size_t)m->n_sys * 8);
     L.iters = take((size_t)m->n_sys * 8);
@@ -285,7 +279,6 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.lam_psi = take(2 * nc * 8);
     L.lam_phi = take(2 * nw * 8);
     L.grad = take(nc * 8);
-    L.part_G = take(n_items * nc * 8);
     L.bnd = take(4 * (size_t)m->nf * nc * 8);
     L.mem_count = take(2 * (size_t)m->n_sys * 4);
     L.wres = take((size_t)m->n_sys * 8);
@@ -296,7 +289,6 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.ax = take((naa + 1) * 8);            // + the gauge shift of the pass
     L.actl = take(8 * 4);
     L.kraw = take((size_t)m->n_sys * 8);
-    L.part_Twi = take(m->wall_in ? n_items * (size_t)m->ndim * nc * 8 : 8);
     // the parts below depend on precision / recycle / keep_state / accel, so
     // the state a resumed solve reads (above, and U) keeps its place
     L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
@@ -304,6 +296,7 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.mem_bytes = 2 * (size_t)m->n_sys * 2 * (size_t)std::max(o->recycle, 0) * nwrap * tsz;
     L.mem = take(L.mem_bytes);
     L.Tstore = o->keep_state ? take((size_t)m->n_sys * nc * 8) : 0;
+    L.X = take((size_t)m->n_sys * nc * tsz);
     // last: the mixing history (an adjoint may use another depth than the
     // forward solve whose stored state it reads)
     const size_t M = (size_t)std::max(o->accel, 0);
@@ -334,7 +327,6 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
     g.n_perp = m->ncells / (m->grad_axis == 0 ? m->nx : (m->grad_axis == 1 ? m->ny : m->nz));
     g.fc = m->d_fc; g.wall_idx = m->d_wall_idx; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face;
     g.mfp = m->d_mfp; g.dirs = m->d_dirs; g.Dw = m->d_D; g.S = m->d_S; g.wout = m->d_wout;
-    g.wall_in = m->wall_in;
     g.gauge = m->n_modes > 0 ? 1 : 0;
     g.kappa_axis = m->d_kax;
     if (ws) {
@@ -345,9 +337,7 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.T_L = (double*)(ws + L.T_L);
         g.U = ws + L.U;
         g.kry = L.kry ? ws + L.kry : nullptr;
-        g.part_TL = (double*)(ws + L.part_TL);
-        g.part_Tw = (double*)(ws + L.part_Tw);
-        g.part_J = (double*)(ws + L.part_J);
+        g.X = ws + L.X;
         g.ksys = (double*)(ws + L.ksys);
         g.kfsys = (double*)(ws + L.kfsys);
         g.iters = (long long*)(ws + L.iters);
@@ -361,7 +351,6 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.lam_psi = (double*)(ws + L.lam_psi);
         g.lam_phi = (double*)(ws + L.lam_phi);
         g.gradient = (double*)(ws + L.grad);
-        g.part_G = (double*)(ws + L.part_G);
         g.bnd = (double*)(ws + L.bnd);
         g.mem = ws + L.mem;
         g.mem_count = (int*)(ws + L.mem_count);
@@ -370,7 +359,6 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.ax = (double*)(ws + L.ax);
         g.actl = (int*)(ws + L.actl);
         g.kraw = (double*)(ws + L.kraw);
-        g.part_Twi = (double*)(ws + L.part_Twi);
         if (accel > 0) {
             g.ag = (double*)(ws + L.ag);
             g.axp = (double*)(ws + L.axp);
@@ -485,7 +473,6 @@ struct Run {
     int waves = 4, cpl = 1, nzmax = 1, precision = 0, accel = 0;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
     size_t lds = 0;               // the largest any launch of this run needs
-    size_t lds_for[2][2] = {};    // [adjoint][want_J]
     int max_cells = 0, max_walls = 0;
     ~Run() {
         if (d_views) soft(hipFree(d_views), "hipFree(views)");
@@ -507,21 +494,18 @@ obte_status resolve_waves(const obte_mesh* const* meshes, int n, const obte_solv
     }
     size_t per_wave = 0;
     {
-        int cpl = 1, nzm = 1, win = 0;
+        int cpl = 1, nzm = 1;
         for (int i = 0; i < n; ++i) {
             cpl = std::max(cpl, (meshes[i]->nx + 63) / 64);
             nzm = std::max(nzm, meshes[i]->nz);
-            win |= meshes[i]->wall_in;
         }
-        const int nd = nzm > 1 ? 3 : 2;
-        // reduction rows (double buffered; the largest set, the flux replay),
-        // plus in 3D one row per z-plane in the compute type
-        per_wave = 2 * (size_t)red_rows(nd, 0, 1, win) * 64 * cpl * sizeof(double);
-        if (nzm > 1) per_wave += (size_t)nzm * 64 * cpl * (o->precision == OBTE_FP32 ? 4 : 8);
+        // 3D: one row per z-plane in the compute type (2D keeps its rows in
+        // registers and needs no LDS)
+        if (nzm > 1) per_wave = (size_t)nzm * 64 * cpl * (o->precision == OBTE_FP32 ? 4 : 8);
         const size_t cap = 64 * 1024;
         if (per_wave > cap)
             return fail(OBTE_ERR_ARG, "a wave needs %zu bytes of LDS (nx, nz too large; limit %zu)", per_wave, cap);
-        const int wmax = (int)(cap / per_wave);
+        const int wmax = per_wave > 0 ? (int)(cap / per_wave) : 8;
         if (W > wmax) {
             if (o->waves_per_group) return fail(OBTE_ERR_ARG, "waves_per_group %d needs more than 64 KiB of LDS (max %d)", W, wmax);
             W = wmax;
@@ -573,17 +557,6 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
             return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
     R.lds = (size_t)W * per_wave;
-    {
-        // launches size their LDS for the slot rows they use
-        const int nd = R.nzmax > 1 ? 3 : 2;
-        int win = 0;
-        for (int gi = 0; gi < n; ++gi) win |= meshes[gi]->wall_in;
-        const size_t row = 64 * (size_t)R.cpl;
-        const size_t zr = R.nzmax > 1 ? (size_t)R.nzmax * row * (o->precision == OBTE_FP32 ? 4 : 8) : 0;
-        for (int a = 0; a < 2; ++a)
-            for (int j = 0; j < 2; ++j)
-                R.lds_for[a][j] = (size_t)W * (2 * (size_t)red_rows(nd, a, j, win) * row * sizeof(double) + zr);
-    }
     HIPCHK(hipMalloc((void**)&R.d_views, R.views.size() * sizeof(GeomDev)));
     HIPCHK(hipMalloc((void**)&R.d_items, R.items.size() * sizeof(Item)));
     HIPCHK(hipMalloc((void**)&R.d_pending, sizeof(int)));
@@ -595,10 +568,10 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
 obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Timer* tm, int k) {
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k], st));
     HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items, (int)R.items.size(),
-                             R.waves, pp, R.lds_for[pp.adjoint ? 1 : 0][pp.want_J ? 1 : 0], st));
+                             R.waves, pp, R.lds, st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 1], st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 2], st));
-    HIPCHK(launch_reduce_pass(R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
+    HIPCHK(launch_reduce_pass(R.precision, R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
     if (R.gauge && !pp.adjoint) HIPCHK(launch_gauge(R.d_views, (int)R.views.size(), R.max_cells + R.max_walls, st));
     if (R.accel > 0) HIPCHK(launch_anderson(R.d_views, (int)R.views.size(), R.max_cells + R.max_walls, pp, st));
     HIPCHK(launch_finalize(R.d_views, (int)R.views.size(), pp, st));
@@ -791,10 +764,10 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
             rp.store_T = keep_T ? 1 : 0;
             HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items,
                                      (int)R.items.size(), R.waves, rp,
-                                     R.lds_for[rp.adjoint ? 1 : 0][rp.want_J ? 1 : 0], st));
+                                     R.lds, st));
         }
     }
-    if (n == 1 && (T_L_out || J_out)) HIPCHK(launch_output(meshes[0]->d_geom, 1, T_L_out, o->only_fourier ? nullptr : J_out, nullptr, st));
+    if (n == 1 && (T_L_out || J_out)) HIPCHK(launch_output(meshes[0]->d_geom, R.precision, meshes[0]->ncells, T_L_out, o->only_fourier ? nullptr : J_out, nullptr, st));
     if (n == 1 && J_out && o->only_fourier) HIPCHK(hipMemsetAsync(J_out, 0, sizeof(double) * meshes[0]->ncells * meshes[0]->ndim, st));
     // results
     obte_status ret = OBTE_OK;
@@ -1148,14 +1121,6 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
         for (int sys = 0; sys < m->n_sys; ++sys)
             m->wout[(size_t)f * m->n_sys + sys] = tot > 0.0 ? std::max(0.0, m->S[sys * 3 + ax] * sg) / tot : 0.0;
     }
-    // a wall weight on the face a system's direction enters through (S and
-    // the direction disagree in sign: only with a mode table)
-    m->wall_in = 0;
-    for (int f = 0; f < m->nf && m->nwalls > 0; ++f)
-        for (int sys = 0; sys < m->n_sys; ++sys) {
-            const bool out_face = (m->dirs3[(sys % m->n_dir) * 3 + (f >> 1)] > 0.0) == ((f & 1) != 0);
-            if (!out_face && m->wout[(size_t)f * m->n_sys + sys] > 0.0) m->wall_in = 1;
-        }
     // device tables
     free_dev(m);
     HIPCHK(hipGetDevice(&m->device));
@@ -1289,7 +1254,7 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     if (o->timing && (s = tm.init(K)) != OBTE_OK) return s;
     s = outer_loop(R, pp, K, st, o->max_outer, &tm);
     if (s != OBTE_OK) return s;
-    HIPCHK(launch_output(m->d_geom, 1, nullptr, nullptr, grad_dev, st));
+    HIPCHK(launch_output(m->d_geom, R.precision, m->ncells, nullptr, nullptr, grad_dev, st));
     std::vector<int> ctrl(CTRL_N);
     HIPCHK(hipMemcpyAsync(ctrl.data(), R.views[0].ctrl, CTRL_N * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -167,13 +167,6 @@ __device__ __forceinline__ void wave_scan(T& A, T& Q, T& P) {
     scan_step<0x143, 0xc>(A, Q, P);   // row_bcast:31 into rows 2, 3
 }
 
-// Workgroup barrier ordering LDS only (pending global loads stay in flight).
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // Loads through these views compile to global (not flat) loads, which keep
 // only the vector-memory counter pending while the row computes.
 template <typename T>
@@ -187,39 +180,16 @@ using gmut_t = __attribute__((address_space(1))) T*;
 template <typename T>
 __device__ __forceinline__ gmut_t<T> gmut(T* p) { return (gmut_t<T>)p; }
 
-// Reduction state of a lockstep sweep.  The output pointers are copied here
-// once: kept in registers, they are not reloaded after every barrier.
+// Per-wave state of a sweep that keeps its result: the kappa sums in
+// registers, and the solution stored row by row (the sums over systems per
+// cell and per wall are taken afterwards by the reduction kernel).
+template <typename T>
 struct Red {
-    double* lds;      // 2 * W * NV * ROW doubles
-    int w, W, ROW;
-    int local;        // item index within the geometry
-    int want_J, store_T;
-    int NV;           // slot rows per wave (red_rows)
-    int wall_in;      // forward: also the walls a system meets against its direction
+    int store_T;
     double kacc, kface;
-    gmut_t<double> pTL, pTw, pG, pJ;   // this item's partial rows
-    gmut_t<double> Tstore;             // this system's stored state (or null)
-    gptr_t<double> T_L;
-    int ncells;
+    gmut_t<T> X;               // this system's solution (null: inactive wave)
+    gmut_t<double> Tstore;     // this system's stored state (or null)
 };
-
-constexpr int WMAX = 8;     // systems per workgroup, at most
-
-// Fixed-order sum of the W slot values at v (loaded together, then added;
-// the index is clamped so every load stays inside the block's slots).
-__device__ __forceinline__ double slot_sum(const double* buf, int W, int NV, int ROW, int v, int p) {
-    double t[WMAX];
-#pragma unroll
-    for (int ww = 0; ww < WMAX; ++ww) {
-        const double val = buf[(size_t)((ww < W ? ww : 0) * NV + v) * ROW + p];
-        t[ww] = ww < W ? val : 0.0;
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int ww = 0; ww < WMAX; ++ww) s += t[ww];
-    return s;
-}
-
 
 // 1/d: hardware reciprocal (float), refined by two Newton steps (double).
 __device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
@@ -319,7 +289,7 @@ template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, class I
 __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, const Views<T>& vw,
                                          int active, int lane, int adj, int jj, int kk,
                                          const RowIn<T, CPL>& cur, Rows<T, CPL, D3>& rows, IO& io,
-                                         const double (&mb)[3], const double (&wo)[3], Red* rd) {
+                                         const double (&mb)[3], Red<T>* rd) {
     constexpr int ND = D3 ? 3 : 2;
     const int nx = g.nx, ny = g.ny;
     const T cz = D3 ? s.c[2] : T(0);
@@ -379,37 +349,20 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 #pragma unroll
         for (int c = 0; c < CPL; ++c) io.out(kk, c, lane, xrow[c]);
     }
-    if (RED) {
+    if (RED && rd->X) {
         const int iy = s.pos[1] ? jj : ny - 1 - jj;
         const int iz = D3 ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
         const int rowbase = nx * (iy + ny * iz);
-        const int ROW = rd->ROW, W = rd->W;
-        const int NV = rd->NV;
-        // the slots are double buffered by row parity: a wave writes this
-        // buffer again two rows later, after the next row's barrier, which
-        // every wave reaches only once it has combined this row
-        double* buf = rd->lds + (size_t)((jj * (D3 ? g.nz : 1) + kk) & 1) * W * NV * ROW;
-        // the cells this wave combines after the barrier: a contiguous share
-        // of the row (their face words are loaded now, ahead of the barrier)
-        const int CH = (ROW + W - 1) / W;
-        const int pbeg = rd->w * CH, pend = min(nx, pbeg + CH);
-        uint32_t fcc[CPL];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int p = pbeg + lane + WAVE * c;
-            fcc[c] = p < pend ? (uint32_t)vw.fc[rowbase + (s.pos[0] ? p : nx - 1 - p)] : 0u;
-        }
-        bool wall_here = false;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int p = lane * CPL + c;
+            if (p >= nx) continue;
             const uint32_t wv = cur.w[c];
-            const bool sol = p < nx && active && fc_solid(wv);
-            const double xv = sol ? (double)xrow[c] : 0.0;
-            double* slot = buf + (size_t)(rd->w * NV) * ROW + p;
-            double gp = 0.0;
+            const bool sol = fc_solid(wv);
+            const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
+            const T xt = sol ? xrow[c] : T(0);
             if (sol) {
-                const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
+                const double xv = (double)xt;
                 rd->kacc += xv;
                 if (adj) {
                     // p^T lambda: forward jump inflow = reversed outflow faces
@@ -419,8 +372,6 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                         if (cl == FC_JUMP_P) rd->kface += s.cd[ax] * g.dT * xv;
                         else if (cl == FC_JUMP_M) rd->kface -= s.cd[ax] * g.dT * xv;
                     }
-                    // gradient partial lambda (T - T_L), linear in lambda
-                    gp = xv * (rd->Tstore[cell] - rd->T_L[cell]);
                 } else {
                     // kappa through the periodic plane of the gradient axis;
                     // the jump term belongs to the b sweep only
@@ -431,78 +382,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                 }
                 if (rd->store_T) rd->Tstore[cell] = xv;
             }
-            slot[0] = adj ? xv : s.Dml * xv;
-            // wall slots exist where the geometry sends this direction into a
-            // wall (every wave of the block writes them, 0 when inactive)
-#pragma unroll
-            for (int ax = 0; ax < ND; ++ax) {
-                if (p < nx && fc_solid(wv) && fc_class(wv, s.fout[ax]) == FC_WALL) {
-                    slot[(size_t)(1 + ax) * ROW] = (adj ? s.cd[ax] : wo[ax]) * xv;
-                    wall_here = true;
-                }
-            }
-            if (!adj && rd->wall_in) {
-                // the wall's outgoing-flux weights follow S, which (mode
-                // tables) may leave through the face this direction enters by
-                const int xr = 1 + ND + (rd->want_J ? ND : 0);
-                for (int ax = 0; ax < ND; ++ax) {
-                    if (p < nx && fc_solid(wv) && fc_class(wv, s.fin[ax]) == FC_WALL) {
-                        slot[(size_t)(xr + ax) * ROW] = g.wout[s.fin[ax] * g.n_sys + s.sys] * xv;
-                        wall_here = true;
-                    }
-                }
-            }
-            if (adj) {
-                slot[(size_t)(1 + ND) * ROW] = gp;
-            } else if (rd->want_J) {
-#pragma unroll
-                for (int ax = 0; ax < ND; ++ax) slot[(size_t)(1 + ND + ax) * ROW] = s.S[ax] * xv;
-            }
-        }
-        // the same in every wave of the block (geometry and direction only)
-        const bool wall_row = __any(wall_here);
-        lds_barrier();
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int p = pbeg + lane + WAVE * c;
-            if (p >= pend) continue;
-            const uint32_t wv = fcc[c];
-            const bool sol = fc_solid(wv);
-            const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
-            const double sum = slot_sum(buf, W, NV, ROW, 0, p);
-            gmut_t<double> dst = rd->pTL + cell;
-            *dst = ADD ? *dst + sum : (sol ? sum : 0.0);
-            if (wall_row && sol) {
-#pragma unroll
-                for (int ax = 0; ax < ND; ++ax) {
-                    if (fc_class(wv, s.fout[ax]) != FC_WALL) continue;
-                    const double sw = slot_sum(buf, W, NV, ROW, 1 + ax, p);
-                    gmut_t<double> dw = rd->pTw + (size_t)ax * rd->ncells + cell;
-                    *dw = ADD ? *dw + sw : sw;
-                }
-                if (!adj && rd->wall_in) {
-                    const int xr = 1 + ND + (rd->want_J ? ND : 0);
-                    for (int ax = 0; ax < ND; ++ax) {
-                        if (fc_class(wv, s.fin[ax]) != FC_WALL) continue;
-                        const double sw = slot_sum(buf, W, NV, ROW, xr + ax, p);
-                        gmut_t<double> dw =
-                            gmut(g.part_Twi + ((size_t)rd->local * g.ndim + ax) * rd->ncells + cell);
-                        *dw = ADD ? *dw + sw : sw;
-                    }
-                }
-            }
-            if (adj) {
-                const double sg = slot_sum(buf, W, NV, ROW, 1 + ND, p);
-                gmut_t<double> dg = rd->pG + cell;
-                *dg = ADD ? *dg + sg : sg;
-            } else if (rd->want_J) {
-#pragma unroll
-                for (int ax = 0; ax < ND; ++ax) {
-                    const double sj = slot_sum(buf, W, NV, ROW, 1 + ND + ax, p);
-                    gmut_t<double> dj = rd->pJ + (size_t)cell * ND + ax;
-                    *dj = ADD ? *dj + sj : sj;
-                }
-            }
+            rd->X[cell] = ADD ? rd->X[cell] + xt : xt;
         }
     }
 }
@@ -516,12 +396,14 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 // block.  Returns the last row (jj = ny-1) in xl.  Row inputs are prefetched
 // two rows ahead (2D) through a three-buffer rotation without copies.
 // ---------------------------------------------------------------------------
+constexpr int PF2D = 4;    // 2D rows in flight (prefetch depth + 1)
+
 template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, class IO>
 __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int active, int lane, int adj,
                                       const double* __restrict__ srcbase, const double* __restrict__ bnd,
-                                      IO& io, Red* rd, T* zrows) {
+                                      IO& io, Red<T>* rd, T* zrows) {
     constexpr int ND = D3 ? 3 : 2;
-    double mb[3], wo[3];
+    double mb[3];
     // boundary input face per axis: forward, the wall this direction enters
     // from; adjoint, the wall whose temperature takes this system, the one
     // that S leaves through (with kappa_m weights: the reversed inflow face)
@@ -530,7 +412,6 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     for (int ax = 0; ax < 3; ++ax) {
         fb[ax] = adj ? 2 * ax + (s.S[ax] > 0.0 ? 1 : 0) : s.fin[ax];
         mb[ax] = adj ? (ax < ND ? g.wout[fb[ax] * g.n_sys + s.sys] : 0.0) : s.cd[ax];
-        wo[ax] = ax < ND ? g.wout[s.fout[ax] * g.n_sys + s.sys] : 0.0;
     }
     Views<T> vw;
     vw.fc = gview(g.fc);
@@ -546,23 +427,22 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     rows.ROW = WAVE * CPL;
     const int ny = g.ny;
     if (!D3) {
-        // four buffers: the loads of row jj + 3 are issued before row jj runs
-        RowIn<T, CPL> b0, b1, b2, b3;
-        load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 0, 0, b0);
-        if (ny > 1) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 1, 0, b1);
-        if (ny > 2) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 2, 0, b2);
-        for (int jj = 0; jj < ny; jj += 4) {
-            if (jj + 3 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 3, 0, b3);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj, 0, b0, rows, io, mb, wo, rd);
-            if (jj + 1 >= ny) break;
-            if (jj + 4 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 4, 0, b0);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 1, 0, b1, rows, io, mb, wo, rd);
-            if (jj + 2 >= ny) break;
-            if (jj + 5 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 5, 0, b1);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 2, 0, b2, rows, io, mb, wo, rd);
-            if (jj + 3 >= ny) break;
-            if (jj + 6 < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + 6, 0, b2);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + 3, 0, b3, rows, io, mb, wo, rd);
+        // PF2D buffers in rotation: the loads of row jj + PF2D - 1 are issued
+        // before row jj runs (the unrolled rotation keeps every index static)
+        RowIn<T, CPL> b[PF2D];
+#pragma unroll
+        for (int r = 0; r < PF2D - 1; ++r)
+            if (r < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, r, 0, b[r]);
+        for (int jj = 0; jj < ny; jj += PF2D) {
+#pragma unroll
+            for (int r = 0; r < PF2D; ++r) {
+                if (jj + r < ny) {
+                    if (jj + r + PF2D - 1 < ny)
+                        load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + r + PF2D - 1, 0, b[(r + PF2D - 1) % PF2D]);
+                    row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + r, 0, b[r], rows, io,
+                                                           mb, rd);
+                }
+            }
         }
     } else {
         // 3D: rows (jj, kk) with kk inner; a three-buffer rotation keeps the
@@ -573,13 +453,13 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
         if (nrows > 1) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 1 / nz, 1 % nz, b1);
         for (int r = 0; r < nrows; r += 3) {
             if (r + 2 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 2) / nz, (r + 2) % nz, b2);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, r / nz, r % nz, b0, rows, io, mb, wo, rd);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, r / nz, r % nz, b0, rows, io, mb, rd);
             if (r + 1 >= nrows) break;
             if (r + 3 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 3) / nz, (r + 3) % nz, b0);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, (r + 1) / nz, (r + 1) % nz, b1, rows, io, mb, wo, rd);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, (r + 1) / nz, (r + 1) % nz, b1, rows, io, mb, rd);
             if (r + 2 >= nrows) break;
             if (r + 4 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 4) / nz, (r + 4) % nz, b1);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, (r + 2) / nz, (r + 2) % nz, b2, rows, io, mb, wo, rd);
+            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, (r + 2) / nz, (r + 2) % nz, b2, rows, io, mb, rd);
         }
     }
 }
@@ -697,8 +577,19 @@ struct Mem {
 
 // Per-system results of a pass: kappa partials and counters.
 template <typename T>
+__device__ __forceinline__ Red<T> make_red(const GeomDev& g, const SysC<T>& s, int active, const PassParams& pp) {
+    Red<T> rd;
+    rd.store_T = pp.store_T;
+    rd.kacc = 0.0;
+    rd.kface = 0.0;
+    rd.X = active ? gmut(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.ncells) : nullptr;
+    rd.Tstore = (active && g.Tstore) ? gmut(g.Tstore + (size_t)s.sys * g.ncells) : nullptr;
+    return rd;
+}
+
+template <typename T>
 __device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s, int active, int lane,
-                                              int adj, const PassParams& pp, const Red& rd,
+                                              int adj, const PassParams& pp, const Red<T>& rd,
                                               long long n_it, long long n_sw) {
     const double ks = wave_sum(rd.kacc), kf = wave_sum(rd.kface);
     if (active && lane == 0) {
@@ -719,24 +610,24 @@ __device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s
 
 // ---------------------------------------------------------------------------
 // One outer pass for every work item (block = one item = W systems sharing a
-// direction).  Phase A: all waves sweep in lockstep with the sources b and
-// the previous wrap inflow u0, writing the reductions.  Phase B: each wave
-// corrects its wrap inflow (recycled projection, then BiCGSTAB on the wrap
-// row).  Phase C: if any wave changed u, a lockstep correction sweep with
-// source P (u - u0) adds its (linear) contribution to the reductions.
+// direction, so their table and source loads touch the same lines).  Phase
+// A: each wave sweeps with the sources b and the previous wrap inflow u0 and
+// stores its solution.  Phase B: each wave corrects its wrap inflow
+// (recycled projection, then BiCGSTAB on the wrap row).  Phase C: a wave that
+// changed u sweeps the source P (u - u0) and adds the (linear) response to
+// its stored solution.
 // ---------------------------------------------------------------------------
 template <typename T, int CPL>
 __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ geoms,
                                                     const Item* __restrict__ items, int n_items,
                                                     PassParams pp) {
     constexpr int NZ = 1;      // 2D: the wrap row is one x-row, held in registers
-    extern __shared__ double lds[];
     const int it = blockIdx.x;
     if (it >= n_items) return;
     const Item item = items[it];
     const GeomDev& g = geoms[item.geom];
     if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = item.m0 + w;
     const int active = (w < item.nm) && (m < g.n_mfp);
     const int adj = pp.adjoint;
@@ -762,25 +653,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
         const int p = lane * CPL + c;
         u[k][c] = (active && k < g.nz && p < g.nx) ? Uall[(size_t)s.sys * g.nwrap + k * g.nx + p] : T(0);
     });
-    Red rd;
-    rd.lds = lds;
-    rd.w = w;
-    rd.W = W;
-    rd.ROW = WAVE * CPL;
-    rd.local = item.local;
-    rd.want_J = pp.want_J;
-    rd.store_T = pp.store_T;
-    rd.kacc = 0.0;
-    rd.kface = 0.0;
-    rd.NV = red_rows(2, adj, pp.want_J, g.wall_in);
-    rd.wall_in = g.wall_in;
-    rd.ncells = g.ncells;
-    rd.pTL = gmut(g.part_TL + (size_t)item.local * g.ncells);
-    rd.pTw = gmut(g.part_Tw + (size_t)item.local * g.ndim * g.ncells);
-    rd.pG = gmut(g.part_G + (size_t)item.local * g.ncells);
-    rd.pJ = gmut(g.part_J + (size_t)item.local * g.ncells * g.ndim);
-    rd.Tstore = g.Tstore ? gmut(g.Tstore + (size_t)s.sys * g.ncells) : nullptr;
-    rd.T_L = gview(g.T_L);
+    Red<T> rd = make_red<T>(g, s, active, pp);
     // ---- phase A
     {
         RegIO<T, CPL> io{u[0], xl[0]};
@@ -879,11 +752,11 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
             });
         }
     }
-    // ---- phase C: lockstep correction sweep when any wave moved its inflow
-    // (skipped when the correction is lagged into the next pass)
-    if (!pp.lag_wrap && __syncthreads_or(need)) {
+    // ---- phase C: correction sweep of a wave that moved its inflow (skipped
+    // when the correction is lagged into the next pass)
+    if (!pp.lag_wrap && need) {
         RegIO<T, CPL> io{du[0], xl[0]};
-        sweep<T, CPL, false, false, true, true>(g, s, active && need, lane, adj, srcbase, bnd, io, &rd, nullptr);
+        sweep<T, CPL, false, false, true, true>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
         ++n_sw;
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
@@ -918,7 +791,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     const Item item = items[it];
     const GeomDev& g = geoms[item.geom];
     if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = item.m0 + w;
     const int active = (w < item.nm) && (m < g.n_mfp);
     const int adj = pp.adjoint;
@@ -933,28 +806,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     const gmut_t<T> K = gmut(reinterpret_cast<T*>(g.kry) + (size_t)s.sys * KV_N * nw);
     const gmut_t<T> xl = K + (size_t)KV_XL * nw;
     const gmut_t<T> du = K + (size_t)KV_DU * nw;
-    // per-wave LDS: the reduction rows, then nz rows of this wave
-    const int NVR = red_rows(3, adj, pp.want_J, g.wall_in);
-    T* zrows = reinterpret_cast<T*>(lds + (size_t)2 * W * NVR * WAVE * CPL) + (size_t)w * nz * WAVE * CPL;
-    Red rd;
-    rd.lds = lds;
-    rd.w = w;
-    rd.W = W;
-    rd.ROW = WAVE * CPL;
-    rd.local = item.local;
-    rd.want_J = pp.want_J;
-    rd.store_T = pp.store_T;
-    rd.kacc = 0.0;
-    rd.kface = 0.0;
-    rd.NV = NVR;
-    rd.wall_in = g.wall_in;
-    rd.ncells = g.ncells;
-    rd.pTL = gmut(g.part_TL + (size_t)item.local * g.ncells);
-    rd.pTw = gmut(g.part_Tw + (size_t)item.local * g.ndim * g.ncells);
-    rd.pG = gmut(g.part_G + (size_t)item.local * g.ncells);
-    rd.pJ = gmut(g.part_J + (size_t)item.local * g.ncells * g.ndim);
-    rd.Tstore = g.Tstore ? gmut(g.Tstore + (size_t)s.sys * g.ncells) : nullptr;
-    rd.T_L = gview(g.T_L);
+    // per-wave LDS: nz rows of this wave
+    T* zrows = reinterpret_cast<T*>(lds) + (size_t)w * nz * WAVE * CPL;
+    Red<T> rd = make_red<T>(g, s, active, pp);
     // ---- phase A
     {
         GlobIO<T, CPL> io{U, xl, nx, active};
@@ -1086,9 +940,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
         if (need) PLOOP(U[i] += du[i]);
     }
     // ---- phase C (see the 2D kernel)
-    if (!pp.lag_wrap && __syncthreads_or(need)) {
+    if (!pp.lag_wrap && need) {
         GlobIO<T, CPL> io{du, nullptr, nx, 0};
-        sweep<T, CPL, true, false, true, true>(g, s, active && need, lane, adj, srcbase, bnd, io, &rd, zrows);
+        sweep<T, CPL, true, false, true, true>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
         ++n_sw;
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
@@ -1096,38 +950,59 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
 #undef PLOOP
 
 // ---------------------------------------------------------------------------
-// Per-cell / per-wall sums of the item partials (fixed order) and the next
-// pass's inputs sigma T_L and T_w.
+// Per-cell / per-wall sums over the systems' stored solutions (fixed order)
+// and the next pass's inputs sigma T_L and T_w.  Forward: T_L = sum D x and
+// T_w = sum ReLu(S.n)/sum ReLu(S.n) x at the wall cell.  Adjoint: Psi = sigma
+// sum lambda and Phi_f = sum of c_a lambda over the directions entering
+// through f (the transpose of the wall coupling).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_reduce_pass(const GeomDev* __restrict__ geoms, PassParams pp) {
-    __shared__ double part[4][64];
+constexpr int RQ = 16;      // waves per reduction block: system chunks of one 64-cell strip
+
+template <typename T>
+__global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restrict__ geoms, PassParams pp) {
+    __shared__ double part[RQ][64];
     const GeomDev& g = geoms[blockIdx.y];
     if (g.ctrl[CTRL_DONE] && pp.mode == 0) return;
     const int pass = g.ctrl[CTRL_PASS];
     const int out = (pass + 1) & 1;
     const int adj = pp.adjoint;
-    // cells: 64 per block, the item sum split in 4 fixed chunks combined in order
+    const int nc = g.ncells;
+    const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
+    const gptr_t<double> D = gview(g.Dw);
+    // cells: 64 per block, the system sum split in RQ fixed chunks combined in order
     const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
     const int cell = blockIdx.x * 64 + cl;
-    const int per = (g.n_items + 3) / 4;
-    const int i0 = q * per, i1 = min(g.n_items, i0 + per);
+    const int per = (g.n_sys + RQ - 1) / RQ;
+    const int i0 = q * per, i1 = min(g.n_sys, i0 + per);
     double acc = 0.0;
-    if (cell < g.ncells) {
+    if (cell < nc) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int i = i0;
-        for (; i + 3 < i1; i += 4) {
-            a0 += g.part_TL[(size_t)i * g.ncells + cell];
-            a1 += g.part_TL[(size_t)(i + 1) * g.ncells + cell];
-            a2 += g.part_TL[(size_t)(i + 2) * g.ncells + cell];
-            a3 += g.part_TL[(size_t)(i + 3) * g.ncells + cell];
+        if (adj) {
+            for (; i + 3 < i1; i += 4) {
+                a0 += (double)X[(size_t)i * nc + cell];
+                a1 += (double)X[(size_t)(i + 1) * nc + cell];
+                a2 += (double)X[(size_t)(i + 2) * nc + cell];
+                a3 += (double)X[(size_t)(i + 3) * nc + cell];
+            }
+            for (; i < i1; ++i) a0 += (double)X[(size_t)i * nc + cell];
+        } else {
+            for (; i + 3 < i1; i += 4) {
+                a0 += D[i] * (double)X[(size_t)i * nc + cell];
+                a1 += D[i + 1] * (double)X[(size_t)(i + 1) * nc + cell];
+                a2 += D[i + 2] * (double)X[(size_t)(i + 2) * nc + cell];
+                a3 += D[i + 3] * (double)X[(size_t)(i + 3) * nc + cell];
+            }
+            for (; i < i1; ++i) a0 += D[i] * (double)X[(size_t)i * nc + cell];
         }
-        for (; i < i1; ++i) a0 += g.part_TL[(size_t)i * g.ncells + cell];
         acc = (a0 + a1) + (a2 + a3);
     }
     part[q][cl] = acc;
     __syncthreads();
-    if (q == 0 && cell < g.ncells) {
-        const double tot = ((part[0][cl] + part[1][cl]) + part[2][cl]) + part[3][cl];
+    if (q == 0 && cell < nc) {
+        double tot = part[0][cl];
+#pragma unroll
+        for (int j = 1; j < RQ; ++j) tot += part[j][cl];
         const bool sol = fc_solid(g.fc[cell]);
         const double xv = sol ? tot : 0.0;
         if (!adj) g.T_L[cell] = xv;
@@ -1135,45 +1010,44 @@ __global__ void __launch_bounds__(256) k_reduce_pass(const GeomDev* __restrict__
             g.ag[cell] = xv;               // the mixing step writes the next inputs
         } else {
             g.ax[cell] = xv;
-            if (adj) g.lam_psi[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * tot : 0.0;
-            else g.sT[(size_t)out * g.ncells + cell] = sol ? g.sigma[cell] * tot : 0.0;
+            if (adj) g.lam_psi[(size_t)out * nc + cell] = sol ? g.sigma[cell] * tot : 0.0;
+            else g.sT[(size_t)out * nc + cell] = sol ? g.sigma[cell] * tot : 0.0;
         }
     }
-    // walls: one wavefront per wall face; items whose direction leaves the
-    // cell through the face (forward) or enters it (adjoint: outflow of the
-    // reversed direction); each lane sums a fixed strided subset, then a
-    // butterfly, so the order is fixed
+    // walls: one wavefront per wall face; each lane sums a fixed strided
+    // subset of the systems, then a butterfly, so the order is fixed
     const int lane = threadIdx.x & 63;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    double* bnd_out = g.bnd + ((size_t)(adj ? 2 : 0) + out) * g.nf * g.ncells;
+    double* bnd_out = g.bnd + ((size_t)(adj ? 2 : 0) + out) * g.nf * nc;
     for (int wi = wave; wi < g.nwalls; wi += nwaves) {
         const int f = g.wall_face[wi];
         const int ax = f >> 1;
         const double nsgn = (f & 1) ? 1.0 : -1.0;
+        const int wc = g.wall_cell[wi];
         double a = 0.0;
-        const int cell = g.wall_cell[wi];
-        for (int i = lane; i < g.n_items; i += 64) {
-            const int l = i / g.n_grp;          // items are ordered (l, MFP group)
-            const double sd = g.dirs[l * 3 + ax];
-            const size_t at = ((size_t)i * g.ndim + ax) * g.ncells + cell;
-            if (adj) {
-                if (sd * nsgn < 0.0) a += g.part_Tw[at];
-            } else if ((sd > 0.0) == ((f & 1) != 0)) {
-                a += g.part_Tw[at];             // the face is this direction's outflow face
-            } else if (g.wall_in) {
-                a += g.part_Twi[at];
+        if (adj) {
+            for (int sys = lane; sys < g.n_sys; sys += 64) {
+                const int m = sys / g.n_dir, l = sys - m * g.n_dir;
+                const double sd = g.dirs[l * 3 + ax];
+                if (sd * nsgn < 0.0) a += g.mfp[m] * fabs(sd) / g.h[ax] * (double)X[(size_t)sys * nc + wc];
+            }
+        } else {
+            const gptr_t<double> wout = gview(g.wout + (size_t)f * g.n_sys);
+            for (int sys = lane; sys < g.n_sys; sys += 64) {
+                const double wv = wout[sys];
+                if (wv != 0.0) a += wv * (double)X[(size_t)sys * nc + wc];
             }
         }
         a = wave_sum(a);
         if (lane == 0) {
             if (g.aa_m > 0) {
-                g.ag[g.ncells + wi] = a;
+                g.ag[nc + wi] = a;
             } else {
-                g.ax[g.ncells + wi] = a;
+                g.ax[nc + wi] = a;
                 if (adj) g.lam_phi[(size_t)out * g.nwalls + wi] = a;
                 else g.Tw[(size_t)out * g.nwalls + wi] = a;
-                bnd_out[(size_t)f * g.ncells + g.wall_cell[wi]] = a;
+                bnd_out[(size_t)f * nc + wc] = a;
             }
         }
     }
@@ -1815,11 +1689,43 @@ __global__ void k_prep_sigma(const GeomDev* __restrict__ gp, const double* __res
     }
 }
 
-// Outputs of one geometry: T_L with the solid-cell mean removed, the flux map
-// J (sum of the item partials of the replayed last pass) and the adjoint
-// gradient -sum_ml lambda (T - T_L).
-__global__ void __launch_bounds__(1024) k_output(const GeomDev* __restrict__ gp, double* T_L_out,
-                                                double* J_out, double* grad_out) {
+// Flux map of one geometry from the stored solutions of the replayed last
+// sweep: J_i = sum_ml S_ml x_iml (one thread per cell, systems in order).
+template <typename T>
+__global__ void __launch_bounds__(256) k_flux(const GeomDev* __restrict__ gp, double* J_out) {
+    const GeomDev& g = *gp;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncells) return;
+    const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
+    double j[3] = {0.0, 0.0, 0.0};
+    for (int sys = 0; sys < g.n_sys; ++sys) {
+        const double x = (double)X[(size_t)sys * g.ncells + c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) j[a] += g.S[sys * 3 + a] * x;
+    }
+    const bool sol = fc_solid(g.fc[c]);
+    for (int a = 0; a < g.ndim; ++a) J_out[(size_t)c * g.ndim + a] = sol ? j[a] : 0.0;
+}
+
+// Adjoint gradient of one geometry: -sum_ml lambda_iml (T_iml - T_L,i) from
+// the stored adjoint solutions and the stored forward state.
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad(const GeomDev* __restrict__ gp, double* grad_out) {
+    const GeomDev& g = *gp;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncells) return;
+    const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
+    const double tl = g.T_L[c];
+    double acc = 0.0;
+    for (int sys = 0; sys < g.n_sys; ++sys) {
+        const size_t e = (size_t)sys * g.ncells + c;
+        acc += (double)X[e] * (g.Tstore[e] - tl);
+    }
+    grad_out[c] = fc_solid(g.fc[c]) ? -acc : 0.0;
+}
+
+// Lattice temperature of one geometry with the solid-cell mean removed.
+__global__ void __launch_bounds__(1024) k_output(const GeomDev* __restrict__ gp, double* T_L_out) {
     __shared__ double red[32];
     const GeomDev& g = *gp;
     const int n = g.ncells;
@@ -1832,20 +1738,6 @@ __global__ void __launch_bounds__(1024) k_output(const GeomDev* __restrict__ gp,
         const double mean = ns > 0.0 ? sx / ns : 0.0;
         for (int c = threadIdx.x; c < n; c += blockDim.x)
             T_L_out[c] = fc_solid(g.fc[c]) ? g.T_L[c] - mean : 0.0;
-    }
-    if (J_out) {
-        for (int e = threadIdx.x; e < n * g.ndim; e += blockDim.x) {
-            double acc = 0.0;
-            for (int i = 0; i < g.n_items; ++i) acc += g.part_J[(size_t)i * n * g.ndim + e];
-            J_out[e] = fc_solid(g.fc[e / g.ndim]) ? acc : 0.0;
-        }
-    }
-    if (grad_out) {
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
-            double acc = 0.0;
-            for (int i = 0; i < g.n_items; ++i) acc += g.part_G[(size_t)i * n + c];
-            grad_out[c] = fc_solid(g.fc[c]) ? -acc : 0.0;
-        }
     }
 }
 
@@ -1940,13 +1832,14 @@ hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, c
     }
 }
 
-hipError_t launch_reduce_pass(const GeomDev* geoms_dev, int n_geoms, int max_cells, int max_walls,
-                              PassParams pp, hipStream_t st) {
+hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells,
+                              int max_walls, PassParams pp, hipStream_t st) {
     (void)max_walls;
     int blocks = (max_cells + 63) / 64;
     if (blocks < 1) blocks = 1;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_reduce_pass, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp);
+    if (precision == 1) hipLaunchKernelGGL(k_reduce_pass<float>, dim3(blocks, n_geoms), dim3(64 * RQ), 0, st, geoms_dev, pp);
+    else hipLaunchKernelGGL(k_reduce_pass<double>, dim3(blocks, n_geoms), dim3(64 * RQ), 0, st, geoms_dev, pp);
     return hipGetLastError();
 }
 
@@ -2083,10 +1976,18 @@ hipError_t launch_prep_sigma(const GeomDev* g_dev, int ncells, const double* sig
     return hipGetLastError();
 }
 
-hipError_t launch_output(const GeomDev* geoms_dev, int n_geoms, double* T_L_out, double* J_out,
+hipError_t launch_output(const GeomDev* geom_dev, int precision, int ncells, double* T_L_out, double* J_out,
                          double* grad_out, hipStream_t st) {
-    (void)n_geoms;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_output, dim3(1), dim3(1024), 0, st, geoms_dev, T_L_out, J_out, grad_out);
+    const dim3 grid((ncells + 255) / 256);
+    if (T_L_out) hipLaunchKernelGGL(k_output, dim3(1), dim3(1024), 0, st, geom_dev, T_L_out);
+    if (J_out) {
+        if (precision == 1) hipLaunchKernelGGL(k_flux<float>, grid, dim3(256), 0, st, geom_dev, J_out);
+        else hipLaunchKernelGGL(k_flux<double>, grid, dim3(256), 0, st, geom_dev, J_out);
+    }
+    if (grad_out) {
+        if (precision == 1) hipLaunchKernelGGL(k_grad<float>, grid, dim3(256), 0, st, geom_dev, grad_out);
+        else hipLaunchKernelGGL(k_grad<double>, grid, dim3(256), 0, st, geom_dev, grad_out);
+    }
     return hipGetLastError();
 }

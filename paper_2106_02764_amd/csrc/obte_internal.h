@@ -17,13 +17,6 @@ enum { CTRL_DONE = 0, CTRL_PASS = 1, CTRL_CONVERGED = 2, CTRL_NONFINITE = 3, CTR
 
 // wrap-plane vectors per system kept in the workspace by the 3D pass kernel
 constexpr int KRY3_VECS = 11;
-// reduction rows per wave in the pass kernels' LDS: T_L and the walls (one
-// per axis), then the gradient partial (adjoint) or the flux (per axis, only
-// when the flux map is wanted), then (forward, wall_in) the walls a system
-// reaches against its direction (one per axis)
-__host__ __device__ constexpr int red_rows(int ndim, int adjoint, int want_J, int wall_in = 0) {
-    return 1 + ndim + (adjoint ? 1 : (want_J ? ndim : 0)) + ((!adjoint && wall_in) ? ndim : 0);
-}
 
 // Per-geometry view used by every kernel: static tables (library-owned) plus
 // the per-solve workspace carve (caller-owned).
@@ -55,9 +48,8 @@ struct GeomDev {
     double* T_L;                 // ncells: latest lattice temperature
     void* U;                     // n_sys * nwrap (compute precision): wrap inflow vectors
     void* kry;                   // 3D: n_sys * 11 * nwrap (compute precision): wrap-plane Krylov vectors
-    double* part_TL;             // n_items * ncells
-    double* part_Tw;             // n_items * ndim * ncells: wall partial at (item, axis of the wall face, cell)
-    double* part_J;              // n_items * ncells * ndim
+    void* X;                     // n_sys * ncells (compute precision): each system's solution of
+                                 // the pass (forward T, adjoint lambda), 0 in pores
     double* ksys;                // n_sys: kappa_cc contribution of each system
     double* kfsys;               // n_sys: kappa_face contribution
     long long* iters;            // n_sys: accumulated BiCGSTAB iterations
@@ -71,7 +63,6 @@ struct GeomDev {
     double* lam_psi;             // adjoint: 2 * ncells (double buffered Psi)
     double* lam_phi;             // adjoint: 2 * nwalls (double buffered Phi)
     double* gradient;            // adjoint: ncells
-    double* part_G;              // adjoint: n_items * ncells (gradient partials)
     double* bnd;                 // 4 * nf * ncells: inflow boundary value per (face, cell);
                                  // forward buffers 0/1, adjoint buffers 2/3 (double buffered)
     void* mem;                   // 2 * n_sys * 2 * mem_R * nwrap: recycled Krylov pairs
@@ -93,11 +84,6 @@ struct GeomDev {
     double* agram;               // aa_m * aa_m Gram matrix of the adF columns, then aa_m |adX_j|^2
     double* apart;               // per-block partial sums of the mixing kernels
     double* kraw;                // n_sys: sum over cells of each system's last solution
-    // 1 when some system's flux weight S points out of a wall face that its
-    // direction enters through (mode tables only): the wall temperature then
-    // also takes those systems, through part_Twi [item][ndim][ncells]
-    int wall_in;
-    double* part_Twi;
     // 1 with a mode table: the outer iterates are re-centred every pass
     // (ax[n_aa] holds the shift between the two gauge kernels)
     int gauge;
@@ -143,8 +129,8 @@ hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, hipStrea
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
                              const Item* items_dev, int n_items, int waves, PassParams pp,
                              size_t lds_bytes, hipStream_t st);
-hipError_t launch_reduce_pass(const GeomDev* geoms_dev, int n_geoms, int max_cells, int max_walls,
-                              PassParams pp, hipStream_t st);
+hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells,
+                              int max_walls, PassParams pp, hipStream_t st);
 // Anderson mixing: per-block partials (up to 256 blocks of 256 threads per
 // geometry, 2 * AA_MAX + 3 sums each), then the combination.
 constexpr size_t aa_partial_doubles() { return 256 * (2 * AA_MAX + 3); }
@@ -157,7 +143,9 @@ hipError_t launch_kappa_modes(const int* sys, const double* w, const double* Sg,
 hipError_t launch_gauge(const GeomDev* geoms_dev, int n_geoms, int max_aa, hipStream_t st);
 hipError_t launch_anderson(const GeomDev* geoms_dev, int n_geoms, int max_naa, PassParams pp, hipStream_t st);
 hipError_t launch_finalize(const GeomDev* geoms_dev, int n_geoms, PassParams pp, hipStream_t st);
-hipError_t launch_output(const GeomDev* geoms_dev, int n_geoms, double* T_L_out, double* J_out,
+// outputs of one geometry (T_L centred, the flux map, the adjoint gradient;
+// each skipped when its pointer is null)
+hipError_t launch_output(const GeomDev* geom_dev, int precision, int ncells, double* T_L_out, double* J_out,
                          double* grad_out, hipStream_t st);
 hipError_t launch_prep_sigma(const GeomDev* g_dev, int ncells, const double* sig, hipStream_t st);
 hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, const GeomDev& g_host,
