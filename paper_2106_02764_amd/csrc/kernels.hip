@@ -146,25 +146,39 @@ __device__ __forceinline__ double readlane(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One Hillis-Steele step of the affine-map scan: this lane's map (A,Q,P)
-// is composed after the map of the source lane (identity where none).
-template <int CTRL, int RM, typename T>
-__device__ __forceinline__ void scan_step(T& A, T& Q, T& P) {
-    const T A2 = dpp<CTRL, RM>(A, T(0)), Q2 = dpp<CTRL, RM>(Q, T(1)), P2 = dpp<CTRL, RM>(P, T(0));
-    A = A + Q * A2;
-    P = P + Q * P2;
-    Q = Q * Q2;
+// One Hillis-Steele step of the affine-map scan: this lane's map x -> A + Q x
+// is composed after the map of the source lane (identity where none).  Only
+// A and P = 1 - Q are carried: P keeps full relative accuracy where it is
+// small (a nearly closed cyclic chain, the closure divides by it), and where
+// 1 - P is inexact (Q tiny) it only scales terms it makes negligible.
+// Full-mask row shifts read the source with bound_ctrl (a lane without
+// source reads 0, the identity's A and P).
+template <int CTRL, int RM>
+__device__ __forceinline__ void scan_step(float& A, float& P) {
+    const bool bc = RM == 0xf;
+    const float A2 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(A), CTRL, RM, 0xf, bc));
+    const float P2 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(P), CTRL, RM, 0xf, bc));
+    const float t = 1.0f - P;
+    A = A + t * A2;
+    P = P + t * P2;
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ void scan_step(double& A, double& P) {
+    const double A2 = dpp<CTRL, RM>(A, 0.0), P2 = dpp<CTRL, RM>(P, 0.0);
+    const double t = 1.0 - P;
+    A = A + t * A2;
+    P = P + t * P2;
 }
 
-// Inclusive wavefront scan of x -> A + Q x maps (P = 1 - Q carried exactly).
+// Inclusive wavefront scan of the maps (A, P).
 template <typename T>
-__device__ __forceinline__ void wave_scan(T& A, T& Q, T& P) {
-    scan_step<0x111, 0xf>(A, Q, P);   // row_shr:1
-    scan_step<0x112, 0xf>(A, Q, P);   // row_shr:2
-    scan_step<0x114, 0xf>(A, Q, P);   // row_shr:4
-    scan_step<0x118, 0xf>(A, Q, P);   // row_shr:8
-    scan_step<0x142, 0xa>(A, Q, P);   // row_bcast:15 into rows 1, 3
-    scan_step<0x143, 0xc>(A, Q, P);   // row_bcast:31 into rows 2, 3
+__device__ __forceinline__ void wave_scan(T& A, T& P) {
+    scan_step<0x111, 0xf>(A, P);   // row_shr:1
+    scan_step<0x112, 0xf>(A, P);   // row_shr:2
+    scan_step<0x114, 0xf>(A, P);   // row_shr:4
+    scan_step<0x118, 0xf>(A, P);   // row_shr:8
+    scan_step<0x142, 0xa>(A, P);   // row_bcast:15 into rows 1, 3
+    scan_step<0x143, 0xc>(A, P);   // row_bcast:31 into rows 2, 3
 }
 
 // Loads through these views compile to global (not flat) loads, which keep
@@ -293,8 +307,11 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
     constexpr int ND = D3 ? 3 : 2;
     const int nx = g.nx, ny = g.ny;
     const T cz = D3 ? s.c[2] : T(0);
+    // diagonal without sigma (2D: no z term, so no +0 is left in the chain)
+    const T cdiag = D3 ? s.c[0] + s.c[1] + cz : s.c[0] + s.c[1];
+    const T cyz = D3 ? s.c[1] + cz : s.c[1];
     T a[CPL], q[CPL];
-    T Al = T(0), Ql = T(1), Pl = T(0);
+    T Al, Pl;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int p = lane * CPL + c;
@@ -304,38 +321,41 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         const int cly = fc_class(w, s.fin[1]);
         const int clz = D3 ? fc_class(w, s.fin[2]) : FC_WALL;
         const T sg = cur.sg[c];
-        const T rdv = recip(sg + s.c[0] + s.c[1] + cz);
-        T src = T(0);
+        const T rdv = recip(sg + cdiag);
+        // kk and jj are wave-uniform: the wrap input is read on the first row only
+        T yin = T(0);
+        if (cly != FC_WALL) yin = (jj == 0) ? io.in(kk, c, lane) : s.c[1] * rows.prev_y(kk, c, lane);
+        T rhs = yin;
         if (WITH_B) {
             double sd = adj ? s.kw + s.Dml * cur.sb[c] : cur.sb[c];
             sd += mb[0] * cur.bx[c] + mb[1] * cur.by[c];
             if (D3) sd += mb[2] * cur.bz[c];
-            src = (T)sd;
+            rhs = (T)sd + yin;
         }
-        // kk and jj are wave-uniform: the wrap input is read on the first row only
-        T yin = T(0);
-        if (cly != FC_WALL) yin = (jj == 0) ? io.in(kk, c, lane) : s.c[1] * rows.prev_y(kk, c, lane);
-        T zin = T(0);
-        if (D3) zin = (clz != FC_WALL && kk > 0) ? cz * rows.prev_z(c) : T(0);
+        if (D3) rhs += (clz != FC_WALL && kk > 0) ? cz * rows.prev_z(c) : T(0);
         const bool xs = (clx != FC_WALL);
-        T av = (src + yin + zin) * rdv;
+        T av = rhs * rdv;
         T qv = xs ? s.c[0] * rdv : T(0);
-        T pv = (sg + s.c[1] + cz + (xs ? T(0) : s.c[0])) * rdv;
+        T pv = (sg + (xs ? cyz : cdiag)) * rdv;
         // pore: (0, 0, 1) breaks the chain; beyond the row: identity (0, 1, 0)
         if (!sol) { av = T(0); qv = T(0); pv = T(1); }
         if (p >= nx) { av = T(0); qv = T(1); pv = T(0); }
         a[c] = av;
         q[c] = qv;
-        Al = av + qv * Al;
-        Pl = pv + qv * Pl;
-        Ql = qv * Ql;
+        if (c == 0) {
+            Al = av;
+            Pl = pv;
+        } else {
+            Al = av + qv * Al;
+            Pl = pv + qv * Pl;
+        }
     }
-    T A = Al, Q = Ql, P = Pl;
-    wave_scan(A, Q, P);
+    T A = Al, P = Pl;
+    wave_scan(A, P);
     const T At = readlane(A, WAVE - 1), Pt = readlane(P, WAVE - 1);
     const T xin = (Pt > T(0)) ? At * recip(Pt) : T(0);   // cyclic closure x_{-1} = x_{nx-1}
-    const T Ae = dpp<0x138, 0xf>(A, T(0)), Qe = dpp<0x138, 0xf>(Q, T(1));   // wave_shr:1
-    T xp = Ae + Qe * xin;
+    const T Ae = dpp<0x138, 0xf>(A, T(0)), Pe = dpp<0x138, 0xf>(P, T(0));   // wave_shr:1
+    T xp = Ae + (T(1) - Pe) * xin;
     T xrow[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
