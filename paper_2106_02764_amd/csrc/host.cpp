@@ -754,6 +754,9 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
     }
     if (!o->only_fourier) {
         PassParams pp = base_params(o);
+        pp.sigma1 = 1;
+        for (int i = 0; i < n; ++i)
+            if (sigma && sigma[i]) pp.sigma1 = 0;
         s = outer_loop(R, pp, K, st, o->max_outer, &tm);
         if (s != OBTE_OK) return s;
         // replay the last pass's final sweep for the flux map / stored state
@@ -1249,6 +1252,7 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     HIPCHK(hipMemsetAsync(ws + L.actl, 0, 8 * sizeof(int), st));
     PassParams pp = base_params(o);
     pp.adjoint = 1;
+    pp.sigma1 = sigma_dev ? 0 : 1;
     const int K = (o->passes_per_graph <= 1 || !st || o->timing) ? 1 : o->passes_per_graph;
     Timer tm;
     if (o->timing && (s = tm.init(K)) != OBTE_OK) return s;

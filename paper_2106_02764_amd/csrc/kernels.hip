@@ -230,7 +230,7 @@ struct Views {
     gptr_t<double> src, bx, by, bz;
 };
 
-template <typename T, int CPL, bool D3, bool WITH_B>
+template <typename T, int CPL, bool D3, bool WITH_B, bool S1>
 __device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, const Views<T>& v, int lane,
                                          int jj, int kk, RowIn<T, CPL>& r) {
     const int nx = g.nx;
@@ -243,7 +243,7 @@ __device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, con
         const bool in = p < nx;
         const int cell = rowbase + (in ? (s.pos[0] ? p : nx - 1 - p) : 0);
         r.w[c] = in ? (uint32_t)v.fc[cell] : 0u;
-        r.sg[c] = v.sg[cell];
+        r.sg[c] = S1 ? T(1) : v.sg[cell];
         if (WITH_B) {
             r.sb[c] = v.src[cell];
             r.bx[c] = v.bx[cell];
@@ -299,7 +299,7 @@ struct GlobIO {
 };
 
 // One row step of the sweep (cells of row (jj, kk) in upwind order).
-template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, class IO>
+template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, class IO>
 __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, const Views<T>& vw,
                                          int active, int lane, int adj, int jj, int kk,
                                          const RowIn<T, CPL>& cur, Rows<T, CPL, D3>& rows, IO& io,
@@ -310,6 +310,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
     // diagonal without sigma (2D: no z term, so no +0 is left in the chain)
     const T cdiag = D3 ? s.c[0] + s.c[1] + cz : s.c[0] + s.c[1];
     const T cyz = D3 ? s.c[1] + cz : s.c[1];
+    const T rdv1 = S1 ? recip(T(1) + cdiag) : T(0);
     T a[CPL], q[CPL];
     T Al, Pl;
 #pragma unroll
@@ -320,8 +321,9 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         const int clx = fc_class(w, s.fin[0]);
         const int cly = fc_class(w, s.fin[1]);
         const int clz = D3 ? fc_class(w, s.fin[2]) : FC_WALL;
-        const T sg = cur.sg[c];
-        const T rdv = recip(sg + cdiag);
+        // sigma = 1 everywhere (no multiplier given): rdv is this system's constant
+        const T sg = S1 ? T(1) : cur.sg[c];
+        const T rdv = S1 ? rdv1 : recip(sg + cdiag);
         // kk and jj are wave-uniform: the wrap input is read on the first row only
         T yin = T(0);
         if (cly != FC_WALL) yin = (jj == 0) ? io.in(kk, c, lane) : s.c[1] * rows.prev_y(kk, c, lane);
@@ -337,9 +339,12 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         T av = rhs * rdv;
         T qv = xs ? s.c[0] * rdv : T(0);
         T pv = (sg + (xs ? cyz : cdiag)) * rdv;
-        // pore: (0, 0, 1) breaks the chain; beyond the row: identity (0, 1, 0)
-        if (!sol) { av = T(0); qv = T(0); pv = T(1); }
-        if (p >= nx) { av = T(0); qv = T(1); pv = T(0); }
+        // pore: (0, 0, 1) breaks the chain; beyond the row (face word 0, so
+        // not solid either): the identity (0, 1, 0)
+        const bool beyond = p >= nx;
+        av = sol ? av : T(0);
+        qv = sol ? qv : (beyond ? T(1) : T(0));
+        pv = sol ? pv : (beyond ? T(0) : T(1));
         a[c] = av;
         q[c] = qv;
         if (c == 0) {
@@ -418,7 +423,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 // ---------------------------------------------------------------------------
 constexpr int PF2D = 4;    // 2D rows in flight (prefetch depth + 1)
 
-template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, class IO>
+template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, class IO>
 __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int active, int lane, int adj,
                                       const double* __restrict__ srcbase, const double* __restrict__ bnd,
                                       IO& io, Red<T>* rd, T* zrows) {
@@ -452,14 +457,14 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
         RowIn<T, CPL> b[PF2D];
 #pragma unroll
         for (int r = 0; r < PF2D - 1; ++r)
-            if (r < ny) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, r, 0, b[r]);
+            if (r < ny) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, r, 0, b[r]);
         for (int jj = 0; jj < ny; jj += PF2D) {
 #pragma unroll
             for (int r = 0; r < PF2D; ++r) {
                 if (jj + r < ny) {
                     if (jj + r + PF2D - 1 < ny)
-                        load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, jj + r + PF2D - 1, 0, b[(r + PF2D - 1) % PF2D]);
-                    row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, jj + r, 0, b[r], rows, io,
+                        load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, jj + r + PF2D - 1, 0, b[(r + PF2D - 1) % PF2D]);
+                    row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, jj + r, 0, b[r], rows, io,
                                                            mb, rd);
                 }
             }
@@ -469,17 +474,17 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
         // inputs two rows ahead (the row order is y-major, z-minor)
         const int nz = g.nz, nrows = ny * nz;
         RowIn<T, CPL> b0, b1, b2;
-        load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 0, 0, b0);
-        if (nrows > 1) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, 1 / nz, 1 % nz, b1);
+        load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, 0, 0, b0);
+        if (nrows > 1) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, 1 / nz, 1 % nz, b1);
         for (int r = 0; r < nrows; r += 3) {
-            if (r + 2 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 2) / nz, (r + 2) % nz, b2);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, r / nz, r % nz, b0, rows, io, mb, rd);
+            if (r + 2 < nrows) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, (r + 2) / nz, (r + 2) % nz, b2);
+            row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, r / nz, r % nz, b0, rows, io, mb, rd);
             if (r + 1 >= nrows) break;
-            if (r + 3 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 3) / nz, (r + 3) % nz, b0);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, (r + 1) / nz, (r + 1) % nz, b1, rows, io, mb, rd);
+            if (r + 3 < nrows) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, (r + 3) / nz, (r + 3) % nz, b0);
+            row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, (r + 1) / nz, (r + 1) % nz, b1, rows, io, mb, rd);
             if (r + 2 >= nrows) break;
-            if (r + 4 < nrows) load_row<T, CPL, D3, WITH_B>(g, s, vw, lane, (r + 4) / nz, (r + 4) % nz, b1);
-            row_step<T, CPL, D3, WITH_B, RED, ADD>(g, s, vw, active, lane, adj, (r + 2) / nz, (r + 2) % nz, b2, rows, io, mb, rd);
+            if (r + 4 < nrows) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, (r + 4) / nz, (r + 4) % nz, b1);
+            row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, (r + 2) / nz, (r + 2) % nz, b2, rows, io, mb, rd);
         }
     }
 }
@@ -637,7 +642,7 @@ __device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s
 // changed u sweeps the source P (u - u0) and adds the (linear) response to
 // its stored solution.
 // ---------------------------------------------------------------------------
-template <typename T, int CPL>
+template <typename T, int CPL, int ADJ, int SIG1>
 __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ geoms,
                                                     const Item* __restrict__ items, int n_items,
                                                     PassParams pp) {
@@ -650,7 +655,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = item.m0 + w;
     const int active = (w < item.nm) && (m < g.n_mfp);
-    const int adj = pp.adjoint;
+    constexpr int adj = ADJ;     // the adjoint's branches fold at compile time
     const SysC<T> s = make_sys<T>(g, active ? m : item.m0, item.l, adj);
     const int pass = g.ctrl[CTRL_PASS];
     const int buf_in = (pp.mode == 1) ? ((pass + 1) & 1) : (pass & 1);
@@ -677,7 +682,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     // ---- phase A
     {
         RegIO<T, CPL> io{u[0], xl[0]};
-        sweep<T, CPL, false, true, true, false>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+        sweep<T, CPL, false, true, true, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
     }
     long long n_it = 0, n_sw = 1;
     int need = 0;
@@ -720,7 +725,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 VLOOP(p[k][c] = r[k][c] + (T)beta * (p[k][c] - (T)omega * v[k][c]));
                 {
                     RegIO<T, CPL> io{p[0], xl[0]};
-                    sweep<T, CPL, false, false, false, false>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                    sweep<T, CPL, false, false, false, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
                 }
                 ++n_sw;
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
@@ -745,7 +750,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 }
                 {
                     RegIO<T, CPL> io{sv[0], xl[0]};
-                    sweep<T, CPL, false, false, false, false>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                    sweep<T, CPL, false, false, false, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
                 }
                 ++n_sw;
                 VLOOP(t[k][c] = sv[k][c] - mk[k][c] * xl[k][c]);
@@ -776,7 +781,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     // when the correction is lagged into the next pass)
     if (!pp.lag_wrap && need) {
         RegIO<T, CPL> io{du[0], xl[0]};
-        sweep<T, CPL, false, false, true, true>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+        sweep<T, CPL, false, false, true, true, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
         ++n_sw;
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
@@ -801,7 +806,7 @@ static_assert(KV_N == KRY3_VECS, "workspace carve and kernel disagree on the 3D 
             }                                           \
         }
 
-template <typename T, int CPL>
+template <typename T, int CPL, int ADJ, int SIG1>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL == 1 ? 3 : 1))) k_sweep_pass3(const GeomDev* __restrict__ geoms,
                                                      const Item* __restrict__ items, int n_items,
                                                      PassParams pp) {
@@ -814,7 +819,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = item.m0 + w;
     const int active = (w < item.nm) && (m < g.n_mfp);
-    const int adj = pp.adjoint;
+    constexpr int adj = ADJ;
     const SysC<T> s = make_sys<T>(g, active ? m : item.m0, item.l, adj);
     const int pass = g.ctrl[CTRL_PASS];
     const int buf_in = (pp.mode == 1) ? ((pass + 1) & 1) : (pass & 1);
@@ -832,7 +837,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     // ---- phase A
     {
         GlobIO<T, CPL> io{U, xl, nx, active};
-        sweep<T, CPL, true, true, true, false>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+        sweep<T, CPL, true, true, true, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
     }
     long long n_it = 0, n_sw = 1;
     int need = 0;
@@ -889,7 +894,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
                 PLOOP(p[i] = r[i] + (T)beta * (p[i] - (T)omega * v[i]));
                 {
                     GlobIO<T, CPL> io{p, xl, nx, 1};
-                    sweep<T, CPL, true, false, false, false>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
+                    sweep<T, CPL, true, false, false, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
                 }
                 ++n_sw;
                 acc = 0.0;
@@ -924,7 +929,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
                 }
                 {
                     GlobIO<T, CPL> io{sv, xl, nx, 1};
-                    sweep<T, CPL, true, false, false, false>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
+                    sweep<T, CPL, true, false, false, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
                 }
                 ++n_sw;
                 double tt = 0.0, ts = 0.0;
@@ -962,7 +967,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     // ---- phase C (see the 2D kernel)
     if (!pp.lag_wrap && need) {
         GlobIO<T, CPL> io{du, nullptr, nx, 0};
-        sweep<T, CPL, true, false, true, true>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+        sweep<T, CPL, true, false, true, true, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
         ++n_sw;
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
@@ -1806,7 +1811,14 @@ template <typename T, int CPL>
 static hipError_t launch_sweep_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
                                  size_t lds, hipStream_t st) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL((k_sweep_pass<T, CPL>), dim3(n), dim3(64 * waves), lds, st, g, it, n, pp);
+    const dim3 grid(n), block(64 * waves);
+    if (pp.adjoint) {
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass<T, CPL, 1, 1>), grid, block, lds, st, g, it, n, pp);
+        else hipLaunchKernelGGL((k_sweep_pass<T, CPL, 1, 0>), grid, block, lds, st, g, it, n, pp);
+    } else {
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass<T, CPL, 0, 1>), grid, block, lds, st, g, it, n, pp);
+        else hipLaunchKernelGGL((k_sweep_pass<T, CPL, 0, 0>), grid, block, lds, st, g, it, n, pp);
+    }
     return hipGetLastError();
 }
 
@@ -1814,7 +1826,14 @@ template <typename T, int CPL>
 static hipError_t launch_sweep3_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
                                   size_t lds, hipStream_t st) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL((k_sweep_pass3<T, CPL>), dim3(n), dim3(64 * waves), lds, st, g, it, n, pp);
+    const dim3 grid(n), block(64 * waves);
+    if (pp.adjoint) {
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 1, 1>), grid, block, lds, st, g, it, n, pp);
+        else hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 1, 0>), grid, block, lds, st, g, it, n, pp);
+    } else {
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 0, 1>), grid, block, lds, st, g, it, n, pp);
+        else hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 0, 0>), grid, block, lds, st, g, it, n, pp);
+    }
     return hipGetLastError();
 }
 

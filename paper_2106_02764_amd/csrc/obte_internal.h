@@ -113,6 +113,7 @@ struct PassParams {
     double inner_rtol; // per-pass wrap solve stops once the residual fell by this factor
     double wrap_tol;   // stop test: every relative wrap residual <= wrap_tol
     int stop_rule;     // 0 = relative change, 1 = change * rho / (1 - rho)
+    int sigma1;        // 1 when no geometry of the launch has a sigma field (sigma = 1)
 };
 
 // kernel launchers (kernels.hip)
