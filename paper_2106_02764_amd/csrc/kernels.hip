@@ -228,15 +228,19 @@ struct Views {
     gptr_t<uint16_t> fc;
     gptr_t<T> sg;
     gptr_t<double> src, bx, by, bz;
+    // geometry scalars read once per sweep: the row loop stores to global
+    // memory, after which the compiler would reload them from the view
+    int nx, ny, nz, ga;
+    double dT;
 };
 
 template <typename T, int CPL, bool D3, bool WITH_B, bool S1>
 __device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, const Views<T>& v, int lane,
                                          int jj, int kk, RowIn<T, CPL>& r) {
-    const int nx = g.nx;
-    const int iy = s.pos[1] ? jj : g.ny - 1 - jj;
-    const int iz = D3 ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
-    const int rowbase = nx * (iy + g.ny * iz);
+    const int nx = v.nx;
+    const int iy = s.pos[1] ? jj : v.ny - 1 - jj;
+    const int iz = D3 ? (s.pos[2] ? kk : v.nz - 1 - kk) : 0;
+    const int rowbase = nx * (iy + v.ny * iz);
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int p = lane * CPL + c;
@@ -305,12 +309,14 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                                          const RowIn<T, CPL>& cur, Rows<T, CPL, D3>& rows, IO& io,
                                          const double (&mb)[3], Red<T>* rd) {
     constexpr int ND = D3 ? 3 : 2;
-    const int nx = g.nx, ny = g.ny;
+    const int nx = vw.nx, ny = vw.ny;
     const T cz = D3 ? s.c[2] : T(0);
     // diagonal without sigma (2D: no z term, so no +0 is left in the chain)
     const T cdiag = D3 ? s.c[0] + s.c[1] + cz : s.c[0] + s.c[1];
     const T cyz = D3 ? s.c[1] + cz : s.c[1];
+    // sigma = 1: the cell coefficients are this system's constants
     const T rdv1 = S1 ? recip(T(1) + cdiag) : T(0);
+    const T q1 = s.c[0] * rdv1, pxs1 = (T(1) + cyz) * rdv1, pnx1 = (T(1) + cdiag) * rdv1;
     T a[CPL], q[CPL];
     T Al, Pl;
 #pragma unroll
@@ -337,8 +343,8 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         if (D3) rhs += (clz != FC_WALL && kk > 0) ? cz * rows.prev_z(c) : T(0);
         const bool xs = (clx != FC_WALL);
         T av = rhs * rdv;
-        T qv = xs ? s.c[0] * rdv : T(0);
-        T pv = (sg + (xs ? cyz : cdiag)) * rdv;
+        T qv = xs ? (S1 ? q1 : s.c[0] * rdv) : T(0);
+        T pv = S1 ? (xs ? pxs1 : pnx1) : (sg + (xs ? cyz : cdiag)) * rdv;
         // pore: (0, 0, 1) breaks the chain; beyond the row (face word 0, so
         // not solid either): the identity (0, 1, 0)
         const bool beyond = p >= nx;
@@ -376,7 +382,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
     }
     if (RED && rd->X) {
         const int iy = s.pos[1] ? jj : ny - 1 - jj;
-        const int iz = D3 ? (s.pos[2] ? kk : g.nz - 1 - kk) : 0;
+        const int iz = D3 ? (s.pos[2] ? kk : vw.nz - 1 - kk) : 0;
         const int rowbase = nx * (iy + ny * iz);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
@@ -394,16 +400,16 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 #pragma unroll
                     for (int ax = 0; ax < ND; ++ax) {
                         const int cl = fc_class(wv, s.fout[ax]);
-                        if (cl == FC_JUMP_P) rd->kface += s.cd[ax] * g.dT * xv;
-                        else if (cl == FC_JUMP_M) rd->kface -= s.cd[ax] * g.dT * xv;
+                        if (cl == FC_JUMP_P) rd->kface += s.cd[ax] * vw.dT * xv;
+                        else if (cl == FC_JUMP_M) rd->kface -= s.cd[ax] * vw.dT * xv;
                     }
                 } else {
                     // kappa through the periodic plane of the gradient axis;
                     // the jump term belongs to the b sweep only
-                    if (g.grad_axis == 0 && p == nx - 1 && fc_class(wv, s.fout[0]) != FC_WALL)
-                        rd->kface += xv + ((!ADD && s.pos[0]) ? g.dT : 0.0);
-                    if (g.grad_axis == 1 && jj == ny - 1 && fc_class(wv, s.fout[1]) != FC_WALL)
-                        rd->kface += xv + ((!ADD && s.pos[1]) ? g.dT : 0.0);
+                    if (vw.ga == 0 && p == nx - 1 && fc_class(wv, s.fout[0]) != FC_WALL)
+                        rd->kface += xv + ((!ADD && s.pos[0]) ? vw.dT : 0.0);
+                    if (vw.ga == 1 && jj == ny - 1 && fc_class(wv, s.fout[1]) != FC_WALL)
+                        rd->kface += xv + ((!ADD && s.pos[1]) ? vw.dT : 0.0);
                 }
                 if (rd->store_T) rd->Tstore[cell] = xv;
             }
@@ -445,6 +451,11 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     vw.bx = gview(bnd + (size_t)fb[0] * g.ncells);
     vw.by = gview(bnd + (size_t)fb[1] * g.ncells);
     vw.bz = gview(bnd + (size_t)(D3 ? fb[2] : 0) * g.ncells);
+    vw.nx = g.nx;
+    vw.ny = g.ny;
+    vw.nz = g.nz;
+    vw.ga = g.grad_axis;
+    vw.dT = g.dT;
     Rows<T, CPL, D3> rows;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) rows.xr[c] = T(0);
