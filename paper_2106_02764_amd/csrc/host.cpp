@@ -467,19 +467,21 @@ struct Run {
     std::vector<obte_mesh*> meshes;
     std::vector<GeomDev> views;
     std::vector<Item> items;
+    // device copies of the views and the item list, and the pending count,
+    // in the caller's workspace after the geometries (no allocation per call)
     GeomDev* d_views = nullptr;
     Item* d_items = nullptr;
     int* d_pending = nullptr;     // geometries whose Fourier CG still iterates
+    size_t state_off = 0, state_bytes = 0;
     int waves = 4, cpl = 1, nzmax = 1, precision = 0, accel = 0;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
     size_t lds = 0;               // the largest any launch of this run needs
     int max_cells = 0, max_walls = 0;
-    ~Run() {
-        if (d_views) soft(hipFree(d_views), "hipFree(views)");
-        if (d_items) soft(hipFree(d_items), "hipFree(items)");
-        if (d_pending) soft(hipFree(d_pending), "hipFree(pending)");
-    }
 };
+
+size_t run_state_bytes(size_t n_views, size_t n_items) {
+    return align256(n_views * sizeof(GeomDev)) + align256(n_items * sizeof(Item)) + 256;
+}
 
 // Systems per workgroup of a launch over these meshes, and the LDS each of
 // its waves needs (the same rule for the workspace size and the solve).
@@ -557,9 +559,19 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
             return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
     R.lds = (size_t)W * per_wave;
-    HIPCHK(hipMalloc((void**)&R.d_views, R.views.size() * sizeof(GeomDev)));
-    HIPCHK(hipMalloc((void**)&R.d_items, R.items.size() * sizeof(Item)));
-    HIPCHK(hipMalloc((void**)&R.d_pending, sizeof(int)));
+    R.state_off = off;
+    R.state_bytes = run_state_bytes(R.views.size(), R.items.size());
+    return OBTE_OK;
+}
+
+// Place the run's device state in the workspace (after the size check).
+obte_status upload_run(Run& R, char* ws) {
+    char* p = ws + R.state_off;
+    R.d_views = (GeomDev*)p;
+    p += align256(R.views.size() * sizeof(GeomDev));
+    R.d_items = (Item*)p;
+    p += align256(R.items.size() * sizeof(Item));
+    R.d_pending = (int*)p;
     HIPCHK(hipMemcpy(R.d_views, R.views.data(), R.views.size() * sizeof(GeomDev), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(R.d_items, R.items.data(), R.items.size() * sizeof(Item), hipMemcpyHostToDevice));
     return OBTE_OK;
@@ -709,10 +721,10 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
     s = build_run(R, meshes, n, o, (char*)workspace, &offs);
     if (s != OBTE_OK) return s;
     {
-        size_t need = 0;
-        for (int i = 0; i < n; ++i) need += align256(make_layout(meshes[i], o, R.waves).total);
+        const size_t need = R.state_off + R.state_bytes;
         if (ws_bytes < need)
             return fail(OBTE_ERR_NOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+        if ((s = upload_run(R, (char*)workspace)) != OBTE_OK) return s;
     }
     for (int i = 0; i < n; ++i) {
         obte_mesh* m = meshes[i];
@@ -1172,9 +1184,12 @@ obte_status obte_workspace_size_batch(const obte_mesh* const* meshes, int n, con
     size_t per_wave = 0;
     s = resolve_waves(meshes, n, o, &W, &per_wave);
     if (s != OBTE_OK) return s;
-    size_t total = 0;
-    for (int i = 0; i < n; ++i) total += align256(make_layout(meshes[i], o, W).total);
-    *bytes = total;
+    size_t total = 0, items = 0;
+    for (int i = 0; i < n; ++i) {
+        total += align256(make_layout(meshes[i], o, W).total);
+        items += (size_t)meshes[i]->n_dir * n_groups(meshes[i], W);
+    }
+    *bytes = total + run_state_bytes(n, items);
     return OBTE_OK;
 }
 
@@ -1233,8 +1248,9 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     s = build_run(R, &mp, 1, &oo, (char*)workspace, nullptr);
     if (s != OBTE_OK) return s;
     Layout L = make_layout(m, &oo, R.waves);
-    if (ws_bytes < align256(L.total))
+    if (ws_bytes < R.state_off + R.state_bytes)
         return fail(OBTE_ERR_NOMEM, "workspace too small for the adjoint (accel deeper than the forward solve's?)");
+    if ((s = upload_run(R, (char*)workspace)) != OBTE_OK) return s;
     char* ws = (char*)workspace;
     // lambda^(0) = 0: Psi = Phi = 0, no warm start, fresh counters
     HIPCHK(hipMemsetAsync(ws + L.lam_psi, 0, 2 * (size_t)m->ncells * 8, st));
