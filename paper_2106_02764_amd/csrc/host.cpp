@@ -68,7 +68,7 @@ struct obte_mesh {
     // device tables (library-owned)
     int device = -1;
     uint16_t* d_fc = nullptr;
-    int *d_wall_idx = nullptr, *d_wall_cell = nullptr, *d_wall_face = nullptr;
+    int *d_wall_cell = nullptr, *d_wall_face = nullptr;
     double *d_mfp = nullptr, *d_dirs = nullptr, *d_D = nullptr, *d_S = nullptr, *d_wout = nullptr,
            *d_kax = nullptr;
     GeomDev* d_geom = nullptr;      // single-geometry view (apply, outputs)
@@ -322,10 +322,8 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
     g.grad_axis = m->grad_axis;
     g.dT = m->dT;
     g.n_mfp = m->n_mfp; g.n_dir = m->n_dir; g.n_sys = m->n_sys;
-    g.n_grp = waves > 0 ? n_groups(m, waves) : 1;
-    g.n_items = m->n_dir * g.n_grp;
     g.n_perp = m->ncells / (m->grad_axis == 0 ? m->nx : (m->grad_axis == 1 ? m->ny : m->nz));
-    g.fc = m->d_fc; g.wall_idx = m->d_wall_idx; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face;
+    g.fc = m->d_fc; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face;
     g.mfp = m->d_mfp; g.dirs = m->d_dirs; g.Dw = m->d_D; g.S = m->d_S; g.wout = m->d_wout;
     g.gauge = m->n_modes > 0 ? 1 : 0;
     g.kappa_axis = m->d_kax;
@@ -382,12 +380,12 @@ obte_status upload(T** dst, const std::vector<T>& src) {
 }
 
 void free_dev(obte_mesh* m) {
-    void* ptrs[] = {m->d_fc, m->d_wall_idx, m->d_wall_cell, m->d_wall_face, m->d_mfp, m->d_dirs,
+    void* ptrs[] = {m->d_fc, m->d_wall_cell, m->d_wall_face, m->d_mfp, m->d_dirs,
                     m->d_D, m->d_S, m->d_wout, m->d_kax, m->d_geom, m->d_mode_sys, m->d_mode_w,
                     m->d_mode_Sg, m->d_kmode};
     for (void* p : ptrs)
         if (p) soft(hipFree(p), "hipFree(table)");
-    m->d_fc = nullptr; m->d_wall_idx = m->d_wall_cell = m->d_wall_face = nullptr;
+    m->d_fc = nullptr; m->d_wall_cell = m->d_wall_face = nullptr;
     m->d_mfp = m->d_dirs = m->d_D = m->d_S = m->d_wout = m->d_kax = nullptr;
     m->d_geom = nullptr;
     m->d_mode_sys = nullptr;
@@ -536,7 +534,6 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         Layout L = make_layout(m, o, W);
         if (offsets) offsets->push_back(off);
         GeomDev v = make_view(m, ws + off, L, W, o->recycle, o->accel);
-        v.item0 = (int)R.items.size();
         const int ng = n_groups(m, W);
         for (int l = 0; l < m->n_dir; ++l)
             for (int gp = 0; gp < ng; ++gp) {
@@ -545,7 +542,6 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
                 it.l = l;
                 it.m0 = gp * W;
                 it.nm = std::min(W, m->n_mfp - gp * W);
-                it.local = l * ng + gp;
                 R.items.push_back(it);
             }
         R.views.push_back(v);
@@ -775,7 +771,6 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         if ((J_out || keep_T) && n == 1) {
             PassParams rp = pp;
             rp.mode = 1;
-            rp.want_J = J_out != nullptr;
             rp.store_T = keep_T ? 1 : 0;
             HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items,
                                      (int)R.items.size(), R.waves, rp,
@@ -1141,7 +1136,6 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     HIPCHK(hipGetDevice(&m->device));
     obte_status s;
     if ((s = upload(&m->d_fc, m->fc)) != OBTE_OK) return s;
-    if ((s = upload(&m->d_wall_idx, m->wall_idx)) != OBTE_OK) return s;
     if ((s = upload(&m->d_wall_cell, m->wall_cell)) != OBTE_OK) return s;
     if ((s = upload(&m->d_wall_face, m->wall_face)) != OBTE_OK) return s;
     if ((s = upload(&m->d_mfp, m->mfp)) != OBTE_OK) return s;

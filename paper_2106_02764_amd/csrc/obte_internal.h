@@ -26,12 +26,9 @@ struct GeomDev {
     int grad_axis;
     double h[3], L[3], dT;
     int n_mfp, n_dir, n_sys;
-    int n_items, item0;          // this geometry's work items in the global list
-    int n_grp;                   // MFP groups per direction (items are ordered l-major)
     int n_perp;                  // ncells / n[grad_axis]
     // ---- static tables
     const uint16_t* fc;          // ncells
-    const int* wall_idx;         // ncells * nf, -1 where the face is not a wall
     const int* wall_cell;        // nwalls
     const int* wall_face;        // nwalls: face index 2a+side of the owning cell
     const double* mfp;           // n_mfp
@@ -97,14 +94,12 @@ struct Item {
     int l;       // direction
     int m0;      // first MFP of the group
     int nm;      // MFPs in the group (<= waves per group)
-    int local;   // item index within its geometry
 };
 
 struct PassParams {
     double inner_tol;
     int max_inner;
     int mode;          // 0 = full pass, 1 = replay the last pass's final sweep only (J / store)
-    int want_J;
     int store_T;       // write the final x of every system to Tstore
     int adjoint;       // 1 = transposed system with adjoint sources
     int max_outer;
