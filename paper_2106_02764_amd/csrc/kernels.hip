@@ -818,7 +818,7 @@ static_assert(KV_N == KRY3_VECS, "workspace carve and kernel disagree on the 3D 
         }
 
 template <typename T, int CPL, int ADJ, int SIG1>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL == 1 ? 3 : 1))) k_sweep_pass3(const GeomDev* __restrict__ geoms,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL == 1 ? (sizeof(T) == 4 ? 5 : 4) : 1))) k_sweep_pass3(const GeomDev* __restrict__ geoms,
                                                      const Item* __restrict__ items, int n_items,
                                                      PassParams pp) {
     extern __shared__ double lds[];
