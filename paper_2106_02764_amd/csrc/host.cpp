@@ -471,6 +471,10 @@ struct Run {
     Item* d_items = nullptr;
     int* d_pending = nullptr;     // geometries whose Fourier CG still iterates
     size_t state_off = 0, state_bytes = 0;
+    // items grouped by cells per lane (ceil(nx / 64)): one launch per class,
+    // so a narrow geometry of a batch does not run the widest row's kernel
+    int cls_first[5] = {}, cls_count[5] = {};
+    size_t cls_lds[5] = {};
     int waves = 4, cpl = 1, nzmax = 1, precision = 0, accel = 0;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
     size_t lds = 0;               // the largest any launch of this run needs
@@ -529,12 +533,14 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     if (s != OBTE_OK) return s;
     R.waves = W;
     size_t off = 0;
+    std::vector<Item> by_cls[5];
     for (int gi = 0; gi < n; ++gi) {
         obte_mesh* m = meshes[gi];
         Layout L = make_layout(m, o, W);
         if (offsets) offsets->push_back(off);
         GeomDev v = make_view(m, ws + off, L, W, o->recycle, o->accel);
         const int ng = n_groups(m, W);
+        const int c = (m->nx + 63) / 64;
         for (int l = 0; l < m->n_dir; ++l)
             for (int gp = 0; gp < ng; ++gp) {
                 Item it;
@@ -542,7 +548,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
                 it.l = l;
                 it.m0 = gp * W;
                 it.nm = std::min(W, m->n_mfp - gp * W);
-                R.items.push_back(it);
+                by_cls[c].push_back(it);
             }
         R.views.push_back(v);
         R.cpl = std::max(R.cpl, (m->nx + 63) / 64);
@@ -555,6 +561,13 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
             return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
     R.lds = (size_t)W * per_wave;
+    const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
+    for (int c = 1; c <= 4; ++c) {
+        R.cls_first[c] = (int)R.items.size();
+        R.cls_count[c] = (int)by_cls[c].size();
+        R.items.insert(R.items.end(), by_cls[c].begin(), by_cls[c].end());
+        R.cls_lds[c] = R.nzmax > 1 ? (size_t)W * R.nzmax * 64 * c * tsz : 0;
+    }
     R.state_off = off;
     R.state_bytes = run_state_bytes(R.views.size(), R.items.size());
     return OBTE_OK;
@@ -573,10 +586,19 @@ obte_status upload_run(Run& R, char* ws) {
     return OBTE_OK;
 }
 
+// The pass kernel over every item, one launch per cells-per-lane class.
+obte_status launch_sweeps(const Run& R, const PassParams& pp, hipStream_t st) {
+    for (int c = 1; c <= 4; ++c)
+        if (R.cls_count[c] > 0)
+            HIPCHK(launch_sweep_pass(R.precision, c, R.nzmax, R.d_views, R.d_items + R.cls_first[c],
+                                     R.cls_count[c], R.waves, pp, R.cls_lds[c], st));
+    return OBTE_OK;
+}
+
 obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Timer* tm, int k) {
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k], st));
-    HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items, (int)R.items.size(),
-                             R.waves, pp, R.lds, st));
+    obte_status s = launch_sweeps(R, pp, st);
+    if (s != OBTE_OK) return s;
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 1], st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 2], st));
     HIPCHK(launch_reduce_pass(R.precision, R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
@@ -772,9 +794,8 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
             PassParams rp = pp;
             rp.mode = 1;
             rp.store_T = keep_T ? 1 : 0;
-            HIPCHK(launch_sweep_pass(R.precision, R.cpl, R.nzmax, R.d_views, R.d_items,
-                                     (int)R.items.size(), R.waves, rp,
-                                     R.lds, st));
+            s = launch_sweeps(R, rp, st);
+            if (s != OBTE_OK) return s;
         }
     }
     if (n == 1 && (T_L_out || J_out)) HIPCHK(launch_output(meshes[0]->d_geom, R.precision, meshes[0]->ncells, T_L_out, o->only_fourier ? nullptr : J_out, nullptr, st));
