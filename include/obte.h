@@ -206,7 +206,10 @@ obte_status obte_mesh_create(const obte_mesh_desc* desc, obte_mesh** out);
  * small tables to the current device).  Must precede obte_solve. */
 obte_status obte_material_set(obte_mesh* mesh, const obte_material_desc* mat);
 
-/* Bytes of device workspace obte_solve / obte_adjoint need for `opts`. */
+/* Bytes of device workspace obte_solve / obte_adjoint need for `opts`.  The
+ * workspace holds every per-solve array, including the launch state (the
+ * geometry views and the work-item list): a solve allocates no device
+ * memory. */
 obte_status obte_workspace_size(const obte_mesh* mesh, const obte_solve_opts* opts,
                                 size_t* bytes);
 
@@ -231,7 +234,8 @@ obte_status obte_solve(obte_mesh* mesh, const obte_solve_opts* opts, const doubl
                        void* workspace_dev, size_t workspace_bytes, void* stream, double* T_L_dev,
                        double* J_dev, obte_stats* stats);
 
-/* Many independent geometries in one persistent launch per pass.  meshes[i]
+/* Many independent geometries in one launch per pass (one per row-width
+ * class: ceil(nx / 64) cells per lane).  meshes[i]
  * and sigma_dev[i] (nullable entries) as above; one workspace holds all, of
  * at least obte_workspace_size_batch bytes (OBTE_ERR_NOMEM otherwise); all
  * meshes must share the number of MFPs unless waves_per_group is set.  kappa_out: host, n doubles (kappa_cc).  stats: host,

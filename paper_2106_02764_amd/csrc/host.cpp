@@ -475,9 +475,8 @@ struct Run {
     // so a narrow geometry of a batch does not run the widest row's kernel
     int cls_first[5] = {}, cls_count[5] = {};
     size_t cls_lds[5] = {};
-    int waves = 4, cpl = 1, nzmax = 1, precision = 0, accel = 0;
+    int waves = 4, nzmax = 1, precision = 0, accel = 0;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
-    size_t lds = 0;               // the largest any launch of this run needs
     int max_cells = 0, max_walls = 0;
 };
 
@@ -551,7 +550,6 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
                 by_cls[c].push_back(it);
             }
         R.views.push_back(v);
-        R.cpl = std::max(R.cpl, (m->nx + 63) / 64);
         R.nzmax = std::max(R.nzmax, m->nz);
         R.max_cells = std::max(R.max_cells, m->ncells);
         R.max_walls = std::max(R.max_walls, m->nwalls);
@@ -560,7 +558,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     for (int gi = 0; gi < n; ++gi)
         if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
             return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
-    R.lds = (size_t)W * per_wave;
+    (void)per_wave;               // the LDS bound was checked by resolve_waves
     const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
     for (int c = 1; c <= 4; ++c) {
         R.cls_first[c] = (int)R.items.size();
