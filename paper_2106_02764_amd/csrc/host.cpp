@@ -53,6 +53,15 @@ constexpr int HIST_CAP = 1 << 16;
 
 }  // namespace
 
+// A captured graph kept across calls while the launches it was captured from
+// (the key: pointers, counts and parameters, as bytes) are unchanged.
+struct GraphSlot {
+    std::vector<unsigned char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void reset();
+};
+
 struct obte_mesh {
     // geometry
     int ndim = 2, nx = 1, ny = 1, nz = 1, nf = 4, ncells = 0, nsolid = 0, nwalls = 0;
@@ -88,7 +97,67 @@ struct obte_mesh {
     int* d_mode_sys = nullptr;
     double *d_mode_w = nullptr, *d_mode_Sg = nullptr, *d_kmode = nullptr;
     bool modes_solved = false;
+    // graphs of the last single-mesh solve / adjoint, reused by the next call
+    // with the same workspace, options and tables
+    GraphSlot g_fourier, g_pass, g_adj;
 };
+
+void GraphSlot::reset() {
+    if (exec) soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
+    if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy");
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+}
+
+template <typename... Ts>
+std::vector<unsigned char> graph_key(const Ts&... parts) {
+    std::vector<unsigned char> k;
+    auto add = [&](const auto& v) {
+        const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+        k.insert(k.end(), p, p + sizeof v);
+    };
+    (add(parts), ...);
+    return k;
+}
+
+// The instantiated graph of `enqueue` captured on st: the slot's when its key
+// matches (then the slot keeps ownership), else a new capture, which the slot
+// takes over (or, without a slot, the caller destroys via *owned_graph).
+template <class F>
+obte_status slot_graph(GraphSlot* slot, const std::vector<unsigned char>& key, hipStream_t st, F enqueue,
+                       hipGraphExec_t* exec_out, hipGraph_t* owned_graph) {
+    *owned_graph = nullptr;
+    if (slot && slot->exec && slot->key == key) {
+        *exec_out = slot->exec;
+        return OBTE_OK;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const obte_status s = enqueue();
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (s != OBTE_OK) {
+        if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy");
+        return s;
+    }
+    if (e != hipSuccess) return fail(OBTE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+        soft(hipGraphDestroy(graph), "hipGraphDestroy");
+        return fail(OBTE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e2));
+    }
+    if (slot) {
+        slot->reset();
+        slot->graph = graph;
+        slot->exec = exec;
+        slot->key = key;
+    } else {
+        *owned_graph = graph;
+    }
+    *exec_out = exec;
+    return OBTE_OK;
+}
 
 namespace {
 
@@ -380,6 +449,9 @@ obte_status upload(T** dst, const std::vector<T>& src) {
 }
 
 void free_dev(obte_mesh* m) {
+    m->g_fourier.reset();
+    m->g_pass.reset();
+    m->g_adj.reset();
     void* ptrs[] = {m->d_fc, m->d_wall_cell, m->d_wall_face, m->d_mfp, m->d_dirs,
                     m->d_D, m->d_S, m->d_wout, m->d_kax, m->d_geom, m->d_mode_sys, m->d_mode_w,
                     m->d_mode_Sg, m->d_kmode};
@@ -610,7 +682,7 @@ obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Tim
 // Fourier first guess of every geometry: CG iterations replayed as HIP graphs
 // of KF iterations (with the count of geometries still iterating at the end)
 // until none is left; direct launches when there is no stream to capture.
-obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st) {
+obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st, GraphSlot* slot) {
     const int n = (int)R.views.size();
     constexpr int KF = 8;     // even: an iteration's parity is its position in the graph
     HIPCHK(launch_fourier_init(R.d_views, n, R.max_cells, st));
@@ -624,19 +696,12 @@ obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st) 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     if (st) {
-        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        const hipError_t e1 = enqueue();
-        const hipError_t e2 = hipStreamEndCapture(st, &graph);
-        if (e1 != hipSuccess || e2 != hipSuccess) {
-            if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy");
-            return fail(OBTE_ERR_HIP, "Fourier graph capture failed: %s",
-                        hipGetErrorString(e1 != hipSuccess ? e1 : e2));
-        }
-        const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e3 != hipSuccess) {
-            soft(hipGraphDestroy(graph), "hipGraphDestroy");
-            return fail(OBTE_ERR_HIP, "Fourier graph instantiate failed: %s", hipGetErrorString(e3));
-        }
+        const auto key = graph_key(R.d_views, R.d_pending, n, R.max_cells, o->fourier_tol, o->max_fourier, KF);
+        obte_status s = slot_graph(slot, key, st, [&]() -> obte_status {
+            const hipError_t e = enqueue();
+            return e == hipSuccess ? OBTE_OK : fail(OBTE_ERR_HIP, "Fourier graph capture: %s", hipGetErrorString(e));
+        }, &exec, &graph);
+        if (s != OBTE_OK) return s;
     }
     obte_status out = OBTE_OK;
     int pending = 1;
@@ -647,8 +712,10 @@ obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st) 
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
         if (e2 != hipSuccess) { out = fail(OBTE_ERR_HIP, "Fourier readback: %s", hipGetErrorString(e2)); break; }
     }
-    if (exec) soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
-    if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy");
+    if (graph) {      // not kept by a slot
+        soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
+        soft(hipGraphDestroy(graph), "hipGraphDestroy");
+    }
     if (out != OBTE_OK) return out;
     HIPCHK(launch_fourier_finish(R.d_views, n, st));
     return OBTE_OK;
@@ -656,24 +723,22 @@ obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st) 
 
 // Replays graphs of K passes until every geometry reports done.
 obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st, int max_outer,
-                       Timer* tm) {
+                       Timer* tm, GraphSlot* slot) {
     const int n = (int)R.views.size();
     std::vector<int> ctrl(CTRL_N);
     if (tm && tm->on && tm->K < K) return fail(OBTE_ERR_STATE, "timer sized for fewer passes");
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     if (K > 1) {
-        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        obte_status s = OBTE_OK;
-        for (int k = 0; k < K && s == OBTE_OK; ++k) s = enqueue_pass(R, pp, st, tm, k);
-        hipError_t e = hipStreamEndCapture(st, &graph);
-        if (s != OBTE_OK) { if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy"); return s; }
-        if (e != hipSuccess) return fail(OBTE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            soft(hipGraphDestroy(graph), "hipGraphDestroy");
-            return fail(OBTE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
-        }
+        const auto key = graph_key(R.d_views, R.d_items, (int)R.views.size(), R.cls_first, R.cls_count, R.cls_lds,
+                                   R.waves, R.precision, R.nzmax, R.max_cells, R.max_walls, R.gauge, R.accel,
+                                   pp, K, tm && tm->on);
+        obte_status s = slot_graph(slot, key, st, [&]() -> obte_status {
+            obte_status sk = OBTE_OK;
+            for (int k = 0; k < K && sk == OBTE_OK; ++k) sk = enqueue_pass(R, pp, st, tm, k);
+            return sk;
+        }, &exec, &graph);
+        if (s != OBTE_OK) return s;
     }
     obte_status out = OBTE_OK;
     int launched = 0;
@@ -699,8 +764,10 @@ obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st
         if (out != OBTE_OK || all_done) break;
         if (launched > max_outer + K + 2) { out = fail(OBTE_ERR_STATE, "outer loop did not terminate"); break; }
     }
-    if (exec) soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
-    if (graph) soft(hipGraphDestroy(graph), "hipGraphDestroy");
+    if (graph) {      // not kept by a slot
+        soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
+        soft(hipGraphDestroy(graph), "hipGraphDestroy");
+    }
     return out;
 }
 
@@ -767,7 +834,7 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
     }
     if (o->init == 0) {
         if (tm.on) HIPCHK(hipEventRecord(tm.f0, st));
-        s = run_fourier(R, o, st);
+        s = run_fourier(R, o, st, n == 1 ? &meshes[0]->g_fourier : nullptr);
         if (s != OBTE_OK) return s;
         if (tm.on) HIPCHK(hipEventRecord(tm.f1, st));
     } else {
@@ -785,7 +852,7 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         pp.sigma1 = 1;
         for (int i = 0; i < n; ++i)
             if (sigma && sigma[i]) pp.sigma1 = 0;
-        s = outer_loop(R, pp, K, st, o->max_outer, &tm);
+        s = outer_loop(R, pp, K, st, o->max_outer, &tm, n == 1 ? &meshes[0]->g_pass : nullptr);
         if (s != OBTE_OK) return s;
         // replay the last pass's final sweep for the flux map / stored state
         if ((J_out || keep_T) && n == 1) {
@@ -1285,7 +1352,7 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     const int K = (o->passes_per_graph <= 1 || !st || o->timing) ? 1 : o->passes_per_graph;
     Timer tm;
     if (o->timing && (s = tm.init(K)) != OBTE_OK) return s;
-    s = outer_loop(R, pp, K, st, o->max_outer, &tm);
+    s = outer_loop(R, pp, K, st, o->max_outer, &tm, &m->g_adj);
     if (s != OBTE_OK) return s;
     HIPCHK(launch_output(m->d_geom, R.precision, m->ncells, nullptr, nullptr, grad_dev, st));
     std::vector<int> ctrl(CTRL_N);
