@@ -182,3 +182,23 @@ def test_converged_anderson(P, name, accel):
     Jref = np.zeros((w.n_cells, w.ndim))
     Jref[prob.mesh.cells] = ref["J"]
     assert rel(r["J"], Jref) < 1e-9
+
+
+def test_repeated_solves_reuse_graphs(P):
+    """A mesh keeps its captured graphs across solves with the same
+    workspace and options: the second solve replays them and gives the
+    same bits; other options capture new ones and still match a fresh
+    solver."""
+    w = ragged_porous()
+    s = P.Solver.from_workload(w)
+    o = s.opts(outer_tol=1e-9, passes_per_graph=4)
+    a = s.solve(o, want_J=True)
+    b = s.solve(o, want_J=True)
+    assert a["kappa"] == b["kappa"] and a["outer_iters"] == b["outer_iters"]
+    assert torch.equal(a["T_L"], b["T_L"]) and torch.equal(a["J"], b["J"])
+    o2 = s.opts(outer_tol=1e-9, passes_per_graph=3, accel=4)
+    c = s.solve(o2)
+    fresh = gpu_solve(P, w, want_J=False, outer_tol=1e-9, passes_per_graph=3, accel=4)
+    assert c["kappa"] == fresh["kappa"] and c["outer_iters"] == fresh["outer_iters"]
+    d = s.solve(o, want_J=True)
+    assert d["kappa"] == a["kappa"] and torch.equal(d["T_L"], a["T_L"])
