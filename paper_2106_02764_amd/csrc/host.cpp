@@ -717,7 +717,7 @@ obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st, 
         soft(hipGraphDestroy(graph), "hipGraphDestroy");
     }
     if (out != OBTE_OK) return out;
-    HIPCHK(launch_fourier_finish(R.d_views, n, st));
+    HIPCHK(launch_fourier_finish(R.d_views, n, R.max_cells, st));
     return OBTE_OK;
 }
 

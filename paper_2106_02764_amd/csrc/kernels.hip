@@ -1282,102 +1282,77 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_apply(const GeomDev* __restri
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        // every loop below runs over the fixed AA_MAX so the small matrices
-        // stay in registers; columns beyond cnt1 are identity rows
+    // The small least-squares solve on the first wave, one lane per entry of
+    // the AA_MAX x AA_MAX Gram matrix: lane t holds entry (r, k) = (t / 8,
+    // t % 8) and the vectors' entry j = t % 8.  Every loop runs over the
+    // fixed AA_MAX; rows and columns beyond cnt1 are identity rows.
+    static_assert(AA_MAX * AA_MAX == WAVE, "one lane per Gram matrix entry");
+    if (threadIdx.x < WAVE) {
+        const int t = threadIdx.x, r = t / AA_MAX, k = t % AA_MAX, j = k;
         const double* dxg = g.agram + M * M;            // |dX_j|^2 of the stored columns
         // this pass's Gram matrix: the new column's row from the partials,
         // the rest from the stored matrix (block 0 stores the new row)
-        double G[AA_MAX][AA_MAX], dxn[AA_MAX], b[AA_MAX], d[AA_MAX], y[AA_MAX];
-#pragma unroll
-        for (int j = 0; j < AA_MAX; ++j) {
-            const bool aj = j < cnt1;
-#pragma unroll
-            for (int k2 = 0; k2 < AA_MAX; ++k2) {
-                double val = (j == k2) ? 1.0 : 0.0;
-                if (aj && k2 < cnt1) {
-                    const bool fresh = have && (j == slot || k2 == slot);
-                    val = fresh ? tot[j == slot ? k2 : j] : g.agram[j * M + k2];
-                }
-                G[j][k2] = val;
-            }
-            dxn[j] = aj ? ((have && j == slot) ? tot[2 * AA_MAX + 2] : dxg[j]) : 0.0;
-            b[j] = aj ? tot[AA_MAX + j] : 0.0;
+        double a = r == k ? 1.0 : 0.0;
+        if (r < cnt1 && k < cnt1) {
+            const bool fresh = have && (r == slot || k == slot);
+            a = fresh ? tot[r == slot ? k : r] : g.agram[r * M + k];
         }
-        if (blockIdx.x == 0 && have) {
-#pragma unroll
-            for (int j = 0; j < AA_MAX; ++j)
-                if (j < cnt1) {
-                    const double val = tot[j];          // new column against column j
-                    g.agram[slot * M + j] = val;
-                    g.agram[j * M + slot] = val;
-                }
-            g.agram[M * M + slot] = tot[2 * AA_MAX + 2];
+        const bool vj = j < cnt1;
+        const double dxn = vj ? ((have && j == slot) ? tot[2 * AA_MAX + 2] : dxg[j]) : 0.0;
+        const double bj = vj ? tot[AA_MAX + j] : 0.0;
+        const double gjj = shfl_at(a, (AA_MAX + 1) * j);
+        if (blockIdx.x == 0 && have && t < cnt1) {
+            const double val = tot[t];                  // new column against column t
+            g.agram[slot * M + t] = val;
+            g.agram[t * M + slot] = val;
+            if (t == 0) g.agram[M * M + slot] = tot[2 * AA_MAX + 2];
         }
         // error estimate for the stop test: with f = (G - I) e for a linear G,
         // |e| <= |f| / s_min(I - G); s_min is estimated by the smallest
         // |dF_j| / |dX_j| over the stored columns (no columns: |f| itself)
-        double smin = 1.0;
+        double sm = (vj && dxn > 0.0) ? sqrt(gjj / dxn) : 1.0;
 #pragma unroll
-        for (int j = 0; j < AA_MAX; ++j)
-            if (j < cnt1 && dxn[j] > 0.0) smin = fmin(smin, sqrt(G[j][j] / dxn[j]));
-        smin = fmax(smin, 1e-3);
+        for (int m = 1; m < AA_MAX; m <<= 1) sm = fmin(sm, shfl_xor(sm, m));
+        const double smin = fmax(fmin(sm, 1.0), 1e-3);
         const double sf = tot[2 * AA_MAX], sx = tot[2 * AA_MAX + 1];
         const double res = sx > 0.0 ? sqrt(sf / sx) : (sf > 0.0 ? INFINITY : 0.0);
-        if (blockIdx.x == 0) g.fscal[3] = res / smin;
+        if (blockIdx.x == 0 && t == 0) g.fscal[3] = res / smin;
         // scaled normal equations with a small ridge, Cholesky in place
-        bool ok = cnt1 > 0;
-#pragma unroll
-        for (int j = 0; j < AA_MAX; ++j) {
-            d[j] = j < cnt1 ? sqrt(G[j][j]) : 1.0;
-            ok = ok && d[j] > 0.0 && isfinite(d[j]);
-        }
+        // (right-looking: step p finishes column p and updates the trailing
+        // block), then the two triangular solves; ok is wave-uniform
+        const double dj = vj ? sqrt(gjj) : 1.0;
+        bool ok = cnt1 > 0 && __all(dj > 0.0 && isfinite(dj));
+        double y = 0.0;
         if (ok) {
+            const double dr = shfl_at(dj, r);
+            a = a / (dr * dj) + ((r == k && r < cnt1) ? 1e-10 : 0.0);
 #pragma unroll
-            for (int j = 0; j < AA_MAX; ++j)
-#pragma unroll
-                for (int k2 = 0; k2 < AA_MAX; ++k2)
-                    G[j][k2] = G[j][k2] / (d[j] * d[k2]) + ((j == k2 && j < cnt1) ? 1e-10 : 0.0);
-#pragma unroll
-            for (int j = 0; j < AA_MAX; ++j) {
-                double s2 = G[j][j];
-#pragma unroll
-                for (int k2 = 0; k2 < j; ++k2) s2 -= G[j][k2] * G[j][k2];
+            for (int p = 0; p < AA_MAX; ++p) {
+                const double s2 = shfl_at(a, (AA_MAX + 1) * p);
                 ok = ok && s2 > 1e-14;
-                const double ljj = sqrt(fmax(s2, 1e-300));
-                G[j][j] = ljj;
+                const double lpp = sqrt(fmax(s2, 1e-300));
+                if (k == p) a = r == p ? lpp : (r > p ? a / lpp : a);
+                const double lr = shfl_at(a, AA_MAX * r + p), lk = shfl_at(a, AA_MAX * k + p);
+                if (r > p && k > p && k <= r) a -= lr * lk;
+            }
+            y = bj / dj;
 #pragma unroll
-                for (int r = j + 1; r < AA_MAX; ++r) {
-                    double t = G[r][j];
-#pragma unroll
-                    for (int k2 = 0; k2 < j; ++k2) t -= G[r][k2] * G[j][k2];
-                    G[r][j] = t / ljj;
-                }
+            for (int p = 0; p < AA_MAX; ++p) {
+                const double yp = shfl_at(y, p) / shfl_at(a, (AA_MAX + 1) * p);
+                const double ljp = shfl_at(a, AA_MAX * j + p);
+                y = j == p ? yp : (j > p ? y - ljp * yp : y);
             }
 #pragma unroll
-            for (int j = 0; j < AA_MAX; ++j) {
-                double t = b[j] / d[j];
-#pragma unroll
-                for (int k2 = 0; k2 < j; ++k2) t -= G[j][k2] * y[k2];
-                y[j] = t / G[j][j];
+            for (int p = AA_MAX - 1; p >= 0; --p) {
+                const double zp = shfl_at(y, p) / shfl_at(a, (AA_MAX + 1) * p);
+                const double lpj = shfl_at(a, AA_MAX * p + j);
+                y = j == p ? zp : (j < p ? y - lpj * zp : y);
             }
-#pragma unroll
-            for (int j = AA_MAX - 1; j >= 0; --j) {
-                double t = y[j];
-#pragma unroll
-                for (int k2 = j + 1; k2 < AA_MAX; ++k2) t -= G[k2][j] * y[k2];
-                y[j] = t / G[j][j];
-            }
-#pragma unroll
-            for (int j = 0; j < AA_MAX; ++j) {
-                const double gj = j < cnt1 ? y[j] / d[j] : 0.0;
-                ok = ok && isfinite(gj);
-                y[j] = gj;
-            }
+            y = vj ? y / dj : 0.0;
+            ok = ok && __all(isfinite(y));
         }
-#pragma unroll
-        for (int j = 0; j < AA_MAX; ++j) gam[j] = ok ? y[j] : 0.0;
-        if (blockIdx.x == 0) {
+        if (t < AA_MAX) gam[t] = ok ? y : 0.0;
+        if (blockIdx.x == 0 && t == 0) {
             int* ao = g.actl + 4 * out;
             if (ok || cnt1 == 0) {
                 ao[0] = cnt1;
@@ -1419,69 +1394,6 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_apply(const GeomDev* __restri
 // order (no atomics), so every block of a geometry takes the same decisions,
 // and a converged geometry's blocks exit at once.
 // ---------------------------------------------------------------------------
-// Shared epilogue: x (solution, global) -> mean-free T_F, sigma T_F, T_w, the
-// inflow boundary tables and kappa_F; resets the pass control words.
-__device__ void fourier_epilogue(const GeomDev& g, double* red, int iter, double rn, double bn) {
-    const int n = g.ncells, nf = g.nf;
-    double* x = g.fx;
-    double sx = 0.0, ns = 0.0;
-    for (int c = threadIdx.x; c < n; c += blockDim.x)
-        if (fc_solid(g.fc[c])) { sx += x[c]; ns += 1.0; }
-    sx = block_sum(sx, red);
-    ns = block_sum(ns, red);
-    const double mean = sx / ns;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const bool sol = fc_solid(g.fc[c]);
-        const double t = sol ? x[c] - mean : 0.0;
-        x[c] = t;
-        g.T_L[c] = t;
-        g.sT[c] = sol ? g.sigma[c] * t : 0.0;   // buffer 0
-    }
-    __syncthreads();
-    // inflow boundary values per (face, cell): periodic jumps +-dT (fixed),
-    // walls T_w (updated every pass), interior 0; forward buffers 0 and 1,
-    // adjoint buffers 2 and 3 (no jump source; walls updated per pass)
-    for (int e = threadIdx.x; e < nf * n; e += blockDim.x) {
-        const int f = e / n, c = e - f * n;
-        const uint16_t w = g.fc[c];
-        const int cl = fc_solid(w) ? fc_class(w, f) : FC_INTERIOR;
-        const double v = cl == FC_JUMP_P ? g.dT : (cl == FC_JUMP_M ? -g.dT : 0.0);
-        g.bnd[e] = v;
-        g.bnd[(size_t)nf * n + e] = v;
-        g.bnd[(size_t)2 * nf * n + e] = 0.0;
-        g.bnd[(size_t)3 * nf * n + e] = 0.0;
-    }
-    __syncthreads();
-    for (int wi = threadIdx.x; wi < g.nwalls; wi += blockDim.x) {
-        const double t = x[g.wall_cell[wi]];
-        g.Tw[wi] = t;
-        g.bnd[(size_t)g.wall_face[wi] * n + g.wall_cell[wi]] = t;
-        g.ax[n + wi] = t;
-    }
-    // the first iterate of the outer fixed point, mixing history cleared
-    for (int c = threadIdx.x; c < n; c += blockDim.x) g.ax[c] = x[c];
-    if (g.aa_m > 0 && threadIdx.x < 8) g.actl[threadIdx.x] = 0;
-    // kappa_F: plane flux through the periodic plane of the gradient axis
-    const int ga = g.grad_axis;
-    double fl = 0.0;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const uint16_t w = g.fc[c];
-        if (!fc_solid(w)) continue;
-        const int f = 2 * ga;   // '-' face of the cell at index 0
-        if (fc_class(w, f) == FC_JUMP_P) {
-            const int j = nbr_cell(g, c, f);
-            fl += g.kappa_axis[ga] * (x[j] + g.dT - x[c]) / g.h[ga];
-        }
-    }
-    fl = block_sum(fl, red);
-    if (threadIdx.x == 0) {
-        g.fscal[0] = g.L[ga] / (g.dT * (double)g.n_perp) * fl;
-        g.fscal[1] = (double)iter;
-        g.fscal[2] = bn > 0.0 ? rn / bn : 0.0;
-        for (int i = 0; i < CTRL_N; ++i) g.ctrl[i] = 0;
-    }
-}
-
 __device__ __forceinline__ double fourier_rhs(const GeomDev& g, uint16_t w, const double (&kf)[3]) {
     double b = 0.0;
     if (fc_solid(w))
@@ -1497,7 +1409,7 @@ constexpr int FB_MAX = 256, FB_THREADS = 256;
 
 // This geometry's CG storage (in the fx region) and block b's cell range.
 struct FView {
-    double *x, *r, *p0, *p1, *ap, *pap, *rr0, *rr1, *sc;   // sc: [0] |b|, [1] done, [4] iterations
+    double *x, *r, *p0, *p1, *ap, *pap, *rr0, *rr1, *sc;   // sc: [0] |b|, [1] done, [2] mean of x, [4] iterations
     int n, B, c0, c1;
 };
 __device__ __forceinline__ FView fourier_view(const GeomDev& g, int b) {
@@ -1668,15 +1580,81 @@ __global__ void __launch_bounds__(256) k_fourier_pending(const GeomDev* __restri
     if (threadIdx.x == 0) *pending = (int)c;
 }
 
+// End of the Fourier solve, in two kernels.  The first (one block per
+// geometry) takes the solid-cell mean of x, which the gauge removes, and
+// kappa_F from the plane flux through the periodic plane of the gradient axis
+// (differences of x, so the mean drops out); it stores the mean in sc[2] and
+// resets the pass control words.  The second, over the geometry's cell blocks,
+// writes the mean-free T_F as T_L, sigma T_F, the wall temperatures, the
+// first iterate of the outer fixed point and the inflow tables: periodic
+// jumps +-dT (fixed), walls T_w (updated every pass), interior 0; forward
+// buffers 0 and 1, adjoint buffers 2 and 3 (no jump source; walls updated per
+// pass).  A wall's first temperature is its cell's, so buffer 0's wall entries
+// take the cell value directly.
 __global__ void __launch_bounds__(1024) k_fourier_finish(const GeomDev* __restrict__ geoms) {
     __shared__ double red[32];
     const GeomDev& g = geoms[blockIdx.x];
     const FView v = fourier_view(g, 0);
     const int it = (int)v.sc[4];
-    const double rr = sum_partials((it & 1) ? v.rr1 : v.rr0, v.B, red);
+    const double rn = sqrt(sum_partials((it & 1) ? v.rr1 : v.rr0, v.B, red));
     const double bn = v.sc[0];
-    __syncthreads();
-    fourier_epilogue(g, red, it, sqrt(rr), bn);
+    const int n = g.ncells, ga = g.grad_axis;
+    const double* x = g.fx;
+    double sx = 0.0, ns = 0.0, fl = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const uint16_t w = g.fc[c];
+        if (!fc_solid(w)) continue;
+        sx += x[c];
+        ns += 1.0;
+        const int f = 2 * ga;   // '-' face of the cell at index 0
+        if (fc_class(w, f) == FC_JUMP_P) {
+            const int j = nbr_cell(g, c, f);
+            fl += g.kappa_axis[ga] * (x[j] + g.dT - x[c]) / g.h[ga];
+        }
+    }
+    sx = block_sum(sx, red);
+    ns = block_sum(ns, red);
+    fl = block_sum(fl, red);
+    if (g.aa_m > 0 && threadIdx.x < 8) g.actl[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        v.sc[2] = sx / ns;
+        g.fscal[0] = g.L[ga] / (g.dT * (double)g.n_perp) * fl;
+        g.fscal[1] = (double)it;
+        g.fscal[2] = bn > 0.0 ? rn / bn : 0.0;
+        for (int i = 0; i < CTRL_N; ++i) g.ctrl[i] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(FB_THREADS) k_fourier_fill(const GeomDev* __restrict__ geoms) {
+    const GeomDev& g = geoms[blockIdx.y];
+    const FView v = fourier_view(g, blockIdx.x);
+    if ((int)blockIdx.x >= v.B) return;
+    const int n = g.ncells, nf = g.nf;
+    const double mean = v.sc[2];
+    const double* x = g.fx;
+    const size_t nb = (size_t)nf * n;
+    for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
+        const uint16_t w = g.fc[c];
+        const bool sol = fc_solid(w);
+        const double t = sol ? x[c] - mean : 0.0;
+        g.T_L[c] = t;
+        g.sT[c] = sol ? g.sigma[c] * t : 0.0;   // buffer 0
+        g.ax[c] = t;
+        for (int f = 0; f < nf; ++f) {
+            const int cl = sol ? fc_class(w, f) : FC_INTERIOR;
+            const double jv = cl == FC_JUMP_P ? g.dT : (cl == FC_JUMP_M ? -g.dT : 0.0);
+            const size_t e = (size_t)f * n + c;
+            g.bnd[e] = cl == FC_WALL ? t : jv;
+            g.bnd[nb + e] = jv;
+            g.bnd[2 * nb + e] = 0.0;
+            g.bnd[3 * nb + e] = 0.0;
+        }
+    }
+    for (int wi = blockIdx.x * blockDim.x + threadIdx.x; wi < g.nwalls; wi += v.B * blockDim.x) {
+        const double t = x[g.wall_cell[wi]] - mean;
+        g.Tw[wi] = t;
+        g.ax[n + wi] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1812,9 +1790,10 @@ hipError_t launch_fourier_pending(const GeomDev* geoms_dev, int n_geoms, int* pe
     return hipGetLastError();
 }
 
-hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, hipStream_t st) {
+hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, int max_cells, hipStream_t st) {
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_fourier_finish, dim3(n_geoms), dim3(1024), 0, st, geoms_dev);
+    hipLaunchKernelGGL(k_fourier_fill, dim3(fourier_blocks(max_cells), n_geoms), dim3(FB_THREADS), 0, st, geoms_dev);
     return hipGetLastError();
 }
 

@@ -121,7 +121,7 @@ hipError_t launch_fourier_init(const GeomDev* geoms_dev, int n_geoms, int max_ce
 hipError_t launch_fourier_iter(const GeomDev* geoms_dev, int n_geoms, int max_cells, int parity, double tol,
                                int max_iter, hipStream_t st);
 hipError_t launch_fourier_pending(const GeomDev* geoms_dev, int n_geoms, int* pending_dev, hipStream_t st);
-hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, hipStream_t st);
+hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, int max_cells, hipStream_t st);
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
                              const Item* items_dev, int n_items, int waves, PassParams pp,
                              size_t lds_bytes, hipStream_t st);
