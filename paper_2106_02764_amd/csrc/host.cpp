@@ -77,7 +77,7 @@ struct obte_mesh {
     // device tables (library-owned)
     int device = -1;
     uint16_t* d_fc = nullptr;
-    int *d_wall_cell = nullptr, *d_wall_face = nullptr;
+    int *d_wall_cell = nullptr, *d_wall_face = nullptr, *d_wall_idx = nullptr;
     double *d_mfp = nullptr, *d_dirs = nullptr, *d_D = nullptr, *d_S = nullptr, *d_wout = nullptr,
            *d_kax = nullptr;
     GeomDev* d_geom = nullptr;      // single-geometry view (apply, outputs)
@@ -392,7 +392,7 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
     g.dT = m->dT;
     g.n_mfp = m->n_mfp; g.n_dir = m->n_dir; g.n_sys = m->n_sys;
     g.n_perp = m->ncells / (m->grad_axis == 0 ? m->nx : (m->grad_axis == 1 ? m->ny : m->nz));
-    g.fc = m->d_fc; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face;
+    g.fc = m->d_fc; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face; g.wall_idx = m->d_wall_idx;
     g.mfp = m->d_mfp; g.dirs = m->d_dirs; g.Dw = m->d_D; g.S = m->d_S; g.wout = m->d_wout;
     g.gauge = m->n_modes > 0 ? 1 : 0;
     g.kappa_axis = m->d_kax;
@@ -452,12 +452,12 @@ void free_dev(obte_mesh* m) {
     m->g_fourier.reset();
     m->g_pass.reset();
     m->g_adj.reset();
-    void* ptrs[] = {m->d_fc, m->d_wall_cell, m->d_wall_face, m->d_mfp, m->d_dirs,
+    void* ptrs[] = {m->d_fc, m->d_wall_cell, m->d_wall_face, m->d_wall_idx, m->d_mfp, m->d_dirs,
                     m->d_D, m->d_S, m->d_wout, m->d_kax, m->d_geom, m->d_mode_sys, m->d_mode_w,
                     m->d_mode_Sg, m->d_kmode};
     for (void* p : ptrs)
         if (p) soft(hipFree(p), "hipFree(table)");
-    m->d_fc = nullptr; m->d_wall_cell = m->d_wall_face = nullptr;
+    m->d_fc = nullptr; m->d_wall_cell = m->d_wall_face = m->d_wall_idx = nullptr;
     m->d_mfp = m->d_dirs = m->d_D = m->d_S = m->d_wout = m->d_kax = nullptr;
     m->d_geom = nullptr;
     m->d_mode_sys = nullptr;
@@ -1224,6 +1224,7 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     if ((s = upload(&m->d_fc, m->fc)) != OBTE_OK) return s;
     if ((s = upload(&m->d_wall_cell, m->wall_cell)) != OBTE_OK) return s;
     if ((s = upload(&m->d_wall_face, m->wall_face)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_wall_idx, m->wall_idx)) != OBTE_OK) return s;
     if ((s = upload(&m->d_mfp, m->mfp)) != OBTE_OK) return s;
     if ((s = upload(&m->d_dirs, m->dirs3)) != OBTE_OK) return s;
     if ((s = upload(&m->d_D, m->Dw)) != OBTE_OK) return s;

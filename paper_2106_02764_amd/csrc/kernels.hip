@@ -990,49 +990,136 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
 // and the next pass's inputs sigma T_L and T_w.  Forward: T_L = sum D x and
 // T_w = sum ReLu(S.n)/sum ReLu(S.n) x at the wall cell.  Adjoint: Psi = sigma
 // sum lambda and Phi_f = sum of c_a lambda over the directions entering
-// through f (the transpose of the wall coupling).
+// through f (the transpose of the wall coupling).  A block owns a strip of 64
+// cells and its RQ waves split the systems in fixed chunks; a wall face reads
+// only its own cell's values, so the walls of the strip's cells are summed
+// from the same loads.  Every sum is combined over the chunks in order.
 // ---------------------------------------------------------------------------
 constexpr int RQ = 16;      // waves per reduction block: system chunks of one 64-cell strip
 
 template <typename T>
 __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restrict__ geoms, PassParams pp) {
     __shared__ double part[RQ][64];
+    __shared__ double cfl[RQ][6][64];      // per wave: wall weights of 64 systems
     const GeomDev& g = geoms[blockIdx.y];
     if (g.ctrl[CTRL_DONE] && pp.mode == 0) return;
     const int pass = g.ctrl[CTRL_PASS];
     const int out = (pass + 1) & 1;
     const int adj = pp.adjoint;
-    const int nc = g.ncells;
+    const int nc = g.ncells, nf = g.nf, ns = g.n_sys, nd = g.n_dir;
     const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
     const gptr_t<double> D = gview(g.Dw);
-    // cells: 64 per block, the system sum split in RQ fixed chunks combined in order
     const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
     const int cell = blockIdx.x * 64 + cl;
-    const int per = (g.n_sys + RQ - 1) / RQ;
-    const int i0 = q * per, i1 = min(g.n_sys, i0 + per);
-    double acc = 0.0;
+    const int per = (ns + RQ - 1) / RQ;
+    const int i0 = q * per, i1 = min(ns, i0 + per);
+    // wall faces of this lane's cell (bit f), and of the strip: the same in
+    // every wave of the block
+    int wm = 0;
     if (cell < nc) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int i = i0;
-        if (adj) {
-            for (; i + 3 < i1; i += 4) {
-                a0 += (double)X[(size_t)i * nc + cell];
-                a1 += (double)X[(size_t)(i + 1) * nc + cell];
-                a2 += (double)X[(size_t)(i + 2) * nc + cell];
-                a3 += (double)X[(size_t)(i + 3) * nc + cell];
-            }
-            for (; i < i1; ++i) a0 += (double)X[(size_t)i * nc + cell];
-        } else {
-            for (; i + 3 < i1; i += 4) {
-                a0 += D[i] * (double)X[(size_t)i * nc + cell];
-                a1 += D[i + 1] * (double)X[(size_t)(i + 1) * nc + cell];
-                a2 += D[i + 2] * (double)X[(size_t)(i + 2) * nc + cell];
-                a3 += D[i + 3] * (double)X[(size_t)(i + 3) * nc + cell];
-            }
-            for (; i < i1; ++i) a0 += D[i] * (double)X[(size_t)i * nc + cell];
-        }
-        acc = (a0 + a1) + (a2 + a3);
+        const uint16_t w = g.fc[cell];
+        if (fc_solid(w))
+            for (int f = 0; f < nf; ++f) wm |= (fc_class(w, f) == FC_WALL ? 1 : 0) << f;
     }
+    int wany = wm;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) wany |= shfl_xor(wany, m);
+    double acc = 0.0;
+    double aw[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (!wany) {
+        if (cell < nc) {
+            int i = i0;
+            if (adj) {
+                for (; i + 3 < i1; i += 4) {
+                    a0 += (double)X[(size_t)i * nc + cell];
+                    a1 += (double)X[(size_t)(i + 1) * nc + cell];
+                    a2 += (double)X[(size_t)(i + 2) * nc + cell];
+                    a3 += (double)X[(size_t)(i + 3) * nc + cell];
+                }
+                for (; i < i1; ++i) a0 += (double)X[(size_t)i * nc + cell];
+            } else {
+                for (; i + 3 < i1; i += 4) {
+                    a0 += D[i] * (double)X[(size_t)i * nc + cell];
+                    a1 += D[i + 1] * (double)X[(size_t)(i + 1) * nc + cell];
+                    a2 += D[i + 2] * (double)X[(size_t)(i + 2) * nc + cell];
+                    a3 += D[i + 3] * (double)X[(size_t)(i + 3) * nc + cell];
+                }
+                for (; i < i1; ++i) a0 += D[i] * (double)X[(size_t)i * nc + cell];
+            }
+        }
+    } else {
+        // the same cell sums in the same order, and the wall faces' sums with
+        // the weights of 64 systems at a time staged in the wave's LDS rows
+        const bool in = cell < nc;
+        const int cs = in ? cell : nc - 1;          // in-range loads, dropped below
+        for (int ib = i0; ib < i1; ib += 64) {
+            // lane l: the weights of system ib + l at the strip's wall faces
+            // (forward: ReLu(S.n) / sum; adjoint: c_a of the directions
+            // entering through the face)
+            const bool lv = ib + cl < i1;
+            const int il = lv ? ib + cl : ns - 1;
+            double cf[6];
+            if (!adj) {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) cf[f] = g.wout[(size_t)min(f, nf - 1) * ns + il];
+            } else {
+                const int m = il / nd, l = il - m * nd;
+                const double mf = g.mfp[m];
+                const double sd3[3] = {g.dirs[l * 3], g.dirs[l * 3 + 1], g.dirs[l * 3 + 2]};
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    const int ax = f >> 1;
+                    const double sd = sd3[ax];
+                    const double nsgn = (f & 1) ? 1.0 : -1.0;
+                    cf[f] = sd * nsgn < 0.0 ? mf * fabs(sd) / g.h[ax] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+                if (f < nf && ((wany >> f) & 1)) cfl[q][f][cl] = lv ? cf[f] : 0.0;
+            // the wave reads back its own rows (LDS ops of a wave complete in order)
+            __builtin_amdgcn_wave_barrier();
+            const int nb = min(64, i1 - ib);
+            int u0 = 0;
+            for (; u0 + 3 < nb; u0 += 4) {
+                const int i = ib + u0;
+                double dv[4], xv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) dv[u] = D[i + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) xv[u] = (double)X[(size_t)(i + u) * nc + cs];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    xv[u] = in ? xv[u] : 0.0;
+                    dv[u] = adj ? 1.0 : dv[u];          // 1 * x is x exactly
+                }
+                a0 += dv[0] * xv[0];
+                a1 += dv[1] * xv[1];
+                a2 += dv[2] * xv[2];
+                a3 += dv[3] * xv[3];
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    if (f >= nf || !((wany >> f) & 1)) continue;
+                    const double* cp = &cfl[q][f][u0];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) aw[f] += cp[u] * xv[u];   // zero weight: + 0
+                }
+            }
+            for (; u0 < nb; ++u0) {
+                const int i = ib + u0;
+                const double xr = (double)X[(size_t)i * nc + cs];
+                const double x = in ? xr : 0.0;
+                a0 += adj ? x : D[i] * x;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    if (f >= nf || !((wany >> f) & 1)) continue;
+                    aw[f] += cfl[q][f][u0] * x;
+                }
+            }
+        }
+    }
+    if (cell < nc) acc = (a0 + a1) + (a2 + a3);
     part[q][cl] = acc;
     __syncthreads();
     if (q == 0 && cell < nc) {
@@ -1050,40 +1137,26 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
             else g.sT[(size_t)out * nc + cell] = sol ? g.sigma[cell] * tot : 0.0;
         }
     }
-    // walls: one wavefront per wall face; each lane sums a fixed strided
-    // subset of the systems, then a butterfly, so the order is fixed
-    const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    double* bnd_out = g.bnd + ((size_t)(adj ? 2 : 0) + out) * g.nf * nc;
-    for (int wi = wave; wi < g.nwalls; wi += nwaves) {
-        const int f = g.wall_face[wi];
-        const int ax = f >> 1;
-        const double nsgn = (f & 1) ? 1.0 : -1.0;
-        const int wc = g.wall_cell[wi];
-        double a = 0.0;
-        if (adj) {
-            for (int sys = lane; sys < g.n_sys; sys += 64) {
-                const int m = sys / g.n_dir, l = sys - m * g.n_dir;
-                const double sd = g.dirs[l * 3 + ax];
-                if (sd * nsgn < 0.0) a += g.mfp[m] * fabs(sd) / g.h[ax] * (double)X[(size_t)sys * nc + wc];
-            }
-        } else {
-            const gptr_t<double> wout = gview(g.wout + (size_t)f * g.n_sys);
-            for (int sys = lane; sys < g.n_sys; sys += 64) {
-                const double wv = wout[sys];
-                if (wv != 0.0) a += wv * (double)X[(size_t)sys * nc + wc];
-            }
-        }
-        a = wave_sum(a);
-        if (lane == 0) {
+    if (!wany) return;                     // block-uniform
+    double* bnd_out = g.bnd + ((size_t)(adj ? 2 : 0) + out) * nf * nc;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (f >= nf || !((wany >> f) & 1)) continue;
+        __syncthreads();                   // the previous sum's reads are done
+        part[q][cl] = aw[f];
+        __syncthreads();
+        if (q == 0 && ((wm >> f) & 1)) {
+            double a = part[0][cl];
+#pragma unroll
+            for (int j = 1; j < RQ; ++j) a += part[j][cl];
+            const int wi = g.wall_idx[cell * nf + f];
             if (g.aa_m > 0) {
                 g.ag[nc + wi] = a;
             } else {
                 g.ax[nc + wi] = a;
                 if (adj) g.lam_phi[(size_t)out * g.nwalls + wi] = a;
                 else g.Tw[(size_t)out * g.nwalls + wi] = a;
-                bnd_out[(size_t)f * nc + wc] = a;
+                bnd_out[(size_t)f * nc + cell] = a;
             }
         }
     }

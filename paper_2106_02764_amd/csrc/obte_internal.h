@@ -31,6 +31,7 @@ struct GeomDev {
     const uint16_t* fc;          // ncells
     const int* wall_cell;        // nwalls
     const int* wall_face;        // nwalls: face index 2a+side of the owning cell
+    const int* wall_idx;         // ncells * nf: wall index of (cell, face), -1 if not a wall
     const double* mfp;           // n_mfp
     const double* dirs;          // n_dir * 3 (z = 0 in 2D)
     const double* Dw;            // n_sys: T_L weights D_ml
