@@ -1031,6 +1031,19 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
         if (cell < nc) {
             int i = i0;
             if (adj) {
+                for (; i + 7 < i1; i += 8) {
+                    double xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nc + cell];
+                    a0 += xv[0];
+                    a1 += xv[1];
+                    a2 += xv[2];
+                    a3 += xv[3];
+                    a0 += xv[4];
+                    a1 += xv[5];
+                    a2 += xv[6];
+                    a3 += xv[7];
+                }
                 for (; i + 3 < i1; i += 4) {
                     a0 += (double)X[(size_t)i * nc + cell];
                     a1 += (double)X[(size_t)(i + 1) * nc + cell];
@@ -1039,6 +1052,19 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
                 }
                 for (; i < i1; ++i) a0 += (double)X[(size_t)i * nc + cell];
             } else {
+                for (; i + 7 < i1; i += 8) {
+                    double xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nc + cell];
+                    a0 += D[i] * xv[0];
+                    a1 += D[i + 1] * xv[1];
+                    a2 += D[i + 2] * xv[2];
+                    a3 += D[i + 3] * xv[3];
+                    a0 += D[i + 4] * xv[4];
+                    a1 += D[i + 5] * xv[5];
+                    a2 += D[i + 6] * xv[6];
+                    a3 += D[i + 7] * xv[7];
+                }
                 for (; i + 3 < i1; i += 4) {
                     a0 += D[i] * (double)X[(size_t)i * nc + cell];
                     a1 += D[i + 1] * (double)X[(size_t)(i + 1) * nc + cell];
@@ -1082,6 +1108,34 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
             __builtin_amdgcn_wave_barrier();
             const int nb = min(64, i1 - ib);
             int u0 = 0;
+            for (; u0 + 7 < nb; u0 += 8) {
+                const int i = ib + u0;
+                double dv[8], xv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) dv[u] = D[i + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nc + cs];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    xv[u] = in ? xv[u] : 0.0;
+                    dv[u] = adj ? 1.0 : dv[u];          // 1 * x is x exactly
+                }
+                a0 += dv[0] * xv[0];
+                a1 += dv[1] * xv[1];
+                a2 += dv[2] * xv[2];
+                a3 += dv[3] * xv[3];
+                a0 += dv[4] * xv[4];
+                a1 += dv[5] * xv[5];
+                a2 += dv[6] * xv[6];
+                a3 += dv[7] * xv[7];
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    if (f >= nf || !((wany >> f) & 1)) continue;
+                    const double* cp = &cfl[q][f][u0];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) aw[f] += cp[u] * xv[u];   // zero weight: + 0
+                }
+            }
             for (; u0 + 3 < nb; u0 += 4) {
                 const int i = ib + u0;
                 double dv[4], xv[4];
