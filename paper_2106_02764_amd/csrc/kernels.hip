@@ -1536,7 +1536,7 @@ constexpr int FB_MAX = 256, FB_THREADS = 256;
 
 // This geometry's CG storage (in the fx region) and block b's cell range.
 struct FView {
-    double *x, *r, *p0, *p1, *ap, *pap, *rr0, *rr1, *sc;   // sc: [0] |b|, [1] done, [2] mean of x, [4] iterations
+    double *x, *r, *p0, *p1, *ap, *pap, *rr0, *rr1, *sc;   // sc: [0] |b|, [1] done, [4] iterations
     int n, B, c0, c1;
 };
 __device__ __forceinline__ FView fourier_view(const GeomDev& g, int b) {
@@ -1707,28 +1707,28 @@ __global__ void __launch_bounds__(256) k_fourier_pending(const GeomDev* __restri
     if (threadIdx.x == 0) *pending = (int)c;
 }
 
-// End of the Fourier solve, in two kernels.  The first (one block per
-// geometry) takes the solid-cell mean of x, which the gauge removes, and
-// kappa_F from the plane flux through the periodic plane of the gradient axis
-// (differences of x, so the mean drops out); it stores the mean in sc[2] and
-// resets the pass control words.  The second, over the geometry's cell blocks,
-// writes the mean-free T_F as T_L, sigma T_F, the wall temperatures, the
-// first iterate of the outer fixed point and the inflow tables: periodic
-// jumps +-dT (fixed), walls T_w (updated every pass), interior 0; forward
-// buffers 0 and 1, adjoint buffers 2 and 3 (no jump source; walls updated per
-// pass).  A wall's first temperature is its cell's, so buffer 0's wall entries
-// take the cell value directly.
-__global__ void __launch_bounds__(1024) k_fourier_finish(const GeomDev* __restrict__ geoms) {
+// End of the Fourier solve, in two kernels over the geometry's cell blocks.
+// The first stores per-block partials of the solid-cell sum of x and count
+// (the mean, which the gauge removes) and of the plane flux through the
+// periodic plane of the gradient axis (kappa_F; differences of x, so the mean
+// drops out) in the CG's direction buffers, free once it has ended.  The
+// second sums them in a fixed order in every block and writes the mean-free
+// T_F as T_L, sigma T_F, the wall temperatures, the first iterate of the
+// outer fixed point and the inflow tables: periodic jumps +-dT (fixed), walls
+// T_w (updated every pass), interior 0; forward buffers 0 and 1, adjoint
+// buffers 2 and 3 (no jump source; walls updated per pass).  A wall's first
+// temperature is its cell's, so buffer 0's wall entries take the cell value.
+// Block 0 also stores kappa_F and the CG statistics and resets the pass
+// control words.
+__global__ void __launch_bounds__(FB_THREADS) k_fourier_part(const GeomDev* __restrict__ geoms) {
     __shared__ double red[32];
-    const GeomDev& g = geoms[blockIdx.x];
-    const FView v = fourier_view(g, 0);
-    const int it = (int)v.sc[4];
-    const double rn = sqrt(sum_partials((it & 1) ? v.rr1 : v.rr0, v.B, red));
-    const double bn = v.sc[0];
-    const int n = g.ncells, ga = g.grad_axis;
+    const GeomDev& g = geoms[blockIdx.y];
+    const FView v = fourier_view(g, blockIdx.x);
+    if ((int)blockIdx.x >= v.B) return;
+    const int ga = g.grad_axis;
     const double* x = g.fx;
     double sx = 0.0, ns = 0.0, fl = 0.0;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
         const uint16_t w = g.fc[c];
         if (!fc_solid(w)) continue;
         sx += x[c];
@@ -1742,22 +1742,35 @@ __global__ void __launch_bounds__(1024) k_fourier_finish(const GeomDev* __restri
     sx = block_sum(sx, red);
     ns = block_sum(ns, red);
     fl = block_sum(fl, red);
-    if (g.aa_m > 0 && threadIdx.x < 8) g.actl[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
-        v.sc[2] = sx / ns;
-        g.fscal[0] = g.L[ga] / (g.dT * (double)g.n_perp) * fl;
-        g.fscal[1] = (double)it;
-        g.fscal[2] = bn > 0.0 ? rn / bn : 0.0;
-        for (int i = 0; i < CTRL_N; ++i) g.ctrl[i] = 0;
+        v.p0[blockIdx.x] = sx;
+        v.p1[blockIdx.x] = ns;
+        v.ap[blockIdx.x] = fl;
     }
 }
 
 __global__ void __launch_bounds__(FB_THREADS) k_fourier_fill(const GeomDev* __restrict__ geoms) {
+    __shared__ double red[32];
     const GeomDev& g = geoms[blockIdx.y];
     const FView v = fourier_view(g, blockIdx.x);
     if ((int)blockIdx.x >= v.B) return;
     const int n = g.ncells, nf = g.nf;
-    const double mean = v.sc[2];
+    const double sx = sum_partials(v.p0, v.B, red);
+    const double mean = sx / sum_partials(v.p1, v.B, red);
+    if (blockIdx.x == 0) {
+        const int it = (int)v.sc[4];
+        const double rn = sqrt(sum_partials((it & 1) ? v.rr1 : v.rr0, v.B, red));
+        const double fl = sum_partials(v.ap, v.B, red);
+        const double bn = v.sc[0];
+        const int ga = g.grad_axis;
+        if (g.aa_m > 0 && threadIdx.x < 8) g.actl[threadIdx.x] = 0;
+        if (threadIdx.x == 0) {
+            g.fscal[0] = g.L[ga] / (g.dT * (double)g.n_perp) * fl;
+            g.fscal[1] = (double)it;
+            g.fscal[2] = bn > 0.0 ? rn / bn : 0.0;
+            for (int i = 0; i < CTRL_N; ++i) g.ctrl[i] = 0;
+        }
+    }
     const double* x = g.fx;
     const size_t nb = (size_t)nf * n;
     for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
@@ -1919,8 +1932,9 @@ hipError_t launch_fourier_pending(const GeomDev* geoms_dev, int n_geoms, int* pe
 
 hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, int max_cells, hipStream_t st) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_fourier_finish, dim3(n_geoms), dim3(1024), 0, st, geoms_dev);
-    hipLaunchKernelGGL(k_fourier_fill, dim3(fourier_blocks(max_cells), n_geoms), dim3(FB_THREADS), 0, st, geoms_dev);
+    const dim3 grid(fourier_blocks(max_cells), n_geoms);
+    hipLaunchKernelGGL(k_fourier_part, grid, dim3(FB_THREADS), 0, st, geoms_dev);
+    hipLaunchKernelGGL(k_fourier_fill, grid, dim3(FB_THREADS), 0, st, geoms_dev);
     return hipGetLastError();
 }
 
