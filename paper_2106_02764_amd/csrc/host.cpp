@@ -97,6 +97,9 @@ struct obte_mesh {
     int* d_mode_sys = nullptr;
     double *d_mode_w = nullptr, *d_mode_Sg = nullptr, *d_kmode = nullptr;
     bool modes_solved = false;
+    // pinned host staging for the per-solve read-backs (grown on demand)
+    char* h_stage = nullptr;
+    size_t h_stage_bytes = 0;
     // graphs of the last single-mesh solve / adjoint, reused by the next call
     // with the same workspace, options and tables
     GraphSlot g_fourier, g_pass, g_adj;
@@ -550,6 +553,38 @@ struct Run {
     int waves = 4, nzmax = 1, precision = 0, accel = 0;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
     int max_cells = 0, max_walls = 0;
+    // pinned host slots for the loop read-backs (two per loop, see
+    // speculative loops below); null: plain synchronous read-backs
+    int* h_pin = nullptr;
+};
+
+// Pinned staging of a mesh: bytes [0, STAGE_LOOP) hold the loop read-back
+// slots, the rest the per-solve result read-backs.  Grown only while no copy
+// into it is in flight (at a solve's start, or after a stream synchronize).
+constexpr size_t STAGE_LOOP = 256;
+static_assert((4 + 2 * CTRL_N) * sizeof(int) <= STAGE_LOOP, "loop read-back slots exceed the staging head");
+obte_status ensure_stage(obte_mesh* m, size_t need) {
+    if (m->h_stage_bytes >= need) return OBTE_OK;
+    if (m->h_stage) soft(hipHostFree(m->h_stage), "hipHostFree(stage)");
+    m->h_stage = nullptr;
+    m->h_stage_bytes = 0;
+    HIPCHK(hipHostMalloc((void**)&m->h_stage, need, hipHostMallocDefault));
+    m->h_stage_bytes = need;
+    return OBTE_OK;
+}
+
+// Two events for a speculative loop, destroyed with it.
+struct EventPair {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t create() {
+        hipError_t e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+        return e;
+    }
+    ~EventPair() {
+        for (hipEvent_t x : ev)
+            if (x) soft(hipEventDestroy(x), "hipEventDestroy");
+    }
 };
 
 size_t run_state_bytes(size_t n_views, size_t n_items) {
@@ -704,15 +739,45 @@ obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st, 
         if (s != OBTE_OK) return s;
     }
     obte_status out = OBTE_OK;
-    int pending = 1;
-    for (int it = 0; pending > 0 && it <= o->max_fourier + KF; it += KF) {
-        const hipError_t e = exec ? hipGraphLaunch(exec, st) : enqueue();
-        if (e != hipSuccess) { out = fail(OBTE_ERR_HIP, "Fourier iterations: %s", hipGetErrorString(e)); break; }
-        hipError_t e2 = hipMemcpyAsync(&pending, R.d_pending, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
-        if (e2 != hipSuccess) { out = fail(OBTE_ERR_HIP, "Fourier readback: %s", hipGetErrorString(e2)); break; }
+    EventPair evp;
+    if (exec && R.h_pin) {
+        // speculative: the next graph is queued before the previous one's
+        // count is read, so the GPU does not idle on the host round trip; a
+        // graph queued after convergence runs as early exits
+        hipError_t e = evp.create();
+        int* slot2[2] = {R.h_pin, R.h_pin + 1};
+        auto launch = [&](int b) -> hipError_t {
+            hipError_t e2 = hipGraphLaunch(exec, st);
+            if (e2 == hipSuccess) e2 = hipMemcpyAsync(slot2[b], R.d_pending, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e2 == hipSuccess) e2 = hipEventRecord(evp.ev[b], st);
+            return e2;
+        };
+        int it = KF, cur = 0;
+        if (e == hipSuccess) e = launch(cur);
+        while (e == hipSuccess) {
+            const bool more = it <= o->max_fourier + KF;
+            if (more) {
+                e = launch(cur ^ 1);
+                it += KF;
+                if (e != hipSuccess) break;
+            }
+            e = hipEventSynchronize(evp.ev[cur]);
+            if (e != hipSuccess || *slot2[cur] == 0 || !more) break;
+            cur ^= 1;
+        }
+        if (e != hipSuccess) out = fail(OBTE_ERR_HIP, "Fourier iterations: %s", hipGetErrorString(e));
+    } else {
+        int pending = 1;
+        for (int it = 0; pending > 0 && it <= o->max_fourier + KF; it += KF) {
+            const hipError_t e = exec ? hipGraphLaunch(exec, st) : enqueue();
+            if (e != hipSuccess) { out = fail(OBTE_ERR_HIP, "Fourier iterations: %s", hipGetErrorString(e)); break; }
+            hipError_t e2 = hipMemcpyAsync(&pending, R.d_pending, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+            if (e2 != hipSuccess) { out = fail(OBTE_ERR_HIP, "Fourier readback: %s", hipGetErrorString(e2)); break; }
+        }
     }
-    if (graph) {      // not kept by a slot
+    if (graph) {      // not kept by a slot: a queued graph ends first
+        soft(hipStreamSynchronize(st), "hipStreamSynchronize");
         soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
         soft(hipGraphDestroy(graph), "hipGraphDestroy");
     }
@@ -742,6 +807,45 @@ obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st
     }
     obte_status out = OBTE_OK;
     int launched = 0;
+    if (exec && n == 1 && !(tm && tm->on) && R.h_pin) {
+        // speculative, as the Fourier loop: one graph of K passes queued
+        // ahead; passes after convergence exit at once (the done flag)
+        EventPair evp;
+        hipError_t e = evp.create();
+        int* slot2[2] = {R.h_pin + 4, R.h_pin + 4 + CTRL_N};
+        auto launch = [&](int b) -> hipError_t {
+            hipError_t e2 = hipGraphLaunch(exec, st);
+            if (e2 == hipSuccess)
+                e2 = hipMemcpyAsync(slot2[b], R.views[0].ctrl, CTRL_N * sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e2 == hipSuccess) e2 = hipEventRecord(evp.ev[b], st);
+            return e2;
+        };
+        int cur = 0;
+        if (e == hipSuccess) e = launch(cur);
+        launched = K;
+        bool done = false;
+        while (e == hipSuccess) {
+            const bool more = launched <= max_outer + K;
+            if (more) {
+                e = launch(cur ^ 1);
+                launched += K;
+                if (e != hipSuccess) break;
+            }
+            e = hipEventSynchronize(evp.ev[cur]);
+            if (e != hipSuccess) break;
+            done = slot2[cur][CTRL_DONE] != 0;
+            if (done || !more) break;
+            cur ^= 1;
+        }
+        if (e != hipSuccess) out = fail(OBTE_ERR_HIP, "graph launch / readback: %s", hipGetErrorString(e));
+        else if (!done) out = fail(OBTE_ERR_STATE, "outer loop did not terminate");
+        if (graph) {      // not kept by a slot: the queued graph ends first
+            soft(hipStreamSynchronize(st), "hipStreamSynchronize");
+            soft(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
+            soft(hipGraphDestroy(graph), "hipGraphDestroy");
+        }
+        return out;
+    }
     while (true) {
         if (exec) {
             hipError_t e = hipGraphLaunch(exec, st);
@@ -808,6 +912,8 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         if (ws_bytes < need)
             return fail(OBTE_ERR_NOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
         if ((s = upload_run(R, (char*)workspace)) != OBTE_OK) return s;
+        if ((s = ensure_stage(meshes[0], STAGE_LOOP)) != OBTE_OK) return s;
+        R.h_pin = (int*)meshes[0]->h_stage;
     }
     for (int i = 0; i < n; ++i) {
         obte_mesh* m = meshes[i];
@@ -880,12 +986,25 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
             wrh(passes + 1, 0.0);
         std::vector<long long> its(m->n_sys), sws(m->n_sys);
         if (passes > 0) {
-            HIPCHK(hipMemcpy(hist.data(), v.hist, passes * sizeof(double), hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(histf.data(), v.hist_face, passes * sizeof(double), hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(wrh.data(), v.wres_hist, passes * sizeof(double), hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(ks.data(), v.ksys, m->n_sys * sizeof(double), hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(its.data(), v.iters, m->n_sys * sizeof(long long), hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(sws.data(), v.sweeps, m->n_sys * sizeof(long long), hipMemcpyDeviceToHost));
+            // one wait for the six read-backs: asynchronous copies into pinned memory
+            const size_t hb = (size_t)passes * sizeof(double), sb = (size_t)m->n_sys * 8;
+            obte_status se = ensure_stage(m, STAGE_LOOP + 3 * hb + 3 * sb);
+            if (se != OBTE_OK) return se;
+            char* hs = m->h_stage + STAGE_LOOP;
+            const void* src[6] = {v.hist, v.hist_face, v.wres_hist, v.ksys, v.iters, v.sweeps};
+            void* dst[6] = {hist.data(), histf.data(), wrh.data(), ks.data(), its.data(), sws.data()};
+            const size_t len[6] = {hb, hb, hb, sb, sb, sb};
+            size_t off = 0;
+            for (int k = 0; k < 6; ++k) {
+                HIPCHK(hipMemcpyAsync(hs + off, src[k], len[k], hipMemcpyDeviceToHost, st));
+                off += len[k];
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            off = 0;
+            for (int k = 0; k < 6; ++k) {
+                std::memcpy(dst[k], hs + off, len[k]);
+                off += len[k];
+            }
         }
         m->kappa_fourier = fs[0];
         m->kappa = passes > 0 ? hist[passes - 1] : fs[0];
@@ -1332,6 +1451,8 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     if (ws_bytes < R.state_off + R.state_bytes)
         return fail(OBTE_ERR_NOMEM, "workspace too small for the adjoint (accel deeper than the forward solve's?)");
     if ((s = upload_run(R, (char*)workspace)) != OBTE_OK) return s;
+    if ((s = ensure_stage(m, STAGE_LOOP)) != OBTE_OK) return s;
+    R.h_pin = (int*)m->h_stage;
     char* ws = (char*)workspace;
     // lambda^(0) = 0: Psi = Phi = 0, no warm start, fresh counters
     HIPCHK(hipMemsetAsync(ws + L.lam_psi, 0, 2 * (size_t)m->ncells * 8, st));
@@ -1479,6 +1600,7 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
 void obte_mesh_destroy(obte_mesh* m) {
     if (!m) return;
     free_dev(m);
+    if (m->h_stage) soft(hipHostFree(m->h_stage), "hipHostFree(stage)");
     delete m;
 }
 
