@@ -209,7 +209,9 @@ obte_status obte_material_set(obte_mesh* mesh, const obte_material_desc* mat);
 /* Bytes of device workspace obte_solve / obte_adjoint need for `opts`.  The
  * workspace holds every per-solve array, including the launch state (the
  * geometry views and the work-item list): a solve allocates no device
- * memory. */
+ * memory.  Each mesh keeps a small pinned host buffer for the flags and
+ * results read back during its solves (taken at its first solve, grown when a
+ * solve needs more, freed by obte_mesh_destroy). */
 obte_status obte_workspace_size(const obte_mesh* mesh, const obte_solve_opts* opts,
                                 size_t* bytes);
 
