@@ -1334,14 +1334,19 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_partial(const GeomDev* __rest
     for (int j = 0; j < AA_MAX; ++j) { dA[j] = 0.0; db[j] = 0.0; }
     double ff = 0.0, xx = 0.0, dxx = 0.0;
     for (int i = v.c0 + threadIdx.x; i < v.c1; i += blockDim.x) {
-        const double x = g.ax[i];
-        const double f = g.ag[i] - x;
+        // every load first (the stored columns from in-range slots, unused
+        // ones dropped below), so they are in flight together
+        const double x = g.ax[i], gi = g.ag[i], fp = g.afp[i], xp = g.axp[i];
+        double hF[AA_MAX];
+#pragma unroll
+        for (int j = 0; j < AA_MAX; ++j) hF[j] = g.adF[(size_t)min(j, M - 1) * n + i];
+        const double f = gi - x;
         xx += x * x;
         ff += f * f;
         double df = 0.0;
         if (have) {
-            df = f - g.afp[i];
-            const double dx = x - g.axp[i];
+            df = f - fp;
+            const double dx = x - xp;
             dxx += dx * dx;
             g.adX[(size_t)slot * n + i] = dx;
             g.adF[(size_t)slot * n + i] = df;
@@ -1351,7 +1356,7 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_partial(const GeomDev* __rest
 #pragma unroll
         for (int j = 0; j < AA_MAX; ++j) {
             if (j < cnt1) {
-                const double Fj = (have && j == slot) ? df : g.adF[(size_t)j * n + i];
+                const double Fj = (have && j == slot) ? df : hF[j];
                 db[j] += Fj * f;
                 if (have) dA[j] += df * Fj;
             }
@@ -1494,9 +1499,17 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_apply(const GeomDev* __restri
     __syncthreads();
     double* bnd_out = g.bnd + ((size_t)(adj ? 2 : 0) + out) * g.nf * nc;
     for (int i = v.c0 + threadIdx.x; i < v.c1; i += blockDim.x) {
+        double hX[AA_MAX], hF[AA_MAX];       // loaded together, unused slots dropped
+#pragma unroll
+        for (int j = 0; j < AA_MAX; ++j) {
+            const size_t o = (size_t)min(j, M - 1) * n + i;
+            hX[j] = g.adX[o];
+            hF[j] = g.adF[o];
+        }
         double xn = g.axp[i] + g.afp[i];
-        for (int j = 0; j < cnt1; ++j)
-            xn -= gam[j] * (g.adX[(size_t)j * n + i] + g.adF[(size_t)j * n + i]);
+#pragma unroll
+        for (int j = 0; j < AA_MAX; ++j)
+            if (j < cnt1) xn -= gam[j] * (hX[j] + hF[j]);
         if (i < nc) {
             const bool sol = fc_solid(g.fc[i]);
             xn = sol ? xn : 0.0;
