@@ -49,6 +49,20 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// N butterfly sums at once, step by step, so the cross-lane reads of the N
+// values are in flight together; each value is summed exactly as wave_sum does.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        double t[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) t[q] = shfl_xor(v[q], m);
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] += t[q];
+    }
+}
+
 // Deterministic block sum (blockDim.x multiple of 64, <= 1024).
 __device__ double block_sum(double v, double* red) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1363,15 +1377,19 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_partial(const GeomDev* __rest
         }
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double sums[AA_NP];
 #pragma unroll
     for (int j = 0; j < AA_MAX; ++j) {
-        const double a = wave_sum(dA[j]), b = wave_sum(db[j]);
-        if (lane == 0) { red[j][wid] = a; red[AA_MAX + j][wid] = b; }
+        sums[j] = dA[j];
+        sums[AA_MAX + j] = db[j];
     }
-    {
-        const double t = wave_sum(ff), u = wave_sum(xx), w2 = wave_sum(dxx);
-        if (lane == 0) { red[2 * AA_MAX][wid] = t; red[2 * AA_MAX + 1][wid] = u; red[2 * AA_MAX + 2][wid] = w2; }
-    }
+    sums[2 * AA_MAX] = ff;
+    sums[2 * AA_MAX + 1] = xx;
+    sums[2 * AA_MAX + 2] = dxx;
+    wave_sum_n(sums);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < AA_NP; ++q) red[q][wid] = sums[q];
     __syncthreads();
     if (threadIdx.x < AA_NP) {
         double t = 0.0;
@@ -1401,11 +1419,16 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_apply(const GeomDev* __restri
     {
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
         const bool mine = (int)threadIdx.x < v.B;
-        const double* row = g.apart + (size_t)threadIdx.x * AA_NP;
-        for (int q = 0; q < AA_NP; ++q) {
-            const double t = wave_sum(mine ? row[q] : 0.0);
-            if (lane == 0) wred[q][wid] = t;
-        }
+        const double* row = g.apart + (size_t)(mine ? threadIdx.x : 0) * AA_NP;
+        double sums[AA_NP];
+#pragma unroll
+        for (int q = 0; q < AA_NP; ++q) sums[q] = row[q];
+#pragma unroll
+        for (int q = 0; q < AA_NP; ++q) sums[q] = mine ? sums[q] : 0.0;
+        wave_sum_n(sums);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < AA_NP; ++q) wred[q][wid] = sums[q];
         __syncthreads();
         if ((int)threadIdx.x < AA_NP) {
             double t = 0.0;
