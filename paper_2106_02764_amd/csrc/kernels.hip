@@ -80,6 +80,31 @@ __device__ double block_sum(double v, double* red) {
     return red[16];
 }
 
+// Two block sums in one pass (red: at least 34 doubles); each value is summed
+// exactly as block_sum sums it.
+__device__ void block_sum2(double& a, double& b, double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double v[2] = {a, b};
+    wave_sum_n(v);
+    __syncthreads();
+    if (lane == 0) {
+        red[wid] = v[0];
+        red[16 + wid] = v[1];
+    }
+    __syncthreads();
+    if (wid == 0) {
+        double t[2] = {lane < nw ? red[lane] : 0.0, lane < nw ? red[16 + lane] : 0.0};
+        wave_sum_n(t);
+        if (lane == 0) {
+            red[32] = t[0];
+            red[33] = t[1];
+        }
+    }
+    __syncthreads();
+    a = red[32];
+    b = red[33];
+}
+
 __device__ __forceinline__ int nbr_cell(const GeomDev& g, int cell, int f) {
     int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
     const int a = f >> 1, step = (f & 1) ? 1 : -1;
@@ -1232,7 +1257,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
 
 // kappa, history and the convergence test of Algorithm 1 (one block per geometry).
 __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
-    __shared__ double red[32];
+    __shared__ double red[56];
     const GeomDev& g = geoms[blockIdx.x];
     if (g.ctrl[CTRL_DONE]) return;
     double k = 0.0, kf = 0.0, wr = 0.0;
@@ -1242,18 +1267,17 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
         wr = fmax(wr, g.wres[i]);
     }
     // fixed-order: every thread sums a fixed strided subset, then block_sum
-    k = block_sum(k, red);
-    kf = block_sum(kf, red);
+    block_sum2(k, kf, red);
     // max of the wrap residuals (every value is >= 0: max via the sum of a
     // one-hot is not needed, a plain block max suffices)
     __syncthreads();
     {
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         for (int m2 = 32; m2 >= 1; m2 >>= 1) wr = fmax(wr, shfl_xor(wr, m2));
-        if (lane == 0) red[20 + wid] = wr;
+        if (lane == 0) red[36 + wid] = wr;
         __syncthreads();
         wr = 0.0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) wr = fmax(wr, red[20 + i]);
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) wr = fmax(wr, red[36 + i]);
     }
     if (threadIdx.x == 0) {
         const int pass = g.ctrl[CTRL_PASS];
@@ -1607,8 +1631,20 @@ __device__ __forceinline__ double sum_partials(const double* part, int B, double
     return block_sum(t, red);
 }
 
+// two of them in one pass (red: at least 34 doubles)
+__device__ __forceinline__ void sum_partials2(const double* p, const double* q, int B, double* red, double& sp,
+                                              double& sq) {
+    sp = 0.0;
+    sq = 0.0;
+    for (int i = threadIdx.x; i < B; i += blockDim.x) {
+        sp += p[i];
+        sq += q[i];
+    }
+    block_sum2(sp, sq, red);
+}
+
 __global__ void __launch_bounds__(FB_THREADS) k_fourier_init(const GeomDev* __restrict__ geoms) {
-    __shared__ double red[32];
+    __shared__ double red[40];
     const GeomDev& g = geoms[blockIdx.y];
     const FView v = fourier_view(g, blockIdx.x);
     if ((int)blockIdx.x >= v.B) return;
@@ -1641,8 +1677,7 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_init(const GeomDev* __re
         s += r0 * r0;
         bb += b * b;
     }
-    s = block_sum(s, red);
-    bb = block_sum(bb, red);
+    block_sum2(s, bb, red);
     if (threadIdx.x == 0) {
         v.rr0[blockIdx.x] = s;
         v.pap[blockIdx.x] = bb;              // |b|^2 partials, read by k_fourier_norm
@@ -1656,11 +1691,11 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_init(const GeomDev* __re
 
 // |b| of every geometry (one block each); a zero first residual is converged
 __global__ void __launch_bounds__(FB_THREADS) k_fourier_norm(const GeomDev* __restrict__ geoms) {
-    __shared__ double red[32];
+    __shared__ double red[40];
     const GeomDev& g = geoms[blockIdx.x];
     const FView v = fourier_view(g, 0);
-    const double bb = sum_partials(v.pap, v.B, red);
-    const double rr = sum_partials(v.rr0, v.B, red);
+    double bb, rr;
+    sum_partials2(v.pap, v.rr0, v.B, red, bb, rr);
     if (threadIdx.x == 0) {
         v.sc[0] = sqrt(bb);
         if (!(bb > 0.0) || !(rr > 0.0)) v.sc[1] = 1.0;
@@ -1671,12 +1706,12 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_norm(const GeomDev* __re
 // the geometry computes the same sums).  q: iteration parity.
 __global__ void __launch_bounds__(FB_THREADS) k_fourier_pq(const GeomDev* __restrict__ geoms, int q,
                                                          double tol, int max_iter) {
-    __shared__ double red[32];
+    __shared__ double red[40];
     const GeomDev& g = geoms[blockIdx.y];
     const FView v = fourier_view(g, blockIdx.x);
     if ((int)blockIdx.x >= v.B || v.sc[1] != 0.0) return;
-    const double rr_new = sum_partials(q ? v.rr1 : v.rr0, v.B, red);
-    const double rr_old = sum_partials(q ? v.rr0 : v.rr1, v.B, red);
+    double rr_new, rr_old;
+    sum_partials2(q ? v.rr1 : v.rr0, q ? v.rr0 : v.rr1, v.B, red, rr_new, rr_old);
     const double rn = sqrt(rr_new);
     if (!(rn > tol * v.sc[0]) || v.sc[4] >= (double)max_iter) {
         if (blockIdx.x == 0 && threadIdx.x == 0) v.sc[1] = 1.0;
@@ -1711,12 +1746,12 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_pq(const GeomDev* __rest
 
 // x += alpha p, r -= alpha A p and the partials of the new r.r.
 __global__ void __launch_bounds__(FB_THREADS) k_fourier_xr(const GeomDev* __restrict__ geoms, int q) {
-    __shared__ double red[32];
+    __shared__ double red[40];
     const GeomDev& g = geoms[blockIdx.y];
     const FView v = fourier_view(g, blockIdx.x);
     if ((int)blockIdx.x >= v.B || v.sc[1] != 0.0) return;
-    const double pap = sum_partials(v.pap, v.B, red);
-    const double rr = sum_partials(q ? v.rr1 : v.rr0, v.B, red);
+    double pap, rr;
+    sum_partials2(v.pap, q ? v.rr1 : v.rr0, v.B, red, pap, rr);
     const double alpha = rr / pap;
     const double* pnew = q ? v.p0 : v.p1;
     double s = 0.0;
@@ -1786,13 +1821,14 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_part(const GeomDev* __re
 }
 
 __global__ void __launch_bounds__(FB_THREADS) k_fourier_fill(const GeomDev* __restrict__ geoms) {
-    __shared__ double red[32];
+    __shared__ double red[40];
     const GeomDev& g = geoms[blockIdx.y];
     const FView v = fourier_view(g, blockIdx.x);
     if ((int)blockIdx.x >= v.B) return;
     const int n = g.ncells, nf = g.nf;
-    const double sx = sum_partials(v.p0, v.B, red);
-    const double mean = sx / sum_partials(v.p1, v.B, red);
+    double sx, sn;
+    sum_partials2(v.p0, v.p1, v.B, red, sx, sn);
+    const double mean = sx / sn;
     if (blockIdx.x == 0) {
         const int it = (int)v.sc[4];
         const double rn = sqrt(sum_partials((it & 1) ? v.rr1 : v.rr0, v.B, red));
