@@ -1261,10 +1261,24 @@ __global__ void k_finalize(const GeomDev* __restrict__ geoms, PassParams pp) {
     const GeomDev& g = geoms[blockIdx.x];
     if (g.ctrl[CTRL_DONE]) return;
     double k = 0.0, kf = 0.0, wr = 0.0;
-    for (int i = threadIdx.x; i < g.n_sys; i += blockDim.x) {
-        k += g.ksys[i];
-        kf += g.kfsys[i];
-        wr = fmax(wr, g.wres[i]);
+    const int ns = g.n_sys, bd = blockDim.x;
+    // thread t takes t, t + bd, ... in that order, 8 loads of each in flight
+    for (int i0 = threadIdx.x; i0 < ns; i0 += 8 * bd) {
+        double a[8], b[8], c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = min(i0 + u * bd, ns - 1);
+            a[u] = g.ksys[i];
+            b[u] = g.kfsys[i];
+            c[u] = g.wres[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + u * bd < ns) {
+                k += a[u];
+                kf += b[u];
+                wr = fmax(wr, c[u]);
+            }
     }
     // fixed-order: every thread sums a fixed strided subset, then block_sum
     block_sum2(k, kf, red);
