@@ -125,7 +125,9 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * inflow is then lagged like T_L; the fixed point is unchanged).  init: 0 = Fourier first guess, 1 = resume
  * from the state left in the workspace by the previous call.
  * passes_per_graph: outer passes captured per HIP-graph replay (>= 1); the
- * host reads kappa back once per replay.  waves_per_group: systems that share
+ * host reads the done flags back once per replay, with the next replay of a
+ * single-mesh solve already queued (passes after the stop exit at once, so
+ * the pass count and results do not depend on it).  waves_per_group: systems that share
  * one workgroup's lockstep reduction (1..8, 0 = auto).  fourier_tol /
  * max_fourier: CG tolerance (relative residual) and iteration cap of the
  * Fourier first guess.  only_fourier: stop after the first guess.
