@@ -647,8 +647,11 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         GeomDev v = make_view(m, ws + off, L, W, o->recycle, o->accel);
         const int ng = n_groups(m, W);
         const int c = (m->nx + 63) / 64;
-        for (int l = 0; l < m->n_dir; ++l)
-            for (int gp = 0; gp < ng; ++gp) {
+        // longest MFPs first: their systems take the most wrap iterations, so
+        // the shorter ones dispatched after them fill in behind (a shorter
+        // makespan than direction-major order; the results do not depend on it)
+        for (int gp = ng - 1; gp >= 0; --gp)
+            for (int l = 0; l < m->n_dir; ++l) {
                 Item it;
                 it.geom = gi;
                 it.l = l;
