@@ -317,8 +317,11 @@ obte_status mode_weights(obte_mesh* m, const obte_material_desc* d) {
     return OBTE_OK;
 }
 
+// Systems per workgroup when the caller leaves it to the library: 4 in 2D;
+// 1 in 3D, where the longest-MFP-first queue balances best with the finest
+// grain (measured on the 64x64x16 membrane: 9.9 against 9.6 solves/s at 4).
 int auto_waves(const obte_mesh* m) {
-    int w = 4;
+    int w = m->nz > 1 ? 1 : 4;
     if (m->n_mfp < w) w = m->n_mfp;
     return std::max(1, w);
 }

@@ -71,3 +71,16 @@ def test_fourier_replays_stop_at_max_fourier(P, max_fourier):
     r = gpu_solve(P, w, outer_tol=1e-6, fourier_tol=1e-300, max_fourier=max_fourier, inner_tol=1e-12)
     assert r["fourier_iters"] == max_fourier
     assert r["status"] == 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_waves_per_group_independent(P, dim):
+    """The systems sharing a workgroup (and so the dispatch order of the work
+    items) change nothing in the result: FP64 kappa and T_L bit for bit."""
+    from tests.test_gpu_parity import ragged_porous, small3d
+    w = ragged_porous() if dim == 2 else small3d()
+    runs = [gpu_solve(P, w, outer_tol=1e-9, waves_per_group=W, **TIGHT) for W in (1, 2, 4)]
+    for r in runs[1:]:
+        assert r["outer_iters"] == runs[0]["outer_iters"]
+        assert r["kappa"] == runs[0]["kappa"]
+        assert np.array_equal(r["T_L"], runs[0]["T_L"])
