@@ -57,7 +57,7 @@ REF = dict(precision=0, outer_tol=1e-10, stop_rule=0, accel=8, inner_tol=1e-12, 
 # solve, each scaled by the same counter on a plain 256 MiB copy); valid only
 # for the kernel source it was taken on.
 TRAFFIC = {"kernels_sha256": "20fec19db13a9f29bbfdd5e55b4ec4268560855d3d5497170bbc4a01a957acb1",
-           "fetch_bytes": 8682269, "write_bytes": 95372858}
+           "fetch_bytes": 8683431, "write_bytes": 95372851}
 
 
 def parse():
