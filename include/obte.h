@@ -128,7 +128,7 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * host reads the done flags back once per replay, with the next replay of a
  * single-mesh solve already queued (passes after the stop exit at once, so
  * the pass count and results do not depend on it).  waves_per_group: systems that share
- * one workgroup's lockstep reduction (1..8, 0 = auto).  fourier_tol /
+ * one workgroup's lockstep reduction (1..8, 0 = auto: 4 in 2D, 1 in 3D).  fourier_tol /
  * max_fourier: CG tolerance (relative residual) and iteration cap of the
  * Fourier first guess.  only_fourier: stop after the first guess.
  * keep_state: store the converged per-system solutions in the workspace (the
