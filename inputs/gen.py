@@ -297,13 +297,11 @@ def small_3d(nx: int, ny: int, nz: int, solid=None, n_theta: int = 4, n_phi: int
                     sigma=None if sigma is None else np.asarray(sigma, float).ravel())
 
 
-def with_modes(w: Workload, n_modes: int, seed: int, on_node: bool = False,
+def with_modes(w: Workload, n_modes: int, seed: int,
                mfp_lo: float | None = None, mfp_hi: float | None = None, dim3: bool = False,
                n_static: int = 0) -> Workload:
     """A copy of `w` whose material is a synthetic mode table.
 
-    on_node: one mode per grid point F_ml = Lambda_m s_l with the kernel's
-    weight alpha_ml (the interpolation is then the identity).  Otherwise
     n_modes modes (n_modes/2 random ones and their reverses -F, so the table
     carries no net flux) with log-uniform |F| in [mfp_lo, mfp_hi] (default: a
     bit beyond the grid, so some modes are clamped), uniform random directions,
@@ -315,11 +313,6 @@ def with_modes(w: Workload, n_modes: int, seed: int, on_node: bool = False,
     import dataclasses
     rng = np.random.default_rng(seed)
     nd = w.ndim
-    if on_node:
-        mu = float(np.sum(w.dir_w * w.dirs[:, w.grad_axis] ** 2))
-        alpha = w.kappa_m[:, None] * w.dir_w[None, :] / (w.mfp[:, None] ** 2 * mu)
-        F = (w.mfp[:, None, None] * w.dirs[None, :, :]).reshape(-1, nd)
-        return dataclasses.replace(w, modes=(F, alpha.ravel()), name=w.name + "_nodes")
     lo = w.mfp.min() / 2 if mfp_lo is None else mfp_lo
     hi = w.mfp.max() * 2 if mfp_hi is None else mfp_hi
     half = n_modes // 2

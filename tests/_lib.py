@@ -31,3 +31,14 @@ def solid_to_full(prob, vec_solid):
 def rel(a, b):
     a, b = np.asarray(a, float), np.asarray(b, float)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def on_node_modes(w):
+    """A copy of workload `w` whose material is a mode table with one mode on
+    every grid node, F_ml = Lambda_m s_l, weighted by the oracle's own grid
+    weights alpha_ml (so the interpolation onto the grid is the identity)."""
+    import dataclasses
+    from oracle.material import material_weights
+    wts = material_weights(w.mfp, w.dirs, w.dir_w, w.kappa_m, w.grad_axis)
+    F = (w.mfp[:, None, None] * w.dirs[None, :, :]).reshape(-1, w.ndim)
+    return dataclasses.replace(w, modes=(F, wts["alpha"].ravel()), name=w.name + "_nodes")

@@ -13,6 +13,7 @@ from oracle.fourier import dirichlet_energy_kappa, fourier_solve
 from oracle.material import Material, wall_weights
 from oracle.mesh import Mesh
 from oracle.adjoint import adjoint_dense, adjoint_source_iteration, gradient_from
+from tests._lib import on_node_modes
 
 NM = 1e-9
 
@@ -377,7 +378,7 @@ def test_modes_on_node_identity():
     single 1, the grid weights equal the kernel path's, and kappa_mu is the
     per-system kappa."""
     w0 = gen.small_2d(8, 6, solid=gen.square_block_mask(8, 6, 2, 5), n_dir=8, n_mfp=3)
-    wn = gen.with_modes(w0, 0, 0, on_node=True)
+    wn = on_node_modes(w0)
     F, _ = wn.modes
     W = interp_weights(w0.mfp, w0.dirs, F)
     for mu, terms in enumerate(W):
@@ -493,7 +494,7 @@ def test_exact_modes_on_nodes_equal_kernel_path():
     the kernel's weights is the grid problem itself, systems renumbered."""
     import dataclasses
     w0 = gen.small_2d(10, 8, solid=gen.square_block_mask(10, 8, 3, 6), n_dir=8, n_mfp=3)
-    we = dataclasses.replace(gen.with_modes(w0, 0, 0, on_node=True), modes_exact=True)
+    we = dataclasses.replace(on_node_modes(w0), modes_exact=True)
     p0, pe = Problem(w0), Problem(we)
     assert pe.mat.n_mfp == 1 and pe.mat.n_dir == 24
     r0 = source_iteration(p0, tol=1e-13)
