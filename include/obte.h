@@ -132,12 +132,7 @@ enum { OBTE_FP64 = 0, OBTE_FP32 = 1 };
  * max_fourier: CG tolerance (relative residual) and iteration cap of the
  * Fourier first guess.  only_fourier: stop after the first guess.
  * keep_state: store the converged per-system solutions in the workspace (the
- * forward checkpoint obte_adjoint needs; n_systems * n_cells doubles).
- * recycle: Krylov pairs kept per system across outer passes (0..32): the
- * periodic-wrap matrix of a system is fixed during a solve, so earlier
- * products project most of a later pass's wrap residual away.  2D meshes
- * only; experimental (the orthogonalised pairs lose accuracy over many
- * passes), off by default.
+ * forward checkpoint obte_adjoint needs; n_systems * n_solid doubles).
  * timing: record HIP events on `stream` around every sweep, reduction and
  * Fourier launch and report their summed durations in obte_stats (the pass
  * kernels are then launched directly instead of through a HIP graph).
@@ -171,7 +166,6 @@ typedef struct {
     double fourier_tol;
     int max_fourier;
     int keep_state;
-    int recycle;
     int lag_wrap;
     double inner_rtol;
     double wrap_tol;
@@ -195,6 +189,14 @@ typedef struct {
     double sweep_ms;          /* summed duration of the sweep kernel launches */
     double reduce_ms;         /* summed duration of the per-pass reduction kernels */
     double fourier_ms;        /* duration of the Fourier first guess */
+    /* Energy balance of the last pass (section Model: T_L is the temperature
+     * that conserves energy, sum_ml alpha_ml sigma_i (T_iml - T_L,i) = 0):
+     * max_i |sum_ml alpha_ml sigma_i (T_iml - T_L,i)| over the mean of
+     * sum_ml alpha_ml |T_iml| per solid cell, with T the last pass's solutions
+     * and T_L the lattice temperature they were solved with.  It vanishes at
+     * the fixed point and measures how far the last pass is from it (forward
+     * solves; 0 for an adjoint or without passes). */
+    double energy_residual;
 } obte_stats;
 
 /* Fill opts with defaults (FP64, outer_tol 1e-8, ...). */
@@ -249,9 +251,26 @@ obte_status obte_solve_batch(obte_mesh* const* meshes, int n, const obte_solve_o
                              size_t workspace_bytes, void* stream, double* kappa_out,
                              obte_stats* stats);
 
-/* kappa_cc of the last solve and, if kappa_per_mfp is non-NULL, its split
- * over the n_mfp MFPs (host arrays). */
+/* Effective conductivity of the last solve (paper Eq. (keff): kappa_eff =
+ * -(L/dT) times the heat flux through the cell's cross-section), in the
+ * cell-centred form kappa_cc = L / (dT N_cells) sum_i sum_ml S_ml,g T_iml:
+ * the volume-averaged flux J of section Model along the gradient axis g,
+ * with N_cells counting pores (they carry no flux).  kappa_eff: host, one
+ * double.  kappa_per_mfp (nullable): host, n_mfp doubles, the same sum split
+ * over the MFPs.  OBTE_ERR_ARG for a NULL mesh, OBTE_ERR_STATE before the
+ * first completed solve on it; the values are those the last obte_solve /
+ * obte_solve_batch member wrote, also when it returned
+ * OBTE_ERR_NOT_CONVERGED. */
 obte_status obte_kappa(const obte_mesh* mesh, double* kappa_eff, double* kappa_per_mfp);
+
+/* Per-system work of the last obte_solve / obte_solve_batch member on this
+ * mesh, summed over its passes (Appendix A, Eq. (iter2): one (m,l) system is
+ * one upwind solve per pass): inner_iters, the wrap-row BiCGSTAB iterations;
+ * sweeps, the upwind sweeps (one per pass plus two per iteration, plus the
+ * correction sweep without lag_wrap).  Host arrays of obte_mesh_n_systems()
+ * entries in system order sys = m * n_dir + l; either may be NULL.
+ * OBTE_ERR_STATE before a solve that ran passes. */
+obte_status obte_system_counts(const obte_mesh* mesh, long long* inner_iters, long long* sweeps);
 
 /* Mode-resolved conductivity of the last solve (paper Eq. mode-resolved, in
  * the cell-centred form of kappa_cc): kappa_mu = L S_mu,g / (dT N_cells)
@@ -286,7 +305,10 @@ obte_status obte_upwind_apply(const obte_mesh* mesh, int precision, int transpos
                               const void* x_dev, void* y_dev, void* stream);
 
 /* Save / restore the outer-loop state (pass count, kappa history, T_L, T_w
- * and the wrap inflow vectors) of the last solve to a host file.  Loading
+ * and the wrap inflow vectors) of the last solve to a host file.  Save checks
+ * its arguments before it opens the file (a rejected call leaves the file
+ * untouched) and closes it on every path; OBTE_ERR_HIP if a read-back or a
+ * write fails, OBTE_ERR_ARG if the file cannot be opened or does not match.  Loading
  * needs a mesh with the same geometry and material; a following obte_solve
  * with init = 1 and the same precision, waves_per_group and keep_state
  * continues the iteration exactly where the saved run stopped. */

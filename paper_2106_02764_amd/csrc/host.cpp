@@ -51,6 +51,9 @@ void soft(hipError_t e, const char* what) {
 // depend on max_outer and a checkpoint can be resumed with a larger cap.
 constexpr int HIST_CAP = 1 << 16;
 
+// checkpoint file tag (format: header of 9 ints, then the state arrays)
+constexpr int CKPT_MAGIC = 0x4f425447;
+
 }  // namespace
 
 // A captured graph kept across calls while the launches it was captured from
@@ -77,6 +80,8 @@ struct obte_mesh {
     // device tables (library-owned)
     int device = -1;
     uint16_t* d_fc = nullptr;
+    std::vector<int> sidx, scell;   // solid index of each cell (-1 in pores), cell of each solid index
+    int *d_sidx = nullptr, *d_scell = nullptr;
     int *d_wall_cell = nullptr, *d_wall_face = nullptr, *d_wall_idx = nullptr;
     double *d_mfp = nullptr, *d_dirs = nullptr, *d_D = nullptr, *d_S = nullptr, *d_wout = nullptr,
            *d_kax = nullptr;
@@ -87,8 +92,9 @@ struct obte_mesh {
     const double* last_sigma = nullptr;
     double kappa = 0, kappa_face = 0, kappa_fourier = 0;
     std::vector<double> kappa_per_mfp;
+    std::vector<long long> sys_iters, sys_sweeps;   // per system, summed over the passes
     GeomDev host_view{};
-    int last_precision = 0, last_waves = 0, last_max_outer = 0, last_keep = 0, last_recycle = 0;
+    int last_precision = 0, last_waves = 0, last_max_outer = 0, last_keep = 0;
     // mode table (optional): per mode up to MODE_TERMS (system, weight) pairs
     // and its flux weight along the gradient axis; kappa_mu of the last solve
     int n_modes = 0;
@@ -169,7 +175,7 @@ namespace {
 // ---------------------------------------------------------------------------
 struct Layout {
     size_t sigma, sigma_f, sT, Tw, T_L, U, X, ksys, kfsys, iters, sweeps, hist, hist_face, ctrl, fx, fscal,
-        Tstore, lam_psi, lam_phi, grad, bnd, mem, mem_count, mem_bytes, wres, wres_hist, kry, ax, actl, ag,
+        Tstore, lam_psi, lam_phi, grad, bnd, wres, wres_hist, kry, ax, actl, ag,
         axp, afp, adX, adF, agram, apart, kraw, total;
 };
 
@@ -350,12 +356,11 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.sweeps = take((size_t)m->n_sys * 8);
     L.ctrl = take(CTRL_N * 4);
     L.fx = take(fourier_scratch_doubles(nc) * 8);
-    L.fscal = take(4 * 8);
+    L.fscal = take(8 * 8);
     L.lam_psi = take(2 * nc * 8);
     L.lam_phi = take(2 * nw * 8);
     L.grad = take(nc * 8);
     L.bnd = take(4 * (size_t)m->nf * nc * 8);
-    L.mem_count = take(2 * (size_t)m->n_sys * 4);
     L.wres = take((size_t)m->n_sys * 8);
     L.hist = take((size_t)HIST_CAP * 8);
     L.hist_face = take((size_t)HIST_CAP * 8);
@@ -364,14 +369,13 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.ax = take((naa + 1) * 8);            // + the gauge shift of the pass
     L.actl = take(8 * 4);
     L.kraw = take((size_t)m->n_sys * 8);
-    // the parts below depend on precision / recycle / keep_state / accel, so
+    // the parts below depend on precision / keep_state / accel, so
     // the state a resumed solve reads (above, and U) keeps its place
     L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
     L.kry = m->nz > 1 ? take((size_t)m->n_sys * KRY3_VECS * nwrap * tsz) : 0;
-    L.mem_bytes = 2 * (size_t)m->n_sys * 2 * (size_t)std::max(o->recycle, 0) * nwrap * tsz;
-    L.mem = take(L.mem_bytes);
-    L.Tstore = o->keep_state ? take((size_t)m->n_sys * nc * 8) : 0;
-    L.X = take((size_t)m->n_sys * nc * tsz);
+    const size_t nsol = (size_t)m->nsolid;
+    L.Tstore = o->keep_state ? take((size_t)m->n_sys * nsol * 8) : 0;
+    L.X = take((size_t)m->n_sys * nsol * tsz);
     // last: the mixing history (an adjoint may use another depth than the
     // forward solve whose stored state it reads)
     const size_t M = (size_t)std::max(o->accel, 0);
@@ -386,19 +390,18 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     return L;
 }
 
-GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int recycle, int accel) {
+GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int accel) {
     GeomDev g{};
-    g.mem_R = recycle;
     g.n_aa = m->ncells + m->nwalls;
     g.aa_m = accel;
     g.nx = m->nx; g.ny = m->ny; g.nz = m->nz; g.ndim = m->ndim; g.nf = m->nf;
-    g.ncells = m->ncells; g.nwalls = m->nwalls; g.nwrap = m->nx * m->nz;
+    g.ncells = m->ncells; g.nwalls = m->nwalls; g.nwrap = m->nx * m->nz; g.nsolid = m->nsolid;
     for (int a = 0; a < 3; ++a) { g.periodic[a] = m->periodic[a]; g.h[a] = m->h[a]; g.L[a] = m->L[a]; }
     g.grad_axis = m->grad_axis;
     g.dT = m->dT;
     g.n_mfp = m->n_mfp; g.n_dir = m->n_dir; g.n_sys = m->n_sys;
     g.n_perp = m->ncells / (m->grad_axis == 0 ? m->nx : (m->grad_axis == 1 ? m->ny : m->nz));
-    g.fc = m->d_fc; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face; g.wall_idx = m->d_wall_idx;
+    g.fc = m->d_fc; g.sidx = m->d_sidx; g.scell = m->d_scell; g.wall_cell = m->d_wall_cell; g.wall_face = m->d_wall_face; g.wall_idx = m->d_wall_idx;
     g.mfp = m->d_mfp; g.dirs = m->d_dirs; g.Dw = m->d_D; g.S = m->d_S; g.wout = m->d_wout;
     g.gauge = m->n_modes > 0 ? 1 : 0;
     g.kappa_axis = m->d_kax;
@@ -425,8 +428,6 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.lam_phi = (double*)(ws + L.lam_phi);
         g.gradient = (double*)(ws + L.grad);
         g.bnd = (double*)(ws + L.bnd);
-        g.mem = ws + L.mem;
-        g.mem_count = (int*)(ws + L.mem_count);
         g.wres = (double*)(ws + L.wres);
         g.wres_hist = (double*)(ws + L.wres_hist);
         g.ax = (double*)(ws + L.ax);
@@ -458,12 +459,12 @@ void free_dev(obte_mesh* m) {
     m->g_fourier.reset();
     m->g_pass.reset();
     m->g_adj.reset();
-    void* ptrs[] = {m->d_fc, m->d_wall_cell, m->d_wall_face, m->d_wall_idx, m->d_mfp, m->d_dirs,
+    void* ptrs[] = {m->d_fc, m->d_sidx, m->d_scell, m->d_wall_cell, m->d_wall_face, m->d_wall_idx, m->d_mfp, m->d_dirs,
                     m->d_D, m->d_S, m->d_wout, m->d_kax, m->d_geom, m->d_mode_sys, m->d_mode_w,
                     m->d_mode_Sg, m->d_kmode};
     for (void* p : ptrs)
         if (p) soft(hipFree(p), "hipFree(table)");
-    m->d_fc = nullptr; m->d_wall_cell = m->d_wall_face = m->d_wall_idx = nullptr;
+    m->d_fc = nullptr; m->d_sidx = m->d_scell = nullptr; m->d_wall_cell = m->d_wall_face = m->d_wall_idx = nullptr;
     m->d_mfp = m->d_dirs = m->d_D = m->d_S = m->d_wout = m->d_kax = nullptr;
     m->d_geom = nullptr;
     m->d_mode_sys = nullptr;
@@ -484,7 +485,6 @@ obte_status check_opts(const obte_solve_opts* o) {
     if (!(o->fourier_tol > 0.0) || o->max_fourier < 0)
         return fail(OBTE_ERR_ARG, "fourier_tol must be > 0 and max_fourier >= 0");
     if (o->init != 0 && o->init != 1) return fail(OBTE_ERR_ARG, "init must be 0 or 1");
-    if (o->recycle < 0 || o->recycle > 32) return fail(OBTE_ERR_ARG, "recycle must be in 0..32");
     if (o->lag_wrap != 0 && o->lag_wrap != 1) return fail(OBTE_ERR_ARG, "lag_wrap must be 0 or 1");
     if (!(o->wrap_tol >= 0.0)) return fail(OBTE_ERR_ARG, "wrap_tol must be >= 0");
     if (!(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0)) return fail(OBTE_ERR_ARG, "inner_rtol must be in [0, 1)");
@@ -555,7 +555,7 @@ struct Run {
     size_t cls_lds[5] = {};
     int waves = 4, nzmax = 1, precision = 0, accel = 0;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
-    int max_cells = 0, max_walls = 0;
+    int max_cells = 0, max_walls = 0, max_solid = 0;
     // pinned host slots for the loop read-backs (two per loop, see
     // speculative loops below); null: plain synchronous read-backs
     int* h_pin = nullptr;
@@ -623,7 +623,6 @@ obte_status resolve_waves(const obte_mesh* const* meshes, int n, const obte_solv
             if (o->waves_per_group) return fail(OBTE_ERR_ARG, "waves_per_group %d needs more than 64 KiB of LDS (max %d)", W, wmax);
             W = wmax;
         }
-        if (nzm > 1 && o->recycle > 0) return fail(OBTE_ERR_ARG, "recycle is not available for 3D meshes");
     }
     *W_out = W;
     *per_wave_out = per_wave;
@@ -647,7 +646,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         obte_mesh* m = meshes[gi];
         Layout L = make_layout(m, o, W);
         if (offsets) offsets->push_back(off);
-        GeomDev v = make_view(m, ws + off, L, W, o->recycle, o->accel);
+        GeomDev v = make_view(m, ws + off, L, W, o->accel);
         const int ng = n_groups(m, W);
         const int c = (m->nx + 63) / 64;
         // longest MFPs first: their systems take the most wrap iterations, so
@@ -665,6 +664,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         R.views.push_back(v);
         R.nzmax = std::max(R.nzmax, m->nz);
         R.max_cells = std::max(R.max_cells, m->ncells);
+        R.max_solid = std::max(R.max_solid, m->nsolid);
         R.max_walls = std::max(R.max_walls, m->nwalls);
         off += align256(L.total);
     }
@@ -712,7 +712,7 @@ obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Tim
     if (s != OBTE_OK) return s;
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 1], st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 2], st));
-    HIPCHK(launch_reduce_pass(R.precision, R.d_views, (int)R.views.size(), R.max_cells, R.max_walls, pp, st));
+    HIPCHK(launch_reduce_pass(R.precision, R.d_views, (int)R.views.size(), R.max_solid, pp, st));
     if (R.gauge && !pp.adjoint) HIPCHK(launch_gauge(R.d_views, (int)R.views.size(), R.max_cells + R.max_walls, st));
     if (R.accel > 0) HIPCHK(launch_anderson(R.d_views, (int)R.views.size(), R.max_cells + R.max_walls, pp, st));
     HIPCHK(launch_finalize(R.d_views, (int)R.views.size(), pp, st));
@@ -931,7 +931,6 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         if (o->init == 0) {
             const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
             HIPCHK(hipMemsetAsync(ws + L.U, 0, 2 * (size_t)m->n_sys * m->nx * m->nz * tsz, st));
-            HIPCHK(hipMemsetAsync(ws + L.mem_count, 0, 2 * (size_t)m->n_sys * 4, st));
         }
         HIPCHK(hipMemsetAsync(ws + L.iters, 0, 2 * (size_t)m->n_sys * 8, st));
         HIPCHK(hipMemsetAsync(ws + L.wres, 0, (size_t)m->n_sys * 8, st));
@@ -966,6 +965,9 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
             if (sigma && sigma[i]) pp.sigma1 = 0;
         s = outer_loop(R, pp, K, st, o->max_outer, &tm, n == 1 ? &meshes[0]->g_pass : nullptr);
         if (s != OBTE_OK) return s;
+        // energy balance of the last pass, from its stored solutions
+        for (int i = 0; i < n; ++i)
+            HIPCHK(launch_energy(meshes[i]->d_geom, R.precision, meshes[i]->nsolid, st));
         // replay the last pass's final sweep for the flux map / stored state
         if ((J_out || keep_T) && n == 1) {
             PassParams rp = pp;
@@ -983,7 +985,7 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         obte_mesh* m = meshes[i];
         const GeomDev& v = R.views[i];
         std::vector<int> ctrl(CTRL_N);
-        double fs[4];
+        double fs[5];
         HIPCHK(hipMemcpyAsync(ctrl.data(), v.ctrl, CTRL_N * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(fs, v.fscal, sizeof fs, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1017,6 +1019,8 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         m->kappa_face = passes > 0 ? histf[passes - 1] : fs[0];
         m->kappa_per_mfp.assign(m->n_mfp, 0.0);
         for (int sys = 0; sys < m->n_sys; ++sys) m->kappa_per_mfp[sys / m->n_dir] += ks[sys];
+        m->sys_iters = its;
+        m->sys_sweeps = sws;
         m->modes_solved = false;
         if (m->n_modes > 0 && passes > 0) {
             // mode-resolved kappa: gather of the per-system sums (kernel)
@@ -1037,7 +1041,6 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         m->last_waves = R.waves;
         m->last_max_outer = o->max_outer;
         m->last_keep = o->keep_state;
-        m->last_recycle = o->recycle;
         obte_status si = OBTE_OK;
         if (ctrl[CTRL_NONFINITE]) si = fail(OBTE_ERR_NUMERIC, "non-finite kappa in mesh %d", i);
         else if (!o->only_fourier && !ctrl[CTRL_CONVERGED])
@@ -1061,6 +1064,7 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
             S.sweep_ms = tm.sweep_ms;
             S.reduce_ms = tm.reduce_ms;
             S.fourier_ms = 0.0;
+            S.energy_residual = passes > 0 ? fs[4] : 0.0;
             if (tm.on && o->init == 0) {
                 float f = 0;
                 hipError_t e = hipEventElapsedTime(&f, tm.f0, tm.f1);
@@ -1097,7 +1101,6 @@ void obte_default_opts(obte_solve_opts* o) {
     o->fourier_tol = 1e-13;
     o->max_fourier = 20000;
     o->keep_state = 0;
-    o->recycle = 0;
     o->lag_wrap = 0;
     o->inner_rtol = 0.0;
     o->wrap_tol = 0.0;
@@ -1144,12 +1147,14 @@ obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
     m->grad_axis = d->grad_axis;
     m->dT = d->dT_ext;
     m->fc.assign(nc, 0);
+    m->sidx.assign(nc, -1);
     m->wall_idx.assign(nc * m->nf, -1);
     const int n3[3] = {m->nx, m->ny, m->nz};
     for (long long c = 0; c < nc; ++c) {
         if (d->solid[c] > 1) { delete m; return fail(OBTE_ERR_ARG, "solid mask entries must be 0/1"); }
         if (!d->solid[c]) continue;
-        m->nsolid++;
+        m->sidx[c] = m->nsolid++;
+        m->scell.push_back((int)c);
         const int q0[3] = {(int)(c % m->nx), (int)((c / m->nx) % m->ny), (int)(c / ((long long)m->nx * m->ny))};
         uint16_t w = 1;
         for (int a = 0; a < d->ndim; ++a)
@@ -1347,6 +1352,8 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     HIPCHK(hipGetDevice(&m->device));
     obte_status s;
     if ((s = upload(&m->d_fc, m->fc)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_sidx, m->sidx)) != OBTE_OK) return s;
+    if ((s = upload(&m->d_scell, m->scell)) != OBTE_OK) return s;
     if ((s = upload(&m->d_wall_cell, m->wall_cell)) != OBTE_OK) return s;
     if ((s = upload(&m->d_wall_face, m->wall_face)) != OBTE_OK) return s;
     if ((s = upload(&m->d_wall_idx, m->wall_idx)) != OBTE_OK) return s;
@@ -1364,7 +1371,7 @@ obte_status obte_material_set(obte_mesh* m, const obte_material_desc* d) {
     }
     m->modes_solved = false;
     HIPCHK(hipMalloc((void**)&m->d_geom, sizeof(GeomDev)));
-    GeomDev v = make_view(m, nullptr, Layout{}, 0, 0, 0);
+    GeomDev v = make_view(m, nullptr, Layout{}, 0, 0);
     HIPCHK(hipMemcpy(m->d_geom, &v, sizeof v, hipMemcpyHostToDevice));
     m->host_view = v;
     m->has_material = true;
@@ -1433,6 +1440,17 @@ obte_status obte_kappa(const obte_mesh* m, double* kappa_eff, double* kappa_per_
     return OBTE_OK;
 }
 
+obte_status obte_system_counts(const obte_mesh* m, long long* inner_iters, long long* sweeps) {
+    if (!m) return fail(OBTE_ERR_ARG, "mesh is NULL");
+    if (!m->solved) return fail(OBTE_ERR_STATE, "no solve has completed on this mesh");
+    if ((int)m->sys_sweeps.size() != m->n_sys) return fail(OBTE_ERR_STATE, "the last solve ran no passes");
+    for (int i = 0; i < m->n_sys; ++i) {
+        if (inner_iters) inner_iters[i] = m->sys_iters[i];
+        if (sweeps) sweeps[i] = m->sys_sweeps[i];
+    }
+    return OBTE_OK;
+}
+
 obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* sigma_dev,
                          void* workspace, size_t ws_bytes, void* stream, double* grad_dev,
                          obte_stats* stats) {
@@ -1449,7 +1467,6 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     obte_solve_opts oo = *o;
     oo.waves_per_group = m->last_waves;
     oo.keep_state = 1;
-    oo.recycle = m->last_recycle;
     obte_mesh* mp = m;
     s = build_run(R, &mp, 1, &oo, (char*)workspace, nullptr);
     if (s != OBTE_OK) return s;
@@ -1466,7 +1483,6 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
     const size_t half = (size_t)m->n_sys * m->nx * m->nz * tsz;
     HIPCHK(hipMemsetAsync(ws + L.U + half, 0, half, st));
-    HIPCHK(hipMemsetAsync(ws + L.mem_count + (size_t)m->n_sys * 4, 0, (size_t)m->n_sys * 4, st));
     HIPCHK(hipMemsetAsync(ws + L.bnd + 2 * (size_t)m->nf * m->ncells * 8, 0,
                           2 * (size_t)m->nf * m->ncells * 8, st));
     HIPCHK(hipMemsetAsync(ws + L.iters, 0, 2 * (size_t)m->n_sys * 8, st));
@@ -1507,6 +1523,7 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
         stats->sweep_ms = tm.sweep_ms;
         stats->reduce_ms = tm.reduce_ms;
         stats->fourier_ms = 0.0;
+        stats->energy_residual = 0.0;
     }
     if (ctrl[CTRL_NONFINITE]) return fail(OBTE_ERR_NUMERIC, "non-finite adjoint functional");
     if (!ctrl[CTRL_CONVERGED]) return fail(OBTE_ERR_NOT_CONVERGED, "adjoint: no convergence in %d passes", passes);
@@ -1528,13 +1545,14 @@ obte_status obte_upwind_apply(const obte_mesh* m, int precision, int transpose, 
 obte_status obte_checkpoint_save(const obte_mesh* m, const void* workspace, const char* path) {
     if (!m || !workspace || !path) return fail(OBTE_ERR_ARG, "NULL argument");
     if (!m->solved) return fail(OBTE_ERR_STATE, "nothing to checkpoint");
+    if (m->last_ws != workspace) return fail(OBTE_ERR_ARG, "workspace differs from the last solve's");
+    // every check precedes the open: a rejected call leaves the file untouched
     FILE* f = fopen(path, "wb");
     if (!f) return fail(OBTE_ERR_ARG, "cannot open %s", path);
     // header: magic, sizes; body: ctrl, T_L, sT (2), Tw (2), U, hist
     const GeomDev& v = m->host_view;
-    if (m->last_ws != workspace) return fail(OBTE_ERR_ARG, "workspace differs from the last solve's");
-    const int hdr[10] = {0x4f425446, m->ncells, m->nwalls, m->n_sys, m->nx * m->nz, m->last_precision,
-                         m->last_waves, m->last_max_outer, m->last_keep, m->last_recycle};
+    const int hdr[9] = {CKPT_MAGIC, m->ncells, m->nwalls, m->n_sys, m->nx * m->nz, m->last_precision,
+                        m->last_waves, m->last_max_outer, m->last_keep};
     fwrite(hdr, sizeof hdr, 1, f);
     auto dump = [&](const void* dptr, size_t bytes) -> bool {
         std::vector<char> buf(bytes);
@@ -1548,9 +1566,7 @@ obte_status obte_checkpoint_save(const obte_mesh* m, const void* workspace, cons
     ok = ok && dump(v.T_L, (size_t)m->ncells * 8) && dump(v.sT, 2 * (size_t)m->ncells * 8) &&
          dump(v.Tw, 2 * (size_t)std::max(m->nwalls, 1) * 8) &&
          dump(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz) &&
-         dump(v.bnd, 2 * (size_t)m->nf * m->ncells * 8) && dump(v.mem_count, (size_t)m->n_sys * 4) &&
-         (m->last_recycle == 0 ||
-          dump(v.mem, (size_t)m->n_sys * 2 * m->last_recycle * m->nx * m->nz * tsz)) &&
+         dump(v.bnd, 2 * (size_t)m->nf * m->ncells * 8) &&
          dump(v.ax, ((size_t)m->ncells + m->nwalls) * 8);
     const int passes = ctrl[CTRL_PASS];
     fwrite(&passes, sizeof passes, 1, f);
@@ -1565,8 +1581,8 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     if (!m->has_material) return fail(OBTE_ERR_STATE, "material not set");
     FILE* f = fopen(path, "rb");
     if (!f) return fail(OBTE_ERR_ARG, "cannot open %s", path);
-    int hdr[10];
-    if (fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != 0x4f425446 || hdr[1] != m->ncells ||
+    int hdr[9];
+    if (fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != CKPT_MAGIC || hdr[1] != m->ncells ||
         hdr[2] != m->nwalls || hdr[3] != m->n_sys || hdr[4] != m->nx * m->nz) {
         fclose(f);
         return fail(OBTE_ERR_ARG, "checkpoint does not match this mesh / precision");
@@ -1576,8 +1592,7 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     o.precision = hdr[5];
     o.max_outer = hdr[7];
     o.keep_state = hdr[8];
-    o.recycle = hdr[9];
-    const GeomDev v = make_view(m, (char*)workspace, make_layout(m, &o, hdr[6]), hdr[6], hdr[9], 0);
+    const GeomDev v = make_view(m, (char*)workspace, make_layout(m, &o, hdr[6]), hdr[6], 0);
     auto load = [&](void* dptr, size_t bytes) -> bool {
         std::vector<char> buf(bytes);
         if (fread(buf.data(), 1, bytes, f) != bytes) return false;
@@ -1587,8 +1602,7 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     bool ok = load(v.ctrl, CTRL_N * sizeof(int)) && load(v.T_L, (size_t)m->ncells * 8) &&
               load(v.sT, 2 * (size_t)m->ncells * 8) && load(v.Tw, 2 * (size_t)std::max(m->nwalls, 1) * 8) &&
               load(v.U, (size_t)m->n_sys * m->nx * m->nz * tsz) &&
-              load(v.bnd, 2 * (size_t)m->nf * m->ncells * 8) && load(v.mem_count, (size_t)m->n_sys * 4) &&
-              (hdr[9] == 0 || load(v.mem, (size_t)m->n_sys * 2 * hdr[9] * m->nx * m->nz * tsz)) &&
+              load(v.bnd, 2 * (size_t)m->nf * m->ncells * 8) &&
               load(v.ax, ((size_t)m->ncells + m->nwalls) * 8);
     int passes = 0;
     ok = ok && fread(&passes, sizeof passes, 1, f) == 1;
@@ -1599,7 +1613,6 @@ obte_status obte_checkpoint_load(obte_mesh* m, void* workspace, const char* path
     m->last_waves = hdr[6];
     m->last_max_outer = hdr[7];
     m->last_keep = hdr[8];
-    m->last_recycle = hdr[9];
     return OBTE_OK;
 }
 

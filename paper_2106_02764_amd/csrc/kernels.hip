@@ -234,13 +234,13 @@ template <typename T>
 __device__ __forceinline__ gmut_t<T> gmut(T* p) { return (gmut_t<T>)p; }
 
 // Per-wave state of a sweep that keeps its result: the kappa sums in
-// registers, and the solution stored row by row (the sums over systems per
-// cell and per wall are taken afterwards by the reduction kernel).
+// registers, and the solution stored on the solid cells (the sums over
+// systems per cell and per wall are taken afterwards by the reduction kernel).
 template <typename T>
 struct Red {
     int store_T;
     double kacc, kface;
-    gmut_t<T> X;               // this system's solution (null: inactive wave)
+    gmut_t<T> X;               // this system's solution by solid index (null: inactive wave)
     gmut_t<double> Tstore;     // this system's stored state (or null)
 };
 
@@ -259,13 +259,28 @@ struct RowIn {
     T sg[CPL];
     double sb[CPL];     // base source (sigma T_L, or k + D Psi)
     double bx[CPL], by[CPL], bz[CPL];   // inflow boundary values per axis
+    int si[CPL];        // solid index of the cell (sweeps that store), -1 in pores
+    T ui[CPL];          // 3D: the wrap-plane input of the row's plane (used on the first y-row)
+};
+
+// Row results of a storing sweep, kept in registers until a group of rows is
+// stored together.  A wave's global loads and stores share one counter on
+// gfx9, and with both kinds in flight every wait for a prefetched row must
+// drain the whole counter; storing once per group keeps the row prefetch
+// overlapped everywhere else.
+template <typename T, int CPL>
+struct RowOut {
+    T x[CPL];
+    int si[CPL];        // -1: nothing to store
 };
 
 // per-sweep constant views
 template <typename T>
 struct Views {
     gptr_t<uint16_t> fc;
+    gptr_t<int> sidx;
     gptr_t<T> sg;
+    gptr_t<T> u;                       // 3D: the wrap-plane input (nz x nx)
     gptr_t<double> src, bx, by, bz;
     // geometry scalars read once per sweep: the row loop stores to global
     // memory, after which the compiler would reload them from the view
@@ -273,7 +288,7 @@ struct Views {
     double dT;
 };
 
-template <typename T, int CPL, bool D3, bool WITH_B, bool S1>
+template <typename T, int CPL, bool D3, bool WITH_B, bool S1, bool ST>
 __device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, const Views<T>& v, int lane,
                                          int jj, int kk, RowIn<T, CPL>& r) {
     const int nx = v.nx;
@@ -284,8 +299,14 @@ __device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, con
     for (int c = 0; c < CPL; ++c) {
         const int p = lane * CPL + c;
         const bool in = p < nx;
+        // every lane loads (beyond the row: the row's first cell, masked by
+        // the row step), so no load sits in a branch or feeds a select here:
+        // the compiler then counts the loads in flight exactly and waits
+        // only for the row it is about to use
         const int cell = rowbase + (in ? (s.pos[0] ? p : nx - 1 - p) : 0);
-        r.w[c] = in ? (uint32_t)v.fc[cell] : 0u;
+        r.w[c] = (uint32_t)v.fc[cell];
+        if (ST) r.si[c] = v.sidx[cell];
+        if (D3) r.ui[c] = v.u[kk * nx + min(p, nx - 1)];
         r.sg[c] = S1 ? T(1) : v.sg[cell];
         if (WITH_B) {
             r.sb[c] = v.src[cell];
@@ -323,6 +344,7 @@ struct RegIO {
     const T (&u)[CPL];
     T (&xl)[CPL];
     __device__ __forceinline__ T in(int, int c, int) const { return u[c]; }
+    __device__ __forceinline__ gptr_t<T> input() const { return nullptr; }
     __device__ __forceinline__ void out(int, int c, int, T v) { xl[c] = v; }
 };
 template <typename T, int CPL>
@@ -331,10 +353,9 @@ struct GlobIO {
     gmut_t<T> xl;        // nullptr: the last row is not needed
     int nx;
     int active;
-    __device__ __forceinline__ T in(int kk, int c, int lane) const {
-        const int p = lane * CPL + c;
-        return p < nx ? u[kk * nx + p] : T(0);
-    }
+    __device__ __forceinline__ gptr_t<T> input() const { return u; }
+    // the row loads prefetch the input (Views::u); nothing is read here
+    __device__ __forceinline__ T in(int, int, int) const { return T(0); }
     __device__ __forceinline__ void out(int kk, int c, int lane, T v) {
         const int p = lane * CPL + c;
         if (xl && active && p < nx) xl[kk * nx + p] = v;
@@ -346,7 +367,7 @@ template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1
 __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, const Views<T>& vw,
                                          int active, int lane, int adj, int jj, int kk,
                                          const RowIn<T, CPL>& cur, Rows<T, CPL, D3>& rows, IO& io,
-                                         const double (&mb)[3], Red<T>* rd) {
+                                         const double (&mb)[3], Red<T>* rd, RowOut<T, CPL>& ro) {
     constexpr int ND = D3 ? 3 : 2;
     const int nx = vw.nx, ny = vw.ny;
     const T cz = D3 ? s.c[2] : T(0);
@@ -361,7 +382,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int p = lane * CPL + c;
-        const uint32_t w = cur.w[c];
+        const uint32_t w = p < nx ? cur.w[c] : 0u;     // beyond the row: not solid
         const bool sol = active && fc_solid(w);
         const int clx = fc_class(w, s.fin[0]);
         const int cly = fc_class(w, s.fin[1]);
@@ -369,9 +390,11 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         // sigma = 1 everywhere (no multiplier given): rdv is this system's constant
         const T sg = S1 ? T(1) : cur.sg[c];
         const T rdv = S1 ? rdv1 : recip(sg + cdiag);
-        // kk and jj are wave-uniform: the wrap input is read on the first row only
+        // kk and jj are wave-uniform: the wrap input is used on the first row
+        // only (3D: prefetched with every row, so its load is in no branch)
+        const T uin = D3 ? (p < nx ? cur.ui[c] : T(0)) : io.in(kk, c, lane);
         T yin = T(0);
-        if (cly != FC_WALL) yin = (jj == 0) ? io.in(kk, c, lane) : s.c[1] * rows.prev_y(kk, c, lane);
+        if (cly != FC_WALL) yin = (jj == 0) ? uin : s.c[1] * rows.prev_y(kk, c, lane);
         T rhs = yin;
         if (WITH_B) {
             double sd = adj ? s.kw + s.Dml * cur.sb[c] : cur.sb[c];
@@ -420,19 +443,15 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         for (int c = 0; c < CPL; ++c) io.out(kk, c, lane, xrow[c]);
     }
     if (RED && rd->X) {
-        const int iy = s.pos[1] ? jj : ny - 1 - jj;
-        const int iz = D3 ? (s.pos[2] ? kk : vw.nz - 1 - kk) : 0;
-        const int rowbase = nx * (iy + ny * iz);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int p = lane * CPL + c;
-            if (p >= nx) continue;
-            const uint32_t wv = cur.w[c];
+            const uint32_t wv = p < nx ? cur.w[c] : 0u;
             const bool sol = fc_solid(wv);
-            const int cell = rowbase + (s.pos[0] ? p : nx - 1 - p);
-            const T xt = sol ? xrow[c] : T(0);
+            ro.x[c] = xrow[c];
+            ro.si[c] = sol ? cur.si[c] : -1;
             if (sol) {
-                const double xv = (double)xt;
+                const double xv = (double)xrow[c];
                 rd->kacc += xv;
                 if (adj) {
                     // p^T lambda: forward jump inflow = reversed outflow faces
@@ -450,11 +469,25 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
                     if (vw.ga == 1 && jj == ny - 1 && fc_class(wv, s.fout[1]) != FC_WALL)
                         rd->kface += xv + ((!ADD && s.pos[1]) ? vw.dT : 0.0);
                 }
-                if (rd->store_T) rd->Tstore[cell] = xv;
             }
-            rd->X[cell] = ADD ? rd->X[cell] + xt : xt;
         }
     }
+}
+
+// Store a group of rows of a storing sweep (ADD: add to the stored values).
+template <typename T, int CPL, int NR, bool ADD>
+__device__ __forceinline__ void store_rows(Red<T>* rd, const RowOut<T, CPL> (&ro)[NR]) {
+    if (!rd->X) return;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int i = ro[r].si[c];
+            if (i < 0) continue;
+            const T v = ro[r].x[c];
+            rd->X[i] = ADD ? rd->X[i] + v : v;
+            if (rd->store_T) rd->Tstore[i] = (double)v;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +518,9 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     }
     Views<T> vw;
     vw.fc = gview(g.fc);
+    vw.sidx = gview(g.sidx);
     vw.sg = gview(sigma_ptr<T>(g));
+    vw.u = io.input();
     vw.src = gview(srcbase);
     vw.bx = gview(bnd + (size_t)fb[0] * g.ncells);
     vw.by = gview(bnd + (size_t)fb[1] * g.ncells);
@@ -503,38 +538,68 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     const int ny = g.ny;
     if (!D3) {
         // PF2D buffers in rotation: the loads of row jj + PF2D - 1 are issued
-        // before row jj runs (the unrolled rotation keeps every index static)
+        // before row jj runs (the unrolled rotation keeps every index static);
+        // a storing sweep stores each group of PF2D rows after its last row
         RowIn<T, CPL> b[PF2D];
+        // Prefetches are never skipped (past the last row they reload it):
+        // a load inside a branch would leave the compiler unsure how many
+        // loads are in flight at the join, and it would then wait for all.
 #pragma unroll
         for (int r = 0; r < PF2D - 1; ++r)
-            if (r < ny) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, r, 0, b[r]);
+            load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, min(r, ny - 1), 0, b[r]);
         for (int jj = 0; jj < ny; jj += PF2D) {
+            RowOut<T, CPL> ro[PF2D];
+#pragma unroll
+            for (int r = 0; r < PF2D; ++r)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) ro[r].si[c] = -1;
 #pragma unroll
             for (int r = 0; r < PF2D; ++r) {
-                if (jj + r < ny) {
-                    if (jj + r + PF2D - 1 < ny)
-                        load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, jj + r + PF2D - 1, 0, b[(r + PF2D - 1) % PF2D]);
+                // the first row of a group waits for every access in flight
+                // (the stores of the previous group): its own prefetch is
+                // issued after that wait, not before
+                const int rn = min(jj + r + PF2D - 1, ny - 1);
+                if (!(RED && r == 0))
+                    load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, rn, 0, b[(r + PF2D - 1) % PF2D]);
+                if (jj + r < ny)
                     row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, jj + r, 0, b[r], rows, io,
-                                                           mb, rd);
-                }
+                                                           mb, rd, ro[r]);
+                if (RED && r == 0)
+                    load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, rn, 0, b[(r + PF2D - 1) % PF2D]);
             }
+            if (RED) store_rows<T, CPL, PF2D, ADD>(rd, ro);
         }
     } else {
         // 3D: rows (jj, kk) with kk inner; a three-buffer rotation keeps the
-        // inputs two rows ahead (the row order is y-major, z-minor)
+        // inputs two rows ahead (the row order is y-major, z-minor); a storing
+        // sweep stores each group of three rows after its last row
         const int nz = g.nz, nrows = ny * nz;
+        // prefetches are never skipped (past the last row they reload it)
+        auto pre = [&](int r, RowIn<T, CPL>& b) {
+            const int rr = min(r, nrows - 1);
+            load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, rr / nz, rr % nz, b);
+        };
         RowIn<T, CPL> b0, b1, b2;
-        load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, 0, 0, b0);
-        if (nrows > 1) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, 1 / nz, 1 % nz, b1);
+        pre(0, b0);
+        pre(1, b1);
         for (int r = 0; r < nrows; r += 3) {
-            if (r + 2 < nrows) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, (r + 2) / nz, (r + 2) % nz, b2);
-            row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, r / nz, r % nz, b0, rows, io, mb, rd);
-            if (r + 1 >= nrows) break;
-            if (r + 3 < nrows) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, (r + 3) / nz, (r + 3) % nz, b0);
-            row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, (r + 1) / nz, (r + 1) % nz, b1, rows, io, mb, rd);
-            if (r + 2 >= nrows) break;
-            if (r + 4 < nrows) load_row<T, CPL, D3, WITH_B, S1>(g, s, vw, lane, (r + 4) / nz, (r + 4) % nz, b1);
-            row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, (r + 2) / nz, (r + 2) % nz, b2, rows, io, mb, rd);
+            RowOut<T, CPL> ro[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) ro[q].si[c] = -1;
+            pre(r + 2, b2);
+            row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, r / nz, r % nz, b0, rows, io, mb, rd,
+                                                   ro[0]);
+            pre(r + 3, b0);
+            if (r + 1 < nrows)
+                row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, (r + 1) / nz, (r + 1) % nz, b1,
+                                                       rows, io, mb, rd, ro[1]);
+            pre(r + 4, b1);
+            if (r + 2 < nrows)
+                row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, (r + 2) / nz, (r + 2) % nz, b2,
+                                                       rows, io, mb, rd, ro[2]);
+            if (RED) store_rows<T, CPL, 3, ADD>(rd, ro);
         }
     }
 }
@@ -574,82 +639,6 @@ __device__ __forceinline__ double vdot(const T (&a)[NZ][CPL], const T (&b)[NZ][C
     _Pragma("unroll") for (int k = 0; k < NZ; ++k) \
     _Pragma("unroll") for (int c = 0; c < CPL; ++c) { body; }
 
-// ---------------------------------------------------------------------------
-// Recycled Krylov memory of one system: R pairs (v_i, w_i = (I - G) v_i) with
-// the w_i orthonormal.  The wrap matrix I - G is fixed during a solve, so the
-// pairs gathered in earlier passes solve most of a later pass's residual by a
-// projection.
-// ---------------------------------------------------------------------------
-template <typename T, int CPL, int NZ>
-struct Mem {
-    T* base;     // R pairs, each 2 * nwrap values (v then w)
-    int* count;  // stored pairs (read at the start, written back at the end)
-    int n;       // wave-uniform copy of *count
-    int R, nwrap, nx, nz, lane;
-    // every lane reads and writes only its own entries, so no cross-lane
-    // ordering is needed; the count lives in a register meanwhile
-    __device__ void begin() { n = R > 0 ? min(*count, R) : 0; }
-    __device__ void end() const { if (lane == 0 && R > 0) *count = n; }
-    __device__ T* v(int i) const { return base + (size_t)i * 2 * nwrap; }
-    __device__ T* w(int i) const { return base + (size_t)i * 2 * nwrap + nwrap; }
-    __device__ void load(const T* src, T (&x)[NZ][CPL]) const {
-        VLOOP({
-            const int p = lane * CPL + c;
-            x[k][c] = (k < nz && p < nx) ? src[k * nx + p] : T(0);
-        });
-    }
-    __device__ void store(T* dst, const T (&x)[NZ][CPL]) const {
-        VLOOP({
-            const int p = lane * CPL + c;
-            if (k < nz && p < nx) dst[k * nx + p] = x[k][c];
-        });
-    }
-    // project r onto span(w): u += V c, r -= W c
-    __device__ void project(T (&u)[NZ][CPL], T (&r)[NZ][CPL]) const {
-        for (int i = 0; i < n; ++i) {
-            T wi[NZ][CPL], vi[NZ][CPL];
-            load(w(i), wi);
-            const double ci = vdot<T, CPL, NZ>(wi, r);
-            load(v(i), vi);
-            VLOOP({ r[k][c] -= (T)ci * wi[k][c]; u[k][c] += (T)ci * vi[k][c]; });
-        }
-    }
-    // insert the pair (x, y = (I - G) x), orthonormalising y against the memory
-    __device__ void insert(const T (&x)[NZ][CPL], const T (&y)[NZ][CPL]) {
-        if (R <= 0) return;
-        T xv[NZ][CPL], yv[NZ][CPL];
-        VLOOP({ xv[k][c] = x[k][c]; yv[k][c] = y[k][c]; });
-        const double n0 = sqrt(vdot<T, CPL, NZ>(yv, yv));
-        if (!(n0 > 0.0)) return;
-        for (int i = 0; i < n; ++i) {
-            T wi[NZ][CPL], vi[NZ][CPL];
-            load(w(i), wi);
-            const double h = vdot<T, CPL, NZ>(wi, yv);
-            load(v(i), vi);
-            VLOOP({ yv[k][c] -= (T)h * wi[k][c]; xv[k][c] -= (T)h * vi[k][c]; });
-        }
-        const double nn = sqrt(vdot<T, CPL, NZ>(yv, yv));
-        if (!(nn > 1e-6 * n0)) return;         // (numerically) dependent
-        int slot = n;
-        if (n >= R) {
-            // full: drop the oldest pair (the others stay orthonormal)
-            for (int i = 1; i < R; ++i) {
-                T t[NZ][CPL];
-                load(v(i), t);
-                store(v(i - 1), t);
-                load(w(i), t);
-                store(w(i - 1), t);
-            }
-            slot = R - 1;
-        }
-        const T inv = (T)(1.0 / nn);
-        VLOOP({ xv[k][c] *= inv; yv[k][c] *= inv; });
-        store(v(slot), xv);
-        store(w(slot), yv);
-        if (n < R) ++n;
-    }
-};
-
 // Per-system results of a pass: kappa partials and counters.
 template <typename T>
 __device__ __forceinline__ Red<T> make_red(const GeomDev& g, const SysC<T>& s, int active, const PassParams& pp) {
@@ -657,8 +646,8 @@ __device__ __forceinline__ Red<T> make_red(const GeomDev& g, const SysC<T>& s, i
     rd.store_T = pp.store_T;
     rd.kacc = 0.0;
     rd.kface = 0.0;
-    rd.X = active ? gmut(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.ncells) : nullptr;
-    rd.Tstore = (active && g.Tstore) ? gmut(g.Tstore + (size_t)s.sys * g.ncells) : nullptr;
+    rd.X = active ? gmut(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.nsolid) : nullptr;
+    rd.Tstore = (active && g.Tstore) ? gmut(g.Tstore + (size_t)s.sys * g.nsolid) : nullptr;
     return rd;
 }
 
@@ -688,7 +677,7 @@ __device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s
 // direction, so their table and source loads touch the same lines).  Phase
 // A: each wave sweeps with the sources b and the previous wrap inflow u0 and
 // stores its solution.  Phase B: each wave corrects its wrap inflow
-// (recycled projection, then BiCGSTAB on the wrap row).  Phase C: a wave that
+// (BiCGSTAB on the wrap row).  Phase C: a wave that
 // changed u sweeps the source P (u - u0) and adds the (linear) response to
 // its stored solution.
 // ---------------------------------------------------------------------------
@@ -713,14 +702,6 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     const double* bnd = g.bnd + ((size_t)(adj ? 2 : 0) + buf_in) * g.nf * g.ncells;
     const size_t half = adj ? (size_t)g.n_sys : 0;
     T* Uall = reinterpret_cast<T*>(g.U) + half * g.nwrap;
-    Mem<T, CPL, NZ> mem;
-    mem.R = g.mem_R;
-    mem.nwrap = g.nwrap;
-    mem.nx = g.nx;
-    mem.nz = g.nz;
-    mem.lane = lane;
-    mem.base = reinterpret_cast<T*>(g.mem) + (half + s.sys) * (size_t)2 * g.mem_R * g.nwrap;
-    mem.count = g.mem_count + half + s.sys;
 
     T u[NZ][CPL], xl[NZ][CPL], mk[NZ][CPL];
     wrap_mask<T, CPL, NZ>(g, s, active, lane, mk);
@@ -749,12 +730,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
         // a reduction by inner_rtol of the residual the pass started from
         const double thr = fmax(pp.inner_tol * scale, pp.inner_rtol * rn);
         const double thr_final = pp.inner_tol * scale;
-        mem.begin();
-        if (rn > thr_final && scale > 0.0) {
-            need = 1;
-            mem.project(du, r);
-            rn = sqrt(vdot<T, CPL, NZ>(r, r));
-        }
+        if (rn > thr_final && scale > 0.0) need = 1;
         if (rn > thr && scale > 0.0) {
             // BiCGSTAB for the remaining correction: (I - G) e = r.  A capped
             // BiCGSTAB is not monotone, so the iterate with the smallest
@@ -779,7 +755,6 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 }
                 ++n_sw;
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
-                mem.insert(p, v);
                 const double rv = vdot<T, CPL, NZ>(rh, v);
                 if (!isfinite(rv)) break;
                 if (!(fabs(rv) > 1e-30 * fabs(rho))) {
@@ -804,7 +779,6 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 }
                 ++n_sw;
                 VLOOP(t[k][c] = sv[k][c] - mk[k][c] * xl[k][c]);
-                mem.insert(sv, t);
                 const double tt = vdot<T, CPL, NZ>(t, t);
                 omega = tt > 0.0 ? vdot<T, CPL, NZ>(t, sv) / tt : 0.0;
                 VLOOP(e[k][c] += (T)alpha * p[k][c] + (T)omega * sv[k][c]);
@@ -818,7 +792,6 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
             rn = best;
             VLOOP(du[k][c] += eb[k][c]);
         }
-        mem.end();
         if (lane == 0) g.wres[s.sys] = scale > 0.0 ? rn / scale : 0.0;
         if (need) {
             VLOOP({
@@ -1030,9 +1003,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
 // T_w = sum ReLu(S.n)/sum ReLu(S.n) x at the wall cell.  Adjoint: Psi = sigma
 // sum lambda and Phi_f = sum of c_a lambda over the directions entering
 // through f (the transpose of the wall coupling).  A block owns a strip of 64
-// cells and its RQ waves split the systems in fixed chunks; a wall face reads
-// only its own cell's values, so the walls of the strip's cells are summed
-// from the same loads.  Every sum is combined over the chunks in order.
+// solid cells (consecutive solid indices) and its RQ waves split the systems
+// in fixed chunks; a wall face reads only its own cell's values, so the walls
+// of the strip's cells are summed from the same loads.  Every sum is combined
+// over the chunks in order.  Pore entries of the outputs are never written:
+// they are set to 0 once per solve (k_prep_sigma) and stay 0.
 // ---------------------------------------------------------------------------
 constexpr int RQ = 16;      // waves per reduction block: system chunks of one 64-cell strip
 
@@ -1045,20 +1020,22 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
     const int pass = g.ctrl[CTRL_PASS];
     const int out = (pass + 1) & 1;
     const int adj = pp.adjoint;
-    const int nc = g.ncells, nf = g.nf, ns = g.n_sys, nd = g.n_dir;
+    const int nc = g.ncells, nf = g.nf, ns = g.n_sys, nd = g.n_dir, nsol = g.nsolid;
+    if ((int)blockIdx.x * 64 >= nsol) return;          // block-uniform
     const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
     const gptr_t<double> D = gview(g.Dw);
     const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
-    const int cell = blockIdx.x * 64 + cl;
+    const int j = blockIdx.x * 64 + cl;                 // solid index of this lane
+    const bool in = j < nsol;
+    const int cell = in ? g.scell[j] : -1;
     const int per = (ns + RQ - 1) / RQ;
     const int i0 = q * per, i1 = min(ns, i0 + per);
     // wall faces of this lane's cell (bit f), and of the strip: the same in
     // every wave of the block
     int wm = 0;
-    if (cell < nc) {
+    if (in) {
         const uint16_t w = g.fc[cell];
-        if (fc_solid(w))
-            for (int f = 0; f < nf; ++f) wm |= (fc_class(w, f) == FC_WALL ? 1 : 0) << f;
+        for (int f = 0; f < nf; ++f) wm |= (fc_class(w, f) == FC_WALL ? 1 : 0) << f;
     }
     int wany = wm;
 #pragma unroll
@@ -1067,13 +1044,13 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
     double aw[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (!wany) {
-        if (cell < nc) {
+        if (in) {
             int i = i0;
             if (adj) {
                 for (; i + 7 < i1; i += 8) {
                     double xv[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nc + cell];
+                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nsol + j];
                     a0 += xv[0];
                     a1 += xv[1];
                     a2 += xv[2];
@@ -1084,17 +1061,17 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
                     a3 += xv[7];
                 }
                 for (; i + 3 < i1; i += 4) {
-                    a0 += (double)X[(size_t)i * nc + cell];
-                    a1 += (double)X[(size_t)(i + 1) * nc + cell];
-                    a2 += (double)X[(size_t)(i + 2) * nc + cell];
-                    a3 += (double)X[(size_t)(i + 3) * nc + cell];
+                    a0 += (double)X[(size_t)i * nsol + j];
+                    a1 += (double)X[(size_t)(i + 1) * nsol + j];
+                    a2 += (double)X[(size_t)(i + 2) * nsol + j];
+                    a3 += (double)X[(size_t)(i + 3) * nsol + j];
                 }
-                for (; i < i1; ++i) a0 += (double)X[(size_t)i * nc + cell];
+                for (; i < i1; ++i) a0 += (double)X[(size_t)i * nsol + j];
             } else {
                 for (; i + 7 < i1; i += 8) {
                     double xv[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nc + cell];
+                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nsol + j];
                     a0 += D[i] * xv[0];
                     a1 += D[i + 1] * xv[1];
                     a2 += D[i + 2] * xv[2];
@@ -1105,19 +1082,18 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
                     a3 += D[i + 7] * xv[7];
                 }
                 for (; i + 3 < i1; i += 4) {
-                    a0 += D[i] * (double)X[(size_t)i * nc + cell];
-                    a1 += D[i + 1] * (double)X[(size_t)(i + 1) * nc + cell];
-                    a2 += D[i + 2] * (double)X[(size_t)(i + 2) * nc + cell];
-                    a3 += D[i + 3] * (double)X[(size_t)(i + 3) * nc + cell];
+                    a0 += D[i] * (double)X[(size_t)i * nsol + j];
+                    a1 += D[i + 1] * (double)X[(size_t)(i + 1) * nsol + j];
+                    a2 += D[i + 2] * (double)X[(size_t)(i + 2) * nsol + j];
+                    a3 += D[i + 3] * (double)X[(size_t)(i + 3) * nsol + j];
                 }
-                for (; i < i1; ++i) a0 += D[i] * (double)X[(size_t)i * nc + cell];
+                for (; i < i1; ++i) a0 += D[i] * (double)X[(size_t)i * nsol + j];
             }
         }
     } else {
         // the same cell sums in the same order, and the wall faces' sums with
         // the weights of 64 systems at a time staged in the wave's LDS rows
-        const bool in = cell < nc;
-        const int cs = in ? cell : nc - 1;          // in-range loads, dropped below
+        const int js = in ? j : nsol - 1;           // in-range loads, dropped below
         for (int ib = i0; ib < i1; ib += 64) {
             // lane l: the weights of system ib + l at the strip's wall faces
             // (forward: ReLu(S.n) / sum; adjoint: c_a of the directions
@@ -1153,7 +1129,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
 #pragma unroll
                 for (int u = 0; u < 8; ++u) dv[u] = D[i + u];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nc + cs];
+                for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nsol + js];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     xv[u] = in ? xv[u] : 0.0;
@@ -1181,7 +1157,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
 #pragma unroll
                 for (int u = 0; u < 4; ++u) dv[u] = D[i + u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) xv[u] = (double)X[(size_t)(i + u) * nc + cs];
+                for (int u = 0; u < 4; ++u) xv[u] = (double)X[(size_t)(i + u) * nsol + js];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     xv[u] = in ? xv[u] : 0.0;
@@ -1201,7 +1177,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
             }
             for (; u0 < nb; ++u0) {
                 const int i = ib + u0;
-                const double xr = (double)X[(size_t)i * nc + cs];
+                const double xr = (double)X[(size_t)i * nsol + js];
                 const double x = in ? xr : 0.0;
                 a0 += adj ? x : D[i] * x;
 #pragma unroll
@@ -1212,22 +1188,20 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
             }
         }
     }
-    if (cell < nc) acc = (a0 + a1) + (a2 + a3);
+    if (in) acc = (a0 + a1) + (a2 + a3);
     part[q][cl] = acc;
     __syncthreads();
-    if (q == 0 && cell < nc) {
+    if (q == 0 && in) {
         double tot = part[0][cl];
 #pragma unroll
-        for (int j = 1; j < RQ; ++j) tot += part[j][cl];
-        const bool sol = fc_solid(g.fc[cell]);
-        const double xv = sol ? tot : 0.0;
-        if (!adj) g.T_L[cell] = xv;
+        for (int u = 1; u < RQ; ++u) tot += part[u][cl];
+        if (!adj) g.T_L[cell] = tot;
         if (g.aa_m > 0) {
-            g.ag[cell] = xv;               // the mixing step writes the next inputs
+            g.ag[cell] = tot;              // the mixing step writes the next inputs
         } else {
-            g.ax[cell] = xv;
-            if (adj) g.lam_psi[(size_t)out * nc + cell] = sol ? g.sigma[cell] * tot : 0.0;
-            else g.sT[(size_t)out * nc + cell] = sol ? g.sigma[cell] * tot : 0.0;
+            g.ax[cell] = tot;
+            if (adj) g.lam_psi[(size_t)out * nc + cell] = g.sigma[cell] * tot;
+            else g.sT[(size_t)out * nc + cell] = g.sigma[cell] * tot;
         }
     }
     if (!wany) return;                     // block-uniform
@@ -1241,7 +1215,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
         if (q == 0 && ((wm >> f) & 1)) {
             double a = part[0][cl];
 #pragma unroll
-            for (int j = 1; j < RQ; ++j) a += part[j][cl];
+            for (int u = 1; u < RQ; ++u) a += part[u][cl];
             const int wi = g.wall_idx[cell * nf + f];
             if (g.aa_m > 0) {
                 g.ag[nc + wi] = a;
@@ -1918,14 +1892,32 @@ __global__ void k_apply(const GeomDev* __restrict__ gp, const double* __restrict
 }
 
 
-// sigma per cell (1 where not given or in pores) and its float copy.
+// sigma per cell (1 where not given or in pores) and its float copy; the
+// pore entries of the per-cell pass arrays, which the reduction and the
+// mixing never write, are set to 0 (the solid entries are left as they are,
+// so a resumed solve keeps its state).
 __global__ void k_prep_sigma(const GeomDev* __restrict__ gp, const double* __restrict__ sig_in) {
     const GeomDev& g = *gp;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.ncells; c += gridDim.x * blockDim.x) {
+    const int nc = g.ncells;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        const bool sol = fc_solid(g.fc[c]);
         double v = 1.0;
-        if (sig_in && fc_solid(g.fc[c])) v = sig_in[c];
+        if (sig_in && sol) v = sig_in[c];
         g.sigma[c] = v;
         g.sigma_f[c] = (float)v;
+        if (!sol) {
+            g.T_L[c] = 0.0;
+            g.sT[c] = 0.0;
+            g.sT[nc + c] = 0.0;
+            g.lam_psi[c] = 0.0;
+            g.lam_psi[nc + c] = 0.0;
+            g.ax[c] = 0.0;
+            if (g.aa_m > 0) {
+                g.ag[c] = 0.0;
+                g.axp[c] = 0.0;
+                g.afp[c] = 0.0;
+            }
+        }
     }
 }
 
@@ -1936,15 +1928,16 @@ __global__ void __launch_bounds__(256) k_flux(const GeomDev* __restrict__ gp, do
     const GeomDev& g = *gp;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncells) return;
+    const int i = g.sidx[c];
     const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
     double j[3] = {0.0, 0.0, 0.0};
-    for (int sys = 0; sys < g.n_sys; ++sys) {
-        const double x = (double)X[(size_t)sys * g.ncells + c];
+    if (i >= 0)
+        for (int sys = 0; sys < g.n_sys; ++sys) {
+            const double x = (double)X[(size_t)sys * g.nsolid + i];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) j[a] += g.S[sys * 3 + a] * x;
-    }
-    const bool sol = fc_solid(g.fc[c]);
-    for (int a = 0; a < g.ndim; ++a) J_out[(size_t)c * g.ndim + a] = sol ? j[a] : 0.0;
+            for (int a = 0; a < 3; ++a) j[a] += g.S[sys * 3 + a] * x;
+        }
+    for (int a = 0; a < g.ndim; ++a) J_out[(size_t)c * g.ndim + a] = j[a];
 }
 
 // Adjoint gradient of one geometry: -sum_ml lambda_iml (T_iml - T_L,i) from
@@ -1954,14 +1947,88 @@ __global__ void __launch_bounds__(256) k_grad(const GeomDev* __restrict__ gp, do
     const GeomDev& g = *gp;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncells) return;
+    const int i = g.sidx[c];
     const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
     const double tl = g.T_L[c];
     double acc = 0.0;
-    for (int sys = 0; sys < g.n_sys; ++sys) {
-        const size_t e = (size_t)sys * g.ncells + c;
-        acc += (double)X[e] * (g.Tstore[e] - tl);
+    if (i >= 0)
+        for (int sys = 0; sys < g.n_sys; ++sys) {
+            const size_t e = (size_t)sys * g.nsolid + i;
+            acc += (double)X[e] * (g.Tstore[e] - tl);
+        }
+    grad_out[c] = i >= 0 ? -acc : 0.0;
+}
+
+// Energy balance of the last pass (paper, section Model: T_L is fixed by
+// energy conservation, sum_ml alpha_ml sigma_i (T_iml - T_L,i) = 0 at the
+// fixed point).  With alpha = D sum alpha the residual of cell i is
+// sum alpha |sigma_i sum_ml D_ml T_iml - sigma_i T_L,i^in|, measured against
+// the mean weighted magnitude sum alpha sum_i sum_ml D_ml |T_iml| / N_solid;
+// sum alpha cancels.  One block per 64 solid cells writes its maximum and its
+// sum; k_energy_finish combines them in a fixed order into fscal[4].
+template <typename T>
+__global__ void __launch_bounds__(256) k_energy(const GeomDev* __restrict__ gp) {
+    __shared__ double pm[4][64], ps[4][64];
+    const GeomDev& g = *gp;
+    const int nsol = g.nsolid, ns = g.n_sys;
+    const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
+    const int j = blockIdx.x * 64 + cl;
+    const bool in = j < nsol;
+    const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
+    const gptr_t<double> D = gview(g.Dw);
+    double t = 0.0, a = 0.0;
+    if (in)
+        for (int i = q; i < ns; i += 4) {
+            const double x = (double)X[(size_t)i * nsol + j];
+            t += D[i] * x;
+            a += D[i] * fabs(x);
+        }
+    pm[q][cl] = t;
+    ps[q][cl] = a;
+    __syncthreads();
+    if (q == 0) {
+        double tl = 0.0, ab = 0.0, r = 0.0;
+        if (in) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                tl += pm[u][cl];
+                ab += ps[u][cl];
+            }
+            const int cell = g.scell[j];
+            const int buf = (g.ctrl[CTRL_PASS] + 1) & 1;     // the last pass's input
+            r = fabs(g.sigma[cell] * tl - g.sT[(size_t)buf * g.ncells + cell]);
+        }
+        for (int m = 32; m >= 1; m >>= 1) {
+            r = fmax(r, shfl_xor(r, m));
+            ab += shfl_xor(ab, m);
+        }
+        if (cl == 0) {
+            g.fx[2 * blockIdx.x] = r;
+            g.fx[2 * blockIdx.x + 1] = ab;
+        }
     }
-    grad_out[c] = fc_solid(g.fc[c]) ? -acc : 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_energy_finish(const GeomDev* __restrict__ gp, int nblocks) {
+    __shared__ double red[40];
+    const GeomDev& g = *gp;
+    double r = 0.0, ab = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        r = fmax(r, g.fx[2 * b]);
+        ab += g.fx[2 * b + 1];
+    }
+    for (int m = 32; m >= 1; m >>= 1) r = fmax(r, shfl_xor(r, m));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = r;
+    __syncthreads();
+    double rm = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) rm = fmax(rm, red[w]);
+    __syncthreads();
+    ab = block_sum(ab, red);
+    if (threadIdx.x == 0) {
+        const double mean = g.nsolid > 0 ? ab / (double)g.nsolid : 0.0;
+        g.fscal[4] = mean > 0.0 ? rm / mean : 0.0;
+    }
 }
 
 // Lattice temperature of one geometry with the solid-cell mean removed.
@@ -2088,10 +2155,9 @@ hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, c
     }
 }
 
-hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells,
-                              int max_walls, PassParams pp, hipStream_t st) {
-    (void)max_walls;
-    int blocks = (max_cells + 63) / 64;
+hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_solid,
+                              PassParams pp, hipStream_t st) {
+    int blocks = (max_solid + 63) / 64;
     if (blocks < 1) blocks = 1;
     (void)hipGetLastError();
     if (precision == 1) hipLaunchKernelGGL(k_reduce_pass<float>, dim3(blocks, n_geoms), dim3(64 * RQ), 0, st, geoms_dev, pp);
@@ -2221,6 +2287,15 @@ hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, cons
     else
         hipLaunchKernelGGL(k_apply<float>, grid, dim3(256), 0, st, g_dev, sigma, sys_ids, n_sys,
                            (const float*)x, (float*)y, transpose);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const GeomDev* geom_dev, int precision, int nsolid, hipStream_t st) {
+    const int blocks = nsolid > 0 ? (nsolid + 63) / 64 : 1;
+    (void)hipGetLastError();
+    if (precision == 1) hipLaunchKernelGGL(k_energy<float>, dim3(blocks), dim3(256), 0, st, geom_dev);
+    else hipLaunchKernelGGL(k_energy<double>, dim3(blocks), dim3(256), 0, st, geom_dev);
+    hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(256), 0, st, geom_dev, blocks);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ constexpr int KRY3_VECS = 11;
 // the per-solve workspace carve (caller-owned).
 struct GeomDev {
     int nx, ny, nz, ndim, nf, ncells, nwalls, nwrap;
+    int nsolid;                  // solid cells: the length of one system's stored solution
     int periodic[3];
     int grad_axis;
     double h[3], L[3], dT;
@@ -29,6 +30,8 @@ struct GeomDev {
     int n_perp;                  // ncells / n[grad_axis]
     // ---- static tables
     const uint16_t* fc;          // ncells
+    const int* sidx;             // ncells: solid index of the cell (cells in order), -1 in pores
+    const int* scell;            // nsolid: cell of each solid index
     const int* wall_cell;        // nwalls
     const int* wall_face;        // nwalls: face index 2a+side of the owning cell
     const int* wall_idx;         // ncells * nf: wall index of (cell, face), -1 if not a wall
@@ -46,8 +49,8 @@ struct GeomDev {
     double* T_L;                 // ncells: latest lattice temperature
     void* U;                     // n_sys * nwrap (compute precision): wrap inflow vectors
     void* kry;                   // 3D: n_sys * 11 * nwrap (compute precision): wrap-plane Krylov vectors
-    void* X;                     // n_sys * ncells (compute precision): each system's solution of
-                                 // the pass (forward T, adjoint lambda), 0 in pores
+    void* X;                     // n_sys * nsolid (compute precision): each system's solution of
+                                 // the pass (forward T, adjoint lambda) on the solid cells
     double* ksys;                // n_sys: kappa_cc contribution of each system
     double* kfsys;               // n_sys: kappa_face contribution
     long long* iters;            // n_sys: accumulated BiCGSTAB iterations
@@ -56,16 +59,14 @@ struct GeomDev {
     double* hist_face;           // max_outer
     int* ctrl;                   // CTRL_N ints
     double* fx;                  // Fourier CG vectors: 4 * ncells
-    double* fscal;               // Fourier scalars: [0] kappa_F, [1] iterations, [2] residual
-    double* Tstore;              // n_sys * ncells (adjoint forward state) or null
+    double* fscal;               // scalars: [0] kappa_F, [1] CG iterations, [2] CG residual,
+                                 // [3] mixing error estimate, [4] energy residual of the last pass
+    double* Tstore;              // n_sys * nsolid (adjoint forward state) or null
     double* lam_psi;             // adjoint: 2 * ncells (double buffered Psi)
     double* lam_phi;             // adjoint: 2 * nwalls (double buffered Phi)
     double* gradient;            // adjoint: ncells
     double* bnd;                 // 4 * nf * ncells: inflow boundary value per (face, cell);
                                  // forward buffers 0/1, adjoint buffers 2/3 (double buffered)
-    void* mem;                   // 2 * n_sys * 2 * mem_R * nwrap: recycled Krylov pairs
-    int* mem_count;              // 2 * n_sys
-    int mem_R;                   // pairs kept per system
     double* wres;                // n_sys: relative wrap-row residual after this pass's solve
     double* wres_hist;           // max_outer: max over systems per pass
     // ---- the outer fixed point x = (cell field, wall values), n_aa = ncells + nwalls:
@@ -126,8 +127,14 @@ hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, int max_
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
                              const Item* items_dev, int n_items, int waves, PassParams pp,
                              size_t lds_bytes, hipStream_t st);
-hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells,
-                              int max_walls, PassParams pp, hipStream_t st);
+hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_solid,
+                              PassParams pp, hipStream_t st);
+// Energy balance of the last pass of one geometry (forward solve):
+// max_i |sigma_i T_L,i - sigma_i T_L^in_i| / (sum_i sum_ml D_ml |T_iml| / N_solid) into
+// fscal[4], with T_L = sum_ml D_ml T_iml of the stored solutions.  Scratch:
+// energy_scratch_doubles(nsolid) doubles in the Fourier CG region.
+constexpr size_t energy_scratch_doubles(size_t nsolid) { return 2 * ((nsolid + 63) / 64); }
+hipError_t launch_energy(const GeomDev* geom_dev, int precision, int nsolid, hipStream_t st);
 // Anderson mixing: per-block partials (up to 256 blocks of 256 threads per
 // geometry, 2 * AA_MAX + 3 sums each), then the combination.
 constexpr size_t aa_partial_doubles() { return 256 * (2 * AA_MAX + 3); }

@@ -48,7 +48,7 @@ class obte_solve_opts(C.Structure):
                 ("inner_tol", C.c_double), ("max_inner", C.c_int), ("init", C.c_int),
                 ("only_fourier", C.c_int), ("passes_per_graph", C.c_int),
                 ("waves_per_group", C.c_int), ("fourier_tol", C.c_double),
-                ("max_fourier", C.c_int), ("keep_state", C.c_int), ("recycle", C.c_int),
+                ("max_fourier", C.c_int), ("keep_state", C.c_int),
                 ("lag_wrap", C.c_int), ("inner_rtol", C.c_double), ("wrap_tol", C.c_double),
                 ("timing", C.c_int), ("stop_rule", C.c_int), ("accel", C.c_int)]
 
@@ -59,7 +59,7 @@ class obte_stats(C.Structure):
                 ("kappa_fourier", C.c_double), ("last_rel_change", C.c_double),
                 ("wrap_residual", C.c_double), ("status", C.c_int),
                 ("sweep_launches", C.c_int), ("sweep_ms", C.c_double), ("reduce_ms", C.c_double),
-                ("fourier_ms", C.c_double)]
+                ("fourier_ms", C.c_double), ("energy_residual", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -79,6 +79,7 @@ EXPORTS = {
                                    C.POINTER(C.c_double), C.POINTER(obte_stats)]),
     "obte_kappa": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "obte_kappa_modes": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "obte_system_counts": (C.c_int, [C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
     "obte_adjoint": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.c_void_p, C.c_void_p,
                                C.c_size_t, C.c_void_p, C.c_void_p, C.POINTER(obte_stats)]),
     "obte_upwind_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
@@ -194,6 +195,15 @@ def obte_kappa_modes(mesh):
     out = np.zeros(max(n, 0))
     _check(lib().obte_kappa_modes(mesh, out.ctypes.data_as(C.POINTER(C.c_double))))
     return out
+
+
+def obte_system_counts(mesh):
+    n = lib().obte_mesh_n_systems(mesh)
+    its = np.zeros(max(n, 0), np.int64)
+    sws = np.zeros(max(n, 0), np.int64)
+    P = C.POINTER(C.c_longlong)
+    _check(lib().obte_system_counts(mesh, its.ctypes.data_as(P), sws.ctypes.data_as(P)))
+    return its, sws
 
 
 def obte_workspace_size(mesh, opts):

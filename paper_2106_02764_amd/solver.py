@@ -27,6 +27,8 @@ class Solver:
         self.n_dir = self.n_systems // self.n_mfp
         self.workspace = None
         self.last_stats = None
+        self._sigma = None
+        self.solve_count = 0      # completed solves on this mesh (state checks of KappaEff)
         # a stream of our own (default priority) so the outer loop can be
         # captured into HIP graphs; torch's legacy default stream cannot
         self.stream = torch.cuda.Stream(device=self.device) if self.device.type == "cuda" else None
@@ -65,6 +67,7 @@ class Solver:
         J = torch.empty(self.n_cells * self.ndim, dtype=torch.float64, device=self.device) if want_J else None
         self._sigma = self.sigma_tensor(sigma)
         s = self._stream(stream)
+        self.solve_count += 1
         st = _o.obte_solve(self.mesh, opts, self._sigma, ws, stream=s, T_L=T_L, J=J)
         torch.cuda.current_stream(self.device).wait_stream(s)
         self.last_stats = st
@@ -77,6 +80,10 @@ class Solver:
 
     def kappa(self):
         return _o.obte_kappa(self.mesh, self.n_mfp)
+
+    def system_counts(self):
+        """Per-system (inner iterations, sweeps) of the last solve."""
+        return _o.obte_system_counts(self.mesh)
 
     def kappa_modes(self):
         """Mode-resolved conductivity of the last solve (mode table only)."""
@@ -119,20 +126,35 @@ class Solver:
 
 
 class KappaEff(torch.autograd.Function):
-    """kappa_eff(sigma) with the hand-written adjoint as its backward."""
+    """kappa_eff(sigma) with the hand-written adjoint as its backward.
+
+    The adjoint reads the converged forward state the solver keeps in its
+    workspace.  forward() solves with its own copy of sigma and records the
+    solver's solve count; when another solve ran on the same solver before
+    backward() (another sigma, or this one changed in place), backward()
+    first re-runs this graph's forward solve from the saved copy, so the
+    gradient always belongs to the sigma of its own graph."""
 
     @staticmethod
     def forward(ctx, sigma, solver, opts):
         o = _o.default_opts(**{f: getattr(opts, f) for f, _ in opts._fields_})
         o.keep_state = 1
-        out = solver.solve(o, sigma=sigma.detach(), want_T_L=False)
+        sig = solver.sigma_tensor(sigma.detach()).clone()
+        out = solver.solve(o, sigma=sig, want_T_L=False)
         ctx.solver = solver
         ctx.opts = o
+        ctx.sigma = solver._sigma
+        ctx.count = solver.solve_count
         return torch.tensor(out["kappa"], dtype=torch.float64, device=sigma.device)
 
     @staticmethod
     def backward(ctx, g):
-        grad, _ = ctx.solver.adjoint(ctx.opts)
+        s = ctx.solver
+        if s.solve_count != ctx.count or s._sigma is not ctx.sigma:
+            s.solve(ctx.opts, sigma=ctx.sigma, want_T_L=False)
+            s._sigma = ctx.sigma
+            ctx.count = s.solve_count
+        grad, _ = s.adjoint(ctx.opts)
         return g * grad, None, None
 
 

@@ -71,7 +71,7 @@ def test_replica_adjoint_vs_oracle(P):
     grad = grad.cpu().numpy()
     ref = np.asarray(g["grad"])
     assert st["status"] == 0
-    assert np.linalg.norm(grad - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert np.linalg.norm(grad - ref) <= 1e-10 * np.linalg.norm(ref)
     assert np.all(grad[w.solid.ravel() == 0] == 0)
 
 

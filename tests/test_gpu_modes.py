@@ -9,6 +9,7 @@ import pytest
 from inputs import gen
 from oracle.bte import Problem, source_iteration
 from oracle.modes import kappa_modes
+from tests._lib import on_node_modes
 from tests.gpu_common import gpu_solve, oracle_full, rel, require_gpu
 from tests.test_gpu_parity import ragged_porous, small3d
 
@@ -27,7 +28,7 @@ def test_on_node_modes_match_kernel_path(P):
     the identity, so kappa matches the kappa_m path and kappa_mu is the
     per-system kappa (summed over directions: the per-MFP kappa)."""
     w0 = gen.small_2d(12, 10, solid=gen.square_block_mask(12, 10, 3, 7), n_dir=8, n_mfp=3)
-    wn = gen.with_modes(w0, 0, 0, on_node=True)
+    wn = on_node_modes(w0)
     r0 = gpu_solve(P, w0, **TIGHT)
     rn = gpu_solve(P, wn, **TIGHT)
     assert r0["status"] == 0 and rn["status"] == 0
@@ -41,7 +42,7 @@ def test_on_node_modes_match_kernel_path(P):
                        rtol=1e-10, atol=1e-12 * abs(r0["kappa"]))
     prob = Problem(wn)
     ref = source_iteration(prob, tol=1e-13)
-    assert np.max(np.abs(km - kappa_modes(prob, ref["T"]))) <= 1e-9 * abs(ref["kappa_cc"])
+    assert np.max(np.abs(km - kappa_modes(prob, ref["T"]))) <= 1e-10 * abs(ref["kappa_cc"])
 
 
 CASES = {
@@ -62,7 +63,7 @@ CASES = {
 def oracle_case(name):
     w = CASES[name]()
     prob = Problem(w)
-    return w, prob, source_iteration(prob, tol=1e-13, max_passes=20000)
+    return w, prob, source_iteration(prob, tol=1e-14, max_passes=40000)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -72,16 +73,18 @@ def test_modes_vs_oracle(P, name, accel, lag):
     re-centred pass map: the interpolated weights drift the plain iterates
     by a common constant every pass."""
     w, prob, ref = oracle_case(name)
-    r = gpu_solve(P, w, accel=accel, lag_wrap=lag, **TIGHT)
+    # both sides converged to a 1e-14 change: with contractions close to 1
+    # a 1e-12 stop leaves ~1e-10 of fixed-point error in T_L
+    r = gpu_solve(P, w, accel=accel, lag_wrap=lag, **dict(TIGHT, outer_tol=1e-14, max_outer=40000))
     assert r["status"] == 0
     kc = ref["kappa_cc"]
     assert abs(r["kappa"] - kc) <= 1e-10 * abs(kc)
     assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
-    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-10
     km = r["solver"].kappa_modes()
     km_ref = kappa_modes(prob, ref["T"])
     assert km.shape == km_ref.shape
-    assert np.max(np.abs(km - km_ref)) <= 1e-9 * abs(kc)
+    assert np.max(np.abs(km - km_ref)) <= 1e-10 * abs(kc)
     # sum rule: the modes' shares add up to kappa
     assert abs(km.sum() - r["kappa"]) <= 1e-11 * abs(r["kappa"])
     if name == "bulk":
@@ -155,7 +158,7 @@ def test_modes_adjoint_vs_oracle(P, accel):
     g, st = sv.adjoint(o)
     g = g.cpu().numpy()
     assert abs(st["kappa"] - fwd["kappa_cc"]) < 1e-10 * fwd["kappa_cc"]
-    assert np.linalg.norm(g - gref) <= 1e-9 * np.linalg.norm(gref)
+    assert np.linalg.norm(g - gref) <= 1e-10 * np.linalg.norm(gref)
 
 
 # ---------------------------------------------- no interpolation (Eq. iter3)
@@ -176,12 +179,12 @@ EXACT = {
 def oracle_exact(name):
     w = EXACT[name]()
     prob = Problem(w)
-    return w, prob, source_iteration(prob, tol=1e-13, max_passes=20000)
+    return w, prob, source_iteration(prob, tol=1e-14, max_passes=40000)
 
 
 def test_exact_on_nodes_match_kernel_path(P):
     w0 = gen.small_2d(12, 10, solid=gen.square_block_mask(12, 10, 3, 7), n_dir=8, n_mfp=3)
-    we = _exact(gen.with_modes(w0, 0, 0, on_node=True))
+    we = _exact(on_node_modes(w0))
     r0 = gpu_solve(P, w0, **TIGHT)
     re = gpu_solve(P, we, **TIGHT)
     assert re["solver"].n_systems == 24
@@ -199,9 +202,9 @@ def test_exact_modes_vs_oracle(P, name, accel):
     kc = ref["kappa_cc"]
     assert abs(r["kappa"] - kc) <= 1e-10 * abs(kc)
     assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
-    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-10
     km = r["solver"].kappa_modes()
-    assert np.max(np.abs(km - kappa_modes(prob, ref["T"]))) <= 1e-9 * abs(kc)
+    assert np.max(np.abs(km - kappa_modes(prob, ref["T"]))) <= 1e-10 * abs(kc)
     assert abs(km.sum() - r["kappa"]) <= 1e-11 * abs(r["kappa"])
 
 
@@ -221,4 +224,4 @@ def test_exact_modes_adjoint_vs_oracle(P):
     g, st = sv.adjoint(o)
     g = g.cpu().numpy()
     assert abs(st["kappa"] - fwd["kappa_cc"]) < 1e-10 * fwd["kappa_cc"]
-    assert np.linalg.norm(g - gref) <= 1e-9 * np.linalg.norm(gref)
+    assert np.linalg.norm(g - gref) <= 1e-10 * np.linalg.norm(gref)

@@ -113,12 +113,12 @@ def test_lockstep_passes(P, name):
     ref = source_iteration(prob, n_passes=r["outer_iters"])
     assert abs(r["kappa"] - ref["kappa_cc"]) <= 1e-10 * abs(ref["kappa_cc"])
     assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
-    # T_L (max norm): the wrap-row solve stops at a 1e-14 relative residual
-    # and its matrix has condition numbers up to ~1e4 at the longest MFPs
-    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
+    # T_L and J (max norm) to the 1e-10 FP64 bar; the errors measured on
+    # these cases lie between 4e-15 and 4e-14
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-10
     Jref = np.zeros((w.n_cells, w.ndim))
     Jref[prob.mesh.cells] = ref["J"]
-    assert rel(r["J"], Jref) < 1e-9
+    assert rel(r["J"], Jref) < 1e-10
 
 
 @pytest.mark.parametrize("name", ["cfg1", "bulk", "channel", "3d", "3d_membrane"])
@@ -130,7 +130,7 @@ def test_converged(P, name):
     assert r["status"] == 0
     assert abs(r["kappa"] - ref["kappa_cc"]) <= 1e-10 * abs(ref["kappa_cc"])
     assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
-    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-10
     if name == "bulk":
         assert abs(r["kappa"] - 150.0) < 1e-11 * 150.0
 
@@ -178,10 +178,10 @@ def test_converged_anderson(P, name, accel):
     assert r["outer_iters"] <= ref["passes"]
     assert abs(r["kappa"] - ref["kappa_cc"]) <= 1e-10 * abs(ref["kappa_cc"])
     assert abs(r["kappa_face"] - ref["kappa_face"]) <= 1e-10 * abs(ref["kappa_face"])
-    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-9
+    assert rel(r["T_L"], oracle_full(prob, ref["T_L"])) < 1e-10
     Jref = np.zeros((w.n_cells, w.ndim))
     Jref[prob.mesh.cells] = ref["J"]
-    assert rel(r["J"], Jref) < 1e-9
+    assert rel(r["J"], Jref) < 1e-10
 
 
 def test_repeated_solves_reuse_graphs(P):
