@@ -240,6 +240,26 @@ obte_status obte_solve(obte_mesh* mesh, const obte_solve_opts* opts, const doubl
                        void* workspace_dev, size_t workspace_bytes, void* stream, double* T_L_dev,
                        double* J_dev, obte_stats* stats);
 
+/* obte_solve for callers that cannot allocate device or pinned host memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  The workspace is a file-scope device array of
+ * obte_noalloc_scratch_bytes() bytes (32 MiB) that the library holds on
+ * every device it runs on until the process ends; the call takes the copy
+ * of the current device (which must hold the mesh tables).  Arguments and
+ * results as obte_solve, with: init = 0 (every call starts from the Fourier
+ * guess), keep_state = 0 and timing = 0 (OBTE_ERR_ARG otherwise); a mesh
+ * whose workspace (obte_workspace_size) exceeds the array returns
+ * OBTE_ERR_NOMEM before any device work.  The call launches every kernel
+ * directly on `stream` (no graph capture, no events, no pinned staging) and
+ * allocates nothing; it synchronizes `stream` to read the results back.
+ * All calls on one device share its array, which keeps the last call's
+ * contents: calls that overlap on one device (other host threads, other
+ * streams) race and must be serialised by the caller. */
+obte_status obte_solve_noalloc(obte_mesh* mesh, const obte_solve_opts* opts, const double* sigma_dev,
+                               void* stream, double* T_L_dev, double* J_dev, obte_stats* stats);
+/* Bytes of the per-device array obte_solve_noalloc works in. */
+size_t obte_noalloc_scratch_bytes(void);
+
 /* Many independent geometries in one launch per pass (one per row-width
  * class: ceil(nx / 64) cells per lane).  meshes[i]
  * and sigma_dev[i] (nullable entries) as above; one workspace holds all, of

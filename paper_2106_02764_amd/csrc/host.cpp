@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -723,7 +724,8 @@ obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Tim
 // Fourier first guess of every geometry: CG iterations replayed as HIP graphs
 // of KF iterations (with the count of geometries still iterating at the end)
 // until none is left; direct launches when there is no stream to capture.
-obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st, GraphSlot* slot) {
+obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st, GraphSlot* slot,
+                        bool use_graph = true) {
     const int n = (int)R.views.size();
     constexpr int KF = 8;     // even: an iteration's parity is its position in the graph
     HIPCHK(launch_fourier_init(R.d_views, n, R.max_cells, st));
@@ -736,7 +738,7 @@ obte_status run_fourier(const Run& R, const obte_solve_opts* o, hipStream_t st, 
     };
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    if (st) {
+    if (st && use_graph) {
         const auto key = graph_key(R.d_views, R.d_pending, n, R.max_cells, o->fourier_tol, o->max_fourier, KF);
         obte_status s = slot_graph(slot, key, st, [&]() -> obte_status {
             const hipError_t e = enqueue();
@@ -895,10 +897,12 @@ PassParams base_params(const obte_solve_opts* o) {
     return pp;
 }
 
+// noalloc: no graph capture, no pinned staging, no events (the entry point
+// for callers that cannot allocate); every launch goes directly on `stream`.
 obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o,
                        const double* const* sigma, void* workspace, size_t ws_bytes, void* stream,
                        double* T_L_out, double* J_out, double* kappa_out, obte_stats* stats,
-                       bool keep_T) {
+                       bool keep_T, bool noalloc = false) {
     obte_status s = check_opts(o);
     if (s != OBTE_OK) return s;
     if (!meshes || n < 1) return fail(OBTE_ERR_ARG, "no meshes");
@@ -918,8 +922,10 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         if (ws_bytes < need)
             return fail(OBTE_ERR_NOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
         if ((s = upload_run(R, (char*)workspace)) != OBTE_OK) return s;
-        if ((s = ensure_stage(meshes[0], STAGE_LOOP)) != OBTE_OK) return s;
-        R.h_pin = (int*)meshes[0]->h_stage;
+        if (!noalloc) {
+            if ((s = ensure_stage(meshes[0], STAGE_LOOP)) != OBTE_OK) return s;
+            R.h_pin = (int*)meshes[0]->h_stage;
+        }
     }
     for (int i = 0; i < n; ++i) {
         obte_mesh* m = meshes[i];
@@ -938,14 +944,14 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
     Timer tm;
     // events recorded inside a captured graph cannot be timed: timing runs
     // launch the pass kernels directly
-    const int K = (o->passes_per_graph <= 1 || !st || o->timing) ? 1 : o->passes_per_graph;
+    const int K = (o->passes_per_graph <= 1 || !st || o->timing || noalloc) ? 1 : o->passes_per_graph;
     if (o->timing) {
         s = tm.init(K);
         if (s != OBTE_OK) return s;
     }
     if (o->init == 0) {
         if (tm.on) HIPCHK(hipEventRecord(tm.f0, st));
-        s = run_fourier(R, o, st, n == 1 ? &meshes[0]->g_fourier : nullptr);
+        s = run_fourier(R, o, st, n == 1 ? &meshes[0]->g_fourier : nullptr, !noalloc);
         if (s != OBTE_OK) return s;
         if (tm.on) HIPCHK(hipEventRecord(tm.f1, st));
     } else {
@@ -993,7 +999,16 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         std::vector<double> hist(passes + 1, 0.0), histf(passes + 1, 0.0), ks(m->n_sys), kfs(m->n_sys),
             wrh(passes + 1, 0.0);
         std::vector<long long> its(m->n_sys), sws(m->n_sys);
-        if (passes > 0) {
+        if (passes > 0 && noalloc) {
+            // plain copies into the host vectors (no pinned staging)
+            const size_t hb = (size_t)passes * sizeof(double), sb = (size_t)m->n_sys * 8;
+            HIPCHK(hipMemcpy(hist.data(), v.hist, hb, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(histf.data(), v.hist_face, hb, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(wrh.data(), v.wres_hist, hb, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(ks.data(), v.ksys, sb, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(its.data(), v.iters, sb, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(sws.data(), v.sweeps, sb, hipMemcpyDeviceToHost));
+        } else if (passes > 0) {
             // one wait for the six read-backs: asynchronous copies into pinned memory
             const size_t hb = (size_t)passes * sizeof(double), sb = (size_t)m->n_sys * 8;
             obte_status se = ensure_stage(m, STAGE_LOOP + 3 * hb + 3 * sb);
@@ -1413,6 +1428,65 @@ obte_status obte_solve(obte_mesh* m, const obte_solve_opts* o, const double* sig
     const double* sg[1] = {sigma_dev};
     return solve_impl(&m, 1, o, sg, workspace, ws_bytes, stream, T_L_dev, J_dev, nullptr, stats,
                       o && o->keep_state);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Workspace of obte_solve_noalloc: a file-scope device array, one copy per
+// device.  Host code never passes the array's name to a kernel or a copy: it
+// uses the device address taken once per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t NOALLOC_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+
+// The current device's copy of the array (its address is looked up on the
+// first call on each device, with that device current).
+obte_status scratch_on_current_device(void** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) return fail(OBTE_ERR_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(OBTE_ERR_HIP, "no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return OBTE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t obte_noalloc_scratch_bytes(void) { return NOALLOC_BYTES; }
+
+obte_status obte_solve_noalloc(obte_mesh* m, const obte_solve_opts* o, const double* sigma_dev, void* stream,
+                               double* T_L_dev, double* J_dev, obte_stats* stats) {
+    if (!m) return fail(OBTE_ERR_ARG, "mesh is NULL");
+    if (!o) return fail(OBTE_ERR_ARG, "opts is NULL");
+    if (o->init != 0) return fail(OBTE_ERR_ARG, "obte_solve_noalloc starts from the Fourier guess (init = 0)");
+    if (o->keep_state) return fail(OBTE_ERR_ARG, "obte_solve_noalloc keeps no adjoint state (keep_state = 0)");
+    if (o->timing) return fail(OBTE_ERR_ARG, "obte_solve_noalloc records no events (timing = 0)");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (m->has_material && m->device != dev)
+        return fail(OBTE_ERR_ARG, "the mesh tables are on device %d, the current device is %d", m->device, dev);
+    size_t need = 0;
+    obte_status s = obte_workspace_size(m, o, &need);
+    if (s != OBTE_OK) return s;
+    if (need > NOALLOC_BYTES)
+        return fail(OBTE_ERR_NOMEM, "this solve needs %zu bytes of scratch; obte_solve_noalloc has %zu "
+                                    "(use obte_solve with a caller workspace)", need, NOALLOC_BYTES);
+    void* ws = nullptr;
+    if ((s = scratch_on_current_device(&ws)) != OBTE_OK) return s;
+    const double* sg[1] = {sigma_dev};
+    return solve_impl(&m, 1, o, sg, ws, NOALLOC_BYTES, stream, T_L_dev, J_dev, nullptr, stats, false, true);
 }
 
 obte_status obte_solve_batch(obte_mesh* const* meshes, int n, const obte_solve_opts* o,

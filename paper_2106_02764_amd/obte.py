@@ -74,6 +74,9 @@ EXPORTS = {
                                             C.POINTER(C.c_size_t)]),
     "obte_solve": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.c_void_p, C.c_void_p,
                              C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(obte_stats)]),
+    "obte_solve_noalloc": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.POINTER(obte_stats)]),
+    "obte_noalloc_scratch_bytes": (C.c_size_t, []),
     "obte_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(obte_solve_opts),
                                    C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_void_p,
                                    C.POINTER(C.c_double), C.POINTER(obte_stats)]),
@@ -233,6 +236,19 @@ def obte_solve(mesh, opts, sigma, workspace, stream=None, T_L=None, J=None, rais
     if rc != OBTE_OK and not (rc == OBTE_ERR_NOT_CONVERGED and not raise_not_converged):
         _check(rc)
     return st
+
+
+def obte_solve_noalloc(mesh, opts, sigma, stream=None, T_L=None, J=None, raise_not_converged=False):
+    st = obte_stats()
+    rc = lib().obte_solve_noalloc(mesh, C.byref(opts), _dptr(sigma), _stream(stream), _dptr(T_L), _dptr(J),
+                                  C.byref(st))
+    if rc != OBTE_OK and not (rc == OBTE_ERR_NOT_CONVERGED and not raise_not_converged):
+        _check(rc)
+    return st
+
+
+def obte_noalloc_scratch_bytes():
+    return int(lib().obte_noalloc_scratch_bytes())
 
 
 def obte_solve_batch(meshes, opts, sigmas, workspace, stream=None):
