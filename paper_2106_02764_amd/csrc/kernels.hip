@@ -114,6 +114,31 @@ __device__ __forceinline__ int nbr_cell(const GeomDev& g, int cell, int f) {
     return ix + g.nx * (iy + g.ny * iz);
 }
 
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// Wave-uniform copies of values the compiler cannot prove uniform (loaded
+// after the kernel's first store, or derived from the wave index): scalar
+// registers, so the buffer resources and row offsets built from them are too.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ double uni(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) {
+    const unsigned long long a = (unsigned long long)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+    return (P*)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(uni(p)), 0, (int)uni(bytes), 0x00020000);
+}
+
 // ---------------------------------------------------------------------------
 // per-system constants
 // ---------------------------------------------------------------------------
@@ -150,6 +175,16 @@ __device__ __forceinline__ SysC<T> make_sys(const GeomDev& g, int m, int l, int 
     s.Dml = g.Dw[s.sys];
     s.Sg = g.S[s.sys * 3 + g.grad_axis];
     s.kw = g.L[g.grad_axis] / (g.dT * (double)g.ncells) * s.Sg;
+    // one system per wave: the indices and orientation flags are
+    // wave-uniform (scalar registers; they address the row loads)
+    s.sys = uni(s.sys);
+    s.m = uni(s.m);
+    s.l = uni(s.l);
+    for (int a = 0; a < 3; ++a) {
+        s.pos[a] = uni(s.pos[a]);
+        s.fin[a] = uni(s.fin[a]);
+        s.fout[a] = uni(s.fout[a]);
+    }
     return s;
 }
 
@@ -233,15 +268,54 @@ using gmut_t = __attribute__((address_space(1))) T*;
 template <typename T>
 __device__ __forceinline__ gmut_t<T> gmut(T* p) { return (gmut_t<T>)p; }
 
+// Raw buffer access (gfx9 descriptors): a resource for the whole array, a
+// per-lane byte offset fixed for the sweep and a scalar offset per row, so a
+// row's loads need no per-lane address arithmetic.  A raw buffer access is
+// range-checked on its per-lane offset: a store whose offset is at or past
+// the array's size is dropped (used for pores and beyond-row lanes).
+constexpr uint32_t BUF_OOB = 0x80000000u;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bld16(rsrc_t r, uint32_t vo, uint32_t so) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ uint32_t bld32(rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ double bld64(rsrc_t r, uint32_t vo, uint32_t so) {
+    const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0);
+    return __longlong_as_double(((long long)v.y << 32) | (unsigned long long)v.x);
+}
+template <typename T>
+__device__ __forceinline__ T bldT(rsrc_t r, uint32_t vo, uint32_t so);
+template <>
+__device__ __forceinline__ float bldT<float>(rsrc_t r, uint32_t vo, uint32_t so) {
+    return __uint_as_float(bld32(r, vo, so));
+}
+template <>
+__device__ __forceinline__ double bldT<double>(rsrc_t r, uint32_t vo, uint32_t so) {
+    return bld64(r, vo, so);
+}
+__device__ __forceinline__ void bst(float v, rsrc_t r, uint32_t vo) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, 0, 0);
+}
+__device__ __forceinline__ void bst(double v, rsrc_t r, uint32_t vo) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    u32x2_t w;
+    w.x = (unsigned int)b;
+    w.y = (unsigned int)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)vo, 0, 0);
+}
+
 // Per-wave state of a sweep that keeps its result: the kappa sums in
 // registers, and the solution stored on the solid cells (the sums over
 // systems per cell and per wall are taken afterwards by the reduction kernel).
 template <typename T>
 struct Red {
     int store_T;
+    int on;                    // 0: inactive wave (nothing is stored)
     double kacc, kface;
-    gmut_t<T> X;               // this system's solution by solid index (null: inactive wave)
-    gmut_t<double> Tstore;     // this system's stored state (or null)
+    rsrc_t X;                  // this system's solution by solid index
+    rsrc_t Tstore;             // this system's stored state (store_T only)
 };
 
 // 1/d: hardware reciprocal (float), refined by two Newton steps (double).
@@ -252,15 +326,17 @@ __device__ __forceinline__ double recip(double d) {
     return r * (2.0 - d * r);
 }
 
-// per-row inputs of one lane (prefetched ahead of use)
-template <typename T, int CPL>
+// per-row inputs of one lane (prefetched ahead of use; the 3D-only fields
+// have one dummy entry in 2D, so the rotation buffers stay in registers)
+template <typename T, int CPL, bool D3>
 struct RowIn {
     uint32_t w[CPL];
     T sg[CPL];
     double sb[CPL];     // base source (sigma T_L, or k + D Psi)
-    double bx[CPL], by[CPL], bz[CPL];   // inflow boundary values per axis
+    double bx[CPL], by[CPL];            // inflow boundary values per axis
+    double bz[D3 ? CPL : 1];
     int si[CPL];        // solid index of the cell (sweeps that store), -1 in pores
-    T ui[CPL];          // 3D: the wrap-plane input of the row's plane (used on the first y-row)
+    T ui[D3 ? CPL : 1]; // 3D: the wrap-plane input of the row's plane (used on the first y-row)
 };
 
 // Row results of a storing sweep, kept in registers until a group of rows is
@@ -274,46 +350,41 @@ struct RowOut {
     int si[CPL];        // -1: nothing to store
 };
 
-// per-sweep constant views
-template <typename T>
+// per-sweep constant views: buffer resources of the per-cell tables and of
+// the 3D wrap-plane input, and this lane's byte offsets within a row
+template <typename T, int CPL>
 struct Views {
-    gptr_t<uint16_t> fc;
-    gptr_t<int> sidx;
-    gptr_t<T> sg;
-    gptr_t<T> u;                       // 3D: the wrap-plane input (nz x nx)
-    gptr_t<double> src, bx, by, bz;
+    rsrc_t fc, sidx, sg, u, src, bx, by, bz;
+    uint32_t o2[CPL], o4[CPL], o8[CPL], oT[CPL], ou[CPL];
     // geometry scalars read once per sweep: the row loop stores to global
     // memory, after which the compiler would reload them from the view
     int nx, ny, nz, ga;
+    int lx, cx;                        // lane and register of a row's last cell (p = nx - 1)
     double dT;
 };
 
 template <typename T, int CPL, bool D3, bool WITH_B, bool S1, bool ST>
-__device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, const Views<T>& v, int lane,
-                                         int jj, int kk, RowIn<T, CPL>& r) {
-    const int nx = v.nx;
+__device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, const Views<T, CPL>& v, int lane,
+                                         int jj, int kk, RowIn<T, CPL, D3>& r) {
+    // every lane loads (beyond the row: the row's first cell, masked by the
+    // row step), so no load sits in a branch or feeds a select here: the
+    // compiler then counts the loads in flight exactly and waits only for
+    // the row it is about to use
     const int iy = s.pos[1] ? jj : v.ny - 1 - jj;
     const int iz = D3 ? (s.pos[2] ? kk : v.nz - 1 - kk) : 0;
-    const int rowbase = nx * (iy + v.ny * iz);
+    const uint32_t rowbase = uni((uint32_t)(v.nx * (iy + v.ny * iz)));
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
-        const int p = lane * CPL + c;
-        const bool in = p < nx;
-        // every lane loads (beyond the row: the row's first cell, masked by
-        // the row step), so no load sits in a branch or feeds a select here:
-        // the compiler then counts the loads in flight exactly and waits
-        // only for the row it is about to use
-        const int cell = rowbase + (in ? (s.pos[0] ? p : nx - 1 - p) : 0);
-        r.w[c] = (uint32_t)v.fc[cell];
-        if (ST) r.si[c] = v.sidx[cell];
-        if (D3) r.ui[c] = v.u[kk * nx + min(p, nx - 1)];
-        r.sg[c] = S1 ? T(1) : v.sg[cell];
+        r.w[c] = bld16(v.fc, v.o2[c], rowbase * 2u);
+        if (ST) r.si[c] = (int)bld32(v.sidx, v.o4[c], rowbase * 4u);
+        r.sg[c] = S1 ? T(1) : bldT<T>(v.sg, v.oT[c], rowbase * (uint32_t)sizeof(T));
         if (WITH_B) {
-            r.sb[c] = v.src[cell];
-            r.bx[c] = v.bx[cell];
-            r.by[c] = v.by[cell];
-            if (D3) r.bz[c] = v.bz[cell];
+            r.sb[c] = bld64(v.src, v.o8[c], rowbase * 8u);
+            r.bx[c] = bld64(v.bx, v.o8[c], rowbase * 8u);
+            r.by[c] = bld64(v.by, v.o8[c], rowbase * 8u);
+            if (D3) r.bz[c] = bld64(v.bz, v.o8[c], rowbase * 8u);
         }
+        if (D3) r.ui[c] = bldT<T>(v.u, v.ou[c], uni((uint32_t)(kk * v.nx)) * (uint32_t)sizeof(T));
     }
 }
 
@@ -344,7 +415,7 @@ struct RegIO {
     const T (&u)[CPL];
     T (&xl)[CPL];
     __device__ __forceinline__ T in(int, int c, int) const { return u[c]; }
-    __device__ __forceinline__ gptr_t<T> input() const { return nullptr; }
+    __device__ __forceinline__ const T* input() const { return nullptr; }
     __device__ __forceinline__ void out(int, int c, int, T v) { xl[c] = v; }
 };
 template <typename T, int CPL>
@@ -353,7 +424,7 @@ struct GlobIO {
     gmut_t<T> xl;        // nullptr: the last row is not needed
     int nx;
     int active;
-    __device__ __forceinline__ gptr_t<T> input() const { return u; }
+    __device__ __forceinline__ const T* input() const { return (const T*)u; }
     // the row loads prefetch the input (Views::u); nothing is read here
     __device__ __forceinline__ T in(int, int, int) const { return T(0); }
     __device__ __forceinline__ void out(int kk, int c, int lane, T v) {
@@ -363,10 +434,10 @@ struct GlobIO {
 };
 
 // One row step of the sweep (cells of row (jj, kk) in upwind order).
-template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, class IO>
-__device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, const Views<T>& vw,
+template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, int GA, class IO>
+__device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, const Views<T, CPL>& vw,
                                          int active, int lane, int adj, int jj, int kk,
-                                         const RowIn<T, CPL>& cur, Rows<T, CPL, D3>& rows, IO& io,
+                                         const RowIn<T, CPL, D3>& cur, Rows<T, CPL, D3>& rows, IO& io,
                                          const double (&mb)[3], Red<T>* rd, RowOut<T, CPL>& ro) {
     constexpr int ND = D3 ? 3 : 2;
     const int nx = vw.nx, ny = vw.ny;
@@ -442,7 +513,9 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 #pragma unroll
         for (int c = 0; c < CPL; ++c) io.out(kk, c, lane, xrow[c]);
     }
-    if (RED && rd->X) {
+    if (RED) {
+        // branch-free: cells that contribute nothing add an exact 0 (an
+        // inactive wave's sums are dropped, its stores skipped)
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int p = lane * CPL + c;
@@ -450,43 +523,76 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
             const bool sol = fc_solid(wv);
             ro.x[c] = xrow[c];
             ro.si[c] = sol ? cur.si[c] : -1;
-            if (sol) {
-                const double xv = (double)xrow[c];
-                rd->kacc += xv;
-                if (adj) {
-                    // p^T lambda: forward jump inflow = reversed outflow faces
+            const double xv = sol ? (double)xrow[c] : 0.0;
+            rd->kacc += xv;
+        }
+        // Flux through the periodic plane of the gradient axis (kappa_face;
+        // the adjoint: p^T lambda of the jump inflow, on the forward's jump
+        // faces = this sweep's outflow faces).  The jump term belongs to the
+        // b sweep only.
+        if (GA == 0) {
+            // the plane's cell of a row is its last cell in sweep order
+            // (p = nx - 1): one lane's value, read into a scalar, added on
+            // lane 0 (the wave sum then equals the sum over the rows)
+            // (each register is read into a scalar and the scalars are
+            // selected: selecting the registers first would let the compiler
+            // index the row buffers at run time, which puts them in memory)
+            T xl = readlane(xrow[0], vw.lx);
+            uint32_t wl = (uint32_t)__builtin_amdgcn_readlane((int)cur.w[0], vw.lx);
 #pragma unroll
-                    for (int ax = 0; ax < ND; ++ax) {
-                        const int cl = fc_class(wv, s.fout[ax]);
-                        if (cl == FC_JUMP_P) rd->kface += s.cd[ax] * vw.dT * xv;
-                        else if (cl == FC_JUMP_M) rd->kface -= s.cd[ax] * vw.dT * xv;
-                    }
+            for (int c = 1; c < CPL; ++c) {
+                const T xc = readlane(xrow[c], vw.lx);
+                const uint32_t wc = (uint32_t)__builtin_amdgcn_readlane((int)cur.w[c], vw.lx);
+                xl = (c == vw.cx) ? xc : xl;
+                wl = (c == vw.cx) ? wc : wl;
+            }
+            double add = 0.0;
+            if (fc_solid(wl)) {
+                const int cl = fc_class(wl, s.fout[0]);
+                const double xd = (double)xl;
+                if (adj) {
+                    const double cj = s.cd[0] * vw.dT;
+                    add = cl == FC_JUMP_P ? cj * xd : (cl == FC_JUMP_M ? -cj * xd : 0.0);
                 } else {
-                    // kappa through the periodic plane of the gradient axis;
-                    // the jump term belongs to the b sweep only
-                    if (vw.ga == 0 && p == nx - 1 && fc_class(wv, s.fout[0]) != FC_WALL)
-                        rd->kface += xv + ((!ADD && s.pos[0]) ? vw.dT : 0.0);
-                    if (vw.ga == 1 && jj == ny - 1 && fc_class(wv, s.fout[1]) != FC_WALL)
-                        rd->kface += xv + ((!ADD && s.pos[1]) ? vw.dT : 0.0);
+                    add = cl != FC_WALL ? xd + ((!ADD && s.pos[0]) ? vw.dT : 0.0) : 0.0;
+                }
+            }
+            rd->kface += lane == 0 ? add : 0.0;
+        } else if (GA == 1 && jj == ny - 1) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int p = lane * CPL + c;
+                const uint32_t wv = p < nx ? cur.w[c] : 0u;
+                if (!fc_solid(wv)) continue;
+                const double xv = (double)xrow[c];
+                const int cl = fc_class(wv, s.fout[1]);
+                if (adj) {
+                    const double cj = s.cd[1] * vw.dT;
+                    rd->kface += cl == FC_JUMP_P ? cj * xv : (cl == FC_JUMP_M ? -cj * xv : 0.0);
+                } else if (cl != FC_WALL) {
+                    rd->kface += xv + ((!ADD && s.pos[1]) ? vw.dT : 0.0);
                 }
             }
         }
     }
 }
 
-// Store a group of rows of a storing sweep (ADD: add to the stored values).
+// Store a group of rows of a storing sweep (ADD: add to the stored values);
+// cells with nothing to store get an out-of-range offset, so every lane
+// issues the same stores and the hardware drops those.
 template <typename T, int CPL, int NR, bool ADD>
 __device__ __forceinline__ void store_rows(Red<T>* rd, const RowOut<T, CPL> (&ro)[NR]) {
-    if (!rd->X) return;
+    if (!rd->on) return;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int i = ro[r].si[c];
-            if (i < 0) continue;
-            const T v = ro[r].x[c];
-            rd->X[i] = ADD ? rd->X[i] + v : v;
-            if (rd->store_T) rd->Tstore[i] = (double)v;
+            const uint32_t vo = i >= 0 ? (uint32_t)i * (uint32_t)sizeof(T) : BUF_OOB;
+            T v = ro[r].x[c];
+            if (ADD) v += bldT<T>(rd->X, vo, 0);
+            bst(v, rd->X, vo);
+            if (rd->store_T) bst((double)ro[r].x[c], rd->Tstore, i >= 0 ? (uint32_t)i * 8u : BUF_OOB);
         }
 }
 
@@ -499,9 +605,9 @@ __device__ __forceinline__ void store_rows(Red<T>* rd, const RowOut<T, CPL> (&ro
 // block.  Returns the last row (jj = ny-1) in xl.  Row inputs are prefetched
 // two rows ahead (2D) through a three-buffer rotation without copies.
 // ---------------------------------------------------------------------------
-constexpr int PF2D = 4;    // 2D rows in flight (prefetch depth + 1)
 
-template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, class IO>
+
+template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, int GA, class IO>
 __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int active, int lane, int adj,
                                       const double* __restrict__ srcbase, const double* __restrict__ bnd,
                                       IO& io, Red<T>* rd, T* zrows) {
@@ -516,91 +622,71 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
         fb[ax] = adj ? 2 * ax + (s.S[ax] > 0.0 ? 1 : 0) : s.fin[ax];
         mb[ax] = adj ? (ax < ND ? g.wout[fb[ax] * g.n_sys + s.sys] : 0.0) : s.cd[ax];
     }
-    Views<T> vw;
-    vw.fc = gview(g.fc);
-    vw.sidx = gview(g.sidx);
-    vw.sg = gview(sigma_ptr<T>(g));
-    vw.u = io.input();
-    vw.src = gview(srcbase);
-    vw.bx = gview(bnd + (size_t)fb[0] * g.ncells);
-    vw.by = gview(bnd + (size_t)fb[1] * g.ncells);
-    vw.bz = gview(bnd + (size_t)(D3 ? fb[2] : 0) * g.ncells);
-    vw.nx = g.nx;
-    vw.ny = g.ny;
-    vw.nz = g.nz;
-    vw.ga = g.grad_axis;
-    vw.dT = g.dT;
+    Views<T, CPL> vw;
+    const uint32_t nc = (uint32_t)g.ncells;
+    vw.fc = make_rsrc(g.fc, nc * 2u);
+    vw.sidx = make_rsrc(g.sidx, nc * 4u);
+    vw.sg = make_rsrc(sigma_ptr<T>(g), nc * (uint32_t)sizeof(T));
+    vw.u = make_rsrc(io.input(), (uint32_t)(g.nx * g.nz) * (uint32_t)sizeof(T));
+    vw.src = make_rsrc(srcbase, nc * 8u);
+    vw.bx = make_rsrc(bnd + (size_t)fb[0] * g.ncells, nc * 8u);
+    vw.by = make_rsrc(bnd + (size_t)fb[1] * g.ncells, nc * 8u);
+    vw.bz = make_rsrc(bnd + (size_t)(D3 ? fb[2] : 0) * g.ncells, nc * 8u);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        // cell of this lane within a row (beyond the row: the row's first cell)
+        const int p = lane * CPL + c;
+        const uint32_t lo = p < g.nx ? (uint32_t)(s.pos[0] ? p : g.nx - 1 - p) : 0u;
+        vw.o2[c] = lo * 2u;
+        vw.o4[c] = lo * 4u;
+        vw.o8[c] = lo * 8u;
+        vw.oT[c] = lo * (uint32_t)sizeof(T);
+        vw.ou[c] = (uint32_t)min(p, g.nx - 1) * (uint32_t)sizeof(T);
+    }
+    vw.nx = uni(g.nx);
+    vw.ny = uni(g.ny);
+    vw.nz = uni(g.nz);
+    vw.ga = uni(g.grad_axis);
+    vw.lx = (vw.nx - 1) / CPL;
+    vw.cx = (vw.nx - 1) % CPL;
+    vw.dT = uni(g.dT);
     Rows<T, CPL, D3> rows;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) rows.xr[c] = T(0);
     rows.xz = zrows;
     rows.ROW = WAVE * CPL;
     const int ny = g.ny;
-    if (!D3) {
-        // PF2D buffers in rotation: the loads of row jj + PF2D - 1 are issued
-        // before row jj runs (the unrolled rotation keeps every index static);
-        // a storing sweep stores each group of PF2D rows after its last row
-        RowIn<T, CPL> b[PF2D];
-        // Prefetches are never skipped (past the last row they reload it):
-        // a load inside a branch would leave the compiler unsure how many
-        // loads are in flight at the join, and it would then wait for all.
+    // Rows (jj, kk) in order, kk inner (2D: kk = 0).  A three-buffer
+    // rotation keeps the inputs two rows ahead; prefetches are never skipped
+    // (past the last row they reload it): a load inside a branch would leave
+    // the compiler unsure how many loads are in flight at the join, and it
+    // would then wait for all.  A storing sweep stores each group of three
+    // rows after the group's last row.
+    const int nz = D3 ? g.nz : 1, nrows = ny * nz;
+    auto pre = [&](int r, RowIn<T, CPL, D3>& b) {
+        const int rr = min(r, nrows - 1);
+        load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, D3 ? rr / nz : rr, D3 ? rr % nz : 0, b);
+    };
+    auto step = [&](int r, const RowIn<T, CPL, D3>& b, RowOut<T, CPL>& ro) {
+        row_step<T, CPL, D3, WITH_B, RED, ADD, S1, GA>(g, s, vw, active, lane, adj, D3 ? r / nz : r, D3 ? r % nz : 0,
+                                                       b, rows, io, mb, rd, ro);
+    };
+    RowIn<T, CPL, D3> b0, b1, b2;
+    pre(0, b0);
+    pre(1, b1);
+    for (int r = 0; r < nrows; r += 3) {
+        RowOut<T, CPL> ro[3];
 #pragma unroll
-        for (int r = 0; r < PF2D - 1; ++r)
-            load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, min(r, ny - 1), 0, b[r]);
-        for (int jj = 0; jj < ny; jj += PF2D) {
-            RowOut<T, CPL> ro[PF2D];
+        for (int q = 0; q < 3; ++q)
 #pragma unroll
-            for (int r = 0; r < PF2D; ++r)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) ro[r].si[c] = -1;
-#pragma unroll
-            for (int r = 0; r < PF2D; ++r) {
-                // the first row of a group waits for every access in flight
-                // (the stores of the previous group): its own prefetch is
-                // issued after that wait, not before
-                const int rn = min(jj + r + PF2D - 1, ny - 1);
-                if (!(RED && r == 0))
-                    load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, rn, 0, b[(r + PF2D - 1) % PF2D]);
-                if (jj + r < ny)
-                    row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, jj + r, 0, b[r], rows, io,
-                                                           mb, rd, ro[r]);
-                if (RED && r == 0)
-                    load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, rn, 0, b[(r + PF2D - 1) % PF2D]);
-            }
-            if (RED) store_rows<T, CPL, PF2D, ADD>(rd, ro);
-        }
-    } else {
-        // 3D: rows (jj, kk) with kk inner; a three-buffer rotation keeps the
-        // inputs two rows ahead (the row order is y-major, z-minor); a storing
-        // sweep stores each group of three rows after its last row
-        const int nz = g.nz, nrows = ny * nz;
-        // prefetches are never skipped (past the last row they reload it)
-        auto pre = [&](int r, RowIn<T, CPL>& b) {
-            const int rr = min(r, nrows - 1);
-            load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, rr / nz, rr % nz, b);
-        };
-        RowIn<T, CPL> b0, b1, b2;
-        pre(0, b0);
-        pre(1, b1);
-        for (int r = 0; r < nrows; r += 3) {
-            RowOut<T, CPL> ro[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) ro[q].si[c] = -1;
-            pre(r + 2, b2);
-            row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, r / nz, r % nz, b0, rows, io, mb, rd,
-                                                   ro[0]);
-            pre(r + 3, b0);
-            if (r + 1 < nrows)
-                row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, (r + 1) / nz, (r + 1) % nz, b1,
-                                                       rows, io, mb, rd, ro[1]);
-            pre(r + 4, b1);
-            if (r + 2 < nrows)
-                row_step<T, CPL, D3, WITH_B, RED, ADD, S1>(g, s, vw, active, lane, adj, (r + 2) / nz, (r + 2) % nz, b2,
-                                                       rows, io, mb, rd, ro[2]);
-            if (RED) store_rows<T, CPL, 3, ADD>(rd, ro);
-        }
+            for (int c = 0; c < CPL; ++c) ro[q].si[c] = -1;
+        pre(r + 2, b2);
+        step(r, b0, ro[0]);
+        pre(r + 3, b0);
+        if (r + 1 < nrows) step(r + 1, b1, ro[1]);
+        pre(r + 4, b1);
+        if (r + 2 < nrows) step(r + 2, b2, ro[2]);
+        if (RED) store_rows<T, CPL, 3, ADD>(rd, ro);
     }
 }
 
@@ -643,11 +729,13 @@ __device__ __forceinline__ double vdot(const T (&a)[NZ][CPL], const T (&b)[NZ][C
 template <typename T>
 __device__ __forceinline__ Red<T> make_red(const GeomDev& g, const SysC<T>& s, int active, const PassParams& pp) {
     Red<T> rd;
-    rd.store_T = pp.store_T;
     rd.kacc = 0.0;
     rd.kface = 0.0;
-    rd.X = active ? gmut(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.nsolid) : nullptr;
-    rd.Tstore = (active && g.Tstore) ? gmut(g.Tstore + (size_t)s.sys * g.nsolid) : nullptr;
+    rd.on = active;
+    rd.X = make_rsrc(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.nsolid, (uint32_t)g.nsolid * (uint32_t)sizeof(T));
+    rd.Tstore = make_rsrc(g.Tstore ? g.Tstore + (size_t)s.sys * g.nsolid : nullptr,
+                          g.Tstore ? (uint32_t)g.nsolid * 8u : 0u);
+    rd.store_T = pp.store_T && g.Tstore != nullptr;
     return rd;
 }
 
@@ -691,7 +779,9 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     const Item item = items[it];
     const GeomDev& g = geoms[item.geom];
     if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wave index is wave-uniform: read it into a scalar so that every
+    // per-system quantity (and the buffer resources built from it) is too
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = item.m0 + w;
     const int active = (w < item.nm) && (m < g.n_mfp);
     constexpr int adj = ADJ;     // the adjoint's branches fold at compile time
@@ -713,7 +803,10 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     // ---- phase A
     {
         RegIO<T, CPL> io{u[0], xl[0]};
-        sweep<T, CPL, false, true, true, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+        if (g.grad_axis == 0)
+            sweep<T, CPL, false, true, true, false, SIG1 != 0, 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+        else
+            sweep<T, CPL, false, true, true, false, SIG1 != 0, 1>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
     }
     long long n_it = 0, n_sw = 1;
     int need = 0;
@@ -751,7 +844,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 VLOOP(p[k][c] = r[k][c] + (T)beta * (p[k][c] - (T)omega * v[k][c]));
                 {
                     RegIO<T, CPL> io{p[0], xl[0]};
-                    sweep<T, CPL, false, false, false, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                    sweep<T, CPL, false, false, false, false, SIG1 != 0, -1>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
                 }
                 ++n_sw;
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
@@ -775,7 +868,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 }
                 {
                     RegIO<T, CPL> io{sv[0], xl[0]};
-                    sweep<T, CPL, false, false, false, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                    sweep<T, CPL, false, false, false, false, SIG1 != 0, -1>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
                 }
                 ++n_sw;
                 VLOOP(t[k][c] = sv[k][c] - mk[k][c] * xl[k][c]);
@@ -804,7 +897,10 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     // when the correction is lagged into the next pass)
     if (!pp.lag_wrap && need) {
         RegIO<T, CPL> io{du[0], xl[0]};
-        sweep<T, CPL, false, false, true, true, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+        if (g.grad_axis == 0)
+            sweep<T, CPL, false, false, true, true, SIG1 != 0, 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+        else
+            sweep<T, CPL, false, false, true, true, SIG1 != 0, 1>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
         ++n_sw;
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
@@ -839,7 +935,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     const Item item = items[it];
     const GeomDev& g = geoms[item.geom];
     if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wave index is wave-uniform: read it into a scalar so that every
+    // per-system quantity (and the buffer resources built from it) is too
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = item.m0 + w;
     const int active = (w < item.nm) && (m < g.n_mfp);
     constexpr int adj = ADJ;
@@ -860,7 +958,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     // ---- phase A
     {
         GlobIO<T, CPL> io{U, xl, nx, active};
-        sweep<T, CPL, true, true, true, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+        if (g.grad_axis == 0)
+            sweep<T, CPL, true, true, true, false, SIG1 != 0, 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+        else
+            sweep<T, CPL, true, true, true, false, SIG1 != 0, 1>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
     }
     long long n_it = 0, n_sw = 1;
     int need = 0;
@@ -917,7 +1018,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
                 PLOOP(p[i] = r[i] + (T)beta * (p[i] - (T)omega * v[i]));
                 {
                     GlobIO<T, CPL> io{p, xl, nx, 1};
-                    sweep<T, CPL, true, false, false, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
+                    sweep<T, CPL, true, false, false, false, SIG1 != 0, -1>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
                 }
                 ++n_sw;
                 acc = 0.0;
@@ -952,7 +1053,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
                 }
                 {
                     GlobIO<T, CPL> io{sv, xl, nx, 1};
-                    sweep<T, CPL, true, false, false, false, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
+                    sweep<T, CPL, true, false, false, false, SIG1 != 0, -1>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
                 }
                 ++n_sw;
                 double tt = 0.0, ts = 0.0;
@@ -990,7 +1091,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     // ---- phase C (see the 2D kernel)
     if (!pp.lag_wrap && need) {
         GlobIO<T, CPL> io{du, nullptr, nx, 0};
-        sweep<T, CPL, true, false, true, true, SIG1 != 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+        if (g.grad_axis == 0)
+            sweep<T, CPL, true, false, true, true, SIG1 != 0, 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+        else
+            sweep<T, CPL, true, false, true, true, SIG1 != 0, 1>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
         ++n_sw;
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
