@@ -27,7 +27,13 @@ if ROOT not in sys.path:
 
 METRIC = ("converged κ_eff solves/s and cell·dir·MFP DoF/s, FP32 vs FP64, "
           "at 1e-4 rel err")
-PEAK = {"fp64_vector_tflops": 78.6, "fp32_vector_tflops": 157.3, "hbm_gbs": 8000.0}
+# MI355X published peaks: HBM3E 8 TB/s; vector FP32 78.6 TFLOP/s without
+# packed FP32 (this build switches packed FP32 off; 157.3 with it), FP64 78.6
+PEAK = {"hbm_gbs": 8000.0, "fp32_vector_tflops": 78.6, "fp64_vector_tflops": 78.6}
+# Algorithmic HBM bytes of one upwind sweep of one system, per solid cell: the
+# apply-equivalent of Eq. (iter2)'s left side reads x once and writes y once
+# (2 words of the compute type); the per-cell tables are shared by all systems.
+WORDS_PER_CELL_SWEEP = 2
 # algorithmic flops of one upwind sweep per solid cell: the triangular update
 # x = (b + c_x x_up,x + c_y x_up,y [+ c_z x_up,z]) / d  (2 or 3 FMA + 1 divide
 # counted as 3)
@@ -151,17 +157,24 @@ def leg(P, solver, w, name, steps, warmup, kref, kor):
     return out
 
 
-def roofline(w, tl, kernel, fp32=True):
-    """The pass kernel: algorithmic flops per launch = sweeps in that launch
-    x solid cells x flops per cell-sweep, over its average launch duration."""
-    sweeps_per_launch = tl["sweeps"] / max(tl["sweep_launches"], 1)
+def roofline(w, tl, kernel, tsize=4):
+    """HBM roofline of the pass kernel: algorithmic bytes per launch (sweeps
+    in that launch x solid cells x 2 words of the compute type) over its
+    average launch duration (HIP events on the library's stream); beside it
+    the same launch against the vector ALU peak."""
+    launches = max(tl["sweep_launches"], 1)
+    sweeps_per_launch = tl["sweeps"] / launches
+    avg_ms = tl["sweep_ms"] / launches
+    bytes_ = sweeps_per_launch * w.n_solid * WORDS_PER_CELL_SWEEP * tsize
+    achieved = bytes_ / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     flops = sweeps_per_launch * w.n_solid * FLOPS_PER_CELL_SWEEP[w.ndim]
-    avg_ms = tl["sweep_ms"] / max(tl["sweep_launches"], 1)
-    achieved = flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    peak = PEAK["fp32_vector_tflops"] if fp32 else PEAK["fp64_vector_tflops"]
-    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "kernel": kernel, "avg_launch_ms": avg_ms,
-            "sweeps_per_launch": sweeps_per_launch}
+    tflops = flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    alu_peak = PEAK["fp32_vector_tflops"] if tsize == 4 else PEAK["fp64_vector_tflops"]
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+            "frac": achieved / PEAK["hbm_gbs"], "traffic": None, "kernel": kernel,
+            "avg_launch_ms": avg_ms, "sweeps_per_launch": sweeps_per_launch,
+            "algorithmic_bytes_per_launch": bytes_,
+            "alu_view": {"achieved_tflops": tflops, "peak_tflops": alu_peak, "frac": tflops / alu_peak}}
 
 
 def single(P, name, steps, warmup):
@@ -191,7 +204,8 @@ def batch(P, steps, warmup):
            "dof": dof, "solid_cells": sum(w.n_solid for w in geoms)}
     for name in FORMS:
         o = P.default_opts(**OP[name])
-        o.waves_per_group = P.autotune.tune(solvers, o)
+        choice = P.autotune.tune(solvers, o)
+        P.autotune.apply(o, choice)
         for _ in range(warmup):
             P.solve_batch(solvers, o)
         torch.cuda.synchronize()
@@ -201,12 +215,13 @@ def batch(P, steps, warmup):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         ot = P.default_opts(**OP[name], timing=1)
-        ot.waves_per_group = o.waves_per_group
+        P.autotune.apply(ot, choice)
         _, stt = P.solve_batch(solvers, ot)
         out[name] = {"geometry_solves_per_s": len(geoms) / dt, "ms_per_batch": 1e3 * dt,
                      "dof_per_s": dof / dt,
                      "max_kappa_rel_err_vs_fp64_ref": max(abs(x - y) / y for x, y in zip(k, ref)),
-                     "waves_per_group": o.waves_per_group,
+                     "launch_shape": {"waves_by_class": choice["waves_by_class"],
+                                      "dispatch": choice["dispatch"]},
                      "max_passes": max(x["outer_iters"] for x in st),
                      "mean_passes": sum(x["outer_iters"] for x in st) / len(st),
                      "status_ok": sum(1 for x in st if x["status"] == 0),
@@ -216,18 +231,25 @@ def batch(P, steps, warmup):
     return out
 
 
+def cpu_share():
+    """Host cores this process may use: the affinity set, at most 16 (the
+    host-core share of one GPU on the GPU machine)."""
+    aff = len(os.sched_getaffinity(0))
+    return max(1, min(aff, 16)), aff, os.cpu_count()
+
+
 def cpu_baseline_measure(w, seconds):
     """Time the FP64 oracle on the same workload before the GPU is touched:
     every (m, l) system factored once (SuperLU, reused as in the paper) and a
     few source-iteration passes, with the directions spread over the host
-    cores.  Bounded by `seconds` of passes."""
+    cores (one worker process per core).  Bounded by `seconds` of passes."""
     from oracle.parallel import source_iteration_parallel
-    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    cores, aff, ncpu = cpu_share()
     t0 = time.perf_counter()
     r = source_iteration_parallel(w, n_workers=cores, n_passes=3, time_limit=seconds)
     total = time.perf_counter() - t0
-    return {"cores": cores, "t_factor": r["t_factor"], "pass_s": float(r["pass_times"].mean()),
-            "passes_run": int(r["passes"]), "wall_s": total}
+    return {"cores": cores, "affinity": aff, "cpu_count": ncpu, "t_factor": r["t_factor"],
+            "pass_s": float(r["pass_times"].mean()), "passes_run": int(r["passes"]), "wall_s": total}
 
 
 def cpu_baseline_value(m, passes, dof):
@@ -235,9 +257,92 @@ def cpu_baseline_value(m, passes, dof):
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": m["cores"], "kind": "oracle",
             "sample": (f"full workload, all systems factored ({m['t_factor']:.1f}s) + "
                        f"{m['passes_run']} passes ({m['pass_s']:.3f}s each) on {m['cores']} worker "
-                       f"processes; extrapolated to the {passes} passes the FP64 form needs for "
-                       f"the same error target"),
-            "dof_per_s": dof / per_solve, "seconds_per_solve_estimate": per_solve}
+                       f"processes (affinity set {m['affinity']} cores, os.cpu_count() "
+                       f"{m['cpu_count']}); extrapolated to the {passes} passes the FP64 form needs "
+                       f"for the same error target (Fourier guess and setup not counted)"),
+            "dof_per_s": dof / per_solve, "seconds_per_solve_estimate": per_solve,
+            "cpu_count": m["cpu_count"], "affinity_cores": m["affinity"]}
+
+
+def cpu_cfg1_one_core():
+    """The 32x32 cell (plain method, FP64, 1e-8 relative change), the serial
+    oracle on one core: one full converged solve, Fourier guess included."""
+    from inputs import gen
+    from oracle.bte import Problem, source_iteration
+    w = gen.config1()
+    t0 = time.perf_counter()
+    r = source_iteration(Problem(w), tol=1e-8)
+    dt = time.perf_counter() - t0
+    return {"solves_per_s": 1.0 / dt, "seconds": dt, "passes": int(r["passes"]), "cores": 1,
+            "kappa": r["kappa_cc"], "kind": "oracle (serial, SuperLU per system)"}
+
+
+def cfg1_leg(P, steps, warmup):
+    """The 32x32 cell as specified: plain Algorithm 1 in FP64 to a 1e-8
+    relative change of kappa."""
+    from inputs import gen
+    w = gen.config1()
+    s = P.Solver.from_workload(w)
+    o = s.opts(precision=0, outer_tol=1e-8, stop_rule=0, accel=0, inner_tol=1e-12, fourier_tol=1e-10,
+               passes_per_graph=8, max_outer=20000)
+    r = run_solves(s, o, steps, warmup)
+    return {"workload": "32x32 cell, centred square pore (25%), 24 directions x 10 MFPs, FP64, "
+                        "Algorithm 1 to 1e-8 relative change", "dof": w.dof,
+            "solves_per_s": steps / r["seconds"], "ms_per_solve": 1e3 * r["seconds"] / steps,
+            "passes_per_solve": r["outer_iters"] / steps, "kappa": r["kappa"]}
+
+
+def adjoint_leg(P, name, steps, warmup):
+    """d kappa / d sigma by the transposed source iteration (Eq. (iter2)
+    transposed): adjoint-only gradients/s after one kept forward solve, FP64
+    and FP32 forms at the headline operating points, each gradient's error
+    against a tight FP64 adjoint on the same inputs."""
+    import numpy as np
+    import torch
+    w = make_workload(name)
+    s = P.Solver.from_workload(w)
+    ref_o = s.opts(**dict(REF, keep_state=1))
+    s.solve(ref_o, sigma=w.sigma, want_T_L=False)
+    gref, _ = s.adjoint(ref_o)
+    gref = gref.cpu().numpy()
+    out = {"workload": name, "cells": w.n_cells}
+    for form in ("fp64_aa", "fp32_aa"):
+        o = s.opts(**dict(OP[form], keep_state=1))
+        fw = s.solve(o, sigma=w.sigma, want_T_L=False)
+        for _ in range(warmup):
+            s.adjoint(o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g, st = s.adjoint(o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        g = g.cpu().numpy()
+        out[form] = {"gradients_per_s": 1.0 / dt, "ms_per_gradient": 1e3 * dt,
+                     "adjoint_passes": st["outer_iters"], "forward_passes": fw["outer_iters"],
+                     "max_rel_err_vs_fp64_ref": float(np.max(np.abs(g - gref)) / np.max(np.abs(gref))),
+                     "sum_rel_err_vs_fp64_ref": float(abs(g.sum() - gref.sum()) / abs(gref.sum()))}
+    return out
+
+
+def adjoint_3d(P):
+    """One adjoint pass of the 3D membrane at sigma = 1 (FP32 form, headline
+    operating point) after its kept forward solve."""
+    import torch
+    w = make_workload("cfg5")
+    s = P.Solver.from_workload(w)
+    o = s.opts(**dict(OP[HEADLINE], keep_state=1))
+    fw = s.solve(o, want_T_L=False)
+    s.adjoint(o)                      # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, st = s.adjoint(o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": describe("cfg5", w) + ", d kappa / d sigma at sigma = 1 (FP32 form)",
+            "ms_per_gradient": 1e3 * dt, "adjoint_passes": st["outer_iters"],
+            "forward_passes": fw["outer_iters"], "p_T_lambda_vs_kappa":
+            abs(st["kappa"] - fw["kappa"]) / abs(fw["kappa"])}
 
 
 def fourier_batch(P, steps, warmup):
@@ -307,11 +412,12 @@ def main():
         return
     w0 = make_workload(a.workload)
     cpu = None if a.no_cpu else cpu_baseline_measure(w0, a.cpu_seconds)
+    cpu1 = None if a.no_cpu else cpu_cfg1_one_core()
     import paper_2106_02764_amd as P
 
     w, kref, kor, res = single(P, a.workload, a.steps, a.warmup)
     main_r = res[HEADLINE]
-    roof = roofline(w, main_r["timed_leg"], "k_sweep_pass<float>")
+    roof = roofline(w, main_r["timed_leg"], "k_sweep_pass<float>", tsize=4)
     sha = kernels_sha()
     if TRAFFIC["kernels_sha256"] == sha and a.workload == "cfg2":
         roof["traffic"] = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
@@ -332,13 +438,17 @@ def main():
     }
     if cpu is not None:
         line["cpu_baseline"] = cpu_baseline_value(cpu, int(round(res["fp64"]["passes_per_solve"])), w.dof)
+        line["cpu_baseline"]["cfg1_one_core"] = cpu1
+    line["extra_cfg1_fp64"] = cfg1_leg(P, max(a.steps, 3), a.warmup)
+    line["extra_adjoint_cfg4"] = adjoint_leg(P, "cfg4", max(2, min(a.steps, 5)), 1)
     if not a.no_extras:
         steps_x, warm_x = max(1, min(a.steps, 2)), 1
+        line["extra_adjoint_3d"] = adjoint_3d(P)
         w5, kref5, kor5, res5 = single(P, "cfg5", steps_x, warm_x)
         line["extra_3d_membrane"] = {"workload": describe("cfg5", w5), "dof": w5.dof,
                                      "kappa_ref_fp64": kref5, **res5,
                                      "roofline": roofline(w5, res5[HEADLINE]["timed_leg"],
-                                                          "k_sweep_pass3<float>")}
+                                                          "k_sweep_pass3<float>", tsize=4)}
         line["extra_batch_64"] = batch(P, steps_x, warm_x)
         line["extra_fourier_batch_64"] = fourier_batch(P, max(a.steps, 3), warm_x)
         line["extra_modes_128"] = modes_compare(P, 11520, steps_x, warm_x)

@@ -172,6 +172,14 @@ typedef struct {
     int timing;
     int stop_rule;
     int accel;
+    /* Launch shape of the pass kernel (results do not depend on it; FP64 runs
+     * are bitwise the same).  waves_by_class[c - 1]: systems per workgroup of
+     * the launch over meshes with c = ceil(n[0] / 64) cells per lane (0..8,
+     * 0 = waves_per_group).  dispatch: 0 = each geometry's work items longest
+     * MFPs first (geometry by geometry); 1 = the longest-MFP items of every
+     * geometry of a launch first. */
+    int waves_by_class[4];
+    int dispatch;
 } obte_solve_opts;
 
 typedef struct {

@@ -39,21 +39,25 @@ def _worker(work, rank, n_workers, conn):
         _, T_L, T_w = msg
         TLp = np.zeros(me.n_solid)
         Twp = np.zeros(me.n_walls)
+        Jp = np.zeros((me.n_solid, mat.S.shape[2]))
         kml = {}
         for l in mine:
             for m in range(mat.n_mfp):
                 x = prob.lu(m, l).solve(prob.rhs(m, l, T_L, T_w))
                 TLp += mat.D[m, l] * x
+                Jp += x[:, None] * mat.S[m, l][None, :]
                 if me.n_walls:
                     Twp += prob.wout[:, m, l] * x[prob.wall_cell]
                 kml[(m, l)] = (prob.kappa_cc_system(m, l, x), prob.kappa_face_system(m, l, x))
-        conn.send((TLp, Twp, kml))
+        conn.send((TLp, Twp, Jp, kml))
 
 
 def source_iteration_parallel(work, n_workers=4, tol=1e-8, max_passes=2000, n_passes=None,
                               time_limit=None, verbose=False):
-    """Returns kappa_cc, kappa_face, kappa_fourier, T_L (mean-subtracted),
-    history, passes, and the timings of the factorisation and of each pass."""
+    """Returns kappa_cc, kappa_face, kappa_fourier, T_L (mean-subtracted), the
+    flux map J of the last pass (section Model: J_i = sum_ml S_ml T_iml, per
+    solid cell), history, passes, and the timings of the factorisation and of
+    each pass."""
     ctx = mp.get_context("fork")
     prob = Problem(work)
     me, mat = prob.mesh, prob.mat
@@ -81,12 +85,14 @@ def source_iteration_parallel(work, n_workers=4, tol=1e-8, max_passes=2000, n_pa
                 a.send(("pass", T_L, T_w))
             TL = np.zeros(me.n_solid)
             Tw = np.zeros(me.n_walls)
+            J = np.zeros((me.n_solid, mat.S.shape[2]))
             kml = np.zeros((mat.n_mfp, mat.n_dir))
             kfml = np.zeros((mat.n_mfp, mat.n_dir))
             for a in pipes:
-                TLp, Twp, parts = a.recv()
+                TLp, Twp, Jp, parts = a.recv()
                 TL += TLp
                 Tw += Twp
+                J += Jp
                 for (m, l), (kc, kf) in parts.items():
                     kml[m, l] = kc
                     kfml[m, l] = kf
@@ -118,6 +124,6 @@ def source_iteration_parallel(work, n_workers=4, tol=1e-8, max_passes=2000, n_pa
         for p in procs:
             p.join(timeout=10)
     return {"kappa_cc": hist[-1], "kappa_face": histf[-1], "kappa_fourier": kF,
-            "kappa_per_mfp": kml.sum(axis=1), "T_L": T_L - T_L.mean(), "history": np.asarray(hist),
+            "kappa_per_mfp": kml.sum(axis=1), "T_L": T_L - T_L.mean(), "J": J, "history": np.asarray(hist),
             "passes": len(hist), "converged": converged, "t_factor": t_factor,
             "pass_times": np.asarray(pass_times), "workers": n_workers}

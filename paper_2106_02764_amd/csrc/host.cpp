@@ -96,6 +96,7 @@ struct obte_mesh {
     std::vector<long long> sys_iters, sys_sweeps;   // per system, summed over the passes
     GeomDev host_view{};
     int last_precision = 0, last_waves = 0, last_max_outer = 0, last_keep = 0;
+    int last_waves_cls[4] = {0, 0, 0, 0}, last_dispatch = 0;
     // mode table (optional): per mode up to MODE_TERMS (system, weight) pairs
     // and its flux weight along the gradient axis; kappa_mu of the last solve
     int n_modes = 0;
@@ -491,6 +492,10 @@ obte_status check_opts(const obte_solve_opts* o) {
     if (!(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0)) return fail(OBTE_ERR_ARG, "inner_rtol must be in [0, 1)");
     if (o->stop_rule != 0 && o->stop_rule != 1) return fail(OBTE_ERR_ARG, "stop_rule must be 0 or 1");
     if (o->accel < 0 || o->accel > AA_MAX) return fail(OBTE_ERR_ARG, "accel must be in 0..%d", AA_MAX);
+    for (int c = 0; c < 4; ++c)
+        if (o->waves_by_class[c] < 0 || o->waves_by_class[c] > 8)
+            return fail(OBTE_ERR_ARG, "waves_by_class[%d] must be in 0..8", c);
+    if (o->dispatch != 0 && o->dispatch != 1) return fail(OBTE_ERR_ARG, "dispatch must be 0 or 1");
     return OBTE_OK;
 }
 
@@ -554,7 +559,8 @@ struct Run {
     // so a narrow geometry of a batch does not run the widest row's kernel
     int cls_first[5] = {}, cls_count[5] = {};
     size_t cls_lds[5] = {};
-    int waves = 4, nzmax = 1, precision = 0, accel = 0;
+    int cls_waves[5] = {4, 4, 4, 4, 4};   // systems per workgroup of each launch class
+    int nzmax = 1, precision = 0, accel = 0;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
     int max_cells = 0, max_walls = 0, max_solid = 0;
     // pinned host slots for the loop read-backs (two per loop, see
@@ -595,38 +601,43 @@ size_t run_state_bytes(size_t n_views, size_t n_items) {
     return align256(n_views * sizeof(GeomDev)) + align256(n_items * sizeof(Item)) + 256;
 }
 
-// Systems per workgroup of a launch over these meshes, and the LDS each of
-// its waves needs (the same rule for the workspace size and the solve).
-obte_status resolve_waves(const obte_mesh* const* meshes, int n, const obte_solve_opts* o, int* W_out,
-                          size_t* per_wave_out) {
-    int W = o->waves_per_group;
-    if (W == 0) {
-        W = auto_waves(meshes[0]);
+// Systems per workgroup of each cells-per-lane launch class (Wc[c], c = 1..4
+// = ceil(nx / 64)) over these meshes; the same rule for the workspace size
+// and the solve.  A class takes opts.waves_by_class[c - 1], else
+// waves_per_group, else the automatic choice; in 3D every wave of a group
+// needs nz rows of LDS, which bounds the class's W.
+obte_status resolve_waves(const obte_mesh* const* meshes, int n, const obte_solve_opts* o, int* Wc) {
+    int base = o->waves_per_group;
+    if (base == 0) {
+        base = auto_waves(meshes[0]);
         for (int i = 1; i < n; ++i)
-            if (auto_waves(meshes[i]) != W)
+            if (auto_waves(meshes[i]) != base)
                 return fail(OBTE_ERR_ARG, "meshes differ in their automatic waves_per_group; set it explicitly");
     }
-    size_t per_wave = 0;
-    {
-        int cpl = 1, nzm = 1;
-        for (int i = 0; i < n; ++i) {
-            cpl = std::max(cpl, (meshes[i]->nx + 63) / 64);
-            nzm = std::max(nzm, meshes[i]->nz);
-        }
+    int nzm = 1;
+    bool present[5] = {false, false, false, false, false};
+    for (int i = 0; i < n; ++i) {
+        nzm = std::max(nzm, meshes[i]->nz);
+        present[(meshes[i]->nx + 63) / 64] = true;
+    }
+    const size_t cap = 64 * 1024, tsz = o->precision == OBTE_FP32 ? 4 : 8;
+    for (int c = 1; c <= 4; ++c) {
+        const int set = o->waves_by_class[c - 1];
+        int W = set ? set : base;
         // 3D: one row per z-plane in the compute type (2D keeps its rows in
         // registers and needs no LDS)
-        if (nzm > 1) per_wave = (size_t)nzm * 64 * cpl * (o->precision == OBTE_FP32 ? 4 : 8);
-        const size_t cap = 64 * 1024;
-        if (per_wave > cap)
+        const size_t per_wave = nzm > 1 ? (size_t)nzm * 64 * c * tsz : 0;
+        if (present[c] && per_wave > cap)
             return fail(OBTE_ERR_ARG, "a wave needs %zu bytes of LDS (nx, nz too large; limit %zu)", per_wave, cap);
         const int wmax = per_wave > 0 ? (int)(cap / per_wave) : 8;
-        if (W > wmax) {
-            if (o->waves_per_group) return fail(OBTE_ERR_ARG, "waves_per_group %d needs more than 64 KiB of LDS (max %d)", W, wmax);
+        if (present[c] && W > wmax) {
+            if (set || o->waves_per_group)
+                return fail(OBTE_ERR_ARG, "%d systems per workgroup need more than 64 KiB of LDS (max %d)", W, wmax);
             W = wmax;
         }
+        Wc[c] = std::max(1, W);
     }
-    *W_out = W;
-    *per_wave_out = per_wave;
+    Wc[0] = Wc[1];
     return OBTE_OK;
 }
 
@@ -636,20 +647,20 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     R.precision = o->precision;
     R.accel = o->accel;
     for (int i = 0; i < n; ++i) R.gauge |= meshes[i]->n_modes > 0 ? 1 : 0;
-    int W = 0;
-    size_t per_wave = 0;
-    obte_status s = resolve_waves(meshes, n, o, &W, &per_wave);
+    int Wc[5];
+    obte_status s = resolve_waves(meshes, n, o, Wc);
     if (s != OBTE_OK) return s;
-    R.waves = W;
+    for (int c = 0; c < 5; ++c) R.cls_waves[c] = Wc[c];
     size_t off = 0;
     std::vector<Item> by_cls[5];
     for (int gi = 0; gi < n; ++gi) {
         obte_mesh* m = meshes[gi];
+        const int c = (m->nx + 63) / 64;
+        const int W = Wc[c];
         Layout L = make_layout(m, o, W);
         if (offsets) offsets->push_back(off);
         GeomDev v = make_view(m, ws + off, L, W, o->accel);
         const int ng = n_groups(m, W);
-        const int c = (m->nx + 63) / 64;
         // longest MFPs first: their systems take the most wrap iterations, so
         // the shorter ones dispatched after them fill in behind (a shorter
         // makespan than direction-major order; the results do not depend on it)
@@ -672,13 +683,17 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
     for (int gi = 0; gi < n; ++gi)
         if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
             return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
-    (void)per_wave;               // the LDS bound was checked by resolve_waves
     const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
     for (int c = 1; c <= 4; ++c) {
+        // dispatch = 1: the longest-MFP groups of every geometry first (the
+        // order is stable, so geometries and directions keep theirs)
+        if (o->dispatch == 1)
+            std::stable_sort(by_cls[c].begin(), by_cls[c].end(),
+                             [](const Item& a, const Item& b) { return a.m0 > b.m0; });
         R.cls_first[c] = (int)R.items.size();
         R.cls_count[c] = (int)by_cls[c].size();
         R.items.insert(R.items.end(), by_cls[c].begin(), by_cls[c].end());
-        R.cls_lds[c] = R.nzmax > 1 ? (size_t)W * R.nzmax * 64 * c * tsz : 0;
+        R.cls_lds[c] = R.nzmax > 1 ? (size_t)Wc[c] * R.nzmax * 64 * c * tsz : 0;
     }
     R.state_off = off;
     R.state_bytes = run_state_bytes(R.views.size(), R.items.size());
@@ -703,7 +718,7 @@ obte_status launch_sweeps(const Run& R, const PassParams& pp, hipStream_t st) {
     for (int c = 1; c <= 4; ++c)
         if (R.cls_count[c] > 0)
             HIPCHK(launch_sweep_pass(R.precision, c, R.nzmax, R.d_views, R.d_items + R.cls_first[c],
-                                     R.cls_count[c], R.waves, pp, R.cls_lds[c], st));
+                                     R.cls_count[c], R.cls_waves[c], pp, R.cls_lds[c], st));
     return OBTE_OK;
 }
 
@@ -804,7 +819,7 @@ obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st
     hipGraph_t graph = nullptr;
     if (K > 1) {
         const auto key = graph_key(R.d_views, R.d_items, (int)R.views.size(), R.cls_first, R.cls_count, R.cls_lds,
-                                   R.waves, R.precision, R.nzmax, R.max_cells, R.max_walls, R.gauge, R.accel,
+                                   R.cls_waves, R.precision, R.nzmax, R.max_cells, R.max_walls, R.gauge, R.accel,
                                    pp, K, tm && tm->on);
         obte_status s = slot_graph(slot, key, st, [&]() -> obte_status {
             obte_status sk = OBTE_OK;
@@ -929,7 +944,7 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
     }
     for (int i = 0; i < n; ++i) {
         obte_mesh* m = meshes[i];
-        Layout L = make_layout(m, o, R.waves);
+        Layout L = make_layout(m, o, R.cls_waves[1]);
         char* ws = (char*)workspace + offs[i];
         HIPCHK(hipMemcpy(m->d_geom, &R.views[i], sizeof(GeomDev), hipMemcpyHostToDevice));
         m->host_view = R.views[i];
@@ -1053,7 +1068,9 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         m->last_ws = workspace;
         m->last_sigma = sigma ? sigma[i] : nullptr;
         m->last_precision = o->precision;
-        m->last_waves = R.waves;
+        m->last_waves = R.cls_waves[(m->nx + 63) / 64];
+        for (int c = 0; c < 4; ++c) m->last_waves_cls[c] = R.cls_waves[c + 1];
+        m->last_dispatch = o->dispatch;
         m->last_max_outer = o->max_outer;
         m->last_keep = o->keep_state;
         obte_status si = OBTE_OK;
@@ -1122,6 +1139,8 @@ void obte_default_opts(obte_solve_opts* o) {
     o->timing = 0;
     o->stop_rule = 0;
     o->accel = 0;
+    for (int c = 0; c < 4; ++c) o->waves_by_class[c] = 0;
+    o->dispatch = 0;
 }
 
 obte_status obte_mesh_create(const obte_mesh_desc* d, obte_mesh** out) {
@@ -1408,12 +1427,12 @@ obte_status obte_workspace_size_batch(const obte_mesh* const* meshes, int n, con
         if (!meshes[i]) return fail(OBTE_ERR_ARG, "mesh %d is NULL", i);
         if (!meshes[i]->has_material) return fail(OBTE_ERR_STATE, "material not set on mesh %d", i);
     }
-    int W = 0;
-    size_t per_wave = 0;
-    s = resolve_waves(meshes, n, o, &W, &per_wave);
+    int Wc[5];
+    s = resolve_waves(meshes, n, o, Wc);
     if (s != OBTE_OK) return s;
     size_t total = 0, items = 0;
     for (int i = 0; i < n; ++i) {
+        const int W = Wc[(meshes[i]->nx + 63) / 64];
         total += align256(make_layout(meshes[i], o, W).total);
         items += (size_t)meshes[i]->n_dir * n_groups(meshes[i], W);
     }
@@ -1540,11 +1559,13 @@ obte_status obte_adjoint(obte_mesh* m, const obte_solve_opts* o, const double* s
     Run R;
     obte_solve_opts oo = *o;
     oo.waves_per_group = m->last_waves;
+    for (int c = 0; c < 4; ++c) oo.waves_by_class[c] = m->last_waves_cls[c];
+    oo.dispatch = m->last_dispatch;
     oo.keep_state = 1;
     obte_mesh* mp = m;
     s = build_run(R, &mp, 1, &oo, (char*)workspace, nullptr);
     if (s != OBTE_OK) return s;
-    Layout L = make_layout(m, &oo, R.waves);
+    Layout L = make_layout(m, &oo, R.cls_waves[1]);
     if (ws_bytes < R.state_off + R.state_bytes)
         return fail(OBTE_ERR_NOMEM, "workspace too small for the adjoint (accel deeper than the forward solve's?)");
     if ((s = upload_run(R, (char*)workspace)) != OBTE_OK) return s;

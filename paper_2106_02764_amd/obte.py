@@ -50,7 +50,8 @@ class obte_solve_opts(C.Structure):
                 ("waves_per_group", C.c_int), ("fourier_tol", C.c_double),
                 ("max_fourier", C.c_int), ("keep_state", C.c_int),
                 ("lag_wrap", C.c_int), ("inner_rtol", C.c_double), ("wrap_tol", C.c_double),
-                ("timing", C.c_int), ("stop_rule", C.c_int), ("accel", C.c_int)]
+                ("timing", C.c_int), ("stop_rule", C.c_int), ("accel", C.c_int),
+                ("waves_by_class", C.c_int * 4), ("dispatch", C.c_int)]
 
 
 class obte_stats(C.Structure):
@@ -143,6 +144,8 @@ def default_opts(**kw):
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k == "waves_by_class":
+            v = (C.c_int * 4)(*[int(x) for x in v])
         setattr(o, k, v)
     return o
 

@@ -2,13 +2,16 @@
 
 Calls only the CPU oracle (oracle/) on the seeded inputs (inputs/gen.py) and
 stores kappa_cc, kappa_face, kappa_fourier, per-MFP kappa and T_L at seeded
-sample cells.  Run:  python tests/golden/make_golden.py cfg2 [--workers 8]
+sample cells, and the full T_L and J fields (every cell; pores 0) in
+<config>_fields.npz.  Run:  python tests/golden/make_golden.py cfg2 [--workers 8]
 
 ``cfg5r_adjoint`` stores d kappa / d sigma of that replica at sigma = 1.
 ``cfg5r`` is the 3D membrane at 16x16x4 cells with the full direction and MFP
 sets (the reduced replica of the 64x64x16 case).
 ``cfg3`` stores kappa_cc / kappa_face of the members of the 64-geometry batch
-whose grids are 48x48 or 64x64 (the oracle's cost grows quickly with the grid).
+whose grids are 48x48 or 64x64 (the oracle's cost grows quickly with the grid);
+``cfg3big`` those of four larger members, one or more per row width of the
+GPU launch classes: 128x128 (#54), 192x192 (#12) and 256x256 (#15, #5).
 """
 import argparse
 import json
@@ -27,12 +30,14 @@ from oracle.parallel import source_iteration_parallel  # noqa: E402
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["cfg2", "cfg3", "cfg4", "cfg5r", "cfg5r_adjoint"])
+    ap.add_argument("config", choices=["cfg2", "cfg3", "cfg3big", "cfg4", "cfg5r", "cfg5r_adjoint"])
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-11)
     a = ap.parse_args()
     if a.config == "cfg3":
         return batch(a)
+    if a.config == "cfg3big":
+        return batch(a, members=BIG_MEMBERS, name="cfg3big")
     if a.config == "cfg5r_adjoint":
         return adjoint_replica(a)
     w = {"cfg2": gen.config2, "cfg4": gen.config4,
@@ -51,8 +56,15 @@ def main():
         "T_L_sample": [float(r["T_L"][i]) for i in pick],
         "history_tail": list(map(float, r["history"][-5:])),
         "seconds": time.time() - t0,
+        "fields": f"{a.config}_fields.npz",
     }
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{a.config}_oracle.json")
+    here = os.path.dirname(os.path.abspath(__file__))
+    T_full = np.zeros(w.n_cells)
+    T_full[cells] = r["T_L"]
+    J_full = np.zeros((w.n_cells, w.ndim))
+    J_full[cells] = r["J"]
+    np.savez_compressed(os.path.join(here, f"{a.config}_fields.npz"), T_L=T_full, J=J_full)
+    path = os.path.join(here, f"{a.config}_oracle.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path, out["kappa_cc"], out["passes"])
@@ -80,12 +92,18 @@ def adjoint_replica(a):
     print("wrote", path, r["kappa_cc"], ad["kappa_adj"])
 
 
-def batch(a):
+BIG_MEMBERS = (54, 12, 15, 5)
+
+
+def batch(a, members=None, name="cfg3"):
     geoms = gen.config3()
+    picked = members
     members = []
     t0 = time.time()
     for g, w in enumerate(geoms):
-        if w.n[0] > 64:
+        if picked is None and w.n[0] > 64:
+            continue
+        if picked is not None and g not in picked:
             continue
         r = source_iteration_parallel(w, n_workers=a.workers, tol=a.tol)
         h = r["history"]
@@ -94,9 +112,9 @@ def batch(a):
                         "kappa_face": r["kappa_face"], "kappa_fourier": r["kappa_fourier"],
                         "history_tail": list(map(float, h[-4:]))})
         print(g, w.n[0], r["passes"], r["kappa_cc"], flush=True)
-    out = {"config": "cfg3", "tol": a.tol, "members": members, "seconds": time.time() - t0,
+    out = {"config": name, "tol": a.tol, "members": members, "seconds": time.time() - t0,
            "source": "oracle.parallel.source_iteration_parallel (FP64, SuperLU per system)"}
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg3_oracle.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

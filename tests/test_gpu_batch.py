@@ -1,6 +1,8 @@
 """The 64-geometry batched launch (every geometry's systems in one launch per
 pass) against the oracle's stored values for its small members
-(tests/golden/cfg3_oracle.json), against single-geometry solves, and the
+(tests/golden/cfg3_oracle.json) and for four larger ones, 128x128 to 256x256,
+one or more per launch class of two to four cells per lane
+(tests/golden/cfg3big_oracle.json), against single-geometry solves, and the
 FP32-sweep form against FP64."""
 import json
 import os
@@ -13,6 +15,15 @@ from tests.gpu_common import require_gpu
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_oracle.json")
+GOLD_BIG = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3big_oracle.json")
+
+
+def members():
+    """Every member with an oracle value (small and large)."""
+    out = list(json.load(open(GOLD))["members"])
+    if os.path.exists(GOLD_BIG):
+        out += json.load(open(GOLD_BIG))["members"]
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +43,7 @@ def solvers(P, geoms):
 
 @pytest.fixture(scope="module")
 def k64(P, solvers):
-    o = P.default_opts(outer_tol=1e-12, inner_tol=1e-13, fourier_tol=1e-12, max_outer=6000)
+    o = P.default_opts(outer_tol=1e-13, inner_tol=1e-14, fourier_tol=1e-13, max_outer=8000, accel=8)
     k, st = P.solve_batch(solvers, o)
     assert all(s["status"] == 0 for s in st), [s["status"] for s in st]
     return np.asarray(k), st
@@ -40,15 +51,20 @@ def k64(P, solvers):
 
 def test_batch_fp64_vs_oracle(k64):
     k, st = k64
-    g = json.load(open(GOLD))
-    assert len(g["members"]) >= 8
-    for m in g["members"]:
-        # both sides stop at a 1e-12 relative change; the slowest members
-        # contract at ~0.97 per pass, fixed-point error ~3e-11 each
+    ms = members()
+    assert len(ms) >= 8 + (4 if os.path.exists(GOLD_BIG) else 0)
+    assert {128, 192, 256} <= {m["n"] for m in ms} or not os.path.exists(GOLD_BIG)
+    for m in ms:
+        # the oracle stops at a 1e-12 relative change (the slowest members
+        # contract at ~0.97 per pass: fixed-point error up to ~3e-11); the
+        # GPU at 1e-13 with mixing (error ~1e-13)
         ref = m["kappa_cc"]
-        assert abs(k[m["index"]] - ref) <= 1e-9 * ref, (m["index"], k[m["index"]], ref)
-        assert abs(st[m["index"]]["kappa_face"] - m["kappa_face"]) <= 1e-9 * m["kappa_face"]
-        assert abs(st[m["index"]]["kappa_fourier"] - m["kappa_fourier"]) <= 1e-9 * m["kappa_fourier"]
+        assert abs(k[m["index"]] - ref) <= 1e-10 * ref, (m["index"], k[m["index"]], ref)
+        # kappa_face (the upwind flux through one plane) settles more slowly
+        # than kappa_cc, which the oracle's stop test watches: measured up to
+        # 9e-10 off at the oracle's 1e-12 stop
+        assert abs(st[m["index"]]["kappa_face"] - m["kappa_face"]) <= 2e-9 * m["kappa_face"]
+        assert abs(st[m["index"]]["kappa_fourier"] - m["kappa_fourier"]) <= 1e-10 * m["kappa_fourier"]
 
 
 def test_batch_vs_single_fixed_passes(P, geoms, solvers):
@@ -77,8 +93,7 @@ def test_batch_fp32_vs_fp64(P, solvers, k64):
 @pytest.mark.parametrize("form", ["fp32", "fp64", "fp32_aa", "fp64_aa"])
 def test_bench_operating_points_batch(P, solvers, form):
     import bench
-    g = json.load(open(GOLD))
     k, st = P.solve_batch(solvers, P.default_opts(**bench.OP[form]))
     assert all(s["status"] == 0 for s in st)
-    for m in g["members"]:
+    for m in members():
         assert abs(k[m["index"]] - m["kappa_cc"]) <= 1e-4 * m["kappa_cc"], m["index"]

@@ -34,6 +34,7 @@ def test_parallel_matches_serial(name):
         assert np.max(np.abs(r["history"] - ref["history"])) <= 1e-13 * abs(ref["kappa_cc"])
         scale = np.max(np.abs(ref["T_L"]))
         assert np.max(np.abs(r["T_L"] - ref["T_L"])) <= 1e-13 * scale, workers
+        assert np.max(np.abs(r["J"] - ref["J"])) <= 1e-13 * np.max(np.abs(ref["J"])), workers
 
 
 def test_parallel_converged_stop_matches_serial():
