@@ -62,8 +62,8 @@ REF = dict(precision=0, outer_tol=1e-10, stop_rule=0, accel=8, inner_tol=1e-12, 
 # operating point, per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over one
 # solve, each scaled by the same counter on a plain 256 MiB copy); valid only
 # for the kernel source it was taken on.
-TRAFFIC = {"kernels_sha256": "20fec19db13a9f29bbfdd5e55b4ec4268560855d3d5497170bbc4a01a957acb1",
-           "fetch_bytes": 8683431, "write_bytes": 95372851}
+TRAFFIC = {"kernels_sha256": "a83012b465ca8d5d6e3a4dd094f9dc40080f43f5098068e2ea2eb0bff3a317ff",
+           "fetch_bytes": 8617387, "write_bytes": 59387360}
 
 
 def parse():
@@ -140,15 +140,19 @@ def leg(P, solver, w, name, steps, warmup, kref, kor):
     solves with HIP events around every launch on the library's stream
     (direct launches) for the per-kernel durations."""
     o = solver.opts(**OP[name])
+    # launch shape (systems per workgroup) from the tuner, outside the timing
+    choice = P.autotune.tune(solver, o)
+    P.autotune.apply(o, choice)
     r = run_solves(solver, o, steps, warmup)
-    ot = solver.opts(**OP[name], timing=1)
+    ot = P.autotune.apply(solver.opts(**OP[name], timing=1), choice)
     rt = run_solves(solver, ot, steps, 0)
     out = {"solves_per_s": steps / r["seconds"], "ms_per_solve": 1e3 * r["seconds"] / steps,
            "dof_per_s": w.dof * steps / r["seconds"], "kappa": r["kappa"], "status": r["status"],
            "passes_per_solve": r["outer_iters"] / steps, "sweeps_per_system_pass":
            r["sweeps"] / max(r["outer_iters"] * w.n_systems, 1),
            "kappa_rel_err_vs_fp64_ref": abs(r["kappa"] - kref) / abs(kref),
-           "opts": OP[name],
+           "opts": OP[name], "launch_shape": {"waves_by_class": choice["waves_by_class"],
+                                             "dispatch": choice["dispatch"]},
            "timed_leg": {"solves_per_s": steps / rt["seconds"], "sweep_ms": rt["sweep_ms"],
                          "reduce_ms": rt["reduce_ms"], "fourier_ms": rt["fourier_ms"],
                          "sweep_launches": rt["sweep_launches"], "sweeps": rt["sweeps"]}}
@@ -325,6 +329,45 @@ def adjoint_leg(P, name, steps, warmup):
     return out
 
 
+def apply_leg(P, name="cfg5", launches=20):
+    """The matrix-free upwind apply (Eq. (iter2) left-hand side) over every
+    system of a workload at once: y = (sigma + Lambda_m A_l) x for all (m, l),
+    x and y system-major over all cells.  HBM roofline: algorithmic bytes =
+    one read of x and one write of y per solid DoF (2 x sizeof(T)); the
+    arrays themselves also hold the pore cells (written 0)."""
+    import torch
+    w = make_workload(name)
+    s = P.Solver.from_workload(w)
+    ns, nc = w.n_systems, w.n_cells
+    ids = torch.arange(ns, dtype=torch.int32, device=s.device)
+    out = {"workload": describe(name, w), "systems": ns, "cells": nc, "solid_cells": w.n_solid}
+    for prec, tag in ((1, "fp32"), (0, "fp64")):
+        dt = torch.float32 if prec else torch.float64
+        gen_ = torch.Generator(device=s.device).manual_seed(7)
+        x = torch.randn(ns * nc, dtype=dt, device=s.device, generator=gen_)
+        y = torch.empty_like(x)
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            P.obte.obte_upwind_apply(s.mesh, prec, 0, None, ids, x, y, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(launches):
+            P.obte.obte_upwind_apply(s.mesh, prec, 0, None, ids, x, y, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / launches
+        tsz = 4 if prec else 8
+        alg = 2 * tsz * ns * w.n_solid
+        arr = 2 * tsz * ns * nc
+        out[tag] = {"avg_launch_ms": ms, "algorithmic_bytes_per_launch": alg,
+                    "roofline": {"bound": "hbm", "achieved": alg / ms / 1e6, "peak": PEAK["hbm_gbs"],
+                                 "unit": "GB/s", "frac": alg / ms / 1e6 / PEAK["hbm_gbs"]},
+                    "array_bytes_GBs": arr / ms / 1e6}
+        del x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_3d(P):
     """One adjoint pass of the 3D membrane at sigma = 1 (FP32 form, headline
     operating point) after its kept forward solve."""
@@ -407,8 +450,15 @@ def main():
         import paper_2106_02764_amd as P
         w = make_workload(a.workload)
         s = P.Solver.from_workload(w)
-        r = run_solves(s, s.opts(**OP[HEADLINE], timing=1), a.steps, 0)
-        print(json.dumps({"profile": a.workload, "kernels_sha256": kernels_sha(), **r}), flush=True)
+        # the bench's launch shape: read from the tuner's cache when a bench
+        # run wrote it (else tuned here, and those launches show up in a
+        # trace too)
+        choice = P.autotune.lookup(s, s.opts(**OP[HEADLINE])) or P.autotune.tune(s, s.opts(**OP[HEADLINE]))
+        o = P.autotune.apply(s.opts(**OP[HEADLINE], timing=1), choice)
+        r = run_solves(s, o, a.steps, 0)
+        print(json.dumps({"profile": a.workload, "kernels_sha256": kernels_sha(),
+                          "launch_shape": choice["waves_by_class"], "shape_from_cache": choice["from_cache"],
+                          **r}), flush=True)
         return
     w0 = make_workload(a.workload)
     cpu = None if a.no_cpu else cpu_baseline_measure(w0, a.cpu_seconds)
@@ -444,6 +494,7 @@ def main():
     if not a.no_extras:
         steps_x, warm_x = max(1, min(a.steps, 2)), 1
         line["extra_adjoint_3d"] = adjoint_3d(P)
+        line["extra_upwind_apply"] = apply_leg(P)
         w5, kref5, kor5, res5 = single(P, "cfg5", steps_x, warm_x)
         line["extra_3d_membrane"] = {"workload": describe("cfg5", w5), "dof": w5.dof,
                                      "kappa_ref_fp64": kref5, **res5,

@@ -31,8 +31,8 @@ def _copy(opts, **kw):
     return o
 
 
-def _key(solvers, opts):
-    dev = torch.cuda.get_device_name()
+def _key(solvers, opts, device=None):
+    dev = torch.cuda.get_device_name() if device is None else device
     shapes = sorted({(tuple(s.n), s.n_systems) for s in solvers})
     return (f"{dev}|{shapes}|prec{opts.precision}|rtol{opts.inner_rtol}|lag{opts.lag_wrap}"
             f"|accel{opts.accel}")
@@ -44,6 +44,19 @@ def _load(path):
             return json.load(f)
     except (OSError, ValueError):
         return {}
+
+
+def lookup(solvers, opts, cache_path=None):
+    """A cached choice for these meshes and options taken on any device, or
+    None (for processes that cannot read the device name, e.g. under a
+    profiler's tool library)."""
+    if not isinstance(solvers, (list, tuple)):
+        solvers = [solvers]
+    rest = _key(solvers, opts, device="").split("|", 1)[1]
+    for k, v in _load(cache_path or CACHE).items():
+        if k.split("|", 1)[1] == rest:
+            return dict(v, from_cache=True)
+    return None
 
 
 def classes(solvers):
@@ -79,7 +92,7 @@ def tune(solvers, opts, candidates=(1, 2, 4, 8), passes=4, use_cache=True, cache
     key = _key(solvers, opts)
     cache = _load(path) if use_cache else {}
     if key in cache:
-        return cache[key]
+        return dict(cache[key], from_cache=True)
     wc = [0, 0, 0, 0]
     best = measure(solvers, _copy(opts, waves_by_class=wc, dispatch=0), passes)
     timings = {"auto": best}
@@ -100,7 +113,8 @@ def tune(solvers, opts, candidates=(1, 2, 4, 8), passes=4, use_cache=True, cache
         timings["dispatch1"] = ms
         if ms < best:
             best, disp = ms, 1
-    choice = {"waves_by_class": wc, "dispatch": disp, "ms_per_pass_launch": best, "timings": timings}
+    choice = {"waves_by_class": wc, "dispatch": disp, "ms_per_pass_launch": best, "timings": timings,
+              "from_cache": False}
     if use_cache:
         cache = _load(path)
         cache[key] = choice

@@ -188,6 +188,27 @@ __device__ __forceinline__ SysC<T> make_sys(const GeomDev& g, int m, int l, int 
     return s;
 }
 
+// Upper bound of the gain of a system's wrap map G (inflow of the first row
+// -> mask * c_y * outflow of the last row, sources zero).  One row of the
+// sweep solves (D - C_in) x = c_y y, where D = sigma + sum c and C_in holds
+// the in-row (x, and z in 3D) upwind couplings: an M-matrix whose rows and
+// columns both exceed their off-diagonal sums by at least sigma_min + c_y.
+// So every row transfer has max- and 1-norm (hence 2-norm) at most
+// q = c_y / (sigma_min + c_y), walls and pores only lower it, and
+// |G r| <= q^ny |r| for the BiCGSTAB's 2-norm.  1 when sigma_min <= 0.
+// The sweep-free step is taken only where it cuts the wrap residual at least
+// tenfold: with a weaker cut (up to the forcing term 0.3) the mixed outer
+// iteration needed more passes (22 -> 26 on the 128x128 cell), which cost
+// more than the sweeps saved.
+constexpr double RICH_MAX = 0.1;
+
+template <typename T>
+__device__ __forceinline__ double wrap_gain_bound(const GeomDev& g, const SysC<T>& s) {
+    const double smin = g.fscal[5], cy = s.cd[1];
+    if (!(smin > 0.0)) return 1.0;
+    return pow(cy / (smin + cy), (double)g.ny);
+}
+
 template <typename T>
 __device__ __forceinline__ const T* sigma_ptr(const GeomDev& g);
 template <>
@@ -824,7 +845,14 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
         const double thr = fmax(pp.inner_tol * scale, pp.inner_rtol * rn);
         const double thr_final = pp.inner_tol * scale;
         if (rn > thr_final && scale > 0.0) need = 1;
-        if (rn > thr && scale > 0.0) {
+        const double rho_g = wrap_gain_bound(g, s);
+        if (rn > thr && scale > 0.0 && rho_g * rn <= fmin(thr, fmax(thr_final, RICH_MAX * rn))) {
+            // a weakly coupled wrap (short MFP along y): e = r leaves the
+            // residual G r, at most rho_g |r|, within this pass's target and
+            // below RICH_MAX |r| (or the final tolerance), with no sweep
+            VLOOP(du[k][c] = r[k][c]);
+            rn = rho_g * rn;
+        } else if (rn > thr && scale > 0.0) {
             // BiCGSTAB for the remaining correction: (I - G) e = r.  A capped
             // BiCGSTAB is not monotone, so the iterate with the smallest
             // residual is kept: a pass never increases the wrap residual.
@@ -998,7 +1026,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
         const double thr = fmax(pp.inner_tol * scale, pp.inner_rtol * rn);
         const double thr_final = pp.inner_tol * scale;
         if (rn > thr_final && scale > 0.0) need = 1;
-        if (rn > thr && scale > 0.0) {
+        const double rho_g = wrap_gain_bound(g, s);
+        if (rn > thr && scale > 0.0 && rho_g * rn <= fmin(thr, fmax(thr_final, RICH_MAX * rn))) {
+            // weakly coupled wrap: e = r, no sweep (as in 2D)
+            PLOOP(du[i] = r[i]);
+            rn = rho_g * rn;
+        } else if (rn > thr && scale > 0.0) {
             // BiCGSTAB on (I - G) e = r with the best iterate kept (as in 2D)
             PLOOP({ e[i] = T(0); eb[i] = T(0); rh[i] = r[i]; p[i] = T(0); v[i] = T(0); });
             double best = rn;
@@ -1961,41 +1994,6 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_fill(const GeomDev* __re
     }
 }
 
-// ---------------------------------------------------------------------------
-// Matrix-free upwind apply y = (sigma + Lambda_m A_l) x (or A_l^T) for a set
-// of systems; one thread per (cell, system), cell-major within a system so
-// the x-neighbour loads are coalesced and the y-neighbour row comes from L2.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_apply(const GeomDev* __restrict__ gp, const double* __restrict__ sigma,
-                        const int* __restrict__ sys_ids, int n_sys, const T* __restrict__ x,
-                        T* __restrict__ y, int transpose) {
-    const GeomDev& g = *gp;
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    const int si = blockIdx.y;
-    if (cell >= g.ncells || si >= n_sys) return;
-    const int sys = sys_ids[si];
-    const uint16_t w = g.fc[cell];
-    const size_t off = (size_t)si * g.ncells;
-    if (!fc_solid(w) || sys < 0 || sys >= g.n_sys) { y[off + cell] = T(0); return; }
-    const int m = sys / g.n_dir, l = sys % g.n_dir;
-    const double lam = g.mfp[m];
-    const double sg = sigma ? sigma[cell] : 1.0;
-    const T xc = x[off + cell];
-    double acc = sg * (double)xc;
-    for (int a = 0; a < g.ndim; ++a) {
-        double sa = g.dirs[l * 3 + a];
-        if (transpose) sa = -sa;
-        if (sa == 0.0) continue;
-        const double ca = lam * fabs(sa) / g.h[a];
-        acc += ca * (double)xc;
-        const int fin = 2 * a + (sa > 0.0 ? 0 : 1);
-        if (fc_class(w, fin) != FC_WALL) acc -= ca * (double)x[off + nbr_cell(g, cell, fin)];
-    }
-    y[off + cell] = (T)acc;
-}
-
-
 // sigma per cell (1 where not given or in pores) and its float copy; the
 // pore entries of the per-cell pass arrays, which the reduction and the
 // mixing never write, are set to 0 (the solid entries are left as they are,
@@ -2023,6 +2021,20 @@ __global__ void k_prep_sigma(const GeomDev* __restrict__ gp, const double* __res
             }
         }
     }
+}
+
+// Smallest sigma over the solid cells into fscal[5] (one block, after
+// k_prep_sigma).  The pass kernels bound the gain of a system's wrap map with
+// it (see wrap_gain_bound).
+__global__ void __launch_bounds__(256) k_sigma_min(const GeomDev* __restrict__ gp) {
+    __shared__ double red[4];
+    const GeomDev& g = *gp;
+    double v = INFINITY;
+    for (int j = threadIdx.x; j < g.nsolid; j += blockDim.x) v = fmin(v, g.sigma[g.scell[j]]);
+    for (int m = 32; m >= 1; m >>= 1) v = fmin(v, shfl_xor(v, m));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) g.fscal[5] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
 // Flux map of one geometry from the stored solutions of the replayed last
@@ -2380,20 +2392,6 @@ hipError_t launch_anderson(const GeomDev* geoms_dev, int n_geoms, int max_naa, P
     return hipGetLastError();
 }
 
-hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, const GeomDev& g_host,
-                        const double* sigma, const int* sys_ids, int n_sys, const void* x, void* y,
-                        hipStream_t st) {
-    dim3 grid((g_host.ncells + 255) / 256, n_sys);
-    (void)hipGetLastError();
-    if (precision == 0)
-        hipLaunchKernelGGL(k_apply<double>, grid, dim3(256), 0, st, g_dev, sigma, sys_ids, n_sys,
-                           (const double*)x, (double*)y, transpose);
-    else
-        hipLaunchKernelGGL(k_apply<float>, grid, dim3(256), 0, st, g_dev, sigma, sys_ids, n_sys,
-                           (const float*)x, (float*)y, transpose);
-    return hipGetLastError();
-}
-
 hipError_t launch_energy(const GeomDev* geom_dev, int precision, int nsolid, hipStream_t st) {
     const int blocks = nsolid > 0 ? (nsolid + 63) / 64 : 1;
     (void)hipGetLastError();
@@ -2408,6 +2406,7 @@ hipError_t launch_prep_sigma(const GeomDev* g_dev, int ncells, const double* sig
     if (blocks > 1024) blocks = 1024;
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_prep_sigma, dim3(blocks), dim3(256), 0, st, g_dev, sig);
+    hipLaunchKernelGGL(k_sigma_min, dim3(1), dim3(256), 0, st, g_dev);
     return hipGetLastError();
 }
 

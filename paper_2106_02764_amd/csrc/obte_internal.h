@@ -60,7 +60,8 @@ struct GeomDev {
     int* ctrl;                   // CTRL_N ints
     double* fx;                  // Fourier CG vectors: 4 * ncells
     double* fscal;               // scalars: [0] kappa_F, [1] CG iterations, [2] CG residual,
-                                 // [3] mixing error estimate, [4] energy residual of the last pass
+                                 // [3] mixing error estimate, [4] energy residual of the last pass,
+                                 // [5] smallest sigma over the solid cells
     double* Tstore;              // n_sys * nsolid (adjoint forward state) or null
     double* lam_psi;             // adjoint: 2 * ncells (double buffered Psi)
     double* lam_phi;             // adjoint: 2 * nwalls (double buffered Phi)

@@ -37,6 +37,7 @@ def test_tuned_shape_cached_and_bitwise_neutral(P, tmp_path, monkeypatch):
     n = len(calls)
     again = P.autotune.tune(solvers, o, cache_path=cache)
     assert len(calls) == n                    # served from the cache, nothing timed
+    assert again["from_cache"] and not choice["from_cache"]
     assert again["waves_by_class"] == choice["waves_by_class"] and again["dispatch"] == choice["dispatch"]
     k0, st0 = P.solve_batch(solvers, o)
     ot = P.autotune.apply(P.default_opts(**{f: getattr(o, f) for f, _ in o._fields_}), choice)

@@ -64,14 +64,20 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("name", ["cfg1", "ragged", "3d", "3d_wide"])
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "3d", "3d_wide", "3d_membrane"])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_upwind_apply(P, name, prec):
+@pytest.mark.parametrize("many", [False, True])
+def test_upwind_apply(P, name, prec, many):
+    """Rows of a multiple of four cells (cfg1, the membrane) take the
+    four-cells-per-thread kernel, the others the one-cell kernel; `many`
+    spans several system groups per launch with a partial last group."""
     w = CASES[name]()
     prob = Problem(w)
     s = P.Solver.from_workload(w)
     rng = np.random.default_rng(5)
     ids = [0, w.n_systems - 1, w.n_systems // 2 + 1, 3]
+    if many:
+        ids = list(rng.permutation(w.n_systems)[:min(w.n_systems, 29)])
     X = np.zeros((len(ids), w.n_cells))
     for k in range(len(ids)):
         X[k, prob.mesh.cells] = rng.standard_normal(prob.mesh.n_solid)
