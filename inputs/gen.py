@@ -343,4 +343,112 @@ def with_modes(w: Workload, n_modes: int, seed: int,
     return dataclasses.replace(w, modes=(F, alpha), name=w.name + f"_modes{n_modes}")
 
 
+# ---------------------------------------------------------------------------
+# Unstructured (non-orthogonal) 2D meshes.  The paper meshes its geometries
+# with GMSH Delaunay triangles (section "Geometry module"); there is no mesher
+# here, so a periodic node lattice is displaced by a smooth periodic field
+# (distorted quadrilaterals, or triangles from splitting each quadrilateral
+# along alternating diagonals).  Only node positions and connectivity are
+# produced: areas, centroids, normals and every operator are the consumers'.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class UWorkload:
+    """A periodic 2D cell meshed by polygons (counter-clockwise node lists).
+
+    nodes:  (n_nodes, 2) positions in metres, inside [0, Lx) x [0, Ly) before
+            the displacement;
+    cells:  (n_cells, nv) node ids (nv = 3 or 4);
+    shifts: (n_cells, nv, 2) periodic image of each corner: the corner lies at
+            nodes[id] + shifts * (Lx, Ly);
+    solid:  (n_cells,) uint8 (0 = pore).
+    Both axes are periodic; the applied difference dT is along grad_axis."""
+
+    name: str
+    L: tuple
+    nodes: np.ndarray
+    cells: np.ndarray
+    shifts: np.ndarray
+    solid: np.ndarray
+    grad_axis: int
+    dT: float
+    mfp: np.ndarray
+    kappa_m: np.ndarray
+    dirs: np.ndarray
+    dir_w: np.ndarray
+    sigma: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+    ndim: int = 2
+
+    @property
+    def n_cells(self) -> int:
+        return int(len(self.cells))
+
+    @property
+    def n_solid(self) -> int:
+        return int(self.solid.sum())
+
+    @property
+    def n_systems(self) -> int:
+        return int(len(self.mfp) * len(self.dirs))
+
+
+def unstructured_2d(nx: int, ny: int, L: float = 100 * NM, Ly: float | None = None, amp: float = 0.25,
+                    tri: bool = True, seed: int = 0, pores=(), n_dir: int = 8, n_mfp: int = 3,
+                    mfp_lo: float = 1 * NM, mfp_hi: float = 10e-6, grad_axis: int = 0,
+                    sigma=None) -> UWorkload:
+    """nx x ny node lattice displaced by amp * h times a seeded sum of four
+    periodic Fourier modes (amp = 0: the orthogonal grid); quadrilaterals, or
+    two triangles per quadrilateral.  pores: ((cx, cy), r) circles (with
+    periodic images) removing the cells whose undisplaced centre lies inside."""
+    Ly = L if Ly is None else Ly
+    hx, hy = L / nx, Ly / ny
+    rng = np.random.default_rng([2106027646, seed])
+    I, J = np.meshgrid(np.arange(nx), np.arange(ny))
+    X0, Y0 = I.ravel() * hx, J.ravel() * hy
+    disp = np.zeros((nx * ny, 2))
+    if amp:
+        for axis, h in ((0, hx), (1, hy)):
+            f = np.zeros(nx * ny)
+            for p, q in ((1, 0), (0, 1), (1, 1), (2, 1)):
+                a, ph = rng.uniform(-1, 1), rng.uniform(0, 2 * np.pi)
+                f += a * np.sin(2 * np.pi * (p * X0 / L + q * Y0 / Ly) + ph)
+            disp[:, axis] = amp * h * f / max(np.max(np.abs(f)), 1e-300)
+    nodes = np.stack([X0, Y0], axis=1) + disp
+
+    def corner(i, j):
+        return (i % nx) + nx * (j % ny), (i // nx, j // ny)
+
+    cells, shifts, centres = [], [], []
+    for j in range(ny):
+        for i in range(nx):
+            q = [(i, j), (i + 1, j), (i + 1, j + 1), (i, j + 1)]
+            if tri:
+                if (i + j) % 2 == 0:
+                    polys = [[q[0], q[1], q[2]], [q[0], q[2], q[3]]]
+                else:
+                    polys = [[q[0], q[1], q[3]], [q[1], q[2], q[3]]]
+            else:
+                polys = [q]
+            for poly in polys:
+                ids, sh = zip(*(corner(a, b) for a, b in poly))
+                cells.append(ids)
+                shifts.append(sh)
+                centres.append(np.mean([(a * hx, b * hy) for a, b in poly], axis=0))
+    cells = np.asarray(cells, np.int64)
+    shifts = np.asarray(shifts, np.int64)
+    centres = np.asarray(centres)
+    pore = np.zeros(len(cells), bool)
+    for (cx, cy), r in pores:
+        for ox in (-L, 0.0, L):
+            for oy in (-Ly, 0.0, Ly):
+                pore |= (centres[:, 0] - cx - ox) ** 2 + (centres[:, 1] - cy - oy) ** 2 < r * r
+    mfp = mfp_grid(n_mfp, mfp_lo, mfp_hi)
+    dirs, w = directions_2d(n_dir)
+    return UWorkload(f"u{'tri' if tri else 'quad'}_{nx}x{ny}_a{amp:g}", (L, Ly), nodes, cells, shifts,
+                     (~pore).astype(np.uint8), grad_axis, 1.0, mfp, lognormal_kernel(mfp), dirs, w,
+                     sigma=None if sigma is None else np.asarray(sigma, float).ravel(),
+                     meta={"nx": nx, "ny": ny, "amp": amp, "tri": tri, "seed": seed})
+
+
 CONFIGS = {"cfg1": config1, "cfg2": config2, "cfg4": config4, "cfg5": config5}

@@ -20,7 +20,10 @@ factorisation per (MFP, direction) system reused across passes as the paper
 does.  Also: the dense brute-force solve of the whole coupled system for tiny
 meshes, kappa definitions, and the adjoint d kappa / d sigma.
 
-Modules: material (row a1), mesh (a2), fourier (a3), bte (a4-a8), adjoint (a9).
+Modules: material (row a1), mesh (a2), fourier (a3), bte (a4-a8), adjoint (a9),
+umesh (unstructured 2D meshes: the upwind operator from general face vectors
+and the heat-conduction first guess with the explicit non-orthogonal
+correction of Appendix B).
 """
 from .material import Material, material_weights, wall_weights
 from .mesh import Mesh
@@ -33,3 +36,4 @@ __all__ = [
     "Problem", "source_iteration", "dense_solve", "kappa_cc", "kappa_face", "flux_map",
     "adjoint_source_iteration", "adjoint_dense", "gradient_from",
 ]
+from .umesh import UMesh, UProblem, fourier_nonorth, upwind_operator_u, dense_solve_u

@@ -166,7 +166,9 @@ def source_iteration(prob, tol=1e-8, max_passes=2000, n_passes=None, T_L0=None, 
     """Algorithm 1.  Returns a dict with kappa_cc (primary), kappa_face,
     kappa_fourier, T_L (mean over solid cells subtracted), J, history, T."""
     me, mat = prob.mesh, prob.mat
-    T_F, kF = fourier_solve(me, mat.kappa_axis)
+    # the first guess: the problem's own heat-conduction solve where it has
+    # one (unstructured meshes), else the orthogonal-grid one
+    T_F, kF = prob.fourier() if hasattr(prob, "fourier") else fourier_solve(me, mat.kappa_axis)
     T_L = T_F.copy() if T_L0 is None else np.asarray(T_L0, float).copy()
     if T_w0 is not None:
         T_w = np.asarray(T_w0, float).copy()
