@@ -19,6 +19,16 @@ namespace {
 // ---------------------------------------------------------------------------
 constexpr int APPLY_SYS = 8;
 
+// The dispatcher hands consecutive workgroups to the eight XCDs in turn.
+// Give each XCD a contiguous range of the logical (system group, cell tile)
+// order instead, so the tiles one block's neighbour loads reach (the row and
+// plane before, same system) were fetched into the same XCD's L2.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_order(int w, int n) {
+    const int per = n / N_XCD;
+    return w < per * N_XCD ? (w % N_XCD) * per + w / N_XCD : w;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply(const GeomDev* __restrict__ gp, const double* __restrict__ sigma,
                                                const int* __restrict__ sys_ids, int n_sys,
@@ -27,7 +37,10 @@ __global__ void __launch_bounds__(256) k_apply(const GeomDev* __restrict__ gp, c
     __shared__ int from_plus[APPLY_SYS][3]; // 1: the upwind neighbour along a is on the + side
     __shared__ int valid[APPLY_SYS];
     const GeomDev& g = *gp;
-    const int s0 = blockIdx.y * APPLY_SYS;
+    const int tiles = (g.ncells + 255) / 256;
+    const int lb = xcd_order(blockIdx.x, gridDim.x);
+    const int tile = lb % tiles;
+    const int s0 = (lb / tiles) * APPLY_SYS;
     const int ns = min(APPLY_SYS, n_sys - s0);
     if (threadIdx.x < APPLY_SYS * 3) {
         const int k = threadIdx.x / 3, a = threadIdx.x % 3;
@@ -47,7 +60,7 @@ __global__ void __launch_bounds__(256) k_apply(const GeomDev* __restrict__ gp, c
         if (a == 0) valid[k] = ok;
     }
     __syncthreads();
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cell = tile * blockDim.x + threadIdx.x;
     if (cell >= g.ncells) return;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const uint16_t w = g.fc[cell];
@@ -112,7 +125,10 @@ __global__ void __launch_bounds__(256) k_apply4(const GeomDev* __restrict__ gp, 
     __shared__ int from_plus[NS][3];
     __shared__ int valid[NS];
     const GeomDev& g = *gp;
-    const int s0 = blockIdx.y * NS;
+    const int tiles = (g.ncells / 4 + 255) / 256;
+    const int lb = xcd_order(blockIdx.x, gridDim.x);
+    const int tile = lb % tiles;
+    const int s0 = (lb / tiles) * NS;
     const int ns = min(NS, n_sys - s0);
     if (threadIdx.x < NS * 3) {
         const int k = threadIdx.x / 3, a = threadIdx.x % 3;
@@ -132,7 +148,7 @@ __global__ void __launch_bounds__(256) k_apply4(const GeomDev* __restrict__ gp, 
         if (a == 0) valid[k] = ok;
     }
     __syncthreads();
-    const int c0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int c0 = 4 * (tile * blockDim.x + threadIdx.x);
     if (c0 >= g.ncells) return;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const bool d3 = g.ndim == 3;
@@ -201,16 +217,16 @@ hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, cons
         const int nq = g_host.ncells / 4;
         if (precision == 0) {
             constexpr int NS = 4;
-            hipLaunchKernelGGL((k_apply4<double, NS>), dim3((nq + 255) / 256, (n_sys + NS - 1) / NS), dim3(256), 0,
+            hipLaunchKernelGGL((k_apply4<double, NS>), dim3((nq + 255) / 256 * ((n_sys + NS - 1) / NS)), dim3(256), 0,
                                st, g_dev, sigma, sys_ids, n_sys, (const double*)x, (double*)y, transpose);
         } else {
             constexpr int NS = 8;
-            hipLaunchKernelGGL((k_apply4<float, NS>), dim3((nq + 255) / 256, (n_sys + NS - 1) / NS), dim3(256), 0,
+            hipLaunchKernelGGL((k_apply4<float, NS>), dim3((nq + 255) / 256 * ((n_sys + NS - 1) / NS)), dim3(256), 0,
                                st, g_dev, sigma, sys_ids, n_sys, (const float*)x, (float*)y, transpose);
         }
         return hipGetLastError();
     }
-    dim3 grid((g_host.ncells + 255) / 256, (n_sys + APPLY_SYS - 1) / APPLY_SYS);
+    dim3 grid((g_host.ncells + 255) / 256 * ((n_sys + APPLY_SYS - 1) / APPLY_SYS));
     if (precision == 0)
         hipLaunchKernelGGL(k_apply<double>, grid, dim3(256), 0, st, g_dev, sigma, sys_ids, n_sys,
                            (const double*)x, (double*)y, transpose);

@@ -375,7 +375,7 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     // the state a resumed solve reads (above, and U) keeps its place
     L.U = take(2 * (size_t)m->n_sys * nwrap * tsz);
     L.kry = m->nz > 1 ? take((size_t)m->n_sys * KRY3_VECS * nwrap * tsz) : 0;
-    const size_t nsol = (size_t)m->nsolid;
+    const size_t nsol = x_stride(m->nsolid);
     L.Tstore = o->keep_state ? take((size_t)m->n_sys * nsol * 8) : 0;
     L.X = take((size_t)m->n_sys * nsol * tsz);
     // last: the mixing history (an adjoint may use another depth than the
@@ -398,6 +398,7 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
     g.aa_m = accel;
     g.nx = m->nx; g.ny = m->ny; g.nz = m->nz; g.ndim = m->ndim; g.nf = m->nf;
     g.ncells = m->ncells; g.nwalls = m->nwalls; g.nwrap = m->nx * m->nz; g.nsolid = m->nsolid;
+    g.xs = (int)x_stride(m->nsolid);
     for (int a = 0; a < 3; ++a) { g.periodic[a] = m->periodic[a]; g.h[a] = m->h[a]; g.L[a] = m->L[a]; }
     g.grad_axis = m->grad_axis;
     g.dT = m->dT;
@@ -1115,6 +1116,9 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// the unstructured-mesh driver reports through the same per-thread message
+void obte_set_error(const char* msg) { g_err = msg; }
+
 extern "C" {
 
 const char* obte_last_error(void) { return g_err.c_str(); }

@@ -753,8 +753,8 @@ __device__ __forceinline__ Red<T> make_red(const GeomDev& g, const SysC<T>& s, i
     rd.kacc = 0.0;
     rd.kface = 0.0;
     rd.on = active;
-    rd.X = make_rsrc(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.nsolid, (uint32_t)g.nsolid * (uint32_t)sizeof(T));
-    rd.Tstore = make_rsrc(g.Tstore ? g.Tstore + (size_t)s.sys * g.nsolid : nullptr,
+    rd.X = make_rsrc(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.xs, (uint32_t)g.nsolid * (uint32_t)sizeof(T));
+    rd.Tstore = make_rsrc(g.Tstore ? g.Tstore + (size_t)s.sys * g.xs : nullptr,
                           g.Tstore ? (uint32_t)g.nsolid * 8u : 0u);
     rd.store_T = pp.store_T && g.Tstore != nullptr;
     return rd;
@@ -1157,7 +1157,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
     const int pass = g.ctrl[CTRL_PASS];
     const int out = (pass + 1) & 1;
     const int adj = pp.adjoint;
-    const int nc = g.ncells, nf = g.nf, ns = g.n_sys, nd = g.n_dir, nsol = g.nsolid;
+    const int nc = g.ncells, nf = g.nf, ns = g.n_sys, nd = g.n_dir, nsol = g.nsolid, xs = g.xs;
     if ((int)blockIdx.x * 64 >= nsol) return;          // block-uniform
     const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
     const gptr_t<double> D = gview(g.Dw);
@@ -1187,7 +1187,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
                 for (; i + 7 < i1; i += 8) {
                     double xv[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nsol + j];
+                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * xs + j];
                     a0 += xv[0];
                     a1 += xv[1];
                     a2 += xv[2];
@@ -1198,17 +1198,17 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
                     a3 += xv[7];
                 }
                 for (; i + 3 < i1; i += 4) {
-                    a0 += (double)X[(size_t)i * nsol + j];
-                    a1 += (double)X[(size_t)(i + 1) * nsol + j];
-                    a2 += (double)X[(size_t)(i + 2) * nsol + j];
-                    a3 += (double)X[(size_t)(i + 3) * nsol + j];
+                    a0 += (double)X[(size_t)i * xs + j];
+                    a1 += (double)X[(size_t)(i + 1) * xs + j];
+                    a2 += (double)X[(size_t)(i + 2) * xs + j];
+                    a3 += (double)X[(size_t)(i + 3) * xs + j];
                 }
-                for (; i < i1; ++i) a0 += (double)X[(size_t)i * nsol + j];
+                for (; i < i1; ++i) a0 += (double)X[(size_t)i * xs + j];
             } else {
                 for (; i + 7 < i1; i += 8) {
                     double xv[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nsol + j];
+                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * xs + j];
                     a0 += D[i] * xv[0];
                     a1 += D[i + 1] * xv[1];
                     a2 += D[i + 2] * xv[2];
@@ -1219,12 +1219,12 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
                     a3 += D[i + 7] * xv[7];
                 }
                 for (; i + 3 < i1; i += 4) {
-                    a0 += D[i] * (double)X[(size_t)i * nsol + j];
-                    a1 += D[i + 1] * (double)X[(size_t)(i + 1) * nsol + j];
-                    a2 += D[i + 2] * (double)X[(size_t)(i + 2) * nsol + j];
-                    a3 += D[i + 3] * (double)X[(size_t)(i + 3) * nsol + j];
+                    a0 += D[i] * (double)X[(size_t)i * xs + j];
+                    a1 += D[i + 1] * (double)X[(size_t)(i + 1) * xs + j];
+                    a2 += D[i + 2] * (double)X[(size_t)(i + 2) * xs + j];
+                    a3 += D[i + 3] * (double)X[(size_t)(i + 3) * xs + j];
                 }
-                for (; i < i1; ++i) a0 += D[i] * (double)X[(size_t)i * nsol + j];
+                for (; i < i1; ++i) a0 += D[i] * (double)X[(size_t)i * xs + j];
             }
         }
     } else {
@@ -1266,7 +1266,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
 #pragma unroll
                 for (int u = 0; u < 8; ++u) dv[u] = D[i + u];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * nsol + js];
+                for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * xs + js];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     xv[u] = in ? xv[u] : 0.0;
@@ -1294,7 +1294,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
 #pragma unroll
                 for (int u = 0; u < 4; ++u) dv[u] = D[i + u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) xv[u] = (double)X[(size_t)(i + u) * nsol + js];
+                for (int u = 0; u < 4; ++u) xv[u] = (double)X[(size_t)(i + u) * xs + js];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     xv[u] = in ? xv[u] : 0.0;
@@ -1314,7 +1314,7 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
             }
             for (; u0 < nb; ++u0) {
                 const int i = ib + u0;
-                const double xr = (double)X[(size_t)i * nsol + js];
+                const double xr = (double)X[(size_t)i * xs + js];
                 const double x = in ? xr : 0.0;
                 a0 += adj ? x : D[i] * x;
 #pragma unroll
@@ -1998,13 +1998,16 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_fill(const GeomDev* __re
 // pore entries of the per-cell pass arrays, which the reduction and the
 // mixing never write, are set to 0 (the solid entries are left as they are,
 // so a resumed solve keeps its state).
-__global__ void k_prep_sigma(const GeomDev* __restrict__ gp, const double* __restrict__ sig_in) {
+__global__ void __launch_bounds__(256) k_prep_sigma(const GeomDev* __restrict__ gp, const double* __restrict__ sig_in) {
+    __shared__ double red[4];
     const GeomDev& g = *gp;
     const int nc = g.ncells;
+    double vmin = INFINITY;         // smallest sigma over this block's solid cells
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
         const bool sol = fc_solid(g.fc[c]);
         double v = 1.0;
         if (sig_in && sol) v = sig_in[c];
+        if (sol) vmin = fmin(vmin, v);
         g.sigma[c] = v;
         g.sigma_f[c] = (float)v;
         if (!sol) {
@@ -2021,16 +2024,20 @@ __global__ void k_prep_sigma(const GeomDev* __restrict__ gp, const double* __res
             }
         }
     }
+    for (int m = 32; m >= 1; m >>= 1) vmin = fmin(vmin, shfl_xor(vmin, m));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = vmin;
+    __syncthreads();
+    if (threadIdx.x == 0) g.fx[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
-// Smallest sigma over the solid cells into fscal[5] (one block, after
-// k_prep_sigma).  The pass kernels bound the gain of a system's wrap map with
-// it (see wrap_gain_bound).
-__global__ void __launch_bounds__(256) k_sigma_min(const GeomDev* __restrict__ gp) {
+// Smallest sigma over the solid cells into fscal[5]: the minimum of the
+// per-block minima k_prep_sigma left in fx (one block).  The pass kernels
+// bound the gain of a system's wrap map with it (see wrap_gain_bound).
+__global__ void __launch_bounds__(256) k_sigma_min(const GeomDev* __restrict__ gp, int nblocks) {
     __shared__ double red[4];
     const GeomDev& g = *gp;
     double v = INFINITY;
-    for (int j = threadIdx.x; j < g.nsolid; j += blockDim.x) v = fmin(v, g.sigma[g.scell[j]]);
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v = fmin(v, g.fx[b]);
     for (int m = 32; m >= 1; m >>= 1) v = fmin(v, shfl_xor(v, m));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -2049,7 +2056,7 @@ __global__ void __launch_bounds__(256) k_flux(const GeomDev* __restrict__ gp, do
     double j[3] = {0.0, 0.0, 0.0};
     if (i >= 0)
         for (int sys = 0; sys < g.n_sys; ++sys) {
-            const double x = (double)X[(size_t)sys * g.nsolid + i];
+            const double x = (double)X[(size_t)sys * g.xs + i];
 #pragma unroll
             for (int a = 0; a < 3; ++a) j[a] += g.S[sys * 3 + a] * x;
         }
@@ -2069,7 +2076,7 @@ __global__ void __launch_bounds__(256) k_grad(const GeomDev* __restrict__ gp, do
     double acc = 0.0;
     if (i >= 0)
         for (int sys = 0; sys < g.n_sys; ++sys) {
-            const size_t e = (size_t)sys * g.nsolid + i;
+            const size_t e = (size_t)sys * g.xs + i;
             acc += (double)X[e] * (g.Tstore[e] - tl);
         }
     grad_out[c] = i >= 0 ? -acc : 0.0;
@@ -2082,37 +2089,54 @@ __global__ void __launch_bounds__(256) k_grad(const GeomDev* __restrict__ gp, do
 // the mean weighted magnitude sum alpha sum_i sum_ml D_ml |T_iml| / N_solid;
 // sum alpha cancels.  One block per 64 solid cells writes its maximum and its
 // sum; k_energy_finish combines them in a fixed order into fscal[4].
+constexpr int EQ = 16;      // waves per energy block: system chunks of one 64-cell strip
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_energy(const GeomDev* __restrict__ gp) {
-    __shared__ double pm[4][64], ps[4][64];
+__global__ void __launch_bounds__(64 * EQ) k_energy(const GeomDev* __restrict__ gp) {
+    __shared__ double pm[EQ][64], ps[EQ][64];
     const GeomDev& g = *gp;
-    const int nsol = g.nsolid, ns = g.n_sys;
+    const int nsol = g.nsolid, ns = g.n_sys, xs = g.xs;
     const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
     const int j = blockIdx.x * 64 + cl;
     const bool in = j < nsol;
+    const int js = in ? j : nsol - 1;           // in-range loads, dropped below
     const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
     const gptr_t<double> D = gview(g.Dw);
-    double t = 0.0, a = 0.0;
-    if (in)
-        for (int i = q; i < ns; i += 4) {
-            const double x = (double)X[(size_t)i * nsol + j];
-            t += D[i] * x;
-            a += D[i] * fabs(x);
+    const int per = (ns + EQ - 1) / EQ;
+    const int i0 = q * per, i1 = min(ns, i0 + per);
+    double t[4] = {0.0, 0.0, 0.0, 0.0}, a[4] = {0.0, 0.0, 0.0, 0.0};
+    int i = i0;
+    for (; i + 3 < i1; i += 4) {
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = (double)X[(size_t)(i + u) * xs + js];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            t[u] += D[i + u] * x[u];
+            a[u] += D[i + u] * fabs(x[u]);
         }
-    pm[q][cl] = t;
-    ps[q][cl] = a;
+    }
+    for (; i < i1; ++i) {
+        const double x = (double)X[(size_t)i * xs + js];
+        t[0] += D[i] * x;
+        a[0] += D[i] * fabs(x);
+    }
+    pm[q][cl] = (t[0] + t[1]) + (t[2] + t[3]);
+    ps[q][cl] = (a[0] + a[1]) + (a[2] + a[3]);
     __syncthreads();
     if (q == 0) {
         double tl = 0.0, ab = 0.0, r = 0.0;
-        if (in) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                tl += pm[u][cl];
-                ab += ps[u][cl];
-            }
+        for (int u = 0; u < EQ; ++u) {
+            tl += pm[u][cl];
+            ab += ps[u][cl];
+        }
+        if (in) {
             const int cell = g.scell[j];
             const int buf = (g.ctrl[CTRL_PASS] + 1) & 1;     // the last pass's input
             r = fabs(g.sigma[cell] * tl - g.sT[(size_t)buf * g.ncells + cell]);
+        } else {
+            ab = 0.0;
         }
         for (int m = 32; m >= 1; m >>= 1) {
             r = fmax(r, shfl_xor(r, m));
@@ -2395,8 +2419,8 @@ hipError_t launch_anderson(const GeomDev* geoms_dev, int n_geoms, int max_naa, P
 hipError_t launch_energy(const GeomDev* geom_dev, int precision, int nsolid, hipStream_t st) {
     const int blocks = nsolid > 0 ? (nsolid + 63) / 64 : 1;
     (void)hipGetLastError();
-    if (precision == 1) hipLaunchKernelGGL(k_energy<float>, dim3(blocks), dim3(256), 0, st, geom_dev);
-    else hipLaunchKernelGGL(k_energy<double>, dim3(blocks), dim3(256), 0, st, geom_dev);
+    if (precision == 1) hipLaunchKernelGGL(k_energy<float>, dim3(blocks), dim3(64 * EQ), 0, st, geom_dev);
+    else hipLaunchKernelGGL(k_energy<double>, dim3(blocks), dim3(64 * EQ), 0, st, geom_dev);
     hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(256), 0, st, geom_dev, blocks);
     return hipGetLastError();
 }
@@ -2406,7 +2430,7 @@ hipError_t launch_prep_sigma(const GeomDev* g_dev, int ncells, const double* sig
     if (blocks > 1024) blocks = 1024;
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_prep_sigma, dim3(blocks), dim3(256), 0, st, g_dev, sig);
-    hipLaunchKernelGGL(k_sigma_min, dim3(1), dim3(256), 0, st, g_dev);
+    hipLaunchKernelGGL(k_sigma_min, dim3(1), dim3(256), 0, st, g_dev, blocks);
     return hipGetLastError();
 }
 

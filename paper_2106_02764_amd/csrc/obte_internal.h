@@ -23,6 +23,8 @@ constexpr int KRY3_VECS = 11;
 struct GeomDev {
     int nx, ny, nz, ndim, nf, ncells, nwalls, nwrap;
     int nsolid;                  // solid cells: the length of one system's stored solution
+    int xs;                      // stride of one system's row in X and Tstore: nsolid rounded up
+                                 // to 64 values, so the reductions' 64-cell strips start on lines
     int periodic[3];
     int grad_axis;
     double h[3], L[3], dT;
@@ -49,7 +51,7 @@ struct GeomDev {
     double* T_L;                 // ncells: latest lattice temperature
     void* U;                     // n_sys * nwrap (compute precision): wrap inflow vectors
     void* kry;                   // 3D: n_sys * 11 * nwrap (compute precision): wrap-plane Krylov vectors
-    void* X;                     // n_sys * nsolid (compute precision): each system's solution of
+    void* X;                     // n_sys * xs (compute precision): each system's solution of
                                  // the pass (forward T, adjoint lambda) on the solid cells
     double* ksys;                // n_sys: kappa_cc contribution of each system
     double* kfsys;               // n_sys: kappa_face contribution
@@ -62,7 +64,7 @@ struct GeomDev {
     double* fscal;               // scalars: [0] kappa_F, [1] CG iterations, [2] CG residual,
                                  // [3] mixing error estimate, [4] energy residual of the last pass,
                                  // [5] smallest sigma over the solid cells
-    double* Tstore;              // n_sys * nsolid (adjoint forward state) or null
+    double* Tstore;              // n_sys * xs (adjoint forward state) or null
     double* lam_psi;             // adjoint: 2 * ncells (double buffered Psi)
     double* lam_phi;             // adjoint: 2 * nwalls (double buffered Phi)
     double* gradient;            // adjoint: ncells
@@ -134,6 +136,8 @@ hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geo
 // max_i |sigma_i T_L,i - sigma_i T_L^in_i| / (sum_i sum_ml D_ml |T_iml| / N_solid) into
 // fscal[4], with T_L = sum_ml D_ml T_iml of the stored solutions.  Scratch:
 // energy_scratch_doubles(nsolid) doubles in the Fourier CG region.
+// row stride of the per-system stores X and Tstore
+constexpr size_t x_stride(size_t nsolid) { return (nsolid + 63) / 64 * 64; }
 constexpr size_t energy_scratch_doubles(size_t nsolid) { return 2 * ((nsolid + 63) / 64); }
 hipError_t launch_energy(const GeomDev* geom_dev, int precision, int nsolid, hipStream_t st);
 // Anderson mixing: per-block partials (up to 256 blocks of 256 threads per
@@ -156,3 +160,6 @@ hipError_t launch_prep_sigma(const GeomDev* g_dev, int ncells, const double* sig
 hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, const GeomDev& g_host,
                         const double* sigma, const int* sys_ids, int n_sys, const void* x, void* y,
                         hipStream_t st);
+
+// Set the message obte_last_error returns (host, per thread).
+void obte_set_error(const char* msg);
