@@ -354,6 +354,72 @@ int obte_mesh_n_walls(const obte_mesh* mesh);
 int obte_mesh_n_systems(const obte_mesh* mesh);
 int obte_mesh_n_modes(const obte_mesh* mesh);
 
+/* ---------------------------------------------------------------------
+ * Unstructured 2D meshes (paper: section Geometry module, which meshes the
+ * cell with unstructured polygons; Appendix A, where the mesh enters only
+ * through the face vectors R_ij = A_ij n_ij / V_i; Appendix B, Eqs. (grad)
+ * to (final2), the heat-conduction first guess with the non-orthogonal
+ * secondary flux treated explicitly and least-squares cell gradients).
+ * The cell is periodic along both axes; pore cells are removed and their
+ * faces become diffuse walls.  FP64 throughout; the library owns the solve
+ * buffers (taken at obte_umesh_material_set, freed by obte_umesh_destroy).
+ * ------------------------------------------------------------------- */
+typedef struct obte_umesh obte_umesh;   /* opaque handle */
+
+/* Build the face lists and geometry on the host and upload them to the
+ * current device.
+ * nodes:  host, n_nodes x 2 doubles (metres);
+ * cells:  host int32, n_cells x nv node ids (nv = 3 or 4), counter-clockwise;
+ * shifts: host int32, n_cells x nv x 2: corner k of cell c lies at
+ *         nodes[cells[c][k]] + shifts[c][k] * (Lx, Ly) (periodic images);
+ * solid:  host uint8, n_cells (0 = pore).
+ * Every edge must be shared by exactly two cells (OBTE_ERR_ARG otherwise,
+ * and for clockwise or degenerate cells, sizes out of range or no solid
+ * cell).  The applied difference dT > 0 is along grad_axis (0 = x, 1 = y),
+ * with T(x + L) = T(x) - dT across the periodic plane.  Limits: at most
+ * 8192 solid cells (a system's solution lives in one workgroup's LDS). */
+obte_status obte_umesh_create(const double* nodes, int n_nodes, const int* cells, const int* shifts,
+                              int n_cells, int nv, const unsigned char* solid, double Lx, double Ly,
+                              int grad_axis, double dT, obte_umesh** out);
+
+/* Material weights on the vectorial-MFP grid (section Model, Appendix A):
+ * mfp (n_mfp), in-plane unit directions dirs (n_dir x 2), weights dir_w
+ * (summing to 1), per-MFP conductivity kappa_m; all host.  Builds the
+ * per-direction sweep order: the cells sorted into upwind levels with the
+ * periodic faces cut (OBTE_ERR_ARG if the upwind graph of some direction has
+ * a cycle, which convex cells do not produce). */
+obte_status obte_umesh_material_set(obte_umesh* mesh, const double* mfp, int n_mfp, const double* dirs,
+                                    const double* dir_w, int n_dir, const double* kappa_m);
+
+/* Heat-conduction first guess, Eq. (final2): outer iterations of
+ * A T^(n) = S T^(n-1) + P until max|T^(n) - T^(n-1)| <= tol max|T^(n)|
+ * (at most max_outer), each solved by conjugate gradients to a relative
+ * residual of cg_tol.  T_dev: device, n_cells doubles (mean zero over the
+ * solid cells, 0 in pores); kappa_F: host, the face flux across the
+ * periodic plane times L / (dT A_perp); outer_iters: host, may be NULL.
+ * OBTE_ERR_NOT_CONVERGED if max_outer was reached (results written). */
+obte_status obte_umesh_fourier(obte_umesh* mesh, double tol, int max_outer, double cg_tol, void* stream,
+                               double* T_dev, double* kappa_F, int* outer_iters);
+
+/* Algorithm 1 on the unstructured mesh: the Fourier first guess (to
+ * opts->fourier_tol), then passes until |kappa_n - kappa_{n-1}| <=
+ * opts->outer_tol |kappa_n| or opts->max_outer passes.  Each pass solves
+ * every (m, l) system exactly up to its periodic-face coupling, which
+ * BiCGSTAB solves to opts->inner_tol (at most opts->max_inner iterations).
+ * Only precision = OBTE_FP64, init = 0 and accel = 0 are accepted.
+ * sigma_dev: device, n_cells relaxation multipliers, or NULL for 1.
+ * T_L_dev: device, n_cells doubles (mean zero over solid cells) or NULL.
+ * stats: kappa (kappa_cc), kappa_face, kappa_fourier, outer_iters,
+ * inner_iters, wrap_residual, last_rel_change, status. */
+obte_status obte_umesh_solve(obte_umesh* mesh, const obte_solve_opts* opts, const double* sigma_dev,
+                             void* stream, double* T_L_dev, obte_stats* stats);
+
+void obte_umesh_destroy(obte_umesh* mesh);
+int obte_umesh_n_solid(const obte_umesh* mesh);
+int obte_umesh_n_faces(const obte_umesh* mesh);   /* interior faces between solid cells */
+int obte_umesh_n_walls(const obte_umesh* mesh);
+int obte_umesh_n_levels(const obte_umesh* mesh, int direction);  /* upwind levels of a direction */
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,6 @@ there is no CPU fallback.
 """
 from . import autotune, obte
 from .obte import ObteError, default_opts, lib
-from .solver import KappaEff, Solver, solve_batch
+from .solver import KappaEff, Solver, UMeshSolver, solve_batch
 
-__all__ = ["obte", "ObteError", "default_opts", "lib", "Solver", "KappaEff", "solve_batch"]
+__all__ = ["obte", "ObteError", "default_opts", "lib", "Solver", "UMeshSolver", "KappaEff", "solve_batch"]

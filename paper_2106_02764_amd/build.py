@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libobte.so")
-SOURCES = ["kernels.hip", "apply.hip", "host.cpp"]
+SOURCES = ["kernels.hip", "apply.hip", "host.cpp", "ukernels.hip", "umesh.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

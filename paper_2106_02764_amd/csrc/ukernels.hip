@@ -1,0 +1,483 @@
+// gfx950 kernels of the unstructured-mesh path (paper: section Geometry
+// module; Appendix A with general face vectors R_ij = A_ij n_ij / V_i;
+// Appendix B, heat conduction with the non-orthogonal correction).
+//
+// Heat conduction (Eq. (final2)): the primary flux is implicit, the
+// secondary flux explicit.  One workgroup runs the whole outer iteration of
+// a mesh: least-squares cell gradients of the current T, the secondary flux
+// of every face, then a conjugate-gradient solve of the volume-scaled
+// primary-flux Laplacian (warm-started from the current T), until T stops
+// changing.
+//
+// Transport: one wavefront owns one (m, l) system.  Within a direction the
+// cells are ordered upwind (the host sorts them into levels whose cells
+// depend only on earlier levels, the periodic faces cut), so a sweep is one
+// pass over the levels with the solution in LDS.  The values entering
+// through periodic faces form the system's wrap vector u; BiCGSTAB solves
+// (I - G) e = r for its correction, G being one sweep with u as the only
+// source, as on the structured grids.  All sums are in a fixed order: FP64
+// results are bitwise reproducible.
+#include "umesh_internal.h"
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int UF_THREADS = 1024;
+
+__device__ __forceinline__ double shfl_xor(double v, int m) { return __shfl_xor(v, m, WAVE); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor(v, m);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, shfl_xor(v, m));
+    return v;
+}
+
+// Block-wide sum (every thread gets the same value; waves combined in order).
+__device__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s += red[k];
+    return s;
+}
+
+__device__ double block_max(double v, double* red) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s = fmax(s, red[k]);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// heat conduction with the explicit secondary flux
+// ---------------------------------------------------------------------------
+__device__ void ucell_gradients(const UFourierDev& f) {
+    for (int i = threadIdx.x; i < f.ns; i += blockDim.x) {
+        double gx = 0.0, gy = 0.0;
+        const double Ti = f.T[i];
+        for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
+            const double q = f.T[f.nb_j[k]] + f.nb_del[k] * f.dT - Ti;
+            gx += f.nb_w[2 * k] * q;
+            gy += f.nb_w[2 * k + 1] * q;
+        }
+        f.g[2 * i] = gx;
+        f.g[2 * i + 1] = gy;
+    }
+}
+
+__device__ __forceinline__ void uface_gradient(const UFourierDev& f, int fc, double& gx, double& gy) {
+    const int i = f.fi[fc], j = f.fj[fc];
+    const double w = f.fw[fc];
+    gx = (1.0 - w) * f.g[2 * i] + w * f.g[2 * j];
+    gy = (1.0 - w) * f.g[2 * i + 1] + w * f.g[2 * j + 1];
+}
+
+// (A x)_i for A = minus the volume-scaled primary-flux Laplacian
+__device__ __forceinline__ double uapply(const UFourierDev& f, const double* x, int i) {
+    double y = 0.0;
+    const double xi = x[i];
+    for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) y += f.nb_a[k] * (xi - x[f.nb_j[k]]);
+    return y;
+}
+
+__global__ void __launch_bounds__(UF_THREADS) k_ufourier(const UFourierDev* __restrict__ fp, double tol,
+                                                         int max_outer, double cg_tol, int max_cg) {
+    __shared__ double red[UF_THREADS / 64];
+    const UFourierDev& f = *fp;
+    const int ns = f.ns, t = threadIdx.x, B = blockDim.x;
+    double* Tp = f.q;       // the previous outer iterate (q is free between CG solves)
+    int outer = 0, cg_total = 0;
+    double change = 0.0;
+    for (outer = 1; outer <= max_outer; ++outer) {
+        ucell_gradients(f);
+        __syncthreads();
+        for (int fc = t; fc < f.nfaces; fc += B) {
+            double gx, gy;
+            uface_gradient(f, fc, gx, gy);
+            f.bf[fc] = gx * f.fc[2 * fc] + gy * f.fc[2 * fc + 1];
+        }
+        __syncthreads();
+        // b = -(P + B): the right-hand side of A T = b, A = -Laplacian
+        double bb = 0.0;
+        for (int i = t; i < ns; i += B) {
+            double s = f.P[i];
+            for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
+                const int code = f.nb_f[k];
+                const double v = f.bf[code >> 1];
+                s += (code & 1) ? -v : v;
+            }
+            f.b[i] = -s;
+            Tp[i] = f.T[i];
+            bb += s * s;
+        }
+        bb = block_sum(bb, red);
+        // conjugate gradients from the current T
+        double rr = 0.0;
+        for (int i = t; i < ns; i += B) {
+            const double ri = f.b[i] - uapply(f, f.T, i);
+            f.r[i] = ri;
+            f.p[i] = ri;
+            rr += ri * ri;
+        }
+        rr = block_sum(rr, red);
+        const double stop = cg_tol * cg_tol * bb;
+        for (int it = 0; it < max_cg && rr > stop; ++it) {
+            double pq = 0.0;
+            for (int i = t; i < ns; i += B) {
+                const double qi = uapply(f, f.p, i);
+                f.b[i] = qi;                       // b is free once r is formed
+                pq += f.p[i] * qi;
+            }
+            pq = block_sum(pq, red);
+            if (!(pq > 0.0)) break;
+            const double alpha = rr / pq;
+            double rn = 0.0;
+            for (int i = t; i < ns; i += B) {
+                f.T[i] += alpha * f.p[i];
+                const double ri = f.r[i] - alpha * f.b[i];
+                f.r[i] = ri;
+                rn += ri * ri;
+            }
+            rn = block_sum(rn, red);
+            const double beta = rn / rr;
+            rr = rn;
+            for (int i = t; i < ns; i += B) f.p[i] = f.r[i] + beta * f.p[i];
+            ++cg_total;
+            __syncthreads();
+        }
+        // mean zero, then the change against the previous iterate
+        double sm = 0.0;
+        for (int i = t; i < ns; i += B) sm += f.T[i];
+        const double mean = block_sum(sm, red) / (double)ns;
+        double dmax = 0.0, tmax = 0.0;
+        for (int i = t; i < ns; i += B) {
+            const double v = f.T[i] - mean;
+            f.T[i] = v;
+            dmax = fmax(dmax, fabs(v - Tp[i]));
+            tmax = fmax(tmax, fabs(v));
+        }
+        dmax = block_max(dmax, red);
+        tmax = block_max(tmax, red);
+        change = tmax > 0.0 ? dmax / tmax : 0.0;
+        if (dmax <= tol * fmax(tmax, 1e-300)) break;
+    }
+    // kappa_F: the total face flux (primary + secondary) across the periodic
+    // plane of the gradient axis
+    __syncthreads();
+    ucell_gradients(f);
+    __syncthreads();
+    double tot = 0.0;
+    for (int c = t; c < f.ncut; c += B) {
+        const int fc = f.cut_f[c];
+        double gx, gy;
+        uface_gradient(f, fc, gx, gy);
+        const int ip = f.cut_s[c] > 0 ? f.fi[fc] : f.fj[fc];
+        const int jn = f.cut_s[c] > 0 ? f.fj[fc] : f.fi[fc];
+        const double a = f.cut_K[3 * c], kx = f.cut_K[3 * c + 1], ky = f.cut_K[3 * c + 2];
+        const double gd = gx * f.cut_d[2 * c] + gy * f.cut_d[2 * c + 1];
+        // a = n.K n / (n.d); the secondary part g.K n - (n.K n)(g.d)/(n.d)
+        tot += f.cut_A[c] * (a * (f.T[jn] + f.dT - f.T[ip]) + (gx * kx + gy * ky) - a * gd);
+    }
+    tot = block_sum(tot, red);
+    if (t == 0) {
+        f.out[0] = f.Lg / (f.dT * f.Aperp) * tot;
+        f.out[1] = (double)(outer > max_outer ? max_outer : outer);
+        f.out[2] = (double)cg_total;
+        f.out[3] = change;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// transport: one pass for every system
+// ---------------------------------------------------------------------------
+struct USys {
+    int sys, l, lb, nlev, nw;
+    double lam;
+    const int* up;
+    const double* del;
+};
+
+// One sweep of the system: x (LDS) from the sources (src: sigma T_L and the
+// wall values; else none) and the wrap inflow staged in LDS.
+__device__ void usweep(const UGeomDev& g, const USys& s, bool src, double* x, const double* uin) {
+    const int lane = threadIdx.x, ns = g.ns;
+    for (int k = 0; k < s.nlev; ++k) {
+        const int p0 = g.lptr[s.lb + k], p1 = g.lptr[s.lb + k + 1];
+        for (int p = p0 + lane; p < p1; p += WAVE) {
+            const size_t pl = (size_t)s.l * ns + p;
+            const int i = g.ord[pl];
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < UFACES; ++q) {
+                const int code = g.inc[pl * UFACES + q];
+                if (code == UNONE) continue;
+                double v;
+                if (code >= ns) v = uin[code - ns];
+                else if (code >= 0) v = x[code];
+                else v = src ? g.T_w[UWALL0 - code] : 0.0;
+                acc += g.inv[pl * UFACES + q] * v;
+            }
+            const double sg = g.sigma[i];
+            const double rhs = src ? sg * g.T_L[i] : 0.0;
+            x[i] = (rhs + s.lam * acc) / (sg + s.lam * g.dout[pl]);
+        }
+        __syncthreads();
+    }
+}
+
+template <int WPL>
+__device__ __forceinline__ void ustage(const USys& s, const double (&v)[WPL], double* uin) {
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+        const int q = k * WAVE + threadIdx.x;
+        if (q < s.nw) uin[q] = v[k];
+    }
+    __syncthreads();
+}
+
+// G v: the values a homogeneous sweep with inflow v carries back across the
+// periodic faces
+template <int WPL>
+__device__ __forceinline__ void ugather(const USys& s, const double* x, double (&out)[WPL]) {
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+        const int q = k * WAVE + threadIdx.x;
+        out[k] = q < s.nw ? x[s.up[q]] : 0.0;
+    }
+}
+
+template <int WPL>
+__device__ __forceinline__ double udot(const double (&a)[WPL], const double (&b)[WPL]) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) v += a[k] * b[k];
+    return wave_sum(v);
+}
+
+template <int WPL>
+__global__ void __launch_bounds__(WAVE) k_upass(const UGeomDev* __restrict__ gp, double inner_tol, int max_inner) {
+    extern __shared__ double lds[];
+    const UGeomDev& g = *gp;
+    const int lane = threadIdx.x;
+    USys s;
+    s.sys = blockIdx.x;
+    const int m = s.sys / g.n_dir;
+    s.l = s.sys % g.n_dir;
+    s.lam = g.mfp[m];
+    s.lb = g.lbase[s.l];
+    s.nlev = g.nlev[s.l];
+    s.nw = g.nwrap[s.l];
+    s.up = g.wup + (size_t)s.l * g.wmax;
+    s.del = g.wdel + (size_t)s.l * g.wmax;
+    double* x = lds;
+    double* uin = lds + g.ns;
+    double* U = g.U + (size_t)s.sys * g.wmax;
+    double u[WPL], ez[WPL], r[WPL];
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+        const int q = k * WAVE + lane;
+        u[k] = q < s.nw ? U[q] : 0.0;
+    }
+    // ---- the sweep with the sources and the wrap inflow of the last pass
+    ustage(s, u, uin);
+    usweep(g, s, true, x, uin);
+    ugather(s, x, ez);
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+        const int q = k * WAVE + lane;
+        if (q < s.nw) ez[k] += s.del[q];
+        r[k] = ez[k] - u[k];
+    }
+    const double scale = sqrt(udot(ez, ez));
+    double rn = sqrt(udot(r, r));
+    long long its = 0;
+    const double thr = inner_tol * scale;
+    if (s.nw > 0 && scale > 0.0 && rn > thr) {
+        // ---- BiCGSTAB on (I - G) e = r, the best iterate kept
+        double e[WPL], eb[WPL], rh[WPL], p[WPL], v[WPL], sv[WPL], tt[WPL], gx[WPL];
+#pragma unroll
+        for (int k = 0; k < WPL; ++k) {
+            e[k] = 0.0; eb[k] = 0.0; rh[k] = r[k]; p[k] = 0.0; v[k] = 0.0;
+        }
+        double best = rn, rho_old = 1.0, alpha = 1.0, omega = 1.0;
+        int restarts = 0;
+        for (int it = 0; it < max_inner; ++it) {
+            double rho = udot(rh, r);
+            if (fabs(rho) <= 1e-30 * rn * rn || !(omega != 0.0)) {
+#pragma unroll
+                for (int k = 0; k < WPL; ++k) { rh[k] = r[k]; p[k] = 0.0; v[k] = 0.0; }
+                rho = udot(r, r);
+                rho_old = 1.0; alpha = 1.0; omega = 1.0;
+            }
+            const double beta = (rho / rho_old) * (alpha / omega);
+#pragma unroll
+            for (int k = 0; k < WPL; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
+            ustage(s, p, uin);
+            usweep(g, s, false, x, uin);
+            ugather(s, x, gx);
+#pragma unroll
+            for (int k = 0; k < WPL; ++k) v[k] = p[k] - gx[k];
+            const double rv = udot(rh, v);
+            if (!isfinite(rv)) break;
+            if (!(fabs(rv) > 1e-30 * fabs(rho))) {
+                if (restarts++ >= 4) break;
+                omega = 0.0;
+                continue;
+            }
+            alpha = rho / rv;
+#pragma unroll
+            for (int k = 0; k < WPL; ++k) sv[k] = r[k] - alpha * v[k];
+            const double sn = sqrt(udot(sv, sv));
+            ++its;
+            if (sn <= thr) {
+#pragma unroll
+                for (int k = 0; k < WPL; ++k) e[k] += alpha * p[k];
+                if (sn < best) {
+                    best = sn;
+#pragma unroll
+                    for (int k = 0; k < WPL; ++k) eb[k] = e[k];
+                }
+                break;
+            }
+            ustage(s, sv, uin);
+            usweep(g, s, false, x, uin);
+            ugather(s, x, gx);
+#pragma unroll
+            for (int k = 0; k < WPL; ++k) tt[k] = sv[k] - gx[k];
+            const double t2 = udot(tt, tt);
+            omega = t2 > 0.0 ? udot(tt, sv) / t2 : 0.0;
+#pragma unroll
+            for (int k = 0; k < WPL; ++k) {
+                e[k] += alpha * p[k] + omega * sv[k];
+                r[k] = sv[k] - omega * tt[k];
+            }
+            rn = sqrt(udot(r, r));
+            rho_old = rho;
+            if (!isfinite(rn)) break;
+            if (rn < best) {
+                best = rn;
+#pragma unroll
+                for (int k = 0; k < WPL; ++k) eb[k] = e[k];
+            }
+            if (rn <= thr) break;
+        }
+        rn = best;
+        // ---- the corrected inflow, and the final sweep with it
+#pragma unroll
+        for (int k = 0; k < WPL; ++k) {
+            u[k] += eb[k];
+            const int q = k * WAVE + lane;
+            if (q < s.nw) U[q] = u[k];
+        }
+        ustage(s, u, uin);
+        usweep(g, s, true, x, uin);
+    }
+    // ---- the stored solution and this system's kappa shares
+    double kc = 0.0;
+    double* X = g.X + (size_t)s.sys * g.ns;
+    for (int i = lane; i < g.ns; i += WAVE) {
+        const double xv = x[i];
+        X[i] = xv;
+        kc += g.V[i] * xv;
+    }
+    kc = wave_sum(kc);
+    const double Sx = g.S[2 * s.sys], Sy = g.S[2 * s.sys + 1];
+    double kf = 0.0;
+    for (int c = lane; c < g.ncut; c += WAVE) {
+        const double sn = Sx * g.cut_An[2 * c] + Sy * g.cut_An[2 * c + 1];     // A_f S . n
+        const double up = sn > 0.0 ? x[g.cut_i[c]] : x[g.cut_j[c]] + g.dT;
+        kf -= sn * up;                 // flow from the + side cell out across the cut
+    }
+    kf = wave_sum(kf);
+    if (lane == 0) {
+        const double Sg = g.S[2 * s.sys + g.grad_axis];
+        g.ksys[s.sys] = g.Lg / (g.dT * g.Vbox) * Sg * kc;
+        g.kfsys[s.sys] = g.Lg / (g.dT * g.Aperp) * kf;
+        g.iters[s.sys] += its;
+        g.wres[s.sys] = scale > 0.0 ? rn / scale : 0.0;
+    }
+}
+
+// T_L = sum D x per cell, T_w = sum of the outgoing weights times x at the
+// wall's cell, both over the systems in order.
+__global__ void __launch_bounds__(256) k_ureduce(const UGeomDev* __restrict__ gp) {
+    const UGeomDev& g = *gp;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < g.ns) {
+        double acc = 0.0;
+        for (int sys = 0; sys < g.n_sys; ++sys) acc += g.Dw[sys] * g.X[(size_t)sys * g.ns + t];
+        g.T_L[t] = acc;
+    } else if (t < g.ns + g.nwalls) {
+        const int w = t - g.ns;
+        const int c = g.wcell[w];
+        double acc = 0.0;
+        for (int sys = 0; sys < g.n_sys; ++sys) acc += g.wout[(size_t)w * g.n_sys + sys] * g.X[(size_t)sys * g.ns + c];
+        g.T_w[w] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_ukappa(const UGeomDev* __restrict__ gp) {
+    __shared__ double red[4];
+    const UGeomDev& g = *gp;
+    double a = 0.0, b = 0.0, w = 0.0;
+    // fixed order: each thread a contiguous chunk, then the block in order
+    const int per = (g.n_sys + blockDim.x - 1) / blockDim.x;
+    const int i0 = threadIdx.x * per, i1 = min(g.n_sys, i0 + per);
+    for (int i = i0; i < i1; ++i) {
+        a += g.ksys[i];
+        b += g.kfsys[i];
+        w = fmax(w, g.wres[i]);
+    }
+    a = block_sum(a, red);
+    b = block_sum(b, red);
+    w = block_max(w, red);
+    if (threadIdx.x == 0) {
+        g.kap[0] = a;
+        g.kap[1] = b;
+        g.kap[2] = w;
+    }
+}
+
+}  // namespace
+
+hipError_t ulaunch_fourier(const UFourierDev* f_dev, int ns, double tol, int max_outer, double cg_tol, int max_cg,
+                           hipStream_t st) {
+    (void)ns;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_ufourier, dim3(1), dim3(UF_THREADS), 0, st, f_dev, tol, max_outer, cg_tol, max_cg);
+    return hipGetLastError();
+}
+
+hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int wpl, size_t lds_bytes, double inner_tol, int max_inner,
+                        hipStream_t st) {
+    (void)hipGetLastError();
+    switch (wpl) {
+    case 1: hipLaunchKernelGGL(k_upass<1>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, max_inner); break;
+    case 2: hipLaunchKernelGGL(k_upass<2>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, max_inner); break;
+    case 4: hipLaunchKernelGGL(k_upass<4>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, max_inner); break;
+    case 8: hipLaunchKernelGGL(k_upass<8>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, max_inner); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ulaunch_reduce(const UGeomDev* g_dev, int ns, int nwalls, hipStream_t st) {
+    (void)hipGetLastError();
+    const int n = ns + nwalls;
+    hipLaunchKernelGGL(k_ureduce, dim3((n + 255) / 256), dim3(256), 0, st, g_dev);
+    hipLaunchKernelGGL(k_ukappa, dim3(1), dim3(256), 0, st, g_dev);
+    return hipGetLastError();
+}

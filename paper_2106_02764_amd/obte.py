@@ -97,6 +97,21 @@ EXPORTS = {
     "obte_mesh_n_walls": (C.c_int, [C.c_void_p]),
     "obte_mesh_n_systems": (C.c_int, [C.c_void_p]),
     "obte_mesh_n_modes": (C.c_int, [C.c_void_p]),
+    # unstructured 2D meshes
+    "obte_umesh_create": (C.c_int, [C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                    C.c_int, C.c_int, C.POINTER(C.c_uint8), C.c_double, C.c_double, C.c_int,
+                                    C.c_double, C.POINTER(C.c_void_p)]),
+    "obte_umesh_material_set": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]),
+    "obte_umesh_fourier": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "obte_umesh_solve": (C.c_int, [C.c_void_p, C.POINTER(obte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.POINTER(obte_stats)]),
+    "obte_umesh_destroy": (None, [C.c_void_p]),
+    "obte_umesh_n_solid": (C.c_int, [C.c_void_p]),
+    "obte_umesh_n_faces": (C.c_int, [C.c_void_p]),
+    "obte_umesh_n_walls": (C.c_int, [C.c_void_p]),
+    "obte_umesh_n_levels": (C.c_int, [C.c_void_p, C.c_int]),
 }
 
 _lib = None
@@ -304,3 +319,50 @@ def obte_mesh_counts(mesh):
     L = lib()
     return {"n_cells": L.obte_mesh_n_cells(mesh), "n_solid": L.obte_mesh_n_solid(mesh),
             "n_walls": L.obte_mesh_n_walls(mesh), "n_systems": L.obte_mesh_n_systems(mesh)}
+
+
+# ---------------------------------------------------------------------------
+# unstructured 2D meshes
+# ---------------------------------------------------------------------------
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.POINTER(np.ctypeslib.as_ctypes_type(dtype)))
+
+
+def obte_umesh_create(nodes, cells, shifts, solid, L, grad_axis, dT):
+    nodes_a, pn = _host(nodes, np.float64)
+    cells_a, pc = _host(cells, np.int32)
+    shifts_a, ps = _host(shifts, np.int32)
+    solid_a, pso = _host(solid, np.uint8)
+    n_cells, nv = cells_a.shape
+    h = C.c_void_p()
+    _check(lib().obte_umesh_create(pn, len(nodes_a), pc, ps, n_cells, nv, pso, float(L[0]), float(L[1]),
+                                   int(grad_axis), float(dT), C.byref(h)))
+    return h
+
+
+def obte_umesh_material_set(mesh, mfp, dirs, dir_w, kappa_m):
+    mfp_a, pm = _host(mfp, np.float64)
+    dirs_a, pd = _host(np.asarray(dirs, float)[:, :2], np.float64)
+    w_a, pw = _host(dir_w, np.float64)
+    k_a, pk = _host(kappa_m, np.float64)
+    _check(lib().obte_umesh_material_set(mesh, pm, len(mfp_a), pd, pw, len(w_a), pk))
+
+
+def obte_umesh_fourier(mesh, tol, max_outer, cg_tol, T, stream=None, raise_not_converged=True):
+    kF = C.c_double()
+    it = C.c_int()
+    st = lib().obte_umesh_fourier(mesh, float(tol), int(max_outer), float(cg_tol), _stream(stream), _dptr(T),
+                                  C.byref(kF), C.byref(it))
+    if st != OBTE_OK and (raise_not_converged or st != OBTE_ERR_NOT_CONVERGED):
+        _check(st)
+    return kF.value, it.value, st
+
+
+def obte_umesh_solve(mesh, opts, sigma, T_L, stream=None, raise_not_converged=False):
+    stats = obte_stats()
+    st = lib().obte_umesh_solve(mesh, C.byref(opts), _dptr(sigma), _stream(stream), _dptr(T_L), C.byref(stats))
+    if st != OBTE_OK and (raise_not_converged or st != OBTE_ERR_NOT_CONVERGED):
+        _check(st)
+    return stats

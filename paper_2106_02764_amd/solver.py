@@ -168,3 +168,59 @@ def solve_batch(solvers, opts, sigmas=None, device="cuda"):
     k, st = _o.obte_solve_batch([s.mesh for s in solvers], opts, sg, ws, stream=stream)
     torch.cuda.current_stream().wait_stream(stream)
     return k, [x.as_dict() for x in st]
+
+
+class UMeshSolver:
+    """One unstructured 2D mesh (obte_umesh handle) with its material."""
+
+    def __init__(self, nodes, cells, shifts, solid, L, grad_axis, dT, mfp, dirs, dir_w, kappa_m, device="cuda"):
+        self.device = torch.device(device)
+        self.n_cells = len(cells)
+        self.mesh = _o.obte_umesh_create(nodes, cells, shifts, solid, L, grad_axis, dT)
+        _o.obte_umesh_material_set(self.mesh, mfp, dirs, dir_w, kappa_m)
+        L_ = _o.lib()
+        self.n_solid = L_.obte_umesh_n_solid(self.mesh)
+        self.n_faces = L_.obte_umesh_n_faces(self.mesh)
+        self.n_walls = L_.obte_umesh_n_walls(self.mesh)
+        self.n_dir = len(dir_w)
+        self.n_systems = len(mfp) * self.n_dir
+        self.stream = torch.cuda.Stream(device=self.device)
+
+    @classmethod
+    def from_workload(cls, w, device="cuda"):
+        return cls(w.nodes, w.cells, w.shifts, w.solid, w.L, w.grad_axis, w.dT, w.mfp, w.dirs, w.dir_w,
+                   w.kappa_m, device=device)
+
+    def levels(self):
+        return [_o.lib().obte_umesh_n_levels(self.mesh, l) for l in range(self.n_dir)]
+
+    def opts(self, **kw):
+        return _o.default_opts(**kw)
+
+    def fourier(self, tol=1e-13, max_outer=1000, cg_tol=1e-14):
+        T = torch.zeros(self.n_cells, dtype=torch.float64, device=self.device)
+        kF, it, st = _o.obte_umesh_fourier(self.mesh, tol, max_outer, cg_tol, T, stream=self.stream)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return {"T": T, "kappa_fourier": kF, "outer_iters": it, "status": st}
+
+    def solve(self, opts, sigma=None, want_T_L=True):
+        sg = None
+        if sigma is not None:
+            sg = torch.as_tensor(np.asarray(sigma, np.float64), device=self.device).contiguous()
+        T_L = torch.zeros(self.n_cells, dtype=torch.float64, device=self.device) if want_T_L else None
+        st = _o.obte_umesh_solve(self.mesh, opts, sg, T_L, stream=self.stream)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        out = st.as_dict()
+        out["T_L"] = T_L
+        return out
+
+    def close(self):
+        if getattr(self, "mesh", None):
+            _o.lib().obte_umesh_destroy(self.mesh)
+            self.mesh = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -169,3 +169,50 @@ def test_options_rejected_on_host(L, field, value):
         L.obte_workspace_size(h, L.default_opts(**{field: value}))
     assert e.value.status == L.OBTE_ERR_ARG
     L.obte_mesh_destroy(h)
+
+
+# ---- unstructured meshes: host-side construction (no device work before
+# the material is set)
+
+def _umesh(L, w):
+    return L.obte_umesh_create(w.nodes, w.cells, w.shifts, w.solid, w.L, w.grad_axis, w.dT)
+
+
+@pytest.mark.parametrize("tri", [False, True])
+def test_umesh_counts_match_oracle(L, tri):
+    from oracle.umesh import UMesh
+    w = gen.unstructured_2d(9, 7, amp=0.3, tri=tri, seed=3, pores=[((40e-9, 55e-9), 22e-9)])
+    h = _umesh(L, w)
+    try:
+        um = UMesh(w.L, w.nodes, w.cells, w.shifts, w.solid, w.grad_axis, w.dT)
+        lib = L.lib()
+        assert lib.obte_umesh_n_solid(h) == um.n_solid
+        assert lib.obte_umesh_n_faces(h) == um.n_faces
+        assert lib.obte_umesh_n_walls(h) == um.n_walls
+        assert lib.obte_umesh_n_levels(h, 0) == -1          # no material yet
+    finally:
+        L.lib().obte_umesh_destroy(h)
+
+
+def test_umesh_create_rejects(L):
+    w = gen.unstructured_2d(6, 5, amp=0.2, tri=True, seed=1)
+    bad = []
+    cw, cws = w.cells.copy(), w.shifts.copy()
+    cw[3], cws[3] = cw[3][::-1], cws[3][::-1]                # one clockwise cell
+    bad.append(dict(cells=cw, shifts=cws))
+    gone = np.delete(w.cells, 7, axis=0)                     # a hole: unmatched edges
+    bad.append(dict(cells=gone, shifts=np.delete(w.shifts, 7, axis=0), solid=np.delete(w.solid, 7)))
+    bad.append(dict(solid=np.zeros_like(w.solid)))
+    oob = w.cells.copy()
+    oob[0, 0] = len(w.nodes)
+    bad.append(dict(cells=oob))
+    for b in bad:
+        args = dict(nodes=w.nodes, cells=w.cells, shifts=w.shifts, solid=w.solid)
+        args.update(b)
+        with pytest.raises(L.ObteError) as e:
+            L.obte_umesh_create(args["nodes"], args["cells"], args["shifts"], args["solid"], w.L, 0, 1.0)
+        assert e.value.status == L.OBTE_ERR_ARG
+    for Lx, ga, dT in ((0.0, 0, 1.0), (1e-7, 2, 1.0), (1e-7, 0, 0.0)):
+        with pytest.raises(L.ObteError) as e:
+            L.obte_umesh_create(w.nodes, w.cells, w.shifts, w.solid, (Lx, 1e-7), ga, dT)
+        assert e.value.status == L.OBTE_ERR_ARG
