@@ -23,6 +23,10 @@ CASES = {
                                                 pores=[((30 * NM, 40 * NM), 20 * NM)], n_dir=12, n_mfp=3,
                                                 sigma=np.random.default_rng(2).uniform(0.6, 1.6, 143)),
     "tri_bulk": lambda: gen.unstructured_2d(10, 9, amp=0.3, tri=True, seed=5, n_dir=8, n_mfp=2),
+    # levels wider than a wavefront and more than 64 periodic faces per
+    # direction (several wrap slots per lane)
+    "tri_big": lambda: gen.unstructured_2d(48, 40, amp=0.3, tri=True, seed=6, L=200 * NM, Ly=160 * NM,
+                                           pores=[((100 * NM, 80 * NM), 45 * NM)], n_dir=8, n_mfp=3),
 }
 
 
@@ -68,6 +72,8 @@ def test_lockstep_passes_vs_oracle(P, name):
     assert abs(r["kappa_fourier"] - ref["kappa_fourier"]) <= 1e-10 * abs(ref["kappa_fourier"])
     assert rel(r["T_L"].cpu().numpy(), full(prob.mesh, ref["T_L"])) <= 1e-10
     assert all(n >= 1 for n in s.levels())
+    if name == "tri_big":
+        assert s.n_solid > 64 * 20
 
 
 def test_converged_vs_oracle(P):
