@@ -74,7 +74,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extras", action="store_true", help="skip the 3D and batch workloads")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
-    p.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg4", "cfg5"])
+    p.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg4", "cfg5", "umesh"],
+                   help="umesh: only with --profile (the unstructured-mesh leg)")
     p.add_argument("--profile", action="store_true",
                    help="only run --steps solves of --workload at the headline operating point "
                         "with direct launches (for rocprofv3 counter runs) and exit")
@@ -395,6 +396,7 @@ def unstructured_leg(P, steps=3):
                         f"{s.n_walls} wall faces), centred pore r=30 nm in a 100 nm cell, 48 directions x 30 MFPs, "
                         "FP64, Algorithm 1 to a 1e-6 relative change",
             "solves_per_s": 1.0 / dt, "ms_per_solve": 1e3 * dt, "passes": r["outer_iters"],
+            "bicgstab_iters_per_system_pass": r["inner_iters"] / max(r["outer_iters"] * s.n_systems, 1),
             "ms_per_pass": 1e3 * dt / max(r["outer_iters"], 1), "kappa": r["kappa"], "kappa_face": r["kappa_face"],
             "kappa_fourier": r["kappa_fourier"], "status": r["status"],
             "fourier_ms": 1e3 * (time.perf_counter() - t1), "fourier_outer_iters": f["outer_iters"],
@@ -478,6 +480,13 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is design-only)"}))
+        sys.exit(2)
+    if a.profile and a.workload == "umesh":
+        import paper_2106_02764_amd as P
+        print(json.dumps({"profile": "umesh", **unstructured_leg(P, steps=a.steps)}), flush=True)
+        return
+    if a.workload == "umesh":
+        print(json.dumps({"error": "--workload umesh runs only with --profile"}))
         sys.exit(2)
     if a.profile:
         import paper_2106_02764_amd as P

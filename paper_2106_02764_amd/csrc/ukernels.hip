@@ -93,6 +93,12 @@ __device__ __forceinline__ double uapply(const UFourierDev& f, const double* x, 
     return y;
 }
 
+__device__ __forceinline__ double udiag(const UFourierDev& f, int i) {
+    double d = 0.0;
+    for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) d += f.nb_a[k];
+    return d > 0.0 ? d : 1.0;
+}
+
 __global__ void __launch_bounds__(UF_THREADS) k_ufourier(const UFourierDev* __restrict__ fp, double tol,
                                                          int max_outer, double cg_tol, int max_cg) {
     __shared__ double red[UF_THREADS / 64];
@@ -124,15 +130,19 @@ __global__ void __launch_bounds__(UF_THREADS) k_ufourier(const UFourierDev* __re
             bb += s * s;
         }
         bb = block_sum(bb, red);
-        // conjugate gradients from the current T
-        double rr = 0.0;
+        // conjugate gradients from the current T, preconditioned by the
+        // diagonal (the sum of the cell's primary coefficients)
+        double rr = 0.0, rz = 0.0;
         for (int i = t; i < ns; i += B) {
             const double ri = f.b[i] - uapply(f, f.T, i);
+            const double zi = ri / udiag(f, i);
             f.r[i] = ri;
-            f.p[i] = ri;
+            f.p[i] = zi;
             rr += ri * ri;
+            rz += ri * zi;
         }
         rr = block_sum(rr, red);
+        rz = block_sum(rz, red);
         const double stop = cg_tol * cg_tol * bb;
         for (int it = 0; it < max_cg && rr > stop; ++it) {
             double pq = 0.0;
@@ -143,18 +153,21 @@ __global__ void __launch_bounds__(UF_THREADS) k_ufourier(const UFourierDev* __re
             }
             pq = block_sum(pq, red);
             if (!(pq > 0.0)) break;
-            const double alpha = rr / pq;
-            double rn = 0.0;
+            const double alpha = rz / pq;
+            double rn = 0.0, zn = 0.0;
             for (int i = t; i < ns; i += B) {
                 f.T[i] += alpha * f.p[i];
                 const double ri = f.r[i] - alpha * f.b[i];
                 f.r[i] = ri;
                 rn += ri * ri;
+                zn += ri * ri / udiag(f, i);
             }
             rn = block_sum(rn, red);
-            const double beta = rn / rr;
+            zn = block_sum(zn, red);
+            const double beta = zn / rz;
             rr = rn;
-            for (int i = t; i < ns; i += B) f.p[i] = f.r[i] + beta * f.p[i];
+            rz = zn;
+            for (int i = t; i < ns; i += B) f.p[i] = f.r[i] / udiag(f, i) + beta * f.p[i];
             ++cg_total;
             __syncthreads();
         }
@@ -211,30 +224,69 @@ struct USys {
 };
 
 // One sweep of the system: x (LDS) from the sources (src: sigma T_L and the
-// wall values; else none) and the wrap inflow staged in LDS.
-__device__ void usweep(const UGeomDev& g, const USys& s, bool src, double* x, const double* uin) {
-    const int lane = threadIdx.x, ns = g.ns;
-    for (int k = 0; k < s.nlev; ++k) {
-        const int p0 = g.lptr[s.lb + k], p1 = g.lptr[s.lb + k + 1];
-        for (int p = p0 + lane; p < p1; p += WAVE) {
-            const size_t pl = (size_t)s.l * ns + p;
-            const int i = g.ord[pl];
-            double acc = 0.0;
+// wall values; else none) and the wrap inflow staged in LDS.  The workgroup
+// is one wavefront, whose LDS accesses are executed in program order, so
+// level k + 1 reads what level k wrote without a barrier; the table entries
+// of a lane's cell in the next level (independent of the solution) are
+// loaded while the current level is solved.
+struct UEnt {
+    int i;
+    double d, sg, b;              // outflow sum, sigma, sigma T_L + the wall inflow
+    int code[UFACES];             // cell / wrap-slot inflows (walls folded into b)
+    double c[UFACES];
+};
+
+__device__ __forceinline__ void ufetch(const UGeomDev& g, const USys& s, bool src, int p, UEnt& e) {
+    const size_t pl = (size_t)s.l * g.ns + p;
+    e.i = g.ord[pl];
+    e.d = g.dout[pl];
+    e.sg = g.sigma[e.i];
+    double wall = 0.0;
 #pragma unroll
-            for (int q = 0; q < UFACES; ++q) {
-                const int code = g.inc[pl * UFACES + q];
-                if (code == UNONE) continue;
-                double v;
-                if (code >= ns) v = uin[code - ns];
-                else if (code >= 0) v = x[code];
-                else v = src ? g.T_w[UWALL0 - code] : 0.0;
-                acc += g.inv[pl * UFACES + q] * v;
-            }
-            const double sg = g.sigma[i];
-            const double rhs = src ? sg * g.T_L[i] : 0.0;
-            x[i] = (rhs + s.lam * acc) / (sg + s.lam * g.dout[pl]);
+    for (int q = 0; q < UFACES; ++q) {
+        const int code = g.inc[pl * UFACES + q];
+        const double c = g.inv[pl * UFACES + q];
+        const bool w = code <= UWALL0;
+        wall += (w && src) ? c * g.T_w[w ? UWALL0 - code : 0] : 0.0;
+        e.code[q] = w ? UNONE : code;
+        e.c[q] = c;
+    }
+    e.b = src ? e.sg * g.T_L[e.i] + s.lam * wall : 0.0;
+}
+
+__device__ __forceinline__ void usolve(const UGeomDev& g, const USys& s, const UEnt& e, double* x, const double* uin) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < UFACES; ++q) {
+        const int code = e.code[q];
+        if (code == UNONE) continue;
+        const double v = code >= g.ns ? uin[code - g.ns] : x[code];
+        acc += e.c[q] * v;
+    }
+    x[e.i] = (e.b + s.lam * acc) / (e.sg + s.lam * e.d);
+}
+
+__device__ void usweep(const UGeomDev& g, const USys& s, bool src, double* x, const double* uin) {
+    const int lane = threadIdx.x;
+    int p0 = g.lptr[s.lb], p1 = g.lptr[s.lb + 1];
+    UEnt cur, nxt;
+    if (p0 + lane < p1) ufetch(g, s, src, p0 + lane, cur);
+    for (int k = 0; k < s.nlev; ++k) {
+        const bool more = k + 1 < s.nlev;
+        const int q0 = more ? g.lptr[s.lb + k + 1] : 0, q1 = more ? g.lptr[s.lb + k + 2] : 0;
+        if (q0 + lane < q1) ufetch(g, s, src, q0 + lane, nxt);
+        if (p0 + lane < p1) usolve(g, s, cur, x, uin);
+        for (int p = p0 + lane + WAVE; p < p1; p += WAVE) {
+            UEnt e;
+            ufetch(g, s, src, p, e);
+            usolve(g, s, e, x, uin);
         }
-        __syncthreads();
+        // keeps the compiler from moving this level's LDS accesses past the
+        // next level's
+        __builtin_amdgcn_wave_barrier();
+        cur = nxt;
+        p0 = q0;
+        p1 = q1;
     }
 }
 
@@ -245,7 +297,7 @@ __device__ __forceinline__ void ustage(const USys& s, const double (&v)[WPL], do
         const int q = k * WAVE + threadIdx.x;
         if (q < s.nw) uin[q] = v[k];
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
 }
 
 // G v: the values a homogeneous sweep with inflow v carries back across the
@@ -273,9 +325,13 @@ __global__ void __launch_bounds__(WAVE) k_upass(const UGeomDev* __restrict__ gp,
     const UGeomDev& g = *gp;
     const int lane = threadIdx.x;
     USys s;
-    s.sys = blockIdx.x;
-    const int m = s.sys / g.n_dir;
-    s.l = s.sys % g.n_dir;
+    // longest MFPs first (they take the most wrap iterations); the direction
+    // is the fast index, so with the workgroups dealt to the eight XCDs in
+    // turn each XCD sweeps a fixed subset of the directions and their tables
+    // stay in its L2
+    s.l = (int)blockIdx.x % g.n_dir;
+    const int m = g.n_mfp - 1 - (int)blockIdx.x / g.n_dir;
+    s.sys = m * g.n_dir + s.l;
     s.lam = g.mfp[m];
     s.lb = g.lbase[s.l];
     s.nlev = g.nlev[s.l];
@@ -412,20 +468,40 @@ __global__ void __launch_bounds__(WAVE) k_upass(const UGeomDev* __restrict__ gp,
 }
 
 // T_L = sum D x per cell, T_w = sum of the outgoing weights times x at the
-// wall's cell, both over the systems in order.
-__global__ void __launch_bounds__(256) k_ureduce(const UGeomDev* __restrict__ gp) {
+// wall's cell.  A block owns 64 cells (or 64 wall faces); its UQ waves sum
+// fixed chunks of the systems, combined in order.
+constexpr int UQ = 16;
+
+__global__ void __launch_bounds__(64 * UQ) k_ureduce(const UGeomDev* __restrict__ gp) {
+    __shared__ double part[UQ][64];
     const UGeomDev& g = *gp;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < g.ns) {
+    const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
+    const int cblocks = (g.ns + 63) / 64;
+    const bool walls = (int)blockIdx.x >= cblocks;
+    const int t = (walls ? (int)blockIdx.x - cblocks : (int)blockIdx.x) * 64 + cl;
+    const int n = walls ? g.nwalls : g.ns;
+    const bool in = t < n;
+    const int cell = in ? (walls ? g.wcell[t] : t) : 0;
+    const int per = (g.n_sys + UQ - 1) / UQ;
+    const int i0 = q * per, i1 = min(g.n_sys, i0 + per);
+    double a0 = 0.0, a1 = 0.0;
+    int i = i0;
+    for (; i + 1 < i1; i += 2) {
+        const double x0 = g.X[(size_t)i * g.ns + cell], x1 = g.X[(size_t)(i + 1) * g.ns + cell];
+        const double w0 = walls ? (in ? g.wout[(size_t)t * g.n_sys + i] : 0.0) : g.Dw[i];
+        const double w1 = walls ? (in ? g.wout[(size_t)t * g.n_sys + i + 1] : 0.0) : g.Dw[i + 1];
+        a0 += w0 * x0;
+        a1 += w1 * x1;
+    }
+    if (i < i1) a0 += (walls ? (in ? g.wout[(size_t)t * g.n_sys + i] : 0.0) : g.Dw[i]) * g.X[(size_t)i * g.ns + cell];
+    part[q][cl] = a0 + a1;
+    __syncthreads();
+    if (q == 0 && in) {
         double acc = 0.0;
-        for (int sys = 0; sys < g.n_sys; ++sys) acc += g.Dw[sys] * g.X[(size_t)sys * g.ns + t];
-        g.T_L[t] = acc;
-    } else if (t < g.ns + g.nwalls) {
-        const int w = t - g.ns;
-        const int c = g.wcell[w];
-        double acc = 0.0;
-        for (int sys = 0; sys < g.n_sys; ++sys) acc += g.wout[(size_t)w * g.n_sys + sys] * g.X[(size_t)sys * g.ns + c];
-        g.T_w[w] = acc;
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) acc += part[u][cl];
+        if (walls) g.T_w[t] = acc;
+        else g.T_L[t] = acc;
     }
 }
 
@@ -476,8 +552,8 @@ hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int wpl, size_t lds_by
 
 hipError_t ulaunch_reduce(const UGeomDev* g_dev, int ns, int nwalls, hipStream_t st) {
     (void)hipGetLastError();
-    const int n = ns + nwalls;
-    hipLaunchKernelGGL(k_ureduce, dim3((n + 255) / 256), dim3(256), 0, st, g_dev);
+    const int blocks = (ns + 63) / 64 + (nwalls + 63) / 64;
+    hipLaunchKernelGGL(k_ureduce, dim3(blocks), dim3(64 * UQ), 0, st, g_dev);
     hipLaunchKernelGGL(k_ukappa, dim3(1), dim3(256), 0, st, g_dev);
     return hipGetLastError();
 }

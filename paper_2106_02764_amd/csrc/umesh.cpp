@@ -691,7 +691,9 @@ obte_status obte_umesh_solve(obte_umesh* m, const obte_solve_opts* o, const doub
     // first guess: T_L = T_F, T_w = T_F of the wall's cell
     double kF = 0.0;
     int fit = 0;
-    obte_status sf = obte_umesh_fourier(m, o->fourier_tol, o->max_fourier, 1e-14, stream, nullptr, &kF, &fit);
+    // each conjugate-gradient solve to a hundredth of the outer tolerance
+    const double cg_tol = std::max(1e-14, 1e-2 * o->fourier_tol);
+    obte_status sf = obte_umesh_fourier(m, o->fourier_tol, o->max_fourier, cg_tol, stream, nullptr, &kF, &fit);
     if (sf != OBTE_OK && sf != OBTE_ERR_NOT_CONVERGED) return sf;
     UHIP(hipMemcpyAsync(g.T_L, m->fh.T, sizeof(double) * ns, hipMemcpyDeviceToDevice, st));
     if (nw > 0) {
