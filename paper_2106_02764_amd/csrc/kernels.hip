@@ -454,8 +454,10 @@ struct GlobIO {
     }
 };
 
-// One row step of the sweep (cells of row (jj, kk) in upwind order).
-template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, int GA, class IO>
+// One row step of the sweep (cells of row (jj, kk) in upwind order).  FULL:
+// the row fills every lane (nx = 64 CPL), so no lane holds cells beyond it.
+template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, int GA, bool FULL = false,
+          class IO>
 __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, const Views<T, CPL>& vw,
                                          int active, int lane, int adj, int jj, int kk,
                                          const RowIn<T, CPL, D3>& cur, Rows<T, CPL, D3>& rows, IO& io,
@@ -474,7 +476,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int p = lane * CPL + c;
-        const uint32_t w = p < nx ? cur.w[c] : 0u;     // beyond the row: not solid
+        const uint32_t w = (FULL || p < nx) ? cur.w[c] : 0u;     // beyond the row: not solid
         const bool sol = active && fc_solid(w);
         const int clx = fc_class(w, s.fin[0]);
         const int cly = fc_class(w, s.fin[1]);
@@ -501,7 +503,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         T pv = S1 ? (xs ? pxs1 : pnx1) : (sg + (xs ? cyz : cdiag)) * rdv;
         // pore: (0, 0, 1) breaks the chain; beyond the row (face word 0, so
         // not solid either): the identity (0, 1, 0)
-        const bool beyond = p >= nx;
+        const bool beyond = !FULL && p >= nx;
         av = sol ? av : T(0);
         qv = sol ? qv : (beyond ? T(1) : T(0));
         pv = sol ? pv : (beyond ? T(0) : T(1));
@@ -526,7 +528,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
     for (int c = 0; c < CPL; ++c) {
         const T xv = a[c] + q[c] * xp;
         const int p = lane * CPL + c;
-        xrow[c] = (p < nx) ? xv : T(0);
+        xrow[c] = (FULL || p < nx) ? xv : T(0);
         rows.put(kk, c, lane, xrow[c]);
         xp = xv;
     }
@@ -537,16 +539,18 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
     if (RED) {
         // branch-free: cells that contribute nothing add an exact 0 (an
         // inactive wave's sums are dropped, its stores skipped)
+        // the row's cells summed in the compute type, the rows in double
+        T rsum = T(0);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int p = lane * CPL + c;
-            const uint32_t wv = p < nx ? cur.w[c] : 0u;
+            const uint32_t wv = (FULL || p < nx) ? cur.w[c] : 0u;
             const bool sol = fc_solid(wv);
             ro.x[c] = xrow[c];
             ro.si[c] = sol ? cur.si[c] : -1;
-            const double xv = sol ? (double)xrow[c] : 0.0;
-            rd->kacc += xv;
+            rsum += sol ? xrow[c] : T(0);
         }
+        rd->kacc += (double)rsum;
         // Flux through the periodic plane of the gradient axis (kappa_face;
         // the adjoint: p^T lambda of the jump inflow, on the forward's jump
         // faces = this sweep's outflow faces).  The jump term belongs to the
@@ -583,7 +587,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int p = lane * CPL + c;
-                const uint32_t wv = p < nx ? cur.w[c] : 0u;
+                const uint32_t wv = (FULL || p < nx) ? cur.w[c] : 0u;
                 if (!fc_solid(wv)) continue;
                 const double xv = (double)xrow[c];
                 const int cl = fc_class(wv, s.fout[1]);
@@ -628,7 +632,8 @@ __device__ __forceinline__ void store_rows(Red<T>* rd, const RowOut<T, CPL> (&ro
 // ---------------------------------------------------------------------------
 
 
-template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, int GA, class IO>
+template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, int GA, bool FULL = false,
+          class IO>
 __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int active, int lane, int adj,
                                       const double* __restrict__ srcbase, const double* __restrict__ bnd,
                                       IO& io, Red<T>* rd, T* zrows) {
@@ -689,7 +694,7 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
         load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, D3 ? rr / nz : rr, D3 ? rr % nz : 0, b);
     };
     auto step = [&](int r, const RowIn<T, CPL, D3>& b, RowOut<T, CPL>& ro) {
-        row_step<T, CPL, D3, WITH_B, RED, ADD, S1, GA>(g, s, vw, active, lane, adj, D3 ? r / nz : r, D3 ? r % nz : 0,
+        row_step<T, CPL, D3, WITH_B, RED, ADD, S1, GA, FULL>(g, s, vw, active, lane, adj, D3 ? r / nz : r, D3 ? r % nz : 0,
                                                        b, rows, io, mb, rd, ro);
     };
     RowIn<T, CPL, D3> b0, b1, b2;
@@ -790,7 +795,7 @@ __device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s
 // changed u sweeps the source P (u - u0) and adds the (linear) response to
 // its stored solution.
 // ---------------------------------------------------------------------------
-template <typename T, int CPL, int ADJ, int SIG1>
+template <typename T, int CPL, int ADJ, int SIG1, bool FULL>
 __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ geoms,
                                                     const Item* __restrict__ items, int n_items,
                                                     PassParams pp) {
@@ -825,9 +830,9 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     {
         RegIO<T, CPL> io{u[0], xl[0]};
         if (g.grad_axis == 0)
-            sweep<T, CPL, false, true, true, false, SIG1 != 0, 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+            sweep<T, CPL, false, true, true, false, SIG1 != 0, 0, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
         else
-            sweep<T, CPL, false, true, true, false, SIG1 != 0, 1>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+            sweep<T, CPL, false, true, true, false, SIG1 != 0, 1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
     }
     long long n_it = 0, n_sw = 1;
     int need = 0;
@@ -872,7 +877,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 VLOOP(p[k][c] = r[k][c] + (T)beta * (p[k][c] - (T)omega * v[k][c]));
                 {
                     RegIO<T, CPL> io{p[0], xl[0]};
-                    sweep<T, CPL, false, false, false, false, SIG1 != 0, -1>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                    sweep<T, CPL, false, false, false, false, SIG1 != 0, -1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
                 }
                 ++n_sw;
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
@@ -896,7 +901,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 }
                 {
                     RegIO<T, CPL> io{sv[0], xl[0]};
-                    sweep<T, CPL, false, false, false, false, SIG1 != 0, -1>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                    sweep<T, CPL, false, false, false, false, SIG1 != 0, -1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
                 }
                 ++n_sw;
                 VLOOP(t[k][c] = sv[k][c] - mk[k][c] * xl[k][c]);
@@ -926,9 +931,9 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     if (!pp.lag_wrap && need) {
         RegIO<T, CPL> io{du[0], xl[0]};
         if (g.grad_axis == 0)
-            sweep<T, CPL, false, false, true, true, SIG1 != 0, 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+            sweep<T, CPL, false, false, true, true, SIG1 != 0, 0, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
         else
-            sweep<T, CPL, false, false, true, true, SIG1 != 0, 1>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+            sweep<T, CPL, false, false, true, true, SIG1 != 0, 1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
         ++n_sw;
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
@@ -2231,19 +2236,26 @@ hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, int max_
     return hipGetLastError();
 }
 
-template <typename T, int CPL>
-static hipError_t launch_sweep_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
+template <typename T, int CPL, bool FULL>
+static hipError_t launch_sweep_f(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
                                  size_t lds, hipStream_t st) {
     (void)hipGetLastError();
     const dim3 grid(n), block(64 * waves);
     if (pp.adjoint) {
-        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass<T, CPL, 1, 1>), grid, block, lds, st, g, it, n, pp);
-        else hipLaunchKernelGGL((k_sweep_pass<T, CPL, 1, 0>), grid, block, lds, st, g, it, n, pp);
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass<T, CPL, 1, 1, FULL>), grid, block, lds, st, g, it, n, pp);
+        else hipLaunchKernelGGL((k_sweep_pass<T, CPL, 1, 0, FULL>), grid, block, lds, st, g, it, n, pp);
     } else {
-        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass<T, CPL, 0, 1>), grid, block, lds, st, g, it, n, pp);
-        else hipLaunchKernelGGL((k_sweep_pass<T, CPL, 0, 0>), grid, block, lds, st, g, it, n, pp);
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass<T, CPL, 0, 1, FULL>), grid, block, lds, st, g, it, n, pp);
+        else hipLaunchKernelGGL((k_sweep_pass<T, CPL, 0, 0, FULL>), grid, block, lds, st, g, it, n, pp);
     }
     return hipGetLastError();
+}
+
+template <typename T, int CPL>
+static hipError_t launch_sweep_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
+                                 size_t lds, hipStream_t st, int full) {
+    return full ? launch_sweep_f<T, CPL, true>(g, it, n, waves, pp, lds, st)
+                : launch_sweep_f<T, CPL, false>(g, it, n, waves, pp, lds, st);
 }
 
 template <typename T, int CPL>
@@ -2262,7 +2274,7 @@ static hipError_t launch_sweep3_t(const GeomDev* g, const Item* it, int n, int w
 }
 
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, const Item* it,
-                             int n, int waves, PassParams pp, size_t lds, hipStream_t st) {
+                             int n, int waves, PassParams pp, size_t lds, hipStream_t st, int full) {
     if (nz > 1) {
         if (precision == 0) {
             switch (cpl) {
@@ -2281,17 +2293,17 @@ hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, c
     }
     if (precision == 0) {
         switch (cpl) {
-            case 1: return launch_sweep_t<double, 1>(g, it, n, waves, pp, lds, st);
-            case 2: return launch_sweep_t<double, 2>(g, it, n, waves, pp, lds, st);
-            case 3: return launch_sweep_t<double, 3>(g, it, n, waves, pp, lds, st);
-            default: return launch_sweep_t<double, 4>(g, it, n, waves, pp, lds, st);
+            case 1: return launch_sweep_t<double, 1>(g, it, n, waves, pp, lds, st, full);
+            case 2: return launch_sweep_t<double, 2>(g, it, n, waves, pp, lds, st, full);
+            case 3: return launch_sweep_t<double, 3>(g, it, n, waves, pp, lds, st, full);
+            default: return launch_sweep_t<double, 4>(g, it, n, waves, pp, lds, st, full);
         }
     }
     switch (cpl) {
-        case 1: return launch_sweep_t<float, 1>(g, it, n, waves, pp, lds, st);
-        case 2: return launch_sweep_t<float, 2>(g, it, n, waves, pp, lds, st);
-        case 3: return launch_sweep_t<float, 3>(g, it, n, waves, pp, lds, st);
-        default: return launch_sweep_t<float, 4>(g, it, n, waves, pp, lds, st);
+        case 1: return launch_sweep_t<float, 1>(g, it, n, waves, pp, lds, st, full);
+        case 2: return launch_sweep_t<float, 2>(g, it, n, waves, pp, lds, st, full);
+        case 3: return launch_sweep_t<float, 3>(g, it, n, waves, pp, lds, st, full);
+        default: return launch_sweep_t<float, 4>(g, it, n, waves, pp, lds, st, full);
     }
 }
 

@@ -129,7 +129,7 @@ hipError_t launch_fourier_pending(const GeomDev* geoms_dev, int n_geoms, int* pe
 hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, int max_cells, hipStream_t st);
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
                              const Item* items_dev, int n_items, int waves, PassParams pp,
-                             size_t lds_bytes, hipStream_t st);
+                             size_t lds_bytes, hipStream_t st, int full);
 hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_solid,
                               PassParams pp, hipStream_t st);
 // Energy balance of the last pass of one geometry (forward solve):
