@@ -107,25 +107,27 @@ __global__ void __launch_bounds__(256) k_apply(const GeomDev* __restrict__ gp, c
     }
 }
 
-// Four consecutive cells of one row per thread (rows of a multiple of four
-// cells): the centre values, the upwind y and z neighbours and the store are
-// one 16-byte (FP32) or two 16-byte (FP64) accesses, and the x neighbours come
-// from the same registers except one value at the quad's edge.  Per thread
-// NS systems, whose loads are all issued before the first store.
-template <typename T>
-struct alignas(4 * sizeof(T)) Quad {
-    T v[4];
+// N consecutive cells of one row per thread (32 bytes: four doubles or
+// eight floats; rows of a multiple of N cells): the centre values, the
+// upwind y and z neighbours and the store are 32-byte accesses, and the x
+// neighbours come from the same registers except one value at the group's
+// edge.  Per thread NS systems, whose loads are all issued before the first
+// store; the results are written past the caches (streaming stores), so the
+// L2 keeps the inputs the neighbouring tiles read again.
+template <typename T, int N>
+struct alignas(N * sizeof(T)) Vec {
+    T v[N];
 };
 
-template <typename T, int NS>
-__global__ void __launch_bounds__(256) k_apply4(const GeomDev* __restrict__ gp, const double* __restrict__ sigma,
+template <typename T, int NS, int N>
+__global__ void __launch_bounds__(256) k_applyv(const GeomDev* __restrict__ gp, const double* __restrict__ sigma,
                                                 const int* __restrict__ sys_ids, int n_sys,
                                                 const T* __restrict__ x, T* __restrict__ y, int transpose) {
     __shared__ double coef[NS][3];
     __shared__ int from_plus[NS][3];
     __shared__ int valid[NS];
     const GeomDev& g = *gp;
-    const int tiles = (g.ncells / 4 + 255) / 256;
+    const int tiles = (g.ncells / N + 255) / 256;
     const int lb = xcd_order(blockIdx.x, gridDim.x);
     const int tile = lb % tiles;
     const int s0 = (lb / tiles) * NS;
@@ -148,33 +150,33 @@ __global__ void __launch_bounds__(256) k_apply4(const GeomDev* __restrict__ gp, 
         if (a == 0) valid[k] = ok;
     }
     __syncthreads();
-    const int c0 = 4 * (tile * blockDim.x + threadIdx.x);
+    const int c0 = N * (tile * blockDim.x + threadIdx.x);
     if (c0 >= g.ncells) return;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const bool d3 = g.ndim == 3;
-    uint16_t w[4];
-    double sg[4];
+    uint16_t w[N];
+    double sg[N];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < N; ++j) {
         w[j] = g.fc[c0 + j];
         sg[j] = sigma ? sigma[c0 + j] : 1.0;
     }
     const int ix = c0 % nx, iy = (c0 / nx) % ny, iz = c0 / (nx * ny);
-    const int left = c0 + (ix > 0 ? -1 : nx - 1);                 // x neighbour of the first cell, - side
-    const int right = c0 + 3 + (ix + 3 < nx - 1 ? 1 : 1 - nx);    // of the last cell, + side
+    const int left = c0 + (ix > 0 ? -1 : nx - 1);                          // x neighbour of the first cell, - side
+    const int right = c0 + N - 1 + (ix + N - 1 < nx - 1 ? 1 : 1 - nx);     // of the last cell, + side
     const int ym = c0 + (iy > 0 ? -nx : nx * (ny - 1)), yp = c0 + (iy < ny - 1 ? nx : -nx * (ny - 1));
     const int zm = c0 + (iz > 0 ? -nx * ny : nx * ny * (nz - 1));
     const int zp = c0 + (iz < nz - 1 ? nx * ny : -nx * ny * (nz - 1));
     const size_t nc = (size_t)g.ncells;
-    Quad<T> xc[NS], xy[NS], xz[NS];
+    Vec<T, N> xc[NS], xy[NS], xz[NS];
     T xb[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const T* xk = x + (size_t)(s0 + (k < ns ? k : 0)) * nc;
-        xc[k] = *reinterpret_cast<const Quad<T>*>(xk + c0);
+        xc[k] = *reinterpret_cast<const Vec<T, N>*>(xk + c0);
         xb[k] = xk[from_plus[k][0] ? right : left];
-        xy[k] = *reinterpret_cast<const Quad<T>*>(xk + (from_plus[k][1] ? yp : ym));
-        if (d3) xz[k] = *reinterpret_cast<const Quad<T>*>(xk + (from_plus[k][2] ? zp : zm));
+        xy[k] = *reinterpret_cast<const Vec<T, N>*>(xk + (from_plus[k][1] ? yp : ym));
+        if (d3) xz[k] = *reinterpret_cast<const Vec<T, N>*>(xk + (from_plus[k][2] ? zp : zm));
         else xz[k] = xc[k];
     }
 #pragma unroll
@@ -182,12 +184,13 @@ __global__ void __launch_bounds__(256) k_apply4(const GeomDev* __restrict__ gp, 
         if (k >= ns) break;
         const int px = from_plus[k][0], py = from_plus[k][1], pz = from_plus[k][2];
         const double cx = coef[k][0], cy = coef[k][1], cz = coef[k][2];
-        Quad<T> out;
+        T* yk = y + (size_t)(s0 + k) * nc + c0;
+        Vec<T, N> out;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < N; ++j) {
             const double xv = (double)xc[k].v[j];
             const T xl = j > 0 ? xc[k].v[j > 0 ? j - 1 : 0] : xb[k];
-            const T xr = j < 3 ? xc[k].v[j < 3 ? j + 1 : 3] : xb[k];
+            const T xr = j < N - 1 ? xc[k].v[j < N - 1 ? j + 1 : N - 1] : xb[k];
             double acc = sg[j] * xv;
             acc += cx * xv;
             acc -= fc_class(w[j], px) != FC_WALL ? cx * (double)(px ? xr : xl) : 0.0;
@@ -197,7 +200,16 @@ __global__ void __launch_bounds__(256) k_apply4(const GeomDev* __restrict__ gp, 
             acc -= (d3 && fc_class(w[j], 4 + pz) != FC_WALL) ? cz * (double)xz[k].v[j] : 0.0;
             out.v[j] = (fc_solid(w[j]) && valid[k]) ? (T)acc : T(0);
         }
-        *reinterpret_cast<Quad<T>*>(y + (size_t)(s0 + k) * nc + c0) = out;
+        // 16-byte streaming stores of the group
+        using V16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+        constexpr int E = 16 / sizeof(T);
+#pragma unroll
+        for (int h = 0; h < N / E; ++h) {
+            V16 v;
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = out.v[h * E + e];
+            __builtin_nontemporal_store(v, reinterpret_cast<V16*>(yk) + h);
+        }
     }
 }
 
@@ -207,23 +219,20 @@ hipError_t launch_apply(int precision, int transpose, const GeomDev* g_dev, cons
                         const double* sigma, const int* sys_ids, int n_sys, const void* x, void* y,
                         hipStream_t st) {
     (void)hipGetLastError();
-    // the quad form: rows of a multiple of four cells and 16-byte aligned
-    // arrays (x, y, sigma) so that no quad access straddles a row or is
-    // misaligned
-    const size_t qa = precision == 0 ? 32 : 16;
-    const bool quads = g_host.nx % 4 == 0 && (uintptr_t)x % qa == 0 && (uintptr_t)y % qa == 0 &&
-                       (uintptr_t)sigma % 16 == 0;
-    if (quads) {
-        const int nq = g_host.ncells / 4;
-        if (precision == 0) {
-            constexpr int NS = 4;
-            hipLaunchKernelGGL((k_apply4<double, NS>), dim3((nq + 255) / 256 * ((n_sys + NS - 1) / NS)), dim3(256), 0,
-                               st, g_dev, sigma, sys_ids, n_sys, (const double*)x, (double*)y, transpose);
-        } else {
-            constexpr int NS = 8;
-            hipLaunchKernelGGL((k_apply4<float, NS>), dim3((nq + 255) / 256 * ((n_sys + NS - 1) / NS)), dim3(256), 0,
-                               st, g_dev, sigma, sys_ids, n_sys, (const float*)x, (float*)y, transpose);
-        }
+    // the vector form: rows of a multiple of N cells (32 bytes of values per
+    // thread) and 32-byte aligned x, y, so that no access straddles a row or
+    // is misaligned
+    const int N = precision == 0 ? 4 : 8;
+    const bool vec = g_host.nx % N == 0 && (uintptr_t)x % 32 == 0 && (uintptr_t)y % 32 == 0;
+    if (vec) {
+        constexpr int NS = 4;
+        const int groups = (g_host.ncells / N + 255) / 256 * ((n_sys + NS - 1) / NS);
+        if (precision == 0)
+            hipLaunchKernelGGL((k_applyv<double, NS, 4>), dim3(groups), dim3(256), 0, st, g_dev, sigma, sys_ids,
+                               n_sys, (const double*)x, (double*)y, transpose);
+        else
+            hipLaunchKernelGGL((k_applyv<float, NS, 8>), dim3(groups), dim3(256), 0, st, g_dev, sigma, sys_ids,
+                               n_sys, (const float*)x, (float*)y, transpose);
         return hipGetLastError();
     }
     dim3 grid((g_host.ncells + 255) / 256 * ((n_sys + APPLY_SYS - 1) / APPLY_SYS));
