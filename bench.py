@@ -62,8 +62,8 @@ REF = dict(precision=0, outer_tol=1e-10, stop_rule=0, accel=8, inner_tol=1e-12, 
 # operating point, per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over one
 # solve, each scaled by the same counter on a plain 256 MiB copy); valid only
 # for the kernel source it was taken on.
-TRAFFIC = {"kernels_sha256": "587d815066fbfda34a0786033e9c74c57bb1eb10c85288e9ec223c6e6663ea90",
-           "fetch_bytes": 8643169, "write_bytes": 59386904}
+TRAFFIC = {"kernels_sha256": "cf3504277473796f276563e5fd7cfa0f9df219f822e01098e8a07128109f1df1",
+           "fetch_bytes": 8574137, "write_bytes": 59387184}
 
 
 def parse():
@@ -374,14 +374,15 @@ def unstructured_leg(P, steps=3):
     cells with unstructured polygons): a 100 nm cell with a centred pore
     (r = 30 nm), 64 x 64 node lattice displaced by 0.3 h, two triangles per
     quadrilateral; 48 directions x 30 MFPs; FP64; the non-orthogonal
-    heat-conduction first guess, then passes to a 1e-6 relative change."""
+    heat-conduction first guess, then passes to a 1e-6 relative change
+    (forcing term 0.3 on the periodic-face solves)."""
     import torch
     from inputs import gen
     nm = 1e-9
     w = gen.unstructured_2d(64, 64, amp=0.3, tri=True, seed=7, L=100 * nm,
                             pores=[((50 * nm, 50 * nm), 30 * nm)], n_dir=48, n_mfp=30, mfp_hi=100e-6)
     s = P.UMeshSolver.from_workload(w)
-    o = s.opts(outer_tol=1e-6, max_outer=3000, inner_tol=1e-10, max_inner=100, fourier_tol=1e-8)
+    o = s.opts(outer_tol=1e-6, max_outer=3000, inner_tol=1e-8, inner_rtol=0.3, max_inner=100, fourier_tol=1e-8)
     r = s.solve(o)                      # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -405,7 +405,10 @@ obte_status obte_umesh_fourier(obte_umesh* mesh, double tol, int max_outer, doub
  * opts->fourier_tol), then passes until |kappa_n - kappa_{n-1}| <=
  * opts->outer_tol |kappa_n| or opts->max_outer passes.  Each pass solves
  * every (m, l) system exactly up to its periodic-face coupling, which
- * BiCGSTAB solves to opts->inner_tol (at most opts->max_inner iterations).
+ * BiCGSTAB solves to opts->inner_tol (at most opts->max_inner iterations),
+ * or, with opts->inner_rtol > 0, until its residual fell by that factor (the
+ * rest carries into the next pass; the stop test then also requires every
+ * relative wrap residual <= wrap_tol, as for obte_solve).
  * Only precision = OBTE_FP64, init = 0 and accel = 0 are accepted.
  * sigma_dev: device, n_cells relaxation multipliers, or NULL for 1.
  * T_L_dev: device, n_cells doubles (mean zero over solid cells) or NULL.

@@ -561,7 +561,7 @@ struct Run {
     int cls_first[5] = {}, cls_count[5] = {};
     size_t cls_lds[5] = {};
     int cls_waves[5] = {4, 4, 4, 4, 4};   // systems per workgroup of each launch class
-    int cls_full[5] = {1, 1, 1, 1, 1};    // 2D class whose every row is exactly 64 * class cells
+    int cls_full[5] = {1, 1, 1, 1, 1};    // class whose every row is exactly 64 * class cells
     int nzmax = 1, precision = 0, accel = 0;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
     int max_cells = 0, max_walls = 0, max_solid = 0;
@@ -659,7 +659,7 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         obte_mesh* m = meshes[gi];
         const int c = (m->nx + 63) / 64;
         const int W = Wc[c];
-        if (m->nx != 64 * c || m->nz > 1) R.cls_full[c] = 0;
+        if (m->nx != 64 * c) R.cls_full[c] = 0;
         Layout L = make_layout(m, o, W);
         if (offsets) offsets->push_back(off);
         GeomDev v = make_view(m, ws + off, L, W, o->accel);

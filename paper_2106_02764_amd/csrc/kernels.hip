@@ -486,7 +486,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         const T rdv = S1 ? rdv1 : recip(sg + cdiag);
         // kk and jj are wave-uniform: the wrap input is used on the first row
         // only (3D: prefetched with every row, so its load is in no branch)
-        const T uin = D3 ? (p < nx ? cur.ui[c] : T(0)) : io.in(kk, c, lane);
+        const T uin = D3 ? ((FULL || p < nx) ? cur.ui[c] : T(0)) : io.in(kk, c, lane);
         T yin = T(0);
         if (cly != FC_WALL) yin = (jj == 0) ? uin : s.c[1] * rows.prev_y(kk, c, lane);
         T rhs = yin;
@@ -958,7 +958,7 @@ static_assert(KV_N == KRY3_VECS, "workspace carve and kernel disagree on the 3D 
             }                                           \
         }
 
-template <typename T, int CPL, int ADJ, int SIG1>
+template <typename T, int CPL, int ADJ, int SIG1, bool FULL>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL == 1 ? (sizeof(T) == 4 ? 5 : 4) : 1))) k_sweep_pass3(const GeomDev* __restrict__ geoms,
                                                      const Item* __restrict__ items, int n_items,
                                                      PassParams pp) {
@@ -992,9 +992,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     {
         GlobIO<T, CPL> io{U, xl, nx, active};
         if (g.grad_axis == 0)
-            sweep<T, CPL, true, true, true, false, SIG1 != 0, 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+            sweep<T, CPL, true, true, true, false, SIG1 != 0, 0, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
         else
-            sweep<T, CPL, true, true, true, false, SIG1 != 0, 1>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+            sweep<T, CPL, true, true, true, false, SIG1 != 0, 1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
     }
     long long n_it = 0, n_sw = 1;
     int need = 0;
@@ -1056,7 +1056,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
                 PLOOP(p[i] = r[i] + (T)beta * (p[i] - (T)omega * v[i]));
                 {
                     GlobIO<T, CPL> io{p, xl, nx, 1};
-                    sweep<T, CPL, true, false, false, false, SIG1 != 0, -1>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
+                    sweep<T, CPL, true, false, false, false, SIG1 != 0, -1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
                 }
                 ++n_sw;
                 acc = 0.0;
@@ -1091,7 +1091,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
                 }
                 {
                     GlobIO<T, CPL> io{sv, xl, nx, 1};
-                    sweep<T, CPL, true, false, false, false, SIG1 != 0, -1>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
+                    sweep<T, CPL, true, false, false, false, SIG1 != 0, -1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
                 }
                 ++n_sw;
                 double tt = 0.0, ts = 0.0;
@@ -1130,9 +1130,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     if (!pp.lag_wrap && need) {
         GlobIO<T, CPL> io{du, nullptr, nx, 0};
         if (g.grad_axis == 0)
-            sweep<T, CPL, true, false, true, true, SIG1 != 0, 0>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+            sweep<T, CPL, true, false, true, true, SIG1 != 0, 0, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
         else
-            sweep<T, CPL, true, false, true, true, SIG1 != 0, 1>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
+            sweep<T, CPL, true, false, true, true, SIG1 != 0, 1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
         ++n_sw;
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
@@ -2258,19 +2258,26 @@ static hipError_t launch_sweep_t(const GeomDev* g, const Item* it, int n, int wa
                 : launch_sweep_f<T, CPL, false>(g, it, n, waves, pp, lds, st);
 }
 
-template <typename T, int CPL>
-static hipError_t launch_sweep3_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
+template <typename T, int CPL, bool FULL>
+static hipError_t launch_sweep3_f(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
                                   size_t lds, hipStream_t st) {
     (void)hipGetLastError();
     const dim3 grid(n), block(64 * waves);
     if (pp.adjoint) {
-        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 1, 1>), grid, block, lds, st, g, it, n, pp);
-        else hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 1, 0>), grid, block, lds, st, g, it, n, pp);
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 1, 1, FULL>), grid, block, lds, st, g, it, n, pp);
+        else hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 1, 0, FULL>), grid, block, lds, st, g, it, n, pp);
     } else {
-        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 0, 1>), grid, block, lds, st, g, it, n, pp);
-        else hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 0, 0>), grid, block, lds, st, g, it, n, pp);
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 0, 1, FULL>), grid, block, lds, st, g, it, n, pp);
+        else hipLaunchKernelGGL((k_sweep_pass3<T, CPL, 0, 0, FULL>), grid, block, lds, st, g, it, n, pp);
     }
     return hipGetLastError();
+}
+
+template <typename T, int CPL>
+static hipError_t launch_sweep3_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
+                                  size_t lds, hipStream_t st, int full) {
+    return full ? launch_sweep3_f<T, CPL, true>(g, it, n, waves, pp, lds, st)
+                : launch_sweep3_f<T, CPL, false>(g, it, n, waves, pp, lds, st);
 }
 
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, const Item* it,
@@ -2278,17 +2285,17 @@ hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, c
     if (nz > 1) {
         if (precision == 0) {
             switch (cpl) {
-                case 1: return launch_sweep3_t<double, 1>(g, it, n, waves, pp, lds, st);
-                case 2: return launch_sweep3_t<double, 2>(g, it, n, waves, pp, lds, st);
-                case 3: return launch_sweep3_t<double, 3>(g, it, n, waves, pp, lds, st);
-                default: return launch_sweep3_t<double, 4>(g, it, n, waves, pp, lds, st);
+                case 1: return launch_sweep3_t<double, 1>(g, it, n, waves, pp, lds, st, full);
+                case 2: return launch_sweep3_t<double, 2>(g, it, n, waves, pp, lds, st, full);
+                case 3: return launch_sweep3_t<double, 3>(g, it, n, waves, pp, lds, st, full);
+                default: return launch_sweep3_t<double, 4>(g, it, n, waves, pp, lds, st, full);
             }
         }
         switch (cpl) {
-            case 1: return launch_sweep3_t<float, 1>(g, it, n, waves, pp, lds, st);
-            case 2: return launch_sweep3_t<float, 2>(g, it, n, waves, pp, lds, st);
-            case 3: return launch_sweep3_t<float, 3>(g, it, n, waves, pp, lds, st);
-            default: return launch_sweep3_t<float, 4>(g, it, n, waves, pp, lds, st);
+            case 1: return launch_sweep3_t<float, 1>(g, it, n, waves, pp, lds, st, full);
+            case 2: return launch_sweep3_t<float, 2>(g, it, n, waves, pp, lds, st, full);
+            case 3: return launch_sweep3_t<float, 3>(g, it, n, waves, pp, lds, st, full);
+            default: return launch_sweep3_t<float, 4>(g, it, n, waves, pp, lds, st, full);
         }
     }
     if (precision == 0) {

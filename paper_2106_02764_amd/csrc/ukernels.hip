@@ -320,7 +320,8 @@ __device__ __forceinline__ double udot(const double (&a)[WPL], const double (&b)
 }
 
 template <int WPL>
-__global__ void __launch_bounds__(WAVE) k_upass(const UGeomDev* __restrict__ gp, double inner_tol, int max_inner) {
+__global__ void __launch_bounds__(WAVE) k_upass(const UGeomDev* __restrict__ gp, double inner_tol, double inner_rtol,
+                                                int max_inner) {
     extern __shared__ double lds[];
     const UGeomDev& g = *gp;
     const int lane = threadIdx.x;
@@ -360,7 +361,10 @@ __global__ void __launch_bounds__(WAVE) k_upass(const UGeomDev* __restrict__ gp,
     const double scale = sqrt(udot(ez, ez));
     double rn = sqrt(udot(r, r));
     long long its = 0;
-    const double thr = inner_tol * scale;
+    // this pass's target: inner_tol relative to the inflow, or (forcing
+    // term) a cut by inner_rtol of the residual the pass started from; the
+    // rest carries into the next pass through U
+    const double thr = fmax(inner_tol * scale, inner_rtol * rn);
     if (s.nw > 0 && scale > 0.0 && rn > thr) {
         // ---- BiCGSTAB on (I - G) e = r, the best iterate kept
         double e[WPL], eb[WPL], rh[WPL], p[WPL], v[WPL], sv[WPL], tt[WPL], gx[WPL];
@@ -537,14 +541,14 @@ hipError_t ulaunch_fourier(const UFourierDev* f_dev, int ns, double tol, int max
     return hipGetLastError();
 }
 
-hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int wpl, size_t lds_bytes, double inner_tol, int max_inner,
-                        hipStream_t st) {
+hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int wpl, size_t lds_bytes, double inner_tol,
+                        double inner_rtol, int max_inner, hipStream_t st) {
     (void)hipGetLastError();
     switch (wpl) {
-    case 1: hipLaunchKernelGGL(k_upass<1>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, max_inner); break;
-    case 2: hipLaunchKernelGGL(k_upass<2>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, max_inner); break;
-    case 4: hipLaunchKernelGGL(k_upass<4>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, max_inner); break;
-    case 8: hipLaunchKernelGGL(k_upass<8>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, max_inner); break;
+    case 1: hipLaunchKernelGGL(k_upass<1>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, inner_rtol, max_inner); break;
+    case 2: hipLaunchKernelGGL(k_upass<2>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, inner_rtol, max_inner); break;
+    case 4: hipLaunchKernelGGL(k_upass<4>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, inner_rtol, max_inner); break;
+    case 8: hipLaunchKernelGGL(k_upass<8>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, inner_rtol, max_inner); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

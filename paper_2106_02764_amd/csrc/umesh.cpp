@@ -676,6 +676,7 @@ obte_status obte_umesh_solve(obte_umesh* m, const obte_solve_opts* o, const doub
     if (o->init != 0) return ufail(OBTE_ERR_ARG, "the unstructured path starts from the Fourier guess (init 0)");
     if (o->accel != 0) return ufail(OBTE_ERR_ARG, "the unstructured path runs Algorithm 1 (accel 0)");
     if (o->max_outer < 1 || !(o->outer_tol >= 0.0) || !(o->inner_tol > 0.0) || o->max_inner < 1 ||
+        !(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0) ||
         !(o->fourier_tol >= 0.0) || o->max_fourier < 1)
         return ufail(OBTE_ERR_ARG, "invalid tolerances or iteration caps");
     hipStream_t st = (hipStream_t)stream;
@@ -707,16 +708,20 @@ obte_status obte_umesh_solve(obte_umesh* m, const obte_solve_opts* o, const doub
     const size_t lds = sizeof(double) * ((size_t)ns + m->wmax);
     std::vector<double> hist;
     double kap[4] = {0, 0, 0, 0};
+    const double wrap_tol = o->wrap_tol > 0.0 ? o->wrap_tol : std::max(o->inner_tol, 0.2 * o->outer_tol);
     bool converged = false;
     int passes = 0;
     for (passes = 1; passes <= o->max_outer; ++passes) {
-        UHIP(ulaunch_pass(m->gd, m->n_sys, wpl, lds, o->inner_tol, o->max_inner, st));
+        UHIP(ulaunch_pass(m->gd, m->n_sys, wpl, lds, o->inner_tol, o->inner_rtol, o->max_inner, st));
         UHIP(ulaunch_reduce(m->gd, ns, nw, st));
         UHIP(hipMemcpyAsync(kap, g.kap, sizeof kap, hipMemcpyDeviceToHost, st));
         UHIP(hipStreamSynchronize(st));
         if (!std::isfinite(kap[0])) return ufail(OBTE_ERR_NUMERIC, "non-finite kappa in pass %d", passes);
         hist.push_back(kap[0]);
-        if (hist.size() >= 2 && std::fabs(kap[0] - hist[hist.size() - 2]) <= o->outer_tol * std::fabs(kap[0])) {
+        // Algorithm 1's test, and every wrap solved to wrap_tol (a forcing
+        // term leaves part of the periodic coupling to later passes)
+        if (hist.size() >= 2 && std::fabs(kap[0] - hist[hist.size() - 2]) <= o->outer_tol * std::fabs(kap[0]) &&
+            kap[2] <= wrap_tol) {
             converged = true;
             break;
         }

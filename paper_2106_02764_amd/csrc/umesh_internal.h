@@ -87,5 +87,5 @@ struct UFourierDev {
 hipError_t ulaunch_fourier(const UFourierDev* f_dev, int ns, double tol, int max_outer, double cg_tol,
                            int max_cg, hipStream_t st);
 hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int wpl, size_t lds_bytes, double inner_tol,
-                        int max_inner, hipStream_t st);
+                        double inner_rtol, int max_inner, hipStream_t st);
 hipError_t ulaunch_reduce(const UGeomDev* g_dev, int ns, int nwalls, hipStream_t st);

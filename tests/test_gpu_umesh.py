@@ -123,3 +123,19 @@ def test_umesh_rejections(P):
         assert e.value.status == P.obte.OBTE_ERR_ARG
     r = s.solve(s.opts(outer_tol=0.0, max_outer=2))
     assert r["status"] == P.obte.OBTE_ERR_NOT_CONVERGED and r["outer_iters"] == 2
+
+
+def test_forcing_term_same_fixed_point(P):
+    """A forcing term on the periodic-face solves (part of the coupling left
+    to later passes) converges to the same kappa and T_L, in fewer inner
+    iterations."""
+    w = CASES["tri_pore"]()
+    s = P.UMeshSolver.from_workload(w)
+    base = dict(outer_tol=1e-12, max_outer=5000, inner_tol=1e-14, max_inner=200, fourier_tol=1e-13)
+    r0 = s.solve(s.opts(**base))
+    r1 = s.solve(s.opts(inner_rtol=0.3, **base))
+    assert r0["status"] == 0 and r1["status"] == 0
+    assert r1["inner_iters"] < r0["inner_iters"]
+    assert abs(r1["kappa"] - r0["kappa"]) <= 1e-10 * abs(r0["kappa"])
+    assert rel(r1["T_L"].cpu().numpy(), r0["T_L"].cpu().numpy()) <= 1e-9
+    assert r1["wrap_residual"] <= 2e-13
