@@ -178,7 +178,7 @@ namespace {
 struct Layout {
     size_t sigma, sigma_f, sT, Tw, T_L, U, X, ksys, kfsys, iters, sweeps, hist, hist_face, ctrl, fx, fscal,
         Tstore, lam_psi, lam_phi, grad, bnd, wres, wres_hist, kry, ax, actl, ag,
-        axp, afp, adX, adF, agram, apart, kraw, total;
+        axp, afp, adX, adF, agram, apart, kraw, qrec, qoff, qsg, qalt, total;
 };
 
 // Linear interpolation weights of x on the sorted values v (clamped to the
@@ -378,6 +378,11 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     const size_t nsol = x_stride(m->nsolid);
     L.Tstore = o->keep_state ? take((size_t)m->n_sys * nsol * 8) : 0;
     L.X = take((size_t)m->n_sys * nsol * tsz);
+    // 2D: the pass inputs in the four sweep orientations' order
+    L.qrec = m->nz == 1 ? take(4 * nc * 4 * tsz) : 0;
+    L.qoff = m->nz == 1 ? take(4 * nc * 4) : 0;
+    L.qsg = m->nz == 1 ? take(4 * nc * tsz) : 0;
+    L.qalt = m->nz == 1 ? take(4 * nc * 2 * tsz) : 0;
     // last: the mixing history (an adjoint may use another depth than the
     // forward solve whose stored state it reads)
     const size_t M = (size_t)std::max(o->accel, 0);
@@ -408,6 +413,29 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
     g.mfp = m->d_mfp; g.dirs = m->d_dirs; g.Dw = m->d_D; g.S = m->d_S; g.wout = m->d_wout;
     g.gauge = m->n_modes > 0 ? 1 : 0;
     g.kappa_axis = m->d_kax;
+    // kappa_face plane cells per sweep quadrant (2D): solid cells that are
+    // last along the gradient axis in that quadrant's sweep order and whose
+    // outflow face there is open
+    if (m->nz == 1 && !m->fc.empty())
+        for (int q = 0; q < 4; ++q) {
+            const int negx = q & 1, negy = q >> 1, ga = m->grad_axis;
+            const int fo = ga == 0 ? 1 - negx : 3 - negy;
+            int cnt = 0;
+            if (ga == 0) {
+                const int ix = negx ? 0 : m->nx - 1;
+                for (int iy = 0; iy < m->ny; ++iy) {
+                    const uint16_t w = m->fc[(size_t)iy * m->nx + ix];
+                    cnt += fc_solid(w) && fc_class(w, fo) != FC_WALL;
+                }
+            } else {
+                const int iy = negy ? 0 : m->ny - 1;
+                for (int ix = 0; ix < m->nx; ++ix) {
+                    const uint16_t w = m->fc[(size_t)iy * m->nx + ix];
+                    cnt += fc_solid(w) && fc_class(w, fo) != FC_WALL;
+                }
+            }
+            g.qnk[q] = cnt;
+        }
     if (ws) {
         g.sigma = (double*)(ws + L.sigma);
         g.sigma_f = (float*)(ws + L.sigma_f);
@@ -436,6 +464,12 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.ax = (double*)(ws + L.ax);
         g.actl = (int*)(ws + L.actl);
         g.kraw = (double*)(ws + L.kraw);
+        if (m->nz == 1) {
+            g.qrec = ws + L.qrec;
+            g.qoff = (uint32_t*)(ws + L.qoff);
+            g.qsg = ws + L.qsg;
+            g.qalt = ws + L.qalt;
+        }
         if (accel > 0) {
             g.ag = (double*)(ws + L.ag);
             g.axp = (double*)(ws + L.axp);
@@ -718,6 +752,8 @@ obte_status upload_run(Run& R, char* ws) {
 
 // The pass kernel over every item, one launch per cells-per-lane class.
 obte_status launch_sweeps(const Run& R, const PassParams& pp, hipStream_t st) {
+    if (R.nzmax == 1)
+        HIPCHK(launch_pack_rows(R.precision, R.d_views, (int)R.views.size(), R.max_cells, pp, st));
     for (int c = 1; c <= 4; ++c)
         if (R.cls_count[c] > 0)
             HIPCHK(launch_sweep_pass(R.precision, c, R.nzmax, R.d_views, R.d_items + R.cls_first[c],

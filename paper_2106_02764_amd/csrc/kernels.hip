@@ -29,6 +29,7 @@
 // a fixed order and a third reduces kappa, so FP64 results are bitwise
 // reproducible (no floating-point atomics).
 #include "obte_internal.h"
+#include <type_traits>
 
 namespace {
 
@@ -716,6 +717,342 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2D sweeps in the quadrant layout.  Every system whose direction falls in
+// quadrant q reads the same per-cell inputs in the same order, so the pack
+// kernel writes them once per pass in that order (GeomDev::qrec, qoff, qsg):
+// a sweep row is then contiguous records behind one scalar row offset, and a
+// row step spends a few multiply-adds per cell (the face classes are
+// decoded, the sources converted and the pores zeroed once per pass, not
+// once per system).  x-upwind position p of a row and x-upwind lane order
+// are the same, so a lane's CPL cells are consecutive records.
+// ---------------------------------------------------------------------------
+struct alignas(16) QRecF {
+    float sb, bx, by;
+    uint32_t meta;
+};
+struct alignas(16) QRecD {
+    double sb, bx, by;
+    uint32_t meta, pad;
+};
+template <typename T>
+using QRec = typename std::conditional<sizeof(T) == 4, QRecF, QRecD>::type;
+static_assert(sizeof(QRecF) == 16 && sizeof(QRecD) == 32, "record = four compute-type words");
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pack_rows(const GeomDev* __restrict__ geoms, PassParams pp) {
+    const GeomDev& g = geoms[blockIdx.y];
+    if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
+    // the buffers the pass's sweeps read (the same rule as the pass kernel)
+    const int pass = g.ctrl[CTRL_PASS];
+    const int buf = (pp.mode == 1) ? ((pass + 1) & 1) : (pass & 1);
+    const int nx = g.nx, ny = g.ny, nc = g.ncells, ga = g.grad_axis;
+    const double* src = (pp.adjoint ? g.lam_psi : g.sT) + (size_t)buf * nc;
+    const double* bnd = g.bnd + ((size_t)(pp.adjoint ? 2 : 0) + buf) * g.nf * nc;
+    const T* sig = sigma_ptr<T>(g);
+    QRec<T>* rec = reinterpret_cast<QRec<T>*>(g.qrec);
+    T* qsg = reinterpret_cast<T*>(g.qsg);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * nc; i += gridDim.x * blockDim.x) {
+        const int q = i / nc, k = i - q * nc;
+        const int r = k / nx, p = k - r * nx;
+        const int negx = q & 1, negy = q >> 1;          // 1: the sweep runs towards - along the axis
+        const int cell = (negy ? ny - 1 - r : r) * nx + (negx ? nx - 1 - p : p);
+        const uint16_t w = g.fc[cell];
+        const bool sol = fc_solid(w);
+        // inflow face per axis (face 2a + side, side 1 = '+'): the '-' face
+        // of a sweep towards +; the same rule gives the adjoint's boundary
+        // face (its sweep runs along -s, its values sit on the faces S leaves by)
+        const int fix = negx, fiy = 2 + negy;
+        const bool ox = sol && fc_class(w, fix) != FC_WALL;
+        const bool oy = sol && fc_class(w, fiy) != FC_WALL;
+        const bool plane = ga == 0 ? p == nx - 1 : r == ny - 1;
+        const int fo = ga == 0 ? 1 - negx : 3 - negy;   // outflow face along the gradient axis
+        const bool kf = sol && plane && fc_class(w, fo) != FC_WALL;
+        QRec<T> e{};
+        e.sb = sol ? (T)src[cell] : T(0);
+        e.bx = sol ? (T)bnd[(size_t)fix * nc + cell] : T(0);
+        e.by = sol ? (T)bnd[(size_t)fiy * nc + cell] : T(0);
+        e.meta = (uint32_t)ox | ((uint32_t)oy << 8) | ((uint32_t)kf << 16) | ((uint32_t)sol << 24);
+        rec[i] = e;
+        g.qoff[i] = sol ? (uint32_t)g.sidx[cell] * (uint32_t)sizeof(T) : QOFF_NONE;
+        qsg[i] = sig[cell];
+        if (pp.adjoint) {
+            T* alt = reinterpret_cast<T*>(g.qalt) + 2 * (size_t)i;
+            alt[0] = sol ? (T)bnd[(size_t)(1 - negx) * nc + cell] : T(0);
+            alt[1] = sol ? (T)bnd[(size_t)(3 - negy) * nc + cell] : T(0);
+        }
+    }
+}
+
+typedef unsigned int u32x3_t __attribute__((ext_vector_type(3)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+// N consecutive dwords at one lane offset, in loads of at most four dwords
+template <int N>
+__device__ __forceinline__ void bld_dw(uint32_t (&d)[N], rsrc_t r, uint32_t vo, uint32_t so) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+        const int n = N - i < 4 ? N - i : 4;
+        const uint32_t o = vo + 4u * (uint32_t)i;
+        if (n == 4) {
+            const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)o, (int)so, 0);
+            d[i] = v.x; d[i + 1] = v.y; d[i + 2] = v.z; d[i + 3] = v.w;
+        } else if (n == 3) {
+            const u32x3_t v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)o, (int)so, 0);
+            d[i] = v.x; d[i + 1] = v.y; d[i + 2] = v.z;
+        } else if (n == 2) {
+            const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)o, (int)so, 0);
+            d[i] = v.x; d[i + 1] = v.y;
+        } else {
+            d[i] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)o, (int)so, 0);
+        }
+    }
+}
+template <typename T>
+__device__ __forceinline__ T from_dw(const uint32_t* d);
+template <>
+__device__ __forceinline__ float from_dw<float>(const uint32_t* d) { return __uint_as_float(d[0]); }
+template <>
+__device__ __forceinline__ double from_dw<double>(const uint32_t* d) {
+    return __longlong_as_double(((long long)d[1] << 32) | (unsigned long long)d[0]);
+}
+// a byte of a record's flag word as a compute-type 0 / 1
+template <typename T, int B>
+__device__ __forceinline__ T flag(uint32_t m) { return (T)(float)((m >> (8 * B)) & 0xffu); }
+
+template <typename T, int CPL>
+struct QViews {
+    rsrc_t rec, off, sg, alt;
+    uint32_t orec[CPL];    // byte offset of this lane's records within a row
+    uint32_t ooff, osg;    // byte offset of this lane's first store offset / sigma within a row
+    int nx, ny;
+};
+
+template <typename T, int CPL>
+struct QRowIn {
+    T sb[CPL], bx[CPL], by[CPL];
+    T bxo[CPL], byo[CPL];      // adjoint: boundary values of the outflow faces
+    uint32_t meta[CPL];
+    uint32_t so[CPL];
+    T sg[CPL];
+};
+
+template <typename T, int CPL>
+struct QRowOut {
+    T x[CPL];
+    uint32_t so[CPL];
+};
+
+template <typename T, int CPL, bool WITH_B, bool ADJ, bool S1, bool ST>
+__device__ __forceinline__ void load_qrow(const QViews<T, CPL>& v, int r, QRowIn<T, CPL>& b) {
+    constexpr uint32_t RB = 4 * sizeof(T);
+    const uint32_t k0 = uni((uint32_t)(r * v.nx));    // first record of sweep row r
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        if (WITH_B) {
+            uint32_t d[RB / 4];
+            bld_dw<RB / 4>(d, v.rec, v.orec[c], k0 * RB);
+            b.sb[c] = from_dw<T>(d);
+            b.bx[c] = from_dw<T>(d + sizeof(T) / 4);
+            b.by[c] = from_dw<T>(d + 2 * sizeof(T) / 4);
+            b.meta[c] = d[3 * sizeof(T) / 4];
+        } else {
+            b.meta[c] = bld32(v.rec, v.orec[c] + 3u * (uint32_t)sizeof(T), k0 * RB);
+        }
+    }
+    if (ST) bld_dw<CPL>(b.so, v.off, v.ooff, k0 * 4u);
+    if (ADJ && WITH_B) {
+        uint32_t d[CPL * 2 * sizeof(T) / 4];
+        bld_dw<CPL * 2 * sizeof(T) / 4>(d, v.alt, v.ooff * 2u * (uint32_t)(sizeof(T) / 4), k0 * 2u * (uint32_t)sizeof(T));
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            b.bxo[c] = from_dw<T>(d + 2 * c * sizeof(T) / 4);
+            b.byo[c] = from_dw<T>(d + (2 * c + 1) * sizeof(T) / 4);
+        }
+    }
+    if (!S1) {
+        uint32_t d[CPL * sizeof(T) / 4];
+        bld_dw<CPL * sizeof(T) / 4>(d, v.sg, v.osg, k0 * (uint32_t)sizeof(T));
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) b.sg[c] = from_dw<T>(d + c * sizeof(T) / 4);
+    }
+}
+
+// One row step of a 2D sweep in the quadrant layout (row jj in y-upwind
+// order).  yp holds the y inflow of each cell of the row: the wrap input on
+// the first row, then c_y x of the row below.  mb: per-system weights of the
+// boundary values of the inflow faces, mo: of the outflow faces (adjoint);
+// sk, sdm: the adjoint's constant source and T_L weight.
+template <typename T, int CPL, bool WITH_B, bool RED, bool ADJ, bool S1, int GA, bool FULL, class IO>
+__device__ __forceinline__ void qrow_step(const SysC<T>& s, const QViews<T, CPL>& vw, int lane, int jj,
+                                          const QRowIn<T, CPL>& cur, T (&yp)[CPL], IO& io, const T (&mb)[2],
+                                          const T (&mo)[2], T sk, T sdm, Red<T>* rd, QRowOut<T, CPL>& ro) {
+    const int nx = vw.nx;
+    const T c0 = s.c[0], c1 = s.c[1], cdiag = s.c[0] + s.c[1];
+    // sigma = 1: the cell coefficients are this system's constants
+    const T rdv1 = S1 ? recip(T(1) + cdiag) : T(0);
+    const T q1 = c0 * rdv1, px1 = (T(1) + c1) * rdv1;
+    T a[CPL], q[CPL];
+    T Al, Pl;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const uint32_t mt = cur.meta[c];
+        const T fx = flag<T, 0>(mt), fy = flag<T, 1>(mt);
+        T rhs;
+        if (WITH_B) {
+            T base = ADJ ? sk + sdm * cur.sb[c] : cur.sb[c];
+            if (ADJ) base += mo[0] * cur.bxo[c] + mo[1] * cur.byo[c];   // + 0 unless S leaves by an outflow face
+            rhs = fy * yp[c] + (base + (mb[0] * cur.bx[c] + mb[1] * cur.by[c]));
+        } else {
+            rhs = fy * yp[c];
+        }
+        T rdv, qx, px;
+        if (S1) {
+            rdv = rdv1; qx = q1; px = px1;
+        } else {
+            rdv = recip(cur.sg[c] + cdiag);
+            qx = c0 * rdv;
+            px = (cur.sg[c] + c1) * rdv;
+        }
+        T av = rhs * rdv;
+        // pores: (A, Q, P) = (0, 0, 1) breaks the chain; their inputs are
+        // zero, so only the adjoint's constant source needs the mask
+        if (ADJ && WITH_B) av = (mt >> 24) ? av : T(0);
+        T qv = fx * qx;                  // x inflow closed (wall, pore): Q = 0, P = 1
+        T pv = fx * px + (T(1) - fx);
+        if (!FULL) {
+            // beyond the row: the identity (0, 1, 0)
+            const bool bey = lane * CPL + c >= nx;
+            av = bey ? T(0) : av;
+            qv = bey ? T(1) : qv;
+            pv = bey ? T(0) : pv;
+        }
+        a[c] = av;
+        q[c] = qv;
+        if (c == 0) {
+            Al = av;
+            Pl = pv;
+        } else {
+            Al = av + qv * Al;
+            Pl = pv + qv * Pl;
+        }
+    }
+    T A = Al, P = Pl;
+    wave_scan(A, P);
+    const T At = readlane(A, WAVE - 1), Pt = readlane(P, WAVE - 1);
+    // cyclic closure x_{-1} = x_{nx-1}; with sigma = 1 every open cell has
+    // P > 0, so P_t > 0
+    const T xin = S1 ? At * recip(Pt) : ((Pt > T(0)) ? At * recip(Pt) : T(0));
+    // this lane's last cell, handed to the next lane (lane 0 takes the closure)
+    const T xe = A + (T(1) - P) * xin;
+    T xp = dpp<0x138, 0xf>(xe, xin);    // wave_shr:1
+    T xrow[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const T xv = a[c] + q[c] * xp;
+        xrow[c] = (FULL || lane * CPL + c < nx) ? xv : T(0);
+        xp = xv;
+    }
+    if (jj == vw.ny - 1) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) io.out(0, c, lane, xrow[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) yp[c] = c1 * xrow[c];
+    if (RED) {
+        // pores hold an exact 0; kappa_face sums x over the plane cells
+        // (the jump terms are added once per system at the end)
+        T rsum = T(0);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            rsum += xrow[c];
+            ro.x[c] = xrow[c];
+            ro.so[c] = (FULL || lane * CPL + c < nx) ? cur.so[c] : QOFF_NONE;
+        }
+        rd->kacc += (double)rsum;
+        if (GA == 0 || (GA == 1 && jj == vw.ny - 1)) {
+            T ks = T(0);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) ks += flag<T, 2>(cur.meta[c]) * xrow[c];
+            rd->kface += (double)ks;
+        }
+    }
+}
+
+template <typename T, int CPL, int NR, bool ADD>
+__device__ __forceinline__ void store_qrows(Red<T>* rd, const QRowOut<T, CPL> (&ro)[NR]) {
+    if (!rd->on) return;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const uint32_t vo = ro[r].so[c];
+            T v = ro[r].x[c];
+            if (ADD) v += bldT<T>(rd->X, vo, 0);
+            bst(v, rd->X, vo);
+            if (rd->store_T) bst((double)ro[r].x[c], rd->Tstore, vo * (uint32_t)(8 / sizeof(T)));
+        }
+}
+
+// The 2D upwind sweep in the quadrant layout (see sweep() for the phases'
+// use of WITH_B / RED / ADD).  Row inputs are prefetched two rows ahead
+// through a three-buffer rotation.
+template <typename T, int CPL, bool WITH_B, bool RED, bool ADD, bool ADJ, bool S1, int GA, bool FULL, class IO>
+__device__ __forceinline__ void qsweep(const GeomDev& g, const SysC<T>& s, int lane, IO& io, Red<T>* rd) {
+    constexpr uint32_t RB = 4 * sizeof(T);
+    const int qd = (s.pos[0] ? 0 : 1) | (s.pos[1] ? 0 : 2);
+    const uint32_t nc = (uint32_t)g.ncells;
+    QViews<T, CPL> vw;
+    vw.rec = make_rsrc(static_cast<const char*>(g.qrec) + (size_t)qd * nc * RB, nc * RB);
+    vw.off = make_rsrc(g.qoff + (size_t)qd * nc, nc * 4u);
+    vw.sg = make_rsrc(static_cast<const T*>(g.qsg) + (size_t)qd * nc, nc * (uint32_t)sizeof(T));
+    vw.alt = make_rsrc(static_cast<const T*>(g.qalt) + 2 * (size_t)qd * nc, nc * 2u * (uint32_t)sizeof(T));
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) vw.orec[c] = (uint32_t)(lane * CPL + c) * RB;
+    vw.ooff = (uint32_t)(lane * CPL) * 4u;
+    vw.osg = (uint32_t)(lane * CPL) * (uint32_t)sizeof(T);
+    vw.nx = uni(g.nx);
+    vw.ny = uni(g.ny);
+    // per-system weights of the boundary values: forward Lambda |s_a| / h_a
+    // on the inflow faces; adjoint the outgoing wall weight of the face S
+    // leaves through (the sweep's inflow face, or with a mode table
+    // possibly its outflow face)
+    T mb[2], mo[2];
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        const int fb = 2 * ax + (s.S[ax] > 0.0 ? 1 : 0);
+        const T wv = ADJ ? (T)g.wout[fb * g.n_sys + s.sys] : (T)s.cd[ax];
+        const bool in = !ADJ || fb == s.fin[ax];
+        mb[ax] = in ? wv : T(0);
+        mo[ax] = in ? T(0) : wv;
+    }
+    const T sk = (T)s.kw, sdm = (T)s.Dml;
+    T yp[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) yp[c] = io.in(0, c, lane);
+    const int ny = vw.ny;
+    auto pre = [&](int r, QRowIn<T, CPL>& b) { load_qrow<T, CPL, WITH_B, ADJ, S1, RED>(vw, min(r, ny - 1), b); };
+    auto step = [&](int r, const QRowIn<T, CPL>& b, QRowOut<T, CPL>& ro) {
+        qrow_step<T, CPL, WITH_B, RED, ADJ, S1, GA, FULL>(s, vw, lane, r, b, yp, io, mb, mo, sk, sdm, rd, ro);
+    };
+    QRowIn<T, CPL> b0, b1, b2;
+    pre(0, b0);
+    pre(1, b1);
+    for (int r = 0; r < ny; r += 3) {
+        QRowOut<T, CPL> ro[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) ro[u].so[c] = QOFF_NONE;
+        pre(r + 2, b2);
+        step(r, b0, ro[0]);
+        pre(r + 3, b0);
+        if (r + 1 < ny) step(r + 1, b1, ro[1]);
+        pre(r + 4, b1);
+        if (r + 2 < ny) step(r + 2, b2, ro[2]);
+        if (RED) store_qrows<T, CPL, 3, ADD>(rd, ro);
+    }
+}
+
 // E' x: inflow of the wrap row from the last row, c_y x_last where the pair
 // across the y-wrap is solid.
 template <typename T, int CPL, int NZ>
@@ -812,10 +1149,6 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     const int active = (w < item.nm) && (m < g.n_mfp);
     constexpr int adj = ADJ;     // the adjoint's branches fold at compile time
     const SysC<T> s = make_sys<T>(g, active ? m : item.m0, item.l, adj);
-    const int pass = g.ctrl[CTRL_PASS];
-    const int buf_in = (pp.mode == 1) ? ((pass + 1) & 1) : (pass & 1);
-    const double* srcbase = adj ? (g.lam_psi + (size_t)buf_in * g.ncells) : (g.sT + (size_t)buf_in * g.ncells);
-    const double* bnd = g.bnd + ((size_t)(adj ? 2 : 0) + buf_in) * g.nf * g.ncells;
     const size_t half = adj ? (size_t)g.n_sys : 0;
     T* Uall = reinterpret_cast<T*>(g.U) + half * g.nwrap;
 
@@ -830,9 +1163,9 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     {
         RegIO<T, CPL> io{u[0], xl[0]};
         if (g.grad_axis == 0)
-            sweep<T, CPL, false, true, true, false, SIG1 != 0, 0, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+            qsweep<T, CPL, true, true, false, ADJ != 0, SIG1 != 0, 0, FULL>(g, s, lane, io, &rd);
         else
-            sweep<T, CPL, false, true, true, false, SIG1 != 0, 1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+            qsweep<T, CPL, true, true, false, ADJ != 0, SIG1 != 0, 1, FULL>(g, s, lane, io, &rd);
     }
     long long n_it = 0, n_sw = 1;
     int need = 0;
@@ -877,7 +1210,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 VLOOP(p[k][c] = r[k][c] + (T)beta * (p[k][c] - (T)omega * v[k][c]));
                 {
                     RegIO<T, CPL> io{p[0], xl[0]};
-                    sweep<T, CPL, false, false, false, false, SIG1 != 0, -1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                    qsweep<T, CPL, false, false, false, ADJ != 0, SIG1 != 0, -1, FULL>(g, s, lane, io, nullptr);
                 }
                 ++n_sw;
                 VLOOP(v[k][c] = p[k][c] - mk[k][c] * xl[k][c]);
@@ -901,7 +1234,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
                 }
                 {
                     RegIO<T, CPL> io{sv[0], xl[0]};
-                    sweep<T, CPL, false, false, false, false, SIG1 != 0, -1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, nullptr);
+                    qsweep<T, CPL, false, false, false, ADJ != 0, SIG1 != 0, -1, FULL>(g, s, lane, io, nullptr);
                 }
                 ++n_sw;
                 VLOOP(t[k][c] = sv[k][c] - mk[k][c] * xl[k][c]);
@@ -931,10 +1264,24 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     if (!pp.lag_wrap && need) {
         RegIO<T, CPL> io{du[0], xl[0]};
         if (g.grad_axis == 0)
-            sweep<T, CPL, false, false, true, true, SIG1 != 0, 0, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+            qsweep<T, CPL, false, true, true, ADJ != 0, SIG1 != 0, 0, FULL>(g, s, lane, io, &rd);
         else
-            sweep<T, CPL, false, false, true, true, SIG1 != 0, 1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, nullptr);
+            qsweep<T, CPL, false, true, true, ADJ != 0, SIG1 != 0, 1, FULL>(g, s, lane, io, &rd);
         ++n_sw;
+    }
+    // kappa_face: the sweeps summed x over the plane cells.  The forward adds
+    // the jump dT once per plane cell when it crosses the plane towards +
+    // (the image there is hotter); the adjoint weighs its jump faces by
+    // Lambda |s_a| / h_a dT, with the sign of the jump (the '+' face's image
+    // is colder)
+    {
+        // (selects, not a run-time index: that would put s in scratch memory)
+        const bool ga0 = g.grad_axis == 0;
+        const int qd = (s.pos[0] ? 0 : 1) | (s.pos[1] ? 0 : 2);
+        const bool pos = ga0 ? s.pos[0] : s.pos[1];
+        const double cd = ga0 ? s.cd[0] : s.cd[1];
+        if (adj) rd.kface *= (pos ? -1.0 : 1.0) * cd * g.dT;
+        else if (lane == 0 && pos) rd.kface += g.dT * (double)g.qnk[qd];
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
 }
@@ -2312,6 +2659,17 @@ hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, c
         case 3: return launch_sweep_t<float, 3>(g, it, n, waves, pp, lds, st, full);
         default: return launch_sweep_t<float, 4>(g, it, n, waves, pp, lds, st, full);
     }
+}
+
+hipError_t launch_pack_rows(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells, PassParams pp,
+                            hipStream_t st) {
+    // four records per cell; at most 512 blocks per geometry (grid-stride)
+    int blocks = (4 * max_cells + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 512 ? 512 : blocks);
+    (void)hipGetLastError();
+    if (precision == 1) hipLaunchKernelGGL(k_pack_rows<float>, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp);
+    else hipLaunchKernelGGL(k_pack_rows<double>, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_solid,

@@ -90,7 +90,23 @@ struct GeomDev {
     // (ax[n_aa] holds the shift between the two gauge kernels)
     int gauge;
     int* actl;                   // 2 x 4 (by pass parity): stored columns, ring head, previous pass valid
+    // ---- 2D sweep inputs of the pass in each sweep orientation's order,
+    // written by the pack kernel before the pass's sweeps.  Quadrant
+    // q = [s_x < 0] + 2 [s_y < 0]; entry q * ncells + r * nx + p is the cell
+    // at row r (y-upwind order) and position p (x-upwind order).
+    void* qrec;                  // 4 * ncells records {sb, bx, by, meta} of 4 compute-type words
+                                 // (meta: byte 0 x inflow open, 1 y inflow open, 2 kappa_face
+                                 // plane cell, 3 solid)
+    uint32_t* qoff;              // 4 * ncells: byte offset of the cell's stored value, QOFF_NONE in pores
+    void* qsg;                   // 4 * ncells: sigma in the compute type
+    void* qalt;                  // adjoint passes: 4 * ncells pairs {bx, by} of the outflow faces
+                                 // (with a mode table S may leave against the sweep direction)
+    int qnk[4];                  // per quadrant: cells flagged as kappa_face plane cells
 };
+
+// Store offset of a pore cell: past any stored array, also when doubled for
+// the FP64 copy of an FP32 solution (raw buffer stores there are dropped).
+constexpr uint32_t QOFF_NONE = 0x7FFFFFF0u;
 
 constexpr int AA_MAX = 8;
 
@@ -130,6 +146,10 @@ hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, int max_
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
                              const Item* items_dev, int n_items, int waves, PassParams pp,
                              size_t lds_bytes, hipStream_t st, int full);
+// 2D: the pass inputs in the quadrant layout (GeomDev::qrec, qoff, qsg) of
+// every geometry, read from the buffers the pass's sweeps consume.
+hipError_t launch_pack_rows(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells, PassParams pp,
+                            hipStream_t st);
 hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_solid,
                               PassParams pp, hipStream_t st);
 // Energy balance of the last pass of one geometry (forward solve):
