@@ -277,6 +277,41 @@ __device__ __forceinline__ void wave_scan(T& A, T& P) {
     scan_step<0x143, 0xc>(A, P);   // row_bcast:31 into rows 2, 3
 }
 
+// FP32: a step is t = 1 - P and two multiply-adds whose multiplicand is the
+// accumulator itself read from the source lane (a DPP operand may name the
+// destination: the source lanes are read before any is written; and the
+// rows a row_bcast step writes never hold its source lane).  A lane with no
+// source reads 0 (bound_ctrl), a row that a row_bcast step does not write
+// keeps its map: both compose the identity.  The compiler does not fold its
+// own DPP moves into v_fmac, so this saves two moves per step and the zero
+// fills of the row_bcast steps.  Hazard: a DPP read needs two wait states
+// after the VALU write of its register; within a step the v_sub and the
+// other accumulator's update provide them, s_nop 1 covers the first step.
+__device__ __forceinline__ void wave_scan(float& A, float& P) {
+    float t;
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_sub_f32 %2, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %2 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %1, %2 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_sub_f32 %2, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %2 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %1, %2 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_sub_f32 %2, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %2 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %1, %2 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_sub_f32 %2, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %2 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %1, %2 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_sub_f32 %2, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %2 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %1, %2 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_sub_f32 %2, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %2 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %1, %2 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(A), "+v"(P), "=&v"(t));
+}
+
 // Loads through these views compile to global (not flat) loads, which keep
 // only the vector-memory counter pending while the row computes.
 template <typename T>
@@ -336,6 +371,7 @@ struct Red {
     int store_T;
     int on;                    // 0: inactive wave (nothing is stored)
     double kacc, kface;
+    T kt, kft;                 // per-lane partials of kacc / kface in the compute type (2D)
     rsrc_t X;                  // this system's solution by solid index
     rsrc_t Tstore;             // this system's stored state (store_T only)
 };
@@ -842,10 +878,12 @@ struct QRowOut {
     uint32_t so[CPL];
 };
 
+// Row inputs at record k0 (the row's first cell; at or past the end of the
+// table, as for the prefetch beyond the last row, the range-checked loads
+// return zeros that no row step uses).
 template <typename T, int CPL, bool WITH_B, bool ADJ, bool S1, bool ST>
-__device__ __forceinline__ void load_qrow(const QViews<T, CPL>& v, int r, QRowIn<T, CPL>& b) {
+__device__ __forceinline__ void load_qrow(const QViews<T, CPL>& v, uint32_t k0, QRowIn<T, CPL>& b) {
     constexpr uint32_t RB = 4 * sizeof(T);
-    const uint32_t k0 = uni((uint32_t)(r * v.nx));    // first record of sweep row r
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         if (WITH_B) {
@@ -959,21 +997,25 @@ __device__ __forceinline__ void qrow_step(const SysC<T>& s, const QViews<T, CPL>
 #pragma unroll
     for (int c = 0; c < CPL; ++c) yp[c] = c1 * xrow[c];
     if (RED) {
-        // pores hold an exact 0; kappa_face sums x over the plane cells
-        // (the jump terms are added once per system at the end)
-        T rsum = T(0);
+        // per-lane partials in the compute type (a lane holds at most
+        // CPL cells of each row; the systems' sums are taken in double).
+        // Pores hold an exact 0; kappa_face sums x over the plane cells (the
+        // jump terms are added once per system at the end): with full rows
+        // along x the plane cell of a row is its last register
+        T rsum = xrow[0];
+#pragma unroll
+        for (int c = 1; c < CPL; ++c) rsum += xrow[c];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            rsum += xrow[c];
             ro.x[c] = xrow[c];
             ro.so[c] = (FULL || lane * CPL + c < nx) ? cur.so[c] : QOFF_NONE;
         }
-        rd->kacc += (double)rsum;
-        if (GA == 0 || (GA == 1 && jj == vw.ny - 1)) {
-            T ks = T(0);
+        rd->kt += rsum;
+        if (GA == 0 && FULL) {
+            rd->kft += flag<T, 2>(cur.meta[CPL - 1]) * xrow[CPL - 1];
+        } else if (GA == 0 || (GA == 1 && jj == vw.ny - 1)) {
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) ks += flag<T, 2>(cur.meta[c]) * xrow[c];
-            rd->kface += (double)ks;
+            for (int c = 0; c < CPL; ++c) rd->kft += flag<T, 2>(cur.meta[c]) * xrow[c];
         }
     }
 }
@@ -981,6 +1023,14 @@ __device__ __forceinline__ void qrow_step(const SysC<T>& s, const QViews<T, CPL>
 template <typename T, int CPL, int NR, bool ADD>
 __device__ __forceinline__ void store_qrows(Red<T>* rd, const QRowOut<T, CPL> (&ro)[NR]) {
     if (!rd->on) return;
+    // one branch on the wave-uniform flag, not one per store
+    if (rd->store_T) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                bst((double)ro[r].x[c], rd->Tstore, ro[r].so[c] * (uint32_t)(8 / sizeof(T)));
+    }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -989,7 +1039,6 @@ __device__ __forceinline__ void store_qrows(Red<T>* rd, const QRowOut<T, CPL> (&
             T v = ro[r].x[c];
             if (ADD) v += bldT<T>(rd->X, vo, 0);
             bst(v, rd->X, vo);
-            if (rd->store_T) bst((double)ro[r].x[c], rd->Tstore, vo * (uint32_t)(8 / sizeof(T)));
         }
 }
 
@@ -1030,7 +1079,14 @@ __device__ __forceinline__ void qsweep(const GeomDev& g, const SysC<T>& s, int l
 #pragma unroll
     for (int c = 0; c < CPL; ++c) yp[c] = io.in(0, c, lane);
     const int ny = vw.ny;
-    auto pre = [&](int r, QRowIn<T, CPL>& b) { load_qrow<T, CPL, WITH_B, ADJ, S1, RED>(vw, min(r, ny - 1), b); };
+    // rows are prefetched in order: the first record of the next one is a
+    // running scalar
+    uint32_t knext = 0;
+    const uint32_t nxu = (uint32_t)vw.nx;
+    auto pre = [&](int, QRowIn<T, CPL>& b) {
+        load_qrow<T, CPL, WITH_B, ADJ, S1, RED>(vw, knext, b);
+        knext += nxu;
+    };
     auto step = [&](int r, const QRowIn<T, CPL>& b, QRowOut<T, CPL>& ro) {
         qrow_step<T, CPL, WITH_B, RED, ADJ, S1, GA, FULL>(s, vw, lane, r, b, yp, io, mb, mo, sk, sdm, rd, ro);
     };
@@ -1094,6 +1150,8 @@ __device__ __forceinline__ Red<T> make_red(const GeomDev& g, const SysC<T>& s, i
     Red<T> rd;
     rd.kacc = 0.0;
     rd.kface = 0.0;
+    rd.kt = T(0);
+    rd.kft = T(0);
     rd.on = active;
     rd.X = make_rsrc(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.xs, (uint32_t)g.nsolid * (uint32_t)sizeof(T));
     rd.Tstore = make_rsrc(g.Tstore ? g.Tstore + (size_t)s.sys * g.xs : nullptr,
@@ -1106,7 +1164,7 @@ template <typename T>
 __device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s, int active, int lane,
                                               int adj, const PassParams& pp, const Red<T>& rd,
                                               long long n_it, long long n_sw) {
-    const double ks = wave_sum(rd.kacc), kf = wave_sum(rd.kface);
+    const double ks = wave_sum(rd.kacc + (double)rd.kt), kf = wave_sum(rd.kface + (double)rd.kft);
     if (active && lane == 0) {
         if (adj) {
             g.ksys[s.sys] = kf;                 // this system's share of p^T lambda
@@ -1280,6 +1338,8 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
         const int qd = (s.pos[0] ? 0 : 1) | (s.pos[1] ? 0 : 2);
         const bool pos = ga0 ? s.pos[0] : s.pos[1];
         const double cd = ga0 ? s.cd[0] : s.cd[1];
+        rd.kface += (double)rd.kft;
+        rd.kft = T(0);
         if (adj) rd.kface *= (pos ? -1.0 : 1.0) * cd * g.dT;
         else if (lane == 0 && pos) rd.kface += g.dT * (double)g.qnk[qd];
     }
