@@ -1020,11 +1020,11 @@ __device__ __forceinline__ void qrow_step(const SysC<T>& s, const QViews<T, CPL>
     }
 }
 
-template <typename T, int CPL, int NR, bool ADD>
+// (an inactive wave's resources have size 0: its stores are dropped).
+// STT: also store the FP64 copy of x (the adjoint's stored forward state).
+template <typename T, int CPL, int NR, bool ADD, bool STT>
 __device__ __forceinline__ void store_qrows(Red<T>* rd, const QRowOut<T, CPL> (&ro)[NR]) {
-    if (!rd->on) return;
-    // one branch on the wave-uniform flag, not one per store
-    if (rd->store_T) {
+    if (STT) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -1045,7 +1045,8 @@ __device__ __forceinline__ void store_qrows(Red<T>* rd, const QRowOut<T, CPL> (&
 // The 2D upwind sweep in the quadrant layout (see sweep() for the phases'
 // use of WITH_B / RED / ADD).  Row inputs are prefetched two rows ahead
 // through a three-buffer rotation.
-template <typename T, int CPL, bool WITH_B, bool RED, bool ADD, bool ADJ, bool S1, int GA, bool FULL, class IO>
+template <typename T, int CPL, bool WITH_B, bool RED, bool ADD, bool ADJ, bool S1, int GA, bool FULL,
+          bool STT = false, class IO>
 __device__ __forceinline__ void qsweep(const GeomDev& g, const SysC<T>& s, int lane, IO& io, Red<T>* rd) {
     constexpr uint32_t RB = 4 * sizeof(T);
     const int qd = (s.pos[0] ? 0 : 1) | (s.pos[1] ? 0 : 2);
@@ -1093,19 +1094,40 @@ __device__ __forceinline__ void qsweep(const GeomDev& g, const SysC<T>& s, int l
     QRowIn<T, CPL> b0, b1, b2;
     pre(0, b0);
     pre(1, b1);
-    for (int r = 0; r < ny; r += 3) {
-        QRowOut<T, CPL> ro[3];
+    if (RED && !ADD) {
+        // each row is stored right after its step, before the prefetch
+        // reloads the buffer holding its store offsets (vector-memory ops
+        // complete in order, so the stores delay no wait for a later row)
+        auto sstep = [&](int r, const QRowIn<T, CPL>& b) {
+            QRowOut<T, CPL> ro[1];
+            step(r, b, ro[0]);
+            store_qrows<T, CPL, 1, false, STT>(rd, ro);
+        };
+        for (int r = 0; r < ny; r += 3) {
+            pre(r + 2, b2);
+            sstep(r, b0);
+            pre(r + 3, b0);
+            if (r + 1 < ny) sstep(r + 1, b1);
+            pre(r + 4, b1);
+            if (r + 2 < ny) sstep(r + 2, b2);
+        }
+    } else {
+        // no stores, or an update of the stored values (three rows of
+        // results are added to the stored ones together)
+        for (int r = 0; r < ny; r += 3) {
+            QRowOut<T, CPL> ro[3];
 #pragma unroll
-        for (int u = 0; u < 3; ++u)
+            for (int u = 0; u < 3; ++u)
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) ro[u].so[c] = QOFF_NONE;
-        pre(r + 2, b2);
-        step(r, b0, ro[0]);
-        pre(r + 3, b0);
-        if (r + 1 < ny) step(r + 1, b1, ro[1]);
-        pre(r + 4, b1);
-        if (r + 2 < ny) step(r + 2, b2, ro[2]);
-        if (RED) store_qrows<T, CPL, 3, ADD>(rd, ro);
+                for (int c = 0; c < CPL; ++c) ro[u].so[c] = QOFF_NONE;
+            pre(r + 2, b2);
+            step(r, b0, ro[0]);
+            pre(r + 3, b0);
+            if (r + 1 < ny) step(r + 1, b1, ro[1]);
+            pre(r + 4, b1);
+            if (r + 2 < ny) step(r + 2, b2, ro[2]);
+            if (RED) store_qrows<T, CPL, 3, ADD, false>(rd, ro);
+        }
     }
 }
 
@@ -1153,9 +1175,11 @@ __device__ __forceinline__ Red<T> make_red(const GeomDev& g, const SysC<T>& s, i
     rd.kt = T(0);
     rd.kft = T(0);
     rd.on = active;
-    rd.X = make_rsrc(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.xs, (uint32_t)g.nsolid * (uint32_t)sizeof(T));
+    // size 0 for an inactive wave: every store through it is dropped
+    rd.X = make_rsrc(reinterpret_cast<T*>(g.X) + (size_t)s.sys * g.xs,
+                     active ? (uint32_t)g.nsolid * (uint32_t)sizeof(T) : 0u);
     rd.Tstore = make_rsrc(g.Tstore ? g.Tstore + (size_t)s.sys * g.xs : nullptr,
-                          g.Tstore ? (uint32_t)g.nsolid * 8u : 0u);
+                          (g.Tstore && active) ? (uint32_t)g.nsolid * 8u : 0u);
     rd.store_T = pp.store_T && g.Tstore != nullptr;
     return rd;
 }
@@ -1220,10 +1244,15 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     // ---- phase A
     {
         RegIO<T, CPL> io{u[0], xl[0]};
-        if (g.grad_axis == 0)
-            qsweep<T, CPL, true, true, false, ADJ != 0, SIG1 != 0, 0, FULL>(g, s, lane, io, &rd);
-        else
-            qsweep<T, CPL, true, true, false, ADJ != 0, SIG1 != 0, 1, FULL>(g, s, lane, io, &rd);
+        // the forward's replay that keeps its state stores an FP64 copy too
+        const bool stt = ADJ == 0 && rd.store_T;
+        if (g.grad_axis == 0) {
+            if (stt) qsweep<T, CPL, true, true, false, ADJ != 0, SIG1 != 0, 0, FULL, ADJ == 0>(g, s, lane, io, &rd);
+            else qsweep<T, CPL, true, true, false, ADJ != 0, SIG1 != 0, 0, FULL>(g, s, lane, io, &rd);
+        } else {
+            if (stt) qsweep<T, CPL, true, true, false, ADJ != 0, SIG1 != 0, 1, FULL, ADJ == 0>(g, s, lane, io, &rd);
+            else qsweep<T, CPL, true, true, false, ADJ != 0, SIG1 != 0, 1, FULL>(g, s, lane, io, &rd);
+        }
     }
     long long n_it = 0, n_sw = 1;
     int need = 0;
