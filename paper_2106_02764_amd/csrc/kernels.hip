@@ -915,26 +915,134 @@ __device__ __forceinline__ void load_qrow(const QViews<T, CPL>& v, uint32_t k0, 
     }
 }
 
-// One row step of a 2D sweep in the quadrant layout (row jj in y-upwind
-// order).  yp holds the y inflow of each cell of the row: the wrap input on
-// the first row, then c_y x of the row below.  mb: per-system weights of the
-// boundary values of the inflow faces, mo: of the outflow faces (adjoint);
-// sk, sdm: the adjoint's constant source and T_L weight.
-template <typename T, int CPL, bool WITH_B, bool RED, bool ADJ, bool S1, int GA, bool FULL, class IO>
-__device__ __forceinline__ void qrow_step(const SysC<T>& s, const QViews<T, CPL>& vw, int lane, int jj,
-                                          const QRowIn<T, CPL>& cur, T (&yp)[CPL], IO& io, const T (&mb)[2],
-                                          const T (&mo)[2], T sk, T sdm, Red<T>* rd, QRowOut<T, CPL>& ro) {
-    const int nx = vw.nx;
+// The part of a row's maps that depends neither on the sources nor on the
+// row below: Q of each cell, 1 / diagonal, the scan weights t_k = 1 - P of
+// the lane's running map before step k, 1 - P of its inclusive map and 1 / P
+// of the whole row.  A sweep computes it one row ahead, so the chain from one
+// row's solution to the next holds only the A half of the scan.
+template <typename T, int CPL>
+struct QPart {
+    T q[CPL];
+    T rdv[CPL];
+    T t[6];
+    T omP;
+    T rPt;
+};
+
+// Q, 1 / diagonal of each cell of a row and P of the lane's segment.
+template <typename T, int CPL, bool S1, bool FULL>
+__device__ __forceinline__ T qpart_cells(const SysC<T>& s, int nx, int lane, const QRowIn<T, CPL>& b,
+                                         QPart<T, CPL>& o) {
     const T c0 = s.c[0], c1 = s.c[1], cdiag = s.c[0] + s.c[1];
     // sigma = 1: the cell coefficients are this system's constants
     const T rdv1 = S1 ? recip(T(1) + cdiag) : T(0);
     const T q1 = c0 * rdv1, px1 = (T(1) + c1) * rdv1;
-    T a[CPL], q[CPL];
-    T Al, Pl;
+    T Pl;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const T fx = flag<T, 0>(b.meta[c]);
+        T rdv, qx, px;
+        if (S1) {
+            rdv = rdv1; qx = q1; px = px1;
+        } else {
+            rdv = recip(b.sg[c] + cdiag);
+            qx = c0 * rdv;
+            px = (b.sg[c] + c1) * rdv;
+        }
+        T qv = fx * qx;                  // x inflow closed (wall, pore): Q = 0, P = 1
+        T pv = fx * px + (T(1) - fx);
+        if (!FULL) {
+            // beyond the row: the identity (Q, P) = (1, 0)
+            const bool bey = lane * CPL + c >= nx;
+            qv = bey ? T(1) : qv;
+            pv = bey ? T(0) : pv;
+        }
+        o.q[c] = qv;
+        o.rdv[c] = rdv;
+        Pl = c == 0 ? pv : pv + qv * Pl;
+    }
+    return Pl;
+}
+
+// 1 - P of the lane's inclusive map and 1 / P of the row (cyclic closure
+// x_{-1} = x_{nx-1}; with sigma = 1 every open cell has P > 0, so P_t > 0).
+template <typename T, int CPL, bool S1>
+__device__ __forceinline__ void qpart_close(T P, QPart<T, CPL>& o) {
+    const T Pt = readlane(P, WAVE - 1);
+    o.rPt = S1 ? recip(Pt) : (Pt > T(0) ? recip(Pt) : T(0));
+    o.omP = T(1) - P;
+}
+
+// The P half of the scan alone (the first row of a sweep), recording t_k.
+template <typename T>
+__device__ __forceinline__ void pscan(T& P, T (&t)[6]) {
+    t[0] = T(1) - P; P = P + t[0] * dpp<0x111, 0xf>(P, T(0));   // row_shr:1
+    t[1] = T(1) - P; P = P + t[1] * dpp<0x112, 0xf>(P, T(0));   // row_shr:2
+    t[2] = T(1) - P; P = P + t[2] * dpp<0x114, 0xf>(P, T(0));   // row_shr:4
+    t[3] = T(1) - P; P = P + t[3] * dpp<0x118, 0xf>(P, T(0));   // row_shr:8
+    t[4] = T(1) - P; P = P + t[4] * dpp<0x142, 0xa>(P, T(0));   // row_bcast:15 into rows 1, 3
+    t[5] = T(1) - P; P = P + t[5] * dpp<0x143, 0xc>(P, T(0));   // row_bcast:31 into rows 2, 3
+}
+
+// This row's A scan with its recorded weights t, and the next row's P scan
+// recording tn (the same steps as wave_scan; the two chains interleave).
+template <typename T>
+__device__ __forceinline__ void scan_pair(T& A, const T (&t)[6], T& P, T (&tn)[6]) {
+    tn[0] = T(1) - P; A = A + t[0] * dpp<0x111, 0xf>(A, T(0)); P = P + tn[0] * dpp<0x111, 0xf>(P, T(0));
+    tn[1] = T(1) - P; A = A + t[1] * dpp<0x112, 0xf>(A, T(0)); P = P + tn[1] * dpp<0x112, 0xf>(P, T(0));
+    tn[2] = T(1) - P; A = A + t[2] * dpp<0x114, 0xf>(A, T(0)); P = P + tn[2] * dpp<0x114, 0xf>(P, T(0));
+    tn[3] = T(1) - P; A = A + t[3] * dpp<0x118, 0xf>(A, T(0)); P = P + tn[3] * dpp<0x118, 0xf>(P, T(0));
+    tn[4] = T(1) - P; A = A + t[4] * dpp<0x142, 0xa>(A, T(0)); P = P + tn[4] * dpp<0x142, 0xa>(P, T(0));
+    tn[5] = T(1) - P; A = A + t[5] * dpp<0x143, 0xc>(A, T(0)); P = P + tn[5] * dpp<0x143, 0xc>(P, T(0));
+}
+// FP32: the same with the DPP read folded into v_fmac (see wave_scan); each
+// accumulator's DPP read comes two instructions after its last write.
+__device__ __forceinline__ void scan_pair(float& A, const float (&t)[6], float& P, float (&tn)[6]) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_sub_f32 %2, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %8 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %1, %2 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_sub_f32 %3, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %9 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %1, %3 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_sub_f32 %4, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %10 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %1, %4 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_sub_f32 %5, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %11 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %1, %5 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_sub_f32 %6, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %12 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %1, %6 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_sub_f32 %7, 1.0, %1\n\t"
+        "v_fmac_f32_dpp %0, %0, %13 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %1, %7 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(A), "+v"(P), "=&v"(tn[0]), "=&v"(tn[1]), "=&v"(tn[2]), "=&v"(tn[3]), "=&v"(tn[4]), "=&v"(tn[5])
+        : "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3]), "v"(t[4]), "v"(t[5]));
+}
+
+// One row step of a 2D sweep in the quadrant layout (row jj in y-upwind
+// order), with the source-free part qp of this row, and computing qn of the
+// next row (inputs nxt).  yp holds the y inflow of each cell of the row: the
+// wrap input on the first row, then c_y x of the row below.  mb: per-system
+// weights of the boundary values of the inflow faces, mo: of the outflow
+// faces (adjoint); sk, sdm: the adjoint's constant source and T_L weight.
+template <typename T, int CPL, bool WITH_B, bool RED, bool ADJ, bool S1, int GA, bool FULL, class IO>
+__device__ __forceinline__ void qrow_step(const SysC<T>& s, const QViews<T, CPL>& vw, int lane, int jj,
+                                          const QRowIn<T, CPL>& cur, const QPart<T, CPL>& qp,
+                                          const QRowIn<T, CPL>& nxt, QPart<T, CPL>& qn, T (&yp)[CPL], IO& io,
+                                          const T (&mb)[2], const T (&mo)[2], T sk, T sdm, Red<T>* rd,
+                                          QRowOut<T, CPL>& ro) {
+    const int nx = vw.nx;
+    const T c1 = s.c[1];
+    T Pn = qpart_cells<T, CPL, S1, FULL>(s, nx, lane, nxt, qn);
+    T a[CPL];
+    T Al;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const uint32_t mt = cur.meta[c];
-        const T fx = flag<T, 0>(mt), fy = flag<T, 1>(mt);
+        const T fy = flag<T, 1>(mt);
         T rhs;
         if (WITH_B) {
             T base = ADJ ? sk + sdm * cur.sb[c] : cur.sb[c];
@@ -943,50 +1051,26 @@ __device__ __forceinline__ void qrow_step(const SysC<T>& s, const QViews<T, CPL>
         } else {
             rhs = fy * yp[c];
         }
-        T rdv, qx, px;
-        if (S1) {
-            rdv = rdv1; qx = q1; px = px1;
-        } else {
-            rdv = recip(cur.sg[c] + cdiag);
-            qx = c0 * rdv;
-            px = (cur.sg[c] + c1) * rdv;
-        }
-        T av = rhs * rdv;
+        T av = rhs * qp.rdv[c];
         // pores: (A, Q, P) = (0, 0, 1) breaks the chain; their inputs are
         // zero, so only the adjoint's constant source needs the mask
         if (ADJ && WITH_B) av = (mt >> 24) ? av : T(0);
-        T qv = fx * qx;                  // x inflow closed (wall, pore): Q = 0, P = 1
-        T pv = fx * px + (T(1) - fx);
-        if (!FULL) {
-            // beyond the row: the identity (0, 1, 0)
-            const bool bey = lane * CPL + c >= nx;
-            av = bey ? T(0) : av;
-            qv = bey ? T(1) : qv;
-            pv = bey ? T(0) : pv;
-        }
+        if (!FULL) av = (lane * CPL + c >= nx) ? T(0) : av;    // beyond the row
         a[c] = av;
-        q[c] = qv;
-        if (c == 0) {
-            Al = av;
-            Pl = pv;
-        } else {
-            Al = av + qv * Al;
-            Pl = pv + qv * Pl;
-        }
+        Al = c == 0 ? av : av + qp.q[c] * Al;
     }
-    T A = Al, P = Pl;
-    wave_scan(A, P);
-    const T At = readlane(A, WAVE - 1), Pt = readlane(P, WAVE - 1);
-    // cyclic closure x_{-1} = x_{nx-1}; with sigma = 1 every open cell has
-    // P > 0, so P_t > 0
-    const T xin = S1 ? At * recip(Pt) : ((Pt > T(0)) ? At * recip(Pt) : T(0));
+    T A = Al;
+    scan_pair(A, qp.t, Pn, qn.t);
+    qpart_close<T, CPL, S1>(Pn, qn);
+    const T At = readlane(A, WAVE - 1);
+    const T xin = At * qp.rPt;
     // this lane's last cell, handed to the next lane (lane 0 takes the closure)
-    const T xe = A + (T(1) - P) * xin;
+    const T xe = A + qp.omP * xin;
     T xp = dpp<0x138, 0xf>(xe, xin);    // wave_shr:1
     T xrow[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
-        const T xv = a[c] + q[c] * xp;
+        const T xv = a[c] + qp.q[c] * xp;
         xrow[c] = (FULL || lane * CPL + c < nx) ? xv : T(0);
         xp = xv;
     }
@@ -1043,8 +1127,7 @@ __device__ __forceinline__ void store_qrows(Red<T>* rd, const QRowOut<T, CPL> (&
 }
 
 // The 2D upwind sweep in the quadrant layout (see sweep() for the phases'
-// use of WITH_B / RED / ADD).  Row inputs are prefetched two rows ahead
-// through a three-buffer rotation.
+// use of WITH_B / RED / ADD).
 template <typename T, int CPL, bool WITH_B, bool RED, bool ADD, bool ADJ, bool S1, int GA, bool FULL,
           bool STT = false, class IO>
 __device__ __forceinline__ void qsweep(const GeomDev& g, const SysC<T>& s, int lane, IO& io, Red<T>* rd) {
@@ -1088,45 +1171,81 @@ __device__ __forceinline__ void qsweep(const GeomDev& g, const SysC<T>& s, int l
         load_qrow<T, CPL, WITH_B, ADJ, S1, RED>(vw, knext, b);
         knext += nxu;
     };
-    auto step = [&](int r, const QRowIn<T, CPL>& b, QRowOut<T, CPL>& ro) {
-        qrow_step<T, CPL, WITH_B, RED, ADJ, S1, GA, FULL>(s, vw, lane, r, b, yp, io, mb, mo, sk, sdm, rd, ro);
+    auto step = [&](int r, const QRowIn<T, CPL>& b, const QPart<T, CPL>& qp, const QRowIn<T, CPL>& bn,
+                    QPart<T, CPL>& qn, QRowOut<T, CPL>& ro) {
+        qrow_step<T, CPL, WITH_B, RED, ADJ, S1, GA, FULL>(s, vw, lane, r, b, qp, bn, qn, yp, io, mb, mo, sk, sdm,
+                                                           rd, ro);
     };
-    QRowIn<T, CPL> b0, b1, b2;
-    pre(0, b0);
-    pre(1, b1);
+    // four row buffers: a row's inputs arrive three rows ahead, the
+    // source-free part of the next row is taken from them two rows after
+    // their loads were issued
+    QRowIn<T, CPL> b0, b1, b2, b3;
+    QPart<T, CPL> p0, p1, p2, p3;
     if (RED && !ADD) {
-        // each row is stored right after its step, before the prefetch
-        // reloads the buffer holding its store offsets (vector-memory ops
-        // complete in order, so the stores delay no wait for a later row)
-        auto sstep = [&](int r, const QRowIn<T, CPL>& b) {
+        // Each row is stored right after its step, before the prefetch
+        // reloads the buffer holding its store offsets.  Vector-memory ops
+        // complete in order, so a wait for a prefetched row need not include
+        // later stores; but at the loop header the compiler keeps, per
+        // register, the most recent position any path gives its load.  So
+        // the loop body has no branch (steps past the last row store
+        // nothing) and the first group of rows is peeled: the loop is only
+        // entered from a copy of its own body, and its waits stay partial.
+        pre(0, b0);
+        pre(1, b1);
+        pre(2, b2);
+        {
+            T P = qpart_cells<T, CPL, S1, FULL>(s, vw.nx, lane, b0, p0);
+            pscan(P, p0.t);
+            qpart_close<T, CPL, S1>(P, p0);
+        }
+        auto sstep = [&](int r, const QRowIn<T, CPL>& b, const QPart<T, CPL>& qp, const QRowIn<T, CPL>& bn,
+                         QPart<T, CPL>& qn) {
             QRowOut<T, CPL> ro[1];
-            step(r, b, ro[0]);
+            step(r, b, qp, bn, qn, ro[0]);
+            // past the last row the inputs read as zeros (x = 0) and the
+            // offsets are replaced (a zero offset would address a cell)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) ro[0].so[c] = r < ny ? ro[0].so[c] : QOFF_NONE;
             store_qrows<T, CPL, 1, false, STT>(rd, ro);
         };
-        for (int r = 0; r < ny; r += 3) {
-            pre(r + 2, b2);
-            sstep(r, b0);
-            pre(r + 3, b0);
-            if (r + 1 < ny) sstep(r + 1, b1);
-            pre(r + 4, b1);
-            if (r + 2 < ny) sstep(r + 2, b2);
-        }
+        auto group = [&](int r) {
+            pre(r + 3, b3);
+            sstep(r, b0, p0, b1, p1);
+            pre(r + 4, b0);
+            sstep(r + 1, b1, p1, b2, p2);
+            pre(r + 5, b1);
+            sstep(r + 2, b2, p2, b3, p3);
+            pre(r + 6, b2);
+            sstep(r + 3, b3, p3, b0, p0);
+        };
+        group(0);
+        for (int r = 4; r < ny; r += 4) group(r);
     } else {
-        // no stores, or an update of the stored values (three rows of
+        pre(0, b0);
+        pre(1, b1);
+        pre(2, b2);
+        {
+            T P = qpart_cells<T, CPL, S1, FULL>(s, vw.nx, lane, b0, p0);
+            pscan(P, p0.t);
+            qpart_close<T, CPL, S1>(P, p0);
+        }
+        // no stores, or an update of the stored values (four rows of
         // results are added to the stored ones together)
-        for (int r = 0; r < ny; r += 3) {
-            QRowOut<T, CPL> ro[3];
+        for (int r = 0; r < ny; r += 4) {
+            QRowOut<T, CPL> ro[4];
 #pragma unroll
-            for (int u = 0; u < 3; ++u)
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) ro[u].so[c] = QOFF_NONE;
-            pre(r + 2, b2);
-            step(r, b0, ro[0]);
-            pre(r + 3, b0);
-            if (r + 1 < ny) step(r + 1, b1, ro[1]);
-            pre(r + 4, b1);
-            if (r + 2 < ny) step(r + 2, b2, ro[2]);
-            if (RED) store_qrows<T, CPL, 3, ADD, false>(rd, ro);
+            pre(r + 3, b3);
+            step(r, b0, p0, b1, p1, ro[0]);
+            pre(r + 4, b0);
+            if (r + 1 < ny) step(r + 1, b1, p1, b2, p2, ro[1]);
+            pre(r + 5, b1);
+            if (r + 2 < ny) step(r + 2, b2, p2, b3, p3, ro[2]);
+            pre(r + 6, b2);
+            if (r + 3 < ny) step(r + 3, b3, p3, b0, p0, ro[3]);
+            if (RED) store_qrows<T, CPL, 4, ADD, false>(rd, ro);
         }
     }
 }
@@ -1214,19 +1333,14 @@ __device__ __forceinline__ void finish_system(const GeomDev& g, const SysC<T>& s
 // changed u sweeps the source P (u - u0) and adds the (linear) response to
 // its stored solution.
 // ---------------------------------------------------------------------------
+// One system's pass (wave w of work item `item`; w is wave-uniform, so every
+// per-system quantity and the buffer resources built from it are scalars).
 template <typename T, int CPL, int ADJ, int SIG1, bool FULL>
-__global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ geoms,
-                                                    const Item* __restrict__ items, int n_items,
-                                                    PassParams pp) {
+__device__ __forceinline__ void pass_system(const GeomDev* __restrict__ geoms, const Item& item, int w,
+                                            int lane, const PassParams& pp) {
     constexpr int NZ = 1;      // 2D: the wrap row is one x-row, held in registers
-    const int it = blockIdx.x;
-    if (it >= n_items) return;
-    const Item item = items[it];
     const GeomDev& g = geoms[item.geom];
     if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
-    // the wave index is wave-uniform: read it into a scalar so that every
-    // per-system quantity (and the buffer resources built from it) is too
-    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = item.m0 + w;
     const int active = (w < item.nm) && (m < g.n_mfp);
     constexpr int adj = ADJ;     // the adjoint's branches fold at compile time
@@ -1373,6 +1487,17 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
         else if (lane == 0 && pos) rd.kface += g.dT * (double)g.qnk[qd];
     }
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
+}
+
+// The 2D pass: one workgroup per work item, one of its systems per wave.
+template <typename T, int CPL, int ADJ, int SIG1, bool FULL>
+__global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ geoms,
+                                                    const Item* __restrict__ items, int n_items,
+                                                    PassParams pp) {
+    const int it = blockIdx.x;
+    if (it >= n_items) return;
+    pass_system<T, CPL, ADJ, SIG1, FULL>(geoms, items[it], __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                                         threadIdx.x & 63, pp);
 }
 
 // ---------------------------------------------------------------------------
