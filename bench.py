@@ -62,8 +62,8 @@ REF = dict(precision=0, outer_tol=1e-10, stop_rule=0, accel=8, inner_tol=1e-12, 
 # operating point, per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over one
 # solve, each scaled by the same counter on a plain 256 MiB copy); valid only
 # for the kernel source it was taken on.
-TRAFFIC = {"kernels_sha256": "cf3504277473796f276563e5fd7cfa0f9df219f822e01098e8a07128109f1df1",
-           "fetch_bytes": 8574137, "write_bytes": 59387184}
+TRAFFIC = {"kernels_sha256": "02ba2c90f9db2b3116968489921025e678bbfd84b60c94ee3acc825e95131dae",
+           "fetch_bytes": 15581298, "write_bytes": 59393175}
 
 
 def parse():

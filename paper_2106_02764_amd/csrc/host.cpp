@@ -751,9 +751,12 @@ obte_status upload_run(Run& R, char* ws) {
 }
 
 // The pass kernel over every item, one launch per cells-per-lane class.
-obte_status launch_sweeps(const Run& R, const PassParams& pp, hipStream_t st) {
+// (start: an event recorded after the 2D input packing, so that it and the
+// end event bracket the pass kernels alone)
+obte_status launch_sweeps(const Run& R, const PassParams& pp, hipStream_t st, hipEvent_t start = nullptr) {
     if (R.nzmax == 1)
         HIPCHK(launch_pack_rows(R.precision, R.d_views, (int)R.views.size(), R.max_cells, pp, st));
+    if (start) HIPCHK(hipEventRecord(start, st));
     for (int c = 1; c <= 4; ++c)
         if (R.cls_count[c] > 0)
             HIPCHK(launch_sweep_pass(R.precision, c, R.nzmax, R.d_views, R.d_items + R.cls_first[c],
@@ -762,8 +765,7 @@ obte_status launch_sweeps(const Run& R, const PassParams& pp, hipStream_t st) {
 }
 
 obte_status enqueue_pass(const Run& R, const PassParams& pp, hipStream_t st, Timer* tm, int k) {
-    if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k], st));
-    obte_status s = launch_sweeps(R, pp, st);
+    obte_status s = launch_sweeps(R, pp, st, (tm && tm->on) ? tm->ev[4 * k] : nullptr);
     if (s != OBTE_OK) return s;
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 1], st));
     if (tm && tm->on) HIPCHK(hipEventRecord(tm->ev[4 * k + 2], st));
