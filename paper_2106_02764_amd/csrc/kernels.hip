@@ -1705,34 +1705,47 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
 // and the next pass's inputs sigma T_L and T_w.  Forward: T_L = sum D x and
 // T_w = sum ReLu(S.n)/sum ReLu(S.n) x at the wall cell.  Adjoint: Psi = sigma
 // sum lambda and Phi_f = sum of c_a lambda over the directions entering
-// through f (the transpose of the wall coupling).  A block owns a strip of 64
-// solid cells (consecutive solid indices) and its RQ waves split the systems
-// in fixed chunks; a wall face reads only its own cell's values, so the walls
-// of the strip's cells are summed from the same loads.  Every sum is combined
-// over the chunks in order.  Pore entries of the outputs are never written:
-// they are set to 0 once per solve (k_prep_sigma) and stay 0.
+// through f (the transpose of the wall coupling).  A block owns a strip of RC
+// solid cells (consecutive solid indices: one 128-byte segment of a system's
+// FP32 values); each of its RQ waves holds the strip twice (lanes 0-31 and
+// 32-63), and the 2 RQ half-waves split the systems in fixed chunks, so twice
+// as many loads are in flight per strip as with one chunk per wave.  A
+// half-wave stages the weights of RC systems at a time in LDS (D, or 1 in
+// the adjoint, and the wall weights), zero beyond its chunk, so every
+// half-wave runs the same trip count, in groups of RG in-range loads.  A wall face reads
+// only its own cell's values, so the walls of the strip's cells are summed
+// from the same loads.  Every sum is combined over the chunks in order.
+// Pore entries of the outputs are never written: they are set to 0 once per
+// solve (k_prep_sigma) and stay 0.
 // ---------------------------------------------------------------------------
-constexpr int RQ = 16;      // waves per reduction block: system chunks of one 64-cell strip
+constexpr int RQ = 16;      // waves per reduction block
+constexpr int RC = 32;      // solid cells per strip
+constexpr int RH = 2 * RQ;  // system chunks per strip: one per half-wave
+constexpr int RG = 16;      // loads in flight per lane: systems per group
+static_assert(RC == 32 && RC % RG == 0 && RG % 4 == 0, "a strip is one half of a wave, read in groups of RG systems");
 
 template <typename T>
 __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restrict__ geoms, PassParams pp) {
-    __shared__ double part[RQ][64];
-    __shared__ double cfl[RQ][6][64];      // per wave: wall weights of 64 systems
+    __shared__ double wt[RH][7][RC];       // per half-wave: row 0 D (or 1), rows 1..6 the wall weights
+    __shared__ double part[RH][RC];
     const GeomDev& g = geoms[blockIdx.y];
     if (g.ctrl[CTRL_DONE] && pp.mode == 0) return;
     const int pass = g.ctrl[CTRL_PASS];
     const int out = (pass + 1) & 1;
     const int adj = pp.adjoint;
     const int nc = g.ncells, nf = g.nf, ns = g.n_sys, nd = g.n_dir, nsol = g.nsolid, xs = g.xs;
-    if ((int)blockIdx.x * 64 >= nsol) return;          // block-uniform
+    if ((int)blockIdx.x * RC >= nsol) return;          // block-uniform
     const gptr_t<T> X = gview(reinterpret_cast<const T*>(g.X));
     const gptr_t<double> D = gview(g.Dw);
     const int q = threadIdx.x >> 6, cl = threadIdx.x & 63;
-    const int j = blockIdx.x * 64 + cl;                 // solid index of this lane
+    const int h = cl >> 5, c = cl & (RC - 1);
+    const int hq = 2 * q + h;                           // this half-wave's chunk
+    const int j = blockIdx.x * RC + c;                  // solid index of this lane
     const bool in = j < nsol;
+    const int js = in ? j : nsol - 1;                   // in-range loads, dropped below
     const int cell = in ? g.scell[j] : -1;
-    const int per = (ns + RQ - 1) / RQ;
-    const int i0 = q * per, i1 = min(ns, i0 + per);
+    const int per = (ns + RH - 1) / RH;                 // the same trip count in every chunk
+    const int i0 = hq * per, i1 = min(ns, i0 + per);
     // wall faces of this lane's cell (bit f), and of the strip: the same in
     // every wave of the block
     int wm = 0;
@@ -1743,66 +1756,17 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
     int wany = wm;
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) wany |= shfl_xor(wany, m);
-    double acc = 0.0;
-    double aw[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    if (!wany) {
-        if (in) {
-            int i = i0;
-            if (adj) {
-                for (; i + 7 < i1; i += 8) {
-                    double xv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * xs + j];
-                    a0 += xv[0];
-                    a1 += xv[1];
-                    a2 += xv[2];
-                    a3 += xv[3];
-                    a0 += xv[4];
-                    a1 += xv[5];
-                    a2 += xv[6];
-                    a3 += xv[7];
-                }
-                for (; i + 3 < i1; i += 4) {
-                    a0 += (double)X[(size_t)i * xs + j];
-                    a1 += (double)X[(size_t)(i + 1) * xs + j];
-                    a2 += (double)X[(size_t)(i + 2) * xs + j];
-                    a3 += (double)X[(size_t)(i + 3) * xs + j];
-                }
-                for (; i < i1; ++i) a0 += (double)X[(size_t)i * xs + j];
-            } else {
-                for (; i + 7 < i1; i += 8) {
-                    double xv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * xs + j];
-                    a0 += D[i] * xv[0];
-                    a1 += D[i + 1] * xv[1];
-                    a2 += D[i + 2] * xv[2];
-                    a3 += D[i + 3] * xv[3];
-                    a0 += D[i + 4] * xv[4];
-                    a1 += D[i + 5] * xv[5];
-                    a2 += D[i + 6] * xv[6];
-                    a3 += D[i + 7] * xv[7];
-                }
-                for (; i + 3 < i1; i += 4) {
-                    a0 += D[i] * (double)X[(size_t)i * xs + j];
-                    a1 += D[i + 1] * (double)X[(size_t)(i + 1) * xs + j];
-                    a2 += D[i + 2] * (double)X[(size_t)(i + 2) * xs + j];
-                    a3 += D[i + 3] * (double)X[(size_t)(i + 3) * xs + j];
-                }
-                for (; i < i1; ++i) a0 += D[i] * (double)X[(size_t)i * xs + j];
-            }
-        }
-    } else {
-        // the same cell sums in the same order, and the wall faces' sums with
-        // the weights of 64 systems at a time staged in the wave's LDS rows
-        const int js = in ? j : nsol - 1;           // in-range loads, dropped below
-        for (int ib = i0; ib < i1; ib += 64) {
-            // lane l: the weights of system ib + l at the strip's wall faces
-            // (forward: ReLu(S.n) / sum; adjoint: c_a of the directions
-            // entering through the face)
-            const bool lv = ib + cl < i1;
-            const int il = lv ? ib + cl : ns - 1;
+    double aw[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < per; r += RC) {
+        // lane c of the half-wave: the weights of system i0 + r + c (forward
+        // walls: ReLu(S.n) / sum; adjoint walls: c_a of the directions
+        // entering through the face)
+        const int is = i0 + r + c;
+        const bool lv = is < i1;
+        const int il = lv ? is : ns - 1;
+        wt[hq][0][c] = lv ? (adj ? 1.0 : D[il]) : 0.0;
+        if (wany) {
             double cf[6];
             if (!adj) {
 #pragma unroll
@@ -1821,83 +1785,45 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
             }
 #pragma unroll
             for (int f = 0; f < 6; ++f)
-                if (f < nf && ((wany >> f) & 1)) cfl[q][f][cl] = lv ? cf[f] : 0.0;
-            // the wave reads back its own rows (LDS ops of a wave complete in order)
-            __builtin_amdgcn_wave_barrier();
-            const int nb = min(64, i1 - ib);
-            int u0 = 0;
-            for (; u0 + 7 < nb; u0 += 8) {
-                const int i = ib + u0;
-                double dv[8], xv[8];
+                if (f < nf && ((wany >> f) & 1)) wt[hq][1 + f][c] = lv ? cf[f] : 0.0;
+        }
+        // the wave reads back its own rows (LDS ops of a wave complete in order)
+        __builtin_amdgcn_wave_barrier();
+        // groups of RG systems: past the chunk's end the weights are 0 and the
+        // loads stay in range
+        const int nb = min(RC, (per - r + RG - 1) & ~(RG - 1));
+        const int ib = i0 + r;
+        for (int u0 = 0; u0 < nb; u0 += RG) {
+            double xv[RG];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) dv[u] = D[i + u];
+            for (int u = 0; u < RG; ++u) xv[u] = (double)X[(size_t)min(ib + u0 + u, ns - 1) * xs + js];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) xv[u] = (double)X[(size_t)(i + u) * xs + js];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    xv[u] = in ? xv[u] : 0.0;
-                    dv[u] = adj ? 1.0 : dv[u];          // 1 * x is x exactly
-                }
-                a0 += dv[0] * xv[0];
-                a1 += dv[1] * xv[1];
-                a2 += dv[2] * xv[2];
-                a3 += dv[3] * xv[3];
-                a0 += dv[4] * xv[4];
-                a1 += dv[5] * xv[5];
-                a2 += dv[6] * xv[6];
-                a3 += dv[7] * xv[7];
-#pragma unroll
-                for (int f = 0; f < 6; ++f) {
-                    if (f >= nf || !((wany >> f) & 1)) continue;
-                    const double* cp = &cfl[q][f][u0];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) aw[f] += cp[u] * xv[u];   // zero weight: + 0
-                }
+            for (int u = 0; u < RG; u += 4) {
+                a0 += wt[hq][0][u0 + u] * xv[u];
+                a1 += wt[hq][0][u0 + u + 1] * xv[u + 1];
+                a2 += wt[hq][0][u0 + u + 2] * xv[u + 2];
+                a3 += wt[hq][0][u0 + u + 3] * xv[u + 3];
             }
-            for (; u0 + 3 < nb; u0 += 4) {
-                const int i = ib + u0;
-                double dv[4], xv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) dv[u] = D[i + u];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) xv[u] = (double)X[(size_t)(i + u) * xs + js];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    xv[u] = in ? xv[u] : 0.0;
-                    dv[u] = adj ? 1.0 : dv[u];          // 1 * x is x exactly
-                }
-                a0 += dv[0] * xv[0];
-                a1 += dv[1] * xv[1];
-                a2 += dv[2] * xv[2];
-                a3 += dv[3] * xv[3];
+            if (wany) {
 #pragma unroll
                 for (int f = 0; f < 6; ++f) {
                     if (f >= nf || !((wany >> f) & 1)) continue;
-                    const double* cp = &cfl[q][f][u0];
+                    const double* cp = &wt[hq][1 + f][u0];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) aw[f] += cp[u] * xv[u];   // zero weight: + 0
-                }
-            }
-            for (; u0 < nb; ++u0) {
-                const int i = ib + u0;
-                const double xr = (double)X[(size_t)i * xs + js];
-                const double x = in ? xr : 0.0;
-                a0 += adj ? x : D[i] * x;
-#pragma unroll
-                for (int f = 0; f < 6; ++f) {
-                    if (f >= nf || !((wany >> f) & 1)) continue;
-                    aw[f] += cfl[q][f][u0] * x;
+                    for (int u = 0; u < RG; ++u) aw[f] += cp[u] * xv[u];   // zero weight: + 0
                 }
             }
         }
+        // this round's weights are read before the next round writes them
+        __builtin_amdgcn_wave_barrier();
     }
-    if (in) acc = (a0 + a1) + (a2 + a3);
-    part[q][cl] = acc;
+    part[hq][c] = in ? (a0 + a1) + (a2 + a3) : 0.0;
     __syncthreads();
-    if (q == 0 && in) {
-        double tot = part[0][cl];
+    const bool head = q == 0 && h == 0;                 // lanes 0..RC-1 of wave 0 write
+    if (head && in) {
+        double tot = part[0][c];
 #pragma unroll
-        for (int u = 1; u < RQ; ++u) tot += part[u][cl];
+        for (int u = 1; u < RH; ++u) tot += part[u][c];
         if (!adj) g.T_L[cell] = tot;
         if (g.aa_m > 0) {
             g.ag[cell] = tot;              // the mixing step writes the next inputs
@@ -1913,12 +1839,12 @@ __global__ void __launch_bounds__(64 * RQ) k_reduce_pass(const GeomDev* __restri
     for (int f = 0; f < 6; ++f) {
         if (f >= nf || !((wany >> f) & 1)) continue;
         __syncthreads();                   // the previous sum's reads are done
-        part[q][cl] = aw[f];
+        part[hq][c] = aw[f];
         __syncthreads();
-        if (q == 0 && ((wm >> f) & 1)) {
-            double a = part[0][cl];
+        if (head && ((wm >> f) & 1)) {
+            double a = part[0][c];
 #pragma unroll
-            for (int u = 1; u < RQ; ++u) a += part[u][cl];
+            for (int u = 1; u < RH; ++u) a += part[u][c];
             const int wi = g.wall_idx[cell * nf + f];
             if (g.aa_m > 0) {
                 g.ag[nc + wi] = a;
@@ -2888,7 +2814,7 @@ hipError_t launch_pack_rows(int precision, const GeomDev* geoms_dev, int n_geoms
 
 hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_solid,
                               PassParams pp, hipStream_t st) {
-    int blocks = (max_solid + 63) / 64;
+    int blocks = (max_solid + RC - 1) / RC;
     if (blocks < 1) blocks = 1;
     (void)hipGetLastError();
     if (precision == 1) hipLaunchKernelGGL(k_reduce_pass<float>, dim3(blocks, n_geoms), dim3(64 * RQ), 0, st, geoms_dev, pp);

@@ -29,6 +29,7 @@ def test_default_opts(L):
     o = L.default_opts()
     assert o.precision == L.OBTE_FP64 and o.max_outer > 0 and o.inner_tol > 0
     assert o.keep_state == 0 and o.stop_rule == 0 and o.timing == 0 and o.accel == 0
+    assert list(o.waves_by_class) == [0, 0, 0, 0] and o.dispatch == 0
 
 
 def _desc_ok(**kw):
@@ -157,7 +158,7 @@ def test_solve_state_errors_on_host(L):
     ("precision", 2), ("outer_tol", -1.0), ("max_outer", 0), ("max_outer", 65536),
     ("inner_tol", 0.0), ("max_inner", -1), ("waves_per_group", 9), ("passes_per_graph", -1),
     ("fourier_tol", 0.0), ("init", 2), ("lag_wrap", 2), ("wrap_tol", -1.0),
-    ("inner_rtol", 1.0), ("stop_rule", 2), ("accel", -1), ("accel", 9)])
+    ("inner_rtol", 1.0), ("stop_rule", 2), ("accel", -1), ("accel", 9), ("dispatch", 2)])
 def test_options_rejected_on_host(L, field, value):
     w = gen.small_2d(8, 6)
     h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
