@@ -2193,10 +2193,11 @@ __global__ void __launch_bounds__(AA_THREADS) k_aa_apply(const GeomDev* __restri
 // ---------------------------------------------------------------------------
 // Fourier first guess: CG on the negated 5/7-point finite-volume Laplacian
 // with adiabatic pores and the periodic jump (Appendix B on the structured
-// grid), spread over up to FB_MAX blocks per geometry.  Two kernels per
-// iteration; each sums the per-block partials of the previous one in a fixed
-// order (no atomics), so every block of a geometry takes the same decisions,
-// and a converged geometry's blocks exit at once.
+// grid), spread over up to FB_MAX blocks per geometry.  One kernel per
+// iteration (the Chronopoulos-Gear arrangement of CG, below); it sums the
+// per-block partials of the previous one in a fixed order (no atomics), so
+// every block of a geometry takes the same decisions, and a converged
+// geometry's blocks exit at once.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double fourier_rhs(const GeomDev& g, uint16_t w, const double (&kf)[3]) {
     double b = 0.0;
@@ -2212,8 +2213,12 @@ __device__ __forceinline__ double fourier_rhs(const GeomDev& g, uint16_t w, cons
 constexpr int FB_MAX = 256, FB_THREADS = 256;
 
 // This geometry's CG storage (in the fx region) and block b's cell range.
+// r, s = A r and q = A p are double buffered by iteration parity; gp / dp hold
+// the per-block partials of (r, r) and (r, s) by parity.  sc: [0] |b|, [1]
+// done, [4] iterations, [6 + q] iterations done before an iteration of
+// parity q, [8 + q] its (r, r) and [10 + q] its alpha.
 struct FView {
-    double *x, *r, *p0, *p1, *ap, *pap, *rr0, *rr1, *sc;   // sc: [0] |b|, [1] done, [4] iterations
+    double *x, *p, *r[2], *s[2], *q[2], *gp[2], *dp[2], *sc;
     int n, B, c0, c1;
 };
 __device__ __forceinline__ FView fourier_view(const GeomDev& g, int b) {
@@ -2223,14 +2228,18 @@ __device__ __forceinline__ FView fourier_view(const GeomDev& g, int b) {
     v.B = min(FB_MAX, (n + FB_THREADS - 1) / FB_THREADS);
     double* f = g.fx;
     v.x = f;
-    v.r = f + n;
-    v.p0 = f + 2 * (size_t)n;
-    v.p1 = f + 3 * (size_t)n;
-    v.ap = f + 4 * (size_t)n;
-    v.pap = f + 5 * (size_t)n;
-    v.rr0 = v.pap + FB_MAX;
-    v.rr1 = v.rr0 + FB_MAX;
-    v.sc = v.rr1 + FB_MAX;
+    v.p = f + n;
+    for (int k = 0; k < 2; ++k) {
+        v.r[k] = f + (size_t)(2 + k) * n;
+        v.s[k] = f + (size_t)(4 + k) * n;
+        v.q[k] = f + (size_t)(6 + k) * n;
+    }
+    double* pt = f + 8 * (size_t)n;
+    v.gp[0] = pt;
+    v.gp[1] = pt + FB_MAX;
+    v.dp[0] = pt + 2 * FB_MAX;
+    v.dp[1] = pt + 3 * FB_MAX;
+    v.sc = pt + 4 * FB_MAX;
     const int chunk = (n + v.B - 1) / v.B;
     v.c0 = min(n, b * chunk);
     v.c1 = min(n, v.c0 + chunk);
@@ -2289,19 +2298,20 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_init(const GeomDev* __re
             r0 = b - y;
         }
         v.x[c] = x0;
-        v.r[c] = r0;
-        v.p0[c] = 0.0;
+        v.r[0][c] = r0;
+        v.p[c] = 0.0;
+        v.q[0][c] = 0.0;
         s += r0 * r0;
         bb += b * b;
     }
     block_sum2(s, bb, red);
     if (threadIdx.x == 0) {
-        v.rr0[blockIdx.x] = s;
-        v.pap[blockIdx.x] = bb;              // |b|^2 partials, read by k_fourier_norm
-        v.rr1[blockIdx.x] = INFINITY;        // first beta = 0
+        v.gp[0][blockIdx.x] = s;
+        v.dp[1][blockIdx.x] = bb;            // |b|^2 partials, read by k_fourier_norm
         if (blockIdx.x == 0) {
             v.sc[1] = 0.0;
             v.sc[4] = 0.0;
+            v.sc[6] = 0.0;
         }
     }
 }
@@ -2312,76 +2322,112 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_norm(const GeomDev* __re
     const GeomDev& g = geoms[blockIdx.x];
     const FView v = fourier_view(g, 0);
     double bb, rr;
-    sum_partials2(v.pap, v.rr0, v.B, red, bb, rr);
+    sum_partials2(v.dp[1], v.gp[0], v.B, red, bb, rr);
     if (threadIdx.x == 0) {
         v.sc[0] = sqrt(bb);
         if (!(bb > 0.0) || !(rr > 0.0)) v.sc[1] = 1.0;
     }
 }
 
-// p <- r + beta p, A p and the partials of p.Ap; the stop test (every block of
-// the geometry computes the same sums).  q: iteration parity.
-__global__ void __launch_bounds__(FB_THREADS) k_fourier_pq(const GeomDev* __restrict__ geoms, int q,
+__device__ __forceinline__ void fourier_k(const GeomDev& g, double& k0, double& k1, double& k2) {
+    k0 = g.kappa_axis[0] / (g.h[0] * g.h[0]);
+    k1 = g.ndim > 1 ? g.kappa_axis[1] / (g.h[1] * g.h[1]) : 0.0;
+    k2 = g.ndim > 2 ? g.kappa_axis[2] / (g.h[2] * g.h[2]) : 0.0;
+}
+
+// s_0 = A r_0 and the partials of (r_0, s_0).
+__global__ void __launch_bounds__(FB_THREADS) k_fourier_s0(const GeomDev* __restrict__ geoms) {
+    __shared__ double red[40];
+    const GeomDev& g = geoms[blockIdx.y];
+    const FView v = fourier_view(g, blockIdx.x);
+    if ((int)blockIdx.x >= v.B) return;
+    double k0, k1, k2;
+    fourier_k(g, k0, k1, k2);
+    const double* r = v.r[0];
+    double d = 0.0;
+    for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
+        const uint16_t w = g.fc[c];
+        double y = 0.0;
+        if (fc_solid(w))
+            for (int f = 0; f < g.nf; ++f) {
+                if (fc_class(w, f) == FC_WALL) continue;
+                y += axis_pick(k0, k1, k2, f >> 1) * (r[c] - r[nbr_cell(g, c, f)]);
+            }
+        v.s[0][c] = y;
+        d += r[c] * y;
+    }
+    d = block_sum(d, red);
+    if (threadIdx.x == 0) v.dp[0][blockIdx.x] = d;
+}
+
+// One CG iteration in the Chronopoulos-Gear arrangement: s = A r and q = A p
+// are carried by recurrence, so both inner products of an iteration, gamma =
+// (r, r) and delta = (r, A r), come from one pass over the cells:
+//   beta_k = gamma_k / gamma_{k-1},  alpha_k = gamma_k / (delta_k - beta_k
+//   gamma_k / alpha_{k-1})  (k = 0: beta = 0, alpha = gamma / delta),
+//   p = r + beta p,  q = s + beta q,  x += alpha p,  r' = r - alpha q,
+//   s' = A r'  and the partials of (r', r'), (r', s').
+// Iteration k (parity qq) reads r_k, s_k, q_{k-1} from buffers qq and writes
+// r_{k+1}, s_{k+1}, q_k into buffers qq ^ 1; A r' at a cell needs r' at its
+// neighbours, which every block forms itself from the unchanged buffers qq.
+// The stop test (every block computes the same sums) is the one of the plain
+// CG: |r_k| <= tol |b|, or max_iter iterations.
+__global__ void __launch_bounds__(FB_THREADS) k_fourier_cg(const GeomDev* __restrict__ geoms, int qq,
                                                          double tol, int max_iter) {
     __shared__ double red[40];
     const GeomDev& g = geoms[blockIdx.y];
     const FView v = fourier_view(g, blockIdx.x);
     if ((int)blockIdx.x >= v.B || v.sc[1] != 0.0) return;
-    double rr_new, rr_old;
-    sum_partials2(q ? v.rr1 : v.rr0, q ? v.rr0 : v.rr1, v.B, red, rr_new, rr_old);
-    const double rn = sqrt(rr_new);
-    if (!(rn > tol * v.sc[0]) || v.sc[4] >= (double)max_iter) {
+    double gam, del;
+    sum_partials2(v.gp[qq], v.dp[qq], v.B, red, gam, del);
+    const int it = (int)v.sc[6 + qq];
+    if (!(sqrt(gam) > tol * v.sc[0]) || it >= max_iter) {
         if (blockIdx.x == 0 && threadIdx.x == 0) v.sc[1] = 1.0;
         return;
     }
-    const double beta = isinf(rr_old) ? 0.0 : rr_new / rr_old;
-    const double* pold = q ? v.p1 : v.p0;
-    double* pnew = q ? v.p0 : v.p1;
-    const double k0 = g.kappa_axis[0] / (g.h[0] * g.h[0]);
-    const double k1 = g.ndim > 1 ? g.kappa_axis[1] / (g.h[1] * g.h[1]) : 0.0;
-    const double k2 = g.ndim > 2 ? g.kappa_axis[2] / (g.h[2] * g.h[2]) : 0.0;
+    double alpha = gam / del, beta = 0.0;
+    if (it > 0) {
+        beta = gam / v.sc[8 + (qq ^ 1)];
+        alpha = gam / (del - beta * gam / v.sc[10 + (qq ^ 1)]);
+    }
+    double k0, k1, k2;
+    fourier_k(g, k0, k1, k2);
     const int nf = g.nf;
-    double pap = 0.0;
+    const double *r = v.r[qq], *s = v.s[qq], *qo = v.q[qq];
+    double *rn = v.r[qq ^ 1], *sn = v.s[qq ^ 1], *qn = v.q[qq ^ 1];
+    double gs = 0.0, ds = 0.0;
     for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
         const uint16_t w = g.fc[c];
-        double pc = 0.0, y = 0.0;
+        double rc = 0.0, sa = 0.0, qc = 0.0;
         if (fc_solid(w)) {
-            pc = v.r[c] + beta * pold[c];
+            const double pc = r[c] + beta * v.p[c];
+            v.p[c] = pc;
+            qc = s[c] + beta * qo[c];
+            v.x[c] += alpha * pc;
+            rc = r[c] - alpha * qc;
             for (int f = 0; f < nf; ++f) {
                 if (fc_class(w, f) == FC_WALL) continue;
                 const int j = nbr_cell(g, c, f);
-                y += axis_pick(k0, k1, k2, f >> 1) * (pc - (v.r[j] + beta * pold[j]));
+                const double rj = r[j] - alpha * (s[j] + beta * qo[j]);
+                sa += axis_pick(k0, k1, k2, f >> 1) * (rc - rj);
             }
         }
-        pnew[c] = pc;
-        v.ap[c] = y;
-        pap += pc * y;
+        rn[c] = rc;
+        sn[c] = sa;
+        qn[c] = qc;
+        gs += rc * rc;
+        ds += rc * sa;
     }
-    pap = block_sum(pap, red);
-    if (threadIdx.x == 0) v.pap[blockIdx.x] = pap;
-}
-
-// x += alpha p, r -= alpha A p and the partials of the new r.r.
-__global__ void __launch_bounds__(FB_THREADS) k_fourier_xr(const GeomDev* __restrict__ geoms, int q) {
-    __shared__ double red[40];
-    const GeomDev& g = geoms[blockIdx.y];
-    const FView v = fourier_view(g, blockIdx.x);
-    if ((int)blockIdx.x >= v.B || v.sc[1] != 0.0) return;
-    double pap, rr;
-    sum_partials2(v.pap, q ? v.rr1 : v.rr0, v.B, red, pap, rr);
-    const double alpha = rr / pap;
-    const double* pnew = q ? v.p0 : v.p1;
-    double s = 0.0;
-    for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
-        v.x[c] += alpha * pnew[c];
-        const double rc = v.r[c] - alpha * v.ap[c];
-        v.r[c] = rc;
-        s += rc * rc;
-    }
-    s = block_sum(s, red);
+    block_sum2(gs, ds, red);
     if (threadIdx.x == 0) {
-        (q ? v.rr0 : v.rr1)[blockIdx.x] = s;
-        if (blockIdx.x == 0) v.sc[4] += 1.0;
+        v.gp[qq ^ 1][blockIdx.x] = gs;
+        v.dp[qq ^ 1][blockIdx.x] = ds;
+        if (blockIdx.x == 0) {
+            v.sc[8 + qq] = gam;
+            v.sc[10 + qq] = alpha;
+            v.sc[6 + (qq ^ 1)] = (double)(it + 1);
+            v.sc[4] = (double)(it + 1);
+        }
     }
 }
 
@@ -2431,9 +2477,9 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_part(const GeomDev* __re
     ns = block_sum(ns, red);
     fl = block_sum(fl, red);
     if (threadIdx.x == 0) {
-        v.p0[blockIdx.x] = sx;
-        v.p1[blockIdx.x] = ns;
-        v.ap[blockIdx.x] = fl;
+        v.s[0][blockIdx.x] = sx;
+        v.s[1][blockIdx.x] = ns;
+        v.q[0][blockIdx.x] = fl;
     }
 }
 
@@ -2444,12 +2490,12 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_fill(const GeomDev* __re
     if ((int)blockIdx.x >= v.B) return;
     const int n = g.ncells, nf = g.nf;
     double sx, sn;
-    sum_partials2(v.p0, v.p1, v.B, red, sx, sn);
+    sum_partials2(v.s[0], v.s[1], v.B, red, sx, sn);
     const double mean = sx / sn;
     if (blockIdx.x == 0) {
         const int it = (int)v.sc[4];
-        const double rn = sqrt(sum_partials((it & 1) ? v.rr1 : v.rr0, v.B, red));
-        const double fl = sum_partials(v.ap, v.B, red);
+        const double rn = sqrt(sum_partials(v.gp[it & 1], v.B, red));
+        const double fl = sum_partials(v.q[0], v.B, red);
         const double bn = v.sc[0];
         const int ga = g.grad_axis;
         if (g.aa_m > 0 && threadIdx.x < 8) g.actl[threadIdx.x] = 0;
@@ -2685,7 +2731,8 @@ __global__ void __launch_bounds__(1024) k_output(const GeomDev* __restrict__ gp,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static_assert(fourier_scratch_doubles(0) == 3 * FB_MAX + 8, "Fourier scratch carve and kernels disagree");
+static_assert(fourier_scratch_doubles(0) == 4 * FB_MAX + 16 && fourier_scratch_doubles(1) == 4 * FB_MAX + 24,
+              "Fourier scratch carve and kernels disagree");
 static_assert(aa_partial_doubles() == (size_t)AAB_MAX * AA_NP, "mixing partials carve and kernels disagree");
 
 int fourier_blocks(int max_cells) {
@@ -2697,6 +2744,7 @@ hipError_t launch_fourier_init(const GeomDev* geoms_dev, int n_geoms, int max_ce
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_fourier_init, dim3(fourier_blocks(max_cells), n_geoms), dim3(FB_THREADS), 0, st, geoms_dev);
     hipLaunchKernelGGL(k_fourier_norm, dim3(n_geoms), dim3(FB_THREADS), 0, st, geoms_dev);
+    hipLaunchKernelGGL(k_fourier_s0, dim3(fourier_blocks(max_cells), n_geoms), dim3(FB_THREADS), 0, st, geoms_dev);
     return hipGetLastError();
 }
 
@@ -2704,8 +2752,7 @@ hipError_t launch_fourier_iter(const GeomDev* geoms_dev, int n_geoms, int max_ce
                                int max_iter, hipStream_t st) {
     (void)hipGetLastError();
     const dim3 grid(fourier_blocks(max_cells), n_geoms);
-    hipLaunchKernelGGL(k_fourier_pq, grid, dim3(FB_THREADS), 0, st, geoms_dev, parity, tol, max_iter);
-    hipLaunchKernelGGL(k_fourier_xr, grid, dim3(FB_THREADS), 0, st, geoms_dev, parity);
+    hipLaunchKernelGGL(k_fourier_cg, grid, dim3(FB_THREADS), 0, st, geoms_dev, parity, tol, max_iter);
     return hipGetLastError();
 }
 

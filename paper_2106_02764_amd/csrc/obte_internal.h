@@ -60,7 +60,7 @@ struct GeomDev {
     double* hist;                // max_outer
     double* hist_face;           // max_outer
     int* ctrl;                   // CTRL_N ints
-    double* fx;                  // Fourier CG vectors: 4 * ncells
+    double* fx;                  // Fourier CG vectors: 8 * ncells, partials and scalars
     double* fscal;               // scalars: [0] kappa_F, [1] CG iterations, [2] CG residual,
                                  // [3] mixing error estimate, [4] energy residual of the last pass,
                                  // [5] smallest sigma over the solid cells
@@ -137,7 +137,7 @@ struct PassParams {
 // the direction / A p kernel and the x, r update, the count of geometries
 // still iterating, and the epilogue (mean-free T_F, pass inputs, kappa_F).
 // fx must hold fourier_scratch_doubles(ncells) doubles.
-constexpr size_t fourier_scratch_doubles(size_t ncells) { return 5 * ncells + 3 * 256 + 8; }
+constexpr size_t fourier_scratch_doubles(size_t ncells) { return 8 * ncells + 4 * 256 + 16; }
 hipError_t launch_fourier_init(const GeomDev* geoms_dev, int n_geoms, int max_cells, hipStream_t st);
 hipError_t launch_fourier_iter(const GeomDev* geoms_dev, int n_geoms, int max_cells, int parity, double tol,
                                int max_iter, hipStream_t st);
