@@ -106,13 +106,24 @@ __device__ void block_sum2(double& a, double& b, double* red) {
     b = red[33];
 }
 
-__device__ __forceinline__ int nbr_cell(const GeomDev& g, int cell, int f) {
-    int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
-    const int a = f >> 1, step = (f & 1) ? 1 : -1;
-    if (a == 0) ix = (ix + step + g.nx) % g.nx;
-    else if (a == 1) iy = (iy + step + g.ny) % g.ny;
-    else iz = (iz + step + g.nz) % g.nz;
-    return ix + g.nx * (iy + g.ny * iz);
+// A cell's grid coordinates (one division chain per cell), and its
+// neighbour across face f (2a: '-' side of axis a, 2a + 1: '+' side) with the
+// periodic wrap taken by comparison, so the per-face lookups divide nothing.
+struct CellPos {
+    int ix, iy, iz;
+};
+__device__ __forceinline__ CellPos cell_pos(const GeomDev& g, int cell) {
+    const int q = cell / g.nx, r = q / g.ny;
+    return {cell - q * g.nx, q - r * g.ny, r};
+}
+__device__ __forceinline__ int nbr_cell(const GeomDev& g, int cell, const CellPos& cp, int f) {
+    const int a = f >> 1;
+    const bool up = f & 1;
+    const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+    const int i = a == 0 ? cp.ix : (a == 1 ? cp.iy : cp.iz);
+    const int st = a == 0 ? 1 : (a == 1 ? g.nx : g.nx * g.ny);
+    if (up) return i == n - 1 ? cell - (n - 1) * st : cell + st;
+    return i == 0 ? cell + (n - 1) * st : cell - st;
 }
 
 using rsrc_t = __amdgpu_buffer_rsrc_t;
@@ -726,12 +737,20 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     // would then wait for all.  A storing sweep stores each group of three
     // rows after the group's last row.
     const int nz = D3 ? g.nz : 1, nrows = ny * nz;
+    // row r -> (r / nz, r % nz) by a multiply with mz = ceil(2^32 / nz), not a
+    // division per row: r mz / 2^32 = r / nz + r e / (nz 2^32) with e = mz nz
+    // - 2^32 < nz, so the floor is exact while r e < 2^32, i.e. for every
+    // r < 2^25 (nz <= 128)
+    const uint64_t mz = D3 ? ((1ull << 32) + (uint64_t)nz - 1) / (uint64_t)nz : 1ull;
+    auto row_j = [&](int r) { return D3 ? (int)(((uint64_t)(uint32_t)r * mz) >> 32) : r; };
     auto pre = [&](int r, RowIn<T, CPL, D3>& b) {
         const int rr = min(r, nrows - 1);
-        load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, D3 ? rr / nz : rr, D3 ? rr % nz : 0, b);
+        const int jr = row_j(rr);
+        load_row<T, CPL, D3, WITH_B, S1, RED>(g, s, vw, lane, jr, D3 ? rr - jr * nz : 0, b);
     };
     auto step = [&](int r, const RowIn<T, CPL, D3>& b, RowOut<T, CPL>& ro) {
-        row_step<T, CPL, D3, WITH_B, RED, ADD, S1, GA, FULL>(g, s, vw, active, lane, adj, D3 ? r / nz : r, D3 ? r % nz : 0,
+        const int jr = row_j(r);
+        row_step<T, CPL, D3, WITH_B, RED, ADD, S1, GA, FULL>(g, s, vw, active, lane, adj, jr, D3 ? r - jr * nz : 0,
                                                        b, rows, io, mb, rd, ro);
     };
     RowIn<T, CPL, D3> b0, b1, b2;
@@ -2217,9 +2236,16 @@ constexpr int FB_MAX = 256, FB_THREADS = 256;
 // the per-block partials of (r, r) and (r, s) by parity.  sc: [0] |b|, [1]
 // done, [4] iterations, [6 + q] iterations done before an iteration of
 // parity q, [8 + q] its (r, r) and [10 + q] its alpha.
+// (the buffers are selected by ternaries, never by a run-time array index,
+// which would put the view in private memory)
 struct FView {
-    double *x, *p, *r[2], *s[2], *q[2], *gp[2], *dp[2], *sc;
+    double *x, *p, *r0, *r1, *s0, *s1, *q0, *q1, *gp0, *gp1, *dp0, *dp1, *sc;
     int n, B, c0, c1;
+    __device__ double* r(int k) const { return k ? r1 : r0; }
+    __device__ double* s(int k) const { return k ? s1 : s0; }
+    __device__ double* q(int k) const { return k ? q1 : q0; }
+    __device__ double* gp(int k) const { return k ? gp1 : gp0; }
+    __device__ double* dp(int k) const { return k ? dp1 : dp0; }
 };
 __device__ __forceinline__ FView fourier_view(const GeomDev& g, int b) {
     FView v;
@@ -2229,16 +2255,17 @@ __device__ __forceinline__ FView fourier_view(const GeomDev& g, int b) {
     double* f = g.fx;
     v.x = f;
     v.p = f + n;
-    for (int k = 0; k < 2; ++k) {
-        v.r[k] = f + (size_t)(2 + k) * n;
-        v.s[k] = f + (size_t)(4 + k) * n;
-        v.q[k] = f + (size_t)(6 + k) * n;
-    }
+    v.r0 = f + 2 * (size_t)n;
+    v.r1 = f + 3 * (size_t)n;
+    v.s0 = f + 4 * (size_t)n;
+    v.s1 = f + 5 * (size_t)n;
+    v.q0 = f + 6 * (size_t)n;
+    v.q1 = f + 7 * (size_t)n;
     double* pt = f + 8 * (size_t)n;
-    v.gp[0] = pt;
-    v.gp[1] = pt + FB_MAX;
-    v.dp[0] = pt + 2 * FB_MAX;
-    v.dp[1] = pt + 3 * FB_MAX;
+    v.gp0 = pt;
+    v.gp1 = pt + FB_MAX;
+    v.dp0 = pt + 2 * FB_MAX;
+    v.dp1 = pt + 3 * FB_MAX;
     v.sc = pt + 4 * FB_MAX;
     const int chunk = (n + v.B - 1) / v.B;
     v.c0 = min(n, b * chunk);
@@ -2288,26 +2315,27 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_init(const GeomDev* __re
     double s = 0.0, bb = 0.0;
     for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
         const uint16_t w = g.fc[c];
+        const CellPos cp = cell_pos(g, c);
         const double b = fourier_rhs(g, w, kf);
         double x0 = 0.0, r0 = 0.0;
         if (fc_solid(w)) {
             x0 = lin(c);
             double y = 0.0;
             for (int f = 0; f < g.nf; ++f)
-                if (fc_class(w, f) != FC_WALL) y += kf[f >> 1] * (x0 - lin(nbr_cell(g, c, f)));
+                if (fc_class(w, f) != FC_WALL) y += kf[f >> 1] * (x0 - lin(nbr_cell(g, c, cp, f)));
             r0 = b - y;
         }
         v.x[c] = x0;
-        v.r[0][c] = r0;
+        v.r(0)[c] = r0;
         v.p[c] = 0.0;
-        v.q[0][c] = 0.0;
+        v.q(0)[c] = 0.0;
         s += r0 * r0;
         bb += b * b;
     }
     block_sum2(s, bb, red);
     if (threadIdx.x == 0) {
-        v.gp[0][blockIdx.x] = s;
-        v.dp[1][blockIdx.x] = bb;            // |b|^2 partials, read by k_fourier_norm
+        v.gp(0)[blockIdx.x] = s;
+        v.dp(1)[blockIdx.x] = bb;            // |b|^2 partials, read by k_fourier_norm
         if (blockIdx.x == 0) {
             v.sc[1] = 0.0;
             v.sc[4] = 0.0;
@@ -2322,7 +2350,7 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_norm(const GeomDev* __re
     const GeomDev& g = geoms[blockIdx.x];
     const FView v = fourier_view(g, 0);
     double bb, rr;
-    sum_partials2(v.dp[1], v.gp[0], v.B, red, bb, rr);
+    sum_partials2(v.dp(1), v.gp(0), v.B, red, bb, rr);
     if (threadIdx.x == 0) {
         v.sc[0] = sqrt(bb);
         if (!(bb > 0.0) || !(rr > 0.0)) v.sc[1] = 1.0;
@@ -2343,21 +2371,22 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_s0(const GeomDev* __rest
     if ((int)blockIdx.x >= v.B) return;
     double k0, k1, k2;
     fourier_k(g, k0, k1, k2);
-    const double* r = v.r[0];
+    const double* r = v.r(0);
     double d = 0.0;
     for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
         const uint16_t w = g.fc[c];
+        const CellPos cp = cell_pos(g, c);
         double y = 0.0;
         if (fc_solid(w))
             for (int f = 0; f < g.nf; ++f) {
                 if (fc_class(w, f) == FC_WALL) continue;
-                y += axis_pick(k0, k1, k2, f >> 1) * (r[c] - r[nbr_cell(g, c, f)]);
+                y += axis_pick(k0, k1, k2, f >> 1) * (r[c] - r[nbr_cell(g, c, cp, f)]);
             }
-        v.s[0][c] = y;
+        v.s(0)[c] = y;
         d += r[c] * y;
     }
     d = block_sum(d, red);
-    if (threadIdx.x == 0) v.dp[0][blockIdx.x] = d;
+    if (threadIdx.x == 0) v.dp(0)[blockIdx.x] = d;
 }
 
 // One CG iteration in the Chronopoulos-Gear arrangement: s = A r and q = A p
@@ -2379,7 +2408,7 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_cg(const GeomDev* __rest
     const FView v = fourier_view(g, blockIdx.x);
     if ((int)blockIdx.x >= v.B || v.sc[1] != 0.0) return;
     double gam, del;
-    sum_partials2(v.gp[qq], v.dp[qq], v.B, red, gam, del);
+    sum_partials2(v.gp(qq), v.dp(qq), v.B, red, gam, del);
     const int it = (int)v.sc[6 + qq];
     if (!(sqrt(gam) > tol * v.sc[0]) || it >= max_iter) {
         if (blockIdx.x == 0 && threadIdx.x == 0) v.sc[1] = 1.0;
@@ -2393,11 +2422,12 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_cg(const GeomDev* __rest
     double k0, k1, k2;
     fourier_k(g, k0, k1, k2);
     const int nf = g.nf;
-    const double *r = v.r[qq], *s = v.s[qq], *qo = v.q[qq];
-    double *rn = v.r[qq ^ 1], *sn = v.s[qq ^ 1], *qn = v.q[qq ^ 1];
+    const double *r = v.r(qq), *s = v.s(qq), *qo = v.q(qq);
+    double *rn = v.r(qq ^ 1), *sn = v.s(qq ^ 1), *qn = v.q(qq ^ 1);
     double gs = 0.0, ds = 0.0;
     for (int c = v.c0 + threadIdx.x; c < v.c1; c += blockDim.x) {
         const uint16_t w = g.fc[c];
+        const CellPos cp = cell_pos(g, c);
         double rc = 0.0, sa = 0.0, qc = 0.0;
         if (fc_solid(w)) {
             const double pc = r[c] + beta * v.p[c];
@@ -2407,7 +2437,7 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_cg(const GeomDev* __rest
             rc = r[c] - alpha * qc;
             for (int f = 0; f < nf; ++f) {
                 if (fc_class(w, f) == FC_WALL) continue;
-                const int j = nbr_cell(g, c, f);
+                const int j = nbr_cell(g, c, cp, f);
                 const double rj = r[j] - alpha * (s[j] + beta * qo[j]);
                 sa += axis_pick(k0, k1, k2, f >> 1) * (rc - rj);
             }
@@ -2420,8 +2450,8 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_cg(const GeomDev* __rest
     }
     block_sum2(gs, ds, red);
     if (threadIdx.x == 0) {
-        v.gp[qq ^ 1][blockIdx.x] = gs;
-        v.dp[qq ^ 1][blockIdx.x] = ds;
+        v.gp(qq ^ 1)[blockIdx.x] = gs;
+        v.dp(qq ^ 1)[blockIdx.x] = ds;
         if (blockIdx.x == 0) {
             v.sc[8 + qq] = gam;
             v.sc[10 + qq] = alpha;
@@ -2469,7 +2499,7 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_part(const GeomDev* __re
         ns += 1.0;
         const int f = 2 * ga;   // '-' face of the cell at index 0
         if (fc_class(w, f) == FC_JUMP_P) {
-            const int j = nbr_cell(g, c, f);
+            const int j = nbr_cell(g, c, cell_pos(g, c), f);
             fl += g.kappa_axis[ga] * (x[j] + g.dT - x[c]) / g.h[ga];
         }
     }
@@ -2477,9 +2507,9 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_part(const GeomDev* __re
     ns = block_sum(ns, red);
     fl = block_sum(fl, red);
     if (threadIdx.x == 0) {
-        v.s[0][blockIdx.x] = sx;
-        v.s[1][blockIdx.x] = ns;
-        v.q[0][blockIdx.x] = fl;
+        v.s(0)[blockIdx.x] = sx;
+        v.s(1)[blockIdx.x] = ns;
+        v.q(0)[blockIdx.x] = fl;
     }
 }
 
@@ -2490,12 +2520,12 @@ __global__ void __launch_bounds__(FB_THREADS) k_fourier_fill(const GeomDev* __re
     if ((int)blockIdx.x >= v.B) return;
     const int n = g.ncells, nf = g.nf;
     double sx, sn;
-    sum_partials2(v.s[0], v.s[1], v.B, red, sx, sn);
+    sum_partials2(v.s(0), v.s(1), v.B, red, sx, sn);
     const double mean = sx / sn;
     if (blockIdx.x == 0) {
         const int it = (int)v.sc[4];
-        const double rn = sqrt(sum_partials(v.gp[it & 1], v.B, red));
-        const double fl = sum_partials(v.q[0], v.B, red);
+        const double rn = sqrt(sum_partials(v.gp(it & 1), v.B, red));
+        const double fl = sum_partials(v.q(0), v.B, red);
         const double bn = v.sc[0];
         const int ga = g.grad_axis;
         if (g.aa_m > 0 && threadIdx.x < 8) g.actl[threadIdx.x] = 0;
