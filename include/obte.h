@@ -176,8 +176,12 @@ typedef struct {
      * are bitwise the same).  waves_by_class[c - 1]: systems per workgroup of
      * the launch over meshes with c = ceil(n[0] / 64) cells per lane (0..8,
      * 0 = waves_per_group).  dispatch: 0 = each geometry's work items longest
-     * MFPs first (geometry by geometry); 1 = the longest-MFP items of every
-     * geometry of a launch first. */
+     * MFPs first (geometry by geometry), one launch per class; 1 = the
+     * longest-MFP items of every geometry of a launch first; 2 (2D meshes;
+     * 3D takes 1) = one persistent launch over the items of every class,
+     * longest MFPs first over all geometries: each workgroup takes the next
+     * item from a device-side queue until none is left (the workgroups have
+     * as many waves as the widest class asks for). */
     int waves_by_class[4];
     int dispatch;
 } obte_solve_opts;

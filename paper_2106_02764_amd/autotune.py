@@ -1,8 +1,10 @@
 """Launch-shape autotuner of the pass kernel.
 
 The knobs are the systems per workgroup of each cells-per-lane launch class
-(``waves_by_class``) and the order the work items are dispatched in
-(``dispatch``).  Neither changes a result (FP64 runs are bitwise the same),
+(``waves_by_class``) and how the work items are dispatched (``dispatch``:
+one launch per class geometry by geometry, longest MFPs first over all
+geometries, or one persistent launch whose workgroups take the items from a
+device-side queue).  Neither changes a result (FP64 runs are bitwise the same),
 only the time of a pass.  ``tune`` times a few passes per candidate with the
 library's own HIP-event timers (coordinate descent: one class at a time,
 then the dispatch order) and caches the winner per (device, mesh shapes,
@@ -109,10 +111,11 @@ def tune(solvers, opts, candidates=(1, 2, 4, 8), passes=4, use_cache=True, cache
                 best, wc = ms, trial
     disp = 0
     if len(solvers) > 1:
-        ms = measure(solvers, _copy(opts, waves_by_class=wc, dispatch=1), passes)
-        timings["dispatch1"] = ms
-        if ms < best:
-            best, disp = ms, 1
+        for d in (1, 2):
+            ms = measure(solvers, _copy(opts, waves_by_class=wc, dispatch=d), passes)
+            timings[f"dispatch{d}"] = ms
+            if ms < best:
+                best, disp = ms, d
     choice = {"waves_by_class": wc, "dispatch": disp, "ms_per_pass_launch": best, "timings": timings,
               "from_cache": False}
     if use_cache:

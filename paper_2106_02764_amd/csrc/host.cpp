@@ -530,7 +530,7 @@ obte_status check_opts(const obte_solve_opts* o) {
     for (int c = 0; c < 4; ++c)
         if (o->waves_by_class[c] < 0 || o->waves_by_class[c] > 8)
             return fail(OBTE_ERR_ARG, "waves_by_class[%d] must be in 0..8", c);
-    if (o->dispatch != 0 && o->dispatch != 1) return fail(OBTE_ERR_ARG, "dispatch must be 0 or 1");
+    if (o->dispatch < 0 || o->dispatch > 2) return fail(OBTE_ERR_ARG, "dispatch must be 0, 1 or 2");
     return OBTE_OK;
 }
 
@@ -597,6 +597,10 @@ struct Run {
     int cls_waves[5] = {4, 4, 4, 4, 4};   // systems per workgroup of each launch class
     int cls_full[5] = {1, 1, 1, 1, 1};    // class whose every row is exactly 64 * class cells
     int nzmax = 1, precision = 0, accel = 0;
+    // 2D with dispatch = 2: every item in one persistent launch of queue_waves
+    // waves per group, the groups taking items from the device counter d_queue
+    int queue = 0, queue_waves = 1;
+    int* d_queue = nullptr;
     int gauge = 0;                // some geometry has a mode table (re-centred passes)
     int max_cells = 0, max_walls = 0, max_solid = 0;
     // pinned host slots for the loop read-backs (two per loop, see
@@ -721,6 +725,22 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         if ((meshes[gi]->nz > 1) != (R.nzmax > 1))
             return fail(OBTE_ERR_ARG, "a batch cannot mix 2D and 3D meshes");
     const size_t tsz = o->precision == OBTE_FP32 ? 4 : 8;
+    R.queue = o->dispatch == 2 && R.nzmax == 1;
+    if (R.queue) {
+        // one list over every class, longest-MFP groups of every geometry
+        // first; a group has as many waves as the widest class needs
+        std::vector<Item> all;
+        for (int c = 1; c <= 4; ++c) {
+            all.insert(all.end(), by_cls[c].begin(), by_cls[c].end());
+            if (!by_cls[c].empty()) R.queue_waves = std::max(R.queue_waves, Wc[c]);
+            by_cls[c].clear();
+        }
+        std::stable_sort(all.begin(), all.end(), [](const Item& a, const Item& b) { return a.m0 > b.m0; });
+        by_cls[0] = std::move(all);
+        R.cls_first[0] = 0;
+        R.cls_count[0] = (int)by_cls[0].size();
+        R.items = by_cls[0];
+    }
     for (int c = 1; c <= 4; ++c) {
         // dispatch = 1: the longest-MFP groups of every geometry first (the
         // order is stable, so geometries and directions keep theirs)
@@ -745,6 +765,7 @@ obte_status upload_run(Run& R, char* ws) {
     R.d_items = (Item*)p;
     p += align256(R.items.size() * sizeof(Item));
     R.d_pending = (int*)p;
+    R.d_queue = R.d_pending + 16;       // within the state's last 256 bytes
     HIPCHK(hipMemcpy(R.d_views, R.views.data(), R.views.size() * sizeof(GeomDev), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(R.d_items, R.items.data(), R.items.size() * sizeof(Item), hipMemcpyHostToDevice));
     return OBTE_OK;
@@ -755,8 +776,14 @@ obte_status upload_run(Run& R, char* ws) {
 // end event bracket the pass kernels alone)
 obte_status launch_sweeps(const Run& R, const PassParams& pp, hipStream_t st, hipEvent_t start = nullptr) {
     if (R.nzmax == 1)
-        HIPCHK(launch_pack_rows(R.precision, R.d_views, (int)R.views.size(), R.max_cells, pp, st));
+        HIPCHK(launch_pack_rows(R.precision, R.d_views, (int)R.views.size(), R.max_cells, pp, st,
+                                R.queue ? R.d_queue : nullptr));
     if (start) HIPCHK(hipEventRecord(start, st));
+    if (R.queue) {
+        HIPCHK(launch_sweep_queue(R.precision, R.d_views, R.d_items, R.cls_count[0], R.queue_waves, pp, st,
+                                  R.d_queue));
+        return OBTE_OK;
+    }
     for (int c = 1; c <= 4; ++c)
         if (R.cls_count[c] > 0)
             HIPCHK(launch_sweep_pass(R.precision, c, R.nzmax, R.d_views, R.d_items + R.cls_first[c],
@@ -861,7 +888,7 @@ obte_status outer_loop(const Run& R, const PassParams& pp, int K, hipStream_t st
     if (K > 1) {
         const auto key = graph_key(R.d_views, R.d_items, (int)R.views.size(), R.cls_first, R.cls_count, R.cls_lds,
                                    R.cls_waves, R.precision, R.nzmax, R.max_cells, R.max_walls, R.gauge, R.accel,
-                                   pp, K, tm && tm->on);
+                                   R.queue, R.queue_waves, pp, K, tm && tm->on);
         obte_status s = slot_graph(slot, key, st, [&]() -> obte_status {
             obte_status sk = OBTE_OK;
             for (int k = 0; k < K && sk == OBTE_OK; ++k) sk = enqueue_pass(R, pp, st, tm, k);

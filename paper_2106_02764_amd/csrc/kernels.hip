@@ -795,7 +795,10 @@ using QRec = typename std::conditional<sizeof(T) == 4, QRecF, QRecD>::type;
 static_assert(sizeof(QRecF) == 16 && sizeof(QRecD) == 32, "record = four compute-type words");
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_pack_rows(const GeomDev* __restrict__ geoms, PassParams pp) {
+__global__ void __launch_bounds__(256) k_pack_rows(const GeomDev* __restrict__ geoms, PassParams pp,
+                                                   int* __restrict__ queue) {
+    // the pass's item queue (persistent launches) starts at the first item
+    if (queue && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *queue = 0;
     const GeomDev& g = geoms[blockIdx.y];
     if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
     // the buffers the pass's sweeps read (the same rule as the pass kernel)
@@ -1517,6 +1520,35 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
     if (it >= n_items) return;
     pass_system<T, CPL, ADJ, SIG1, FULL>(geoms, items[it], __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
                                          threadIdx.x & 63, pp);
+}
+
+// The 2D pass over every work item of a batch in one persistent launch: a
+// workgroup takes the next item from a device-side queue (an atomic counter,
+// set to 0 by the pack kernel before every pass) until none is left and runs
+// it with its geometry's cells-per-lane body, so the items of every launch
+// class share one grid (ordered longest MFPs first over all geometries).
+// The waves of a group never wait for each other inside an item; the two
+// barriers only order the group's read of the slot against its next write.
+template <typename T, int ADJ, int SIG1>
+__global__ void __launch_bounds__(512) k_sweep_queue(const GeomDev* __restrict__ geoms,
+                                                     const Item* __restrict__ items, int n_items,
+                                                     PassParams pp, int* __restrict__ queue) {
+    __shared__ int slot;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) slot = atomicAdd(queue, 1);
+        __syncthreads();
+        const int it = slot;
+        if (it >= n_items) return;                     // every wave of the group leaves together
+        const Item item = items[it];
+        switch ((geoms[item.geom].nx + WAVE - 1) / WAVE) {
+            case 1: pass_system<T, 1, ADJ, SIG1, false>(geoms, item, w, lane, pp); break;
+            case 2: pass_system<T, 2, ADJ, SIG1, false>(geoms, item, w, lane, pp); break;
+            case 3: pass_system<T, 3, ADJ, SIG1, false>(geoms, item, w, lane, pp); break;
+            default: pass_system<T, 4, ADJ, SIG1, false>(geoms, item, w, lane, pp); break;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2878,14 +2910,39 @@ hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, c
     }
 }
 
+template <typename T>
+static hipError_t launch_queue_t(const GeomDev* g, const Item* it, int n, int waves, PassParams pp, hipStream_t st,
+                                 int* queue, int groups) {
+    (void)hipGetLastError();
+    const dim3 grid(groups), block(64 * waves);
+    if (pp.adjoint) {
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_queue<T, 1, 1>), grid, block, 0, st, g, it, n, pp, queue);
+        else hipLaunchKernelGGL((k_sweep_queue<T, 1, 0>), grid, block, 0, st, g, it, n, pp, queue);
+    } else {
+        if (pp.sigma1) hipLaunchKernelGGL((k_sweep_queue<T, 0, 1>), grid, block, 0, st, g, it, n, pp, queue);
+        else hipLaunchKernelGGL((k_sweep_queue<T, 0, 0>), grid, block, 0, st, g, it, n, pp, queue);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_queue(int precision, const GeomDev* g, const Item* it, int n, int waves, PassParams pp,
+                              hipStream_t st, int* queue) {
+    // enough groups to fill every SIMD; a group that starts once the queue is
+    // empty leaves at once
+    const int cap = 8192 / (waves > 1 ? waves : 1);
+    const int groups = n < cap ? (n > 1 ? n : 1) : cap;
+    return precision == 1 ? launch_queue_t<float>(g, it, n, waves, pp, st, queue, groups)
+                          : launch_queue_t<double>(g, it, n, waves, pp, st, queue, groups);
+}
+
 hipError_t launch_pack_rows(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells, PassParams pp,
-                            hipStream_t st) {
+                            hipStream_t st, int* queue) {
     // four records per cell; at most 512 blocks per geometry (grid-stride)
     int blocks = (4 * max_cells + 255) / 256;
     blocks = blocks < 1 ? 1 : (blocks > 512 ? 512 : blocks);
     (void)hipGetLastError();
-    if (precision == 1) hipLaunchKernelGGL(k_pack_rows<float>, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp);
-    else hipLaunchKernelGGL(k_pack_rows<double>, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp);
+    if (precision == 1) hipLaunchKernelGGL(k_pack_rows<float>, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp, queue);
+    else hipLaunchKernelGGL(k_pack_rows<double>, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp, queue);
     return hipGetLastError();
 }
 

@@ -146,10 +146,15 @@ hipError_t launch_fourier_finish(const GeomDev* geoms_dev, int n_geoms, int max_
 hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* geoms_dev,
                              const Item* items_dev, int n_items, int waves, PassParams pp,
                              size_t lds_bytes, hipStream_t st, int full);
+// 2D: every item of a batch in one persistent launch; the groups take items
+// from the device counter *queue, which launch_pack_rows sets to 0.
+hipError_t launch_sweep_queue(int precision, const GeomDev* geoms_dev, const Item* items_dev, int n_items,
+                              int waves, PassParams pp, hipStream_t st, int* queue);
 // 2D: the pass inputs in the quadrant layout (GeomDev::qrec, qoff, qsg) of
-// every geometry, read from the buffers the pass's sweeps consume.
+// every geometry, read from the buffers the pass's sweeps consume; a non-null
+// queue (the persistent launch's item counter) is set to 0.
 hipError_t launch_pack_rows(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells, PassParams pp,
-                            hipStream_t st);
+                            hipStream_t st, int* queue);
 hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_solid,
                               PassParams pp, hipStream_t st);
 // Energy balance of the last pass of one geometry (forward solve):

@@ -1,5 +1,5 @@
 """GPU: the launch-shape autotuner (systems per workgroup per launch class,
-dispatch order) on a batch that spans three launch classes: the choice is
+dispatch order, one persistent launch with a device-side item queue) on a batch that spans three launch classes: the choice is
 cached and reused, and it leaves FP64 results bitwise unchanged."""
 import numpy as np
 import pytest
@@ -32,7 +32,7 @@ def test_tuned_shape_cached_and_bitwise_neutral(P, tmp_path, monkeypatch):
     monkeypatch.setattr(P.autotune, "measure", lambda *a, **k: calls.append(1) or real(*a, **k))
     choice = P.autotune.tune(solvers, o, cache_path=cache)
     assert len(calls) >= 1 + 3 * 4          # baseline, 3 classes x 4 candidates (+ dispatch)
-    assert len(choice["waves_by_class"]) == 4 and choice["dispatch"] in (0, 1)
+    assert len(choice["waves_by_class"]) == 4 and choice["dispatch"] in (0, 1, 2)
     assert all(0 <= w <= 8 for w in choice["waves_by_class"])
     n = len(calls)
     again = P.autotune.tune(solvers, o, cache_path=cache)
@@ -50,3 +50,40 @@ def test_tuned_shape_cached_and_bitwise_neutral(P, tmp_path, monkeypatch):
                           {"waves_by_class": [1, 2, 8, 0], "dispatch": 1})
     k2, _ = P.solve_batch(solvers, ox)
     assert k2 == k0
+    # one persistent launch over the three classes (device-side item queue),
+    # with equal and with mixed systems per workgroup
+    for wc in ([1, 1, 1, 0], [2, 1, 4, 0]):
+        oq = P.autotune.apply(P.default_opts(**{f: getattr(o, f) for f, _ in o._fields_}),
+                              {"waves_by_class": wc, "dispatch": 2})
+        kq, stq = P.solve_batch(solvers, oq)
+        assert [x["status"] for x in stq] == [0, 0, 0]
+        assert kq == k0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_queue_launch_four_classes(P, precision):
+    """dispatch = 2 runs the items of all four cells-per-lane classes in one
+    persistent launch (workgroups taking items from a device-side queue):
+    the same kappa, kappa_face and pass count as one launch per class, and
+    the adjoint of a queued forward solve equals the per-class one."""
+    ws = [gen.small_2d(n, 12, solid=gen.square_block_mask(n, 12, 3, 8), n_dir=8, n_mfp=5,
+                       L=n * 1e-9, Ly=12e-9) for n in (40, 100, 150, 220)]
+    solvers = [P.Solver.from_workload(w) for w in ws]
+    base = dict(precision=precision, outer_tol=1e-9, inner_tol=1e-12 if precision == 0 else 1e-6,
+                fourier_tol=1e-12, max_outer=3000, accel=4)
+    res = {}
+    for d in (0, 2):
+        k, st = P.solve_batch(solvers, P.default_opts(**base, dispatch=d))
+        assert [x["status"] for x in st] == [0, 0, 0, 0]
+        res[d] = (k, [x["kappa_face"] for x in st], [x["outer_iters"] for x in st])
+    assert res[2] == res[0]                       # bitwise: the order of items changes no sum
+    if precision == 0:
+        s = P.Solver.from_workload(ws[3])
+        grads = []
+        for d in (0, 2):
+            o = s.opts(**base, keep_state=1, dispatch=d)
+            out = s.solve(o, want_T_L=False)
+            assert out["status"] == 0
+            g, _ = s.adjoint(o)
+            grads.append(g.cpu().numpy())
+        assert np.array_equal(grads[0], grads[1])

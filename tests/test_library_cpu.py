@@ -158,7 +158,7 @@ def test_solve_state_errors_on_host(L):
     ("precision", 2), ("outer_tol", -1.0), ("max_outer", 0), ("max_outer", 65536),
     ("inner_tol", 0.0), ("max_inner", -1), ("waves_per_group", 9), ("passes_per_graph", -1),
     ("fourier_tol", 0.0), ("init", 2), ("lag_wrap", 2), ("wrap_tol", -1.0),
-    ("inner_rtol", 1.0), ("stop_rule", 2), ("accel", -1), ("accel", 9), ("dispatch", 2)])
+    ("inner_rtol", 1.0), ("stop_rule", 2), ("accel", -1), ("accel", 9), ("dispatch", -1), ("dispatch", 3)])
 def test_options_rejected_on_host(L, field, value):
     w = gen.small_2d(8, 6)
     h = L.obte_mesh_create(w.ndim, w.n, w.L, w.solid, w.periodic, w.grad_axis, w.dT)
