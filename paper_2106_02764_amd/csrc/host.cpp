@@ -379,7 +379,7 @@ Layout make_layout(const obte_mesh* m, const obte_solve_opts* o, int waves) {
     L.Tstore = o->keep_state ? take((size_t)m->n_sys * nsol * 8) : 0;
     L.X = take((size_t)m->n_sys * nsol * tsz);
     // 2D: the pass inputs in the four sweep orientations' order
-    L.qrec = m->nz == 1 ? take(4 * nc * 4 * tsz) : 0;
+    L.qrec = m->nz == 1 ? take(4 * nc * 4 * tsz) : take((1 + (size_t)m->nf) * nc * tsz);
     L.qoff = m->nz == 1 ? take(4 * nc * 4) : 0;
     L.qsg = m->nz == 1 ? take(4 * nc * tsz) : 0;
     L.qalt = m->nz == 1 ? take(4 * nc * 2 * tsz) : 0;
@@ -464,8 +464,8 @@ GeomDev make_view(const obte_mesh* m, char* ws, const Layout& L, int waves, int 
         g.ax = (double*)(ws + L.ax);
         g.actl = (int*)(ws + L.actl);
         g.kraw = (double*)(ws + L.kraw);
+        g.qrec = ws + L.qrec;
         if (m->nz == 1) {
-            g.qrec = ws + L.qrec;
             g.qoff = (uint32_t*)(ws + L.qoff);
             g.qsg = ws + L.qsg;
             g.qalt = ws + L.qalt;
@@ -778,6 +778,8 @@ obte_status launch_sweeps(const Run& R, const PassParams& pp, hipStream_t st, hi
     if (R.nzmax == 1)
         HIPCHK(launch_pack_rows(R.precision, R.d_views, (int)R.views.size(), R.max_cells, pp, st,
                                 R.queue ? R.d_queue : nullptr));
+    else
+        HIPCHK(launch_pack3(R.precision, R.d_views, (int)R.views.size(), R.max_cells, pp, st));
     if (start) HIPCHK(hipEventRecord(start, st));
     if (R.queue) {
         HIPCHK(launch_sweep_queue(R.precision, R.d_views, R.d_items, R.cls_count[0], R.queue_waves, pp, st,

@@ -401,9 +401,9 @@ template <typename T, int CPL, bool D3>
 struct RowIn {
     uint32_t w[CPL];
     T sg[CPL];
-    double sb[CPL];     // base source (sigma T_L, or k + D Psi)
-    double bx[CPL], by[CPL];            // inflow boundary values per axis
-    double bz[D3 ? CPL : 1];
+    T sb[CPL];          // base source (sigma T_L, or k + D Psi), compute type
+    T bx[CPL], by[CPL];                 // inflow boundary values per axis
+    T bz[D3 ? CPL : 1];
     int si[CPL];        // solid index of the cell (sweeps that store), -1 in pores
     T ui[D3 ? CPL : 1]; // 3D: the wrap-plane input of the row's plane (used on the first y-row)
 };
@@ -424,7 +424,7 @@ struct RowOut {
 template <typename T, int CPL>
 struct Views {
     rsrc_t fc, sidx, sg, u, src, bx, by, bz;
-    uint32_t o2[CPL], o4[CPL], o8[CPL], oT[CPL], ou[CPL];
+    uint32_t o2[CPL], o4[CPL], oT[CPL], ou[CPL];
     // geometry scalars read once per sweep: the row loop stores to global
     // memory, after which the compiler would reload them from the view
     int nx, ny, nz, ga;
@@ -448,10 +448,11 @@ __device__ __forceinline__ void load_row(const GeomDev& g, const SysC<T>& s, con
         if (ST) r.si[c] = (int)bld32(v.sidx, v.o4[c], rowbase * 4u);
         r.sg[c] = S1 ? T(1) : bldT<T>(v.sg, v.oT[c], rowbase * (uint32_t)sizeof(T));
         if (WITH_B) {
-            r.sb[c] = bld64(v.src, v.o8[c], rowbase * 8u);
-            r.bx[c] = bld64(v.bx, v.o8[c], rowbase * 8u);
-            r.by[c] = bld64(v.by, v.o8[c], rowbase * 8u);
-            if (D3) r.bz[c] = bld64(v.bz, v.o8[c], rowbase * 8u);
+            const uint32_t rb = rowbase * (uint32_t)sizeof(T);
+            r.sb[c] = bldT<T>(v.src, v.oT[c], rb);
+            r.bx[c] = bldT<T>(v.bx, v.oT[c], rb);
+            r.by[c] = bldT<T>(v.by, v.oT[c], rb);
+            if (D3) r.bz[c] = bldT<T>(v.bz, v.oT[c], rb);
         }
         if (D3) r.ui[c] = bldT<T>(v.u, v.ou[c], uni((uint32_t)(kk * v.nx)) * (uint32_t)sizeof(T));
     }
@@ -535,14 +536,17 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
         // kk and jj are wave-uniform: the wrap input is used on the first row
         // only (3D: prefetched with every row, so its load is in no branch)
         const T uin = D3 ? ((FULL || p < nx) ? cur.ui[c] : T(0)) : io.in(kk, c, lane);
-        T yin = T(0);
-        if (cly != FC_WALL) yin = (jj == 0) ? uin : s.c[1] * rows.prev_y(kk, c, lane);
+        // the row below in y is read unconditionally (no branch around the
+        // LDS load) and selected
+        const T py = rows.prev_y(kk, c, lane);
+        const T yin = cly != FC_WALL ? ((jj == 0) ? uin : s.c[1] * py) : T(0);
         T rhs = yin;
         if (WITH_B) {
-            double sd = adj ? s.kw + s.Dml * cur.sb[c] : cur.sb[c];
-            sd += mb[0] * cur.bx[c] + mb[1] * cur.by[c];
-            if (D3) sd += mb[2] * cur.bz[c];
-            rhs = (T)sd + yin;
+            // in the compute type (the sources were converted once per pass)
+            T sd = adj ? (T)s.kw + (T)s.Dml * cur.sb[c] : cur.sb[c];
+            sd += (T)mb[0] * cur.bx[c] + (T)mb[1] * cur.by[c];
+            if (D3) sd += (T)mb[2] * cur.bz[c];
+            rhs = sd + yin;
         }
         if (D3) rhs += (clz != FC_WALL && kk > 0) ? cz * rows.prev_z(c) : T(0);
         const bool xs = (clx != FC_WALL);
@@ -683,7 +687,7 @@ __device__ __forceinline__ void store_rows(Red<T>* rd, const RowOut<T, CPL> (&ro
 template <typename T, int CPL, bool D3, bool WITH_B, bool RED, bool ADD, bool S1, int GA, bool FULL = false,
           class IO>
 __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int active, int lane, int adj,
-                                      const double* __restrict__ srcbase, const double* __restrict__ bnd,
+                                      const T* __restrict__ srcbase, const T* __restrict__ bnd,
                                       IO& io, Red<T>* rd, T* zrows) {
     constexpr int ND = D3 ? 3 : 2;
     double mb[3];
@@ -702,10 +706,11 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
     vw.sidx = make_rsrc(g.sidx, nc * 4u);
     vw.sg = make_rsrc(sigma_ptr<T>(g), nc * (uint32_t)sizeof(T));
     vw.u = make_rsrc(io.input(), (uint32_t)(g.nx * g.nz) * (uint32_t)sizeof(T));
-    vw.src = make_rsrc(srcbase, nc * 8u);
-    vw.bx = make_rsrc(bnd + (size_t)fb[0] * g.ncells, nc * 8u);
-    vw.by = make_rsrc(bnd + (size_t)fb[1] * g.ncells, nc * 8u);
-    vw.bz = make_rsrc(bnd + (size_t)(D3 ? fb[2] : 0) * g.ncells, nc * 8u);
+    const uint32_t tb = nc * (uint32_t)sizeof(T);
+    vw.src = make_rsrc(srcbase, tb);
+    vw.bx = make_rsrc(bnd + (size_t)fb[0] * g.ncells, tb);
+    vw.by = make_rsrc(bnd + (size_t)fb[1] * g.ncells, tb);
+    vw.bz = make_rsrc(bnd + (size_t)(D3 ? fb[2] : 0) * g.ncells, tb);
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         // cell of this lane within a row (beyond the row: the row's first cell)
@@ -713,7 +718,6 @@ __device__ __forceinline__ void sweep(const GeomDev& g, const SysC<T>& s, int ac
         const uint32_t lo = p < g.nx ? (uint32_t)(s.pos[0] ? p : g.nx - 1 - p) : 0u;
         vw.o2[c] = lo * 2u;
         vw.o4[c] = lo * 4u;
-        vw.o8[c] = lo * 8u;
         vw.oT[c] = lo * (uint32_t)sizeof(T);
         vw.ou[c] = (uint32_t)min(p, g.nx - 1) * (uint32_t)sizeof(T);
     }
@@ -1587,10 +1591,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     const int active = (w < item.nm) && (m < g.n_mfp);
     constexpr int adj = ADJ;
     const SysC<T> s = make_sys<T>(g, active ? m : item.m0, item.l, adj);
-    const int pass = g.ctrl[CTRL_PASS];
-    const int buf_in = (pp.mode == 1) ? ((pass + 1) & 1) : (pass & 1);
-    const double* srcbase = adj ? (g.lam_psi + (size_t)buf_in * g.ncells) : (g.sT + (size_t)buf_in * g.ncells);
-    const double* bnd = g.bnd + ((size_t)(adj ? 2 : 0) + buf_in) * g.nf * g.ncells;
+    // the pass's sources and inflow tables, converted to the compute type by
+    // k_pack3 before the pass
+    const T* srcbase = static_cast<const T*>(g.qrec);
+    const T* bnd = srcbase + g.ncells;
     const int nx = g.nx, nz = g.nz, nw = g.nwrap;
     const size_t half = adj ? (size_t)g.n_sys : 0;
     const gmut_t<T> U = gmut(reinterpret_cast<T*>(g.U) + (half + s.sys) * (size_t)nw);
@@ -2908,6 +2912,33 @@ hipError_t launch_sweep_pass(int precision, int cpl, int nz, const GeomDev* g, c
         case 3: return launch_sweep_t<float, 3>(g, it, n, waves, pp, lds, st, full);
         default: return launch_sweep_t<float, 4>(g, it, n, waves, pp, lds, st, full);
     }
+}
+
+// 3D: the pass's sources (sigma T_L, or sigma sum lambda in the adjoint) and
+// inflow tables, read from the buffers the pass's sweeps consume (the rule of
+// the pass kernel), in the compute type: qrec = [src | bnd face 0 | ... ].
+template <typename T>
+__global__ void __launch_bounds__(256) k_pack3(const GeomDev* __restrict__ geoms, PassParams pp) {
+    const GeomDev& g = geoms[blockIdx.y];
+    if (pp.mode == 0 && g.ctrl[CTRL_DONE]) return;
+    const int pass = g.ctrl[CTRL_PASS];
+    const int buf = (pp.mode == 1) ? ((pass + 1) & 1) : (pass & 1);
+    const size_t nc = (size_t)g.ncells, nb = (size_t)g.nf * nc;
+    const double* src = (pp.adjoint ? g.lam_psi : g.sT) + (size_t)buf * nc;
+    const double* bnd = g.bnd + ((size_t)(pp.adjoint ? 2 : 0) + buf) * nb;
+    T* out = static_cast<T*>(g.qrec);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc + nb; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (T)(i < nc ? src[i] : bnd[i - nc]);
+}
+
+hipError_t launch_pack3(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells, PassParams pp,
+                        hipStream_t st) {
+    int blocks = (7 * max_cells + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+    (void)hipGetLastError();
+    if (precision == 1) hipLaunchKernelGGL(k_pack3<float>, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp);
+    else hipLaunchKernelGGL(k_pack3<double>, dim3(blocks, n_geoms), dim3(256), 0, st, geoms_dev, pp);
+    return hipGetLastError();
 }
 
 template <typename T>

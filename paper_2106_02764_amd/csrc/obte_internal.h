@@ -96,7 +96,8 @@ struct GeomDev {
     // at row r (y-upwind order) and position p (x-upwind order).
     void* qrec;                  // 4 * ncells records {sb, bx, by, meta} of 4 compute-type words
                                  // (meta: byte 0 x inflow open, 1 y inflow open, 2 kappa_face
-                                 // plane cell, 3 solid)
+                                 // plane cell, 3 solid).  3D: the pass's sources (ncells) and
+                                 // inflow tables (nf * ncells) in the compute type
     uint32_t* qoff;              // 4 * ncells: byte offset of the cell's stored value, QOFF_NONE in pores
     void* qsg;                   // 4 * ncells: sigma in the compute type
     void* qalt;                  // adjoint passes: 4 * ncells pairs {bx, by} of the outflow faces
@@ -155,6 +156,9 @@ hipError_t launch_sweep_queue(int precision, const GeomDev* geoms_dev, const Ite
 // queue (the persistent launch's item counter) is set to 0.
 hipError_t launch_pack_rows(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells, PassParams pp,
                             hipStream_t st, int* queue);
+// 3D: the pass's sources and inflow tables in the compute type (GeomDev::qrec).
+hipError_t launch_pack3(int precision, const GeomDev* geoms_dev, int n_geoms, int max_cells, PassParams pp,
+                        hipStream_t st);
 hipError_t launch_reduce_pass(int precision, const GeomDev* geoms_dev, int n_geoms, int max_solid,
                               PassParams pp, hipStream_t st);
 // Energy balance of the last pass of one geometry (forward solve):
