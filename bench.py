@@ -62,8 +62,8 @@ REF = dict(precision=0, outer_tol=1e-10, stop_rule=0, accel=8, inner_tol=1e-12, 
 # operating point, per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over one
 # solve, each scaled by the same counter on a plain 256 MiB copy); valid only
 # for the kernel source it was taken on.
-TRAFFIC = {"kernels_sha256": "0b3fb2fc3140dd4828bf34bb5ece5511f0dfd1ebc0c5559b1b39fb82d5cfd6ca",
-           "fetch_bytes": 15587218, "write_bytes": 59391559}
+TRAFFIC = {"kernels_sha256": "523486508474d8cee82c5e28f842f0c8abb915e97a2979d04691d116335d7667",
+           "fetch_bytes": 15546242, "write_bytes": 59392019}
 
 
 def parse():
