@@ -669,6 +669,14 @@ obte_status resolve_waves(const obte_mesh* const* meshes, int n, const obte_solv
         const size_t per_wave = nzm > 1 ? (size_t)nzm * 64 * c * tsz : 0;
         if (present[c] && per_wave > cap)
             return fail(OBTE_ERR_ARG, "a wave needs %zu bytes of LDS (nx, nz too large; limit %zu)", per_wave, cap);
+        // 2D FP64 rows of 3 or 4 cells per lane (and the FP64 persistent
+        // launch, which holds every class body) run at most 4 waves per
+        // group: the kernels' register budget
+        if (present[c] && nzm == 1 && o->precision == OBTE_FP64 && (c >= 3 || o->dispatch == 2) && W > 4) {
+            if (set || o->waves_per_group)
+                return fail(OBTE_ERR_ARG, "FP64 sweeps of %d cells per lane take at most 4 systems per workgroup", c);
+            W = 4;
+        }
         const int wmax = per_wave > 0 ? (int)(cap / per_wave) : 8;
         if (present[c] && W > wmax) {
             if (set || o->waves_per_group)

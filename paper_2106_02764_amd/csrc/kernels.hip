@@ -1515,9 +1515,16 @@ __device__ __forceinline__ void pass_system(const GeomDev* __restrict__ geoms, c
     finish_system(g, s, active, lane, adj, pp, rd, n_it, n_sw);
 }
 
+// Threads per workgroup of a 2D pass kernel: FP64 rows of 3 or 4 cells per
+// lane hold more registers than two waves per SIMD leave (they spilled to
+// scratch), so those kernels take at most 4 waves per group (the host caps
+// the systems per workgroup to match).
+template <typename T, int CPL>
+constexpr int pass_threads() { return (sizeof(T) == 8 && CPL >= 3) ? 256 : 512; }
+
 // The 2D pass: one workgroup per work item, one of its systems per wave.
 template <typename T, int CPL, int ADJ, int SIG1, bool FULL>
-__global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ geoms,
+__global__ void __launch_bounds__((pass_threads<T, CPL>())) k_sweep_pass(const GeomDev* __restrict__ geoms,
                                                     const Item* __restrict__ items, int n_items,
                                                     PassParams pp) {
     const int it = blockIdx.x;
@@ -1534,7 +1541,7 @@ __global__ void __launch_bounds__(512) k_sweep_pass(const GeomDev* __restrict__ 
 // The waves of a group never wait for each other inside an item; the two
 // barriers only order the group's read of the slot against its next write.
 template <typename T, int ADJ, int SIG1>
-__global__ void __launch_bounds__(512) k_sweep_queue(const GeomDev* __restrict__ geoms,
+__global__ void __launch_bounds__((pass_threads<T, 4>())) k_sweep_queue(const GeomDev* __restrict__ geoms,
                                                      const Item* __restrict__ items, int n_items,
                                                      PassParams pp, int* __restrict__ queue) {
     __shared__ int slot;

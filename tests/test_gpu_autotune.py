@@ -47,7 +47,7 @@ def test_tuned_shape_cached_and_bitwise_neutral(P, tmp_path, monkeypatch):
     # every other shape too: one system per workgroup everywhere, the
     # batch-wide longest-MFP-first order
     ox = P.autotune.apply(P.default_opts(**{f: getattr(o, f) for f, _ in o._fields_}),
-                          {"waves_by_class": [1, 2, 8, 0], "dispatch": 1})
+                          {"waves_by_class": [1, 8, 4, 0], "dispatch": 1})
     k2, _ = P.solve_batch(solvers, ox)
     assert k2 == k0
     # one persistent launch over the three classes (device-side item queue),
@@ -87,3 +87,20 @@ def test_queue_launch_four_classes(P, precision):
             g, _ = s.adjoint(o)
             grads.append(g.cpu().numpy())
         assert np.array_equal(grads[0], grads[1])
+
+
+def test_fp64_wide_rows_cap_systems_per_workgroup(P):
+    """FP64 sweeps of 3 or 4 cells per lane run at most 4 systems per
+    workgroup (their kernels' register budget): 8 is refused on the host
+    for those classes, accepted in FP32 and for narrower rows; the automatic
+    choice stays within the cap."""
+    w = gen.small_2d(150, 8, n_dir=8, n_mfp=9, L=150e-9, Ly=8e-9)
+    s = P.Solver.from_workload(w)
+    O = P.obte
+    with pytest.raises(P.ObteError) as e:
+        O.obte_workspace_size(s.mesh, P.default_opts(precision=0, waves_by_class=[0, 0, 8, 0]))
+    assert e.value.status == O.OBTE_ERR_ARG
+    assert O.obte_workspace_size(s.mesh, P.default_opts(precision=1, waves_by_class=[0, 0, 8, 0])) > 0
+    assert O.obte_workspace_size(s.mesh, P.default_opts(precision=0, waves_by_class=[8, 8, 4, 4])) > 0
+    out = s.solve(s.opts(precision=0, outer_tol=1e-8, waves_per_group=0), want_T_L=False)
+    assert out["status"] == 0
