@@ -227,8 +227,9 @@ struct USys {
 // wall values; else none) and the wrap inflow staged in LDS.  The workgroup
 // is one wavefront, whose LDS accesses are executed in program order, so
 // level k + 1 reads what level k wrote without a barrier; the table entries
-// of a lane's cell in the next level (independent of the solution) are
-// loaded while the current level is solved.
+// of a lane's cell in the next level (independent of the solution, and all
+// indexed by the sweep position: the pass's sources are packed in sweep
+// order by k_upack) are loaded two levels ahead of their solve.
 struct UEnt {
     int i;
     double d, sg, b;              // outflow sum, sigma, sigma T_L + the wall inflow
@@ -240,18 +241,36 @@ __device__ __forceinline__ void ufetch(const UGeomDev& g, const USys& s, bool sr
     const size_t pl = (size_t)s.l * g.ns + p;
     e.i = g.ord[pl];
     e.d = g.dout[pl];
-    e.sg = g.sigma[e.i];
-    double wall = 0.0;
+    e.sg = g.psg[pl];
+    const double b0 = g.pb0[pl], bw = g.pbw[pl];
 #pragma unroll
     for (int q = 0; q < UFACES; ++q) {
         const int code = g.inc[pl * UFACES + q];
-        const double c = g.inv[pl * UFACES + q];
-        const bool w = code <= UWALL0;
-        wall += (w && src) ? c * g.T_w[w ? UWALL0 - code : 0] : 0.0;
-        e.code[q] = w ? UNONE : code;
-        e.c[q] = c;
+        e.code[q] = code <= UWALL0 ? UNONE : code;
+        e.c[q] = g.inv[pl * UFACES + q];
     }
-    e.b = src ? e.sg * g.T_L[e.i] + s.lam * wall : 0.0;
+    e.b = src ? b0 + s.lam * bw : 0.0;
+}
+
+// The pass's sources in every direction's sweep order: sigma, sigma T_L and
+// the inflow wall sum of the cell at each position (one thread per position).
+__global__ void __launch_bounds__(256) k_upack(const UGeomDev* __restrict__ gp) {
+    const UGeomDev& g = *gp;
+    const size_t n = (size_t)g.n_dir * g.ns;
+    for (size_t pl = (size_t)blockIdx.x * blockDim.x + threadIdx.x; pl < n; pl += (size_t)gridDim.x * blockDim.x) {
+        const int i = g.ord[pl];
+        double wall = 0.0;
+#pragma unroll
+        for (int q = 0; q < UFACES; ++q) {
+            const int code = g.inc[pl * UFACES + q];
+            const bool w = code <= UWALL0;
+            wall += w ? g.inv[pl * UFACES + q] * g.T_w[UWALL0 - code] : 0.0;
+        }
+        const double sg = g.sigma[i];
+        g.psg[pl] = sg;
+        g.pb0[pl] = sg * g.T_L[i];
+        g.pbw[pl] = wall;
+    }
 }
 
 __device__ __forceinline__ void usolve(const UGeomDev& g, const USys& s, const UEnt& e, double* x, const double* uin) {
@@ -268,15 +287,22 @@ __device__ __forceinline__ void usolve(const UGeomDev& g, const USys& s, const U
 
 __device__ void usweep(const UGeomDev& g, const USys& s, bool src, double* x, const double* uin) {
     const int lane = threadIdx.x;
-    int p0 = g.lptr[s.lb], p1 = g.lptr[s.lb + 1];
-    UEnt cur, nxt;
-    if (p0 + lane < p1) ufetch(g, s, src, p0 + lane, cur);
-    for (int k = 0; k < s.nlev; ++k) {
-        const bool more = k + 1 < s.nlev;
-        const int q0 = more ? g.lptr[s.lb + k + 1] : 0, q1 = more ? g.lptr[s.lb + k + 2] : 0;
-        if (q0 + lane < q1) ufetch(g, s, src, q0 + lane, nxt);
-        if (p0 + lane < p1) usolve(g, s, cur, x, uin);
-        for (int p = p0 + lane + WAVE; p < p1; p += WAVE) {
+    // level k spans positions [lp[k], lp[k + 1]); past the last level the
+    // bounds clamp to its end (empty ranges).  At level k the entries of level
+    // k + 2 are fetched (two levels of loads in flight) and the bound that
+    // ends level k + 3 is loaded a level before it is needed.
+    const int* lp = g.lptr + s.lb;
+    const int L = s.nlev;
+    auto bound = [&](int k) { return lp[k < L ? k : L]; };
+    int a0 = bound(0), a1 = bound(1), e1 = bound(2), e2 = bound(3);
+    UEnt cur, nxt, nx2;
+    if (a0 + lane < a1) ufetch(g, s, src, a0 + lane, cur);
+    if (a1 + lane < e1) ufetch(g, s, src, a1 + lane, nxt);
+    for (int k = 0; k < L; ++k) {
+        const int e3 = bound(k + 4);
+        if (e1 + lane < e2) ufetch(g, s, src, e1 + lane, nx2);
+        if (a0 + lane < a1) usolve(g, s, cur, x, uin);
+        for (int p = a0 + lane + WAVE; p < a1; p += WAVE) {
             UEnt e;
             ufetch(g, s, src, p, e);
             usolve(g, s, e, x, uin);
@@ -285,8 +311,11 @@ __device__ void usweep(const UGeomDev& g, const USys& s, bool src, double* x, co
         // next level's
         __builtin_amdgcn_wave_barrier();
         cur = nxt;
-        p0 = q0;
-        p1 = q1;
+        nxt = nx2;
+        a0 = a1;
+        a1 = e1;
+        e1 = e2;
+        e2 = e3;
     }
 }
 
@@ -541,9 +570,12 @@ hipError_t ulaunch_fourier(const UFourierDev* f_dev, int ns, double tol, int max
     return hipGetLastError();
 }
 
-hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int wpl, size_t lds_bytes, double inner_tol,
+hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int n_pos, int wpl, size_t lds_bytes, double inner_tol,
                         double inner_rtol, int max_inner, hipStream_t st) {
     (void)hipGetLastError();
+    int blocks = (n_pos + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+    hipLaunchKernelGGL(k_upack, dim3(blocks), dim3(256), 0, st, g_dev);
     switch (wpl) {
     case 1: hipLaunchKernelGGL(k_upass<1>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, inner_rtol, max_inner); break;
     case 2: hipLaunchKernelGGL(k_upass<2>, dim3(n_sys), dim3(WAVE), lds_bytes, st, g_dev, inner_tol, inner_rtol, max_inner); break;

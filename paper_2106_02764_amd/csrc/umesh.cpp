@@ -598,6 +598,9 @@ obte_status obte_umesh_material_set(obte_umesh* m, const double* mfp, int n_mfp,
     AL(&g.iters, m->n_sys);
     AL(&g.kap, 4);
     AL(&g.wres, m->n_sys);
+    AL(&g.psg, (size_t)n_dir * ns);
+    AL(&g.pb0, (size_t)n_dir * ns);
+    AL(&g.pbw, (size_t)n_dir * ns);
     UFourierDev fdv{};
     fdv.ns = ns;
     fdv.nfaces = nf;
@@ -712,7 +715,7 @@ obte_status obte_umesh_solve(obte_umesh* m, const obte_solve_opts* o, const doub
     bool converged = false;
     int passes = 0;
     for (passes = 1; passes <= o->max_outer; ++passes) {
-        UHIP(ulaunch_pass(m->gd, m->n_sys, wpl, lds, o->inner_tol, o->inner_rtol, o->max_inner, st));
+        UHIP(ulaunch_pass(m->gd, m->n_sys, m->n_dir * ns, wpl, lds, o->inner_tol, o->inner_rtol, o->max_inner, st));
         UHIP(ulaunch_reduce(m->gd, ns, nw, st));
         UHIP(hipMemcpyAsync(kap, g.kap, sizeof kap, hipMemcpyDeviceToHost, st));
         UHIP(hipStreamSynchronize(st));

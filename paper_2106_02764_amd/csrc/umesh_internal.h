@@ -52,6 +52,12 @@ struct UGeomDev {
     long long* iters;         // n_sys: accumulated BiCGSTAB iterations
     double* kap;              // 4: kappa_cc, kappa_face of the pass, max relative wrap residual
     double* wres;             // n_sys: relative wrap residual after the pass
+    // ---- per pass, in every direction's sweep order (k_upack): sigma of the
+    // cell at each position, sigma T_L, and the sum over its inflow wall faces
+    // of |s.n| A / V T_w (the wall part of the source before the factor Lambda)
+    double* psg;              // n_dir * ns
+    double* pb0;              // n_dir * ns
+    double* pbw;              // n_dir * ns
 };
 
 struct UFourierDev {
@@ -86,6 +92,8 @@ struct UFourierDev {
 
 hipError_t ulaunch_fourier(const UFourierDev* f_dev, int ns, double tol, int max_outer, double cg_tol,
                            int max_cg, hipStream_t st);
-hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int wpl, size_t lds_bytes, double inner_tol,
+// the pass's sources packed in sweep order (n_pos = n_dir * n_solid
+// positions), then every system's pass
+hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int n_pos, int wpl, size_t lds_bytes, double inner_tol,
                         double inner_rtol, int max_inner, hipStream_t st);
 hipError_t ulaunch_reduce(const UGeomDev* g_dev, int ns, int nwalls, hipStream_t st);
