@@ -64,20 +64,6 @@ __device__ double block_max(double v, double* red) {
 // ---------------------------------------------------------------------------
 // heat conduction with the explicit secondary flux
 // ---------------------------------------------------------------------------
-__device__ void ucell_gradients(const UFourierDev& f) {
-    for (int i = threadIdx.x; i < f.ns; i += blockDim.x) {
-        double gx = 0.0, gy = 0.0;
-        const double Ti = f.T[i];
-        for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
-            const double q = f.T[f.nb_j[k]] + f.nb_del[k] * f.dT - Ti;
-            gx += f.nb_w[2 * k] * q;
-            gy += f.nb_w[2 * k + 1] * q;
-        }
-        f.g[2 * i] = gx;
-        f.g[2 * i + 1] = gy;
-    }
-}
-
 __device__ __forceinline__ void uface_gradient(const UFourierDev& f, int fc, double& gx, double& gy) {
     const int i = f.fi[fc], j = f.fj[fc];
     const double w = f.fw[fc];
@@ -99,101 +85,218 @@ __device__ __forceinline__ double udiag(const UFourierDev& f, int i) {
     return d > 0.0 ? d : 1.0;
 }
 
-__global__ void __launch_bounds__(UF_THREADS) k_ufourier(const UFourierDev* __restrict__ fp, double tol,
-                                                         int max_outer, double cg_tol, int max_cg) {
+// ---- the outer iteration over several blocks of UFB cells.  Every sum is
+// taken as per-block partials that each consumer adds in block order, so
+// every block takes the same decisions and FP64 results are reproducible.
+constexpr int UFB = 256;
+enum { UP_RR0, UP_RR1, UP_RZ0, UP_RZ1, UP_PQ, UP_BB, UP_ST, UP_DM, UP_TM };
+static_assert(UP_TM + 1 == UF_SLOTS, "partial slots of the heat-conduction kernels");
+
+__host__ __device__ __forceinline__ int uf_blocks(int ns) { return (ns + UFB - 1) / UFB; }
+
+// fixed-order sum (or max) of the B partials of a slot, in every thread
+__device__ __forceinline__ double uf_sum(const UFourierDev& f, int slot, int B, double* red) {
+    const double v = (int)threadIdx.x < B ? f.fpart[slot * UF_MAXB + threadIdx.x] : 0.0;
+    return block_sum(v, red);
+}
+__device__ __forceinline__ double uf_max(const UFourierDev& f, int slot, int B, double* red) {
+    const double v = (int)threadIdx.x < B ? f.fpart[slot * UF_MAXB + threadIdx.x] : 0.0;
+    return block_max(v, red);
+}
+
+__device__ __forceinline__ void ucell_gradient(const UFourierDev& f, int i) {
+    double gx = 0.0, gy = 0.0;
+    const double Ti = f.T[i];
+    for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
+        const double q = f.T[f.nb_j[k]] + f.nb_del[k] * f.dT - Ti;
+        gx += f.nb_w[2 * k] * q;
+        gy += f.nb_w[2 * k + 1] * q;
+    }
+    f.g[2 * i] = gx;
+    f.g[2 * i + 1] = gy;
+}
+
+// cell gradients of the current T
+__global__ void __launch_bounds__(UFB) k_uf_grad(const UFourierDev* __restrict__ fp) {
+    const UFourierDev& f = *fp;
+    const int i = blockIdx.x * UFB + threadIdx.x;
+    if (i < f.ns) ucell_gradient(f, i);
+}
+
+// the secondary flux of every face from the interpolated face gradient
+__global__ void __launch_bounds__(UFB) k_uf_face(const UFourierDev* __restrict__ fp) {
+    const UFourierDev& f = *fp;
+    const int fc = blockIdx.x * UFB + threadIdx.x;
+    if (fc >= f.nfaces) return;
+    double gx, gy;
+    uface_gradient(f, fc, gx, gy);
+    f.bf[fc] = gx * f.fc[2 * fc] + gy * f.fc[2 * fc + 1];
+}
+
+// b = -(P + B) (the right-hand side of A T = b, A = -Laplacian), the previous
+// iterate, the diagonal, the first residual r = b - A T (warm start from T)
+// and its preconditioned form; partials of |b|^2, r.r and r.z.  The CG
+// direction of parity 1 (the one before the first) is 0.
+__global__ void __launch_bounds__(UFB) k_uf_init(const UFourierDev* __restrict__ fp) {
+    __shared__ double red[UFB / 64];
+    const UFourierDev& f = *fp;
+    const int i = blockIdx.x * UFB + threadIdx.x;
+    double bb = 0.0, rr = 0.0, rz = 0.0;
+    if (i < f.ns) {
+        double s = f.P[i];
+        for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
+            const int code = f.nb_f[k];
+            const double v = f.bf[code >> 1];
+            s += (code & 1) ? -v : v;
+        }
+        const double d = udiag(f, i);
+        const double ri = -s - uapply(f, f.T, i);
+        f.tp[i] = f.T[i];
+        f.dg[i] = d;
+        f.r[i] = ri;
+        f.p2[i] = 0.0;
+        bb = s * s;
+        rr = ri * ri;
+        rz = ri * (ri / d);
+    }
+    bb = block_sum(bb, red);
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        f.fpart[UP_BB * UF_MAXB + blockIdx.x] = bb;
+        f.fpart[UP_RR0 * UF_MAXB + blockIdx.x] = rr;
+        f.fpart[UP_RZ0 * UF_MAXB + blockIdx.x] = rz;
+        if (blockIdx.x == 0) {
+            f.fsc[0] = 0.0;            // this solve's CG runs
+            f.fsc[1] = 0.0;            // its iterations
+        }
+    }
+}
+
+// CG iteration it (parity q = it & 1), first half: the stop test on r.r, the
+// direction p = z + beta p_old (z = r / diag; beta = 0 first) written to the
+// parity-q buffer and q = A p, which needs p at the neighbours: each block
+// forms them from r and the parity-(q ^ 1) buffer, neither written here;
+// partials of p.q.  Parity 0 directions live in p, parity 1 in p2.
+__global__ void __launch_bounds__(UFB) k_uf_pq(const UFourierDev* __restrict__ fp, int q, double cg_tol,
+                                               int max_cg) {
+    __shared__ double red[UFB / 64];
+    const UFourierDev& f = *fp;
+    if (f.fsc[0] != 0.0) return;
+    const int B = uf_blocks(f.ns);
+    const double rr = uf_sum(f, UP_RR0 + q, B, red), rz = uf_sum(f, UP_RZ0 + q, B, red);
+    const double bb = uf_sum(f, UP_BB, B, red);
+    const int it = (int)f.fsc[1];
+    if (!(rr > cg_tol * cg_tol * bb) || it >= max_cg) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) f.fsc[0] = 1.0;
+        return;
+    }
+    const double beta = it == 0 ? 0.0 : rz / uf_sum(f, UP_RZ0 + (q ^ 1), B, red);
+    const double* po = q ? f.p : f.p2;
+    double* pn = q ? f.p2 : f.p;
+    const int i = blockIdx.x * UFB + threadIdx.x;
+    double pq = 0.0;
+    if (i < f.ns) {
+        const double pc = f.r[i] / f.dg[i] + beta * po[i];
+        double y = 0.0;
+        for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
+            const int j = f.nb_j[k];
+            y += f.nb_a[k] * (pc - (f.r[j] / f.dg[j] + beta * po[j]));
+        }
+        pn[i] = pc;
+        f.q[i] = y;
+        pq = pc * y;
+    }
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) f.fpart[UP_PQ * UF_MAXB + blockIdx.x] = pq;
+}
+
+// second half: alpha = r.z / p.q, T += alpha p, r -= alpha q, partials of the
+// new r.r and r.z into parity q ^ 1; the iteration counts
+__global__ void __launch_bounds__(UFB) k_uf_xr(const UFourierDev* __restrict__ fp, int q) {
+    __shared__ double red[UFB / 64];
+    const UFourierDev& f = *fp;
+    if (f.fsc[0] != 0.0) return;
+    const int B = uf_blocks(f.ns);
+    const double pq = uf_sum(f, UP_PQ, B, red), rz = uf_sum(f, UP_RZ0 + q, B, red);
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) f.fsc[0] = 1.0;
+        return;
+    }
+    const double alpha = rz / pq;
+    const double* pn = q ? f.p2 : f.p;
+    const int i = blockIdx.x * UFB + threadIdx.x;
+    double rn = 0.0, zn = 0.0;
+    if (i < f.ns) {
+        f.T[i] += alpha * pn[i];
+        const double ri = f.r[i] - alpha * f.q[i];
+        f.r[i] = ri;
+        rn = ri * ri;
+        zn = ri * ri / f.dg[i];
+    }
+    rn = block_sum(rn, red);
+    zn = block_sum(zn, red);
+    if (threadIdx.x == 0) {
+        f.fpart[(UP_RR0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = rn;
+        f.fpart[(UP_RZ0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = zn;
+        if (blockIdx.x == 0) {
+            f.fsc[1] += 1.0;
+            f.fsc[2] += 1.0;
+        }
+    }
+}
+
+// end of an outer iteration: partials of the sum of T ...
+__global__ void __launch_bounds__(UFB) k_uf_sum(const UFourierDev* __restrict__ fp) {
+    __shared__ double red[UFB / 64];
+    const UFourierDev& f = *fp;
+    const int i = blockIdx.x * UFB + threadIdx.x;
+    const double v = block_sum(i < f.ns ? f.T[i] : 0.0, red);
+    if (threadIdx.x == 0) f.fpart[UP_ST * UF_MAXB + blockIdx.x] = v;
+}
+
+// ... the mean removed, and partials of max |T - T_prev| and max |T|
+__global__ void __launch_bounds__(UFB) k_uf_center(const UFourierDev* __restrict__ fp) {
+    __shared__ double red[UFB / 64];
+    const UFourierDev& f = *fp;
+    const double mean = uf_sum(f, UP_ST, uf_blocks(f.ns), red) / (double)f.ns;
+    const int i = blockIdx.x * UFB + threadIdx.x;
+    double dmax = 0.0, tmax = 0.0;
+    if (i < f.ns) {
+        const double v = f.T[i] - mean;
+        f.T[i] = v;
+        dmax = fabs(v - f.tp[i]);
+        tmax = fabs(v);
+    }
+    dmax = block_max(dmax, red);
+    tmax = block_max(tmax, red);
+    if (threadIdx.x == 0) {
+        f.fpart[UP_DM * UF_MAXB + blockIdx.x] = dmax;
+        f.fpart[UP_TM * UF_MAXB + blockIdx.x] = tmax;
+    }
+}
+
+// ... the change and the outer stop test (one block)
+__global__ void __launch_bounds__(UFB) k_uf_change(const UFourierDev* __restrict__ fp, double tol) {
+    __shared__ double red[UFB / 64];
+    const UFourierDev& f = *fp;
+    const int B = uf_blocks(f.ns);
+    const double dmax = uf_max(f, UP_DM, B, red), tmax = uf_max(f, UP_TM, B, red);
+    if (threadIdx.x == 0) {
+        f.fsc[3] += 1.0;
+        f.fsc[4] = tmax > 0.0 ? dmax / tmax : 0.0;
+        f.fsc[5] = dmax <= tol * fmax(tmax, 1e-300) ? 1.0 : 0.0;
+    }
+}
+
+// kappa_F: the total face flux (primary + secondary) across the periodic
+// plane of the gradient axis, from the final T's gradients (one block; the
+// gradients are taken by k_uf_grad before it); the statistics into out
+__global__ void __launch_bounds__(UF_THREADS) k_uf_kappa(const UFourierDev* __restrict__ fp) {
     __shared__ double red[UF_THREADS / 64];
     const UFourierDev& f = *fp;
-    const int ns = f.ns, t = threadIdx.x, B = blockDim.x;
-    double* Tp = f.q;       // the previous outer iterate (q is free between CG solves)
-    int outer = 0, cg_total = 0;
-    double change = 0.0;
-    for (outer = 1; outer <= max_outer; ++outer) {
-        ucell_gradients(f);
-        __syncthreads();
-        for (int fc = t; fc < f.nfaces; fc += B) {
-            double gx, gy;
-            uface_gradient(f, fc, gx, gy);
-            f.bf[fc] = gx * f.fc[2 * fc] + gy * f.fc[2 * fc + 1];
-        }
-        __syncthreads();
-        // b = -(P + B): the right-hand side of A T = b, A = -Laplacian
-        double bb = 0.0;
-        for (int i = t; i < ns; i += B) {
-            double s = f.P[i];
-            for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
-                const int code = f.nb_f[k];
-                const double v = f.bf[code >> 1];
-                s += (code & 1) ? -v : v;
-            }
-            f.b[i] = -s;
-            Tp[i] = f.T[i];
-            bb += s * s;
-        }
-        bb = block_sum(bb, red);
-        // conjugate gradients from the current T, preconditioned by the
-        // diagonal (the sum of the cell's primary coefficients)
-        double rr = 0.0, rz = 0.0;
-        for (int i = t; i < ns; i += B) {
-            const double ri = f.b[i] - uapply(f, f.T, i);
-            const double zi = ri / udiag(f, i);
-            f.r[i] = ri;
-            f.p[i] = zi;
-            rr += ri * ri;
-            rz += ri * zi;
-        }
-        rr = block_sum(rr, red);
-        rz = block_sum(rz, red);
-        const double stop = cg_tol * cg_tol * bb;
-        for (int it = 0; it < max_cg && rr > stop; ++it) {
-            double pq = 0.0;
-            for (int i = t; i < ns; i += B) {
-                const double qi = uapply(f, f.p, i);
-                f.b[i] = qi;                       // b is free once r is formed
-                pq += f.p[i] * qi;
-            }
-            pq = block_sum(pq, red);
-            if (!(pq > 0.0)) break;
-            const double alpha = rz / pq;
-            double rn = 0.0, zn = 0.0;
-            for (int i = t; i < ns; i += B) {
-                f.T[i] += alpha * f.p[i];
-                const double ri = f.r[i] - alpha * f.b[i];
-                f.r[i] = ri;
-                rn += ri * ri;
-                zn += ri * ri / udiag(f, i);
-            }
-            rn = block_sum(rn, red);
-            zn = block_sum(zn, red);
-            const double beta = zn / rz;
-            rr = rn;
-            rz = zn;
-            for (int i = t; i < ns; i += B) f.p[i] = f.r[i] / udiag(f, i) + beta * f.p[i];
-            ++cg_total;
-            __syncthreads();
-        }
-        // mean zero, then the change against the previous iterate
-        double sm = 0.0;
-        for (int i = t; i < ns; i += B) sm += f.T[i];
-        const double mean = block_sum(sm, red) / (double)ns;
-        double dmax = 0.0, tmax = 0.0;
-        for (int i = t; i < ns; i += B) {
-            const double v = f.T[i] - mean;
-            f.T[i] = v;
-            dmax = fmax(dmax, fabs(v - Tp[i]));
-            tmax = fmax(tmax, fabs(v));
-        }
-        dmax = block_max(dmax, red);
-        tmax = block_max(tmax, red);
-        change = tmax > 0.0 ? dmax / tmax : 0.0;
-        if (dmax <= tol * fmax(tmax, 1e-300)) break;
-    }
-    // kappa_F: the total face flux (primary + secondary) across the periodic
-    // plane of the gradient axis
-    __syncthreads();
-    ucell_gradients(f);
-    __syncthreads();
     double tot = 0.0;
-    for (int c = t; c < f.ncut; c += B) {
+    for (int c = threadIdx.x; c < f.ncut; c += blockDim.x) {
         const int fc = f.cut_f[c];
         double gx, gy;
         uface_gradient(f, fc, gx, gy);
@@ -205,11 +308,11 @@ __global__ void __launch_bounds__(UF_THREADS) k_ufourier(const UFourierDev* __re
         tot += f.cut_A[c] * (a * (f.T[jn] + f.dT - f.T[ip]) + (gx * kx + gy * ky) - a * gd);
     }
     tot = block_sum(tot, red);
-    if (t == 0) {
+    if (threadIdx.x == 0) {
         f.out[0] = f.Lg / (f.dT * f.Aperp) * tot;
-        f.out[1] = (double)(outer > max_outer ? max_outer : outer);
-        f.out[2] = (double)cg_total;
-        f.out[3] = change;
+        f.out[1] = f.fsc[3];
+        f.out[2] = f.fsc[2];
+        f.out[3] = f.fsc[4];
     }
 }
 
@@ -562,11 +665,42 @@ __global__ void __launch_bounds__(256) k_ukappa(const UGeomDev* __restrict__ gp)
 
 }  // namespace
 
-hipError_t ulaunch_fourier(const UFourierDev* f_dev, int ns, double tol, int max_outer, double cg_tol, int max_cg,
-                           hipStream_t st) {
-    (void)ns;
+hipError_t ulaunch_fourier_start(const UFourierDev* f_dev, int ns, int nfaces, hipStream_t st) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_ufourier, dim3(1), dim3(UF_THREADS), 0, st, f_dev, tol, max_outer, cg_tol, max_cg);
+    const int B = uf_blocks(ns), BF = (nfaces + UFB - 1) / UFB;
+    hipLaunchKernelGGL(k_uf_grad, dim3(B), dim3(UFB), 0, st, f_dev);
+    if (BF > 0) hipLaunchKernelGGL(k_uf_face, dim3(BF), dim3(UFB), 0, st, f_dev);
+    hipLaunchKernelGGL(k_uf_init, dim3(B), dim3(UFB), 0, st, f_dev);
+    return hipGetLastError();
+}
+
+hipError_t ulaunch_fourier_cg(const UFourierDev* f_dev, int ns, int iters, double cg_tol, int max_cg,
+                              hipStream_t st) {
+    (void)hipGetLastError();
+    const int B = uf_blocks(ns);
+    for (int k = 0; k < iters; ++k) {
+        // the parity of an iteration is its count's, which is even at the
+        // start of every chunk (chunks are even and a solve starts at 0)
+        const int q = k & 1;
+        hipLaunchKernelGGL(k_uf_pq, dim3(B), dim3(UFB), 0, st, f_dev, q, cg_tol, max_cg);
+        hipLaunchKernelGGL(k_uf_xr, dim3(B), dim3(UFB), 0, st, f_dev, q);
+    }
+    return hipGetLastError();
+}
+
+hipError_t ulaunch_fourier_end(const UFourierDev* f_dev, int ns, double tol, hipStream_t st) {
+    (void)hipGetLastError();
+    const int B = uf_blocks(ns);
+    hipLaunchKernelGGL(k_uf_sum, dim3(B), dim3(UFB), 0, st, f_dev);
+    hipLaunchKernelGGL(k_uf_center, dim3(B), dim3(UFB), 0, st, f_dev);
+    hipLaunchKernelGGL(k_uf_change, dim3(1), dim3(UFB), 0, st, f_dev, tol);
+    return hipGetLastError();
+}
+
+hipError_t ulaunch_fourier_kappa(const UFourierDev* f_dev, int ns, hipStream_t st) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_uf_grad, dim3(uf_blocks(ns)), dim3(UFB), 0, st, f_dev);
+    hipLaunchKernelGGL(k_uf_kappa, dim3(1), dim3(UF_THREADS), 0, st, f_dev);
     return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ obte_status ufail(obte_status st, const char* fmt, ...) {
     } while (0)
 
 constexpr int MAX_SOLID = 8192;     // with the wrap slots: one workgroup's 64 KiB of LDS
+static_assert(MAX_SOLID <= 256 * UF_MAXB, "heat-conduction partials: one slot per block of 256 cells");
 
 }  // namespace
 
@@ -74,6 +75,7 @@ struct obte_umesh {
     double* sigma1 = nullptr;
     int* scell_d = nullptr;
     int* wcell_d = nullptr;
+    double* h_fsc = nullptr;                   // pinned: the heat-conduction loop scalars read back
 };
 
 namespace {
@@ -81,6 +83,8 @@ namespace {
 void free_dev(obte_umesh* m) {
     for (void* p : m->dev) (void)hipFree(p);
     m->dev.clear();
+    if (m->h_fsc) (void)hipHostFree(m->h_fsc);
+    m->h_fsc = nullptr;
     m->gd = nullptr;
     m->fdv = nullptr;
     (void)hipGetLastError();
@@ -633,6 +637,16 @@ obte_status obte_umesh_material_set(obte_umesh* m, const double* mfp, int n_mfp,
     AL(&fdv.g, 2 * (size_t)ns);
     AL(&fdv.bf, nf);
     AL(&fdv.out, 4);
+    AL(&fdv.p2, ns);
+    AL(&fdv.tp, ns);
+    AL(&fdv.dg, ns);
+    AL(&fdv.fpart, (size_t)UF_SLOTS * UF_MAXB);
+    AL(&fdv.fsc, 8);
+    if (hipHostMalloc((void**)&m->h_fsc, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        m->h_fsc = nullptr;
+        free_dev(m);
+        return ufail(OBTE_ERR_HIP, "hipHostMalloc failed");
+    }
     std::vector<UGeomDev> gv{g};
     std::vector<UFourierDev> fv{fdv};
     UP(&m->gd, gv);
@@ -652,9 +666,26 @@ obte_status obte_umesh_fourier(obte_umesh* m, double tol, int max_outer, double 
     if (!(tol >= 0.0) || !(cg_tol > 0.0) || max_outer < 1) return ufail(OBTE_ERR_ARG, "need tol >= 0, cg_tol > 0, max_outer >= 1");
     hipStream_t st = (hipStream_t)stream;
     UHIP(hipMemsetAsync(m->fh.T, 0, sizeof(double) * m->ns, st));
+    UHIP(hipMemsetAsync(m->fh.fsc, 0, sizeof(double) * 8, st));
     // conjugate gradients end in at most n steps in exact arithmetic; twice
     // that caps a solve whose tolerance sits below the rounding floor
-    UHIP(ulaunch_fourier(m->fdv, m->ns, tol, max_outer, cg_tol, 2 * m->ns + 50, st));
+    const int max_cg = 2 * m->ns + 50;
+    constexpr int CG_CHUNK = 16;        // CG iterations queued per read of the stop flag (even)
+    double* h = m->h_fsc;               // pinned: the loop scalars read back
+    for (int outer = 1; outer <= max_outer; ++outer) {
+        UHIP(ulaunch_fourier_start(m->fdv, m->ns, m->nf, st));
+        for (int done = 0; !done;) {
+            UHIP(ulaunch_fourier_cg(m->fdv, m->ns, CG_CHUNK, cg_tol, max_cg, st));
+            UHIP(hipMemcpyAsync(h, m->fh.fsc, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+            UHIP(hipStreamSynchronize(st));
+            done = h[0] != 0.0;
+        }
+        UHIP(ulaunch_fourier_end(m->fdv, m->ns, tol, st));
+        UHIP(hipMemcpyAsync(h, m->fh.fsc, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+        UHIP(hipStreamSynchronize(st));
+        if (h[5] != 0.0 || !std::isfinite(h[4])) break;
+    }
+    UHIP(ulaunch_fourier_kappa(m->fdv, m->ns, st));
     double out[4];
     UHIP(hipMemcpyAsync(out, m->fh.out, sizeof out, hipMemcpyDeviceToHost, st));
     if (T_dev) {

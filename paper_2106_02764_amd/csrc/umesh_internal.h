@@ -88,10 +88,28 @@ struct UFourierDev {
     double* g;                // 2 * ns: cell gradients
     double* bf;               // nfaces: secondary flux per face
     double* out;              // 4: kappa_F, outer iterations, CG iterations, last relative change
+    // multi-block solve: the second direction buffer, the previous outer
+    // iterate, the diagonal, per-block partial sums and loop scalars
+    double* p2;               // ns
+    double* tp;               // ns
+    double* dg;               // ns
+    double* fpart;            // UF_SLOTS * UF_MAXB
+    double* fsc;              // 8
 };
+constexpr int UF_MAXB = 64;   // blocks of the multi-block heat-conduction kernels (256 cells each)
+constexpr int UF_SLOTS = 9;
 
-hipError_t ulaunch_fourier(const UFourierDev* f_dev, int ns, double tol, int max_outer, double cg_tol,
-                           int max_cg, hipStream_t st);
+// Heat conduction, Eq. (final2), over several blocks: the start of an outer
+// iteration (gradients, secondary fluxes, right-hand side, first residual),
+// `iters` CG iterations (two kernels each; they return at once once the CG
+// has stopped, which fsc[0] says), and the end of an outer iteration (mean
+// removed, the change against the previous iterate in fsc[4], fsc[5] = 1 when
+// it is within tol); then kappa_F and the statistics into out.
+hipError_t ulaunch_fourier_start(const UFourierDev* f_dev, int ns, int nfaces, hipStream_t st);
+hipError_t ulaunch_fourier_cg(const UFourierDev* f_dev, int ns, int iters, double cg_tol, int max_cg,
+                              hipStream_t st);
+hipError_t ulaunch_fourier_end(const UFourierDev* f_dev, int ns, double tol, hipStream_t st);
+hipError_t ulaunch_fourier_kappa(const UFourierDev* f_dev, int ns, hipStream_t st);
 // the pass's sources packed in sweep order (n_pos = n_dir * n_solid
 // positions), then every system's pass
 hipError_t ulaunch_pass(const UGeomDev* g_dev, int n_sys, int n_pos, int wpl, size_t lds_bytes, double inner_tol,
