@@ -89,7 +89,7 @@ __device__ __forceinline__ double udiag(const UFourierDev& f, int i) {
 // taken as per-block partials that each consumer adds in block order, so
 // every block takes the same decisions and FP64 results are reproducible.
 constexpr int UFB = 256;
-enum { UP_RR0, UP_RR1, UP_RZ0, UP_RZ1, UP_PQ, UP_BB, UP_ST, UP_DM, UP_TM };
+enum { UP_RR0, UP_RR1, UP_G0, UP_G1, UP_D0, UP_D1, UP_BB, UP_ST, UP_DM, UP_TM };
 static_assert(UP_TM + 1 == UF_SLOTS, "partial slots of the heat-conduction kernels");
 
 __host__ __device__ __forceinline__ int uf_blocks(int ns) { return (ns + UFB - 1) / UFB; }
@@ -134,14 +134,14 @@ __global__ void __launch_bounds__(UFB) k_uf_face(const UFourierDev* __restrict__
 }
 
 // b = -(P + B) (the right-hand side of A T = b, A = -Laplacian), the previous
-// iterate, the diagonal, the first residual r = b - A T (warm start from T)
-// and its preconditioned form; partials of |b|^2, r.r and r.z.  The CG
-// direction of parity 1 (the one before the first) is 0.
+// iterate, the diagonal and the first residual r = b - A T (warm start from
+// T); partials of |b|^2 and r.r.  The CG's direction p and its image s of
+// the iteration before the first are 0.
 __global__ void __launch_bounds__(UFB) k_uf_init(const UFourierDev* __restrict__ fp) {
     __shared__ double red[UFB / 64];
     const UFourierDev& f = *fp;
     const int i = blockIdx.x * UFB + threadIdx.x;
-    double bb = 0.0, rr = 0.0, rz = 0.0;
+    double bb = 0.0, rr = 0.0;
     if (i < f.ns) {
         double s = f.P[i];
         for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
@@ -149,98 +149,122 @@ __global__ void __launch_bounds__(UFB) k_uf_init(const UFourierDev* __restrict__
             const double v = f.bf[code >> 1];
             s += (code & 1) ? -v : v;
         }
-        const double d = udiag(f, i);
         const double ri = -s - uapply(f, f.T, i);
         f.tp[i] = f.T[i];
-        f.dg[i] = d;
+        f.dg[i] = udiag(f, i);
         f.r[i] = ri;
-        f.p2[i] = 0.0;
+        f.p[i] = 0.0;
+        f.s0[i] = 0.0;             // read as the previous s by the first iteration (parity 0)
         bb = s * s;
         rr = ri * ri;
-        rz = ri * (ri / d);
     }
     bb = block_sum(bb, red);
     rr = block_sum(rr, red);
-    rz = block_sum(rz, red);
     if (threadIdx.x == 0) {
         f.fpart[UP_BB * UF_MAXB + blockIdx.x] = bb;
         f.fpart[UP_RR0 * UF_MAXB + blockIdx.x] = rr;
-        f.fpart[UP_RZ0 * UF_MAXB + blockIdx.x] = rz;
         if (blockIdx.x == 0) {
             f.fsc[0] = 0.0;            // this solve's CG runs
-            f.fsc[1] = 0.0;            // its iterations
+            f.fsc[10] = 0.0;           // iterations done before the next one of parity 0
         }
     }
 }
 
-// CG iteration it (parity q = it & 1), first half: the stop test on r.r, the
-// direction p = z + beta p_old (z = r / diag; beta = 0 first) written to the
-// parity-q buffer and q = A p, which needs p at the neighbours: each block
-// forms them from r and the parity-(q ^ 1) buffer, neither written here;
-// partials of p.q.  Parity 0 directions live in p, parity 1 in p2.
-__global__ void __launch_bounds__(UFB) k_uf_pq(const UFourierDev* __restrict__ fp, int q, double cg_tol,
+// w = A u with u = M^-1 r (M the diagonal) for the first residual, and the
+// partials of gamma = r.u and delta = w.u (parity 0)
+__global__ void __launch_bounds__(UFB) k_uf_w0(const UFourierDev* __restrict__ fp) {
+    __shared__ double red[UFB / 64];
+    const UFourierDev& f = *fp;
+    const int i = blockIdx.x * UFB + threadIdx.x;
+    double gm = 0.0, dl = 0.0;
+    if (i < f.ns) {
+        const double ui = f.r[i] / f.dg[i];
+        double w = 0.0;
+        for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
+            const int j = f.nb_j[k];
+            w += f.nb_a[k] * (ui - f.r[j] / f.dg[j]);
+        }
+        f.w0[i] = w;
+        gm = f.r[i] * ui;
+        dl = w * ui;
+    }
+    gm = block_sum(gm, red);
+    dl = block_sum(dl, red);
+    if (threadIdx.x == 0) {
+        f.fpart[UP_G0 * UF_MAXB + blockIdx.x] = gm;
+        f.fpart[UP_D0 * UF_MAXB + blockIdx.x] = dl;
+    }
+}
+
+// One preconditioned CG iteration in the Chronopoulos-Gear arrangement (one
+// kernel: both inner products of an iteration come from one pass).  With u =
+// M^-1 r, w = A u and s = A p carried by recurrence, iteration k (parity q):
+//   gamma = r.u, delta = w.u (partials of parity q), the stop test on r.r;
+//   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma /
+//   alpha_prev)  (k = 0: beta = 0, alpha = gamma / delta);
+//   p = u + beta p, s = w + beta s, T += alpha p, r' = r - alpha s,
+//   u' = M^-1 r', w' = A u', and the partials of r'.u', w'.u', r'.r'.
+// r, w and s are double buffered by parity (r0 = r, r1), and A u' at a cell
+// needs u' at its neighbours, which every block forms from the unchanged
+// parity-q buffers.  Scalars: fsc[6 + q] gamma, fsc[8 + q] alpha and
+// fsc[10 + q] the iterations done before an iteration of parity q.
+__global__ void __launch_bounds__(UFB) k_uf_cg(const UFourierDev* __restrict__ fp, int q, double cg_tol,
                                                int max_cg) {
     __shared__ double red[UFB / 64];
     const UFourierDev& f = *fp;
     if (f.fsc[0] != 0.0) return;
     const int B = uf_blocks(f.ns);
-    const double rr = uf_sum(f, UP_RR0 + q, B, red), rz = uf_sum(f, UP_RZ0 + q, B, red);
-    const double bb = uf_sum(f, UP_BB, B, red);
-    const int it = (int)f.fsc[1];
-    if (!(rr > cg_tol * cg_tol * bb) || it >= max_cg) {
+    const double rr = uf_sum(f, UP_RR0 + q, B, red), bb = uf_sum(f, UP_BB, B, red);
+    const double gam = uf_sum(f, UP_G0 + q, B, red), del = uf_sum(f, UP_D0 + q, B, red);
+    const int it = (int)f.fsc[10 + q];
+    double alpha = gam / del, beta = 0.0;
+    if (it > 0) {
+        beta = gam / f.fsc[6 + (q ^ 1)];
+        alpha = gam / (del - beta * gam / f.fsc[8 + (q ^ 1)]);
+    }
+    if (!(rr > cg_tol * cg_tol * bb) || it >= max_cg || !(alpha > 0.0) || !isfinite(alpha)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) f.fsc[0] = 1.0;
         return;
     }
-    const double beta = it == 0 ? 0.0 : rz / uf_sum(f, UP_RZ0 + (q ^ 1), B, red);
-    const double* po = q ? f.p : f.p2;
-    double* pn = q ? f.p2 : f.p;
+    const double* r = q ? f.r1 : f.r;
+    const double* w = q ? f.w1 : f.w0;
+    const double* so = q ? f.s1 : f.s0;       // s of the previous iteration (parity q ^ 1 wrote it here)
+    double* rn = q ? f.r : f.r1;
+    double* wn = q ? f.w0 : f.w1;
+    double* sn = q ? f.s0 : f.s1;
     const int i = blockIdx.x * UFB + threadIdx.x;
-    double pq = 0.0;
+    double gm = 0.0, dl = 0.0, r2 = 0.0;
     if (i < f.ns) {
-        const double pc = f.r[i] / f.dg[i] + beta * po[i];
-        double y = 0.0;
+        const double pc = r[i] / f.dg[i] + beta * f.p[i];
+        const double sc = w[i] + beta * so[i];
+        f.p[i] = pc;
+        f.T[i] += alpha * pc;
+        const double ri = r[i] - alpha * sc;
+        const double ui = ri / f.dg[i];
+        double wv = 0.0;
         for (int k = f.nb_ptr[i]; k < f.nb_ptr[i + 1]; ++k) {
             const int j = f.nb_j[k];
-            y += f.nb_a[k] * (pc - (f.r[j] / f.dg[j] + beta * po[j]));
+            const double rj = r[j] - alpha * (w[j] + beta * so[j]);
+            wv += f.nb_a[k] * (ui - rj / f.dg[j]);
         }
-        pn[i] = pc;
-        f.q[i] = y;
-        pq = pc * y;
+        rn[i] = ri;
+        wn[i] = wv;
+        sn[i] = sc;
+        gm = ri * ui;
+        dl = wv * ui;
+        r2 = ri * ri;
     }
-    pq = block_sum(pq, red);
-    if (threadIdx.x == 0) f.fpart[UP_PQ * UF_MAXB + blockIdx.x] = pq;
-}
-
-// second half: alpha = r.z / p.q, T += alpha p, r -= alpha q, partials of the
-// new r.r and r.z into parity q ^ 1; the iteration counts
-__global__ void __launch_bounds__(UFB) k_uf_xr(const UFourierDev* __restrict__ fp, int q) {
-    __shared__ double red[UFB / 64];
-    const UFourierDev& f = *fp;
-    if (f.fsc[0] != 0.0) return;
-    const int B = uf_blocks(f.ns);
-    const double pq = uf_sum(f, UP_PQ, B, red), rz = uf_sum(f, UP_RZ0 + q, B, red);
-    if (!(pq > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) f.fsc[0] = 1.0;
-        return;
-    }
-    const double alpha = rz / pq;
-    const double* pn = q ? f.p2 : f.p;
-    const int i = blockIdx.x * UFB + threadIdx.x;
-    double rn = 0.0, zn = 0.0;
-    if (i < f.ns) {
-        f.T[i] += alpha * pn[i];
-        const double ri = f.r[i] - alpha * f.q[i];
-        f.r[i] = ri;
-        rn = ri * ri;
-        zn = ri * ri / f.dg[i];
-    }
-    rn = block_sum(rn, red);
-    zn = block_sum(zn, red);
+    gm = block_sum(gm, red);
+    dl = block_sum(dl, red);
+    r2 = block_sum(r2, red);
     if (threadIdx.x == 0) {
-        f.fpart[(UP_RR0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = rn;
-        f.fpart[(UP_RZ0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = zn;
+        f.fpart[(UP_G0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = gm;
+        f.fpart[(UP_D0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = dl;
+        f.fpart[(UP_RR0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = r2;
         if (blockIdx.x == 0) {
-            f.fsc[1] += 1.0;
+            f.fsc[6 + q] = gam;
+            f.fsc[8 + q] = alpha;
+            f.fsc[10 + (q ^ 1)] = (double)(it + 1);
             f.fsc[2] += 1.0;
         }
     }
@@ -671,6 +695,7 @@ hipError_t ulaunch_fourier_start(const UFourierDev* f_dev, int ns, int nfaces, h
     hipLaunchKernelGGL(k_uf_grad, dim3(B), dim3(UFB), 0, st, f_dev);
     if (BF > 0) hipLaunchKernelGGL(k_uf_face, dim3(BF), dim3(UFB), 0, st, f_dev);
     hipLaunchKernelGGL(k_uf_init, dim3(B), dim3(UFB), 0, st, f_dev);
+    hipLaunchKernelGGL(k_uf_w0, dim3(B), dim3(UFB), 0, st, f_dev);
     return hipGetLastError();
 }
 
@@ -681,9 +706,7 @@ hipError_t ulaunch_fourier_cg(const UFourierDev* f_dev, int ns, int iters, doubl
     for (int k = 0; k < iters; ++k) {
         // the parity of an iteration is its count's, which is even at the
         // start of every chunk (chunks are even and a solve starts at 0)
-        const int q = k & 1;
-        hipLaunchKernelGGL(k_uf_pq, dim3(B), dim3(UFB), 0, st, f_dev, q, cg_tol, max_cg);
-        hipLaunchKernelGGL(k_uf_xr, dim3(B), dim3(UFB), 0, st, f_dev, q);
+        hipLaunchKernelGGL(k_uf_cg, dim3(B), dim3(UFB), 0, st, f_dev, k & 1, cg_tol, max_cg);
     }
     return hipGetLastError();
 }

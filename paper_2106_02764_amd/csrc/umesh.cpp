@@ -637,12 +637,16 @@ obte_status obte_umesh_material_set(obte_umesh* m, const double* mfp, int n_mfp,
     AL(&fdv.g, 2 * (size_t)ns);
     AL(&fdv.bf, nf);
     AL(&fdv.out, 4);
-    AL(&fdv.p2, ns);
+    AL(&fdv.r1, ns);
+    AL(&fdv.w0, ns);
+    AL(&fdv.w1, ns);
+    AL(&fdv.s0, ns);
+    AL(&fdv.s1, ns);
     AL(&fdv.tp, ns);
     AL(&fdv.dg, ns);
     AL(&fdv.fpart, (size_t)UF_SLOTS * UF_MAXB);
-    AL(&fdv.fsc, 8);
-    if (hipHostMalloc((void**)&m->h_fsc, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    AL(&fdv.fsc, UF_SCALARS);
+    if (hipHostMalloc((void**)&m->h_fsc, UF_SCALARS * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         m->h_fsc = nullptr;
         free_dev(m);
         return ufail(OBTE_ERR_HIP, "hipHostMalloc failed");
@@ -666,7 +670,7 @@ obte_status obte_umesh_fourier(obte_umesh* m, double tol, int max_outer, double 
     if (!(tol >= 0.0) || !(cg_tol > 0.0) || max_outer < 1) return ufail(OBTE_ERR_ARG, "need tol >= 0, cg_tol > 0, max_outer >= 1");
     hipStream_t st = (hipStream_t)stream;
     UHIP(hipMemsetAsync(m->fh.T, 0, sizeof(double) * m->ns, st));
-    UHIP(hipMemsetAsync(m->fh.fsc, 0, sizeof(double) * 8, st));
+    UHIP(hipMemsetAsync(m->fh.fsc, 0, sizeof(double) * UF_SCALARS, st));
     // conjugate gradients end in at most n steps in exact arithmetic; twice
     // that caps a solve whose tolerance sits below the rounding floor
     const int max_cg = 2 * m->ns + 50;
@@ -676,12 +680,12 @@ obte_status obte_umesh_fourier(obte_umesh* m, double tol, int max_outer, double 
         UHIP(ulaunch_fourier_start(m->fdv, m->ns, m->nf, st));
         for (int done = 0; !done;) {
             UHIP(ulaunch_fourier_cg(m->fdv, m->ns, CG_CHUNK, cg_tol, max_cg, st));
-            UHIP(hipMemcpyAsync(h, m->fh.fsc, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+            UHIP(hipMemcpyAsync(h, m->fh.fsc, sizeof(double) * UF_SCALARS, hipMemcpyDeviceToHost, st));
             UHIP(hipStreamSynchronize(st));
             done = h[0] != 0.0;
         }
         UHIP(ulaunch_fourier_end(m->fdv, m->ns, tol, st));
-        UHIP(hipMemcpyAsync(h, m->fh.fsc, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+        UHIP(hipMemcpyAsync(h, m->fh.fsc, sizeof(double) * UF_SCALARS, hipMemcpyDeviceToHost, st));
         UHIP(hipStreamSynchronize(st));
         if (h[5] != 0.0 || !std::isfinite(h[4])) break;
     }

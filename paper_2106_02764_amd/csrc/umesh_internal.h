@@ -90,18 +90,23 @@ struct UFourierDev {
     double* out;              // 4: kappa_F, outer iterations, CG iterations, last relative change
     // multi-block solve: the second direction buffer, the previous outer
     // iterate, the diagonal, per-block partial sums and loop scalars
-    double* p2;               // ns
+    double* r1;               // ns: r, A M^-1 r (w) and A p (s) by CG iteration parity
+    double* w0;
+    double* w1;
+    double* s0;
+    double* s1;
     double* tp;               // ns
     double* dg;               // ns
     double* fpart;            // UF_SLOTS * UF_MAXB
-    double* fsc;              // 8
+    double* fsc;              // UF_SCALARS
 };
 constexpr int UF_MAXB = 64;   // blocks of the multi-block heat-conduction kernels (256 cells each)
-constexpr int UF_SLOTS = 9;
+constexpr int UF_SLOTS = 10;
+constexpr int UF_SCALARS = 16;
 
 // Heat conduction, Eq. (final2), over several blocks: the start of an outer
 // iteration (gradients, secondary fluxes, right-hand side, first residual),
-// `iters` CG iterations (two kernels each; they return at once once the CG
+// `iters` CG iterations (one kernel each; they return at once once the CG
 // has stopped, which fsc[0] says), and the end of an outer iteration (mean
 // removed, the change against the previous iterate in fsc[4], fsc[5] = 1 when
 // it is within tol); then kappa_F and the statistics into out.
