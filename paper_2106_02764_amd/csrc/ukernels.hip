@@ -644,17 +644,27 @@ __global__ void __launch_bounds__(64 * UQ) k_ureduce(const UGeomDev* __restrict_
     const int cell = in ? (walls ? g.wcell[t] : t) : 0;
     const int per = (g.n_sys + UQ - 1) / UQ;
     const int i0 = q * per, i1 = min(g.n_sys, i0 + per);
-    double a0 = 0.0, a1 = 0.0;
+    // eight systems' values in flight per lane, four running sums
+    auto wgt = [&](int k) { return walls ? (in ? g.wout[(size_t)t * g.n_sys + k] : 0.0) : g.Dw[k]; };
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int i = i0;
-    for (; i + 1 < i1; i += 2) {
-        const double x0 = g.X[(size_t)i * g.ns + cell], x1 = g.X[(size_t)(i + 1) * g.ns + cell];
-        const double w0 = walls ? (in ? g.wout[(size_t)t * g.n_sys + i] : 0.0) : g.Dw[i];
-        const double w1 = walls ? (in ? g.wout[(size_t)t * g.n_sys + i + 1] : 0.0) : g.Dw[i + 1];
-        a0 += w0 * x0;
-        a1 += w1 * x1;
+    for (; i + 7 < i1; i += 8) {
+        double xv[8], wv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = g.X[(size_t)(i + u) * g.ns + cell];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wv[u] = wgt(i + u);
+        a0 += wv[0] * xv[0];
+        a1 += wv[1] * xv[1];
+        a2 += wv[2] * xv[2];
+        a3 += wv[3] * xv[3];
+        a0 += wv[4] * xv[4];
+        a1 += wv[5] * xv[5];
+        a2 += wv[6] * xv[6];
+        a3 += wv[7] * xv[7];
     }
-    if (i < i1) a0 += (walls ? (in ? g.wout[(size_t)t * g.n_sys + i] : 0.0) : g.Dw[i]) * g.X[(size_t)i * g.ns + cell];
-    part[q][cl] = a0 + a1;
+    for (; i < i1; ++i) a0 += wgt(i) * g.X[(size_t)i * g.ns + cell];
+    part[q][cl] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     if (q == 0 && in) {
         double acc = 0.0;
