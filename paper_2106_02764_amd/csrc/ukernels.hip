@@ -50,6 +50,26 @@ __device__ double block_sum(double v, double* red) {
     return s;
 }
 
+// N block-wide sums in one exchange (each value summed as block_sum does;
+// red: at least 16 N doubles)
+template <int N>
+__device__ void block_sum_n(double (&v)[N], double* red) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int n = 0; n < N; ++n) red[n * 16 + w] = v[n];
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        double s = 0.0;
+        for (int k = 0; k < nw; ++k) s += red[n * 16 + k];
+        v[n] = s;
+    }
+}
+
 __device__ double block_max(double v, double* red) {
     v = wave_max(v);
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -210,12 +230,20 @@ __global__ void __launch_bounds__(UFB) k_uf_w0(const UFourierDev* __restrict__ f
 // fsc[10 + q] the iterations done before an iteration of parity q.
 __global__ void __launch_bounds__(UFB) k_uf_cg(const UFourierDev* __restrict__ fp, int q, double cg_tol,
                                                int max_cg) {
-    __shared__ double red[UFB / 64];
+    __shared__ double red[4 * 16];
     const UFourierDev& f = *fp;
     if (f.fsc[0] != 0.0) return;
     const int B = uf_blocks(f.ns);
-    const double rr = uf_sum(f, UP_RR0 + q, B, red), bb = uf_sum(f, UP_BB, B, red);
-    const double gam = uf_sum(f, UP_G0 + q, B, red), del = uf_sum(f, UP_D0 + q, B, red);
+    // the four sums of the partials in one exchange (block order, as uf_sum)
+    double sm[4] = {0.0, 0.0, 0.0, 0.0};
+    if ((int)threadIdx.x < B) {
+        sm[0] = f.fpart[(UP_RR0 + q) * UF_MAXB + threadIdx.x];
+        sm[1] = f.fpart[UP_BB * UF_MAXB + threadIdx.x];
+        sm[2] = f.fpart[(UP_G0 + q) * UF_MAXB + threadIdx.x];
+        sm[3] = f.fpart[(UP_D0 + q) * UF_MAXB + threadIdx.x];
+    }
+    block_sum_n(sm, red);
+    const double rr = sm[0], bb = sm[1], gam = sm[2], del = sm[3];
     const int it = (int)f.fsc[10 + q];
     double alpha = gam / del, beta = 0.0;
     if (it > 0) {
@@ -254,13 +282,12 @@ __global__ void __launch_bounds__(UFB) k_uf_cg(const UFourierDev* __restrict__ f
         dl = wv * ui;
         r2 = ri * ri;
     }
-    gm = block_sum(gm, red);
-    dl = block_sum(dl, red);
-    r2 = block_sum(r2, red);
+    double en[3] = {gm, dl, r2};
+    block_sum_n(en, red);
     if (threadIdx.x == 0) {
-        f.fpart[(UP_G0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = gm;
-        f.fpart[(UP_D0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = dl;
-        f.fpart[(UP_RR0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = r2;
+        f.fpart[(UP_G0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = en[0];
+        f.fpart[(UP_D0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = en[1];
+        f.fpart[(UP_RR0 + (q ^ 1)) * UF_MAXB + blockIdx.x] = en[2];
         if (blockIdx.x == 0) {
             f.fsc[6 + q] = gam;
             f.fsc[8 + q] = alpha;
