@@ -175,7 +175,8 @@ typedef struct {
     /* Launch shape of the pass kernel (results do not depend on it; FP64 runs
      * are bitwise the same).  waves_by_class[c - 1]: systems per workgroup of
      * the launch over meshes with c = ceil(n[0] / 64) cells per lane (0..8,
-     * 0 = waves_per_group).  dispatch: 0 = each geometry's work items longest
+     * 0 = waves_per_group; FP64 2D launches with c >= 3, and FP64 launches with
+     * dispatch = 2, take at most 4: larger explicit values are OBTE_ERR_ARG).  dispatch: 0 = each geometry's work items longest
      * MFPs first (geometry by geometry), one launch per class; 1 = the
      * longest-MFP items of every geometry of a launch first; 2 (2D meshes;
      * 3D takes 1) = one persistent launch over the items of every class,
