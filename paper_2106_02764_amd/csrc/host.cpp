@@ -750,9 +750,9 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
         R.items = by_cls[0];
     }
     for (int c = 1; c <= 4; ++c) {
-        // dispatch = 1: the longest-MFP groups of every geometry first (the
-        // order is stable, so geometries and directions keep theirs)
-        if (o->dispatch == 1)
+        // dispatch = 1 (and 2 in 3D): the longest-MFP groups of every geometry
+        // first (the order is stable, so geometries and directions keep theirs)
+        if (o->dispatch == 1 || (o->dispatch == 2 && !R.queue))
             std::stable_sort(by_cls[c].begin(), by_cls[c].end(),
                              [](const Item& a, const Item& b) { return a.m0 > b.m0; });
         R.cls_first[c] = (int)R.items.size();

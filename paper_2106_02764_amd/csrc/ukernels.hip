@@ -449,12 +449,16 @@ __device__ void usweep(const UGeomDev& g, const USys& s, bool src, double* x, co
     const int L = s.nlev;
     auto bound = [&](int k) { return lp[k < L ? k : L]; };
     int a0 = bound(0), a1 = bound(1), e1 = bound(2), e2 = bound(3);
+    // every lane fetches (beyond its level: the level's last entry, or the
+    // first position), so no load sits in a branch: the compiler then counts
+    // the loads in flight exactly and waits only for the level it solves
+    auto pos = [&](int lo, int hi) { return lo + lane < hi ? lo + lane : (hi > 0 ? hi - 1 : 0); };
     UEnt cur, nxt, nx2;
-    if (a0 + lane < a1) ufetch(g, s, src, a0 + lane, cur);
-    if (a1 + lane < e1) ufetch(g, s, src, a1 + lane, nxt);
+    ufetch(g, s, src, pos(a0, a1), cur);
+    ufetch(g, s, src, pos(a1, e1), nxt);
     for (int k = 0; k < L; ++k) {
         const int e3 = bound(k + 4);
-        if (e1 + lane < e2) ufetch(g, s, src, e1 + lane, nx2);
+        ufetch(g, s, src, pos(e1, e2), nx2);
         if (a0 + lane < a1) usolve(g, s, cur, x, uin);
         for (int p = a0 + lane + WAVE; p < a1; p += WAVE) {
             UEnt e;
