@@ -427,14 +427,17 @@ __global__ void __launch_bounds__(256) k_upack(const UGeomDev* __restrict__ gp) 
     }
 }
 
+// The wrap inflow follows the solution in LDS (uin = x + ns), so an inflow
+// code indexes both: x[code] is the upwind cell's value for code < ns and the
+// wrap slot's for code >= ns; unused faces read x[0] and drop it (no branch).
 __device__ __forceinline__ void usolve(const UGeomDev& g, const USys& s, const UEnt& e, double* x, const double* uin) {
+    (void)uin;
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < UFACES; ++q) {
         const int code = e.code[q];
-        if (code == UNONE) continue;
-        const double v = code >= g.ns ? uin[code - g.ns] : x[code];
-        acc += e.c[q] * v;
+        const double v = x[code >= 0 ? code : 0];       // read always, selected
+        acc += code >= 0 ? e.c[q] * v : 0.0;
     }
     x[e.i] = (e.b + s.lam * acc) / (e.sg + s.lam * e.d);
 }
