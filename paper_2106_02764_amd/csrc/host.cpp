@@ -606,6 +606,8 @@ struct Run {
     // pinned host slots for the loop read-backs (two per loop, see
     // speculative loops below); null: plain synchronous read-backs
     int* h_pin = nullptr;
+    // the views in pinned memory (staged upload), or null
+    const GeomDev* h_views = nullptr;
 };
 
 // Pinned staging of a mesh: bytes [0, STAGE_LOOP) hold the loop read-back
@@ -766,7 +768,10 @@ obte_status build_run(Run& R, obte_mesh* const* meshes, int n, const obte_solve_
 }
 
 // Place the run's device state in the workspace (after the size check).
-obte_status upload_run(Run& R, char* ws) {
+// With a staging mesh (its pinned buffer) and a stream, the views and items
+// go through pinned memory with copies queued on the stream (the host does
+// not wait for them); else plain synchronous copies (obte_solve_noalloc).
+obte_status upload_run(Run& R, char* ws, hipStream_t st = nullptr, obte_mesh* stage = nullptr) {
     char* p = ws + R.state_off;
     R.d_views = (GeomDev*)p;
     p += align256(R.views.size() * sizeof(GeomDev));
@@ -774,8 +779,20 @@ obte_status upload_run(Run& R, char* ws) {
     p += align256(R.items.size() * sizeof(Item));
     R.d_pending = (int*)p;
     R.d_queue = R.d_pending + 16;       // within the state's last 256 bytes
-    HIPCHK(hipMemcpy(R.d_views, R.views.data(), R.views.size() * sizeof(GeomDev), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(R.d_items, R.items.data(), R.items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    const size_t vb = R.views.size() * sizeof(GeomDev), ib = R.items.size() * sizeof(Item);
+    if (st && stage) {
+        obte_status s = ensure_stage(stage, STAGE_LOOP + align256(vb) + ib);
+        if (s != OBTE_OK) return s;
+        char* h = stage->h_stage + STAGE_LOOP;
+        std::memcpy(h, R.views.data(), vb);
+        std::memcpy(h + align256(vb), R.items.data(), ib);
+        HIPCHK(hipMemcpyAsync(R.d_views, h, vb, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(R.d_items, h + align256(vb), ib, hipMemcpyHostToDevice, st));
+        R.h_views = reinterpret_cast<const GeomDev*>(h);
+        return OBTE_OK;
+    }
+    HIPCHK(hipMemcpy(R.d_views, R.views.data(), vb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(R.d_items, R.items.data(), ib, hipMemcpyHostToDevice));
     return OBTE_OK;
 }
 
@@ -1014,7 +1031,7 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         const size_t need = R.state_off + R.state_bytes;
         if (ws_bytes < need)
             return fail(OBTE_ERR_NOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
-        if ((s = upload_run(R, (char*)workspace)) != OBTE_OK) return s;
+        if ((s = upload_run(R, (char*)workspace, st, noalloc ? nullptr : meshes[0])) != OBTE_OK) return s;
         if (!noalloc) {
             if ((s = ensure_stage(meshes[0], STAGE_LOOP)) != OBTE_OK) return s;
             R.h_pin = (int*)meshes[0]->h_stage;
@@ -1024,7 +1041,10 @@ obte_status solve_impl(obte_mesh* const* meshes, int n, const obte_solve_opts* o
         obte_mesh* m = meshes[i];
         Layout L = make_layout(m, o, R.cls_waves[1]);
         char* ws = (char*)workspace + offs[i];
-        HIPCHK(hipMemcpy(m->d_geom, &R.views[i], sizeof(GeomDev), hipMemcpyHostToDevice));
+        if (R.h_views)
+            HIPCHK(hipMemcpyAsync(m->d_geom, R.h_views + i, sizeof(GeomDev), hipMemcpyHostToDevice, st));
+        else
+            HIPCHK(hipMemcpy(m->d_geom, &R.views[i], sizeof(GeomDev), hipMemcpyHostToDevice));
         m->host_view = R.views[i];
         HIPCHK(launch_prep_sigma(m->d_geom, m->ncells, sigma ? sigma[i] : nullptr, st));
         if (o->init == 0) {
