@@ -491,17 +491,28 @@ struct RegIO {
 template <typename T, int CPL>
 struct GlobIO {
     gptr_t<T> u;
-    gmut_t<T> xl;        // nullptr: the last row is not needed
+    rsrc_t xl;           // size 0 when the last row is not needed (or the wave is inactive)
     int nx;
-    int active;
     __device__ __forceinline__ const T* input() const { return (const T*)u; }
     // the row loads prefetch the input (Views::u); nothing is read here
     __device__ __forceinline__ T in(int, int, int) const { return T(0); }
+    // a buffer store in no per-lane branch (beyond the row: an offset past
+    // the plane, dropped), so the compiler keeps counting the row prefetches
+    // in flight exactly across it
     __device__ __forceinline__ void out(int kk, int c, int lane, T v) {
         const int p = lane * CPL + c;
-        if (xl && active && p < nx) xl[kk * nx + p] = v;
+        bst(v, xl, p < nx ? (uint32_t)(kk * nx + p) * (uint32_t)sizeof(T) : BUF_OOB);
     }
 };
+// out_plane: the nz x nx plane receiving the last row, or nullptr
+template <typename T, int CPL>
+__device__ __forceinline__ GlobIO<T, CPL> make_gio(gptr_t<T> u, gmut_t<T> out_plane, int nx, int nz, int active) {
+    GlobIO<T, CPL> io;
+    io.u = u;
+    io.xl = make_rsrc((const T*)out_plane, (out_plane && active) ? (uint32_t)(nx * nz) * (uint32_t)sizeof(T) : 0u);
+    io.nx = nx;
+    return io;
+}
 
 // One row step of the sweep (cells of row (jj, kk) in upwind order).  FULL:
 // the row fills every lane (nx = 64 CPL), so no lane holds cells beyond it.
@@ -640,15 +651,18 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
             for (int c = 0; c < CPL; ++c) {
                 const int p = lane * CPL + c;
                 const uint32_t wv = (FULL || p < nx) ? cur.w[c] : 0u;
-                if (!fc_solid(wv)) continue;
+                // selects, not per-lane branches: a divergent region in the
+                // row loop makes the compiler wait for every row prefetch
                 const double xv = (double)xrow[c];
                 const int cl = fc_class(wv, s.fout[1]);
+                double add;
                 if (adj) {
                     const double cj = s.cd[1] * vw.dT;
-                    rd->kface += cl == FC_JUMP_P ? cj * xv : (cl == FC_JUMP_M ? -cj * xv : 0.0);
-                } else if (cl != FC_WALL) {
-                    rd->kface += xv + ((!ADD && s.pos[1]) ? vw.dT : 0.0);
+                    add = cl == FC_JUMP_P ? cj * xv : (cl == FC_JUMP_M ? -cj * xv : 0.0);
+                } else {
+                    add = cl != FC_WALL ? xv + ((!ADD && s.pos[1]) ? vw.dT : 0.0) : 0.0;
                 }
+                rd->kface += fc_solid(wv) ? add : 0.0;
             }
         }
     }
@@ -659,7 +673,7 @@ __device__ __forceinline__ void row_step(const GeomDev& g, const SysC<T>& s, con
 // issues the same stores and the hardware drops those.
 template <typename T, int CPL, int NR, bool ADD>
 __device__ __forceinline__ void store_rows(Red<T>* rd, const RowOut<T, CPL> (&ro)[NR]) {
-    if (!rd->on) return;
+    // no branch on rd->on: an inactive wave's resources have size 0
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -1613,7 +1627,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     Red<T> rd = make_red<T>(g, s, active, pp);
     // ---- phase A
     {
-        GlobIO<T, CPL> io{U, xl, nx, active};
+        GlobIO<T, CPL> io = make_gio<T, CPL>(U, xl, nx, nz, active);
         if (g.grad_axis == 0)
             sweep<T, CPL, true, true, true, false, SIG1 != 0, 0, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
         else
@@ -1678,7 +1692,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
                 const double beta = (rho / rho_old) * (alpha / omega);
                 PLOOP(p[i] = r[i] + (T)beta * (p[i] - (T)omega * v[i]));
                 {
-                    GlobIO<T, CPL> io{p, xl, nx, 1};
+                    GlobIO<T, CPL> io = make_gio<T, CPL>(p, xl, nx, nz, 1);
                     sweep<T, CPL, true, false, false, false, SIG1 != 0, -1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
                 }
                 ++n_sw;
@@ -1713,7 +1727,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
                     break;
                 }
                 {
-                    GlobIO<T, CPL> io{sv, xl, nx, 1};
+                    GlobIO<T, CPL> io = make_gio<T, CPL>(sv, xl, nx, nz, 1);
                     sweep<T, CPL, true, false, false, false, SIG1 != 0, -1, FULL>(g, s, active, lane, adj, srcbase, bnd, io, nullptr, zrows);
                 }
                 ++n_sw;
@@ -1751,7 +1765,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CPL ==
     }
     // ---- phase C (see the 2D kernel)
     if (!pp.lag_wrap && need) {
-        GlobIO<T, CPL> io{du, nullptr, nx, 0};
+        GlobIO<T, CPL> io = make_gio<T, CPL>(du, nullptr, nx, nz, 0);
         if (g.grad_axis == 0)
             sweep<T, CPL, true, false, true, true, SIG1 != 0, 0, FULL>(g, s, active, lane, adj, srcbase, bnd, io, &rd, zrows);
         else
