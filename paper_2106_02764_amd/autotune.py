@@ -112,7 +112,10 @@ def tune(solvers, opts, candidates=(1, 2, 4, 8), passes=4, use_cache=True, cache
     disp = 0
     if len(solvers) > 1:
         for d in (1, 2):
-            ms = measure(solvers, _copy(opts, waves_by_class=wc, dispatch=d), passes)
+            try:
+                ms = measure(solvers, _copy(opts, waves_by_class=wc, dispatch=d), passes)
+            except _o.ObteError:
+                continue        # e.g. the queue's FP64 cap of 4 systems per workgroup
             timings[f"dispatch{d}"] = ms
             if ms < best:
                 best, disp = ms, d
