@@ -1270,23 +1270,34 @@ __device__ __forceinline__ void qsweep(const GeomDev& g, const SysC<T>& s, int l
             qpart_close<T, CPL, S1>(P, p0);
         }
         // no stores, or an update of the stored values (four rows of
-        // results are added to the stored ones together)
-        for (int r = 0; r < ny; r += 4) {
+        // results are added to the stored ones together).  As above, the
+        // body has no branch and the first group is peeled: a step past the
+        // last row reads zero records, so its x is 0, it adds nothing and
+        // stores nothing, and the waits for the prefetched rows stay partial.
+        auto gstep = [&](int r, const QRowIn<T, CPL>& b, const QPart<T, CPL>& qp, const QRowIn<T, CPL>& bn,
+                         QPart<T, CPL>& qn, QRowOut<T, CPL>& ro) {
+            step(r, b, qp, bn, qn, ro);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) ro.so[c] = r < ny ? ro.so[c] : QOFF_NONE;
+        };
+        auto group = [&](int r) {
             QRowOut<T, CPL> ro[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) ro[u].so[c] = QOFF_NONE;
             pre(r + 3, b3);
-            step(r, b0, p0, b1, p1, ro[0]);
+            gstep(r, b0, p0, b1, p1, ro[0]);
             pre(r + 4, b0);
-            if (r + 1 < ny) step(r + 1, b1, p1, b2, p2, ro[1]);
+            gstep(r + 1, b1, p1, b2, p2, ro[1]);
             pre(r + 5, b1);
-            if (r + 2 < ny) step(r + 2, b2, p2, b3, p3, ro[2]);
+            gstep(r + 2, b2, p2, b3, p3, ro[2]);
             pre(r + 6, b2);
-            if (r + 3 < ny) step(r + 3, b3, p3, b0, p0, ro[3]);
+            gstep(r + 3, b3, p3, b0, p0, ro[3]);
             if (RED) store_qrows<T, CPL, 4, ADD, false>(rd, ro);
-        }
+        };
+        group(0);
+        for (int r = 4; r < ny; r += 4) group(r);
     }
 }
 
