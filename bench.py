@@ -62,8 +62,8 @@ REF = dict(precision=0, outer_tol=1e-10, stop_rule=0, accel=8, inner_tol=1e-12, 
 # operating point, per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE over one
 # solve, each scaled by the same counter on a plain 256 MiB copy); valid only
 # for the kernel source it was taken on.
-TRAFFIC = {"kernels_sha256": "3fe136a035843ff42bc93bc2bdc8186a038e8dd65429263a2d4dc0fb24413666",
-           "fetch_bytes": 15604241, "write_bytes": 59392774}
+TRAFFIC = {"kernels_sha256": "a4b87ad98d042e1c01d43d6cddb813d4e054cb9f3ba34e262d5b502025d0f9b5",
+           "fetch_bytes": 15430209, "write_bytes": 59392513}
 
 
 def parse():
